@@ -1,0 +1,794 @@
+/*
+ * LeCo CPU oracle -- TEST INFRASTRUCTURE ONLY (see leco_oracle.h).
+ *
+ * Plain scalar C, one value at a time, in the order the paper describes the
+ * method.  Built with -O2 -ffp-contract=off -fno-fast-math and no -march, so
+ * every floating-point operation is one IEEE-754 binary64 operation rounded
+ * to nearest-even.  Integer sums are exact (unsigned __int128).
+ *
+ * Readings of the paper taken here (all listed again in the design notes):
+ *  - widths use bitlen(x) = floor(log2 x) + 1, bitlen(0) = 0;
+ *  - the regressor is least squares with exact integer sums (section 3.1
+ *    states the closed form), slope = fl(N) / fl(D) in binary64;
+ *  - residuals are stored as unsigned offsets from their minimum, which is
+ *    folded into an integer intercept "base" (the paper's theta0);
+ *  - a partition falls back to the constant (FOR) model when that is not
+ *    wider, when it has one value, or when its range is >= 2^61;
+ *  - prediction at local index t is floor(theta1 * t) in binary64;
+ *  - residual t occupies bits [b*t, b*t + b) of its partition's span,
+ *    least-significant bit first, in little-endian 64-bit words.
+ */
+#include "leco_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+#define HEADER_BYTES 64u
+#define RECORD_BYTES 32u
+#define MAX_PART_LEN (1ull << 20)
+#define MAGIC 0x4F43454Cu /* bytes 'L','E','C','O' */
+#define VERSION 1u
+
+/* ---- small helpers -------------------------------------------------------- */
+
+uint64_t leco_ref_bitlen(uint64_t x) {
+  uint64_t b = 0;
+  while (x != 0) {
+    b++;
+    x >>= 1;
+  }
+  return b;
+}
+
+static uint64_t bitlen128(u128 x) {
+  uint64_t b = 0;
+  while (x != 0) {
+    b++;
+    x >>= 1;
+  }
+  return b;
+}
+
+static uint64_t align16(uint64_t x) { return (x + 15u) & ~(uint64_t)15u; }
+
+static uint64_t load_value(const void *col, int dtype, uint64_t i) {
+  if (dtype == 4) return ((const uint32_t *)col)[i];
+  return ((const uint64_t *)col)[i];
+}
+
+static void put_u64(uint8_t *p, uint64_t x) {
+  for (int k = 0; k < 8; k++) p[k] = (uint8_t)(x >> (8 * k));
+}
+static void put_u32(uint8_t *p, uint32_t x) {
+  for (int k = 0; k < 4; k++) p[k] = (uint8_t)(x >> (8 * k));
+}
+static void put_u16(uint8_t *p, uint16_t x) {
+  p[0] = (uint8_t)x;
+  p[1] = (uint8_t)(x >> 8);
+}
+static uint64_t get_u64(const uint8_t *p) {
+  uint64_t x = 0;
+  for (int k = 7; k >= 0; k--) x = (x << 8) | p[k];
+  return x;
+}
+static uint32_t get_u32(const uint8_t *p) {
+  uint32_t x = 0;
+  for (int k = 3; k >= 0; k--) x = (x << 8) | p[k];
+  return x;
+}
+static double f64_from_bits(uint64_t b) {
+  double d;
+  memcpy(&d, &b, 8);
+  return d;
+}
+static uint64_t bits_from_f64(double d) {
+  uint64_t b;
+  memcpy(&b, &d, 8);
+  return b;
+}
+
+/* Bit k of the packed stream lives in bit (k mod 64) of 64-bit word k / 64;
+ * words are little-endian, so this is byte k / 8, bit k mod 8. */
+static void set_stream_bit(uint8_t *words, uint64_t k) {
+  words[k >> 3] |= (uint8_t)(1u << (k & 7));
+}
+static unsigned get_stream_bit(const uint8_t *words, uint64_t k) {
+  return (words[k >> 3] >> (k & 7)) & 1u;
+}
+
+/* ---- Regressor (section 3.1) ------------------------------------------------ */
+
+/* Least-squares line through (t, y_t), t = 0..n-1, from exact sums:
+ *   slope = (n*S_ty - S_t*S_y) / (n*S_tt - S_t^2).
+ * Then residuals r_t = y_t - floor(slope * t) and their width (section 3.1,
+ * fixed-width deltas).  The constant model is kept when it is not wider. */
+int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant,
+                 leco_ref_model *out) {
+  if (n == 0 || n > MAX_PART_LEN || out == NULL) return LREF_EINVAL;
+  memset(out, 0, sizeof(*out));
+
+  uint64_t vmin = v[0], vmax = v[0];
+  for (uint64_t t = 1; t < n; t++) {
+    if (v[t] < vmin) vmin = v[t];
+    if (v[t] > vmax) vmax = v[t];
+  }
+  uint64_t range = vmax - vmin;
+  out->vmin = vmin;
+  out->vmax = vmax;
+  out->b_for = leco_ref_bitlen(range);
+
+  /* Constant model: every value stored as v - vmin (section 2, FOR). */
+  out->mode = 0;
+  out->theta1 = 0.0;
+  out->base = vmin;
+  out->bits = out->b_for;
+
+  if (n == 1 || force_constant || range >= (1ull << 61)) return LREF_OK;
+
+  /* Exact sums over y_t = v_t - vmin (< 2^61). */
+  u128 s_y = 0, s_ty = 0;
+  for (uint64_t t = 0; t < n; t++) {
+    u128 y = v[t] - vmin;
+    s_y += y;
+    s_ty += (u128)t * y;
+  }
+  u128 nn = n;
+  u128 s_t = nn * (nn - 1) / 2;
+  u128 s_tt = (nn - 1) * nn * (2 * nn - 1) / 6;
+  i128 N = (i128)(nn * s_ty) - (i128)(s_t * s_y);
+  i128 D = (i128)(nn * s_tt) - (i128)(s_t * s_t);
+  out->N_lo = (uint64_t)(u128)N;
+  out->N_hi = (int64_t)(N >> 64);
+  out->D_lo = (uint64_t)(u128)D;
+  out->D_hi = (uint64_t)((u128)D >> 64);
+
+  /* Two correctly rounded conversions, one correctly rounded division. */
+  double fN = (double)N;
+  double fD = (double)D;
+  double slope = fN / fD;
+  if (slope == 0.0) slope = 0.0; /* store +0.0, never -0.0 */
+  out->fitted = 1;
+  out->theta1_ls = slope;
+
+  int64_t r_min = 0, r_max = 0;
+  for (uint64_t t = 0; t < n; t++) {
+    double prod = slope * (double)t;
+    int64_t p = (int64_t)floor(prod);
+    int64_t r = (int64_t)(v[t] - vmin) - p;
+    if (t == 0 || r < r_min) r_min = r;
+    if (t == 0 || r > r_max) r_max = r;
+  }
+  out->r_min = r_min;
+  out->r_max = r_max;
+  out->b_ls = leco_ref_bitlen((uint64_t)r_max - (uint64_t)r_min);
+
+  if (out->b_for <= out->b_ls) return LREF_OK; /* ties keep the constant model */
+
+  out->mode = 1;
+  out->theta1 = slope;
+  out->base = vmin + (uint64_t)r_min;
+  out->bits = out->b_ls;
+  return LREF_OK;
+}
+
+/* Residual u_t stored for value t under a fitted model (both modes):
+ * u_t = v_t - base - floor(theta1 * t), all mod 2^64. */
+static uint64_t model_predict(double theta1, uint64_t t) {
+  double prod = theta1 * (double)t;
+  return (uint64_t)(int64_t)floor(prod);
+}
+
+/* ---- Partitioning ----------------------------------------------------------- */
+
+/* Builds starts[0..m] for fixed partitions of length L (section 3.2.1) or
+ * checks the caller's variable starts (section 3.2.2 / 3.3). */
+static int make_starts(uint64_t n, uint64_t fixed_len, const uint64_t *starts,
+                       uint64_t m_var, uint64_t **starts_out, uint64_t *m_out) {
+  uint64_t m;
+  uint64_t *s;
+  if (fixed_len > 0) {
+    if (fixed_len > MAX_PART_LEN) return LREF_EINVAL;
+    m = n / fixed_len + (n % fixed_len != 0);
+    s = (uint64_t *)malloc((m + 1) * sizeof(uint64_t));
+    if (!s) return LREF_ENOMEM;
+    for (uint64_t j = 0; j < m; j++) s[j] = j * fixed_len;
+    s[m] = n;
+  } else {
+    if (starts == NULL) return LREF_EINVAL;
+    m = m_var;
+    if (starts[0] != 0 || starts[m] != n) return LREF_EINVAL;
+    for (uint64_t j = 0; j < m; j++) {
+      if (starts[j + 1] <= starts[j]) return LREF_EINVAL;
+      if (starts[j + 1] - starts[j] > MAX_PART_LEN) return LREF_EINVAL;
+    }
+    s = (uint64_t *)malloc((m + 1) * sizeof(uint64_t));
+    if (!s) return LREF_ENOMEM;
+    for (uint64_t j = 0; j <= m; j++) s[j] = starts[j];
+  }
+  *starts_out = s;
+  *m_out = m;
+  return LREF_OK;
+}
+
+/* ---- Encoder (section 3.3) -------------------------------------------------- */
+
+typedef struct {
+  uint64_t base;
+  double theta1;
+  uint64_t bits;
+  uint64_t words;
+} part_code;
+
+/* Fits every partition; fills codes[] and the section offsets. */
+static int plan_blob(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
+                     const uint64_t *starts_in, uint64_t m_in, int force_constant,
+                     uint64_t **starts_out, uint64_t *m_out, part_code **codes_out,
+                     uint64_t *words_off, uint64_t *total_words,
+                     uint64_t *blob_bytes) {
+  if (dtype != 4 && dtype != 8) return LREF_EINVAL;
+  if (n > 0 && col == NULL) return LREF_EINVAL;
+  uint64_t *s = NULL, m = 0;
+  int st = make_starts(n, fixed_len, starts_in, m_in, &s, &m);
+  if (st != LREF_OK) return st;
+  part_code *codes = (part_code *)calloc(m ? m : 1, sizeof(part_code));
+  uint64_t *buf = (uint64_t *)malloc(MAX_PART_LEN * sizeof(uint64_t));
+  if (!codes || !buf) {
+    free(s);
+    free(codes);
+    free(buf);
+    return LREF_ENOMEM;
+  }
+  uint64_t tw = 0;
+  for (uint64_t j = 0; j < m; j++) {
+    uint64_t len = s[j + 1] - s[j];
+    for (uint64_t t = 0; t < len; t++) buf[t] = load_value(col, dtype, s[j] + t);
+    leco_ref_model md;
+    leco_ref_fit(buf, len, force_constant, &md);
+    codes[j].base = md.base;
+    codes[j].theta1 = md.theta1;
+    codes[j].bits = md.bits;
+    codes[j].words = (len * md.bits + 63) / 64;
+    tw += codes[j].words;
+  }
+  free(buf);
+  uint64_t after_meta = HEADER_BYTES + RECORD_BYTES * m;
+  if (fixed_len == 0) after_meta += 8 * (m + 1);
+  *words_off = align16(after_meta);
+  *total_words = tw;
+  *blob_bytes = align16(*words_off + 8 * tw);
+  *starts_out = s;
+  *m_out = m;
+  *codes_out = codes;
+  return LREF_OK;
+}
+
+int leco_ref_blob_bytes(const void *col, uint64_t n, int dtype,
+                        uint64_t fixed_len, const uint64_t *starts, uint64_t m,
+                        int force_constant, uint64_t *bytes) {
+  uint64_t *s, mm, wo, tw;
+  part_code *codes;
+  int st = plan_blob(col, n, dtype, fixed_len, starts, m, force_constant, &s,
+                     &mm, &codes, &wo, &tw, bytes);
+  if (st != LREF_OK) return st;
+  free(s);
+  free(codes);
+  return LREF_OK;
+}
+
+int leco_ref_encode(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
+                    const uint64_t *starts, uint64_t m_in, int force_constant,
+                    uint8_t *blob, uint64_t cap, uint64_t *blob_bytes) {
+  uint64_t *s, m, words_off, total_words, size;
+  part_code *codes;
+  int st = plan_blob(col, n, dtype, fixed_len, starts, m_in, force_constant, &s,
+                     &m, &codes, &words_off, &total_words, &size);
+  if (st != LREF_OK) return st;
+  if (blob_bytes) *blob_bytes = size;
+  if (blob == NULL || cap < size) {
+    free(s);
+    free(codes);
+    return LREF_ENOSPC;
+  }
+  memset(blob, 0, size);
+
+  /* Header: self-describing, all metadata needed to decode (section 3). */
+  uint64_t starts_off = fixed_len > 0 ? 0 : HEADER_BYTES + RECORD_BYTES * m;
+  put_u32(blob + 0, MAGIC);
+  put_u16(blob + 4, VERSION);
+  blob[6] = (uint8_t)dtype;
+  blob[7] = fixed_len > 0 ? 0 : 1;
+  put_u64(blob + 8, n);
+  put_u64(blob + 16, m);
+  put_u64(blob + 24, fixed_len);
+  put_u64(blob + 32, HEADER_BYTES);
+  put_u64(blob + 40, starts_off);
+  put_u64(blob + 48, words_off);
+  put_u64(blob + 56, total_words);
+
+  /* Per-partition records: model (intercept, slope), word offset, width. */
+  uint64_t woff = 0;
+  for (uint64_t j = 0; j < m; j++) {
+    uint8_t *r = blob + HEADER_BYTES + RECORD_BYTES * j;
+    put_u64(r + 0, codes[j].base);
+    put_u64(r + 8, bits_from_f64(codes[j].theta1));
+    put_u64(r + 16, woff);
+    r[24] = (uint8_t)codes[j].bits;
+    woff += codes[j].words;
+  }
+  if (fixed_len == 0)
+    for (uint64_t j = 0; j <= m; j++) put_u64(blob + starts_off + 8 * j, s[j]);
+
+  /* Delta array: residual t of partition j at bits [b*t, b*t + b) of the
+   * partition's word span, least-significant bit first. */
+  uint8_t *words = blob + words_off;
+  woff = 0;
+  for (uint64_t j = 0; j < m; j++) {
+    uint64_t len = s[j + 1] - s[j];
+    uint64_t b = codes[j].bits;
+    for (uint64_t t = 0; t < len && b > 0; t++) {
+      uint64_t v = load_value(col, dtype, s[j] + t);
+      uint64_t u = v - codes[j].base - model_predict(codes[j].theta1, t);
+      uint64_t first = 64 * woff + b * t;
+      for (uint64_t k = 0; k < b; k++)
+        if ((u >> k) & 1u) set_stream_bit(words, first + k);
+    }
+    woff += codes[j].words;
+  }
+  free(s);
+  free(codes);
+  return LREF_OK;
+}
+
+/* ---- Blob parsing ----------------------------------------------------------- */
+
+typedef struct {
+  uint64_t n, m, fixed_len, starts_off, words_off, total_words;
+  int dtype, variable;
+  const uint8_t *blob;
+} blob_view;
+
+static int parse_blob(const uint8_t *blob, uint64_t bytes, blob_view *bv) {
+  if (blob == NULL || bytes < HEADER_BYTES) return LREF_EFORMAT;
+  if (get_u32(blob) != MAGIC) return LREF_EFORMAT;
+  if ((blob[4] | (blob[5] << 8)) != VERSION) return LREF_EFORMAT;
+  bv->dtype = blob[6];
+  bv->variable = blob[7];
+  if (bv->dtype != 4 && bv->dtype != 8) return LREF_EFORMAT;
+  if (bv->variable > 1) return LREF_EFORMAT;
+  bv->n = get_u64(blob + 8);
+  bv->m = get_u64(blob + 16);
+  bv->fixed_len = get_u64(blob + 24);
+  uint64_t records_off = get_u64(blob + 32);
+  bv->starts_off = get_u64(blob + 40);
+  bv->words_off = get_u64(blob + 48);
+  bv->total_words = get_u64(blob + 56);
+  bv->blob = blob;
+  if (records_off != HEADER_BYTES) return LREF_EFORMAT;
+  if (bv->m > bytes / RECORD_BYTES) return LREF_EFORMAT;
+  uint64_t meta_end = HEADER_BYTES + RECORD_BYTES * bv->m;
+  if (bv->variable) {
+    if (bv->fixed_len != 0) return LREF_EFORMAT;
+    if (bv->starts_off != meta_end) return LREF_EFORMAT;
+    meta_end += 8 * (bv->m + 1);
+  } else {
+    if (bv->fixed_len == 0 || bv->fixed_len > MAX_PART_LEN) return LREF_EFORMAT;
+    if (bv->starts_off != 0) return LREF_EFORMAT;
+    uint64_t m = bv->n / bv->fixed_len + (bv->n % bv->fixed_len != 0);
+    if (m != bv->m) return LREF_EFORMAT;
+  }
+  if (bv->words_off != align16(meta_end)) return LREF_EFORMAT;
+  if (bv->total_words > bytes / 8) return LREF_EFORMAT;
+  if (bv->words_off + 8 * bv->total_words > bytes) return LREF_EFORMAT;
+  if (bv->variable) {
+    const uint8_t *sp = blob + bv->starts_off;
+    if (get_u64(sp) != 0 || get_u64(sp + 8 * bv->m) != bv->n) return LREF_EFORMAT;
+    for (uint64_t j = 0; j < bv->m; j++) {
+      uint64_t a = get_u64(sp + 8 * j), b = get_u64(sp + 8 * (j + 1));
+      if (b <= a || b - a > MAX_PART_LEN) return LREF_EFORMAT;
+    }
+  }
+  for (uint64_t j = 0; j < bv->m; j++) {
+    const uint8_t *r = blob + HEADER_BYTES + RECORD_BYTES * j;
+    uint64_t bits = r[24];
+    if (bits > 8u * (uint64_t)bv->dtype) return LREF_EFORMAT;
+    uint64_t start, len;
+    if (bv->variable) {
+      start = get_u64(blob + bv->starts_off + 8 * j);
+      len = get_u64(blob + bv->starts_off + 8 * (j + 1)) - start;
+    } else {
+      start = j * bv->fixed_len;
+      len = (j + 1 == bv->m) ? bv->n - start : bv->fixed_len;
+    }
+    uint64_t words = (len * bits + 63) / 64;
+    uint64_t woff = get_u64(r + 16);
+    if (woff > bv->total_words || words > bv->total_words - woff)
+      return LREF_EFORMAT;
+  }
+  return LREF_OK;
+}
+
+static uint64_t part_start(const blob_view *bv, uint64_t j) {
+  if (bv->variable) return get_u64(bv->blob + bv->starts_off + 8 * j);
+  if (j >= bv->m) return bv->n;
+  return j * bv->fixed_len;
+}
+
+/* Decoder locate step (section 3.3): floor(i / L) for fixed partitions,
+ * else the partition with the largest start <= i. */
+static uint64_t locate(const blob_view *bv, uint64_t i) {
+  if (!bv->variable) return i / bv->fixed_len;
+  uint64_t lo = 0, hi = bv->m; /* answer in [lo, hi) */
+  while (hi - lo > 1) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (part_start(bv, mid) <= i)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+/* Decode one position: predicted value floor(theta1 * t) plus the stored
+ * residual read from bits [b*t, b*(t+1)) of the partition (section 3.3). */
+static uint64_t decode_one(const blob_view *bv, uint64_t i) {
+  uint64_t j = locate(bv, i);
+  const uint8_t *r = bv->blob + HEADER_BYTES + RECORD_BYTES * j;
+  uint64_t base = get_u64(r + 0);
+  double theta1 = f64_from_bits(get_u64(r + 8));
+  uint64_t woff = get_u64(r + 16);
+  uint64_t b = r[24];
+  uint64_t t = i - part_start(bv, j);
+  const uint8_t *words = bv->blob + bv->words_off;
+  uint64_t u = 0;
+  uint64_t first = 64 * woff + b * t;
+  for (uint64_t k = 0; k < b; k++)
+    if (get_stream_bit(words, first + k)) u |= (uint64_t)1 << k;
+  uint64_t v = base + model_predict(theta1, t) + u;
+  if (bv->dtype == 4) v &= 0xffffffffull;
+  return v;
+}
+
+static void store_value(void *out, int dtype, uint64_t q, uint64_t v) {
+  if (dtype == 4)
+    ((uint32_t *)out)[q] = (uint32_t)v;
+  else
+    ((uint64_t *)out)[q] = v;
+}
+
+int leco_ref_blob_info(const uint8_t *blob, uint64_t blob_bytes, uint64_t *n,
+                       int *dtype, uint64_t *m) {
+  blob_view bv;
+  int st = parse_blob(blob, blob_bytes, &bv);
+  if (st != LREF_OK) return st;
+  if (n) *n = bv.n;
+  if (dtype) *dtype = bv.dtype;
+  if (m) *m = bv.m;
+  return LREF_OK;
+}
+
+int leco_ref_blob_record(const uint8_t *blob, uint64_t blob_bytes, uint64_t j,
+                         uint64_t *base, double *theta1, uint64_t *word_off,
+                         uint64_t *bits, uint64_t *start, uint64_t *len) {
+  blob_view bv;
+  int st = parse_blob(blob, blob_bytes, &bv);
+  if (st != LREF_OK) return st;
+  if (j >= bv.m) return LREF_ERANGE;
+  const uint8_t *r = blob + HEADER_BYTES + RECORD_BYTES * j;
+  if (base) *base = get_u64(r);
+  if (theta1) *theta1 = f64_from_bits(get_u64(r + 8));
+  if (word_off) *word_off = get_u64(r + 16);
+  if (bits) *bits = r[24];
+  if (start) *start = part_start(&bv, j);
+  if (len) *len = part_start(&bv, j + 1) - part_start(&bv, j);
+  return LREF_OK;
+}
+
+int leco_ref_decode_all(const uint8_t *blob, uint64_t blob_bytes, void *out,
+                        uint64_t out_cap_elems) {
+  blob_view bv;
+  int st = parse_blob(blob, blob_bytes, &bv);
+  if (st != LREF_OK) return st;
+  if (out_cap_elems < bv.n) return LREF_ENOSPC;
+  for (uint64_t i = 0; i < bv.n; i++) store_value(out, bv.dtype, i, decode_one(&bv, i));
+  return LREF_OK;
+}
+
+int leco_ref_decode_range(const uint8_t *blob, uint64_t blob_bytes,
+                          uint64_t begin, uint64_t end, void *out) {
+  blob_view bv;
+  int st = parse_blob(blob, blob_bytes, &bv);
+  if (st != LREF_OK) return st;
+  if (begin > end || end > bv.n) return LREF_ERANGE;
+  for (uint64_t i = begin; i < end; i++)
+    store_value(out, bv.dtype, i - begin, decode_one(&bv, i));
+  return LREF_OK;
+}
+
+int leco_ref_random_access(const uint8_t *blob, uint64_t blob_bytes,
+                           const uint64_t *pos, uint64_t k, void *out) {
+  blob_view bv;
+  int st = parse_blob(blob, blob_bytes, &bv);
+  if (st != LREF_OK) return st;
+  for (uint64_t q = 0; q < k; q++)
+    if (pos[q] >= bv.n) return LREF_ERANGE;
+  for (uint64_t q = 0; q < k; q++) store_value(out, bv.dtype, q, decode_one(&bv, pos[q]));
+  return LREF_OK;
+}
+
+int leco_ref_filter_sum(const uint8_t *blob, uint64_t blob_bytes, uint64_t lo,
+                        uint64_t hi, uint64_t out[3]) {
+  blob_view bv;
+  int st = parse_blob(blob, blob_bytes, &bv);
+  if (st != LREF_OK) return st;
+  u128 sum = 0;
+  uint64_t count = 0;
+  for (uint64_t i = 0; i < bv.n; i++) {
+    uint64_t v = decode_one(&bv, i);
+    if (lo <= v && v < hi) {
+      sum += v;
+      count++;
+    }
+  }
+  out[0] = (uint64_t)sum;
+  out[1] = (uint64_t)(sum >> 64);
+  out[2] = count;
+  return LREF_OK;
+}
+
+/* ---- Variable-length partitioner (section 3.2.2) ---------------------------- */
+
+/* Signed first difference d_k = v_k - v_{k-1} (exact). */
+static i128 first_diff(const uint64_t *v, uint64_t k) {
+  return (i128)v[k] - (i128)v[k - 1];
+}
+
+/* Width of a signed integer including its sign bit: bitlen(|d|) + 1.
+ * This is the reading under which the worked Delta-encoding example of the
+ * partitioning figure (C = 6, merge 62 < 76) comes out as printed. */
+static uint64_t signed_width(i128 d) {
+  u128 a = d < 0 ? (u128)(-d) : (u128)d;
+  return bitlen128(a) + 1;
+}
+
+/* Delta~(v[i, j)) for the linear regressor: bitlen(max d - min d) over the
+ * first differences inside the partition (k = i+1 .. j-1); 0 without two of
+ * them. */
+static uint64_t approx_linear_width(const uint64_t *v, uint64_t i, uint64_t j) {
+  if (j < i + 2) return 0;
+  i128 dmin = first_diff(v, i + 1), dmax = dmin;
+  for (uint64_t k = i + 2; k < j; k++) {
+    i128 d = first_diff(v, k);
+    if (d < dmin) dmin = d;
+    if (d > dmax) dmax = d;
+  }
+  return bitlen128((u128)(dmax - dmin));
+}
+
+/* Delta(v[i, j)) for Delta encoding: widest signed first difference. */
+static uint64_t delta_width(const uint64_t *v, uint64_t i, uint64_t j) {
+  uint64_t w = 0;
+  for (uint64_t k = i + 1; k < j; k++) {
+    uint64_t s = signed_width(first_diff(v, k));
+    if (s > w) w = s;
+  }
+  return w;
+}
+
+int64_t leco_ref_split_cost(const uint64_t *v, uint64_t i, uint64_t j, int model) {
+  uint64_t len = j - i;
+  uint64_t w_old, w_new;
+  if (model == 1) {
+    w_old = delta_width(v, i, j);
+    w_new = delta_width(v, i, j + 1);
+  } else {
+    w_old = approx_linear_width(v, i, j);
+    w_new = approx_linear_width(v, i, j + 1);
+  }
+  return (int64_t)((len + 1) * w_new) - (int64_t)(len * w_old);
+}
+
+uint64_t leco_ref_delta_partition_bits(const uint64_t *v, uint64_t i, uint64_t j,
+                                       uint64_t sm_bits) {
+  return sm_bits + (j - i) * delta_width(v, i, j);
+}
+
+uint64_t leco_ref_partition_cost_bytes(const uint64_t *v, uint64_t i, uint64_t j) {
+  leco_ref_model md;
+  leco_ref_fit(v + i, j - i, 0, &md);
+  return RECORD_BYTES + 8 + 8 * (((j - i) * md.bits + 63) / 64);
+}
+
+static uint64_t *load_column(const void *col, uint64_t n, int dtype) {
+  uint64_t *v = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+  if (!v) return NULL;
+  for (uint64_t i = 0; i < n; i++) v[i] = load_value(col, dtype, i);
+  return v;
+}
+
+/* Merge phase: scan left to right; merge a partition with its right
+ * neighbour when the merged partition is smaller than the two apart, then
+ * retry the merged partition with its new neighbour; repeat full passes
+ * until one makes no merge. */
+static void merge_phase(const uint64_t *v, uint64_t *s, uint64_t *m_io,
+                        uint64_t max_len) {
+  uint64_t m = *m_io;
+  int changed = 1;
+  while (changed) {
+    changed = 0;
+    uint64_t j = 0;
+    while (j + 1 < m) {
+      uint64_t a = s[j], b = s[j + 1], c = s[j + 2];
+      int merged = 0;
+      if (c - a <= max_len) {
+        uint64_t apart = leco_ref_partition_cost_bytes(v, a, b) +
+                         leco_ref_partition_cost_bytes(v, b, c);
+        uint64_t joint = leco_ref_partition_cost_bytes(v, a, c);
+        if (joint < apart) {
+          for (uint64_t k = j + 1; k < m; k++) s[k] = s[k + 1];
+          m--;
+          changed = 1;
+          merged = 1;
+        }
+      }
+      if (!merged) j++;
+    }
+  }
+  *m_io = m;
+}
+
+int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau,
+                              uint64_t sm_bits, uint64_t max_len,
+                              uint64_t *starts_out, uint64_t *m_out) {
+  if ((dtype != 4 && dtype != 8) || max_len == 0 || max_len > MAX_PART_LEN)
+    return LREF_EINVAL;
+  if (n == 0) {
+    starts_out[0] = 0;
+    *m_out = 0;
+    return LREF_OK;
+  }
+  uint64_t *v = load_column(col, n, dtype);
+  if (!v) return LREF_ENOMEM;
+  double threshold = tau * (double)sm_bits;
+
+  /* Split phase, left to right from position 0: keep the running range of
+   * first differences of the current partition and include v[j] while
+   * C = (len+1) * Delta~new - len * Delta~old <= tau * S_M. */
+  uint64_t m = 0;
+  uint64_t i = 0;
+  starts_out[m++] = 0;
+  i128 dmin = 0, dmax = 0;
+  int have_diff = 0;
+  uint64_t w_old = 0;
+  for (uint64_t j = 1; j < n; j++) {
+    i128 d = first_diff(v, j);
+    i128 nmin = have_diff && dmin < d ? dmin : d;
+    i128 nmax = have_diff && dmax > d ? dmax : d;
+    uint64_t w_new = bitlen128((u128)(nmax - nmin));
+    uint64_t len = j - i;
+    double cost = (double)((int64_t)((len + 1) * w_new) - (int64_t)(len * w_old));
+    if (cost <= threshold && len < max_len) {
+      dmin = nmin;
+      dmax = nmax;
+      have_diff = 1;
+      w_old = w_new;
+    } else {
+      i = j;
+      starts_out[m++] = j;
+      have_diff = 0;
+      w_old = 0;
+    }
+  }
+  starts_out[m] = n;
+  merge_phase(v, starts_out, &m, max_len);
+  free(v);
+  *m_out = m;
+  return LREF_OK;
+}
+
+int leco_ref_partition_merge(const void *col, uint64_t n, int dtype,
+                             uint64_t *starts, uint64_t *m, uint64_t max_len) {
+  if ((dtype != 4 && dtype != 8) || max_len == 0 || max_len > MAX_PART_LEN)
+    return LREF_EINVAL;
+  uint64_t *v = load_column(col, n, dtype);
+  if (!v) return LREF_ENOMEM;
+  merge_phase(v, starts, m, max_len);
+  free(v);
+  return LREF_OK;
+}
+
+int leco_ref_partitioning_cost(const void *col, uint64_t n, int dtype,
+                               const uint64_t *starts, uint64_t m,
+                               uint64_t *bytes_out) {
+  if (dtype != 4 && dtype != 8) return LREF_EINVAL;
+  uint64_t *v = load_column(col, n, dtype);
+  if (!v) return LREF_ENOMEM;
+  uint64_t total = 0;
+  for (uint64_t j = 0; j < m; j++)
+    total += leco_ref_partition_cost_bytes(v, starts[j], starts[j + 1]);
+  free(v);
+  *bytes_out = total;
+  return LREF_OK;
+}
+
+/* Dynamic programming over split points (section 3.2): best[k] is the
+ * smallest total cost of v[0, k). */
+int leco_ref_partition_dp(const void *col, uint64_t n, int dtype, uint64_t max_len,
+                          uint64_t *starts_out, uint64_t *m_out,
+                          uint64_t *bytes_out) {
+  if ((dtype != 4 && dtype != 8) || max_len == 0) return LREF_EINVAL;
+  uint64_t *v = load_column(col, n, dtype);
+  uint64_t *best = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
+  uint64_t *from = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
+  if (!v || !best || !from) {
+    free(v);
+    free(best);
+    free(from);
+    return LREF_ENOMEM;
+  }
+  best[0] = 0;
+  for (uint64_t k = 1; k <= n; k++) {
+    best[k] = UINT64_MAX;
+    for (uint64_t i = 0; i < k; i++) {
+      if (k - i > max_len) continue;
+      uint64_t c = best[i] + leco_ref_partition_cost_bytes(v, i, k);
+      if (c < best[k]) {
+        best[k] = c;
+        from[k] = i;
+      }
+    }
+  }
+  uint64_t m = 0;
+  for (uint64_t k = n; k > 0; k = from[k]) m++;
+  starts_out[m] = n;
+  uint64_t idx = m;
+  for (uint64_t k = n; k > 0; k = from[k]) starts_out[--idx] = from[k];
+  if (n == 0) starts_out[0] = 0;
+  *m_out = m;
+  *bytes_out = best[n];
+  free(v);
+  free(best);
+  free(from);
+  return LREF_OK;
+}
+
+int leco_ref_partition_bruteforce(const void *col, uint64_t n, int dtype,
+                                  uint64_t max_len, uint64_t *starts_out,
+                                  uint64_t *m_out, uint64_t *bytes_out) {
+  if ((dtype != 4 && dtype != 8) || n == 0 || n > 24 || max_len == 0)
+    return LREF_EINVAL;
+  uint64_t *v = load_column(col, n, dtype);
+  if (!v) return LREF_ENOMEM;
+  uint64_t best = UINT64_MAX, best_mask = 0;
+  /* bit k-1 of mask set <=> a partition starts at position k (1 <= k < n) */
+  for (uint64_t mask = 0; mask < (1ull << (n - 1)); mask++) {
+    uint64_t total = 0, a = 0;
+    int ok = 1;
+    for (uint64_t k = 1; k <= n; k++) {
+      if (k == n || ((mask >> (k - 1)) & 1u)) {
+        if (k - a > max_len) {
+          ok = 0;
+          break;
+        }
+        total += leco_ref_partition_cost_bytes(v, a, k);
+        a = k;
+      }
+    }
+    if (ok && total < best) {
+      best = total;
+      best_mask = mask;
+    }
+  }
+  uint64_t m = 0;
+  starts_out[m++] = 0;
+  for (uint64_t k = 1; k < n; k++)
+    if ((best_mask >> (k - 1)) & 1u) starts_out[m++] = k;
+  starts_out[m] = n;
+  *m_out = m;
+  *bytes_out = best;
+  free(v);
+  return LREF_OK;
+}

@@ -1,0 +1,145 @@
+/*
+ * LeCo CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, scalar C implementation of what the learned-compression hot
+ * path computes, written from the LeCo paper (Liu, Zeng, Zhang, "LeCo:
+ * Lightweight Compression via Learning Serial Correlations", SIGMOD 2024).
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  The product path (the HIP library) shares no code,
+ * header, table or constant with it.
+ *
+ * Every function names the passage of the paper it follows.  Where the paper
+ * is silent or ambiguous the reading taken is stated next to the code.
+ *
+ * Conventions: all arrays are host memory owned by the caller.  Columns are
+ * little-endian uint32 (dtype 4) or uint64 (dtype 8).  Functions return one
+ * of the LREF_* status codes below and never abort.
+ */
+#ifndef LECO_ORACLE_H
+#define LECO_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LREF_OK = 0,
+  LREF_EINVAL = 1,  /* bad argument (dtype, partitioning, sizes)      */
+  LREF_ENOMEM = 2,  /* host allocation failed                          */
+  LREF_ENOSPC = 3,  /* output buffer too small; required size returned */
+  LREF_EFORMAT = 4, /* blob fails validation                           */
+  LREF_ERANGE = 5   /* a position or range lies outside [0, n)         */
+};
+
+/* Result of fitting one partition (section 3.1 least squares, section 3.3
+ * storage).  mode 0 = constant model (FOR, section 2), 1 = linear. */
+typedef struct {
+  uint64_t vmin, vmax;
+  uint64_t b_for;      /* bitlen(vmax - vmin)                               */
+  int32_t fitted;      /* 1 when the least-squares fit was evaluated        */
+  int32_t mode;        /* 0 = FOR (slope +0.0), 1 = linear                  */
+  uint64_t N_lo;       /* N = n*S_ty - S_t*S_y as two's-complement int128   */
+  int64_t N_hi;
+  uint64_t D_lo;       /* D = n*S_tt - S_t^2 as uint128                     */
+  uint64_t D_hi;
+  double theta1_ls;    /* fl(N)/fl(D), the fitted slope (0 if not fitted)   */
+  int64_t r_min, r_max;/* residual extremes of the linear model             */
+  uint64_t b_ls;       /* bitlen(r_max - r_min)                             */
+  double theta1;       /* stored slope: theta1_ls in linear mode, else +0.0 */
+  uint64_t base;       /* stored integer intercept                          */
+  uint64_t bits;       /* stored residual width b                           */
+} leco_ref_model;
+
+/* bitlen(x) = floor(log2 x) + 1, bitlen(0) = 0 (the paper's ceil(log2 .)
+ * read as "bits needed to store x"). */
+uint64_t leco_ref_bitlen(uint64_t x);
+
+/* Fit one partition of n values (section 3.1, section 3.3). */
+int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant,
+                 leco_ref_model *out);
+
+/* Exact compressed size in bytes for a column under the given partitioning.
+ * fixed_len > 0 selects fixed partitions; otherwise starts[0..m] is used. */
+int leco_ref_blob_bytes(const void *col, uint64_t n, int dtype,
+                        uint64_t fixed_len, const uint64_t *starts, uint64_t m,
+                        int force_constant, uint64_t *bytes);
+
+/* Encode a column into a self-describing blob (section 3, section 3.3).
+ * On LREF_ENOSPC *blob_bytes holds the required size. */
+int leco_ref_encode(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
+                    const uint64_t *starts, uint64_t m, int force_constant,
+                    uint8_t *blob, uint64_t cap, uint64_t *blob_bytes);
+
+/* Blob header fields. */
+int leco_ref_blob_info(const uint8_t *blob, uint64_t blob_bytes, uint64_t *n,
+                       int *dtype, uint64_t *m);
+
+/* Per-partition model as stored in a blob (for diagnostics). */
+int leco_ref_blob_record(const uint8_t *blob, uint64_t blob_bytes, uint64_t j,
+                         uint64_t *base, double *theta1, uint64_t *word_off,
+                         uint64_t *bits, uint64_t *start, uint64_t *len);
+
+/* Decoder (section 3.3): every position is decoded on its own. */
+int leco_ref_decode_all(const uint8_t *blob, uint64_t blob_bytes, void *out,
+                        uint64_t out_cap_elems);
+int leco_ref_decode_range(const uint8_t *blob, uint64_t blob_bytes,
+                          uint64_t begin, uint64_t end, void *out);
+int leco_ref_random_access(const uint8_t *blob, uint64_t blob_bytes,
+                           const uint64_t *pos, uint64_t k, void *out);
+
+/* Sum and count of decoded values v with lo <= v < hi (section 5.1 filter).
+ * out[0] = low 64 bits of the sum, out[1] = high 64 bits, out[2] = count. */
+int leco_ref_filter_sum(const uint8_t *blob, uint64_t blob_bytes, uint64_t lo,
+                        uint64_t hi, uint64_t out[3]);
+
+/* ---- Variable-length partitioner (section 3.2.2) ------------------------ */
+
+/* Split-phase inclusion cost C of appending v[j] to v[i, j):
+ *   model 0 = linear regressor with the approximation Delta~ (bitlen of the
+ *             range of first differences),
+ *   model 1 = Delta encoding with signed first-difference widths.
+ * Result in bits. */
+int64_t leco_ref_split_cost(const uint64_t *v, uint64_t i, uint64_t j,
+                            int model);
+
+/* Delta-encoding partition size S_M + len * Delta(v[i, j)) in bits, with
+ * Delta = the widest signed first difference inside [i, j). */
+uint64_t leco_ref_delta_partition_bits(const uint64_t *v, uint64_t i,
+                                       uint64_t j, uint64_t sm_bits);
+
+/* Size in bytes that a partition v[i, j) costs in a variable-length blob:
+ * 32-byte record + 8-byte start + its residual words. */
+uint64_t leco_ref_partition_cost_bytes(const uint64_t *v, uint64_t i,
+                                       uint64_t j);
+
+/* Greedy split + merge.  starts_out needs room for n + 1 entries.
+ * max_len caps partition length (<= 2^20). */
+int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype,
+                              double tau, uint64_t sm_bits, uint64_t max_len,
+                              uint64_t *starts_out, uint64_t *m_out);
+
+/* Merge phase alone, applied to a given partitioning (in place). */
+int leco_ref_partition_merge(const void *col, uint64_t n, int dtype,
+                             uint64_t *starts, uint64_t *m, uint64_t max_len);
+
+/* Optimal partitioning by dynamic programming (section 3.2), O(n^3). */
+int leco_ref_partition_dp(const void *col, uint64_t n, int dtype,
+                          uint64_t max_len, uint64_t *starts_out,
+                          uint64_t *m_out, uint64_t *bytes_out);
+
+/* Exhaustive search over all 2^(n-1) partitionings (n <= 24). */
+int leco_ref_partition_bruteforce(const void *col, uint64_t n, int dtype,
+                                  uint64_t max_len, uint64_t *starts_out,
+                                  uint64_t *m_out, uint64_t *bytes_out);
+
+/* Sum of leco_ref_partition_cost_bytes over a partitioning. */
+int leco_ref_partitioning_cost(const void *col, uint64_t n, int dtype,
+                               const uint64_t *starts, uint64_t m,
+                               uint64_t *bytes_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,163 @@
+"""Seeded synthetic inputs shaped like the LeCo paper's integer workloads.
+
+This module only draws inputs; it holds none of the codec's arithmetic and is
+shared by the tests, the benchmark and the smoke check, which hand the same
+arrays to the GPU path and to the CPU oracle.
+
+The paper's data sets (sorted 200M-key SOSD-style sets, piecewise-linear ID
+columns, columns with runs of repeated values; section 4.1) are not
+available, so each generator reproduces the described shape instead:
+
+* ``linear_noise``  v_i = 1000 + 7 i + U{0..63}                   (fixed L=1024)
+* ``lognormal_keys`` sorted keys, cumulative sum of max(1, rint(lognormal(3, 1.5)))
+* ``sorted_normal`` sorted samples of N(2^30, 2^26) clipped to uint32
+* ``piecewise_linear`` 1000 random segments, slopes U[0, 50), noise U{0..255}
+* ``constant_runs`` runs of one value, geometric run lengths with mean 64
+"""
+from __future__ import annotations
+
+import numpy as np
+
+U32_MAX = (1 << 32) - 1
+
+# Workload sizes and seeds.
+C1_N, C1_L, C1_SEED, C1_RA, C1_RA_SEED = 1_000_000, 1024, 1, 100_000, 11
+C2_N, C2_L, C2_SEED, C2_RA, C2_RA_SEED = 200_000_000, 4096, 2, 100_000_000, 21
+C3_N, C3_SEEDS = 100_000_000, (31, 32, 33)
+C4_COLS, C4_SEED = 4096, 41
+C5_COLS, C5_N, C5_SEED = 64, 39_062_500, 51
+
+
+def linear_noise(n: int = C1_N, seed: int = C1_SEED, dtype=np.uint64) -> np.ndarray:
+    """v_i = 1000 + 7*i + U{0..63}."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(n, dtype=np.uint64)
+    v = np.uint64(1000) + np.uint64(7) * i + rng.integers(0, 64, size=n, dtype=np.uint64)
+    return v.astype(dtype)
+
+
+def lognormal_keys(n: int = C2_N, seed: int = C2_SEED, dtype=np.uint64) -> np.ndarray:
+    """Sorted keys: cumulative sum of integer gaps max(1, rint(lognormal(3, 1.5)))."""
+    rng = np.random.default_rng(seed)
+    g = np.rint(rng.lognormal(3.0, 1.5, size=n))
+    np.maximum(g, 1.0, out=g)
+    keys = np.cumsum(g.astype(np.uint64))
+    if dtype == np.uint32:
+        assert n == 0 or int(keys[-1]) <= U32_MAX, "keys overflow uint32"
+    return keys.astype(dtype, copy=False)
+
+
+def sorted_normal(n: int = C3_N, seed: int = C3_SEEDS[0]) -> np.ndarray:
+    """Sorted samples of N(2^30, std 2^26), rounded and clipped to uint32."""
+    rng = np.random.default_rng(seed)
+    x = np.rint(rng.normal(float(1 << 30), float(1 << 26), size=n))
+    np.clip(x, 0, U32_MAX, out=x)
+    x.sort()
+    return x.astype(np.uint32)
+
+
+def piecewise_linear(n: int = C3_N, seed: int = C3_SEEDS[1], segments: int = 1000) -> np.ndarray:
+    """Continuous polyline from 0 over `segments` random pieces with slopes in
+    U[0, 50), plus integer noise U{0..255}."""
+    rng = np.random.default_rng(seed)
+    cuts = np.sort(rng.choice(np.arange(1, n), size=min(segments - 1, max(n - 1, 0)),
+                              replace=False)) if n > 1 else np.zeros(0, dtype=np.int64)
+    bounds = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+    slopes = rng.uniform(0.0, 50.0, size=len(bounds) - 1)
+    y = np.empty(n, dtype=np.float64)
+    level = 0.0
+    for s, a, b in zip(slopes, bounds[:-1], bounds[1:]):
+        y[a:b] = level + s * np.arange(b - a, dtype=np.float64)
+        level += s * (b - a)
+    v = np.floor(y).astype(np.uint64) + rng.integers(0, 256, size=n, dtype=np.uint64)
+    assert n == 0 or int(v.max()) <= U32_MAX, "piecewise column overflows uint32"
+    return v.astype(np.uint32)
+
+
+def constant_runs(n: int = C3_N, seed: int = C3_SEEDS[2], mean_run: int = 64) -> np.ndarray:
+    """Runs of one uniform uint32 value with Geometric(1/mean_run) lengths."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(n, dtype=np.uint32)
+    filled = 0
+    while filled < n:
+        k = max(16, (n - filled) // mean_run + 16)
+        runs = rng.geometric(1.0 / mean_run, size=k)
+        vals = rng.integers(0, 1 << 32, size=k, dtype=np.uint64).astype(np.uint32)
+        chunk = np.repeat(vals, runs)[: n - filled]
+        out[filled: filled + len(chunk)] = chunk
+        filled += len(chunk)
+    return out
+
+
+def uniform_positions(n: int, k: int, seed: int) -> np.ndarray:
+    """k uniform random positions in [0, n)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, n, size=k, dtype=np.uint64)
+
+
+def batched_columns(ncols: int = C4_COLS, seed: int = C4_SEED, lo: float = 1e3,
+                    hi: float = 1e7, median: float = 1.3e5, sigma: float = 1.7):
+    """Column specs for the batched workload: lognormal lengths clipped to
+    [lo, hi]; per column uint32 or uint64 and a linear-noise (L=1024) or
+    lognormal-keys (L=4096) generator, each with its own seed.  Returns a
+    list of dicts; call ``make_column`` to draw one."""
+    rng = np.random.default_rng(seed)
+    lens = np.clip(np.rint(np.exp(rng.normal(np.log(median), sigma, size=ncols))), lo, hi)
+    specs = []
+    for c in range(ncols):
+        specs.append(dict(
+            n=int(lens[c]),
+            dtype=np.uint32 if rng.integers(0, 2) == 0 else np.uint64,
+            kind="linear_noise" if rng.integers(0, 2) == 0 else "lognormal_keys",
+            seed=int(rng.integers(0, 2**31)),
+        ))
+    for s in specs:
+        s["fixed_len"] = C1_L if s["kind"] == "linear_noise" else C2_L
+    return specs
+
+
+def make_column(spec: dict) -> np.ndarray:
+    if spec["kind"] == "linear_noise":
+        return linear_noise(spec["n"], spec["seed"], spec["dtype"])
+    return lognormal_keys(spec["n"], spec["seed"], spec["dtype"])
+
+
+def filter_bounds(col: np.ndarray) -> tuple[int, int]:
+    """[vmin + R/4, vmin + 3R/4) for a column with range R = vmax - vmin."""
+    vmin, vmax = int(col.min()), int(col.max())
+    r = vmax - vmin
+    return vmin + r // 4, vmin + (3 * r) // 4
+
+
+def served_columns(ncols: int = C5_COLS, n: int = C5_N, seed: int = C5_SEED):
+    """Column specs for the served workload: uint64 columns alternating the
+    linear-noise and lognormal-keys generators."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for c in range(ncols):
+        kind = "linear_noise" if c % 2 == 0 else "lognormal_keys"
+        specs.append(dict(n=n, dtype=np.uint64, kind=kind, seed=int(rng.integers(0, 2**31)),
+                          fixed_len=C1_L if kind == "linear_noise" else C2_L))
+    return specs
+
+
+def request_stream(num: int, col_lens, seed: int = C5_SEED + 1, rate: float = 1.0):
+    """Poisson request stream: arrival times (seconds, mean gap 1/rate), half
+    random-access batches of floor(2^U[0,16]) positions, half range scans of
+    floor(10^U[3,7]) values, each on a uniform column."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=num)
+    t = np.cumsum(gaps)
+    reqs = []
+    for q in range(num):
+        c = int(rng.integers(0, len(col_lens)))
+        n = int(col_lens[c])
+        if rng.integers(0, 2) == 0:
+            k = int(np.floor(2.0 ** rng.uniform(0, 16)))
+            pos = rng.integers(0, n, size=k, dtype=np.uint64)
+            reqs.append(dict(t=float(t[q]), kind="ra", col=c, positions=pos))
+        else:
+            ln = min(int(np.floor(10.0 ** rng.uniform(3, 7))), n)
+            b = int(rng.integers(0, n - ln + 1))
+            reqs.append(dict(t=float(t[q]), kind="range", col=c, begin=b, end=b + ln))
+    return reqs
