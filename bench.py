@@ -1,0 +1,202 @@
+"""Benchmark of the LeCo hot path on one MI355X.
+
+Workload (sorted 64-bit keys): 200,000,000 uint64 keys, the cumulative sum
+of max(1, rint(lognormal(3, 1.5))) gaps (seed 2), fixed partitions of 4096
+values, and 100,000,000 uniform random positions (seed 21).  The column is
+encoded once on the GPU (and checked against the input); a step is one
+decode_all of the whole column plus one random_access of all positions, with
+inputs and blob resident in HBM.
+
+Prints one JSON line.  `value` is decoded output GB/s of decode_all, from
+HIP events around each decode_all launch on the stream it runs on;
+`roofline` prices that kernel's algorithmic bytes (compressed bytes read
+plus output bytes written) against the 8 TB/s HBM peak.  `cpu_baseline`
+times the CPU oracle on the first 50,331,648 values of the same column.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=200_000_000)
+    ap.add_argument("--lookups", type=int, default=100_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=12 * 4096 * 1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(col: np.ndarray, pos: np.ndarray, sample: int, L: int, gpu_blob: np.ndarray):
+    """Times the oracle (single thread) on the first `sample` values and
+    checks the GPU blob's leading partitions against the oracle's bytes."""
+    import oracle
+    sample = min(sample, len(col)) // L * L
+    part = col[:sample]
+    t0 = time.perf_counter()
+    blob = oracle.encode(part, fixed_len=L)
+    t_enc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dec = oracle.decode_all(blob)
+    t_dec = time.perf_counter() - t0
+    assert np.array_equal(dec, part)
+    p = pos[pos < sample][:2_000_000]
+    t0 = time.perf_counter()
+    ra = oracle.random_access(blob, p)
+    t_ra = time.perf_counter() - t0
+    assert np.array_equal(ra, part[p])
+    # prefix parity: records and words of the sampled partitions
+    m = sample // L
+    hdr = blob[:64].view(np.uint64)
+    words_off, tw = int(hdr[6]), int(hdr[7])
+    ghdr = gpu_blob[:64].view(np.uint64)
+    g_words_off = int(ghdr[6])
+    assert np.array_equal(gpu_blob[64: 64 + 32 * m], blob[64: 64 + 32 * m]), "record parity"
+    assert np.array_equal(gpu_blob[g_words_off: g_words_off + 8 * tw],
+                          blob[words_off: words_off + 8 * tw]), "word parity"
+    return dict(value=sample * 8 / t_dec / 1e9, unit="GB/s", cores=1, kind="oracle",
+                sample=f"first {sample} values ({m} partitions of {L}): decode_all "
+                       f"{t_dec:.2f} s; encode {t_enc:.2f} s ({sample * 8 / t_enc / 1e9:.3f} GB/s); "
+                       f"random_access of {len(p)} positions {t_ra:.2f} s "
+                       f"({len(p) / t_ra:.3e} lookups/s)",
+                encode_GBps=sample * 8 / t_enc / 1e9, lookups_per_s=len(p) / t_ra)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the codec has "
+              "no multi-GPU path in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2306_15374_amd as P
+    from paper_2306_15374_amd import workloads as W
+
+    L = W.C2_L
+    log(f"generating {args.n} keys and {args.lookups} positions")
+    col = W.lognormal_keys(args.n, W.C2_SEED)
+    pos = W.uniform_positions(args.n, args.lookups, W.C2_RA_SEED)
+    codec = P.Codec(0)
+    stream = torch.cuda.current_stream()
+    d_col = torch.from_numpy(col).cuda()
+    d_pos = torch.from_numpy(pos).cuda()
+    torch.cuda.synchronize()
+
+    log("encoding on the GPU")
+    t0 = time.perf_counter()
+    blob = codec.encode(d_col, fixed_len=L)
+    torch.cuda.synchronize()
+    t_enc_first = time.perf_counter() - t0
+    # timed re-encode into the same buffer (scratch already allocated)
+    part, _ = P.make_partitioning(fixed_len=L)
+    cap = P.leco_max_blob_bytes(args.n, P.LECO_U64, part)
+    buf = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    st, size = P.leco_encode(codec.ctx, d_col, args.n, P.LECO_U64, part, buf, cap)
+    e1.record(stream)
+    codec.check("leco_encode", st)
+    torch.cuda.synchronize()
+    t_enc = e0.elapsed_time(e1) / 1e3
+    blob_bytes = blob.numel()
+    assert size == blob_bytes and torch.equal(buf[:size], blob)
+    ratio = blob_bytes / (args.n * 8)
+    log(f"blob {blob_bytes} bytes, ratio {ratio:.4f}, encode {t_enc * 1e3:.2f} ms")
+
+    out = torch.empty(args.n, dtype=torch.uint64, device="cuda")
+    ra_out = torch.empty(args.lookups, dtype=torch.uint64, device="cuda")
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        codec.check("leco_decode_all", P.leco_decode_all(codec.ctx, blob, blob_bytes, out, args.n))
+        if ev is not None:
+            ev[1].record(stream)
+        codec.check("leco_random_access", P.leco_random_access(codec.ctx, blob, blob_bytes, d_pos,
+                                                               args.lookups, ra_out))
+        if ev is not None:
+            ev[2].record(stream)
+
+    log("parity at full size")
+    step()
+    codec.sync()
+    assert torch.equal(out.view(torch.int64), d_col.view(torch.int64)), "decode_all != input"
+    assert torch.equal(ra_out.view(torch.int64), d_col.view(torch.int64)[d_pos.view(torch.int64)]), \
+        "random_access != input[pos]"
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    codec.sync()
+    t_dec = np.mean([e[0].elapsed_time(e[1]) for e in evs]) / 1e3
+    t_ra = np.mean([e[1].elapsed_time(e[2]) for e in evs]) / 1e3
+    out_bytes = args.n * 8
+    dec_gbps = out_bytes / t_dec / 1e9
+    alg_bytes = blob_bytes + out_bytes
+    lookups = args.lookups / t_ra
+    ra_alg = args.lookups * (8 + 8 + 8)        # position, output, residual word
+    ra_gran = args.lookups * (8 + 8 + 64)      # residual touch at 64-byte granularity
+    log(f"decode_all {t_dec * 1e3:.3f} ms = {dec_gbps:.1f} GB/s decoded, "
+        f"{alg_bytes / t_dec / 1e9:.1f} GB/s algorithmic; random_access {t_ra * 1e3:.2f} ms = "
+        f"{lookups:.3e} lookups/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(col, pos, args.cpu_sample, L, blob.cpu().numpy())
+
+    res = {
+        "metric": "decoded GB/s + lookups/s vs HBM roofline (batched/served vs plain); p99 latency",
+        "value": round(dec_gbps, 2),
+        "unit": "GB/s decoded (decode_all output)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic (seeded lognormal-gap sorted keys)",
+        "config": {"workload": "sorted uint64 keys, 200M values, partitions of 4096, "
+                               "decode_all + 100M uniform random_access",
+                   "n": args.n, "partition_len": L, "lookups": args.lookups},
+        "lookups_per_s": round(lookups, 1),
+        "random_access_ms": round(t_ra * 1e3, 4),
+        "random_access_hbm_frac": {"algorithmic_24B": round(ra_alg / t_ra / HBM_PEAK, 4),
+                                   "granular_80B": round(ra_gran / t_ra / HBM_PEAK, 4)},
+        "decode_all_ms": round(t_dec * 1e3, 4),
+        "compression_ratio": round(ratio, 5),
+        "encode_GBps": round(out_bytes / t_enc / 1e9, 2),
+        "roofline": {"bound": "hbm", "achieved": round(alg_bytes / t_dec / 1e9, 1),
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": round(alg_bytes / t_dec / HBM_PEAK, 4), "traffic": None,
+                     "kernel": "k_decode", "bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    codec.close()
+
+
+if __name__ == "__main__":
+    main()

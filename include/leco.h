@@ -1,0 +1,188 @@
+/*
+ * leco.h -- C ABI of the MI355X (gfx950) LeCo codec.
+ *
+ * LeCo (Liu, Zeng, Zhang, "LeCo: Lightweight Compression via Learning Serial
+ * Correlations", SIGMOD 2024) stores an integer column as partitions, each
+ * with a regression model and a fixed-width bit-packed array of residuals;
+ * value[i] = model_j(i - start_j) + residual[i] (section 3, problem
+ * statement; section 3.3, encoder and decoder).  This library runs every
+ * step of encoding and decoding in HIP kernels on one GPU.
+ *
+ * Memory and ownership
+ *   - Arguments ending in `_dev` are device pointers owned by the caller
+ *     (allocated with hipMalloc or as torch tensors).  Arguments ending in
+ *     `_host` are host pointers owned by the caller.  The library never frees
+ *     or retains caller memory beyond the call, except resident blobs handed
+ *     to a server (see leco_server_*), which must stay valid until
+ *     leco_server_stop returns.
+ *   - Calls taking a `stream` only enqueue work on that stream and return;
+ *     results are valid once the stream has reached that point.  Calls marked
+ *     [sync] wait for the stream before returning.
+ *   - A context is not thread-safe: use one per host thread.  Contexts on the
+ *     same device may be used concurrently.
+ *
+ * Errors
+ *   - Every call returns a leco_status.  Argument errors are detected on the
+ *     host before any work is enqueued (LECO_EINVAL, LECO_ENOSPC).
+ *   - Conditions only the GPU can see (a position >= n, a blob whose header,
+ *     records or starts fail validation, an encode output larger than its
+ *     capacity) raise a per-context device flag.  The kernels never read or
+ *     write outside the buffers described by the call's sizes, whatever the
+ *     blob holds; the output for the offending elements is unspecified.  The
+ *     flag is reported, and cleared, by the next leco_sync on the context.
+ *   - leco_last_error returns a description of the last failure.
+ *
+ * Blob format (section 3.3, storage format; little-endian, zero padding)
+ *   header, 64 B: magic "LECO" u32, version u16 = 1, dtype u8 (4 or 8),
+ *     flags u8 (bit 0 = variable-length partitions), n u64, m u64,
+ *     fixed_len u64 (0 if variable), records_off u64 (= 64), starts_off u64
+ *     (0 if fixed), words_off u64, total_words u64;
+ *   records, m x 32 B: intercept `base` u64, slope theta1 as binary64 bits,
+ *     word_off u64 (in 64-bit words, relative to words_off), bit width b u8,
+ *     7 zero bytes;
+ *   starts (variable only): m + 1 u64, starts[0] = 0, starts[m] = n;
+ *   words: begins at the 16-byte-aligned end of the previous section;
+ *     residual t of partition j occupies bits [b*t, b*t + b) of the span that
+ *     begins at word word_off_j, least-significant bit first; each partition
+ *     starts on a fresh word; the blob ends on a 16-byte boundary.
+ *   Total size: align16(align16(64 + 32 m [+ 8 (m + 1)]) + 8 * total_words).
+ *
+ * Model arithmetic (section 3.1 regressor; section 3.3 decoder)
+ *   For partition values v_t (t = 0..n_j-1), vmin/vmax and R = vmax - vmin:
+ *   if n_j = 1, R >= 2^61, or the constant model is forced, the partition
+ *   uses the constant model (frame of reference): theta1 = +0.0,
+ *   base = vmin, b = bitlen(R).  Otherwise the least-squares slope is
+ *   theta1 = fl(N) / fl(D) with N = n*S_ty - S_t*S_y and D = n*S_tt - S_t^2
+ *   from exact integer sums over y_t = v_t - vmin, each converted to binary64
+ *   with round-to-nearest-even and divided once (IEEE); -0.0 becomes +0.0.
+ *   Residuals r_t = y_t - floor(theta1 * t) (one binary64 multiply, no fused
+ *   multiply-add).  If bitlen(R) <= bitlen(max r - min r) the constant model
+ *   is kept; else base = vmin + min r (mod 2^64), b = bitlen(max r - min r).
+ *   Decoding: v = base + floor(theta1 * t) + u (mod 2^64), truncated to the
+ *   column's dtype.
+ */
+#ifndef LECO_H
+#define LECO_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct leco_ctx leco_ctx;
+
+typedef enum {
+  LECO_OK = 0,
+  LECO_EINVAL = 1,  /* bad argument or partitioning                         */
+  LECO_ENOMEM = 2,  /* device or host allocation failed                     */
+  LECO_ENOSPC = 3,  /* output buffer too small (required size is returned)  */
+  LECO_EFORMAT = 4, /* blob failed validation                               */
+  LECO_ERANGE = 5,  /* position or range outside [0, n)                     */
+  LECO_EDEVICE = 6  /* HIP runtime error                                    */
+} leco_status;
+
+typedef enum { LECO_U32 = 4, LECO_U64 = 8 } leco_dtype;
+
+/* Partition assignment (section 3, problem statement; section 3.2).
+ *   fixed_len > 0: fixed partitions of fixed_len values (section 3.2.1), the
+ *                  last one possibly shorter; starts_host is ignored.
+ *   fixed_len = 0: variable partitions (section 3.2.2) given by
+ *                  starts_host[0..num_partitions], strictly increasing,
+ *                  starts_host[0] = 0 and starts_host[num_partitions] = n.
+ *   Every partition holds 1..2^20 values.
+ *   force_constant_model = 1 stores every partition with slope +0.0, which is
+ *   exactly frame-of-reference encoding (section 2). */
+typedef struct {
+  uint64_t fixed_len;
+  const uint64_t *starts_host;
+  uint64_t num_partitions;
+  int32_t force_constant_model;
+  int32_t reserved; /* must be 0 */
+} leco_partitioning;
+
+/* Context on HIP device `hip_device`.  Owns the device error flag, scratch
+ * buffers and the tuning table. */
+leco_status leco_create(int hip_device, leco_ctx **out);
+leco_status leco_destroy(leco_ctx *ctx); /* [sync] on the whole device */
+const char *leco_last_error(const leco_ctx *ctx);
+
+/* Waits for `stream`, then reports and clears the context's device flag:
+ * LECO_ERANGE, LECO_EFORMAT or LECO_ENOSPC if a kernel raised one. [sync] */
+leco_status leco_sync(leco_ctx *ctx, hipStream_t stream);
+
+/* Upper bound of the blob size for any column of n values of this dtype
+ * under this partitioning (every residual at full dtype width). */
+leco_status leco_max_blob_bytes(uint64_t n, leco_dtype dtype,
+                                const leco_partitioning *part, uint64_t *bytes);
+
+/* Parses a host copy of the 64-byte blob header. */
+leco_status leco_blob_info(const void *header_host, uint64_t *n,
+                           leco_dtype *dtype, uint64_t *num_partitions);
+
+/* Full host-side validation of a blob in device memory: copies its header,
+ * records and starts to the host and checks every field. [sync] */
+leco_status leco_validate_blob(leco_ctx *ctx, const void *blob_dev,
+                               uint64_t blob_bytes, hipStream_t stream);
+
+/* Encoder (section 3.3): fits every partition (section 3.1), computes the
+ * residuals and their width, and bit-packs them into blob_dev.
+ *   col_dev: n values of `dtype`.  blob_dev: blob_cap bytes.
+ *   On success *blob_bytes_host is the blob size.  If blob_cap is smaller
+ *   than the size, returns LECO_ENOSPC with the required size in
+ *   *blob_bytes_host and the contents of blob_dev unspecified.  [sync] */
+leco_status leco_encode(leco_ctx *ctx, const void *col_dev, uint64_t n,
+                        leco_dtype dtype, const leco_partitioning *part,
+                        void *blob_dev, uint64_t blob_cap,
+                        uint64_t *blob_bytes_host, hipStream_t stream);
+
+/* Same as leco_encode without waiting: requires blob_cap >=
+ * leco_max_blob_bytes(...) and writes the blob size to *blob_bytes_dev. */
+leco_status leco_encode_async(leco_ctx *ctx, const void *col_dev, uint64_t n,
+                              leco_dtype dtype, const leco_partitioning *part,
+                              void *blob_dev, uint64_t blob_cap,
+                              uint64_t *blob_bytes_dev, hipStream_t stream);
+
+/* Decoder, full column (section 3.3, range decompression over [0, n)).
+ *   out_dev: room for out_cap_elems values of the blob's dtype.  A blob with
+ *   n > out_cap_elems raises LECO_ENOSPC on the device flag. */
+leco_status leco_decode_all(leco_ctx *ctx, const void *blob_dev,
+                            uint64_t blob_bytes, void *out_dev,
+                            uint64_t out_cap_elems, hipStream_t stream);
+
+/* Decoder, positions [begin, end) into out_dev[0 .. end - begin)
+ * (section 3.3, range decompression).  end > n raises LECO_ERANGE. */
+leco_status leco_decode_range(leco_ctx *ctx, const void *blob_dev,
+                              uint64_t blob_bytes, uint64_t begin, uint64_t end,
+                              void *out_dev, hipStream_t stream);
+
+/* Random access (section 3.3): out_dev[q] = value at pos_dev[q], q < k, in
+ * request order.  pos_dev: k uint64 positions in device memory.  A position
+ * >= n raises LECO_ERANGE and leaves out_dev[q] unspecified. */
+leco_status leco_random_access(leco_ctx *ctx, const void *blob_dev,
+                               uint64_t blob_bytes, const uint64_t *pos_dev,
+                               uint64_t k, void *out_dev, hipStream_t stream);
+
+/* Range-filter sum over the decoded column (the filter of section 5.1,
+ * with the model-bound pruning described there): writes
+ * out3_dev[0] = low 64 bits and out3_dev[1] = high 64 bits of the exact sum
+ * of values v with lo <= v < hi, out3_dev[2] = their count. */
+leco_status leco_filter_sum(leco_ctx *ctx, const void *blob_dev,
+                            uint64_t blob_bytes, uint64_t lo, uint64_t hi,
+                            uint64_t *out3_dev, hipStream_t stream);
+
+/* ---- Diagnostics ------------------------------------------------------------
+ * Evaluates the slope arithmetic of the encoder (section 3.1, least-squares
+ * closed form) on the GPU for k given pairs: in_dev holds 4 uint64 per pair,
+ * (N low, N high) as a two's-complement int128 and (D low, D high) as an
+ * unsigned int128 (D > 0); out_dev[i] = fl(N) / fl(D), with each integer
+ * rounded to nearest-even binary64 and one IEEE division, -0.0 mapped to
+ * +0.0 -- exactly the encoder's theta1. */
+leco_status leco_diag_slope(leco_ctx *ctx, const uint64_t *in_dev, uint64_t k,
+                            double *out_dev, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LECO_H */

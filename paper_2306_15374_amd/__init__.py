@@ -1,0 +1,285 @@
+"""MI355X-native LeCo codec: Python binding of ``libleco_hip.so``.
+
+Argument marshalling only: every step of encoding and decoding runs in the
+HIP kernels of the library (see ``include/leco.h`` for the C ABI and the
+blob format).  PyTorch supplies device memory and streams.  There is no CPU
+fallback: if the library is missing, every call raises.
+
+Low-level functions carry the C names (``leco_encode``, ``leco_decode_all``,
+...), take a context, torch CUDA tensors and a stream, and return the
+status.  ``Codec`` wraps them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libleco_hip.so")
+
+LECO_OK, LECO_EINVAL, LECO_ENOMEM, LECO_ENOSPC, LECO_EFORMAT, LECO_ERANGE, LECO_EDEVICE = range(7)
+LECO_U32, LECO_U64 = 4, 8
+STATUS_NAMES = {0: "LECO_OK", 1: "LECO_EINVAL", 2: "LECO_ENOMEM", 3: "LECO_ENOSPC",
+                4: "LECO_EFORMAT", 5: "LECO_ERANGE", 6: "LECO_EDEVICE"}
+
+# Every symbol include/leco.h declares (checked by the ABI tests).
+EXPORTS = [
+    "leco_create", "leco_destroy", "leco_last_error", "leco_sync", "leco_max_blob_bytes",
+    "leco_blob_info", "leco_validate_blob", "leco_encode", "leco_encode_async",
+    "leco_decode_all", "leco_decode_range", "leco_random_access", "leco_filter_sum",
+    "leco_diag_slope",
+]
+
+
+class LecoError(RuntimeError):
+    def __init__(self, fn: str, status: int, detail: str = ""):
+        super().__init__(f"{fn}: {STATUS_NAMES.get(status, status)} {detail}".strip())
+        self.status = status
+
+
+class Partitioning(C.Structure):
+    _fields_ = [("fixed_len", C.c_uint64), ("starts_host", C.c_void_p),
+                ("num_partitions", C.c_uint64), ("force_constant_model", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2306_15374_amd.build`")
+        _lib = _bind(C.CDLL(LIB_PATH))
+    return _lib
+
+
+def _bind(L: C.CDLL) -> C.CDLL:
+    u64, vp, i32 = C.c_uint64, C.c_void_p, C.c_int
+    P = C.POINTER
+    sig = {
+        "leco_create": ([i32, P(vp)], i32),
+        "leco_destroy": ([vp], i32),
+        "leco_last_error": ([vp], C.c_char_p),
+        "leco_sync": ([vp, vp], i32),
+        "leco_max_blob_bytes": ([u64, i32, P(Partitioning), P(u64)], i32),
+        "leco_blob_info": ([vp, P(u64), P(i32), P(u64)], i32),
+        "leco_validate_blob": ([vp, vp, u64, vp], i32),
+        "leco_encode": ([vp, vp, u64, i32, P(Partitioning), vp, u64, P(u64), vp], i32),
+        "leco_encode_async": ([vp, vp, u64, i32, P(Partitioning), vp, u64, vp, vp], i32),
+        "leco_decode_all": ([vp, vp, u64, vp, u64, vp], i32),
+        "leco_decode_range": ([vp, vp, u64, u64, u64, vp, vp], i32),
+        "leco_random_access": ([vp, vp, u64, vp, u64, vp, vp], i32),
+        "leco_filter_sum": ([vp, vp, u64, u64, u64, vp, vp], i32),
+        "leco_diag_slope": ([vp, vp, u64, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype in (torch.uint32, torch.int32):
+        return LECO_U32
+    if t.dtype in (torch.uint64, torch.int64):
+        return LECO_U64
+    raise TypeError(f"column dtype must be 32- or 64-bit integer, got {t.dtype}")
+
+
+def make_partitioning(fixed_len: int = 0, starts=None, force_constant: bool = False):
+    """Returns (Partitioning, keepalive) for a fixed length or host starts."""
+    import numpy as np
+    if fixed_len:
+        return Partitioning(fixed_len, None, 0, int(force_constant), 0), None
+    s = np.ascontiguousarray(starts, dtype=np.uint64)
+    return Partitioning(0, s.ctypes.data, len(s) - 1, int(force_constant), 0), s
+
+
+# ---- C-named wrappers ----------------------------------------------------------
+
+def leco_create(device: int = 0) -> int:
+    h = C.c_void_p()
+    st = lib().leco_create(device, C.byref(h))
+    if st != LECO_OK:
+        raise LecoError("leco_create", st)
+    return h.value
+
+
+def leco_destroy(ctx: int) -> int:
+    return lib().leco_destroy(ctx)
+
+
+def leco_last_error(ctx: int) -> str:
+    return (lib().leco_last_error(ctx) or b"").decode()
+
+
+def leco_sync(ctx: int, stream=None) -> int:
+    return lib().leco_sync(ctx, _stream(stream))
+
+
+def leco_max_blob_bytes(n: int, dtype: int, part: Partitioning) -> int:
+    out = C.c_uint64()
+    st = lib().leco_max_blob_bytes(n, dtype, C.byref(part), C.byref(out))
+    if st != LECO_OK:
+        raise LecoError("leco_max_blob_bytes", st)
+    return out.value
+
+
+def leco_blob_info(header_bytes: bytes):
+    buf = C.create_string_buffer(bytes(header_bytes[:64]), 64)
+    n, dt, m = C.c_uint64(), C.c_int(), C.c_uint64()
+    st = lib().leco_blob_info(buf, C.byref(n), C.byref(dt), C.byref(m))
+    if st != LECO_OK:
+        raise LecoError("leco_blob_info", st)
+    return n.value, dt.value, m.value
+
+
+def leco_validate_blob(ctx: int, blob, blob_bytes: int, stream=None) -> int:
+    return lib().leco_validate_blob(ctx, _ptr(blob), blob_bytes, _stream(stream))
+
+
+def leco_encode(ctx: int, col, n: int, dtype: int, part: Partitioning, blob, blob_cap: int,
+                stream=None) -> tuple[int, int]:
+    size = C.c_uint64()
+    st = lib().leco_encode(ctx, _ptr(col), n, dtype, C.byref(part), _ptr(blob), blob_cap,
+                           C.byref(size), _stream(stream))
+    return st, size.value
+
+
+def leco_encode_async(ctx: int, col, n: int, dtype: int, part: Partitioning, blob,
+                      blob_cap: int, size_dev, stream=None) -> int:
+    return lib().leco_encode_async(ctx, _ptr(col), n, dtype, C.byref(part), _ptr(blob),
+                                   blob_cap, _ptr(size_dev), _stream(stream))
+
+
+def leco_decode_all(ctx: int, blob, blob_bytes: int, out, out_cap: int, stream=None) -> int:
+    return lib().leco_decode_all(ctx, _ptr(blob), blob_bytes, _ptr(out), out_cap, _stream(stream))
+
+
+def leco_decode_range(ctx: int, blob, blob_bytes: int, begin: int, end: int, out,
+                      stream=None) -> int:
+    return lib().leco_decode_range(ctx, _ptr(blob), blob_bytes, begin, end, _ptr(out),
+                                   _stream(stream))
+
+
+def leco_random_access(ctx: int, blob, blob_bytes: int, pos, k: int, out, stream=None) -> int:
+    return lib().leco_random_access(ctx, _ptr(blob), blob_bytes, _ptr(pos), k, _ptr(out),
+                                    _stream(stream))
+
+
+def leco_filter_sum(ctx: int, blob, blob_bytes: int, lo: int, hi: int, out3, stream=None) -> int:
+    return lib().leco_filter_sum(ctx, _ptr(blob), blob_bytes, lo, hi, _ptr(out3),
+                                 _stream(stream))
+
+
+def leco_diag_slope(ctx: int, pairs, k: int, out, stream=None) -> int:
+    return lib().leco_diag_slope(ctx, _ptr(pairs), k, _ptr(out), _stream(stream))
+
+
+# ---- convenience wrapper --------------------------------------------------------------
+
+class Codec:
+    """A context on one device plus tensor-level helpers.  Blobs are uint8
+    CUDA tensors whose length is the blob size."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.ctx = leco_create(device)
+
+    def close(self):
+        if self.ctx:
+            leco_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, fn: str, st: int):
+        if st != LECO_OK:
+            raise LecoError(fn, st, leco_last_error(self.ctx))
+
+    def sync(self, stream=None):
+        self.check("leco_sync", leco_sync(self.ctx, stream))
+
+    def encode(self, col, fixed_len: int = 0, starts=None, force_constant: bool = False,
+               stream=None):
+        """Encodes a CUDA tensor column; returns the blob (uint8 tensor)."""
+        import torch
+        dt = _dtype_code(col)
+        part, keep = make_partitioning(fixed_len, starts, force_constant)
+        cap = leco_max_blob_bytes(col.numel(), dt, part)
+        buf = torch.empty(cap, dtype=torch.uint8, device=col.device)
+        st, size = leco_encode(self.ctx, col, col.numel(), dt, part, buf, cap, stream)
+        del keep
+        self.check("leco_encode", st)
+        return buf[:size]
+
+    def info(self, blob):
+        return leco_blob_info(bytes(blob[:64].cpu().numpy().tobytes()))
+
+    def _out(self, n: int, dt: int, device):
+        import torch
+        return torch.empty(n, dtype=torch.uint32 if dt == LECO_U32 else torch.uint64, device=device)
+
+    def decode_all(self, blob, out=None, stream=None, sync: bool = True):
+        n, dt, _ = self.info(blob)
+        if out is None:
+            out = self._out(n, dt, blob.device)
+        self.check("leco_decode_all", leco_decode_all(self.ctx, blob, blob.numel(), out,
+                                                      out.numel(), stream))
+        if sync:
+            self.sync(stream)
+        return out
+
+    def decode_range(self, blob, begin: int, end: int, out=None, stream=None, sync: bool = True):
+        _, dt, _ = self.info(blob)
+        if out is None:
+            out = self._out(max(end - begin, 0), dt, blob.device)
+        self.check("leco_decode_range", leco_decode_range(self.ctx, blob, blob.numel(), begin,
+                                                          end, out, stream))
+        if sync:
+            self.sync(stream)
+        return out
+
+    def random_access(self, blob, pos, out=None, stream=None, sync: bool = True):
+        _, dt, _ = self.info(blob)
+        if out is None:
+            out = self._out(pos.numel(), dt, blob.device)
+        self.check("leco_random_access", leco_random_access(self.ctx, blob, blob.numel(), pos,
+                                                            pos.numel(), out, stream))
+        if sync:
+            self.sync(stream)
+        return out
+
+    def filter_sum(self, blob, lo: int, hi: int, stream=None) -> tuple[int, int]:
+        import torch
+        out3 = torch.empty(3, dtype=torch.uint64, device=blob.device)
+        self.check("leco_filter_sum", leco_filter_sum(self.ctx, blob, blob.numel(), lo, hi,
+                                                      out3, stream))
+        self.sync(stream)
+        v = [int(x) for x in out3.cpu().numpy()]
+        return (v[1] << 64) | v[0], v[2]
+
+    def validate(self, blob, stream=None) -> int:
+        return leco_validate_blob(self.ctx, blob, blob.numel(), stream)

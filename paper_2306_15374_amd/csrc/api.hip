@@ -1,0 +1,391 @@
+// C ABI of the LeCo HIP library: argument checks on the host, scratch
+// management, the device error flag, and dispatch to the kernels.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.hpp"
+#include "leco_dev.hpp"
+
+using leco::kMaxPartLen;
+
+namespace {
+
+leco_status fail(leco_ctx* ctx, leco_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return st;
+}
+
+leco_status hip_fail(leco_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, LECO_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                               \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Returns a device scratch area of at least `bytes`.  Growing it waits for
+// the whole device first, so no queued kernel still uses the old area.
+leco_status get_scratch(leco_ctx* ctx, size_t bytes, void** out) {
+  if (bytes <= ctx->scratch_bytes) {
+    *out = ctx->scratch;
+    return LECO_OK;
+  }
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  if (ctx->scratch) HIP_TRY(ctx, hipFree(ctx->scratch));
+  ctx->scratch = nullptr;
+  ctx->scratch_bytes = 0;
+  size_t sz = bytes + bytes / 4 + 4096;
+  hipError_t e = hipMalloc(&ctx->scratch, sz);
+  if (e != hipSuccess) return fail(ctx, LECO_ENOMEM, "scratch allocation of %zu bytes failed", sz);
+  ctx->scratch_bytes = sz;
+  *out = ctx->scratch;
+  return LECO_OK;
+}
+
+// Partition count and validation of a partitioning for n values.
+leco_status check_partitioning(leco_ctx* ctx, uint64_t n, const leco_partitioning* part,
+                               uint64_t* m_out) {
+  if (!part) return fail(ctx, LECO_EINVAL, "partitioning is null");
+  if (part->reserved != 0) return fail(ctx, LECO_EINVAL, "reserved field must be 0");
+  if (part->fixed_len > 0) {
+    if (part->fixed_len > kMaxPartLen)
+      return fail(ctx, LECO_EINVAL, "fixed_len %llu exceeds 2^20",
+                  (unsigned long long)part->fixed_len);
+    *m_out = n / part->fixed_len + (n % part->fixed_len != 0);
+    return LECO_OK;
+  }
+  const uint64_t m = part->num_partitions;
+  const uint64_t* s = part->starts_host;
+  if (!s) return fail(ctx, LECO_EINVAL, "starts_host is null for variable partitioning");
+  if (s[0] != 0 || s[m] != n)
+    return fail(ctx, LECO_EINVAL, "starts must begin at 0 and end at n");
+  for (uint64_t j = 0; j < m; ++j) {
+    if (s[j + 1] <= s[j])
+      return fail(ctx, LECO_EINVAL, "starts not strictly increasing at %llu",
+                  (unsigned long long)j);
+    if (s[j + 1] - s[j] > kMaxPartLen)
+      return fail(ctx, LECO_EINVAL, "partition %llu longer than 2^20", (unsigned long long)j);
+  }
+  *m_out = m;
+  return LECO_OK;
+}
+
+uint64_t meta_words_off(uint64_t m, bool variable) {
+  return leco::align16(leco::kHeaderBytes + leco::kRecordBytes * m + (variable ? 8 * (m + 1) : 0));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Carves the encode scratch and fills the plan; copies variable starts.
+leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtype dtype,
+                           const leco_partitioning* part, void* blob, uint64_t cap,
+                           hipStream_t stream, leco::EncodePlan* pl) {
+  if (dtype != LECO_U32 && dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "bad dtype");
+  if (n > 0 && !col) return fail(ctx, LECO_EINVAL, "column is null");
+  if (!blob) return fail(ctx, LECO_EINVAL, "blob is null");
+  if (!aligned16(blob) || (n > 0 && (reinterpret_cast<uintptr_t>(col) % dtype) != 0))
+    return fail(ctx, LECO_EINVAL, "blob must be 16-byte aligned and column dtype-aligned");
+  uint64_t m = 0;
+  leco_status st = check_partitioning(ctx, n, part, &m);
+  if (st != LECO_OK) return st;
+  const bool variable = part->fixed_len == 0;
+  const uint64_t nb = (m + 4095) / 4096;
+  size_t off = 0;
+  const size_t o_models = off; off = align256(off + sizeof(leco::PartModel) * (m ? m : 1));
+  const size_t o_woff = off;   off = align256(off + 8 * (m ? m : 1));
+  const size_t o_part = off;   off = align256(off + 8 * (nb ? nb : 1));
+  const size_t o_misc = off;   off = align256(off + 16);
+  const size_t o_starts = off; off = align256(off + (variable ? 8 * (m + 1) : 8));
+  void* scr = nullptr;
+  st = get_scratch(ctx, off, &scr);
+  if (st != LECO_OK) return st;
+  char* b = static_cast<char*>(scr);
+  pl->col = col;
+  pl->n = n;
+  pl->m = m;
+  pl->fixed_len = part->fixed_len;
+  pl->dtype = uint32_t(dtype);
+  pl->force_constant = part->force_constant_model ? 1 : 0;
+  pl->blob = blob;
+  pl->cap = cap;
+  pl->words_off = meta_words_off(m, variable);
+  pl->models = reinterpret_cast<leco::PartModel*>(b + o_models);
+  pl->word_off = reinterpret_cast<uint64_t*>(b + o_woff);
+  pl->partial = reinterpret_cast<uint64_t*>(b + o_part);
+  pl->total_words = reinterpret_cast<uint64_t*>(b + o_misc);
+  pl->size_dev = reinterpret_cast<uint64_t*>(b + o_misc + 8);
+  pl->starts_dev = nullptr;
+  if (variable) {
+    uint64_t* sd = reinterpret_cast<uint64_t*>(b + o_starts);
+    HIP_TRY(ctx, hipMemcpyAsync(sd, part->starts_host, 8 * (m + 1), hipMemcpyHostToDevice, stream));
+    pl->starts_dev = sd;
+  }
+  return LECO_OK;
+}
+
+leco_status check_blob_args(leco_ctx* ctx, const void* blob, uint64_t blob_bytes) {
+  if (!ctx) return LECO_EINVAL;
+  if (!blob) return fail(ctx, LECO_EINVAL, "blob is null");
+  if (!aligned16(blob)) return fail(ctx, LECO_EINVAL, "blob must be 16-byte aligned");
+  if (blob_bytes < leco::kHeaderBytes) return fail(ctx, LECO_EFORMAT, "blob shorter than its header");
+  return LECO_OK;
+}
+
+uint64_t rd64(const uint8_t* p) {
+  uint64_t x;
+  memcpy(&x, p, 8);
+  return x;
+}
+
+}  // namespace
+
+extern "C" {
+
+leco_status leco_create(int hip_device, leco_ctx** out) {
+  if (!out) return LECO_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
+    return LECO_EDEVICE;
+  if (hipSetDevice(hip_device) != hipSuccess) return LECO_EDEVICE;
+  leco_ctx* ctx = new leco_ctx();
+  ctx->device = hip_device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+    delete ctx;
+    return LECO_EDEVICE;
+  }
+  ctx->num_cus = prop.multiProcessorCount;
+  if (hipMalloc(&ctx->err_dev, 256) != hipSuccess ||
+      hipHostMalloc(&ctx->err_host, 256, hipHostMallocDefault) != hipSuccess) {
+    leco_destroy(ctx);
+    return LECO_ENOMEM;
+  }
+  ctx->pinned_u64 = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ctx->err_host) + 64);
+  if (hipMemset(ctx->err_dev, 0, 256) != hipSuccess) {
+    leco_destroy(ctx);
+    return LECO_EDEVICE;
+  }
+  *out = ctx;
+  return LECO_OK;
+}
+
+leco_status leco_destroy(leco_ctx* ctx) {
+  if (!ctx) return LECO_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->scratch) hipFree(ctx->scratch);
+  if (ctx->err_dev) hipFree(ctx->err_dev);
+  if (ctx->err_host) hipHostFree(ctx->err_host);
+  delete ctx;
+  return LECO_OK;
+}
+
+const char* leco_last_error(const leco_ctx* ctx) {
+  return ctx ? ctx->last_error.c_str() : "no context";
+}
+
+leco_status leco_sync(leco_ctx* ctx, hipStream_t stream) {
+  if (!ctx) return LECO_EINVAL;
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->err_host, ctx->err_dev, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  const int bits = *ctx->err_host;
+  if (bits == 0) return LECO_OK;
+  *ctx->err_host = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->err_dev, ctx->err_host, sizeof(int), hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  if (bits & leco::kErrFormat) return fail(ctx, LECO_EFORMAT, "a kernel found the blob malformed");
+  if (bits & leco::kErrRange) return fail(ctx, LECO_ERANGE, "a position or range lies outside [0, n)");
+  return fail(ctx, LECO_ENOSPC, "an output buffer was too small");
+}
+
+leco_status leco_max_blob_bytes(uint64_t n, leco_dtype dtype, const leco_partitioning* part,
+                                uint64_t* bytes) {
+  if (!bytes || (dtype != LECO_U32 && dtype != LECO_U64)) return LECO_EINVAL;
+  uint64_t m = 0;
+  leco_status st = check_partitioning(nullptr, n, part, &m);
+  if (st != LECO_OK) return st;
+  // every partition at full width: ceil(n_j * 8w / 64) <= n_j * w / 8 + 1
+  const uint64_t words = (n * uint64_t(dtype) + 7) / 8 + m;
+  *bytes = leco::align16(meta_words_off(m, part->fixed_len == 0) + 8 * words);
+  return LECO_OK;
+}
+
+leco_status leco_blob_info(const void* header_host, uint64_t* n, leco_dtype* dtype, uint64_t* m) {
+  if (!header_host) return LECO_EINVAL;
+  const uint8_t* h = static_cast<const uint8_t*>(header_host);
+  uint32_t magic;
+  memcpy(&magic, h, 4);
+  const uint16_t version = uint16_t(h[4] | (h[5] << 8));
+  if (magic != leco::kMagic || version != leco::kVersion || (h[6] != 4 && h[6] != 8))
+    return LECO_EFORMAT;
+  if (n) *n = rd64(h + 8);
+  if (dtype) *dtype = leco_dtype(h[6]);
+  if (m) *m = rd64(h + 16);
+  return LECO_OK;
+}
+
+leco_status leco_validate_blob(leco_ctx* ctx, const void* blob_dev, uint64_t blob_bytes,
+                               hipStream_t stream) {
+  leco_status st = check_blob_args(ctx, blob_dev, blob_bytes);
+  if (st != LECO_OK) return st;
+  uint8_t hdr[64];
+  HIP_TRY(ctx, hipMemcpyAsync(hdr, blob_dev, 64, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  uint32_t magic;
+  memcpy(&magic, hdr, 4);
+  const uint16_t version = uint16_t(hdr[4] | (hdr[5] << 8));
+  const uint32_t dtype = hdr[6], variable = hdr[7];
+  const uint64_t n = rd64(hdr + 8), m = rd64(hdr + 16), L = rd64(hdr + 24);
+  const uint64_t rec_off = rd64(hdr + 32), st_off = rd64(hdr + 40), w_off = rd64(hdr + 48),
+                 tw = rd64(hdr + 56);
+  if (magic != leco::kMagic || version != leco::kVersion)
+    return fail(ctx, LECO_EFORMAT, "bad magic or version");
+  if ((dtype != 4 && dtype != 8) || variable > 1 || rec_off != 64)
+    return fail(ctx, LECO_EFORMAT, "bad dtype, flags or records offset");
+  if (m > blob_bytes / 32) return fail(ctx, LECO_EFORMAT, "partition count exceeds blob");
+  if (variable) {
+    if (L != 0 || st_off != 64 + 32 * m) return fail(ctx, LECO_EFORMAT, "bad starts section");
+  } else {
+    if (L == 0 || L > kMaxPartLen || st_off != 0 || m != n / L + (n % L != 0))
+      return fail(ctx, LECO_EFORMAT, "bad fixed partitioning");
+  }
+  if (w_off != meta_words_off(m, variable)) return fail(ctx, LECO_EFORMAT, "bad words offset");
+  if (tw > blob_bytes / 8 || leco::align16(w_off + 8 * tw) > blob_bytes)
+    return fail(ctx, LECO_EFORMAT, "words section exceeds blob");
+  std::vector<uint8_t> meta(w_off);
+  HIP_TRY(ctx, hipMemcpyAsync(meta.data(), blob_dev, w_off, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  uint64_t expect_off = 0;
+  for (uint64_t j = 0; j < m; ++j) {
+    const uint8_t* r = meta.data() + 64 + 32 * j;
+    uint64_t s0, s1;
+    if (variable) {
+      s0 = rd64(meta.data() + st_off + 8 * j);
+      s1 = rd64(meta.data() + st_off + 8 * (j + 1));
+      if (j == 0 && s0 != 0) return fail(ctx, LECO_EFORMAT, "starts[0] != 0");
+      if (s1 <= s0 || s1 - s0 > kMaxPartLen) return fail(ctx, LECO_EFORMAT, "bad start %llu", (unsigned long long)j);
+    } else {
+      s0 = j * L;
+      s1 = s0 + L < n ? s0 + L : n;
+    }
+    const uint64_t bits = r[24];
+    if (bits > 8 * dtype) return fail(ctx, LECO_EFORMAT, "width too large in partition %llu", (unsigned long long)j);
+    for (int k = 25; k < 32; ++k)
+      if (r[k]) return fail(ctx, LECO_EFORMAT, "nonzero record padding");
+    if (rd64(r + 16) != expect_off) return fail(ctx, LECO_EFORMAT, "word offsets not contiguous");
+    expect_off += ((s1 - s0) * bits + 63) / 64;
+  }
+  if (variable && m > 0 && rd64(meta.data() + st_off + 8 * m) != n)
+    return fail(ctx, LECO_EFORMAT, "starts[m] != n");
+  if (expect_off != tw) return fail(ctx, LECO_EFORMAT, "word count mismatch");
+  return LECO_OK;
+}
+
+static leco_status encode_common(leco_ctx* ctx, const void* col, uint64_t n, leco_dtype dtype,
+                                 const leco_partitioning* part, void* blob, uint64_t cap,
+                                 hipStream_t stream, leco::EncodePlan* pl) {
+  if (!ctx) return LECO_EINVAL;
+  leco_status st = prepare_encode(ctx, col, n, dtype, part, blob, cap, stream, pl);
+  if (st != LECO_OK) return st;
+  HIP_TRY(ctx, leco::launch_encode(ctx, *pl, stream));
+  return LECO_OK;
+}
+
+leco_status leco_encode(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_dtype dtype,
+                        const leco_partitioning* part, void* blob_dev, uint64_t blob_cap,
+                        uint64_t* blob_bytes_host, hipStream_t stream) {
+  leco::EncodePlan pl;
+  leco_status st = encode_common(ctx, col_dev, n, dtype, part, blob_dev, blob_cap, stream, &pl);
+  if (st != LECO_OK) return st;
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned_u64, pl.size_dev, 8, hipMemcpyDeviceToHost, stream));
+  st = leco_sync(ctx, stream);
+  const uint64_t size = *ctx->pinned_u64;
+  if (blob_bytes_host) *blob_bytes_host = size;
+  if (st == LECO_ENOSPC || size > blob_cap)
+    return fail(ctx, LECO_ENOSPC, "blob needs %llu bytes, capacity is %llu",
+                (unsigned long long)size, (unsigned long long)blob_cap);
+  return st;
+}
+
+leco_status leco_encode_async(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_dtype dtype,
+                              const leco_partitioning* part, void* blob_dev, uint64_t blob_cap,
+                              uint64_t* blob_bytes_dev, hipStream_t stream) {
+  if (!ctx) return LECO_EINVAL;
+  if (!blob_bytes_dev) return fail(ctx, LECO_EINVAL, "blob_bytes_dev is null");
+  uint64_t bound = 0;
+  leco_status st = leco_max_blob_bytes(n, dtype, part, &bound);
+  if (st != LECO_OK) return fail(ctx, st, "bad encode arguments");
+  if (blob_cap < bound)
+    return fail(ctx, LECO_ENOSPC, "async encode needs capacity %llu", (unsigned long long)bound);
+  leco::EncodePlan pl;
+  st = encode_common(ctx, col_dev, n, dtype, part, blob_dev, blob_cap, stream, &pl);
+  if (st != LECO_OK) return st;
+  HIP_TRY(ctx, hipMemcpyAsync(blob_bytes_dev, pl.size_dev, 8, hipMemcpyDeviceToDevice, stream));
+  return LECO_OK;
+}
+
+leco_status leco_decode_all(leco_ctx* ctx, const void* blob_dev, uint64_t blob_bytes,
+                            void* out_dev, uint64_t out_cap_elems, hipStream_t stream) {
+  leco_status st = check_blob_args(ctx, blob_dev, blob_bytes);
+  if (st != LECO_OK) return st;
+  if (!out_dev && out_cap_elems) return fail(ctx, LECO_EINVAL, "output is null");
+  if (!aligned16(out_dev)) return fail(ctx, LECO_EINVAL, "output must be 16-byte aligned");
+  HIP_TRY(ctx, leco::launch_decode(ctx, blob_dev, blob_bytes, out_dev, 0, 0, out_cap_elems, true, stream));
+  return LECO_OK;
+}
+
+leco_status leco_decode_range(leco_ctx* ctx, const void* blob_dev, uint64_t blob_bytes,
+                              uint64_t begin, uint64_t end, void* out_dev, hipStream_t stream) {
+  leco_status st = check_blob_args(ctx, blob_dev, blob_bytes);
+  if (st != LECO_OK) return st;
+  if (begin > end) return fail(ctx, LECO_ERANGE, "begin > end");
+  if (end > begin && !out_dev) return fail(ctx, LECO_EINVAL, "output is null");
+  HIP_TRY(ctx, leco::launch_decode(ctx, blob_dev, blob_bytes, out_dev, begin, end, 0, false, stream));
+  return LECO_OK;
+}
+
+leco_status leco_random_access(leco_ctx* ctx, const void* blob_dev, uint64_t blob_bytes,
+                               const uint64_t* pos_dev, uint64_t k, void* out_dev,
+                               hipStream_t stream) {
+  leco_status st = check_blob_args(ctx, blob_dev, blob_bytes);
+  if (st != LECO_OK) return st;
+  if (k && (!pos_dev || !out_dev)) return fail(ctx, LECO_EINVAL, "positions or output is null");
+  if (k > (uint64_t(1) << 40)) return fail(ctx, LECO_EINVAL, "too many positions");
+  HIP_TRY(ctx, leco::launch_random_access(ctx, blob_dev, blob_bytes, pos_dev, k, out_dev, stream));
+  return LECO_OK;
+}
+
+leco_status leco_filter_sum(leco_ctx* ctx, const void* blob_dev, uint64_t blob_bytes, uint64_t lo,
+                            uint64_t hi, uint64_t* out3_dev, hipStream_t stream) {
+  leco_status st = check_blob_args(ctx, blob_dev, blob_bytes);
+  if (st != LECO_OK) return st;
+  if (!out3_dev) return fail(ctx, LECO_EINVAL, "output is null");
+  HIP_TRY(ctx, leco::launch_filter_sum(ctx, blob_dev, blob_bytes, lo, hi, out3_dev, true, stream));
+  return LECO_OK;
+}
+
+leco_status leco_diag_slope(leco_ctx* ctx, const uint64_t* in_dev, uint64_t k, double* out_dev,
+                            hipStream_t stream) {
+  if (!ctx) return LECO_EINVAL;
+  if (k && (!in_dev || !out_dev)) return fail(ctx, LECO_EINVAL, "input or output is null");
+  if (k > (uint64_t(1) << 32)) return fail(ctx, LECO_EINVAL, "too many pairs");
+  HIP_TRY(ctx, leco::launch_diag_slope(in_dev, k, out_dev, stream));
+  return LECO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+// LeCo decoder kernels for gfx950 (section 3.3): full and range decode,
+// random access, and the range-filter sum with model-bound pruning
+// (section 5.1).  Launch helpers at the bottom are called by the C ABI.
+#include "decode_tile.hpp"
+#include "internal.hpp"
+
+namespace leco {
+
+__device__ inline void raise(int* err, int bits) { atomicOr(err, bits); }
+
+// Decode positions [begin, end) into out[g - begin].  Tile k of the launch
+// covers [(first_tile + k) * 2^tile_log2, ...) clipped to [begin, end).  With
+// `all` set, end is taken from the header and checked against out_cap.
+__global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ blob,
+                                                   uint64_t blob_bytes, uint8_t* __restrict__ out,
+                                                   uint64_t begin, uint64_t end, uint64_t out_cap,
+                                                   uint32_t tile_log2, uint64_t num_tiles, int all,
+                                                   int* err) {
+  __shared__ uint4 stage_v[kStageWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v);
+  Header h;
+  if (!load_header(blob, blob_bytes, h)) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
+    return;
+  }
+  uint64_t e = end;
+  if (all) {
+    if (h.n > out_cap) {
+      if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrNoSpace);
+      return;
+    }
+    e = h.n;
+  } else if (end > h.n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrRange);
+    return;
+  }
+  StoreSink sink{out, begin, h.dtype};
+  const uint64_t first = begin >> tile_log2;
+  for (uint64_t k = blockIdx.x; k < num_tiles; k += gridDim.x) {
+    uint64_t g0 = (first + k) << tile_log2;
+    uint64_t g1 = g0 + (uint64_t(1) << tile_log2);
+    if (g0 < begin) g0 = begin;
+    if (g1 > e) g1 = e;
+    if (g0 >= g1) break;
+    if (!decode_tile(blob, h, g0, g1, stage, sink)) {
+      if (threadIdx.x == 0) raise(err, kErrFormat);
+      return;
+    }
+  }
+}
+
+// One lane per requested position: locate the partition, read its record and
+// the one or two words holding the residual, add the prediction.
+__global__ __launch_bounds__(kBlock) void k_random_access(const uint8_t* __restrict__ blob,
+                                                          uint64_t blob_bytes,
+                                                          const uint64_t* __restrict__ pos,
+                                                          uint64_t k, uint8_t* __restrict__ out,
+                                                          int* err) {
+  Header h;
+  if (!load_header(blob, blob_bytes, h)) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
+    return;
+  }
+  const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= k) return;
+  const uint64_t g = pos[i];
+  uint64_t v = 0;
+  if (g >= h.n) {
+    raise(err, kErrRange);
+  } else {
+    const uint64_t j = locate(blob, h, g);
+    Part p;
+    if (!load_part(blob, h, j, p) || g < p.start || g - p.start >= p.len) {
+      raise(err, kErrFormat);
+    } else {
+      const uint32_t t = uint32_t(g - p.start);
+      uint64_t u = 0;
+      if (p.bits) {
+        const uint64_t* words = reinterpret_cast<const uint64_t*>(blob + h.words_off);
+        const uint64_t q = 64 * p.word_off + uint64_t(p.bits) * t;
+        const uint32_t s = uint32_t(q & 63);
+        const uint64_t lo = words[q >> 6];
+        const uint64_t hi = (s + p.bits > 64) ? words[(q >> 6) + 1] : 0;
+        u = (lo >> s) | ((hi << 1) << (63 - s));
+        if (p.bits < 64) u &= (uint64_t(1) << p.bits) - 1;
+      }
+      v = p.base + uint64_t(predict(p.theta1, t)) + u;
+    }
+  }
+  if (h.dtype == 8)
+    reinterpret_cast<uint64_t*>(out)[i] = v;
+  else
+    reinterpret_cast<uint32_t*>(out)[i] = uint32_t(v);
+}
+
+// ---- range-filter sum ------------------------------------------------------
+
+// Accumulates sum and count of values in [lo, hi).  A segment is skipped
+// without reading its residuals when the model bounds its values outside
+// [lo, hi): values of a partition lie in
+//   [base + min_t floor(theta1 t), base + max_t floor(theta1 t) + 2^b - 1]
+// (the prediction is monotone in t), and the bound is used only when that
+// interval, evaluated exactly, lies inside [0, 2^64) so that no value wraps.
+struct FilterSink {
+  uint64_t lo, hi;
+  uint64_t sum_lo, sum_hi, count;
+  int prune;
+  __device__ bool visit_segment(const Part& p, uint32_t t0, uint32_t t1) {
+    if (!prune) return true;
+    const int64_t pa = predict(p.theta1, t0), pb = predict(p.theta1, t1 - 1);
+    const int64_t pmin = pa < pb ? pa : pb, pmax = pa < pb ? pb : pa;
+    // exact [base + pmin, base + pmax + 2^b - 1] as 128-bit signed values
+    const __int128 base = __int128(p.base);
+    const __int128 vmin = base + pmin;
+    const __int128 span = p.bits >= 64 ? (__int128(1) << 64) - 1 : (__int128(1) << p.bits) - 1;
+    const __int128 vmax = base + pmax + span;
+    const __int128 top = __int128(1) << 64;
+    if (vmin < 0 || vmax >= top) return true;  // no safe bound
+    return !(vmax < __int128(lo) || vmin >= __int128(hi));
+  }
+  __device__ void put(uint64_t, uint64_t v) {
+    if (v >= lo && v < hi) {
+      const uint64_t s = sum_lo + v;
+      sum_hi += (s < sum_lo);
+      sum_lo = s;
+      ++count;
+    }
+  }
+};
+
+__global__ void k_zero_u64(uint64_t* p, uint64_t n) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
+// Adds a workgroup's (sum_lo, sum_hi, count) into out3 exactly.
+__device__ inline void block_add_sum(uint64_t sum_lo, uint64_t sum_hi, uint64_t count,
+                                     uint64_t* out3) {
+  __shared__ uint64_t red[3][kBlock];
+  const uint32_t tid = threadIdx.x;
+  red[0][tid] = sum_lo;
+  red[1][tid] = sum_hi;
+  red[2][tid] = count;
+  __syncthreads();
+  for (uint32_t s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const uint64_t a = red[0][tid], b = red[0][tid + s];
+      red[0][tid] = a + b;
+      red[1][tid] += red[1][tid + s] + (a + b < a);
+      red[2][tid] += red[2][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && (red[0][0] | red[1][0] | red[2][0])) {
+    const uint64_t x = red[0][0];
+    const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(out3), x);
+    const uint64_t carry = (old + x < old) ? 1 : 0;
+    atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 1), red[1][0] + carry);
+    atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 2), red[2][0]);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict__ blob,
+                                                       uint64_t blob_bytes, uint64_t lo,
+                                                       uint64_t hi, uint64_t* out3,
+                                                       uint32_t tile_log2, int prune, int* err) {
+  __shared__ uint4 stage_v[kStageWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v);
+  Header h;
+  if (!load_header(blob, blob_bytes, h)) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
+    return;
+  }
+  FilterSink sink{lo, hi, 0, 0, 0, prune};
+  // Persistent grid: the tile count comes from the header.
+  const uint64_t num_tiles = h.n == 0 ? 0 : ((h.n - 1) >> tile_log2) + 1;
+  for (uint64_t k = blockIdx.x; k < num_tiles; k += gridDim.x) {
+    const uint64_t g0 = k << tile_log2;
+    if (g0 >= h.n) break;
+    uint64_t g1 = g0 + (uint64_t(1) << tile_log2);
+    if (g1 > h.n) g1 = h.n;
+    if (!decode_tile(blob, h, g0, g1, stage, sink)) {
+      if (threadIdx.x == 0) raise(err, kErrFormat);
+      return;
+    }
+  }
+  block_add_sum(sink.sum_lo, sink.sum_hi, sink.count, out3);
+}
+
+// ---- launchers ---------------------------------------------------------------
+
+static uint64_t grid_cap(const leco_ctx* ctx, uint64_t tiles) {
+  const uint64_t cap = uint64_t(ctx->num_cus) * ctx->tune.decode_blocks_per_cu;
+  return tiles < cap || cap == 0 ? tiles : cap;
+}
+
+hipError_t launch_decode(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, void* out,
+                         uint64_t begin, uint64_t end, uint64_t out_cap, bool all,
+                         hipStream_t stream) {
+  const uint32_t tl = ctx->tune.tile_log2;
+  const uint64_t e = all ? out_cap : end;
+  if (!all && e <= begin) return hipSuccess;
+  // decode_all always launches, so an empty output still checks n <= 0
+  const uint64_t tiles = e <= begin ? 1 : ((e - 1) >> tl) - (begin >> tl) + 1;
+  const uint64_t grid = grid_cap(ctx, tiles);
+  hipLaunchKernelGGL(k_decode, dim3(uint32_t(grid)), dim3(kBlock), 0, stream,
+                     static_cast<const uint8_t*>(blob), blob_bytes, static_cast<uint8_t*>(out),
+                     begin, end, out_cap, tl, tiles, all ? 1 : 0, ctx->err_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_random_access(leco_ctx* ctx, const void* blob, uint64_t blob_bytes,
+                                const uint64_t* pos, uint64_t k, void* out, hipStream_t stream) {
+  if (k == 0) return hipSuccess;
+  const uint64_t grid = (k + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_random_access, dim3(uint32_t(grid)), dim3(kBlock), 0, stream,
+                     static_cast<const uint8_t*>(blob), blob_bytes, pos, k,
+                     static_cast<uint8_t*>(out), ctx->err_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint64_t grid = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+  hipLaunchKernelGGL(k_zero_u64, dim3(uint32_t(grid)), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_sum(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, uint64_t lo,
+                             uint64_t hi, uint64_t* out3, bool prune, hipStream_t stream) {
+  hipError_t e = launch_zero_u64(out3, 3, stream);
+  if (e != hipSuccess) return e;
+  const uint32_t tl = ctx->tune.tile_log2;
+  const uint64_t grid = uint64_t(ctx->num_cus) * 4;
+  hipLaunchKernelGGL(k_filter_sum, dim3(uint32_t(grid)), dim3(kBlock), 0, stream,
+                     static_cast<const uint8_t*>(blob), blob_bytes, lo, hi, out3, tl,
+                     prune ? 1 : 0, ctx->err_dev);
+  return hipGetLastError();
+}
+
+}  // namespace leco

@@ -1,0 +1,217 @@
+// Device-side building blocks of the LeCo codec for gfx950: blob header and
+// record access with in-kernel validation, exact 128-bit integer helpers,
+// correctly rounded int128 -> binary64 conversion, and residual extraction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace leco {
+
+constexpr uint32_t kMagic = 0x4F43454Cu;  // bytes 'L','E','C','O'
+constexpr uint32_t kVersion = 1;
+constexpr uint64_t kHeaderBytes = 64;
+constexpr uint64_t kRecordBytes = 32;
+constexpr uint64_t kMaxPartLen = 1ull << 20;
+
+// Device error bits, reported by leco_sync.
+constexpr int kErrRange = 1;
+constexpr int kErrFormat = 2;
+constexpr int kErrNoSpace = 4;
+
+__host__ __device__ inline uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
+
+struct Header {
+  uint64_t n, m, fixed_len, starts_off, words_off, total_words;
+  uint32_t dtype;     // 4 or 8
+  uint32_t variable;  // 1 = variable-length partitions
+};
+
+// Reads and checks the 64-byte header against the caller-supplied blob size.
+// Every later access of a kernel stays inside [0, blob_bytes) when this
+// returns true and the per-record checks below pass.
+__device__ inline bool load_header(const uint8_t* blob, uint64_t blob_bytes, Header& h) {
+  if (blob_bytes < kHeaderBytes) return false;
+  const uint64_t* q = reinterpret_cast<const uint64_t*>(blob);
+  uint64_t w0 = q[0];
+  h.n = q[1];
+  h.m = q[2];
+  h.fixed_len = q[3];
+  uint64_t records_off = q[4];
+  h.starts_off = q[5];
+  h.words_off = q[6];
+  h.total_words = q[7];
+  uint32_t magic = uint32_t(w0);
+  uint32_t version = uint32_t(w0 >> 32) & 0xffff;
+  h.dtype = uint32_t(w0 >> 48) & 0xff;
+  h.variable = uint32_t(w0 >> 56);
+  if (magic != kMagic || version != kVersion) return false;
+  if (h.dtype != 4 && h.dtype != 8) return false;
+  if (h.variable > 1 || records_off != kHeaderBytes) return false;
+  if (h.m > blob_bytes / kRecordBytes) return false;
+  uint64_t meta_end = kHeaderBytes + kRecordBytes * h.m;
+  if (h.variable) {
+    if (h.fixed_len != 0 || h.starts_off != meta_end) return false;
+    if (h.m + 1 > blob_bytes / 8) return false;
+    meta_end += 8 * (h.m + 1);
+  } else {
+    if (h.fixed_len == 0 || h.fixed_len > kMaxPartLen || h.starts_off != 0) return false;
+    if (h.n / h.fixed_len + (h.n % h.fixed_len != 0) != h.m) return false;
+  }
+  if (h.words_off != align16(meta_end)) return false;
+  if (h.total_words > blob_bytes / 8) return false;
+  if (align16(h.words_off + 8 * h.total_words) > blob_bytes) return false;
+  return true;
+}
+
+struct Part {
+  uint64_t start, len;   // global index of t = 0 and partition length
+  uint64_t base;         // integer intercept
+  double theta1;         // slope
+  uint64_t word_off;     // first word of the residual span
+  uint32_t bits;         // residual width b
+};
+
+__device__ inline uint64_t part_start(const uint8_t* blob, const Header& h, uint64_t j) {
+  if (h.variable) return reinterpret_cast<const uint64_t*>(blob + h.starts_off)[j];
+  uint64_t s = j * h.fixed_len;
+  return s < h.n ? s : h.n;
+}
+
+// Loads partition j and checks it; false means the blob is corrupt.
+__device__ inline bool load_part(const uint8_t* blob, const Header& h, uint64_t j, Part& p) {
+  if (j >= h.m) return false;
+  const uint64_t* r = reinterpret_cast<const uint64_t*>(blob + kHeaderBytes + kRecordBytes * j);
+  p.base = r[0];
+  p.theta1 = __longlong_as_double(static_cast<long long>(r[1]));
+  p.word_off = r[2];
+  p.bits = uint32_t(r[3] & 0xff);
+  p.start = part_start(blob, h, j);
+  uint64_t end = part_start(blob, h, j + 1);
+  if (end <= p.start || end > h.n || end - p.start > kMaxPartLen) return false;
+  p.len = end - p.start;
+  if (p.bits > 8 * h.dtype) return false;
+  uint64_t words = (p.len * p.bits + 63) >> 6;
+  if (p.word_off > h.total_words || words > h.total_words - p.word_off) return false;
+  return true;
+}
+
+// Partition holding global index g: floor(g / L) for fixed partitions, the
+// last start <= g for variable ones (binary search; the result is checked by
+// the caller against the partition bounds).
+__device__ inline uint64_t locate(const uint8_t* blob, const Header& h, uint64_t g) {
+  if (!h.variable) {
+    // floor(g / L) through a binary64 reciprocal, then exact correction.
+    uint64_t L = h.fixed_len;
+    uint64_t j = uint64_t(double(g) * (1.0 / double(L)));
+    while (j > 0 && j * L > g) --j;
+    while ((j + 1) * L <= g) ++j;
+    return j;
+  }
+  const uint64_t* s = reinterpret_cast<const uint64_t*>(blob + h.starts_off);
+  uint64_t lo = 0, hi = h.m;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    uint64_t mid = lo + ((hi - lo) >> 1);
+    if (s[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---- exact integer helpers --------------------------------------------------
+
+struct U128 {
+  uint64_t lo, hi;
+};
+
+__device__ __host__ inline U128 add128(U128 a, U128 b) {
+  U128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo);
+  return r;
+}
+__device__ __host__ inline U128 sub128(U128 a, U128 b) {
+  U128 r;
+  r.lo = a.lo - b.lo;
+  r.hi = a.hi - b.hi - (a.lo < b.lo);
+  return r;
+}
+__device__ inline U128 mul64x64(uint64_t a, uint64_t b) {
+  U128 r;
+  r.lo = a * b;
+  r.hi = __umul64hi(a, b);
+  return r;
+}
+// Low 128 bits of a 128 x 64 product.
+__device__ inline U128 mul128x64(U128 a, uint64_t b) {
+  U128 r = mul64x64(a.lo, b);
+  r.hi += a.hi * b;
+  return r;
+}
+
+__device__ inline uint32_t bitlen64(uint64_t x) { return x ? 64u - uint32_t(__clzll(x)) : 0u; }
+
+// Correctly rounded (nearest-even) conversion of an unsigned 64-bit integer:
+// the high and low halves convert exactly and their sum rounds once.
+__device__ inline double u64_to_f64(uint64_t x) {
+  double hi = double(uint32_t(x >> 32)) * 4294967296.0;
+  double lo = double(uint32_t(x));
+  return __dadd_rn(hi, lo);
+}
+
+// Correctly rounded conversion of an unsigned 128-bit integer.  Values of 65
+// or more bits are shifted down to exactly 64 bits with every dropped bit
+// ORed into bit 0 (a sticky bit below the rounding position, which lies 11
+// bits down), converted, and scaled back by an exact power of two.
+__device__ inline double u128_to_f64(U128 x) {
+  if (x.hi == 0) return u64_to_f64(x.lo);
+  uint32_t s = bitlen64(x.hi);  // 1..64 bits above the low word
+  uint64_t kept = (s == 64) ? x.hi : ((x.hi << (64 - s)) | (x.lo >> s));
+  uint64_t dropped = (s == 64) ? x.lo : (x.lo << (64 - s));
+  kept |= (dropped != 0);
+  return ldexp(u64_to_f64(kept), int(s));
+}
+
+// Correctly rounded conversion of a two's-complement 128-bit integer.
+__device__ inline double i128_to_f64(U128 x) {
+  bool neg = int64_t(x.hi) < 0;
+  if (neg) x = sub128(U128{0, 0}, x);
+  double m = u128_to_f64(x);
+  return neg ? -m : m;
+}
+
+// floor(theta1 * t) as an integer: one binary64 multiply (no contraction
+// is possible: nothing is added), an exact floor and an exact conversion.
+__device__ inline int64_t predict(double theta1, uint32_t t) {
+  double prod = __dmul_rn(theta1, double(t));
+  return static_cast<int64_t>(floor(prod));
+}
+// Same when every |floor(theta1 * t)| of the partition is below 2^31.
+__device__ inline int32_t predict32(double theta1, uint32_t t) {
+  double prod = __dmul_rn(theta1, double(t));
+  return static_cast<int32_t>(floor(prod));
+}
+
+// True when floor(theta1 * t) fits in int32 for every t < len.  Rounding is
+// monotone, so |fl(theta1 * t)| <= fl(|theta1| * len) for t < len.
+__device__ inline bool prediction_fits_i32(double theta1, uint64_t len) {
+  return __dmul_rn(fabs(theta1), double(len)) < 2147483648.0;
+}
+
+// ---- residual extraction from 32-bit words ---------------------------------
+
+// Width-b field at bit q of a little-endian stream held as 32-bit words,
+// b <= 32: funnel shift of two consecutive words.
+__device__ inline uint32_t extract32(const uint32_t* w, uint32_t q, uint32_t mask) {
+  uint32_t i = q >> 5;
+  return __builtin_amdgcn_alignbit(w[i + 1], w[i], q & 31) & mask;
+}
+// Width-b field, 32 < b <= 64: three consecutive words.
+__device__ inline uint64_t extract64(const uint32_t* w, uint32_t q, uint32_t mask_hi) {
+  uint32_t i = q >> 5, s = q & 31;
+  uint32_t w0 = w[i], w1 = w[i + 1], w2 = w[i + 2];
+  uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, s);
+  uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, s) & mask_hi;
+  return (uint64_t(hi) << 32) | lo;
+}
+
+}  // namespace leco

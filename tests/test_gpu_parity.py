@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle
+on the same seeded inputs.  Bytes of every blob and every decoded value must
+be identical (integer work: bit-exact)."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2306_15374_amd as P
+from paper_2306_15374_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def codec(torch):
+    c = P.Codec(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t) -> np.ndarray:
+    return t.cpu().numpy()
+
+
+def random_partitioning(rng, n: int, max_len: int):
+    s = [0]
+    while s[-1] < n:
+        s.append(min(n, s[-1] + int(rng.integers(1, max_len + 1))))
+    return np.array(s, dtype=np.uint64)
+
+
+def check_column(torch, codec, ref, col: np.ndarray, name: str, fixed_len: int = 0, starts=None,
+                 force_constant: bool = False, ra: int = 2000, seed: int = 0):
+    """Encode on both sides and compare bytes; decode every way and compare."""
+    log(f"[parity] {name}: n={len(col)} dtype={col.dtype} L={fixed_len} "
+        f"m={'-' if starts is None else len(starts) - 1}")
+    rng = np.random.default_rng(seed)
+    expect = ref.encode(col, fixed_len=fixed_len, starts=starts, force_constant=force_constant)
+    d = dev(torch, col)
+    blob = codec.encode(d, fixed_len=fixed_len, starts=starts, force_constant=force_constant)
+    got = host(blob)
+    assert len(got) == len(expect), f"{name}: size {len(got)} != {len(expect)}"
+    if not np.array_equal(got, expect):
+        bad = np.flatnonzero(got != expect)
+        raise AssertionError(f"{name}: {len(bad)} bytes differ, first at {bad[0]}")
+    assert codec.validate(blob) == P.LECO_OK
+    n = len(col)
+    out = codec.decode_all(blob)
+    assert np.array_equal(host(out), col), f"{name}: decode_all"
+    # decoding the oracle's blob gives the same
+    out2 = codec.decode_all(dev(torch, expect))
+    assert np.array_equal(host(out2), col)
+    if n:
+        pos = rng.integers(0, n, size=ra, dtype=np.uint64)
+        pos[:3] = [0, n - 1, n // 2]
+        r = codec.random_access(blob, dev(torch, pos))
+        assert np.array_equal(host(r), ref.random_access(expect, pos)), f"{name}: random_access"
+        for _ in range(4):
+            b = int(rng.integers(0, n))
+            e = int(rng.integers(b, n + 1))
+            r = codec.decode_range(blob, b, e)
+            assert np.array_equal(host(r), col[b:e]), f"{name}: decode_range {b}:{e}"
+        lo, hi = sorted(int(x) for x in rng.choice(col, 2))
+        assert codec.filter_sum(blob, lo, hi) == ref.filter_sum(expect, lo, hi), f"{name}: filter"
+    return blob, expect
+
+
+# ---- workload-shaped cases (scaled so the oracle finishes in seconds) ---------
+
+def test_linear_noise_full_size(torch, codec, ref):
+    col = W.linear_noise(W.C1_N, W.C1_SEED)
+    blob, expect = check_column(torch, codec, ref, col, "linear_noise 1e6 L=1024",
+                                fixed_len=W.C1_L, ra=10)
+    pos = W.uniform_positions(W.C1_N, W.C1_RA, W.C1_RA_SEED)
+    r = codec.random_access(blob, dev(torch, pos))
+    assert np.array_equal(host(r), ref.random_access(expect, pos))
+    assert np.array_equal(host(r), col[pos])
+
+
+@pytest.mark.parametrize("dtype", [np.uint64, np.uint32])
+def test_lognormal_keys_scaled(torch, codec, ref, dtype):
+    col = W.lognormal_keys(2_000_000 + 123, W.C2_SEED, dtype)
+    check_column(torch, codec, ref, col, f"lognormal_keys 2e6 {dtype.__name__}",
+                 fixed_len=W.C2_L)
+
+
+def test_linear_noise_u32_tail(torch, codec, ref):
+    col = W.linear_noise(300_001, 5, np.uint32)
+    check_column(torch, codec, ref, col, "linear_noise u32", fixed_len=1000)
+
+
+@pytest.mark.parametrize("kind", ["sorted_normal", "piecewise_linear", "constant_runs"])
+def test_mixed_distributions_variable_partitions(torch, codec, ref, kind):
+    n = 200_000
+    col = {"sorted_normal": lambda: W.sorted_normal(n, W.C3_SEEDS[0]),
+           "piecewise_linear": lambda: W.piecewise_linear(n, W.C3_SEEDS[1], segments=50),
+           "constant_runs": lambda: W.constant_runs(n, W.C3_SEEDS[2])}[kind]()
+    starts = ref.partition_greedy(col, tau=0.1, sm_bits=320)
+    check_column(torch, codec, ref, col, f"{kind} greedy", starts=starts)
+    check_column(torch, codec, ref, col, f"{kind} fixed", fixed_len=2048)
+
+
+# ---- edge cases ------------------------------------------------------------------
+
+def test_edge_cases(torch, codec, ref):
+    rng = np.random.default_rng(9)
+    cases = [
+        ("empty u64", np.zeros(0, np.uint64), dict(fixed_len=1024)),
+        ("empty u32 var", np.zeros(0, np.uint32), dict(starts=[0])),
+        ("single", np.array([12345], np.uint64), dict(fixed_len=4096)),
+        ("L=1", W.lognormal_keys(3000, 4), dict(fixed_len=1)),
+        ("full range u64 (b=64)", rng.integers(0, 2**64 - 1, 5000, np.uint64, endpoint=True),
+         dict(fixed_len=512)),
+        ("full range u32 (b=32)", rng.integers(0, 2**32 - 1, 5000, np.uint64,
+                                               endpoint=True).astype(np.uint32), dict(fixed_len=300)),
+        ("constant (b=0)", np.full(10_000, 2**63 + 7, np.uint64), dict(fixed_len=4096)),
+        ("decreasing", (2**64 - 1 - np.arange(20_000, dtype=np.uint64) * np.uint64(1000) -
+                        rng.integers(0, 50, 20_000, dtype=np.uint64)), dict(fixed_len=1024)),
+        ("wrap extremes", np.array([2**64 - 1, 0] * 3000, np.uint64), dict(fixed_len=100)),
+        ("huge ranges", np.sort(rng.integers(0, 2**64 - 1, 9000, np.uint64, endpoint=True)),
+         dict(fixed_len=4096)),
+        ("force constant", W.lognormal_keys(50_000, 6), dict(fixed_len=4096, force_constant=True)),
+        ("var lengths 1..50", W.linear_noise(20_000, 7),
+         dict(starts=random_partitioning(rng, 20_000, 50))),
+        ("var long", W.lognormal_keys(70_000, 8),
+         dict(starts=np.array([0, 1, 2, 30_000, 69_999, 70_000], np.uint64))),
+        ("max partition", W.lognormal_keys((1 << 20) + 5, 3), dict(fixed_len=1 << 20)),
+        ("L=4097 ragged", W.lognormal_keys(100_000, 10, np.uint32), dict(fixed_len=4097)),
+    ]
+    for name, col, kw in cases:
+        check_column(torch, codec, ref, col, name, **kw)
+
+
+def test_wide_residuals_across_chunks(torch, codec, ref):
+    """Widths above 32 bits split a 4096-value tile into several LDS chunks."""
+    rng = np.random.default_rng(12)
+    t = np.arange(200_000, dtype=np.uint64)
+    col = t * np.uint64(2**20) + rng.integers(0, 2**45, 200_000, dtype=np.uint64)
+    check_column(torch, codec, ref, col, "b~45 L=65536", fixed_len=65536)
+    check_column(torch, codec, ref, col, "b~45 L=4096", fixed_len=4096)
+
+
+# ---- slope arithmetic ------------------------------------------------------------
+
+def test_device_slope_matches_host_rounding(torch, codec):
+    """fl(N)/fl(D) on the GPU equals Python's correctly rounded int->float
+    conversion followed by an IEEE division, over edge cases and 10^6
+    random pairs in the ranges the fit produces (|N| < 2^121, D < 2^80)."""
+    rng = np.random.default_rng(5)
+    pairs = []
+    edge_n = [0, 1, -1, 2**53 - 1, 2**53, 2**53 + 1, 2**53 + 2, 2**53 + 3, -(2**53 + 1),
+              2**64 - 1, 2**64, 2**64 + 1, 2**65 + 2**12, 2**65 + 2**12 + 1, (1 << 120) - 1,
+              -(1 << 120), (1 << 63) + (1 << 10), (1 << 63) + (1 << 10) + 1, (1 << 63) + (3 << 10),
+              (2**54 + 1) << 60, ((2**53 + 1) << 66) + 1, -(((2**53 + 1) << 66))]
+    edge_d = [1, 3, 12, 2**53 + 1, (1 << 79) + 12345, 2**64 + 1, 2**79 - 1]
+    for a in edge_n:
+        for b in edge_d:
+            pairs.append((a, b))
+    for _ in range(1_000_000 - len(pairs)):
+        nb = int(rng.integers(1, 121))
+        a = int(rng.integers(0, 2**63)) << max(0, nb - 63) | int(rng.integers(0, 2**63))
+        a &= (1 << nb) - 1
+        if rng.integers(0, 2):
+            a = -a
+        db = int(rng.integers(1, 80))
+        b = (int(rng.integers(0, 2**63)) << max(0, db - 63) | int(rng.integers(1, 2**63)))
+        b = (b & ((1 << db) - 1)) or 1
+        pairs.append((a, b))
+    k = len(pairs)
+    arr = np.zeros((k, 4), dtype=np.uint64)
+    for i, (a, b) in enumerate(pairs):
+        ua = a % (1 << 128)
+        arr[i] = [ua & (2**64 - 1), ua >> 64, b & (2**64 - 1), b >> 64]
+    out = torch.empty(k, dtype=torch.float64, device="cuda")
+    codec.check("leco_diag_slope", P.leco_diag_slope(codec.ctx, dev(torch, arr.reshape(-1)), k, out))
+    codec.sync()
+    got = host(out)
+    expect = np.array([float(a) / float(b) for a, b in pairs])
+    expect[expect == 0.0] = 0.0
+    assert np.array_equal(got.view(np.uint64), expect.view(np.uint64))
+
+
+# ---- error paths -----------------------------------------------------------------
+
+def test_error_paths(torch, codec, ref):
+    col = W.linear_noise(10_000, 3)
+    blob = codec.encode(dev(torch, col), fixed_len=1000)
+    # position >= n: flagged on the device, reported by the next sync
+    pos = dev(torch, np.array([5, 10_000, 7], dtype=np.uint64))
+    out = torch.empty(3, dtype=torch.uint64, device="cuda")
+    assert P.leco_random_access(codec.ctx, blob, blob.numel(), pos, 3, out) == P.LECO_OK
+    assert P.leco_sync(codec.ctx) == P.LECO_ERANGE
+    assert P.leco_sync(codec.ctx) == P.LECO_OK  # flag cleared
+    # range past the end
+    out = torch.empty(10, dtype=torch.uint64, device="cuda")
+    assert P.leco_decode_range(codec.ctx, blob, blob.numel(), 9_995, 10_005, out) == P.LECO_OK
+    assert P.leco_sync(codec.ctx) == P.LECO_ERANGE
+    assert P.leco_decode_range(codec.ctx, blob, blob.numel(), 10, 5, out) == P.LECO_ERANGE
+    # output too small for decode_all
+    assert P.leco_decode_all(codec.ctx, blob, blob.numel(), out, 10) == P.LECO_OK
+    assert P.leco_sync(codec.ctx) == P.LECO_ENOSPC
+    # corrupt magic and record width: kernels refuse, validation names it
+    bad = blob.clone()
+    bad[0] ^= 1
+    big = torch.empty(10_000, dtype=torch.uint64, device="cuda")
+    assert P.leco_decode_all(codec.ctx, bad, bad.numel(), big, 10_000) == P.LECO_OK
+    assert P.leco_sync(codec.ctx) == P.LECO_EFORMAT
+    assert codec.validate(bad) == P.LECO_EFORMAT
+    bad = blob.clone()
+    bad[64 + 24] = 65  # width of partition 0
+    assert P.leco_decode_all(codec.ctx, bad, bad.numel(), big, 10_000) == P.LECO_OK
+    assert P.leco_sync(codec.ctx) == P.LECO_EFORMAT
+    assert codec.validate(bad) == P.LECO_EFORMAT
+    # truncated blob
+    assert P.leco_decode_all(codec.ctx, blob, blob.numel() - 16, big, 10_000) == P.LECO_OK
+    assert P.leco_sync(codec.ctx) == P.LECO_EFORMAT
+    # encode capacity too small: required size is returned
+    need = len(ref.encode(col, fixed_len=1000))
+    part, _ = P.make_partitioning(fixed_len=1000)
+    small = torch.empty(need - 16, dtype=torch.uint8, device="cuda")
+    st, size = P.leco_encode(codec.ctx, dev(torch, col), len(col), P.LECO_U64, part, small,
+                             need - 16)
+    assert st == P.LECO_ENOSPC and size == need
+    assert P.leco_sync(codec.ctx) == P.LECO_OK
+    # bad partitioning is rejected on the host
+    part, keep = P.make_partitioning(starts=[0, 10, 10, 10_000])
+    st, _ = P.leco_encode(codec.ctx, dev(torch, col), len(col), P.LECO_U64, part, small, need)
+    assert st == P.LECO_EINVAL
+
+
+def test_encode_async_matches_sync(torch, codec, ref):
+    col = W.lognormal_keys(300_000, 13)
+    part, _ = P.make_partitioning(fixed_len=4096)
+    cap = P.leco_max_blob_bytes(len(col), P.LECO_U64, part)
+    buf = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    size = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    assert P.leco_encode_async(codec.ctx, dev(torch, col), len(col), P.LECO_U64, part, buf, cap,
+                               size) == P.LECO_OK
+    codec.sync()
+    s = int(host(size)[0])
+    assert np.array_equal(host(buf[:s]), ref.encode(col, fixed_len=4096))
