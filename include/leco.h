@@ -182,6 +182,13 @@ leco_status leco_filter_sum(leco_ctx *ctx, const void *blob_dev,
 leco_status leco_diag_slope(leco_ctx *ctx, const uint64_t *in_dev, uint64_t k,
                             double *out_dev, hipStream_t stream);
 
+/* Streaming copy of `bytes` (a multiple of 16, both buffers 16-byte
+ * aligned) from src_dev to dst_dev, or a zero fill of dst_dev when src_dev
+ * is null: a plain HBM-bound reference kernel of known traffic, used to
+ * calibrate bandwidth measurements and hardware traffic counters. */
+leco_status leco_diag_copy(leco_ctx *ctx, const void *src_dev, void *dst_dev,
+                           uint64_t bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,7 @@ EXPORTS = [
     "leco_create", "leco_destroy", "leco_last_error", "leco_sync", "leco_max_blob_bytes",
     "leco_blob_info", "leco_validate_blob", "leco_encode", "leco_encode_async",
     "leco_decode_all", "leco_decode_range", "leco_random_access", "leco_filter_sum",
-    "leco_diag_slope",
+    "leco_diag_slope", "leco_diag_copy",
 ]
 
 
@@ -75,6 +75,7 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_random_access": ([vp, vp, u64, vp, u64, vp, vp], i32),
         "leco_filter_sum": ([vp, vp, u64, u64, u64, vp, vp], i32),
         "leco_diag_slope": ([vp, vp, u64, vp, vp], i32),
+        "leco_diag_copy": ([vp, vp, vp, u64, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -191,6 +192,10 @@ def leco_filter_sum(ctx: int, blob, blob_bytes: int, lo: int, hi: int, out3, str
 
 def leco_diag_slope(ctx: int, pairs, k: int, out, stream=None) -> int:
     return lib().leco_diag_slope(ctx, _ptr(pairs), k, _ptr(out), _stream(stream))
+
+
+def leco_diag_copy(ctx: int, src, dst, nbytes: int, stream=None) -> int:
+    return lib().leco_diag_copy(ctx, _ptr(src), _ptr(dst), nbytes, _stream(stream))
 
 
 # ---- convenience wrapper --------------------------------------------------------------

@@ -170,6 +170,7 @@ leco_status leco_create(int hip_device, leco_ctx** out) {
     return LECO_EDEVICE;
   }
   ctx->num_cus = prop.multiProcessorCount;
+  leco::tune_from_env(ctx->tune);
   if (hipMalloc(&ctx->err_dev, 256) != hipSuccess ||
       hipHostMalloc(&ctx->err_host, 256, hipHostMallocDefault) != hipSuccess) {
     leco_destroy(ctx);
@@ -385,6 +386,15 @@ leco_status leco_diag_slope(leco_ctx* ctx, const uint64_t* in_dev, uint64_t k, d
   if (k && (!in_dev || !out_dev)) return fail(ctx, LECO_EINVAL, "input or output is null");
   if (k > (uint64_t(1) << 32)) return fail(ctx, LECO_EINVAL, "too many pairs");
   HIP_TRY(ctx, leco::launch_diag_slope(in_dev, k, out_dev, stream));
+  return LECO_OK;
+}
+
+leco_status leco_diag_copy(leco_ctx* ctx, const void* src_dev, void* dst_dev, uint64_t bytes,
+                           hipStream_t stream) {
+  if (!ctx) return LECO_EINVAL;
+  if (!dst_dev || !aligned16(dst_dev) || (src_dev && !aligned16(src_dev)) || bytes % 16)
+    return fail(ctx, LECO_EINVAL, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+  HIP_TRY(ctx, leco::launch_diag_copy(ctx, src_dev, dst_dev, bytes, stream));
   return LECO_OK;
 }
 

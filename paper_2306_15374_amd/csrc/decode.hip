@@ -9,13 +9,35 @@ namespace leco {
 __device__ inline void raise(int* err, int bits) { atomicOr(err, bits); }
 
 // Decode positions [begin, end) into out[g - begin].  Tile k of the launch
-// covers [(first_tile + k) * 2^tile_log2, ...) clipped to [begin, end).  With
+// covers [(first_tile + k) * 2^tile_log2, ...) clipped to [begin, end); a
+// workgroup walks tiles vb, vb + grid, ... (vb: its XCD-aware index).  With
 // `all` set, end is taken from the header and checked against out_cap.
+template <typename OutT>
+__device__ void decode_tiles(const uint8_t* __restrict__ blob, const Header& h,
+                             OutT* __restrict__ out, uint64_t begin, uint64_t e,
+                             uint32_t tile_log2, uint64_t num_tiles, bool remap, uint32_t* stage,
+                             int* err) {
+  StoreSink<OutT> sink{out, begin};
+  const uint64_t first = begin >> tile_log2;
+  for (uint64_t k = xcd_virtual_block(blockIdx.x, gridDim.x, remap); k < num_tiles;
+       k += gridDim.x) {
+    uint64_t g0 = (first + k) << tile_log2;
+    uint64_t g1 = g0 + (uint64_t(1) << tile_log2);
+    if (g0 < begin) g0 = begin;
+    if (g1 > e) g1 = e;
+    if (g0 >= g1) break;
+    if (!decode_tile(blob, h, g0, g1, stage, sink)) {
+      if (threadIdx.x == 0) raise(err, kErrFormat);
+      return;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ blob,
                                                    uint64_t blob_bytes, uint8_t* __restrict__ out,
                                                    uint64_t begin, uint64_t end, uint64_t out_cap,
                                                    uint32_t tile_log2, uint64_t num_tiles, int all,
-                                                   int* err) {
+                                                   int remap, int* err) {
   __shared__ uint4 stage_v[kStageWords / 4];
   uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v);
   Header h;
@@ -34,23 +56,27 @@ __global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ b
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrRange);
     return;
   }
-  StoreSink sink{out, begin, h.dtype};
-  const uint64_t first = begin >> tile_log2;
-  for (uint64_t k = blockIdx.x; k < num_tiles; k += gridDim.x) {
-    uint64_t g0 = (first + k) << tile_log2;
-    uint64_t g1 = g0 + (uint64_t(1) << tile_log2);
-    if (g0 < begin) g0 = begin;
-    if (g1 > e) g1 = e;
-    if (g0 >= g1) break;
-    if (!decode_tile(blob, h, g0, g1, stage, sink)) {
-      if (threadIdx.x == 0) raise(err, kErrFormat);
-      return;
-    }
-  }
+  if (h.dtype == 8)
+    decode_tiles(blob, h, reinterpret_cast<uint64_t*>(out), begin, e, tile_log2, num_tiles,
+                 remap != 0, stage, err);
+  else
+    decode_tiles(blob, h, reinterpret_cast<uint32_t*>(out), begin, e, tile_log2, num_tiles,
+                 remap != 0, stage, err);
 }
 
-// One lane per requested position: locate the partition, read its record and
-// the one or two words holding the residual, add the prediction.
+// ---- random access -------------------------------------------------------------
+
+// Value at global position g (which must be < h.n), or a format error.
+struct Lookup {
+  uint64_t j;
+  uint64_t g;
+  uint4 r0, r1;  // the 32-byte record
+};
+
+// kLpt positions per lane, strided by the workgroup size so that position
+// loads and output stores stay coalesced; the lane issues all record loads,
+// then all word loads, so up to 2 kLpt independent loads are in flight.
+template <int kLpt>
 __global__ __launch_bounds__(kBlock) void k_random_access(const uint8_t* __restrict__ blob,
                                                           uint64_t blob_bytes,
                                                           const uint64_t* __restrict__ pos,
@@ -61,36 +87,81 @@ __global__ __launch_bounds__(kBlock) void k_random_access(const uint8_t* __restr
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
     return;
   }
-  const uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= k) return;
-  const uint64_t g = pos[i];
-  uint64_t v = 0;
-  if (g >= h.n) {
-    raise(err, kErrRange);
-  } else {
-    const uint64_t j = locate(blob, h, g);
-    Part p;
-    if (!load_part(blob, h, j, p) || g < p.start || g - p.start >= p.len) {
-      raise(err, kErrFormat);
-    } else {
-      const uint32_t t = uint32_t(g - p.start);
-      uint64_t u = 0;
-      if (p.bits) {
-        const uint64_t* words = reinterpret_cast<const uint64_t*>(blob + h.words_off);
-        const uint64_t q = 64 * p.word_off + uint64_t(p.bits) * t;
-        const uint32_t s = uint32_t(q & 63);
-        const uint64_t lo = words[q >> 6];
-        const uint64_t hi = (s + p.bits > 64) ? words[(q >> 6) + 1] : 0;
-        u = (lo >> s) | ((hi << 1) << (63 - s));
-        if (p.bits < 64) u &= (uint64_t(1) << p.bits) - 1;
-      }
-      v = p.base + uint64_t(predict(p.theta1, t)) + u;
+  const uint64_t i0 = uint64_t(blockIdx.x) * (kBlock * kLpt) + threadIdx.x;
+  const uint64_t* words = reinterpret_cast<const uint64_t*>(blob + h.words_off);
+  uint64_t g[kLpt];
+  bool ok[kLpt];
+#pragma unroll
+  for (int r = 0; r < kLpt; ++r) {
+    const uint64_t i = i0 + uint64_t(r) * kBlock;
+    g[r] = i < k ? pos[i] : 0;
+    ok[r] = i < k;
+  }
+  uint4 r0[kLpt], r1[kLpt];
+  uint64_t start[kLpt], len[kLpt];
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < kLpt; ++r) {
+    if (ok[r] && g[r] >= h.n) {
+      raise(err, kErrRange);
+      ok[r] = false;
+    }
+    const uint64_t j = ok[r] ? locate(blob, h, g[r]) : 0;
+    start[r] = 0;
+    len[r] = 0;
+    if (ok[r]) {
+      const uint4* rec = reinterpret_cast<const uint4*>(blob + kHeaderBytes + kRecordBytes * j);
+      r0[r] = rec[0];
+      r1[r] = rec[1];
+      start[r] = part_start(blob, h, j);
+      len[r] = part_start(blob, h, j + 1) - start[r];
     }
   }
-  if (h.dtype == 8)
-    reinterpret_cast<uint64_t*>(out)[i] = v;
-  else
-    reinterpret_cast<uint32_t*>(out)[i] = uint32_t(v);
+  uint64_t lo[kLpt], hi[kLpt];
+  uint32_t sh[kLpt], bits[kLpt];
+#pragma unroll
+  for (int r = 0; r < kLpt; ++r) {
+    lo[r] = hi[r] = 0;
+    sh[r] = 0;
+    bits[r] = 0;
+    if (!ok[r]) continue;
+    const uint64_t word_off = uint64_t(r1[r].x) | (uint64_t(r1[r].y) << 32);
+    const uint32_t b = r1[r].z & 0xff;
+    const uint64_t nwords = (len[r] * b + 63) >> 6;
+    if (g[r] < start[r] || g[r] - start[r] >= len[r] || len[r] > kMaxPartLen || b > 8 * h.dtype ||
+        word_off > h.total_words || nwords > h.total_words - word_off) {
+      bad = true;
+      ok[r] = false;
+      continue;
+    }
+    bits[r] = b;
+    if (b) {
+      const uint64_t q = 64 * word_off + uint64_t(b) * (g[r] - start[r]);
+      sh[r] = uint32_t(q & 63);
+      lo[r] = words[q >> 6];
+      if (sh[r] + b > 64) hi[r] = words[(q >> 6) + 1];
+    }
+  }
+  if (bad) raise(err, kErrFormat);
+#pragma unroll
+  for (int r = 0; r < kLpt; ++r) {
+    const uint64_t i = i0 + uint64_t(r) * kBlock;
+    if (i >= k) continue;
+    uint64_t v = 0;
+    if (ok[r]) {
+      const uint32_t b = bits[r];
+      uint64_t u = (lo[r] >> sh[r]) | ((hi[r] << 1) << (63 - sh[r]));
+      if (b < 64) u &= (uint64_t(1) << b) - 1;
+      const uint64_t base = uint64_t(r0[r].x) | (uint64_t(r0[r].y) << 32);
+      const double th = __longlong_as_double(
+          static_cast<long long>(uint64_t(r0[r].z) | (uint64_t(r0[r].w) << 32)));
+      v = base + uint64_t(predict(th, uint32_t(g[r] - start[r]))) + u;
+    }
+    if (h.dtype == 8)
+      reinterpret_cast<uint64_t*>(out)[i] = v;
+    else
+      reinterpret_cast<uint32_t*>(out)[i] = uint32_t(v);
+  }
 }
 
 // ---- range-filter sum ------------------------------------------------------
@@ -189,12 +260,21 @@ __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict
   block_add_sum(sink.sum_lo, sink.sum_hi, sink.count, out3);
 }
 
-// ---- launchers ---------------------------------------------------------------
+// ---- diagnostics: streaming copy / fill for HBM calibration -----------------------
 
-static uint64_t grid_cap(const leco_ctx* ctx, uint64_t tiles) {
-  const uint64_t cap = uint64_t(ctx->num_cus) * ctx->tune.decode_blocks_per_cu;
-  return tiles < cap || cap == 0 ? tiles : cap;
+__global__ __launch_bounds__(256) void k_diag_copy(const uint4* __restrict__ src,
+                                                   uint4* __restrict__ dst, uint64_t n16) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride) {
+    const uint4 v = src ? src[i] : make_uint4(0, 0, 0, 0);
+    __builtin_nontemporal_store(v.x, &dst[i].x);
+    __builtin_nontemporal_store(v.y, &dst[i].y);
+    __builtin_nontemporal_store(v.z, &dst[i].z);
+    __builtin_nontemporal_store(v.w, &dst[i].w);
+  }
 }
+
+// ---- launchers ---------------------------------------------------------------
 
 hipError_t launch_decode(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, void* out,
                          uint64_t begin, uint64_t end, uint64_t out_cap, bool all,
@@ -204,20 +284,35 @@ hipError_t launch_decode(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, v
   if (!all && e <= begin) return hipSuccess;
   // decode_all always launches, so an empty output still checks n <= 0
   const uint64_t tiles = e <= begin ? 1 : ((e - 1) >> tl) - (begin >> tl) + 1;
-  const uint64_t grid = grid_cap(ctx, tiles);
+  const uint64_t cap = uint64_t(ctx->num_cus) * ctx->tune.decode_blocks_per_cu;
+  uint64_t grid = (cap == 0 || tiles < cap) ? tiles : cap;
+  if (ctx->tune.xcd_remap) grid = (grid + 7) & ~uint64_t(7);
   hipLaunchKernelGGL(k_decode, dim3(uint32_t(grid)), dim3(kBlock), 0, stream,
                      static_cast<const uint8_t*>(blob), blob_bytes, static_cast<uint8_t*>(out),
-                     begin, end, out_cap, tl, tiles, all ? 1 : 0, ctx->err_dev);
+                     begin, end, out_cap, tl, tiles, all ? 1 : 0, ctx->tune.xcd_remap ? 1 : 0,
+                     ctx->err_dev);
   return hipGetLastError();
+}
+
+template <int kLpt>
+static void launch_ra(const void* blob, uint64_t blob_bytes, const uint64_t* pos, uint64_t k,
+                      void* out, int* err, hipStream_t stream) {
+  const uint64_t per = uint64_t(kBlock) * kLpt;
+  const uint64_t grid = (k + per - 1) / per;
+  hipLaunchKernelGGL(k_random_access<kLpt>, dim3(uint32_t(grid)), dim3(kBlock), 0, stream,
+                     static_cast<const uint8_t*>(blob), blob_bytes, pos, k,
+                     static_cast<uint8_t*>(out), err);
 }
 
 hipError_t launch_random_access(leco_ctx* ctx, const void* blob, uint64_t blob_bytes,
                                 const uint64_t* pos, uint64_t k, void* out, hipStream_t stream) {
   if (k == 0) return hipSuccess;
-  const uint64_t grid = (k + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_random_access, dim3(uint32_t(grid)), dim3(kBlock), 0, stream,
-                     static_cast<const uint8_t*>(blob), blob_bytes, pos, k,
-                     static_cast<uint8_t*>(out), ctx->err_dev);
+  switch (ctx->tune.ra_lookups_per_lane) {
+    case 1: launch_ra<1>(blob, blob_bytes, pos, k, out, ctx->err_dev, stream); break;
+    case 2: launch_ra<2>(blob, blob_bytes, pos, k, out, ctx->err_dev, stream); break;
+    case 8: launch_ra<8>(blob, blob_bytes, pos, k, out, ctx->err_dev, stream); break;
+    default: launch_ra<4>(blob, blob_bytes, pos, k, out, ctx->err_dev, stream); break;
+  }
   return hipGetLastError();
 }
 
@@ -237,6 +332,16 @@ hipError_t launch_filter_sum(leco_ctx* ctx, const void* blob, uint64_t blob_byte
   hipLaunchKernelGGL(k_filter_sum, dim3(uint32_t(grid)), dim3(kBlock), 0, stream,
                      static_cast<const uint8_t*>(blob), blob_bytes, lo, hi, out3, tl,
                      prune ? 1 : 0, ctx->err_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t bytes,
+                            hipStream_t stream) {
+  const uint64_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  const uint64_t grid = uint64_t(ctx->num_cus) * 8;
+  hipLaunchKernelGGL(k_diag_copy, dim3(uint32_t(grid)), dim3(256), 0, stream,
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
   return hipGetLastError();
 }
 

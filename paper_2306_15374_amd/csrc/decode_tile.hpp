@@ -58,28 +58,35 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
         qoff = int64_t(64 * p.word_off) - int64_t(32 * a0);
         __syncthreads();
       }
+      // values handled by this thread: t = c0 + tid + kBlock * i, i < cnt
+      const uint32_t first = c0 + tid;
+      const uint32_t cnt = first < c1 ? (c1 - first + kBlock - 1) / kBlock : 0;
       const uint32_t mask32 = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
       const uint32_t mask_hi = b >= 64 ? 0xffffffffu : (b > 32 ? ((1u << (b - 32)) - 1u) : 0u);
-      uint32_t t = c0 + tid;
-      uint32_t q = uint32_t(qoff + int64_t(b) * t);
+      const uint32_t q0 = uint32_t(qoff + int64_t(b) * first);
       const uint32_t dq = b * kBlock;
-      if (b <= 32) {
-        if (small_pred) {
-          for (; t < c1; t += kBlock, q += dq) {
-            uint32_t u = b ? extract32(stage, q, mask32) : 0u;
-            int64_t pr = predict32(p.theta1, t);
-            sink.put(p.start + t, p.base + uint64_t(pr) + u);
-          }
-        } else {
-          for (; t < c1; t += kBlock, q += dq) {
-            uint32_t u = b ? extract32(stage, q, mask32) : 0u;
-            sink.put(p.start + t, p.base + uint64_t(predict(p.theta1, t)) + u);
-          }
+      const uint64_t g_first = p.start + first;
+      if (b <= 32 && small_pred) {
+#pragma unroll 4
+        for (uint32_t i = 0; i < cnt; ++i) {
+          const uint32_t t = first + i * kBlock;
+          const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
+          const int32_t pr = predict32(p.theta1, t);
+          sink.put(g_first + i * kBlock, p.base + uint64_t(int64_t(pr)) + u);
+        }
+      } else if (b <= 32) {
+#pragma unroll 2
+        for (uint32_t i = 0; i < cnt; ++i) {
+          const uint32_t t = first + i * kBlock;
+          const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
+          sink.put(g_first + i * kBlock, p.base + uint64_t(predict(p.theta1, t)) + u);
         }
       } else {
-        for (; t < c1; t += kBlock, q += dq) {
-          uint64_t u = extract64(stage, q, mask_hi);
-          sink.put(p.start + t, p.base + uint64_t(predict(p.theta1, t)) + u);
+#pragma unroll 2
+        for (uint32_t i = 0; i < cnt; ++i) {
+          const uint32_t t = first + i * kBlock;
+          const uint64_t u = extract64(stage, q0 + i * dq, mask_hi);
+          sink.put(g_first + i * kBlock, p.base + uint64_t(predict(p.theta1, t)) + u);
         }
       }
       if (b != 0) __syncthreads();
@@ -93,17 +100,22 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
 
 // Writes each value to out[g - origin] with the column's width, bypassing
 // the caches (outputs are written once and not read back by the kernel).
+template <typename OutT>
 struct StoreSink {
-  uint8_t* out;
+  OutT* out;
   uint64_t origin;
-  uint32_t dtype;
   __device__ bool visit_segment(const Part&, uint32_t, uint32_t) { return true; }
   __device__ void put(uint64_t g, uint64_t v) {
-    if (dtype == 8)
-      __builtin_nontemporal_store(v, reinterpret_cast<uint64_t*>(out) + (g - origin));
-    else
-      __builtin_nontemporal_store(uint32_t(v), reinterpret_cast<uint32_t*>(out) + (g - origin));
+    __builtin_nontemporal_store(OutT(v), out + (g - origin));
   }
 };
+
+// Maps a workgroup to a virtual index so that each XCD (workgroups are
+// dispatched round-robin over the 8 XCDs) walks a contiguous run of tiles;
+// grid must be a multiple of 8 for the mapping to be a permutation.
+__device__ inline uint64_t xcd_virtual_block(uint32_t b, uint32_t grid, bool remap) {
+  if (!remap || (grid & 7u)) return b;
+  return uint64_t(b & 7u) * (grid >> 3) + (b >> 3);
+}
 
 }  // namespace leco

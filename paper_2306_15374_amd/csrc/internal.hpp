@@ -23,7 +23,13 @@ struct PartModel {
 struct Tune {
   uint32_t tile_log2 = 12;           // values per decode tile = 2^tile_log2
   uint32_t decode_blocks_per_cu = 0; // 0 = one workgroup per tile
+  uint32_t xcd_remap = 0;            // 1 = contiguous tile runs per XCD
+  uint32_t ra_lookups_per_lane = 1;  // 1, 2, 4 or 8 positions per lane
 };
+
+// Reads LECO_TILE_LOG2, LECO_DECODE_BLOCKS_PER_CU, LECO_XCD_REMAP and
+// LECO_RA_LPT overrides from the environment.
+void tune_from_env(Tune& t);
 
 // Everything the encode kernels need, with scratch already carved out.
 struct EncodePlan {
@@ -52,6 +58,8 @@ hipError_t launch_filter_sum(leco_ctx* ctx, const void* blob, uint64_t blob_byte
 hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream);
 hipError_t launch_encode(leco_ctx* ctx, const EncodePlan& plan, hipStream_t stream);
 hipError_t launch_diag_slope(const uint64_t* in, uint64_t k, double* out, hipStream_t stream);
+hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t bytes,
+                            hipStream_t stream);
 
 }  // namespace leco
 
