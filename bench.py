@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--lookups", type=int, default=100_000_000)
     ap.add_argument("--cpu-sample", type=int, default=12 * 4096 * 1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["sorted_keys", "batched"], default="sorted_keys")
+    ap.add_argument("--cols", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -104,12 +106,134 @@ def cpu_baseline(col: np.ndarray, pos: np.ndarray, sample: int, L: int, gpu_blob
                 encode_GBps=sample * 8 / t_enc / 1e9, lookups_per_s=len(p) / t_ra)
 
 
+def time_events(torch, stream, fn, reps: int) -> float:
+    """Median seconds of fn() over reps runs, HIP events on `stream`."""
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    return float(np.median(ts))
+
+
+def bench_batched(args):
+    """4,096 columns (lognormal lengths 1e3..1e7, ~2.0e9 values, half uint32)
+    encoded in one launch and decoded in one persistent launch, against the
+    plain path of one decode_all launch per column on one stream."""
+    import torch
+    import paper_2306_15374_amd as P
+    from paper_2306_15374_amd import workloads as W
+
+    specs = W.batched_columns(args.cols)
+    codec = P.Codec(0)
+    stream = torch.cuda.current_stream()
+    log(f"drawing {len(specs)} columns on the device")
+    cols = [W.make_column_device(s) for s in specs]
+    n_total = sum(s["n"] for s in specs)
+    in_bytes = sum(s["n"] * (4 if s["dtype"] == np.uint32 else 8) for s in specs)
+    bufs, jobs = [], []
+    sizes = torch.zeros(len(specs), dtype=torch.uint64, device="cuda")
+    for i, (s, c) in enumerate(zip(specs, cols)):
+        dt = P.LECO_U32 if s["dtype"] == np.uint32 else P.LECO_U64
+        part, _ = P.make_partitioning(fixed_len=s["fixed_len"])
+        cap = P.leco_max_blob_bytes(s["n"], dt, part)
+        buf = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        bufs.append(buf)
+        jobs.append(P.EncodeJob(c.data_ptr(), s["n"], dt, 0, s["fixed_len"], buf.data_ptr(), cap,
+                                sizes.data_ptr() + 8 * i))
+    torch.cuda.synchronize()
+    log(f"{n_total} values, {in_bytes / 1e9:.2f} GB; batched encode")
+    enc = lambda: codec.check("leco_encode_batch", P.leco_encode_batch(codec.ctx, jobs))
+    enc()
+    codec.sync()
+    t_enc = time_events(torch, stream, enc, 5)
+    codec.sync()
+    sz = sizes.cpu().numpy().view(np.uint64)
+    blob_total = int(sz.sum())
+    blobs = [b[: int(n)] for b, n in zip(bufs, sz)]
+    # every column round-trips; sampled columns match single-column encodes
+    outs = [torch.empty_like(c) for c in cols]
+    sums = torch.zeros((len(specs), 3), dtype=torch.uint64, device="cuda")
+    djobs = []
+    for i, (s, c, b) in enumerate(zip(specs, cols, blobs)):
+        djobs.append(P.DecodeJob(b.data_ptr(), b.numel(), s["n"], outs[i].data_ptr(), 0, 0,
+                                 sums.data_ptr() + 24 * i))
+    # filter bounds [vmin + R/4, vmin + 3R/4) per column (computed on the device)
+    for i, c in enumerate(cols):
+        vmin, vmax = int(c.min()), int(c.max())
+        r = vmax - vmin
+        djobs[i].lo, djobs[i].hi = vmin + r // 4, vmin + (3 * r) // 4
+    batch = P.leco_batch_create(codec.ctx, djobs)
+    st, tl, bpc = P.leco_batch_tune(batch, P.LECO_BATCH_DECODE)
+    codec.check("leco_batch_tune", st)
+    log(f"tuned shape: tile 2^{tl}, blocks/CU {bpc}")
+    run = lambda op: (lambda: codec.check("leco_batch_run", P.leco_batch_run(batch, op)))
+    run(P.LECO_BATCH_DECODE)()
+    codec.sync()
+    for s, c, o in zip(specs, cols, outs):
+        assert torch.equal(o, c), f"batched decode mismatch {s}"
+    for i in range(0, len(specs), 97):
+        assert torch.equal(blobs[i], codec.encode(cols[i], fixed_len=specs[i]["fixed_len"]))
+    t_dec = time_events(torch, stream, run(P.LECO_BATCH_DECODE), args.steps)
+    t_graph = time_events(torch, stream, lambda: codec.check(
+        "graph", P.leco_batch_run_graph(batch, P.LECO_BATCH_DECODE)), args.steps)
+    t_filter = time_events(torch, stream, run(P.LECO_BATCH_FILTER), args.steps)
+    t_fused = time_events(torch, stream, run(P.LECO_BATCH_DECODE | P.LECO_BATCH_FILTER), args.steps)
+    codec.sync()
+    # filter sums against torch on the decoded columns
+    sv = sums.cpu().numpy().view(np.uint64)
+    for i in range(0, len(specs), 61):
+        c = cols[i]
+        sel = c[(c >= djobs[i].lo) & (c < djobs[i].hi)]
+        assert int(sv[i, 2]) == sel.numel() and \
+            ((int(sv[i, 1]) << 64) | int(sv[i, 0])) == int(sel.to(torch.int64).sum())
+
+    def plain():
+        for b, o, s in zip(blobs, outs, specs):
+            codec.check("leco_decode_all", P.leco_decode_all(codec.ctx, b, b.numel(), o, s["n"]))
+    t_plain = time_events(torch, stream, plain, 3)
+    codec.sync()
+    P.leco_batch_destroy(batch)
+    alg = blob_total + in_bytes
+    res = {
+        "metric": "decoded GB/s + lookups/s vs HBM roofline (batched/served vs plain); p99 latency",
+        "value": round(in_bytes / t_dec / 1e9, 2), "unit": "GB/s decoded (batched decode)",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(t_dec * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+u64",
+        "data": "synthetic (device-drawn linear-noise and lognormal-key columns)",
+        "config": {"workload": f"batched: {len(specs)} columns, {n_total} values "
+                               f"({in_bytes / 1e9:.2f} GB), lognormal lengths 1e3..1e7",
+                   "tile_log2": tl, "blocks_per_cu": bpc},
+        "batched_decode_ms": round(t_dec * 1e3, 3),
+        "batched_decode_graph_ms": round(t_graph * 1e3, 3),
+        "plain_per_column_decode_ms": round(t_plain * 1e3, 3),
+        "speedup_vs_plain": round(t_plain / t_dec, 2),
+        "filter_sum_ms": round(t_filter * 1e3, 3),
+        "filter_sum_values_per_s": round(n_total / t_filter, 1),
+        "fused_decode_filter_ms": round(t_fused * 1e3, 3),
+        "batched_encode_ms": round(t_enc * 1e3, 3),
+        "batched_encode_GBps": round(in_bytes / t_enc / 1e9, 2),
+        "compression_ratio": round(blob_total / in_bytes, 5),
+        "roofline": {"bound": "hbm", "achieved": round(alg / t_dec / 1e9, 1), "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": round(alg / t_dec / HBM_PEAK, 4), "traffic": None,
+                     "kernel": "k_batch_decode", "bytes_per_launch": alg},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+    codec.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the codec has "
               "no multi-GPU path in this build.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
     import torch
     import paper_2306_15374_amd as P
     from paper_2306_15374_amd import workloads as W

@@ -172,6 +172,76 @@ leco_status leco_filter_sum(leco_ctx *ctx, const void *blob_dev,
                             uint64_t blob_bytes, uint64_t lo, uint64_t hi,
                             uint64_t *out3_dev, hipStream_t stream);
 
+/* ---- Batched mode -------------------------------------------------------------
+ * Many columns in one launch per direction.  The paper encodes and decodes
+ * one sequence at a time (section 3.3); batching only changes how the work
+ * is scheduled on the GPU, never a value or a byte. */
+
+/* One column to encode with fixed partitions (section 3.2.1).  blob_cap
+ * must be at least leco_max_blob_bytes(n, dtype, {fixed_len}); the blob size
+ * is written to *blob_bytes_dev. */
+typedef struct {
+  const void *col_dev;
+  uint64_t n;
+  leco_dtype dtype;
+  int32_t force_constant_model;
+  uint64_t fixed_len;
+  void *blob_dev;
+  uint64_t blob_cap;
+  uint64_t *blob_bytes_dev;
+} leco_encode_job;
+
+/* Encodes every job in one launch (plus a clearing launch): partitions of
+ * all columns are taken in ticket order by workgroups, and each column's
+ * word offsets come from a look-back confined to that column.  Enqueues
+ * only; jobs_host is copied before the call returns. */
+leco_status leco_encode_batch(leco_ctx *ctx, const leco_encode_job *jobs_host,
+                              uint64_t ncols, hipStream_t stream);
+
+/* One column to decode.  n must equal the blob's value count (checked on
+ * the device).  out_dev receives the n decoded values (or is null); when
+ * sum3_dev is not null it receives the exact sum (low, high 64 bits) and the
+ * count of decoded values v with lo <= v < hi (the filter of section 5.1). */
+typedef struct {
+  const void *blob_dev;
+  uint64_t blob_bytes;
+  uint64_t n;
+  void *out_dev;
+  uint64_t lo, hi;
+  uint64_t *sum3_dev;
+} leco_decode_job;
+
+typedef struct leco_batch leco_batch;
+
+enum { LECO_BATCH_DECODE = 1, LECO_BATCH_FILTER = 2 };
+
+/* Builds the flattened tile table of a set of columns and keeps it in
+ * device memory; the jobs' buffers must stay valid while the batch is used.
+ * [sync] */
+leco_status leco_batch_create(leco_ctx *ctx, const leco_decode_job *jobs_host,
+                              uint64_t ncols, leco_batch **out);
+leco_status leco_batch_destroy(leco_batch *batch);
+
+/* One persistent launch over all tiles of all columns: op is
+ * LECO_BATCH_DECODE, LECO_BATCH_FILTER or both (fused: values are written and
+ * summed in the same pass).  Capturable in a HIP graph. */
+leco_status leco_batch_run(leco_batch *batch, int op, hipStream_t stream);
+
+/* Same work replayed from a HIP graph captured on first use per op. */
+leco_status leco_batch_run_graph(leco_batch *batch, int op, hipStream_t stream);
+
+/* Times the candidate launch shapes (tile size, workgroups per CU) of this
+ * batch for `op` and keeps the fastest; every candidate produces identical
+ * results.  Writes the chosen shape to *tile_log2 and *blocks_per_cu if not
+ * null.  [sync] */
+leco_status leco_batch_tune(leco_batch *batch, int op, hipStream_t stream,
+                            uint32_t *tile_log2, uint32_t *blocks_per_cu);
+
+/* Sets the launch shape explicitly (tile of 2^tile_log2 values, 8..16;
+ * blocks_per_cu = 0 for one workgroup per tile). */
+leco_status leco_batch_set_shape(leco_batch *batch, uint32_t tile_log2,
+                                 uint32_t blocks_per_cu);
+
 /* ---- Diagnostics ------------------------------------------------------------
  * Evaluates the slope arithmetic of the encoder (section 3.1, least-squares
  * closed form) on the GPU for k given pairs: in_dev holds 4 uint64 per pair,

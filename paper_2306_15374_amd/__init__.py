@@ -27,14 +27,30 @@ EXPORTS = [
     "leco_create", "leco_destroy", "leco_last_error", "leco_sync", "leco_max_blob_bytes",
     "leco_blob_info", "leco_validate_blob", "leco_encode", "leco_encode_async",
     "leco_decode_all", "leco_decode_range", "leco_random_access", "leco_filter_sum",
-    "leco_diag_slope", "leco_diag_copy",
+    "leco_diag_slope", "leco_diag_copy", "leco_encode_batch", "leco_batch_create",
+    "leco_batch_destroy", "leco_batch_run", "leco_batch_run_graph", "leco_batch_tune",
+    "leco_batch_set_shape",
 ]
+LECO_BATCH_DECODE, LECO_BATCH_FILTER = 1, 2
 
 
 class LecoError(RuntimeError):
     def __init__(self, fn: str, status: int, detail: str = ""):
         super().__init__(f"{fn}: {STATUS_NAMES.get(status, status)} {detail}".strip())
         self.status = status
+
+
+class EncodeJob(C.Structure):
+    _fields_ = [("col_dev", C.c_void_p), ("n", C.c_uint64), ("dtype", C.c_int),
+                ("force_constant_model", C.c_int32), ("fixed_len", C.c_uint64),
+                ("blob_dev", C.c_void_p), ("blob_cap", C.c_uint64),
+                ("blob_bytes_dev", C.c_void_p)]
+
+
+class DecodeJob(C.Structure):
+    _fields_ = [("blob_dev", C.c_void_p), ("blob_bytes", C.c_uint64), ("n", C.c_uint64),
+                ("out_dev", C.c_void_p), ("lo", C.c_uint64), ("hi", C.c_uint64),
+                ("sum3_dev", C.c_void_p)]
 
 
 class Partitioning(C.Structure):
@@ -76,6 +92,13 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_filter_sum": ([vp, vp, u64, u64, u64, vp, vp], i32),
         "leco_diag_slope": ([vp, vp, u64, vp, vp], i32),
         "leco_diag_copy": ([vp, vp, vp, u64, vp], i32),
+        "leco_encode_batch": ([vp, vp, u64, vp], i32),
+        "leco_batch_create": ([vp, vp, u64, P(vp)], i32),
+        "leco_batch_destroy": ([vp], i32),
+        "leco_batch_run": ([vp, i32, vp], i32),
+        "leco_batch_run_graph": ([vp, i32, vp], i32),
+        "leco_batch_tune": ([vp, i32, vp, P(C.c_uint32), P(C.c_uint32)], i32),
+        "leco_batch_set_shape": ([vp, C.c_uint32, C.c_uint32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -196,6 +219,42 @@ def leco_diag_slope(ctx: int, pairs, k: int, out, stream=None) -> int:
 
 def leco_diag_copy(ctx: int, src, dst, nbytes: int, stream=None) -> int:
     return lib().leco_diag_copy(ctx, _ptr(src), _ptr(dst), nbytes, _stream(stream))
+
+
+def leco_encode_batch(ctx: int, jobs, stream=None) -> int:
+    arr = (EncodeJob * len(jobs))(*jobs)
+    return lib().leco_encode_batch(ctx, arr, len(jobs), _stream(stream))
+
+
+def leco_batch_create(ctx: int, jobs) -> int:
+    arr = (DecodeJob * len(jobs))(*jobs)
+    h = C.c_void_p()
+    st = lib().leco_batch_create(ctx, arr, len(jobs), C.byref(h))
+    if st != LECO_OK:
+        raise LecoError("leco_batch_create", st, leco_last_error(ctx))
+    return h.value
+
+
+def leco_batch_destroy(batch: int) -> int:
+    return lib().leco_batch_destroy(batch)
+
+
+def leco_batch_run(batch: int, op: int, stream=None) -> int:
+    return lib().leco_batch_run(batch, op, _stream(stream))
+
+
+def leco_batch_run_graph(batch: int, op: int, stream=None) -> int:
+    return lib().leco_batch_run_graph(batch, op, _stream(stream))
+
+
+def leco_batch_tune(batch: int, op: int, stream=None) -> tuple[int, int, int]:
+    t, b = C.c_uint32(), C.c_uint32()
+    st = lib().leco_batch_tune(batch, op, _stream(stream), C.byref(t), C.byref(b))
+    return st, t.value, b.value
+
+
+def leco_batch_set_shape(batch: int, tile_log2: int, blocks_per_cu: int) -> int:
+    return lib().leco_batch_set_shape(batch, tile_log2, blocks_per_cu)
 
 
 # ---- convenience wrapper --------------------------------------------------------------

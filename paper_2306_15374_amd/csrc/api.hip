@@ -90,49 +90,57 @@ uint64_t meta_words_off(uint64_t m, bool variable) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Carves the encode scratch and fills the plan; copies variable starts.
+// One single-column encode: the column descriptor plus its scratch.
+struct EncodeCall {
+  leco::EncColumn col;
+  uint64_t* status;             // m look-back words
+  unsigned long long* ticket;   // partition ticket counter
+  uint64_t* size_dev;           // blob size (scratch; used when the caller gives none)
+};
+
+// Checks the arguments, carves the encode scratch and copies variable starts.
 leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtype dtype,
                            const leco_partitioning* part, void* blob, uint64_t cap,
-                           hipStream_t stream, leco::EncodePlan* pl) {
+                           hipStream_t stream, EncodeCall* call) {
   if (dtype != LECO_U32 && dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "bad dtype");
   if (n > 0 && !col) return fail(ctx, LECO_EINVAL, "column is null");
   if (!blob) return fail(ctx, LECO_EINVAL, "blob is null");
   if (!aligned16(blob) || (n > 0 && (reinterpret_cast<uintptr_t>(col) % dtype) != 0))
     return fail(ctx, LECO_EINVAL, "blob must be 16-byte aligned and column dtype-aligned");
+  if (cap < leco::kHeaderBytes) return fail(ctx, LECO_ENOSPC, "blob capacity below 64 bytes");
   uint64_t m = 0;
   leco_status st = check_partitioning(ctx, n, part, &m);
   if (st != LECO_OK) return st;
+  if (m >= (uint64_t(1) << 31)) return fail(ctx, LECO_EINVAL, "too many partitions");
   const bool variable = part->fixed_len == 0;
-  const uint64_t nb = (m + 4095) / 4096;
   size_t off = 0;
-  const size_t o_models = off; off = align256(off + sizeof(leco::PartModel) * (m ? m : 1));
-  const size_t o_woff = off;   off = align256(off + 8 * (m ? m : 1));
-  const size_t o_part = off;   off = align256(off + 8 * (nb ? nb : 1));
+  const size_t o_status = off; off = align256(off + 8 * (m ? m : 1));
   const size_t o_misc = off;   off = align256(off + 16);
   const size_t o_starts = off; off = align256(off + (variable ? 8 * (m + 1) : 8));
   void* scr = nullptr;
   st = get_scratch(ctx, off, &scr);
   if (st != LECO_OK) return st;
   char* b = static_cast<char*>(scr);
-  pl->col = col;
-  pl->n = n;
-  pl->m = m;
-  pl->fixed_len = part->fixed_len;
-  pl->dtype = uint32_t(dtype);
-  pl->force_constant = part->force_constant_model ? 1 : 0;
-  pl->blob = blob;
-  pl->cap = cap;
-  pl->words_off = meta_words_off(m, variable);
-  pl->models = reinterpret_cast<leco::PartModel*>(b + o_models);
-  pl->word_off = reinterpret_cast<uint64_t*>(b + o_woff);
-  pl->partial = reinterpret_cast<uint64_t*>(b + o_part);
-  pl->total_words = reinterpret_cast<uint64_t*>(b + o_misc);
-  pl->size_dev = reinterpret_cast<uint64_t*>(b + o_misc + 8);
-  pl->starts_dev = nullptr;
+  leco::EncColumn& c = call->col;
+  c.col = static_cast<const uint8_t*>(col);
+  c.blob = static_cast<uint8_t*>(blob);
+  c.starts = nullptr;
+  c.n = n;
+  c.m = m;
+  c.fixed_len = part->fixed_len;
+  c.cap = cap;
+  c.words_off = meta_words_off(m, variable);
+  c.part_base = 0;
+  c.dtype = uint32_t(dtype);
+  c.force_constant = part->force_constant_model ? 1 : 0;
+  call->status = reinterpret_cast<uint64_t*>(b + o_status);
+  call->ticket = reinterpret_cast<unsigned long long*>(b + o_misc);
+  call->size_dev = reinterpret_cast<uint64_t*>(b + o_misc + 8);
+  c.size_out = call->size_dev;
   if (variable) {
     uint64_t* sd = reinterpret_cast<uint64_t*>(b + o_starts);
     HIP_TRY(ctx, hipMemcpyAsync(sd, part->starts_host, 8 * (m + 1), hipMemcpyHostToDevice, stream));
-    pl->starts_dev = sd;
+    c.starts = sd;
   }
   return LECO_OK;
 }
@@ -209,6 +217,7 @@ leco_status leco_sync(leco_ctx* ctx, hipStream_t stream) {
   *ctx->err_host = 0;
   HIP_TRY(ctx, hipMemcpyAsync(ctx->err_dev, ctx->err_host, sizeof(int), hipMemcpyHostToDevice, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
+  if (bits & leco::kErrDevice) return fail(ctx, LECO_EDEVICE, "a kernel's bounded wait expired");
   if (bits & leco::kErrFormat) return fail(ctx, LECO_EFORMAT, "a kernel found the blob malformed");
   if (bits & leco::kErrRange) return fail(ctx, LECO_ERANGE, "a position or range lies outside [0, n)");
   return fail(ctx, LECO_ENOSPC, "an output buffer was too small");
@@ -299,21 +308,24 @@ leco_status leco_validate_blob(leco_ctx* ctx, const void* blob_dev, uint64_t blo
 
 static leco_status encode_common(leco_ctx* ctx, const void* col, uint64_t n, leco_dtype dtype,
                                  const leco_partitioning* part, void* blob, uint64_t cap,
-                                 hipStream_t stream, leco::EncodePlan* pl) {
+                                 uint64_t* size_dev, hipStream_t stream, EncodeCall* call) {
   if (!ctx) return LECO_EINVAL;
-  leco_status st = prepare_encode(ctx, col, n, dtype, part, blob, cap, stream, pl);
+  leco_status st = prepare_encode(ctx, col, n, dtype, part, blob, cap, stream, call);
   if (st != LECO_OK) return st;
-  HIP_TRY(ctx, leco::launch_encode(ctx, *pl, stream));
+  if (size_dev) call->col.size_out = size_dev;
+  HIP_TRY(ctx, leco::launch_encode_columns(ctx, nullptr, 1, call->col, call->col.m, call->status,
+                                           call->ticket, stream));
   return LECO_OK;
 }
 
 leco_status leco_encode(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_dtype dtype,
                         const leco_partitioning* part, void* blob_dev, uint64_t blob_cap,
                         uint64_t* blob_bytes_host, hipStream_t stream) {
-  leco::EncodePlan pl;
-  leco_status st = encode_common(ctx, col_dev, n, dtype, part, blob_dev, blob_cap, stream, &pl);
+  EncodeCall call;
+  leco_status st = encode_common(ctx, col_dev, n, dtype, part, blob_dev, blob_cap, nullptr,
+                                 stream, &call);
   if (st != LECO_OK) return st;
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned_u64, pl.size_dev, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned_u64, call.size_dev, 8, hipMemcpyDeviceToHost, stream));
   st = leco_sync(ctx, stream);
   const uint64_t size = *ctx->pinned_u64;
   if (blob_bytes_host) *blob_bytes_host = size;
@@ -333,10 +345,63 @@ leco_status leco_encode_async(leco_ctx* ctx, const void* col_dev, uint64_t n, le
   if (st != LECO_OK) return fail(ctx, st, "bad encode arguments");
   if (blob_cap < bound)
     return fail(ctx, LECO_ENOSPC, "async encode needs capacity %llu", (unsigned long long)bound);
-  leco::EncodePlan pl;
-  st = encode_common(ctx, col_dev, n, dtype, part, blob_dev, blob_cap, stream, &pl);
+  EncodeCall call;
+  return encode_common(ctx, col_dev, n, dtype, part, blob_dev, blob_cap, blob_bytes_dev, stream,
+                       &call);
+}
+
+leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64_t ncols,
+                              hipStream_t stream) {
+  if (!ctx) return LECO_EINVAL;
+  if (ncols && !jobs) return fail(ctx, LECO_EINVAL, "jobs is null");
+  std::vector<leco::EncColumn> cols(ncols);
+  uint64_t parts = 0;
+  for (uint64_t i = 0; i < ncols; ++i) {
+    const leco_encode_job& j = jobs[i];
+    if (j.dtype != LECO_U32 && j.dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "job %llu: bad dtype", (unsigned long long)i);
+    if (j.fixed_len == 0 || j.fixed_len > kMaxPartLen)
+      return fail(ctx, LECO_EINVAL, "job %llu: fixed_len must be in [1, 2^20]", (unsigned long long)i);
+    if ((j.n && !j.col_dev) || !j.blob_dev || !j.blob_bytes_dev || !aligned16(j.blob_dev) ||
+        (reinterpret_cast<uintptr_t>(j.col_dev) % j.dtype))
+      return fail(ctx, LECO_EINVAL, "job %llu: null or misaligned buffer", (unsigned long long)i);
+    leco_partitioning part{j.fixed_len, nullptr, 0, j.force_constant_model, 0};
+    uint64_t bound = 0;
+    leco_max_blob_bytes(j.n, j.dtype, &part, &bound);
+    if (j.blob_cap < bound)
+      return fail(ctx, LECO_ENOSPC, "job %llu: capacity below %llu", (unsigned long long)i,
+                  (unsigned long long)bound);
+    leco::EncColumn& c = cols[i];
+    c.col = static_cast<const uint8_t*>(j.col_dev);
+    c.blob = static_cast<uint8_t*>(j.blob_dev);
+    c.starts = nullptr;
+    c.size_out = j.blob_bytes_dev;
+    c.n = j.n;
+    c.m = j.n / j.fixed_len + (j.n % j.fixed_len != 0);
+    c.fixed_len = j.fixed_len;
+    c.cap = j.blob_cap;
+    c.words_off = meta_words_off(c.m, false);
+    c.part_base = parts;
+    c.dtype = uint32_t(j.dtype);
+    c.force_constant = j.force_constant_model ? 1 : 0;
+    parts += c.m;
+  }
+  if (ncols == 0) return LECO_OK;
+  if (parts >= (uint64_t(1) << 31)) return fail(ctx, LECO_EINVAL, "too many partitions in one batch");
+  size_t off = 0;
+  const size_t o_status = off; off = align256(off + 8 * (parts ? parts : 1));
+  const size_t o_ticket = off; off = align256(off + 8);
+  const size_t o_cols = off;   off = align256(off + sizeof(leco::EncColumn) * ncols);
+  void* scr = nullptr;
+  leco_status st = get_scratch(ctx, off, &scr);
   if (st != LECO_OK) return st;
-  HIP_TRY(ctx, hipMemcpyAsync(blob_bytes_dev, pl.size_dev, 8, hipMemcpyDeviceToDevice, stream));
+  char* b = static_cast<char*>(scr);
+  leco::EncColumn* cols_dev = reinterpret_cast<leco::EncColumn*>(b + o_cols);
+  HIP_TRY(ctx, hipMemcpyAsync(cols_dev, cols.data(), sizeof(leco::EncColumn) * ncols,
+                              hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, leco::launch_encode_columns(ctx, cols_dev, ncols, cols[0], parts,
+                                           reinterpret_cast<uint64_t*>(b + o_status),
+                                           reinterpret_cast<unsigned long long*>(b + o_ticket),
+                                           stream));
   return LECO_OK;
 }
 

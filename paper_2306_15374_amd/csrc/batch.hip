@@ -1,0 +1,324 @@
+// Batched LeCo decoding and encoding: one persistent decode launch over the
+// tiles of thousands of columns (flattened into one table, mixed uint32 and
+// uint64, optional fused range-filter sum), HIP-graph replay, a launch-shape
+// tuner, and a one-launch encoder over a table of columns.
+#include <vector>
+
+#include "decode_tile.hpp"
+#include "internal.hpp"
+
+namespace leco {
+
+// One column of a decode batch in device memory.  tile_base is the index of
+// the column's first tile in the flattened table.
+struct DecCol {
+  const uint8_t* blob;
+  uint64_t blob_bytes;
+  uint64_t n;
+  uint8_t* out;
+  uint64_t lo, hi;
+  uint64_t* sum3;
+  uint64_t tile_base;
+};
+
+// Stores each value (when kStore) and accumulates the filter sum (when
+// kFilter).  Pruning by model bounds is only possible when nothing is stored.
+template <typename OutT, bool kStore, bool kFilter>
+struct BatchSink {
+  static constexpr bool kWholeTile = kStore;
+  OutT* out;
+  FilterSink f;
+  __device__ bool visit_segment(const Part& p, uint32_t t0, uint32_t t1) {
+    return kStore ? true : f.visit_segment(p, t0, t1);
+  }
+  __device__ void put(uint64_t g, uint64_t v) {
+    if (kStore) __builtin_nontemporal_store(OutT(v), out + g);
+    if (kFilter) f.put(g, v);
+  }
+};
+
+template <typename OutT, bool kStore, bool kFilter>
+__device__ bool run_tile(const DecCol& c, const Header& h, uint64_t g0, uint64_t g1,
+                         uint32_t* stage) {
+  BatchSink<OutT, kStore, kFilter> sink{reinterpret_cast<OutT*>(c.out),
+                                        FilterSink{c.lo, c.hi, 0, 0, 0, kStore ? 0 : 1}};
+  if (!decode_tile(c.blob, h, g0, g1, stage, sink)) return false;
+  if (kFilter) block_add_sum(sink.f.sum_lo, sink.f.sum_hi, sink.f.count, c.sum3);
+  return true;
+}
+
+template <bool kStore, bool kFilter>
+__global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restrict__ cols,
+                                                         const uint32_t* __restrict__ tile_col,
+                                                         uint64_t total_tiles, uint32_t tile_log2,
+                                                         int* err) {
+  __shared__ uint4 stage_v[kStageWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v);
+  for (uint64_t k = blockIdx.x; k < total_tiles; k += gridDim.x) {
+    const DecCol& c = cols[tile_col[k]];
+    Header h;
+    if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n) {
+      if (threadIdx.x == 0) raise(err, kErrFormat);
+      continue;
+    }
+    const uint64_t g0 = (k - c.tile_base) << tile_log2;
+    uint64_t g1 = g0 + (uint64_t(1) << tile_log2);
+    if (g1 > c.n) g1 = c.n;
+    const bool filter = kFilter && c.sum3 != nullptr;
+    const bool store = kStore && c.out != nullptr;
+    bool ok;
+    if (h.dtype == 8) {
+      if (store && filter) ok = run_tile<uint64_t, true, true>(c, h, g0, g1, stage);
+      else if (store) ok = run_tile<uint64_t, true, false>(c, h, g0, g1, stage);
+      else if (filter) ok = run_tile<uint64_t, false, true>(c, h, g0, g1, stage);
+      else ok = true;
+    } else {
+      if (store && filter) ok = run_tile<uint32_t, true, true>(c, h, g0, g1, stage);
+      else if (store) ok = run_tile<uint32_t, true, false>(c, h, g0, g1, stage);
+      else if (filter) ok = run_tile<uint32_t, false, true>(c, h, g0, g1, stage);
+      else ok = true;
+    }
+    if (!ok && threadIdx.x == 0) raise(err, kErrFormat);
+  }
+}
+
+__global__ void k_batch_zero_sums(const DecCol* __restrict__ cols, uint64_t ncols) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < ncols;
+       i += uint64_t(gridDim.x) * blockDim.x) {
+    uint64_t* s = cols[i].sum3;
+    if (s) s[0] = s[1] = s[2] = 0;
+  }
+}
+
+}  // namespace leco
+
+// ---- host side ------------------------------------------------------------------
+
+struct leco_batch {
+  leco_ctx* ctx = nullptr;
+  std::vector<leco_decode_job> jobs;
+  leco::DecCol* cols_dev = nullptr;
+  uint32_t* tile_col_dev = nullptr;  // column of every tile
+  uint64_t tile_col_cap = 0;
+  uint64_t total_tiles = 0;
+  uint32_t tile_log2 = 12;
+  uint32_t blocks_per_cu = 0;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+leco_status bfail(leco_batch* b, leco_status st, const char* msg) {
+  if (b && b->ctx) b->ctx->last_error = msg;
+  return st;
+}
+
+void drop_graphs(leco_batch* b) {
+  for (auto& g : b->graphs)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Rebuilds and uploads the flattened tile table for the batch's tile size.
+leco_status upload_table(leco_batch* b) {
+  const uint64_t ncols = b->jobs.size();
+  std::vector<leco::DecCol> cols(ncols);
+  uint64_t tiles = 0;
+  for (uint64_t i = 0; i < ncols; ++i) {
+    const leco_decode_job& j = b->jobs[i];
+    leco::DecCol& c = cols[i];
+    c.blob = static_cast<const uint8_t*>(j.blob_dev);
+    c.blob_bytes = j.blob_bytes;
+    c.n = j.n;
+    c.out = static_cast<uint8_t*>(j.out_dev);
+    c.lo = j.lo;
+    c.hi = j.hi;
+    c.sum3 = j.sum3_dev;
+    c.tile_base = tiles;
+    tiles += (j.n + (uint64_t(1) << b->tile_log2) - 1) >> b->tile_log2;
+  }
+  b->total_tiles = tiles;
+  if (ncols == 0) return LECO_OK;
+  if (ncols > 0xffffffffull) return bfail(b, LECO_EINVAL, "too many columns in one batch");
+  std::vector<uint32_t> tile_col(tiles ? tiles : 1);
+  for (uint64_t i = 0; i < ncols; ++i) {
+    const uint64_t end = i + 1 < ncols ? cols[i + 1].tile_base : tiles;
+    for (uint64_t k = cols[i].tile_base; k < end; ++k) tile_col[k] = uint32_t(i);
+  }
+  if (!b->cols_dev && hipMalloc(&b->cols_dev, sizeof(leco::DecCol) * ncols) != hipSuccess)
+    return bfail(b, LECO_ENOMEM, "batch table allocation failed");
+  if (tile_col.size() > b->tile_col_cap) {
+    if (b->tile_col_dev) hipFree(b->tile_col_dev);
+    b->tile_col_dev = nullptr;
+    b->tile_col_cap = 0;
+    if (hipMalloc(&b->tile_col_dev, 4 * tile_col.size()) != hipSuccess)
+      return bfail(b, LECO_ENOMEM, "batch tile map allocation failed");
+    b->tile_col_cap = tile_col.size();
+  }
+  if (hipMemcpy(b->cols_dev, cols.data(), sizeof(leco::DecCol) * ncols, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->tile_col_dev, tile_col.data(), 4 * tile_col.size(), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return bfail(b, LECO_EDEVICE, "batch table upload failed");
+  drop_graphs(b);
+  return LECO_OK;
+}
+
+hipError_t launch_batch(leco_batch* b, int op, hipStream_t stream) {
+  const uint64_t ncols = b->jobs.size();
+  if (ncols == 0) return hipSuccess;
+  const bool filter = (op & LECO_BATCH_FILTER) != 0, store = (op & LECO_BATCH_DECODE) != 0;
+  if (filter) {
+    const uint64_t g = (ncols + 255) / 256;
+    hipLaunchKernelGGL(leco::k_batch_zero_sums, dim3(uint32_t(g < 1024 ? g : 1024)), dim3(256), 0,
+                       stream, b->cols_dev, ncols);
+  }
+  if (b->total_tiles == 0) return hipGetLastError();
+  const uint64_t cap = uint64_t(b->ctx->num_cus) * b->blocks_per_cu;
+  const uint64_t grid = (cap == 0 || b->total_tiles < cap) ? b->total_tiles : cap;
+  auto k = store && filter ? leco::k_batch_decode<true, true>
+           : store         ? leco::k_batch_decode<true, false>
+                           : leco::k_batch_decode<false, true>;
+  hipLaunchKernelGGL(k, dim3(uint32_t(grid)), dim3(leco::kBlock), 0, stream, b->cols_dev,
+                     b->tile_col_dev, b->total_tiles, b->tile_log2, b->ctx->err_dev);
+  return hipGetLastError();
+}
+
+bool valid_op(int op) { return op >= 1 && op <= 3; }
+
+}  // namespace
+
+extern "C" {
+
+leco_status leco_batch_create(leco_ctx* ctx, const leco_decode_job* jobs, uint64_t ncols,
+                              leco_batch** out) {
+  if (!ctx || !out || (ncols && !jobs)) return LECO_EINVAL;
+  *out = nullptr;
+  for (uint64_t i = 0; i < ncols; ++i) {
+    const leco_decode_job& j = jobs[i];
+    if (!j.blob_dev || (reinterpret_cast<uintptr_t>(j.blob_dev) & 15) || j.blob_bytes < 64) {
+      ctx->last_error = "batch job with a null, unaligned or short blob";
+      return LECO_EINVAL;
+    }
+    if (j.out_dev && (reinterpret_cast<uintptr_t>(j.out_dev) & 3)) {
+      ctx->last_error = "batch job with a misaligned output";
+      return LECO_EINVAL;
+    }
+  }
+  leco_batch* b = new leco_batch();
+  b->ctx = ctx;
+  b->jobs.assign(jobs, jobs + ncols);
+  b->tile_log2 = ctx->tune.tile_log2;
+  b->blocks_per_cu = ctx->tune.decode_blocks_per_cu;
+  if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return LECO_EDEVICE;
+  }
+  const leco_status st = upload_table(b);
+  if (st != LECO_OK) {
+    leco_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return LECO_OK;
+}
+
+leco_status leco_batch_destroy(leco_batch* b) {
+  if (!b) return LECO_OK;
+  hipDeviceSynchronize();
+  drop_graphs(b);
+  if (b->cols_dev) hipFree(b->cols_dev);
+  if (b->tile_col_dev) hipFree(b->tile_col_dev);
+  if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+  delete b;
+  return LECO_OK;
+}
+
+leco_status leco_batch_set_shape(leco_batch* b, uint32_t tile_log2, uint32_t blocks_per_cu) {
+  if (!b || tile_log2 < 8 || tile_log2 > 16 || blocks_per_cu > 64) return LECO_EINVAL;
+  if (tile_log2 == b->tile_log2 && blocks_per_cu == b->blocks_per_cu) return LECO_OK;
+  hipDeviceSynchronize();
+  b->blocks_per_cu = blocks_per_cu;
+  if (tile_log2 != b->tile_log2) {
+    b->tile_log2 = tile_log2;
+    return upload_table(b);
+  }
+  drop_graphs(b);
+  return LECO_OK;
+}
+
+leco_status leco_batch_run(leco_batch* b, int op, hipStream_t stream) {
+  if (!b || !valid_op(op)) return LECO_EINVAL;
+  const hipError_t e = launch_batch(b, op, stream);
+  if (e != hipSuccess) return bfail(b, LECO_EDEVICE, hipGetErrorString(e));
+  return LECO_OK;
+}
+
+leco_status leco_batch_run_graph(leco_batch* b, int op, hipStream_t stream) {
+  if (!b || !valid_op(op)) return LECO_EINVAL;
+  hipGraphExec_t& exec = b->graphs[op];
+  if (!exec) {
+    // Captured on the batch's own stream (the legacy default stream cannot
+    // be captured); the instantiated graph is then launched on `stream`.
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return bfail(b, LECO_EDEVICE, "stream capture failed to start");
+    const hipError_t le = launch_batch(b, op, b->capture_stream);
+    const hipError_t ce = hipStreamEndCapture(b->capture_stream, &g);
+    if (le != hipSuccess || ce != hipSuccess || !g)
+      return bfail(b, LECO_EDEVICE, "batch capture failed");
+    const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      exec = nullptr;
+      return bfail(b, LECO_EDEVICE, "graph instantiation failed");
+    }
+  }
+  if (hipGraphLaunch(exec, stream) != hipSuccess) return bfail(b, LECO_EDEVICE, "graph launch failed");
+  return LECO_OK;
+}
+
+leco_status leco_batch_tune(leco_batch* b, int op, hipStream_t stream, uint32_t* tile_log2,
+                            uint32_t* blocks_per_cu) {
+  if (!b || !valid_op(op)) return LECO_EINVAL;
+  static const uint32_t kTiles[] = {11, 12, 13};
+  static const uint32_t kBpc[] = {0, 4, 8};
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  float best = 1e30f;
+  uint32_t bt = b->tile_log2, bb = b->blocks_per_cu;
+  for (uint32_t tl : kTiles) {
+    for (uint32_t bpc : kBpc) {
+      leco_status st = leco_batch_set_shape(b, tl, bpc);
+      if (st != LECO_OK) return st;
+      launch_batch(b, op, stream);  // warm-up
+      float total = 0.0f;
+      for (int r = 0; r < 3; ++r) {
+        hipEventRecord(e0, stream);
+        launch_batch(b, op, stream);
+        hipEventRecord(e1, stream);
+        hipEventSynchronize(e1);
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        total += ms;
+      }
+      if (total < best) {
+        best = total;
+        bt = tl;
+        bb = bpc;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  const leco_status st = leco_batch_set_shape(b, bt, bb);
+  if (tile_log2) *tile_log2 = bt;
+  if (blocks_per_cu) *blocks_per_cu = bb;
+  return st;
+}
+
+}  // extern "C"

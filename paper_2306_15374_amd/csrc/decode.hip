@@ -6,7 +6,6 @@
 
 namespace leco {
 
-__device__ inline void raise(int* err, int bits) { atomicOr(err, bits); }
 
 // Decode positions [begin, end) into out[g - begin].  Tile k of the launch
 // covers [(first_tile + k) * 2^tile_log2, ...) clipped to [begin, end); a
@@ -166,71 +165,10 @@ __global__ __launch_bounds__(kBlock) void k_random_access(const uint8_t* __restr
 
 // ---- range-filter sum ------------------------------------------------------
 
-// Accumulates sum and count of values in [lo, hi).  A segment is skipped
-// without reading its residuals when the model bounds its values outside
-// [lo, hi): values of a partition lie in
-//   [base + min_t floor(theta1 t), base + max_t floor(theta1 t) + 2^b - 1]
-// (the prediction is monotone in t), and the bound is used only when that
-// interval, evaluated exactly, lies inside [0, 2^64) so that no value wraps.
-struct FilterSink {
-  uint64_t lo, hi;
-  uint64_t sum_lo, sum_hi, count;
-  int prune;
-  __device__ bool visit_segment(const Part& p, uint32_t t0, uint32_t t1) {
-    if (!prune) return true;
-    const int64_t pa = predict(p.theta1, t0), pb = predict(p.theta1, t1 - 1);
-    const int64_t pmin = pa < pb ? pa : pb, pmax = pa < pb ? pb : pa;
-    // exact [base + pmin, base + pmax + 2^b - 1] as 128-bit signed values
-    const __int128 base = __int128(p.base);
-    const __int128 vmin = base + pmin;
-    const __int128 span = p.bits >= 64 ? (__int128(1) << 64) - 1 : (__int128(1) << p.bits) - 1;
-    const __int128 vmax = base + pmax + span;
-    const __int128 top = __int128(1) << 64;
-    if (vmin < 0 || vmax >= top) return true;  // no safe bound
-    return !(vmax < __int128(lo) || vmin >= __int128(hi));
-  }
-  __device__ void put(uint64_t, uint64_t v) {
-    if (v >= lo && v < hi) {
-      const uint64_t s = sum_lo + v;
-      sum_hi += (s < sum_lo);
-      sum_lo = s;
-      ++count;
-    }
-  }
-};
-
 __global__ void k_zero_u64(uint64_t* p, uint64_t n) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += uint64_t(gridDim.x) * blockDim.x)
     p[i] = 0;
-}
-
-// Adds a workgroup's (sum_lo, sum_hi, count) into out3 exactly.
-__device__ inline void block_add_sum(uint64_t sum_lo, uint64_t sum_hi, uint64_t count,
-                                     uint64_t* out3) {
-  __shared__ uint64_t red[3][kBlock];
-  const uint32_t tid = threadIdx.x;
-  red[0][tid] = sum_lo;
-  red[1][tid] = sum_hi;
-  red[2][tid] = count;
-  __syncthreads();
-  for (uint32_t s = kBlock / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const uint64_t a = red[0][tid], b = red[0][tid + s];
-      red[0][tid] = a + b;
-      red[1][tid] += red[1][tid + s] + (a + b < a);
-      red[2][tid] += red[2][tid + s];
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && (red[0][0] | red[1][0] | red[2][0])) {
-    const uint64_t x = red[0][0];
-    const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(out3), x);
-    const uint64_t carry = (old + x < old) ? 1 : 0;
-    atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 1), red[1][0] + carry);
-    atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 2), red[2][0]);
-  }
-  __syncthreads();
 }
 
 __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict__ blob,

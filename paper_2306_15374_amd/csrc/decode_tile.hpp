@@ -20,15 +20,122 @@ __device__ inline uint32_t chunk_values(uint32_t bits) {
   return bits == 0 ? 0xffffffffu : ((kStageWords - 12) * 32u) / bits;
 }
 
+// Decodes values t in [c0, c1) of partition p from the staged words: stage
+// word 0 is 32-bit word (qoff-independent) of the blob such that residual t
+// starts at bit qoff + b t of the stage.  Thread tid takes t = c0 + tid,
+// c0 + tid + 256, ...
+template <class Sink>
+__device__ inline void decode_values(const Part& p, uint32_t c0, uint32_t c1, int64_t qoff,
+                                     const uint32_t* __restrict__ stage, Sink& sink) {
+  const uint32_t b = p.bits;
+  const bool small_pred = prediction_fits_i32(p.theta1, p.len);
+  const uint32_t first = c0 + threadIdx.x;
+  const uint32_t cnt = first < c1 ? (c1 - first + kBlock - 1) / kBlock : 0;
+  const uint32_t mask32 = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
+  const uint32_t mask_hi = b >= 64 ? 0xffffffffu : (b > 32 ? ((1u << (b - 32)) - 1u) : 0u);
+  const uint32_t q0 = uint32_t(qoff + int64_t(b) * first);
+  const uint32_t dq = b * kBlock;
+  const uint64_t g_first = p.start + first;
+  if (b <= 32 && small_pred) {
+#pragma unroll 4
+    for (uint32_t i = 0; i < cnt; ++i) {
+      const uint32_t t = first + i * kBlock;
+      const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
+      const int32_t pr = predict32(p.theta1, t);
+      sink.put(g_first + i * kBlock, p.base + uint64_t(int64_t(pr)) + u);
+    }
+  } else if (b <= 32) {
+#pragma unroll 2
+    for (uint32_t i = 0; i < cnt; ++i) {
+      const uint32_t t = first + i * kBlock;
+      const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
+      sink.put(g_first + i * kBlock, p.base + uint64_t(predict(p.theta1, t)) + u);
+    }
+  } else {
+#pragma unroll 2
+    for (uint32_t i = 0; i < cnt; ++i) {
+      const uint32_t t = first + i * kBlock;
+      const uint64_t u = extract64(stage, q0 + i * dq, mask_hi);
+      sink.put(g_first + i * kBlock, p.base + uint64_t(predict(p.theta1, t)) + u);
+    }
+  }
+}
+
+// 32-bit word range [ws, we) (relative to the words section) holding the
+// residuals t in [t0, t1) of partition p.
+__device__ inline void word_span(const Part& p, uint32_t t0, uint32_t t1, uint64_t& ws,
+                                 uint64_t& we) {
+  ws = 2 * p.word_off + ((uint64_t(p.bits) * t0) >> 5);
+  we = 2 * p.word_off + ((uint64_t(p.bits) * t1 + 31) >> 5);
+}
+
+// Copies 32-bit words [a0, w_end) (a0 a multiple of 4) into the stage with
+// coalesced 16-byte loads.
+__device__ inline void stage_words(const uint32_t* __restrict__ words32, uint64_t a0,
+                                   uint64_t w_end, uint32_t* __restrict__ stage) {
+  const uint32_t nvec = uint32_t((w_end - a0 + 3) >> 2);
+  const uint4* src = reinterpret_cast<const uint4*>(words32 + a0);
+  uint4* dst = reinterpret_cast<uint4*>(stage);
+  for (uint32_t i = threadIdx.x; i < nvec; i += kBlock) dst[i] = src[i];
+}
+
+constexpr uint32_t kMaxTileSegments = 64;
+
 // Sink receives (global position g, decoded value v) for every value.
 // Returns false if the blob failed validation (the caller raises the flag);
 // all control flow depending on it is uniform across the workgroup.
+//
+// When the sink visits every segment (Sink::kWholeTile) and the residual
+// words of all segments of the tile fit the stage, they are staged in one
+// round trip (partitions are laid out back to back, so the span is
+// contiguous) and decoded segment by segment from LDS.  Otherwise each
+// segment is staged and decoded in chunks on its own.
 template <class Sink>
 __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, uint64_t g0,
                             uint64_t g1, uint32_t* __restrict__ stage, Sink& sink) {
-  const uint32_t tid = threadIdx.x;
-  uint64_t j = locate(blob, h, g0);
+  const uint64_t j0 = locate(blob, h, g0);
   const uint32_t* words32 = reinterpret_cast<const uint32_t*>(blob + h.words_off);
+  if (Sink::kWholeTile) {
+    uint64_t j = j0, g = g0, span_lo = 0, span_hi = 0;
+    uint32_t nseg = 0;
+    bool one_round = true;
+    while (g < g1) {
+      Part p;
+      if (!load_part(blob, h, j, p)) return false;
+      if (g < p.start || g - p.start >= p.len) return false;
+      const uint64_t seg_end = (p.start + p.len < g1) ? p.start + p.len : g1;
+      uint64_t ws, we;
+      word_span(p, uint32_t(g - p.start), uint32_t(seg_end - p.start), ws, we);
+      if (nseg == 0) span_lo = ws;
+      else if (ws < span_hi) one_round = false;  // spans must follow each other
+      if (we > span_hi) span_hi = we;
+      g = seg_end;
+      ++j;
+      if (++nseg >= kMaxTileSegments && g < g1) {
+        one_round = false;
+        break;
+      }
+    }
+    const uint64_t a0 = span_lo & ~uint64_t(3);
+    if (one_round && span_hi - a0 + 8 <= kStageWords) {
+      if (span_hi > span_lo) stage_words(words32, a0, span_hi, stage);
+      __syncthreads();
+      j = j0;
+      g = g0;
+      while (g < g1) {
+        Part p;
+        load_part(blob, h, j, p);  // validated above
+        const uint64_t seg_end = (p.start + p.len < g1) ? p.start + p.len : g1;
+        const int64_t qoff = int64_t(64 * p.word_off) - int64_t(32 * a0);
+        decode_values(p, uint32_t(g - p.start), uint32_t(seg_end - p.start), qoff, stage, sink);
+        g = seg_end;
+        ++j;
+      }
+      __syncthreads();
+      return true;
+    }
+  }
+  uint64_t j = j0;
   while (g0 < g1) {
     Part p;
     if (!load_part(blob, h, j, p)) return false;
@@ -36,7 +143,6 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
     const uint64_t seg_end = (p.start + p.len < g1) ? p.start + p.len : g1;
     const uint32_t t_end = uint32_t(seg_end - p.start);
     const uint32_t b = p.bits;
-    const bool small_pred = prediction_fits_i32(p.theta1, p.len);
     if (!sink.visit_segment(p, uint32_t(g0 - p.start), t_end)) {
       g0 = seg_end;
       ++j;
@@ -47,48 +153,14 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
       const uint32_t c1 = (t_end - c0 > step) ? c0 + step : t_end;
       int64_t qoff = 0;
       if (b != 0) {
-        // 32-bit word range of bits [b*c0, b*c1), widened to 16-byte loads.
-        const uint64_t w_first = 2 * p.word_off + ((uint64_t(b) * c0) >> 5);
-        const uint64_t w_last = 2 * p.word_off + ((uint64_t(b) * c1 + 31) >> 5);
-        const uint64_t a0 = w_first & ~uint64_t(3);
-        const uint32_t nvec = uint32_t((w_last - a0 + 3) >> 2);
-        const uint4* src = reinterpret_cast<const uint4*>(words32 + a0);
-        uint4* dst = reinterpret_cast<uint4*>(stage);
-        for (uint32_t i = tid; i < nvec; i += kBlock) dst[i] = src[i];
+        uint64_t ws, we;
+        word_span(p, c0, c1, ws, we);
+        const uint64_t a0 = ws & ~uint64_t(3);
+        stage_words(words32, a0, we, stage);
         qoff = int64_t(64 * p.word_off) - int64_t(32 * a0);
         __syncthreads();
       }
-      // values handled by this thread: t = c0 + tid + kBlock * i, i < cnt
-      const uint32_t first = c0 + tid;
-      const uint32_t cnt = first < c1 ? (c1 - first + kBlock - 1) / kBlock : 0;
-      const uint32_t mask32 = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
-      const uint32_t mask_hi = b >= 64 ? 0xffffffffu : (b > 32 ? ((1u << (b - 32)) - 1u) : 0u);
-      const uint32_t q0 = uint32_t(qoff + int64_t(b) * first);
-      const uint32_t dq = b * kBlock;
-      const uint64_t g_first = p.start + first;
-      if (b <= 32 && small_pred) {
-#pragma unroll 4
-        for (uint32_t i = 0; i < cnt; ++i) {
-          const uint32_t t = first + i * kBlock;
-          const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
-          const int32_t pr = predict32(p.theta1, t);
-          sink.put(g_first + i * kBlock, p.base + uint64_t(int64_t(pr)) + u);
-        }
-      } else if (b <= 32) {
-#pragma unroll 2
-        for (uint32_t i = 0; i < cnt; ++i) {
-          const uint32_t t = first + i * kBlock;
-          const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
-          sink.put(g_first + i * kBlock, p.base + uint64_t(predict(p.theta1, t)) + u);
-        }
-      } else {
-#pragma unroll 2
-        for (uint32_t i = 0; i < cnt; ++i) {
-          const uint32_t t = first + i * kBlock;
-          const uint64_t u = extract64(stage, q0 + i * dq, mask_hi);
-          sink.put(g_first + i * kBlock, p.base + uint64_t(predict(p.theta1, t)) + u);
-        }
-      }
+      decode_values(p, c0, c1, qoff, stage, sink);
       if (b != 0) __syncthreads();
       c0 = c1;
     }
@@ -102,6 +174,7 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
 // the caches (outputs are written once and not read back by the kernel).
 template <typename OutT>
 struct StoreSink {
+  static constexpr bool kWholeTile = true;
   OutT* out;
   uint64_t origin;
   __device__ bool visit_segment(const Part&, uint32_t, uint32_t) { return true; }
@@ -117,5 +190,72 @@ __device__ inline uint64_t xcd_virtual_block(uint32_t b, uint32_t grid, bool rem
   if (!remap || (grid & 7u)) return b;
   return uint64_t(b & 7u) * (grid >> 3) + (b >> 3);
 }
+
+
+__device__ inline void raise(int* err, int bits) { atomicOr(err, bits); }
+
+// Accumulates sum and count of values in [lo, hi).  A segment is skipped
+// without reading its residuals when the model bounds its values outside
+// [lo, hi): values of a partition lie in
+//   [base + min_t floor(theta1 t), base + max_t floor(theta1 t) + 2^b - 1]
+// (the prediction is monotone in t), and the bound is used only when that
+// interval, evaluated exactly, lies inside [0, 2^64) so that no value wraps.
+struct FilterSink {
+  static constexpr bool kWholeTile = false;  // may skip segments by their model bounds
+  uint64_t lo, hi;
+  uint64_t sum_lo, sum_hi, count;
+  int prune;
+  __device__ bool visit_segment(const Part& p, uint32_t t0, uint32_t t1) {
+    if (!prune) return true;
+    const int64_t pa = predict(p.theta1, t0), pb = predict(p.theta1, t1 - 1);
+    const int64_t pmin = pa < pb ? pa : pb, pmax = pa < pb ? pb : pa;
+    // exact [base + pmin, base + pmax + 2^b - 1] as 128-bit signed values
+    const __int128 base = __int128(p.base);
+    const __int128 vmin = base + pmin;
+    const __int128 span = p.bits >= 64 ? (__int128(1) << 64) - 1 : (__int128(1) << p.bits) - 1;
+    const __int128 vmax = base + pmax + span;
+    const __int128 top = __int128(1) << 64;
+    if (vmin < 0 || vmax >= top) return true;  // no safe bound
+    return !(vmax < __int128(lo) || vmin >= __int128(hi));
+  }
+  __device__ void put(uint64_t, uint64_t v) {
+    if (v >= lo && v < hi) {
+      const uint64_t s = sum_lo + v;
+      sum_hi += (s < sum_lo);
+      sum_lo = s;
+      ++count;
+    }
+  }
+};
+
+
+// Adds a workgroup's (sum_lo, sum_hi, count) into out3 exactly.
+__device__ inline void block_add_sum(uint64_t sum_lo, uint64_t sum_hi, uint64_t count,
+                                     uint64_t* out3) {
+  __shared__ uint64_t red[3][kBlock];
+  const uint32_t tid = threadIdx.x;
+  red[0][tid] = sum_lo;
+  red[1][tid] = sum_hi;
+  red[2][tid] = count;
+  __syncthreads();
+  for (uint32_t s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const uint64_t a = red[0][tid], b = red[0][tid + s];
+      red[0][tid] = a + b;
+      red[1][tid] += red[1][tid + s] + (a + b < a);
+      red[2][tid] += red[2][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && (red[0][0] | red[1][0] | red[2][0])) {
+    const uint64_t x = red[0][0];
+    const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(out3), x);
+    const uint64_t carry = (old + x < old) ? 1 : 0;
+    atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 1), red[1][0] + carry);
+    atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 2), red[2][0]);
+  }
+  __syncthreads();
+}
+
 
 }  // namespace leco

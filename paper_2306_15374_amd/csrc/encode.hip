@@ -1,98 +1,137 @@
-// LeCo encoder kernels for gfx950 (section 3.1 regressor, section 3.3
-// encoder): per-partition exact least-squares fit and residual width, an
-// exclusive scan of the word counts, and word-centric bit-packing (one
-// writer per 64-bit word, so the bytes are deterministic).
+// LeCo encoder for gfx950 (section 3.1 regressor, section 3.3 encoder), one
+// pass over the input: each workgroup takes the next partition in ticket
+// order, keeps its values in registers (4096 per partition; longer
+// partitions are streamed in chunks), reduces the range and the exact
+// least-squares sums with wavefront shuffles, derives the slope and the
+// residual width, obtains its word offset from a decoupled look-back over
+// the partitions before it in the same column, and bit-packs its residuals
+// through LDS into the blob.  Works on a table of columns, so one launch
+// encodes one column or thousands.
+//
+// Register-resident partitions whose range is below 2^30 (the usual case)
+// take a narrow path: y = v - vmin fits 32 bits, the exact sums fit 64-bit
+// lanes, and predictions and residuals fit int32.  The arithmetic and its
+// results are the same as on the general path, only carried in fewer bits.
 #include "internal.hpp"
 #include "leco_dev.hpp"
 
 namespace leco {
 
-constexpr int kFitBlock = 256;
-constexpr int kFitRegs = 16;  // values kept in registers per thread (4096 per partition)
+constexpr int kEncBlock = 256;
+constexpr int kEncWaves = kEncBlock / 64;
+constexpr int kEncRegs = 16;                           // values per thread in registers
+constexpr uint32_t kEncRegLen = kEncBlock * kEncRegs;  // 4096
+constexpr uint32_t kPackWords = 2048;                  // 64-bit words in the LDS pack buffer
+constexpr uint64_t kFlagAgg = 1ull << 62;              // look-back status: aggregate
+constexpr uint64_t kFlagPrefix = 2ull << 62;           //                   inclusive prefix
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 24;              // bounded wait on a predecessor
+constexpr uint64_t kNarrowRange = 1ull << 30;
 
 __device__ inline uint64_t load_value(const uint8_t* col, uint32_t dtype, uint64_t i) {
   return dtype == 8 ? reinterpret_cast<const uint64_t*>(col)[i]
                     : uint64_t(reinterpret_cast<const uint32_t*>(col)[i]);
 }
 
-struct PartBounds {
-  uint64_t start, len;
-};
+__device__ inline void raise(int* err, int bits) { atomicOr(err, bits); }
 
-__device__ inline PartBounds enc_bounds(uint64_t j, uint64_t n, uint64_t fixed_len,
-                                        const uint64_t* starts) {
-  if (fixed_len) {
-    const uint64_t s = j * fixed_len;
-    const uint64_t e = s + fixed_len < n ? s + fixed_len : n;
-    return {s, e - s};
-  }
-  return {starts[j], starts[j + 1] - starts[j]};
+// ---- workgroup reductions: wavefront shuffles, then one LDS slot per wave ----
+
+__device__ inline uint64_t shfl_xor64(uint64_t x, int m) {
+  return static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(x), m, 64));
 }
 
-// ---- workgroup reductions (256 threads, LDS trees) -------------------------
-
-struct FitScratch {
-  uint64_t a[kFitBlock], b[kFitBlock], c[kFitBlock], d[kFitBlock], e[kFitBlock], f[kFitBlock];
-  // results broadcast by thread 0
-  uint64_t vmin, vmax;
+struct EncShared {
+  uint64_t words[kPackWords];
+  uint64_t red[kEncWaves][4];
   double theta1;
-  int do_fit;
+  uint64_t word_off;
+  uint64_t ticket;
 };
 
-// min/max of u64 and two exact u128 sums.
-__device__ void reduce_pass1(FitScratch& s, uint64_t& vmin, uint64_t& vmax, U128& sv, U128& stv) {
-  const uint32_t tid = threadIdx.x;
-  s.a[tid] = vmin;
-  s.b[tid] = vmax;
-  s.c[tid] = sv.lo;
-  s.d[tid] = sv.hi;
-  s.e[tid] = stv.lo;
-  s.f[tid] = stv.hi;
-  __syncthreads();
-  for (uint32_t w = kFitBlock / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      s.a[tid] = s.a[tid] < s.a[tid + w] ? s.a[tid] : s.a[tid + w];
-      s.b[tid] = s.b[tid] > s.b[tid + w] ? s.b[tid] : s.b[tid + w];
-      U128 x = add128(U128{s.c[tid], s.d[tid]}, U128{s.c[tid + w], s.d[tid + w]});
-      s.c[tid] = x.lo;
-      s.d[tid] = x.hi;
-      U128 y = add128(U128{s.e[tid], s.f[tid]}, U128{s.e[tid + w], s.f[tid + w]});
-      s.e[tid] = y.lo;
-      s.f[tid] = y.hi;
-    }
-    __syncthreads();
+// Every thread receives the workgroup's min and max (two barriers).
+__device__ inline void block_minmax_u64(EncShared& sh, uint64_t& mn, uint64_t& mx) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const uint64_t a = shfl_xor64(mn, m), b = shfl_xor64(mx, m);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
   }
-  vmin = s.a[0];
-  vmax = s.b[0];
-  sv = U128{s.c[0], s.d[0]};
-  stv = U128{s.e[0], s.f[0]};
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh.red[wave][0] = mn;
+    sh.red[wave][1] = mx;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kEncWaves; ++w) {
+    mn = sh.red[w][0] < mn ? sh.red[w][0] : mn;
+    mx = sh.red[w][1] > mx ? sh.red[w][1] : mx;
+  }
+  __syncthreads();
 }
 
-__device__ void reduce_minmax_i64(FitScratch& s, int64_t& rmin, int64_t& rmax) {
-  const uint32_t tid = threadIdx.x;
-  __syncthreads();
-  s.a[tid] = uint64_t(rmin);
-  s.b[tid] = uint64_t(rmax);
-  __syncthreads();
-  for (uint32_t w = kFitBlock / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      const int64_t x = int64_t(s.a[tid]), y = int64_t(s.a[tid + w]);
-      s.a[tid] = uint64_t(x < y ? x : y);
-      const int64_t u = int64_t(s.b[tid]), v = int64_t(s.b[tid + w]);
-      s.b[tid] = uint64_t(u > v ? u : v);
-    }
-    __syncthreads();
-  }
-  rmin = int64_t(s.a[0]);
-  rmax = int64_t(s.b[0]);
+__device__ inline void block_minmax_i64(EncShared& sh, int64_t& mn, int64_t& mx) {
+  // order-preserving map of int64 onto uint64
+  uint64_t a = uint64_t(mn) ^ (1ull << 63), b = uint64_t(mx) ^ (1ull << 63);
+  block_minmax_u64(sh, a, b);
+  mn = int64_t(a ^ (1ull << 63));
+  mx = int64_t(b ^ (1ull << 63));
 }
 
-// Least-squares slope from exact sums over raw values v_t.  With
-// y_t = v_t - c for any constant c, n*S_ty - S_t*S_y equals
-// n*S_tv - S_t*S_v, so N is formed from the raw sums modulo 2^128; its true
-// magnitude is below 2^121, so the wrapped result is exact.
-__device__ double ls_slope(uint64_t len, U128 sv, U128 stv) {
-  const uint64_t st = len * (len - 1) / 2;                     // < 2^39
+// Exact workgroup sums of two unsigned 128-bit values.
+__device__ inline void block_sum_u128x2(EncShared& sh, U128& x, U128& y) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    x = add128(x, U128{shfl_xor64(x.lo, m), shfl_xor64(x.hi, m)});
+    y = add128(y, U128{shfl_xor64(y.lo, m), shfl_xor64(y.hi, m)});
+  }
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh.red[wave][0] = x.lo;
+    sh.red[wave][1] = x.hi;
+    sh.red[wave][2] = y.lo;
+    sh.red[wave][3] = y.hi;
+  }
+  __syncthreads();
+  x = U128{0, 0};
+  y = U128{0, 0};
+#pragma unroll
+  for (int w = 0; w < kEncWaves; ++w) {
+    x = add128(x, U128{sh.red[w][0], sh.red[w][1]});
+    y = add128(y, U128{sh.red[w][2], sh.red[w][3]});
+  }
+  __syncthreads();
+}
+
+// Exact workgroup sums of two 64-bit values that cannot overflow.
+__device__ inline void block_sum_u64x2(EncShared& sh, uint64_t& x, uint64_t& y) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    x += shfl_xor64(x, m);
+    y += shfl_xor64(y, m);
+  }
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh.red[wave][0] = x;
+    sh.red[wave][1] = y;
+  }
+  __syncthreads();
+  x = y = 0;
+#pragma unroll
+  for (int w = 0; w < kEncWaves; ++w) {
+    x += sh.red[w][0];
+    y += sh.red[w][1];
+  }
+  __syncthreads();
+}
+
+// Least-squares slope from exact sums S_y = sum y_t and S_ty = sum t y_t.
+// Shifting every value by a constant c changes neither n S_ty - S_t S_y nor
+// the slope, so the sums may be taken over v_t or over v_t - vmin; N is
+// formed modulo 2^128 and its true magnitude is below 2^121, so it is exact.
+__device__ inline double ls_slope(uint64_t len, U128 sv, U128 stv) {
+  const uint64_t st = len * (len - 1) / 2;                         // < 2^39
   const uint64_t stt = ((len - 1) * len / 2) * (2 * len - 1) / 3;  // < 2^61, exact
   const U128 N = sub128(mul128x64(stv, len), mul128x64(sv, st));
   const U128 D = sub128(mul64x64(len, stt), mul64x64(st, st));
@@ -101,285 +140,441 @@ __device__ double ls_slope(uint64_t len, U128 sv, U128 stv) {
   return slope;
 }
 
-__global__ __launch_bounds__(kFitBlock) void k_fit(const uint8_t* __restrict__ col, uint64_t n,
-                                                   uint32_t dtype, uint64_t fixed_len,
-                                                   const uint64_t* __restrict__ starts, uint64_t m,
-                                                   int force_constant,
-                                                   PartModel* __restrict__ models) {
-  __shared__ FitScratch s;
-  const uint32_t tid = threadIdx.x;
-  for (uint64_t j = blockIdx.x; j < m; j += gridDim.x) {
-    const PartBounds pb = enc_bounds(j, n, fixed_len, starts);
-    const uint64_t len = pb.len;
-    const uint8_t* base_ptr = col + pb.start * dtype;
-    const bool in_regs = len <= uint64_t(kFitBlock) * kFitRegs;
-    uint64_t regs[kFitRegs];
+// The slope computed once (by wave 0) and broadcast through LDS.
+__device__ inline double block_slope(EncShared& sh, uint64_t len, U128 sv, U128 stv) {
+  if ((threadIdx.x >> 6) == 0) {
+    const double th = ls_slope(len, sv, stv);
+    if (threadIdx.x == 0) sh.theta1 = th;
+  }
+  __syncthreads();
+  return sh.theta1;
+}
 
-    // Pass 1: range and exact sums.
-    uint64_t vmin = ~uint64_t(0), vmax = 0;
-    U128 sv{0, 0}, stv{0, 0};
+// ORs a residual u (< 2^b) into the LDS stream at bit q.
+__device__ inline void or_bits(uint32_t* w, uint32_t q, uint32_t b, uint64_t u) {
+  if (u == 0) return;
+  const uint32_t i = q >> 5, s = q & 31;
+  atomicOr(&w[i], uint32_t(u << s));
+  if (s + b > 32) atomicOr(&w[i + 1], uint32_t(u >> (32 - s)));
+  if (s + b > 64) atomicOr(&w[i + 2], uint32_t(u >> (64 - s)));
+}
+// Same for b <= 32.
+__device__ inline void or_bits32(uint32_t* w, uint32_t q, uint32_t b, uint32_t u) {
+  if (u == 0) return;
+  const uint32_t i = q >> 5, s = q & 31;
+  atomicOr(&w[i], u << s);
+  if (s + b > 32) atomicOr(&w[i + 1], u >> (32 - s));
+}
+
+// The model of one partition, identical in every thread of the workgroup.
+struct Model {
+  uint64_t vmin, base;
+  double theta1;
+  uint32_t bits;
+  bool linear;
+  int64_t rmin;
+};
+
+// Chooses between the constant model and the fitted line (ties keep the
+// constant model, whose width never exceeds bitlen(vmax - vmin)).
+__device__ inline void choose_model(Model& md, double th, int64_t rmin, int64_t rmax) {
+  const uint32_t b_ls = bitlen64(uint64_t(rmax) - uint64_t(rmin));
+  if (b_ls < md.bits) {
+    md.linear = true;
+    md.theta1 = th;
+    md.base = md.vmin + uint64_t(rmin);
+    md.bits = b_ls;
+    md.rmin = rmin;
+  }
+}
+
+__device__ inline const EncColumn& column_of(const EncColumn* cols, uint64_t ncols,
+                                             const EncColumn& single, uint64_t P) {
+  if (cols == nullptr) return single;
+  uint64_t lo = 0, hi = ncols;  // last column with part_base <= P
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (cols[mid].part_base <= P) lo = mid; else hi = mid;
+  }
+  return cols[lo];
+}
+
+__device__ inline void write_header(const EncColumn& c, uint64_t total_words) {
+  uint64_t* hd = reinterpret_cast<uint64_t*>(c.blob);
+  const bool variable = c.fixed_len == 0;
+  hd[0] = uint64_t(kMagic) | (uint64_t(kVersion) << 32) | (uint64_t(c.dtype) << 48) |
+          (uint64_t(variable ? 1 : 0) << 56);
+  hd[1] = c.n;
+  hd[2] = c.m;
+  hd[3] = c.fixed_len;
+  hd[4] = kHeaderBytes;
+  hd[5] = variable ? kHeaderBytes + kRecordBytes * c.m : 0;
+  hd[6] = c.words_off;
+  hd[7] = total_words;
+}
+
+// Header, the last start and the zero padding of a column whose total word
+// count is known; size checked against the capacity.
+__device__ inline void finish_column(const EncColumn& c, uint64_t total_words, int* err) {
+  const uint64_t size = align16(c.words_off + 8 * total_words);
+  if (c.size_out) *c.size_out = size;
+  if (size > c.cap) {
+    raise(err, kErrNoSpace);
+    return;
+  }
+  write_header(c, total_words);
+  const bool variable = c.fixed_len == 0;
+  const uint64_t meta_end = kHeaderBytes + kRecordBytes * c.m + (variable ? 8 * (c.m + 1) : 0);
+  if (variable) reinterpret_cast<uint64_t*>(c.blob + kHeaderBytes + kRecordBytes * c.m)[c.m] = c.n;
+  for (uint64_t i = meta_end; i < c.words_off; ++i) c.blob[i] = 0;
+  for (uint64_t i = c.words_off + 8 * total_words; i < size; ++i) c.blob[i] = 0;
+}
+
+// Word offset of partition P inside its column by decoupled look-back, then
+// its record (and start); the last partition also finishes the column.
+// Wave 0 reads kRows rows of 64 predecessors per round trip (row r, lane l
+// holds partition top - 64 r - l; partitions before the column's first
+// count as an inclusive prefix of 0), so the inclusive-prefix frontier
+// advances kRows * 64 partitions per global-memory round trip.  The status
+// words carry their own value, so relaxed device-scope atomics suffice.
+__device__ uint64_t publish_and_look_back(EncShared& sh, const EncColumn& c, uint64_t P,
+                                          uint64_t j, uint64_t start, uint64_t nwords,
+                                          const Model& md, uint64_t* status, int* err) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    if (lane == 0)
+      __hip_atomic_store(&status[P], (j == 0 ? kFlagPrefix : kFlagAgg) | nwords, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    if (j != 0) {
+      // The first round reads one row (the frontier is usually near); a
+      // round that consumes its whole window without a prefix widens it.
+      constexpr int kRows = 4;
+      int rows = 1;
+      int64_t top = int64_t(P) - 1;
+      uint32_t spins = 0;
+      bool done = false;
+      while (!done) {
+        uint64_t s[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          const int64_t q = top - 64 * r - int64_t(lane);
+          s[r] = (r < rows && q >= int64_t(c.part_base))
+                     ? __hip_atomic_load(&status[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : kFlagPrefix;
+        }
+        uint64_t add = 0;
+        int rows_used = 0;
+        bool wait = false;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+          if (done || wait || r >= rows) continue;
+          const uint64_t not_ready = __ballot((s[r] >> 62) == 0);
+          const uint64_t prefix = __ballot((s[r] >> 62) == 2);
+          const uint32_t first =
+              prefix ? uint32_t(__ffsll(static_cast<long long>(prefix)) - 1) : 64u;
+          const uint64_t needed = first >= 63 ? ~uint64_t(0) : ((uint64_t(2) << first) - 1);
+          if (not_ready & needed) {
+            wait = true;
+            continue;
+          }
+          uint64_t x = lane <= first ? (s[r] & kValueMask) : 0;
+#pragma unroll
+          for (int m = 32; m > 0; m >>= 1) x += shfl_xor64(x, m);
+          add += x;
+          ++rows_used;
+          if (first < 64) done = true;
+        }
+        // rows before the first unready one are final: keep them, move on
+        excl += add;
+        top -= 64 * rows_used;
+        if (wait && !done) {
+          if (++spins > kSpinLimit) {
+            if (lane == 0) raise(err, kErrDevice);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        } else {
+          rows = kRows;
+        }
+      }
+      if (lane == 0)
+        __hip_atomic_store(&status[P], kFlagPrefix | ((excl + nwords) & kValueMask),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) {
+      sh.word_off = excl;
+      const uint64_t rec = kHeaderBytes + kRecordBytes * j;
+      if (rec + kRecordBytes <= c.cap) {
+        uint64_t* r = reinterpret_cast<uint64_t*>(c.blob + rec);
+        r[0] = md.base;
+        r[1] = uint64_t(__double_as_longlong(md.theta1));
+        r[2] = excl;
+        r[3] = uint64_t(md.bits);
+      }
+      if (c.fixed_len == 0) {
+        const uint64_t so = kHeaderBytes + kRecordBytes * c.m + 8 * j;
+        if (so + 8 <= c.cap) *reinterpret_cast<uint64_t*>(c.blob + so) = start;
+      }
+      if (j + 1 == c.m) finish_column(c, excl + nwords, err);
+    }
+  }
+  __syncthreads();
+  return sh.word_off;
+}
+
+// Copies packed words [0, cw) of the LDS buffer to global words [w0, w0+cw).
+__device__ inline void store_words(const EncShared& sh, uint64_t* gwords, uint64_t w0,
+                                   uint32_t cw, uint64_t cap_words) {
+  for (uint32_t i = threadIdx.x; i < cw; i += kEncBlock)
+    if (w0 + i < cap_words) gwords[w0 + i] = sh.words[i];
+}
+
+__device__ inline void zero_words(EncShared& sh, uint32_t cw) {
+  for (uint32_t i = threadIdx.x; i < cw; i += kEncBlock) sh.words[i] = 0;
+}
+
+__global__ __launch_bounds__(kEncBlock) void k_encode(const EncColumn* __restrict__ cols,
+                                                     uint64_t ncols, EncColumn single,
+                                                     uint64_t* __restrict__ status,
+                                                     unsigned long long* __restrict__ ticket,
+                                                     int* err) {
+  __shared__ EncShared sh;
+  const uint32_t tid = threadIdx.x;
+  // Partition order: a ticket from one counter (no assumption on dispatch
+  // order), or the workgroup index (workgroups are dispatched in index
+  // order, so every predecessor of a running workgroup has started).
+  uint64_t P = blockIdx.x;
+  if (ticket) {
+    if (tid == 0) sh.ticket = atomicAdd(ticket, 1ull);
+    __syncthreads();
+    P = sh.ticket;
+  }
+  const EncColumn& c = column_of(cols, ncols, single, P);
+  const uint64_t j = P - c.part_base;
+  uint64_t start, len;
+  if (c.fixed_len) {
+    start = j * c.fixed_len;
+    len = (start + c.fixed_len < c.n ? start + c.fixed_len : c.n) - start;
+  } else {
+    start = c.starts[j];
+    len = c.starts[j + 1] - start;
+  }
+  const uint8_t* src = c.col + start * c.dtype;
+  const bool in_regs = len <= kEncRegLen;
+  const bool fit_allowed = !(len == 1 || c.force_constant);
+  uint64_t* gwords = reinterpret_cast<uint64_t*>(c.blob + c.words_off);
+  const uint64_t cap_words = c.cap > c.words_off ? (c.cap - c.words_off) / 8 : 0;
+  uint32_t* w32 = reinterpret_cast<uint32_t*>(sh.words);
+
+  uint64_t v[kEncRegs];
+  uint64_t vmin = ~uint64_t(0), vmax = 0;
+  U128 sv{0, 0}, stv{0, 0};
+  if (in_regs) {
+#pragma unroll
+    for (int k = 0; k < kEncRegs; ++k) {
+      const uint32_t t = tid + k * kEncBlock;
+      v[k] = t < len ? load_value(src, c.dtype, t) : 0;
+      if (t < len) {
+        vmin = v[k] < vmin ? v[k] : vmin;
+        vmax = v[k] > vmax ? v[k] : vmax;
+      }
+    }
+  } else {
+    // streamed: range and raw sums in one pass
+    for (uint64_t t = tid; t < len; t += kEncBlock) {
+      const uint64_t x = load_value(src, c.dtype, t);
+      vmin = x < vmin ? x : vmin;
+      vmax = x > vmax ? x : vmax;
+      sv = add128(sv, U128{x, 0});
+      stv = add128(stv, mul64x64(t, x));
+    }
+  }
+  block_minmax_u64(sh, vmin, vmax);
+  const uint64_t range = vmax - vmin;
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  const bool fit = fit_allowed && range < (uint64_t(1) << 61);
+
+  if (in_regs && range < kNarrowRange) {
+    // ---- narrow path ----
+    uint32_t y[kEncRegs];
+#pragma unroll
+    for (int k = 0; k < kEncRegs; ++k) y[k] = uint32_t(v[k]) - uint32_t(vmin);  // y < 2^30
+    int32_t r[kEncRegs];
+    bool small = false;
+    if (fit) {
+      uint64_t sy = 0, sty = 0;  // < 2^42 and < 2^54
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = tid + k * kEncBlock;
+        if (t < len) {
+          sy += y[k];
+          sty += uint64_t(t) * y[k];
+        }
+      }
+      block_sum_u64x2(sh, sy, sty);
+      const double th = block_slope(sh, len, U128{sy, 0}, U128{sty, 0});
+      // |floor(theta1 t)| < 2^30 for every t < len, so residuals fit int32
+      small = __dmul_rn(fabs(th), double(len)) < 1073741824.0;
+      int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+      if (small) {
+        int32_t mn = INT32_MAX, mx = INT32_MIN;
+#pragma unroll
+        for (int k = 0; k < kEncRegs; ++k) {
+          const uint32_t t = tid + k * kEncBlock;
+          r[k] = 0;
+          if (t < len) {
+            r[k] = int32_t(y[k]) - predict32(th, t);
+            mn = r[k] < mn ? r[k] : mn;
+            mx = r[k] > mx ? r[k] : mx;
+          }
+        }
+        rmin = mn;
+        rmax = mx;
+      } else {
+#pragma unroll
+        for (int k = 0; k < kEncRegs; ++k) {
+          const uint32_t t = tid + k * kEncBlock;
+          if (t < len) {
+            const int64_t rr = int64_t(y[k]) - predict(th, t);
+            rmin = rr < rmin ? rr : rmin;
+            rmax = rr > rmax ? rr : rmax;
+          }
+        }
+      }
+      block_minmax_i64(sh, rmin, rmax);
+      choose_model(md, th, rmin, rmax);
+    }
+    const uint32_t b = md.bits;  // <= 30
+    const uint64_t nwords = (len * b + 63) >> 6;
+    const uint64_t word_off =
+        publish_and_look_back(sh, c, P, j, start, nwords, md, status, err);
+    if (b == 0) return;
+    const uint32_t cw = uint32_t(nwords);  // <= 4096 * 30 / 64 < kPackWords
+    zero_words(sh, cw);
+    __syncthreads();
+    const int32_t rmin32 = int32_t(md.rmin);
+#pragma unroll
+    for (int k = 0; k < kEncRegs; ++k) {
+      const uint32_t t = tid + k * kEncBlock;
+      if (t < len) {
+        uint32_t u;
+        if (!md.linear) u = y[k];
+        else if (small) u = uint32_t(r[k] - rmin32);
+        else u = uint32_t(uint64_t(int64_t(y[k]) - predict(md.theta1, t)) - uint64_t(md.rmin));
+        or_bits32(w32, t * b, b, u);
+      }
+    }
+    __syncthreads();
+    store_words(sh, gwords, word_off, cw, cap_words);
+    return;
+  }
+
+  // ---- general path: 128-bit sums, 64-bit residuals ----
+  if (fit) {
     if (in_regs) {
 #pragma unroll
-      for (int k = 0; k < kFitRegs; ++k) {
-        const uint32_t t = tid + k * kFitBlock;
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = tid + k * kEncBlock;
         if (t < len) {
-          const uint64_t v = load_value(base_ptr, dtype, t);
-          regs[k] = v;
-          vmin = v < vmin ? v : vmin;
-          vmax = v > vmax ? v : vmax;
-          sv = add128(sv, U128{v, 0});
-          stv = add128(stv, mul64x64(t, v));
+          sv = add128(sv, U128{v[k], 0});
+          stv = add128(stv, mul64x64(t, v[k]));
+        }
+      }
+    }
+    block_sum_u128x2(sh, sv, stv);
+    const double th = block_slope(sh, len, sv, stv);
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+    if (in_regs) {
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = tid + k * kEncBlock;
+        if (t < len) {
+          const int64_t rr = int64_t(v[k] - vmin) - predict(th, t);
+          rmin = rr < rmin ? rr : rmin;
+          rmax = rr > rmax ? rr : rmax;
         }
       }
     } else {
-      for (uint64_t t = tid; t < len; t += kFitBlock) {
-        const uint64_t v = load_value(base_ptr, dtype, t);
-        vmin = v < vmin ? v : vmin;
-        vmax = v > vmax ? v : vmax;
-        sv = add128(sv, U128{v, 0});
-        stv = add128(stv, mul64x64(t, v));
+      for (uint64_t t = tid; t < len; t += kEncBlock) {
+        const int64_t rr = int64_t(load_value(src, c.dtype, t) - vmin) - predict(th, uint32_t(t));
+        rmin = rr < rmin ? rr : rmin;
+        rmax = rr > rmax ? rr : rmax;
       }
     }
-    reduce_pass1(s, vmin, vmax, sv, stv);
-    const uint64_t range = vmax - vmin;
-    const uint32_t b_for = bitlen64(range);
-    const bool fit = !(len == 1 || force_constant || range >= (uint64_t(1) << 61));
+    block_minmax_i64(sh, rmin, rmax);
+    choose_model(md, th, rmin, rmax);
+  }
+  const uint32_t b = md.bits;
+  const uint64_t nwords = (len * b + 63) >> 6;
+  const uint64_t word_off = publish_and_look_back(sh, c, P, j, start, nwords, md, status, err);
+  if (b == 0) return;
 
-    PartModel pm;
-    pm.base = vmin;
-    pm.theta1 = 0.0;
-    pm.bits = b_for;
-    pm.pad = 0;
-    if (fit) {
-      if (tid == 0) s.theta1 = ls_slope(len, sv, stv);
-      __syncthreads();
-      const double th = s.theta1;
-      // Pass 2: residual range of the linear model.
-      int64_t rmin = INT64_MAX, rmax = INT64_MIN;
-      if (in_regs) {
+  // residual t at bits [b t, b t + b) of the partition's span, in chunks
+  // whose words fit the LDS buffer (chunk * b / 64 <= kPackWords)
+  const uint32_t chunk = b <= 32 ? 4096u : 2048u;
+  for (uint64_t c0 = 0; c0 < len; c0 += chunk) {
+    const uint64_t c1 = c0 + chunk < len ? c0 + chunk : len;
+    const uint32_t cw = uint32_t(((c1 - c0) * b + 63) >> 6);
+    zero_words(sh, cw);
+    __syncthreads();
+    if (in_regs) {
 #pragma unroll
-        for (int k = 0; k < kFitRegs; ++k) {
-          const uint32_t t = tid + k * kFitBlock;
-          if (t < len) {
-            const int64_t r = int64_t(regs[k] - vmin) - predict(th, t);
-            rmin = r < rmin ? r : rmin;
-            rmax = r > rmax ? r : rmax;
-          }
-        }
-      } else {
-        for (uint64_t t = tid; t < len; t += kFitBlock) {
-          const int64_t r = int64_t(load_value(base_ptr, dtype, t) - vmin) - predict(th, uint32_t(t));
-          rmin = r < rmin ? r : rmin;
-          rmax = r > rmax ? r : rmax;
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = tid + k * kEncBlock;
+        if (t >= c0 && t < c1) {
+          const uint64_t yy = v[k] - md.base;
+          const uint64_t u = md.linear ? yy - uint64_t(predict(md.theta1, t)) : yy;
+          or_bits(w32, uint32_t(t - c0) * b, b, u);
         }
       }
-      reduce_minmax_i64(s, rmin, rmax);
-      const uint32_t b_ls = bitlen64(uint64_t(rmax) - uint64_t(rmin));
-      if (b_ls < b_for) {  // ties keep the constant model
-        pm.base = vmin + uint64_t(rmin);
-        pm.theta1 = th;
-        pm.bits = b_ls;
+    } else {
+      for (uint64_t t = c0 + tid; t < c1; t += kEncBlock) {
+        const uint64_t yy = load_value(src, c.dtype, t) - md.base;
+        const uint64_t u = md.linear ? yy - uint64_t(predict(md.theta1, uint32_t(t))) : yy;
+        or_bits(w32, uint32_t(t - c0) * b, b, u);
       }
     }
-    pm.nwords = (len * pm.bits + 63) >> 6;
-    if (tid == 0) models[j] = pm;
+    __syncthreads();
+    store_words(sh, gwords, word_off + ((c0 * b) >> 6), cw, cap_words);
     __syncthreads();
   }
 }
 
-// ---- word-offset scan ---------------------------------------------------------
-
-constexpr int kScanBlock = 256;
-constexpr int kScanItems = 16;
-constexpr uint64_t kScanTile = uint64_t(kScanBlock) * kScanItems;
-
-__device__ uint64_t block_exclusive_scan(uint64_t x, uint64_t* sh, uint64_t& total) {
-  const uint32_t tid = threadIdx.x;
-  sh[tid] = x;
-  __syncthreads();
-  for (uint32_t off = 1; off < kScanBlock; off <<= 1) {
-    const uint64_t y = tid >= off ? sh[tid - off] : 0;
-    __syncthreads();
-    sh[tid] += y;
-    __syncthreads();
-  }
-  total = sh[kScanBlock - 1];
-  const uint64_t incl = sh[tid];
-  __syncthreads();
-  return incl - x;
-}
-
-__global__ __launch_bounds__(kScanBlock) void k_scan_partial(const PartModel* __restrict__ models,
-                                                             uint64_t m, uint64_t* partial) {
-  __shared__ uint64_t sh[kScanBlock];
-  const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
-  uint64_t x = 0;
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < m) x += models[base + k].nwords;
-  uint64_t total;
-  block_exclusive_scan(x, sh, total);
-  if (threadIdx.x == 0) partial[blockIdx.x] = total;
-}
-
-// Exclusive scan of the per-tile sums in place (one workgroup, looping with
-// a running carry), then the blob size and the capacity check.
-__global__ __launch_bounds__(kScanBlock) void k_scan_top(uint64_t* partial, uint64_t nb,
-                                                         uint64_t words_off, uint64_t cap,
-                                                         uint64_t* total_words, uint64_t* size_out,
-                                                         int* err) {
-  __shared__ uint64_t sh[kScanBlock];
-  uint64_t carry = 0;
-  for (uint64_t c = 0; c < nb; c += kScanBlock) {
-    const uint64_t i = c + threadIdx.x;
-    const uint64_t x = i < nb ? partial[i] : 0;
-    uint64_t total;
-    const uint64_t ex = block_exclusive_scan(x, sh, total);
-    if (i < nb) partial[i] = carry + ex;
-    carry += total;
-  }
-  if (threadIdx.x == 0) {
-    const uint64_t size = align16(words_off + 8 * carry);
-    *total_words = carry;
-    *size_out = size;
-    if (size > cap) atomicOr(err, kErrNoSpace);
+// Clears the look-back state and ticket, and writes the complete blob of
+// every empty column (no partitions, so no workgroup of k_encode sees it).
+__global__ void k_encode_prepare(const EncColumn* __restrict__ cols, uint64_t ncols,
+                                 EncColumn single, uint64_t* __restrict__ status,
+                                 uint64_t nparts, unsigned long long* ticket, int* err) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (uint64_t i = gid; i < nparts; i += stride) status[i] = 0;
+  if (gid == 0) *ticket = 0;
+  for (uint64_t i = gid; i < ncols; i += stride) {
+    const EncColumn& c = cols ? cols[i] : single;
+    if (c.m != 0) continue;
+    finish_column(c, 0, err);  // also writes starts[0] = 0 of a variable column
   }
 }
 
-// Word offsets of every partition, then (when the blob fits) its records,
-// header, starts and padding.
-__global__ __launch_bounds__(kScanBlock) void k_scan_final(
-    const PartModel* __restrict__ models, uint64_t m, const uint64_t* __restrict__ partial,
-    uint64_t* __restrict__ word_off, uint8_t* __restrict__ blob, uint64_t cap,
-    const uint64_t* __restrict__ total_words, const uint64_t* __restrict__ size_in, uint64_t n,
-    uint32_t dtype, uint64_t fixed_len, const uint64_t* __restrict__ starts, uint64_t words_off) {
-  __shared__ uint64_t sh[kScanBlock];
-  const uint64_t size = *size_in;
-  const bool fits = size <= cap;
-  const uint64_t base = uint64_t(blockIdx.x) * kScanTile + uint64_t(threadIdx.x) * kScanItems;
-  uint64_t x = 0;
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < m) x += models[base + k].nwords;
-  uint64_t total;
-  uint64_t off = block_exclusive_scan(x, sh, total) + (blockIdx.x < gridDim.x && m ? partial[blockIdx.x] : 0);
-  for (int k = 0; k < kScanItems; ++k) {
-    const uint64_t j = base + k;
-    if (j >= m) break;
-    const PartModel pm = models[j];
-    word_off[j] = off;
-    if (fits) {
-      uint64_t* r = reinterpret_cast<uint64_t*>(blob + kHeaderBytes + kRecordBytes * j);
-      r[0] = pm.base;
-      r[1] = uint64_t(__double_as_longlong(pm.theta1));
-      r[2] = off;
-      r[3] = uint64_t(pm.bits & 0xff);
-    }
-    off += pm.nwords;
-  }
-  if (!fits) return;
-  const bool variable = fixed_len == 0;
-  const uint64_t meta_end = kHeaderBytes + kRecordBytes * m + (variable ? 8 * (m + 1) : 0);
-  const uint64_t tw = *total_words;
-  if (variable) {
-    uint64_t* sdst = reinterpret_cast<uint64_t*>(blob + kHeaderBytes + kRecordBytes * m);
-    for (uint64_t i = uint64_t(blockIdx.x) * kScanBlock + threadIdx.x; i <= m;
-         i += uint64_t(gridDim.x) * kScanBlock)
-      sdst[i] = starts[i];
-  }
-  if (blockIdx.x == 0) {
-    // zero padding before the words and after the last word
-    for (uint64_t i = meta_end + threadIdx.x; i < words_off; i += kScanBlock) blob[i] = 0;
-    for (uint64_t i = words_off + 8 * tw + threadIdx.x; i < size; i += kScanBlock) blob[i] = 0;
-    if (threadIdx.x == 0) {
-      uint64_t* hd = reinterpret_cast<uint64_t*>(blob);
-      hd[0] = uint64_t(kMagic) | (uint64_t(kVersion) << 32) | (uint64_t(dtype) << 48) |
-              (uint64_t(variable ? 1 : 0) << 56);
-      hd[1] = n;
-      hd[2] = m;
-      hd[3] = fixed_len;
-      hd[4] = kHeaderBytes;
-      hd[5] = variable ? kHeaderBytes + kRecordBytes * m : 0;
-      hd[6] = words_off;
-      hd[7] = tw;
-    }
-  }
-}
-
-// ---- bit-packing -----------------------------------------------------------------
-
-// Word w of partition j holds bits [64 w, 64 w + 64) of the partition's
-// residual stream; residual t occupies bits [b t, b t + b).  Each thread
-// assembles whole words from the residuals that overlap them.
-__global__ __launch_bounds__(256) void k_pack(const uint8_t* __restrict__ col, uint64_t n,
-                                              uint32_t dtype, uint64_t fixed_len,
-                                              const uint64_t* __restrict__ starts, uint64_t m,
-                                              const PartModel* __restrict__ models,
-                                              const uint64_t* __restrict__ word_off,
-                                              uint8_t* __restrict__ blob, uint64_t cap,
-                                              const uint64_t* __restrict__ size_in,
-                                              uint64_t words_off) {
-  if (*size_in > cap) return;
-  uint64_t* words = reinterpret_cast<uint64_t*>(blob + words_off);
-  for (uint64_t j = blockIdx.x; j < m; j += gridDim.x) {
-    const PartModel pm = models[j];
-    const uint32_t b = pm.bits;
-    if (b == 0) continue;
-    const PartBounds pb = enc_bounds(j, n, fixed_len, starts);
-    const uint8_t* src = col + pb.start * dtype;
-    const uint64_t wbase = word_off[j];
-    for (uint64_t w = threadIdx.x; w < pm.nwords; w += blockDim.x) {
-      const uint32_t bit0 = uint32_t(64 * w);  // < 2^26: partitions hold <= 2^20 values
-      uint64_t t = bit0 / b;
-      uint64_t t_last = (bit0 + 63) / b;
-      if (t_last >= pb.len) t_last = pb.len - 1;
-      uint64_t word = 0;
-      for (; t <= t_last; ++t) {
-        const uint64_t u = load_value(src, dtype, t) - pm.base -
-                           uint64_t(predict(pm.theta1, uint32_t(t)));
-        const int64_t off = int64_t(b * t) - int64_t(bit0);
-        word |= off >= 0 ? (u << off) : (u >> -off);
-      }
-      words[wbase + w] = word;
-    }
-  }
-}
-
-// ---- launcher ---------------------------------------------------------------------
-
-hipError_t launch_encode(leco_ctx* ctx, const EncodePlan& pl, hipStream_t stream) {
-  const uint64_t m = pl.m;
-  const uint64_t fit_cap = uint64_t(ctx->num_cus) * 8;
-  if (m > 0) {
-    const uint64_t g = m < fit_cap ? m : fit_cap;
-    hipLaunchKernelGGL(k_fit, dim3(uint32_t(g)), dim3(kFitBlock), 0, stream,
-                       static_cast<const uint8_t*>(pl.col), pl.n, pl.dtype, pl.fixed_len,
-                       pl.starts_dev, m, pl.force_constant, pl.models);
-  }
-  const uint64_t nb = (m + kScanTile - 1) / kScanTile;
-  if (nb > 0)
-    hipLaunchKernelGGL(k_scan_partial, dim3(uint32_t(nb)), dim3(kScanBlock), 0, stream,
-                       pl.models, m, pl.partial);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, stream, pl.partial, nb,
-                     pl.words_off, pl.cap, pl.total_words, pl.size_dev, ctx->err_dev);
-  const uint64_t nf = nb > 0 ? nb : 1;
-  hipLaunchKernelGGL(k_scan_final, dim3(uint32_t(nf)), dim3(kScanBlock), 0, stream, pl.models, m,
-                     pl.partial, pl.word_off, static_cast<uint8_t*>(pl.blob), pl.cap,
-                     pl.total_words, pl.size_dev, pl.n, pl.dtype, pl.fixed_len, pl.starts_dev,
-                     pl.words_off);
-  if (m > 0) {
-    const uint64_t g = m < fit_cap ? m : fit_cap;
-    hipLaunchKernelGGL(k_pack, dim3(uint32_t(g)), dim3(256), 0, stream,
-                       static_cast<const uint8_t*>(pl.col), pl.n, pl.dtype, pl.fixed_len,
-                       pl.starts_dev, m, pl.models, pl.word_off, static_cast<uint8_t*>(pl.blob),
-                       pl.cap, pl.size_dev, pl.words_off);
-  }
+hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
+                                 const EncColumn& single, uint64_t nparts, uint64_t* status,
+                                 unsigned long long* ticket, hipStream_t stream) {
+  const uint64_t pg = (nparts + 255) / 256;
+  const uint64_t cg = (ncols + 255) / 256;
+  uint64_t g = pg > cg ? pg : cg;
+  if (g == 0) g = 1;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_encode_prepare, dim3(uint32_t(g)), dim3(256), 0, stream, cols_dev, ncols,
+                     single, status, nparts, ticket, ctx->err_dev);
+  if (nparts > 0)
+    hipLaunchKernelGGL(k_encode, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
+                       ncols, single, status, ctx->tune.encode_ticket ? ticket : nullptr,
+                       ctx->err_dev);
   return hipGetLastError();
 }
 
-}  // namespace leco
-
 // ---- diagnostics --------------------------------------------------------------
-
-namespace leco {
 
 __global__ void k_diag_slope(const uint64_t* __restrict__ in, uint64_t k, double* __restrict__ out) {
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;

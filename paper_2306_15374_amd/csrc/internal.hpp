@@ -10,42 +10,30 @@
 
 namespace leco {
 
-// Per-partition model produced by the fit kernel (32 bytes).
-struct PartModel {
-  uint64_t base;
-  double theta1;
-  uint64_t nwords;
-  uint32_t bits;
-  uint32_t pad;
-};
-
-// Launch parameters chosen per context (see the tuner in tune.hip).
+// Launch parameters chosen per context (see tune.hip).
 struct Tune {
   uint32_t tile_log2 = 12;           // values per decode tile = 2^tile_log2
   uint32_t decode_blocks_per_cu = 0; // 0 = one workgroup per tile
   uint32_t xcd_remap = 0;            // 1 = contiguous tile runs per XCD
   uint32_t ra_lookups_per_lane = 1;  // 1, 2, 4 or 8 positions per lane
+  uint32_t encode_ticket = 1;        // 1 = partition order from a ticket counter
 };
 
 // Reads LECO_TILE_LOG2, LECO_DECODE_BLOCKS_PER_CU, LECO_XCD_REMAP and
-// LECO_RA_LPT overrides from the environment.
+// LECO_RA_LPT, LECO_ENCODE_TICKET overrides from the environment.
 void tune_from_env(Tune& t);
 
-// Everything the encode kernels need, with scratch already carved out.
-struct EncodePlan {
-  const void* col;
-  uint64_t n, m, fixed_len;
-  uint32_t dtype;
-  int force_constant;
-  const uint64_t* starts_dev;  // m + 1 starts (variable) or null
-  void* blob;
-  uint64_t cap;
-  uint64_t words_off;
-  PartModel* models;     // m
-  uint64_t* word_off;    // m
-  uint64_t* partial;     // ceil(m / 4096)
-  uint64_t* total_words; // 1
-  uint64_t* size_dev;    // 1
+// One column for the encoder: input, partitioning, output blob.  A table of
+// these (device memory) drives one encode launch over many columns.
+struct EncColumn {
+  const uint8_t* col;      // n values of dtype
+  uint8_t* blob;           // cap bytes
+  const uint64_t* starts;  // m + 1 starts in device memory (variable), else null
+  uint64_t* size_out;      // device word receiving the blob size, or null
+  uint64_t n, m, fixed_len, cap;
+  uint64_t words_off;      // offset of the words section
+  uint64_t part_base;      // index of the column's first partition in the launch
+  uint32_t dtype, force_constant;
 };
 
 hipError_t launch_decode(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, void* out,
@@ -56,7 +44,11 @@ hipError_t launch_random_access(leco_ctx* ctx, const void* blob, uint64_t blob_b
 hipError_t launch_filter_sum(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, uint64_t lo,
                              uint64_t hi, uint64_t* out3, bool prune, hipStream_t stream);
 hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream);
-hipError_t launch_encode(leco_ctx* ctx, const EncodePlan& plan, hipStream_t stream);
+// Encodes ncols columns (table cols_dev, or `single` when cols_dev is null)
+// with nparts partitions in total; status holds nparts look-back words.
+hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
+                                 const EncColumn& single, uint64_t nparts, uint64_t* status,
+                                 unsigned long long* ticket, hipStream_t stream);
 hipError_t launch_diag_slope(const uint64_t* in, uint64_t k, double* out, hipStream_t stream);
 hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t bytes,
                             hipStream_t stream);

@@ -18,6 +18,7 @@ constexpr uint64_t kMaxPartLen = 1ull << 20;
 constexpr int kErrRange = 1;
 constexpr int kErrFormat = 2;
 constexpr int kErrNoSpace = 4;
+constexpr int kErrDevice = 8;  // a bounded wait gave up (never expected)
 
 __host__ __device__ inline uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
 

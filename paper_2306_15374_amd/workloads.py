@@ -161,3 +161,43 @@ def request_stream(num: int, col_lens, seed: int = C5_SEED + 1, rate: float = 1.
             b = int(rng.integers(0, n - ln + 1))
             reqs.append(dict(t=float(t[q]), kind="range", col=c, begin=b, end=b + ln))
     return reqs
+
+
+# ---- device-side generators for the multi-gigabyte workloads ---------------------
+# Drawing 2e9 values on the host takes minutes, so the batched and served
+# workloads draw each column on the GPU with torch's seeded Philox generator
+# (one seed per column).  Same shapes as the host generators above; 32-bit
+# columns are returned as int32 tensors holding the uint32 bit patterns
+# (every generated value is below 2^31), 64-bit columns as int64.
+
+def _torch_gen(seed: int, device):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return g
+
+
+def linear_noise_device(n: int, seed: int, dtype, device="cuda"):
+    import torch
+    g = _torch_gen(seed, device)
+    v = torch.arange(n, dtype=torch.int64, device=device) * 7 + 1000
+    v += torch.randint(0, 64, (n,), generator=g, device=device, dtype=torch.int64)
+    return v.to(torch.int32) if dtype == np.uint32 else v
+
+
+def lognormal_keys_device(n: int, seed: int, dtype, device="cuda"):
+    import torch
+    g = _torch_gen(seed, device)
+    x = torch.randn(n, generator=g, device=device, dtype=torch.float64)
+    gaps = torch.round(torch.exp(x * 1.5 + 3.0)).clamp_(min=1.0).to(torch.int64)
+    keys = torch.cumsum(gaps, 0)
+    if dtype == np.uint32:
+        assert n == 0 or int(keys[-1]) < 2**31, "keys overflow the 32-bit column"
+        return keys.to(torch.int32)
+    return keys
+
+
+def make_column_device(spec: dict, device="cuda"):
+    if spec["kind"] == "linear_noise":
+        return linear_noise_device(spec["n"], spec["seed"], spec["dtype"], device)
+    return lognormal_keys_device(spec["n"], spec["seed"], spec["dtype"], device)
