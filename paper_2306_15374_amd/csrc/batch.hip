@@ -37,14 +37,17 @@ struct BatchSink {
   }
 };
 
+// Decodes this wavefront's share [g0, g1) of a column tile; with kFilter,
+// every thread of the workgroup then joins the exact sum (a workgroup
+// barrier, reached by all waves whatever their share held).
 template <typename OutT, bool kStore, bool kFilter>
 __device__ bool run_tile(const DecCol& c, const Header& h, uint64_t g0, uint64_t g1,
                          uint32_t* stage) {
   BatchSink<OutT, kStore, kFilter> sink{reinterpret_cast<OutT*>(c.out),
                                         FilterSink{c.lo, c.hi, 0, 0, 0, kStore ? 0 : 1}};
-  if (!decode_tile(c.blob, h, g0, g1, stage, sink)) return false;
+  const bool ok = g0 >= g1 || decode_tile(c.blob, h, g0, g1, stage, sink);
   if (kFilter) block_add_sum(sink.f.sum_lo, sink.f.sum_hi, sink.f.count, c.sum3);
-  return true;
+  return ok;
 }
 
 template <bool kStore, bool kFilter>
@@ -52,8 +55,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restric
                                                          const uint32_t* __restrict__ tile_col,
                                                          uint64_t total_tiles, uint32_t tile_log2,
                                                          int* err) {
-  __shared__ uint4 stage_v[kStageWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v);
+  __shared__ uint4 stage_v[kWavesPerBlock * kWaveStageWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveStageWords;
   for (uint64_t k = blockIdx.x; k < total_tiles; k += gridDim.x) {
     const DecCol& c = cols[tile_col[k]];
     Header h;
@@ -61,9 +64,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restric
       if (threadIdx.x == 0) raise(err, kErrFormat);
       continue;
     }
-    const uint64_t g0 = (k - c.tile_base) << tile_log2;
-    uint64_t g1 = g0 + (uint64_t(1) << tile_log2);
-    if (g1 > c.n) g1 = c.n;
+    const uint64_t t0 = (k - c.tile_base) << tile_log2;
+    uint64_t t1 = t0 + (uint64_t(1) << tile_log2);
+    if (t1 > c.n) t1 = c.n;
+    uint64_t g0, g1;
+    wave_share(t0, t1, tile_log2, g0, g1);
     const bool filter = kFilter && c.sum3 != nullptr;
     const bool store = kStore && c.out != nullptr;
     bool ok;
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restric
       else if (filter) ok = run_tile<uint32_t, false, true>(c, h, g0, g1, stage);
       else ok = true;
     }
-    if (!ok && threadIdx.x == 0) raise(err, kErrFormat);
+    if (!ok && lane_id() == 0) raise(err, kErrFormat);
   }
 }
 

@@ -20,14 +20,16 @@ __device__ void decode_tiles(const uint8_t* __restrict__ blob, const Header& h,
   const uint64_t first = begin >> tile_log2;
   for (uint64_t k = xcd_virtual_block(blockIdx.x, gridDim.x, remap); k < num_tiles;
        k += gridDim.x) {
-    uint64_t g0 = (first + k) << tile_log2;
-    uint64_t g1 = g0 + (uint64_t(1) << tile_log2);
-    if (g0 < begin) g0 = begin;
-    if (g1 > e) g1 = e;
-    if (g0 >= g1) break;
-    if (!decode_tile(blob, h, g0, g1, stage, sink)) {
-      if (threadIdx.x == 0) raise(err, kErrFormat);
-      return;
+    uint64_t t0 = (first + k) << tile_log2;
+    uint64_t t1 = t0 + (uint64_t(1) << tile_log2);
+    if (t0 < begin) t0 = begin;
+    if (t1 > e) t1 = e;
+    if (t0 >= t1) break;
+    uint64_t g0, g1;
+    wave_share(t0, t1, tile_log2, g0, g1);
+    if (g0 < g1 && !decode_tile(blob, h, g0, g1, stage, sink)) {
+      if (lane_id() == 0) raise(err, kErrFormat);
+      return;  // no workgroup barrier follows
     }
   }
 }
@@ -37,8 +39,8 @@ __global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ b
                                                    uint64_t begin, uint64_t end, uint64_t out_cap,
                                                    uint32_t tile_log2, uint64_t num_tiles, int all,
                                                    int remap, int* err) {
-  __shared__ uint4 stage_v[kStageWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v);
+  __shared__ uint4 stage_v[kWavesPerBlock * kWaveStageWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveStageWords;
   Header h;
   if (!load_header(blob, blob_bytes, h)) {
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
@@ -175,26 +177,26 @@ __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict
                                                        uint64_t blob_bytes, uint64_t lo,
                                                        uint64_t hi, uint64_t* out3,
                                                        uint32_t tile_log2, int prune, int* err) {
-  __shared__ uint4 stage_v[kStageWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v);
+  __shared__ uint4 stage_v[kWavesPerBlock * kWaveStageWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveStageWords;
   Header h;
   if (!load_header(blob, blob_bytes, h)) {
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
     return;
   }
   FilterSink sink{lo, hi, 0, 0, 0, prune};
+  bool bad = false;
   // Persistent grid: the tile count comes from the header.
   const uint64_t num_tiles = h.n == 0 ? 0 : ((h.n - 1) >> tile_log2) + 1;
   for (uint64_t k = blockIdx.x; k < num_tiles; k += gridDim.x) {
-    const uint64_t g0 = k << tile_log2;
-    if (g0 >= h.n) break;
-    uint64_t g1 = g0 + (uint64_t(1) << tile_log2);
-    if (g1 > h.n) g1 = h.n;
-    if (!decode_tile(blob, h, g0, g1, stage, sink)) {
-      if (threadIdx.x == 0) raise(err, kErrFormat);
-      return;
-    }
+    const uint64_t t0 = k << tile_log2;
+    uint64_t t1 = t0 + (uint64_t(1) << tile_log2);
+    if (t1 > h.n) t1 = h.n;
+    uint64_t g0, g1;
+    wave_share(t0, t1, tile_log2, g0, g1);
+    if (!bad && g0 < g1 && !decode_tile(blob, h, g0, g1, stage, sink)) bad = true;
   }
+  if (bad && lane_id() == 0) raise(err, kErrFormat);
   block_add_sum(sink.sum_lo, sink.sum_hi, sink.count, out3);
 }
 

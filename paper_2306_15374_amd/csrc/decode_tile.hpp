@@ -1,10 +1,13 @@
-// One tile of the LeCo decoder (section 3.3, range decompression): the
-// values of global positions [g0, g1) of one blob, decoded by one 256-thread
-// workgroup.  The tile is cut at partition boundaries into segments and each
-// segment into chunks whose packed residual words fit the LDS stage; each
-// chunk's words are read from HBM once, with coalesced 16-byte loads, and
-// every thread then decodes values t = c0 + tid, c0 + tid + 256, ... from
-// LDS, so each wave stores a contiguous run of outputs.
+// The LeCo decoder's inner loop (section 3.3, range decompression), built
+// around wavefront tiles: each 64-lane wavefront decodes the values of
+// global positions [g0, g1) (1024 of them by default) on its own, with its
+// own slice of LDS and no workgroup barrier.  The tile is cut at partition
+// boundaries into segments; the residual words of all its segments (which
+// lie back to back in the blob) are copied once into the wavefront's LDS
+// slice with coalesced 16-byte loads, then each lane decodes values
+// t = c0 + lane, c0 + lane + 64, ... so that every store of the wavefront
+// covers 64 consecutive outputs.  Tiles whose words do not fit the slice
+// are decoded segment by segment in chunks.
 #pragma once
 
 #include "leco_dev.hpp"
@@ -12,51 +15,69 @@
 namespace leco {
 
 constexpr int kBlock = 256;
-// 32-bit words of LDS per stage (16 KiB of residual words plus slack for
-// the alignment of the first load and the two words read past a field).
-constexpr uint32_t kStageWords = 4096 + 16;
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = kBlock / kWave;
+// 32-bit words of LDS per wavefront: 1024 words of residuals (1024 values
+// at up to 32 bits) plus slack for the alignment of the first load and the
+// two words read past a field.
+constexpr uint32_t kWaveStageWords = 1024 + 16;
 
-__device__ inline uint32_t chunk_values(uint32_t bits) {
-  return bits == 0 ? 0xffffffffu : ((kStageWords - 12) * 32u) / bits;
+__device__ inline uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+// Wavefront index, read from the first lane so the compiler treats it (and
+// every tile bound, partition index and record derived from it) as uniform:
+// scalar registers and scalar loads instead of per-lane ones.
+__device__ inline uint32_t wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
 }
 
-// Decodes values t in [c0, c1) of partition p from the staged words: stage
-// word 0 is 32-bit word (qoff-independent) of the blob such that residual t
-// starts at bit qoff + b t of the stage.  Thread tid takes t = c0 + tid,
-// c0 + tid + 256, ...
+// Orders this wavefront's LDS writes before its later LDS reads (and the
+// reverse); the lanes of a wavefront need no other synchronisation.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint32_t chunk_values(uint32_t bits) {
+  return bits == 0 ? 0xffffffffu : ((kWaveStageWords - 12) * 32u) / bits;
+}
+
+// Decodes values t in [c0, c1) of partition p from the staged words, in
+// which residual t starts at bit qoff + b t.  Lane l takes t = c0 + l,
+// c0 + l + 64, ...
 template <class Sink>
 __device__ inline void decode_values(const Part& p, uint32_t c0, uint32_t c1, int64_t qoff,
-                                     const uint32_t* __restrict__ stage, Sink& sink) {
+                                     const uint32_t* stage, Sink& sink) {
   const uint32_t b = p.bits;
   const bool small_pred = prediction_fits_i32(p.theta1, p.len);
-  const uint32_t first = c0 + threadIdx.x;
-  const uint32_t cnt = first < c1 ? (c1 - first + kBlock - 1) / kBlock : 0;
+  const uint32_t first = c0 + lane_id();
+  const uint32_t cnt = first < c1 ? (c1 - first + kWave - 1) / kWave : 0;
   const uint32_t mask32 = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
   const uint32_t mask_hi = b >= 64 ? 0xffffffffu : (b > 32 ? ((1u << (b - 32)) - 1u) : 0u);
   const uint32_t q0 = uint32_t(qoff + int64_t(b) * first);
-  const uint32_t dq = b * kBlock;
+  const uint32_t dq = b * kWave;
   const uint64_t g_first = p.start + first;
   if (b <= 32 && small_pred) {
 #pragma unroll 4
     for (uint32_t i = 0; i < cnt; ++i) {
-      const uint32_t t = first + i * kBlock;
+      const uint32_t t = first + i * kWave;
       const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
       const int32_t pr = predict32(p.theta1, t);
-      sink.put(g_first + i * kBlock, p.base + uint64_t(int64_t(pr)) + u);
+      sink.put(g_first + i * kWave, p.base + uint64_t(int64_t(pr)) + u);
     }
   } else if (b <= 32) {
 #pragma unroll 2
     for (uint32_t i = 0; i < cnt; ++i) {
-      const uint32_t t = first + i * kBlock;
+      const uint32_t t = first + i * kWave;
       const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
-      sink.put(g_first + i * kBlock, p.base + uint64_t(predict(p.theta1, t)) + u);
+      sink.put(g_first + i * kWave, p.base + uint64_t(predict(p.theta1, t)) + u);
     }
   } else {
 #pragma unroll 2
     for (uint32_t i = 0; i < cnt; ++i) {
-      const uint32_t t = first + i * kBlock;
+      const uint32_t t = first + i * kWave;
       const uint64_t u = extract64(stage, q0 + i * dq, mask_hi);
-      sink.put(g_first + i * kBlock, p.base + uint64_t(predict(p.theta1, t)) + u);
+      sink.put(g_first + i * kWave, p.base + uint64_t(predict(p.theta1, t)) + u);
     }
   }
 }
@@ -70,29 +91,27 @@ __device__ inline void word_span(const Part& p, uint32_t t0, uint32_t t1, uint64
 }
 
 // Copies 32-bit words [a0, w_end) (a0 a multiple of 4) into the stage with
-// coalesced 16-byte loads.
+// coalesced 16-byte loads by the lanes of one wavefront.
 __device__ inline void stage_words(const uint32_t* __restrict__ words32, uint64_t a0,
-                                   uint64_t w_end, uint32_t* __restrict__ stage) {
+                                   uint64_t w_end, uint32_t* stage) {
   const uint32_t nvec = uint32_t((w_end - a0 + 3) >> 2);
   const uint4* src = reinterpret_cast<const uint4*>(words32 + a0);
   uint4* dst = reinterpret_cast<uint4*>(stage);
-  for (uint32_t i = threadIdx.x; i < nvec; i += kBlock) dst[i] = src[i];
+  for (uint32_t i = lane_id(); i < nvec; i += kWave) dst[i] = src[i];
 }
 
 constexpr uint32_t kMaxTileSegments = 64;
 
-// Sink receives (global position g, decoded value v) for every value.
-// Returns false if the blob failed validation (the caller raises the flag);
-// all control flow depending on it is uniform across the workgroup.
+// Decodes one wavefront tile [g0, g1) of a blob into the sink.  Returns
+// false if the blob failed validation (the caller raises the flag); all
+// control flow is uniform across the wavefront.
 //
-// When the sink visits every segment (Sink::kWholeTile) and the residual
-// words of all segments of the tile fit the stage, they are staged in one
-// round trip (partitions are laid out back to back, so the span is
-// contiguous) and decoded segment by segment from LDS.  Otherwise each
-// segment is staged and decoded in chunks on its own.
+// When the sink visits every segment (Sink::kWholeTile) and the words of
+// all segments fit the slice, they are staged in one round trip; otherwise
+// each segment is staged and decoded in chunks on its own.
 template <class Sink>
 __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, uint64_t g0,
-                            uint64_t g1, uint32_t* __restrict__ stage, Sink& sink) {
+                            uint64_t g1, uint32_t* stage, Sink& sink) {
   const uint64_t j0 = locate(blob, h, g0);
   const uint32_t* words32 = reinterpret_cast<const uint32_t*>(blob + h.words_off);
   if (Sink::kWholeTile) {
@@ -117,9 +136,9 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
       }
     }
     const uint64_t a0 = span_lo & ~uint64_t(3);
-    if (one_round && span_hi - a0 + 8 <= kStageWords) {
+    if (one_round && span_hi - a0 + 8 <= kWaveStageWords) {
       if (span_hi > span_lo) stage_words(words32, a0, span_hi, stage);
-      __syncthreads();
+      wave_sync();
       j = j0;
       g = g0;
       while (g < g1) {
@@ -131,7 +150,7 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
         g = seg_end;
         ++j;
       }
-      __syncthreads();
+      wave_sync();
       return true;
     }
   }
@@ -158,16 +177,29 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
         const uint64_t a0 = ws & ~uint64_t(3);
         stage_words(words32, a0, we, stage);
         qoff = int64_t(64 * p.word_off) - int64_t(32 * a0);
-        __syncthreads();
+        wave_sync();
       }
       decode_values(p, c0, c1, qoff, stage, sink);
-      if (b != 0) __syncthreads();
+      if (b != 0) wave_sync();
       c0 = c1;
     }
     g0 = seg_end;
     ++j;
   }
   return true;
+}
+
+// The wavefront's share [g0, g1) of the workgroup tile [t0, t1): quarter w
+// of it (tile boundaries are multiples of 4 values, so quarters are exact
+// for full tiles; a ragged last tile gives empty quarters at its end).
+__device__ inline void wave_share(uint64_t t0, uint64_t t1, uint32_t tile_log2, uint64_t& g0,
+                                  uint64_t& g1) {
+  const uint64_t q = uint64_t(1) << (tile_log2 - 2);
+  const uint64_t w = wave_id();
+  g0 = t0 + w * q;
+  g1 = g0 + q;
+  if (g0 > t1) g0 = t1;
+  if (g1 > t1) g1 = t1;
 }
 
 // Writes each value to out[g - origin] with the column's width, bypassing
@@ -190,7 +222,6 @@ __device__ inline uint64_t xcd_virtual_block(uint32_t b, uint32_t grid, bool rem
   if (!remap || (grid & 7u)) return b;
   return uint64_t(b & 7u) * (grid >> 3) + (b >> 3);
 }
-
 
 __device__ inline void raise(int* err, int bits) { atomicOr(err, bits); }
 
@@ -228,8 +259,8 @@ struct FilterSink {
   }
 };
 
-
-// Adds a workgroup's (sum_lo, sum_hi, count) into out3 exactly.
+// Adds a workgroup's (sum_lo, sum_hi, count) into out3 exactly.  Called by
+// every thread of the workgroup.
 __device__ inline void block_add_sum(uint64_t sum_lo, uint64_t sum_hi, uint64_t count,
                                      uint64_t* out3) {
   __shared__ uint64_t red[3][kBlock];
@@ -256,6 +287,5 @@ __device__ inline void block_add_sum(uint64_t sum_lo, uint64_t sum_hi, uint64_t 
   }
   __syncthreads();
 }
-
 
 }  // namespace leco
