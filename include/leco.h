@@ -242,6 +242,95 @@ leco_status leco_batch_tune(leco_batch *batch, int op, hipStream_t stream,
 leco_status leco_batch_set_shape(leco_batch *batch, uint32_t tile_log2,
                                  uint32_t blocks_per_cu);
 
+/* ---- Served mode --------------------------------------------------------------
+ * Compressed columns stay resident in device memory while a request loop
+ * answers point lookups and range scans (the decoder of section 3.3 for "one
+ * or a range of positions").  Requests are admitted in arrival order when
+ * output memory and an in-flight slot are free; the admitted requests are
+ * packed into steps, one kernel launch each, and consecutive steps run on
+ * different streams so they overlap.  A request's result stays in a
+ * server-owned device buffer until the caller releases it.  Every result
+ * equals what the same request returns alone. */
+
+typedef struct leco_server leco_server;
+
+typedef struct {
+  const void *blob_dev; /* resident blob, valid until leco_server_stop */
+  uint64_t blob_bytes;
+  uint64_t n;           /* value count of the blob (checked at start) */
+} leco_resident_col;
+
+typedef struct {
+  uint64_t out_budget_bytes;   /* device memory for results                */
+  uint32_t max_inflight;       /* admitted, not yet released requests      */
+  uint32_t num_streams;        /* steps that may run concurrently (>= 1)   */
+  uint32_t max_step_items;     /* workgroups per step launch               */
+  uint32_t max_step_positions; /* random-access positions staged per step  */
+  /* Batching: while a step is running, the next one is launched only once
+   * its admitted requests produce min_step_bytes of results, fill half the
+   * step, or the oldest of them has waited max_wait_us.  An idle GPU always
+   * gets the next step at once.  0 disables either rule. */
+  uint64_t min_step_bytes;
+  uint32_t max_wait_us;
+  uint32_t reserved;           /* must be 0 */
+  /* Pinned host memory holding the positions of queued random-access
+   * requests until their step has run (0 selects 64 MiB).  The step kernel
+   * reads positions from it directly. */
+  uint64_t position_ring_bytes;
+} leco_server_config;
+
+enum { LECO_REQ_RANDOM_ACCESS = 1, LECO_REQ_RANGE = 2 };
+
+typedef struct {
+  uint32_t kind;                 /* LECO_REQ_RANDOM_ACCESS or LECO_REQ_RANGE   */
+  uint32_t col;                  /* resident column index                      */
+  const uint64_t *positions_host;/* random access: k positions, copied at submit */
+  uint64_t k;
+  uint64_t begin, end;           /* range: positions [begin, end)              */
+} leco_request;
+
+typedef struct {
+  uint64_t ticket;
+  int32_t status;          /* LECO_OK, or the error that ended the request     */
+  int32_t dtype;           /* 4 or 8                                           */
+  const void *out_dev;     /* count values, valid until leco_server_release    */
+  uint64_t count;
+  double latency_us;       /* submit to observed completion of its step        */
+} leco_completion;
+
+typedef struct {
+  uint64_t submitted, completed, steps, values_out, positions;
+  uint64_t out_bytes_in_use, out_bytes_peak, queued;
+} leco_server_stats;
+
+/* Starts the request loop (one host thread) over resident columns. [sync] */
+leco_status leco_server_start(leco_ctx *ctx, const leco_resident_col *cols_host,
+                              uint64_t ncols, const leco_server_config *cfg,
+                              leco_server **out);
+/* Queues a request; never blocks on the GPU.  Positions are checked against
+ * n and copied into the position ring here (LECO_ERANGE; LECO_ENOMEM when
+ * the ring is momentarily full: retry once earlier requests complete); a
+ * request larger than the whole budget is refused (LECO_ENOSPC). */
+leco_status leco_server_submit(leco_server *s, const leco_request *req,
+                               uint64_t *ticket);
+/* Returns up to max completions (non-blocking). */
+leco_status leco_server_poll(leco_server *s, leco_completion *out, uint64_t max,
+                             uint64_t *got);
+/* Frees a completed request's result memory. */
+leco_status leco_server_release(leco_server *s, uint64_t ticket);
+leco_status leco_server_stats_get(leco_server *s, leco_server_stats *out);
+/* Waits for every admitted step, stops the loop and frees the server. */
+leco_status leco_server_stop(leco_server *s);
+
+/* Open-loop load generator: submits reqs[i] at arrival_s[i] seconds after
+ * the call (busy-waiting), releases each result as it completes, and waits
+ * for all of them.  latency_us_out (n entries, may be null) receives each
+ * request's latency; *elapsed_s the time from the first arrival to the last
+ * completion. */
+leco_status leco_server_replay(leco_server *s, const leco_request *reqs,
+                               const double *arrival_s, uint64_t n,
+                               double *latency_us_out, double *elapsed_s);
+
 /* ---- Diagnostics ------------------------------------------------------------
  * Evaluates the slope arithmetic of the encoder (section 3.1, least-squares
  * closed form) on the GPU for k given pairs: in_dev holds 4 uint64 per pair,

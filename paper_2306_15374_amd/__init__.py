@@ -29,8 +29,10 @@ EXPORTS = [
     "leco_decode_all", "leco_decode_range", "leco_random_access", "leco_filter_sum",
     "leco_diag_slope", "leco_diag_copy", "leco_encode_batch", "leco_batch_create",
     "leco_batch_destroy", "leco_batch_run", "leco_batch_run_graph", "leco_batch_tune",
-    "leco_batch_set_shape",
+    "leco_batch_set_shape", "leco_server_start", "leco_server_submit", "leco_server_poll",
+    "leco_server_release", "leco_server_stats_get", "leco_server_stop", "leco_server_replay",
 ]
+LECO_REQ_RANDOM_ACCESS, LECO_REQ_RANGE = 1, 2
 LECO_BATCH_DECODE, LECO_BATCH_FILTER = 1, 2
 
 
@@ -51,6 +53,34 @@ class DecodeJob(C.Structure):
     _fields_ = [("blob_dev", C.c_void_p), ("blob_bytes", C.c_uint64), ("n", C.c_uint64),
                 ("out_dev", C.c_void_p), ("lo", C.c_uint64), ("hi", C.c_uint64),
                 ("sum3_dev", C.c_void_p)]
+
+
+class ResidentCol(C.Structure):
+    _fields_ = [("blob_dev", C.c_void_p), ("blob_bytes", C.c_uint64), ("n", C.c_uint64)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("out_budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32),
+                ("num_streams", C.c_uint32), ("max_step_items", C.c_uint32),
+                ("max_step_positions", C.c_uint32), ("min_step_bytes", C.c_uint64),
+                ("max_wait_us", C.c_uint32), ("reserved", C.c_uint32),
+                ("position_ring_bytes", C.c_uint64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("col", C.c_uint32), ("positions_host", C.c_void_p),
+                ("k", C.c_uint64), ("begin", C.c_uint64), ("end", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("dtype", C.c_int32),
+                ("out_dev", C.c_void_p), ("count", C.c_uint64), ("latency_us", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(name, C.c_uint64) for name in
+                ("submitted", "completed", "steps", "values_out", "positions",
+                 "out_bytes_in_use", "out_bytes_peak", "queued")]
 
 
 class Partitioning(C.Structure):
@@ -99,6 +129,13 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_batch_run_graph": ([vp, i32, vp], i32),
         "leco_batch_tune": ([vp, i32, vp, P(C.c_uint32), P(C.c_uint32)], i32),
         "leco_batch_set_shape": ([vp, C.c_uint32, C.c_uint32], i32),
+        "leco_server_start": ([vp, vp, u64, P(ServerConfig), P(vp)], i32),
+        "leco_server_submit": ([vp, P(Request), P(u64)], i32),
+        "leco_server_poll": ([vp, vp, u64, P(u64)], i32),
+        "leco_server_release": ([vp, u64], i32),
+        "leco_server_stats_get": ([vp, P(ServerStats)], i32),
+        "leco_server_stop": ([vp], i32),
+        "leco_server_replay": ([vp, vp, vp, u64, vp, P(C.c_double)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -115,7 +152,10 @@ def _stream(stream) -> int:
 
 
 def _ptr(t) -> int | None:
-    return None if t is None else t.data_ptr()
+    """Device or host address of a tensor, or an address given as an int."""
+    if t is None or isinstance(t, int):
+        return t
+    return t.data_ptr()
 
 
 def _dtype_code(t) -> int:
@@ -255,6 +295,56 @@ def leco_batch_tune(batch: int, op: int, stream=None) -> tuple[int, int, int]:
 
 def leco_batch_set_shape(batch: int, tile_log2: int, blocks_per_cu: int) -> int:
     return lib().leco_batch_set_shape(batch, tile_log2, blocks_per_cu)
+
+
+def leco_server_start(ctx: int, cols, cfg: ServerConfig) -> int:
+    arr = (ResidentCol * len(cols))(*cols)
+    h = C.c_void_p()
+    st = lib().leco_server_start(ctx, arr, len(cols), C.byref(cfg), C.byref(h))
+    if st != LECO_OK:
+        raise LecoError("leco_server_start", st, leco_last_error(ctx))
+    return h.value
+
+
+def leco_server_submit(server: int, req: Request) -> tuple[int, int]:
+    t = C.c_uint64()
+    st = lib().leco_server_submit(server, C.byref(req), C.byref(t))
+    return st, t.value
+
+
+def leco_server_poll(server: int, max_n: int = 256) -> list:
+    arr = (Completion * max_n)()
+    got = C.c_uint64()
+    st = lib().leco_server_poll(server, arr, max_n, C.byref(got))
+    if st != LECO_OK:
+        raise LecoError("leco_server_poll", st)
+    return [arr[i] for i in range(got.value)]
+
+
+def leco_server_release(server: int, ticket: int) -> int:
+    return lib().leco_server_release(server, ticket)
+
+
+def leco_server_stats_get(server: int) -> dict:
+    s = ServerStats()
+    st = lib().leco_server_stats_get(server, C.byref(s))
+    if st != LECO_OK:
+        raise LecoError("leco_server_stats_get", st)
+    return {name: getattr(s, name) for name, _ in ServerStats._fields_}
+
+
+def leco_server_stop(server: int) -> int:
+    return lib().leco_server_stop(server)
+
+
+def leco_server_replay(server: int, reqs, arrival_s, latencies_out=None) -> tuple[int, float]:
+    """reqs: a ctypes Request array; arrival_s and latencies_out: float64
+    numpy arrays of the same length."""
+    el = C.c_double()
+    st = lib().leco_server_replay(server, reqs, arrival_s.ctypes.data, len(arrival_s),
+                                  None if latencies_out is None else latencies_out.ctypes.data,
+                                  C.byref(el))
+    return st, el.value
 
 
 # ---- convenience wrapper --------------------------------------------------------------

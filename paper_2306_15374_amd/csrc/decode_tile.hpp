@@ -225,6 +225,29 @@ __device__ inline uint64_t xcd_virtual_block(uint32_t b, uint32_t grid, bool rem
 
 __device__ inline void raise(int* err, int bits) { atomicOr(err, bits); }
 
+// Random access (section 3.3): the value at position g < h.n, from the
+// partition's record and the one or two words holding the residual.  False
+// if the records around g are malformed.
+__device__ inline bool lookup_value(const uint8_t* __restrict__ blob, const Header& h,
+                                    uint64_t g, uint64_t& v) {
+  const uint64_t j = locate(blob, h, g);
+  Part p;
+  if (!load_part(blob, h, j, p) || g < p.start || g - p.start >= p.len) return false;
+  const uint32_t t = uint32_t(g - p.start);
+  uint64_t u = 0;
+  if (p.bits) {
+    const uint64_t* words = reinterpret_cast<const uint64_t*>(blob + h.words_off);
+    const uint64_t q = 64 * p.word_off + uint64_t(p.bits) * t;
+    const uint32_t s = uint32_t(q & 63);
+    const uint64_t lo = words[q >> 6];
+    const uint64_t hi = (s + p.bits > 64) ? words[(q >> 6) + 1] : 0;
+    u = (lo >> s) | ((hi << 1) << (63 - s));
+    if (p.bits < 64) u &= (uint64_t(1) << p.bits) - 1;
+  }
+  v = p.base + uint64_t(predict(p.theta1, t)) + u;
+  return true;
+}
+
 // Accumulates sum and count of values in [lo, hi).  A segment is skipped
 // without reading its residuals when the model bounds its values outside
 // [lo, hi): values of a partition lie in

@@ -1,0 +1,564 @@
+// Served mode: compressed columns resident in HBM, a host request loop with
+// admission by output memory, and steps of mixed random-access and range
+// work executed by one kernel launch each on rotating streams.
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "decode_tile.hpp"
+#include "internal.hpp"
+
+namespace leco {
+
+struct ServeCol {
+  const uint8_t* blob;
+  uint64_t blob_bytes;
+  uint64_t n;
+  uint32_t dtype;
+  uint32_t pad;
+};
+
+// One workgroup of a step.  Random access: positions[a, a + b) of the
+// position ring, results to out_off.  Range: values [a, b) of the column (at
+// most one workgroup tile), results to out_off.
+struct WorkItem {
+  uint32_t kind;
+  uint32_t col;
+  uint64_t a, b;
+  uint64_t out_off;  // bytes into the result arena
+};
+
+constexpr uint32_t kServeTileLog2 = 12;
+constexpr uint64_t kServeTile = uint64_t(1) << kServeTileLog2;
+
+// positions lives in pinned host memory; the lanes of a workgroup read 256
+// consecutive positions, so each wave reads 512 contiguous bytes.
+__global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restrict__ cols,
+                                                       const WorkItem* __restrict__ items,
+                                                       const uint64_t* __restrict__ positions,
+                                                       uint8_t* __restrict__ arena, int* err) {
+  __shared__ uint4 stage_v[kWavesPerBlock * kWaveStageWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveStageWords;
+  const WorkItem it = items[blockIdx.x];
+  const ServeCol c = cols[it.col];
+  Header h;
+  if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n) {
+    if (threadIdx.x == 0) raise(err, kErrFormat);
+    return;
+  }
+  uint8_t* out = arena + it.out_off;
+  if (it.kind == LECO_REQ_RANDOM_ACCESS) {
+    const uint64_t i = threadIdx.x;
+    if (i >= it.b) return;
+    const uint64_t g = positions[it.a + i];
+    uint64_t v = 0;
+    if (g >= h.n || !lookup_value(c.blob, h, g, v)) raise(err, g >= h.n ? kErrRange : kErrFormat);
+    if (h.dtype == 8)
+      reinterpret_cast<uint64_t*>(out)[i] = v;
+    else
+      reinterpret_cast<uint32_t*>(out)[i] = uint32_t(v);
+    return;
+  }
+  uint64_t g0, g1;
+  wave_share(it.a, it.b, kServeTileLog2, g0, g1);
+  if (g0 >= g1) return;
+  bool ok;
+  if (h.dtype == 8) {
+    StoreSink<uint64_t> sink{reinterpret_cast<uint64_t*>(out), it.a};
+    ok = decode_tile(c.blob, h, g0, g1, stage, sink);
+  } else {
+    StoreSink<uint32_t> sink{reinterpret_cast<uint32_t*>(out), it.a};
+    ok = decode_tile(c.blob, h, g0, g1, stage, sink);
+  }
+  if (!ok && lane_id() == 0) raise(err, kErrFormat);
+}
+
+}  // namespace leco
+
+// ---- host side ------------------------------------------------------------------
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) bytes, 256-byte granules: the result
+// arena in device memory and the position ring in pinned host memory.
+class Arena {
+ public:
+  explicit Arena(uint64_t size) { free_[0] = size; }
+  bool alloc(uint64_t bytes, uint64_t* off) {
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const uint64_t rest = it->second - bytes;
+        const uint64_t at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        peak_ = used_ > peak_ ? used_ : peak_;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    bytes = round(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t used() const { return used_; }
+  uint64_t peak() const { return peak_; }
+  static uint64_t round(uint64_t b) { return (b + 255) & ~uint64_t(255); }
+
+ private:
+  uint64_t used_ = 0, peak_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+};
+
+struct Pending {
+  uint64_t ticket;
+  leco_request req;
+  uint64_t pos_off;  // byte offset of the positions in the ring
+  uint64_t count, out_bytes;
+  Clock::time_point t_submit;
+};
+
+struct Result {
+  uint64_t off, bytes;
+  bool done;
+};
+
+// A step slot: its stream, completion event and work-item staging.
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  leco::WorkItem* items_host = nullptr;  // pinned
+  leco::WorkItem* items_dev = nullptr;
+  bool busy = false;
+  std::vector<Pending> reqs;  // requests the running step completes
+  std::vector<uint64_t> offs;
+};
+
+}  // namespace
+
+struct leco_server {
+  leco_ctx* ctx = nullptr;
+  leco_server_config cfg{};
+  std::vector<leco::ServeCol> cols;
+  leco::ServeCol* cols_dev = nullptr;
+  uint8_t* arena_dev = nullptr;
+  Arena* arena = nullptr;
+  uint64_t* ring_host = nullptr;  // pinned, device-accessible
+  uint64_t* ring_dev = nullptr;
+  Arena* ring = nullptr;
+  std::vector<Slot> slots;
+  size_t next_slot = 0;
+
+  std::mutex mu;  // guards everything below and the two allocators
+  std::condition_variable cv;
+  std::deque<Pending> queue;
+  std::unordered_map<uint64_t, Result> results;
+  std::deque<leco_completion> completions;
+  uint64_t next_ticket = 1;
+  uint64_t inflight = 0;  // admitted and not yet released
+  leco_server_stats stats{};
+  std::atomic<bool> stop{false};
+  std::thread worker;
+};
+
+namespace {
+
+leco_status sfail(leco_server* s, leco_status st, const char* msg) {
+  if (s && s->ctx) s->ctx->last_error = msg;
+  return st;
+}
+
+uint64_t step_items(const Pending& p) {
+  return p.req.kind == LECO_REQ_RANDOM_ACCESS ? (p.count + leco::kBlock - 1) / leco::kBlock
+                                              : (p.count + leco::kServeTile - 1) / leco::kServeTile;
+}
+
+// While a step is running, the next one waits until the queued work that
+// fits it is worth a launch: enough result bytes, half the step's items,
+// the step's position capacity, or an old enough request.  Work that does
+// not fit the free memory or slots cannot grow by waiting, so it goes.
+bool batch_ready(const leco_server* s) {
+  const leco_server_config& cfg = s->cfg;
+  if (cfg.max_wait_us &&
+      Clock::now() - s->queue.front().t_submit >= std::chrono::microseconds(cfg.max_wait_us))
+    return true;
+  uint64_t bytes = 0, items = 0, pos = 0, admitted = 0;
+  for (const Pending& p : s->queue) {
+    const uint64_t it = step_items(p);
+    const bool ra = p.req.kind == LECO_REQ_RANDOM_ACCESS;
+    if (items + it > cfg.max_step_items || (ra && pos + p.count > cfg.max_step_positions) ||
+        s->inflight + admitted >= cfg.max_inflight)
+      return true;  // the step is full
+    bytes += p.out_bytes;
+    items += it;
+    pos += ra ? p.count : 0;
+    ++admitted;
+    if (cfg.min_step_bytes && bytes >= cfg.min_step_bytes) return true;
+    if (2 * items >= cfg.max_step_items) return true;
+  }
+  return false;  // the whole queue is a small step: wait for more
+}
+
+// Admits queued requests into a free slot and launches the step.  Called
+// by the worker with s->mu held; returns true if a step was launched.
+bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
+  Slot* slot = nullptr;
+  for (size_t i = 0; i < s->slots.size(); ++i) {
+    Slot& c = s->slots[(s->next_slot + i) % s->slots.size()];
+    if (!c.busy) {
+      slot = &c;
+      s->next_slot = (s->next_slot + i + 1) % s->slots.size();
+      break;
+    }
+  }
+  if (!slot || s->queue.empty()) return false;
+  bool any_busy = false;
+  for (const Slot& c : s->slots) any_busy = any_busy || c.busy;
+  if (any_busy && !batch_ready(s)) return false;
+  uint32_t nitems = 0;
+  uint64_t npos = 0;
+  slot->reqs.clear();
+  slot->offs.clear();
+  while (!s->queue.empty()) {
+    Pending& p = s->queue.front();
+    const bool ra = p.req.kind == LECO_REQ_RANDOM_ACCESS;
+    const uint64_t items = step_items(p);
+    if (nitems + items > s->cfg.max_step_items) break;
+    if (ra && npos + p.count > s->cfg.max_step_positions) break;
+    if (s->inflight >= s->cfg.max_inflight) break;
+    uint64_t off = 0;
+    if (!s->arena->alloc(p.out_bytes ? p.out_bytes : 1, &off)) break;  // wait for memory
+    const leco::ServeCol& col = s->cols[p.req.col];
+    if (ra) {
+      const uint64_t base = p.pos_off / 8;
+      for (uint64_t i = 0; i < items; ++i) {
+        const uint64_t first = i * leco::kBlock;
+        const uint64_t cnt = p.count - first < uint64_t(leco::kBlock) ? p.count - first : leco::kBlock;
+        slot->items_host[nitems++] = leco::WorkItem{LECO_REQ_RANDOM_ACCESS, p.req.col, base + first,
+                                                    cnt, off + first * col.dtype};
+      }
+      npos += p.count;
+    } else {
+      for (uint64_t g = p.req.begin; g < p.req.end; g += leco::kServeTile) {
+        const uint64_t e = g + leco::kServeTile < p.req.end ? g + leco::kServeTile : p.req.end;
+        slot->items_host[nitems++] = leco::WorkItem{LECO_REQ_RANGE, p.req.col, g, e,
+                                                    off + (g - p.req.begin) * col.dtype};
+      }
+    }
+    s->results[p.ticket] = Result{off, p.out_bytes ? p.out_bytes : 1, false};
+    ++s->inflight;
+    slot->offs.push_back(off);
+    slot->reqs.push_back(p);
+    s->queue.pop_front();
+  }
+  if (slot->reqs.empty()) return false;
+  s->stats.steps += 1;
+  lk.unlock();
+  if (nitems) {
+    hipMemcpyAsync(slot->items_dev, slot->items_host, sizeof(leco::WorkItem) * nitems,
+                   hipMemcpyHostToDevice, slot->stream);
+    hipLaunchKernelGGL(leco::k_serve_step, dim3(nitems), dim3(leco::kBlock), 0, slot->stream,
+                       s->cols_dev, slot->items_dev, s->ring_dev, s->arena_dev, s->ctx->err_dev);
+  }
+  hipEventRecord(slot->done, slot->stream);
+  lk.lock();
+  slot->busy = true;
+  return true;
+}
+
+// Retires finished steps: completions, and the ring space of their
+// positions.  Called with s->mu held.
+bool retire_steps(leco_server* s) {
+  bool any = false;
+  for (Slot& slot : s->slots) {
+    if (!slot.busy || hipEventQuery(slot.done) != hipSuccess) continue;
+    const Clock::time_point now = Clock::now();
+    for (size_t i = 0; i < slot.reqs.size(); ++i) {
+      const Pending& p = slot.reqs[i];
+      if (p.req.kind == LECO_REQ_RANDOM_ACCESS && p.count) s->ring->release(p.pos_off, 8 * p.count);
+      auto it = s->results.find(p.ticket);
+      if (it != s->results.end()) it->second.done = true;
+      leco_completion c{};
+      c.ticket = p.ticket;
+      c.status = LECO_OK;
+      c.dtype = int32_t(s->cols[p.req.col].dtype);
+      c.out_dev = s->arena_dev + slot.offs[i];
+      c.count = p.count;
+      c.latency_us = std::chrono::duration<double, std::micro>(now - p.t_submit).count();
+      s->completions.push_back(c);
+      s->stats.completed += 1;
+      s->stats.values_out += p.count;
+    }
+    slot.reqs.clear();
+    slot.busy = false;
+    any = true;
+  }
+  if (any) s->cv.notify_all();
+  return any;
+}
+
+void worker_main(leco_server* s) {
+  hipSetDevice(s->ctx->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    retire_steps(s);
+    const bool launched = launch_step(s, lk);
+    bool busy = false;
+    for (const Slot& slot : s->slots) busy = busy || slot.busy;
+    if (s->stop && s->queue.empty() && !busy) break;
+    if (!launched) {
+      if (busy) {
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
+      } else {
+        s->cv.wait_for(lk, std::chrono::microseconds(200));
+      }
+    }
+  }
+}
+
+void free_server(leco_server* s) {
+  for (Slot& slot : s->slots) {
+    if (slot.stream) hipStreamSynchronize(slot.stream);
+    if (slot.done) hipEventDestroy(slot.done);
+    if (slot.stream) hipStreamDestroy(slot.stream);
+    if (slot.items_host) hipHostFree(slot.items_host);
+    if (slot.items_dev) hipFree(slot.items_dev);
+  }
+  if (s->cols_dev) hipFree(s->cols_dev);
+  if (s->arena_dev) hipFree(s->arena_dev);
+  if (s->ring_host) hipHostFree(s->ring_host);
+  delete s->arena;
+  delete s->ring;
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+leco_status leco_server_start(leco_ctx* ctx, const leco_resident_col* cols, uint64_t ncols,
+                              const leco_server_config* cfg, leco_server** out) {
+  if (!ctx || !out || !cfg || (ncols && !cols)) return LECO_EINVAL;
+  *out = nullptr;
+  if (ncols == 0 || ncols > 0xffffffffull || cfg->out_budget_bytes == 0 || cfg->num_streams == 0 ||
+      cfg->reserved != 0 || cfg->max_step_items == 0 || cfg->max_inflight == 0) {
+    ctx->last_error = "server needs columns, a budget, a stream, step items and in-flight slots";
+    return LECO_EINVAL;
+  }
+  leco_server* s = new leco_server();
+  s->ctx = ctx;
+  s->cfg = *cfg;
+  if (s->cfg.max_step_positions == 0) s->cfg.max_step_positions = 1u << 20;
+  if (s->cfg.position_ring_bytes == 0) s->cfg.position_ring_bytes = uint64_t(64) << 20;
+  hipSetDevice(ctx->device);
+  for (uint64_t i = 0; i < ncols; ++i) {
+    uint8_t hdr[64];
+    if (!cols[i].blob_dev || (reinterpret_cast<uintptr_t>(cols[i].blob_dev) & 15) ||
+        cols[i].blob_bytes < 64 ||
+        hipMemcpy(hdr, cols[i].blob_dev, 64, hipMemcpyDeviceToHost) != hipSuccess) {
+      free_server(s);
+      ctx->last_error = "resident column with a bad blob";
+      return LECO_EINVAL;
+    }
+    uint64_t n = 0;
+    leco_dtype dt;
+    if (leco_blob_info(hdr, &n, &dt, nullptr) != LECO_OK || n != cols[i].n) {
+      free_server(s);
+      ctx->last_error = "resident blob header does not match its column";
+      return LECO_EFORMAT;
+    }
+    s->cols.push_back(leco::ServeCol{static_cast<const uint8_t*>(cols[i].blob_dev),
+                                     cols[i].blob_bytes, n, uint32_t(dt), 0});
+  }
+  bool ok = hipMalloc(&s->cols_dev, sizeof(leco::ServeCol) * ncols) == hipSuccess &&
+            hipMemcpy(s->cols_dev, s->cols.data(), sizeof(leco::ServeCol) * ncols,
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMalloc(&s->arena_dev, cfg->out_budget_bytes) == hipSuccess &&
+            hipHostMalloc(&s->ring_host, s->cfg.position_ring_bytes, hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&s->ring_dev), s->ring_host, 0) ==
+                hipSuccess;
+  s->slots.resize(cfg->num_streams);
+  for (Slot& slot : s->slots) {
+    ok = ok && hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) == hipSuccess &&
+         hipHostMalloc(&slot.items_host, sizeof(leco::WorkItem) * s->cfg.max_step_items,
+                       hipHostMallocDefault) == hipSuccess &&
+         hipMalloc(&slot.items_dev, sizeof(leco::WorkItem) * s->cfg.max_step_items) == hipSuccess;
+  }
+  if (!ok) {
+    free_server(s);
+    ctx->last_error = "server allocation failed";
+    return LECO_ENOMEM;
+  }
+  s->arena = new Arena(cfg->out_budget_bytes);
+  s->ring = new Arena(s->cfg.position_ring_bytes);
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return LECO_OK;
+}
+
+leco_status leco_server_submit(leco_server* s, const leco_request* r, uint64_t* ticket) {
+  if (!s || !r) return LECO_EINVAL;
+  if (r->col >= s->cols.size()) return sfail(s, LECO_EINVAL, "no such resident column");
+  const leco::ServeCol& col = s->cols[r->col];
+  Pending p;
+  p.req = *r;
+  p.pos_off = 0;
+  const bool ra = r->kind == LECO_REQ_RANDOM_ACCESS;
+  if (ra) {
+    if (r->k && !r->positions_host) return sfail(s, LECO_EINVAL, "positions are null");
+    if (r->k > s->cfg.max_step_positions || Arena::round(8 * r->k) > s->cfg.position_ring_bytes)
+      return sfail(s, LECO_EINVAL, "more positions than a step or the position ring holds");
+    for (uint64_t i = 0; i < r->k; ++i)
+      if (r->positions_host[i] >= col.n) return sfail(s, LECO_ERANGE, "position >= n");
+    p.count = r->k;
+  } else if (r->kind == LECO_REQ_RANGE) {
+    if (r->begin > r->end || r->end > col.n) return sfail(s, LECO_ERANGE, "range outside [0, n)");
+    p.count = r->end - r->begin;
+    if ((p.count + leco::kServeTile - 1) / leco::kServeTile > s->cfg.max_step_items)
+      return sfail(s, LECO_EINVAL, "range larger than a step");
+  } else {
+    return sfail(s, LECO_EINVAL, "unknown request kind");
+  }
+  p.out_bytes = p.count * col.dtype;
+  if (Arena::round(p.out_bytes) > s->cfg.out_budget_bytes)
+    return sfail(s, LECO_ENOSPC, "request larger than the output budget");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (ra && p.count) {
+    if (!s->ring->alloc(8 * p.count, &p.pos_off))
+      return sfail(s, LECO_ENOMEM, "position ring full: retry after earlier requests complete");
+    memcpy(reinterpret_cast<uint8_t*>(s->ring_host) + p.pos_off, r->positions_host, 8 * p.count);
+  }
+  p.t_submit = Clock::now();
+  p.ticket = s->next_ticket++;
+  if (ticket) *ticket = p.ticket;
+  s->stats.submitted += 1;
+  if (ra) s->stats.positions += r->k;
+  s->queue.push_back(p);
+  s->cv.notify_all();
+  return LECO_OK;
+}
+
+leco_status leco_server_poll(leco_server* s, leco_completion* out, uint64_t max, uint64_t* got) {
+  if (!s || (max && !out) || !got) return LECO_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  uint64_t k = 0;
+  while (k < max && !s->completions.empty()) {
+    out[k++] = s->completions.front();
+    s->completions.pop_front();
+  }
+  *got = k;
+  return LECO_OK;
+}
+
+leco_status leco_server_release(leco_server* s, uint64_t ticket) {
+  if (!s) return LECO_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->results.find(ticket);
+  if (it == s->results.end() || !it->second.done)
+    return sfail(s, LECO_EINVAL, "ticket is not a completed, unreleased request");
+  s->arena->release(it->second.off, it->second.bytes);
+  s->results.erase(it);
+  --s->inflight;
+  s->cv.notify_all();
+  return LECO_OK;
+}
+
+leco_status leco_server_stats_get(leco_server* s, leco_server_stats* out) {
+  if (!s || !out) return LECO_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->out_bytes_in_use = s->arena->used();
+  out->out_bytes_peak = s->arena->peak();
+  out->queued = s->queue.size();
+  return LECO_OK;
+}
+
+leco_status leco_server_stop(leco_server* s) {
+  if (!s) return LECO_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  hipSetDevice(s->ctx->device);
+  free_server(s);
+  return LECO_OK;
+}
+
+leco_status leco_server_replay(leco_server* s, const leco_request* reqs, const double* arrival_s,
+                               uint64_t n, double* latency_us_out, double* elapsed_s) {
+  if (!s || (n && (!reqs || !arrival_s))) return LECO_EINVAL;
+  std::unordered_map<uint64_t, uint64_t> index;  // ticket -> request number
+  std::vector<leco_completion> buf(256);
+  uint64_t done = 0;
+  const Clock::time_point t0 = Clock::now();
+  Clock::time_point last = t0;
+  auto drain = [&]() {
+    uint64_t got = 0;
+    leco_server_poll(s, buf.data(), buf.size(), &got);
+    for (uint64_t i = 0; i < got; ++i) {
+      auto it = index.find(buf[i].ticket);
+      if (it != index.end() && latency_us_out) latency_us_out[it->second] = buf[i].latency_us;
+      leco_server_release(s, buf[i].ticket);
+      ++done;
+      last = Clock::now();
+    }
+  };
+  for (uint64_t i = 0; i < n; ++i) {
+    const Clock::time_point due =
+        t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+    while (Clock::now() < due) drain();
+    uint64_t ticket = 0;
+    leco_status st;
+    while ((st = leco_server_submit(s, &reqs[i], &ticket)) == LECO_ENOMEM) {
+      drain();  // the position ring frees as earlier steps finish
+      std::this_thread::yield();
+    }
+    if (st != LECO_OK) return st;
+    index[ticket] = i;
+    drain();  // keep releasing results while submitting
+  }
+  while (done < n) {
+    drain();
+    std::this_thread::yield();
+  }
+  if (elapsed_s) {
+    const double first = n ? arrival_s[0] : 0.0;
+    *elapsed_s = std::chrono::duration<double>(last - t0).count() - first;
+  }
+  return LECO_OK;
+}
+
+}  // extern "C"

@@ -201,3 +201,25 @@ def make_column_device(spec: dict, device="cuda"):
     if spec["kind"] == "linear_noise":
         return linear_noise_device(spec["n"], spec["seed"], spec["dtype"], device)
     return lognormal_keys_device(spec["n"], spec["seed"], spec["dtype"], device)
+
+
+def request_mix(num: int, col_lens, seed: int, max_log2_k: float = 16.0,
+                range_exp=(3.0, 7.0), rate: float = 1.0):
+    """Same shape as ``request_stream`` with adjustable size limits:
+    random-access batches of floor(2^U[0, max_log2_k]) positions and range
+    scans of floor(10^U[range_exp]) values."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=num))
+    reqs = []
+    for q in range(num):
+        c = int(rng.integers(0, len(col_lens)))
+        n = int(col_lens[c])
+        if rng.integers(0, 2) == 0:
+            k = int(np.floor(2.0 ** rng.uniform(0, max_log2_k)))
+            reqs.append(dict(t=float(t[q]), kind="ra", col=c,
+                             positions=rng.integers(0, n, size=k, dtype=np.uint64)))
+        else:
+            ln = min(int(np.floor(10.0 ** rng.uniform(*range_exp))), n)
+            b = int(rng.integers(0, n - ln + 1))
+            reqs.append(dict(t=float(t[q]), kind="range", col=c, begin=b, end=b + ln))
+    return reqs

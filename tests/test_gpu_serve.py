@@ -1,0 +1,203 @@
+"""Served mode on the GPU: resident compressed columns, a request loop with
+admission by output memory, steps overlapped on several streams.  Every
+result must equal the column's values, and be the same alone and in the
+mix (tolerance 0: integers)."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+import paper_2306_15374_amd as P
+from paper_2306_15374_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def codec(torch):
+    c = P.Codec(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def columns(torch, codec):
+    specs = [dict(kind="linear_noise", n=1_000_000, dtype=np.uint64, seed=3, fixed_len=1024),
+             dict(kind="lognormal_keys", n=1_500_007, dtype=np.uint64, seed=4, fixed_len=4096),
+             dict(kind="lognormal_keys", n=700_001, dtype=np.uint32, seed=5, fixed_len=4096),
+             dict(kind="linear_noise", n=333_333, dtype=np.uint32, seed=6, fixed_len=1000)]
+    cols, blobs, hosts = [], [], []
+    for s in specs:
+        c = W.make_column_device(s)
+        cols.append(c)
+        blobs.append(codec.encode(c, fixed_len=s["fixed_len"]))
+        hosts.append(c.cpu().numpy().view(np.uint32 if s["dtype"] == np.uint32 else np.uint64))
+    return specs, cols, blobs, hosts
+
+
+def start(codec, columns, budget=256 << 20, streams=2, inflight=1024):
+    specs, cols, blobs, hosts = columns
+    res = [P.ResidentCol(b.data_ptr(), b.numel(), s["n"]) for s, b in zip(specs, blobs)]
+    cfg = P.ServerConfig(budget, inflight, streams, 1 << 16, 1 << 20, 32 << 20, 100, 0, 16 << 20)
+    return P.leco_server_start(codec.ctx, res, cfg)
+
+
+def to_request(r):
+    if r["kind"] == "ra":
+        pos = np.ascontiguousarray(r["positions"], dtype=np.uint64)
+        return P.Request(P.LECO_REQ_RANDOM_ACCESS, r["col"], pos.ctypes.data, len(pos), 0, 0), pos
+    return P.Request(P.LECO_REQ_RANGE, r["col"], None, 0, r["begin"], r["end"]), None
+
+
+def fetch(torch, codec, comp):
+    """Copies a completion's result (device memory owned by the server) to
+    the host through the library's plain copy kernel."""
+    nbytes = comp.count * comp.dtype
+    padded = (nbytes + 15) // 16 * 16
+    buf = torch.empty(max(padded, 16), dtype=torch.uint8, device="cuda")
+    if padded:
+        lib = P.lib()
+        assert lib.leco_diag_copy(codec.ctx, comp.out_dev, buf.data_ptr(), padded,
+                                  torch.cuda.current_stream().cuda_stream) == P.LECO_OK
+    torch.cuda.synchronize()
+    return buf[:nbytes].cpu().numpy().view(np.uint32 if comp.dtype == 4 else np.uint64).copy()
+
+
+def expected(r, hosts):
+    h = hosts[r["col"]]
+    if r["kind"] == "ra":
+        return h[r["positions"].astype(np.int64)]
+    return h[r["begin"]: r["end"]]
+
+
+def run_all(torch, codec, server, reqs, release=True):
+    """Submits every request at once and collects results by ticket."""
+    keep, tickets = [], {}
+    for i, r in enumerate(reqs):
+        req, pos = to_request(r)
+        keep.append(pos)
+        st, t = P.leco_server_submit(server, req)
+        assert st == P.LECO_OK, P.leco_last_error(codec.ctx)
+        tickets[t] = i
+    out = {}
+    deadline = time.time() + 60
+    while len(out) < len(reqs):
+        assert time.time() < deadline, "server did not complete the requests"
+        for c in P.leco_server_poll(server):
+            assert c.status == P.LECO_OK
+            out[tickets[c.ticket]] = fetch(torch, codec, c)
+            if release:
+                assert P.leco_server_release(server, c.ticket) == P.LECO_OK
+    return out
+
+
+def test_mixed_requests_equal_the_column(torch, codec, columns):
+    specs, cols, blobs, hosts = columns
+    reqs = W.request_mix(300, [s["n"] for s in specs], seed=61, max_log2_k=13, range_exp=(1, 5.5))
+    server = start(codec, columns)
+    try:
+        got = run_all(torch, codec, server, reqs)
+        for i, r in enumerate(reqs):
+            assert np.array_equal(got[i], expected(r, hosts)), f"request {i} {r['kind']}"
+        st = P.leco_server_stats_get(server)
+        assert st["completed"] == len(reqs) and st["out_bytes_in_use"] == 0
+    finally:
+        P.leco_server_stop(server)
+    assert codec.sync() is None
+
+
+def test_alone_equals_in_the_mix(torch, codec, columns):
+    specs, cols, blobs, hosts = columns
+    reqs = W.request_mix(120, [s["n"] for s in specs], seed=62, max_log2_k=12, range_exp=(1, 5))
+    server = start(codec, columns, streams=3)
+    try:
+        mixed = run_all(torch, codec, server, reqs)
+        for i in range(0, len(reqs), 3):
+            alone = run_all(torch, codec, server, [reqs[i]])[0]
+            assert np.array_equal(alone, mixed[i]), f"request {i} differs alone"
+    finally:
+        P.leco_server_stop(server)
+
+
+def test_admission_respects_output_budget(torch, codec, columns):
+    specs, cols, blobs, hosts = columns
+    reqs = [dict(kind="range", col=1, begin=b, end=b + 60_000) for b in range(0, 1_200_000, 60_000)]
+    budget = 1 << 20  # two 480 KB results fit at a time
+    server = start(codec, columns, budget=budget, streams=2)
+    try:
+        got = run_all(torch, codec, server, reqs)
+        for i, r in enumerate(reqs):
+            assert np.array_equal(got[i], expected(r, hosts))
+        st = P.leco_server_stats_get(server)
+        assert 0 < st["out_bytes_peak"] <= budget
+        assert st["steps"] >= len(reqs) // 2
+    finally:
+        P.leco_server_stop(server)
+
+
+def test_held_results_block_admission_until_released(torch, codec, columns):
+    specs, cols, blobs, hosts = columns
+    server = start(codec, columns, budget=1 << 20, inflight=2)
+    try:
+        req = P.Request(P.LECO_REQ_RANGE, 0, None, 0, 0, 1000)
+        tickets = [P.leco_server_submit(server, req)[1] for _ in range(3)]
+        comps = []
+        deadline = time.time() + 10
+        while len(comps) < 2 and time.time() < deadline:
+            comps += P.leco_server_poll(server)
+        time.sleep(0.05)
+        comps += P.leco_server_poll(server)
+        assert len(comps) == 2, "the third request must wait for a free in-flight slot"
+        assert P.leco_server_release(server, comps[0].ticket) == P.LECO_OK
+        deadline = time.time() + 10
+        while len(comps) < 3 and time.time() < deadline:
+            comps += P.leco_server_poll(server)
+        assert sorted(c.ticket for c in comps) == sorted(tickets)
+    finally:
+        P.leco_server_stop(server)
+
+
+def test_submit_errors(torch, codec, columns):
+    specs, cols, blobs, hosts = columns
+    server = start(codec, columns, budget=1 << 16)
+    try:
+        bad = np.array([0, specs[0]["n"]], dtype=np.uint64)
+        st, _ = P.leco_server_submit(server, P.Request(P.LECO_REQ_RANDOM_ACCESS, 0, bad.ctypes.data, 2, 0, 0))
+        assert st == P.LECO_ERANGE
+        st, _ = P.leco_server_submit(server, P.Request(P.LECO_REQ_RANGE, 9, None, 0, 0, 10))
+        assert st == P.LECO_EINVAL
+        st, _ = P.leco_server_submit(server, P.Request(P.LECO_REQ_RANGE, 0, None, 0, 0, 100_000))
+        assert st == P.LECO_ENOSPC
+        assert P.leco_server_release(server, 12345) == P.LECO_EINVAL
+    finally:
+        P.leco_server_stop(server)
+
+
+def test_open_loop_replay_reports_latencies(torch, codec, columns):
+    specs, cols, blobs, hosts = columns
+    reqs = W.request_mix(200, [s["n"] for s in specs], seed=63, max_log2_k=10, range_exp=(1, 4),
+                         rate=20_000.0)
+    arr = (P.Request * len(reqs))()
+    keep = []
+    for i, r in enumerate(reqs):
+        arr[i], pos = to_request(r)
+        keep.append(pos)
+    arrival = np.array([r["t"] for r in reqs]) - reqs[0]["t"]
+    lat = np.zeros(len(reqs))
+    server = start(codec, columns)
+    try:
+        st, elapsed = P.leco_server_replay(server, arr, arrival, lat)
+        assert st == P.LECO_OK
+        assert np.all(lat > 0) and elapsed > 0
+    finally:
+        P.leco_server_stop(server)
