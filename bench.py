@@ -11,7 +11,7 @@ Prints one JSON line.  `value` is decoded output GB/s of decode_all, from
 HIP events around each decode_all launch on the stream it runs on;
 `roofline` prices that kernel's algorithmic bytes (compressed bytes read
 plus output bytes written) against the 8 TB/s HBM peak.  `cpu_baseline`
-times the CPU oracle on the first 50,331,648 values of the same column.
+times the CPU oracle on the first 100,663,296 values of the same column.
 """
 from __future__ import annotations
 
@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=200_000_000)
     ap.add_argument("--lookups", type=int, default=100_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=12 * 4096 * 1024)
+    ap.add_argument("--cpu-sample", type=int, default=24 * 4096 * 1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["sorted_keys", "batched", "served"],
                     default="sorted_keys")
