@@ -216,7 +216,12 @@ leco_status leco_batch_create(leco_ctx* ctx, const leco_decode_job* jobs, uint64
   leco_batch* b = new leco_batch();
   b->ctx = ctx;
   b->jobs.assign(jobs, jobs + ncols);
-  b->tile_log2 = ctx->tune.tile_log2;
+  uint64_t all_bytes = 0, all_n = 0;
+  for (uint64_t i = 0; i < ncols; ++i) {
+    all_bytes += jobs[i].blob_bytes;
+    all_n += jobs[i].n;
+  }
+  b->tile_log2 = leco::pick_tile_log2(ctx->tune, all_bytes, all_n);
   b->blocks_per_cu = ctx->tune.decode_blocks_per_cu;
   if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     delete b;
@@ -289,7 +294,7 @@ leco_status leco_batch_run_graph(leco_batch* b, int op, hipStream_t stream) {
 leco_status leco_batch_tune(leco_batch* b, int op, hipStream_t stream, uint32_t* tile_log2,
                             uint32_t* blocks_per_cu) {
   if (!b || !valid_op(op)) return LECO_EINVAL;
-  static const uint32_t kTiles[] = {11, 12, 13};
+  static const uint32_t kTiles[] = {11, 12, 13, 14};
   static const uint32_t kBpc[] = {0, 4, 8};
   hipEvent_t e0, e1;
   hipEventCreate(&e0);

@@ -67,13 +67,6 @@ __global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ b
 
 // ---- random access -------------------------------------------------------------
 
-// Value at global position g (which must be < h.n), or a format error.
-struct Lookup {
-  uint64_t j;
-  uint64_t g;
-  uint4 r0, r1;  // the 32-byte record
-};
-
 // kLpt positions per lane, strided by the workgroup size so that position
 // loads and output stores stay coalesced; the lane issues all record loads,
 // then all word loads, so up to 2 kLpt independent loads are in flight.
@@ -216,11 +209,27 @@ __global__ __launch_bounds__(256) void k_diag_copy(const uint4* __restrict__ src
 
 // ---- launchers ---------------------------------------------------------------
 
+uint32_t pick_tile_log2(const Tune& t, uint64_t blob_bytes, uint64_t n) {
+  if (t.tile_log2) return t.tile_log2;
+  if (n == 0) return 12;
+  // bits per value over the whole blob (records and padding included, so an
+  // overestimate of the residual bits), with 1/16 slack for the per-partition
+  // word alignment and 16 words for the first load's alignment
+  const double bpv = 8.0 * double(blob_bytes) / double(n);
+  uint32_t share_log2 = 12;
+  while (share_log2 > 6 &&
+         double(uint64_t(1) << share_log2) * bpv / 32.0 * 1.0625 + 16.0 > double(kWaveStageWords))
+    --share_log2;
+  return share_log2 + 2;
+}
+
 hipError_t launch_decode(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, void* out,
                          uint64_t begin, uint64_t end, uint64_t out_cap, bool all,
                          hipStream_t stream) {
-  const uint32_t tl = ctx->tune.tile_log2;
   const uint64_t e = all ? out_cap : end;
+  // the total count is not known on the host: out_cap (decode_all) or end
+  // (range) stands in for it
+  const uint32_t tl = pick_tile_log2(ctx->tune, blob_bytes, e);
   if (!all && e <= begin) return hipSuccess;
   // decode_all always launches, so an empty output still checks n <= 0
   const uint64_t tiles = e <= begin ? 1 : ((e - 1) >> tl) - (begin >> tl) + 1;
@@ -267,7 +276,9 @@ hipError_t launch_filter_sum(leco_ctx* ctx, const void* blob, uint64_t blob_byte
                              uint64_t hi, uint64_t* out3, bool prune, hipStream_t stream) {
   hipError_t e = launch_zero_u64(out3, 3, stream);
   if (e != hipSuccess) return e;
-  const uint32_t tl = ctx->tune.tile_log2;
+  // n is read on the device; the filter's segments are staged one by one,
+  // so the tile only sets how the work is cut
+  const uint32_t tl = ctx->tune.tile_log2 ? ctx->tune.tile_log2 : 12;
   const uint64_t grid = uint64_t(ctx->num_cus) * 4;
   hipLaunchKernelGGL(k_filter_sum, dim3(uint32_t(grid)), dim3(kBlock), 0, stream,
                      static_cast<const uint8_t*>(blob), blob_bytes, lo, hi, out3, tl,

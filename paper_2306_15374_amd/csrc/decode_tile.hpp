@@ -45,40 +45,67 @@ __device__ inline uint32_t chunk_values(uint32_t bits) {
 // Decodes values t in [c0, c1) of partition p from the staged words, in
 // which residual t starts at bit qoff + b t.  Lane l takes t = c0 + l,
 // c0 + l + 64, ...
+//
+// The round count is uniform: rounds 0 .. full-1 have every lane active
+// and run unrolled by kUnroll with all residual reads of a group issued
+// before any is used, so the LDS latency is paid once per group; the
+// partial last round (lanes below rem) runs once under the lane mask.
+// Residual extraction, prediction and the sink are chosen per partition
+// outside the loops: U(i) gives the residual of round i, P(t) the
+// prediction at t.
+constexpr uint32_t kUnroll = 4;
+
+template <class Sink, class Residual, class Predict>
+__device__ inline void decode_rounds(const Part& p, uint32_t c0, uint32_t c1, Sink& sink,
+                                     Residual U, Predict P) {
+  const uint32_t lane = lane_id();
+  const uint32_t n = c1 - c0;
+  const uint32_t full = n / kWave, rem = n % kWave;
+  const uint32_t first = c0 + lane;
+  const uint64_t g_first = p.start + first;
+  uint32_t i = 0;
+  for (; i + kUnroll <= full; i += kUnroll) {
+    decltype(U(0u)) u[kUnroll];
+#pragma unroll
+    for (uint32_t k = 0; k < kUnroll; ++k) u[k] = U(i + k);
+#pragma unroll
+    for (uint32_t k = 0; k < kUnroll; ++k) {
+      const uint32_t r = i + k;
+      sink.put(g_first + r * kWave, p.base + uint64_t(P(first + r * kWave)) + u[k]);
+    }
+  }
+  for (; i < full; ++i) sink.put(g_first + i * kWave, p.base + uint64_t(P(first + i * kWave)) + U(i));
+  if (lane < rem)
+    sink.put(g_first + full * kWave, p.base + uint64_t(P(first + full * kWave)) + U(full));
+}
+
 template <class Sink>
 __device__ inline void decode_values(const Part& p, uint32_t c0, uint32_t c1, int64_t qoff,
                                      const uint32_t* stage, Sink& sink) {
   const uint32_t b = p.bits;
-  const bool small_pred = prediction_fits_i32(p.theta1, p.len);
+  const double theta1 = p.theta1;
   const uint32_t first = c0 + lane_id();
-  const uint32_t cnt = first < c1 ? (c1 - first + kWave - 1) / kWave : 0;
-  const uint32_t mask32 = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
-  const uint32_t mask_hi = b >= 64 ? 0xffffffffu : (b > 32 ? ((1u << (b - 32)) - 1u) : 0u);
   const uint32_t q0 = uint32_t(qoff + int64_t(b) * first);
   const uint32_t dq = b * kWave;
-  const uint64_t g_first = p.start + first;
-  if (b <= 32 && small_pred) {
-#pragma unroll 4
-    for (uint32_t i = 0; i < cnt; ++i) {
-      const uint32_t t = first + i * kWave;
-      const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
-      const int32_t pr = predict32(p.theta1, t);
-      sink.put(g_first + i * kWave, p.base + uint64_t(int64_t(pr)) + u);
-    }
+  auto pred32 = [=](uint32_t t) { return int64_t(predict32(theta1, t)); };
+  auto pred64 = [=](uint32_t t) { return predict(theta1, t); };
+  auto zero = [](uint32_t) { return 0u; };
+  if (b == 0) {
+    if (prediction_fits_i32(theta1, p.len))
+      decode_rounds(p, c0, c1, sink, zero, pred32);
+    else
+      decode_rounds(p, c0, c1, sink, zero, pred64);
   } else if (b <= 32) {
-#pragma unroll 2
-    for (uint32_t i = 0; i < cnt; ++i) {
-      const uint32_t t = first + i * kWave;
-      const uint32_t u = b ? extract32(stage, q0 + i * dq, mask32) : 0u;
-      sink.put(g_first + i * kWave, p.base + uint64_t(predict(p.theta1, t)) + u);
-    }
+    const uint32_t mask = b == 32 ? 0xffffffffu : ((1u << b) - 1u);
+    auto res = [=](uint32_t i) { return extract32(stage, q0 + i * dq, mask); };
+    if (prediction_fits_i32(theta1, p.len))
+      decode_rounds(p, c0, c1, sink, res, pred32);
+    else
+      decode_rounds(p, c0, c1, sink, res, pred64);
   } else {
-#pragma unroll 2
-    for (uint32_t i = 0; i < cnt; ++i) {
-      const uint32_t t = first + i * kWave;
-      const uint64_t u = extract64(stage, q0 + i * dq, mask_hi);
-      sink.put(g_first + i * kWave, p.base + uint64_t(predict(p.theta1, t)) + u);
-    }
+    const uint32_t mask_hi = b >= 64 ? 0xffffffffu : ((1u << (b - 32)) - 1u);
+    auto res = [=](uint32_t i) { return extract64(stage, q0 + i * dq, mask_hi); };
+    decode_rounds(p, c0, c1, sink, res, pred64);
   }
 }
 

@@ -12,7 +12,7 @@ namespace leco {
 
 // Launch parameters chosen per context (see tune.hip).
 struct Tune {
-  uint32_t tile_log2 = 12;           // values per decode tile = 2^tile_log2
+  uint32_t tile_log2 = 0;            // values per decode tile = 2^tile_log2; 0 = per blob
   uint32_t decode_blocks_per_cu = 0; // 0 = one workgroup per tile
   uint32_t xcd_remap = 0;            // 1 = contiguous tile runs per XCD
   uint32_t ra_lookups_per_lane = 1;  // 1, 2, 4 or 8 positions per lane
@@ -35,6 +35,13 @@ struct EncColumn {
   uint64_t part_base;      // index of the column's first partition in the launch
   uint32_t dtype, force_constant;
 };
+
+// Decode tile size (log2 of values per workgroup tile) for a blob of
+// blob_bytes holding about n values, unless the environment fixed it: the
+// largest tile (up to 4096 values per wavefront) whose residual words,
+// estimated from the blob's bits per value, fit one wavefront's LDS slice,
+// so that every wavefront stages its words in one round trip.
+uint32_t pick_tile_log2(const Tune& t, uint64_t blob_bytes, uint64_t n);
 
 hipError_t launch_decode(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, void* out,
                          uint64_t begin, uint64_t end, uint64_t out_cap, bool all,

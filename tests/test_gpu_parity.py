@@ -153,12 +153,36 @@ def test_edge_cases(torch, codec, ref):
 
 
 def test_wide_residuals_across_chunks(torch, codec, ref):
-    """Widths above 32 bits split a 4096-value tile into several LDS chunks."""
+    """Widths above 32 bits: the tile size picked from the blob's bits per
+    value keeps each wavefront's words within one LDS slice."""
     rng = np.random.default_rng(12)
     t = np.arange(200_000, dtype=np.uint64)
     col = t * np.uint64(2**20) + rng.integers(0, 2**45, 200_000, dtype=np.uint64)
     check_column(torch, codec, ref, col, "b~45 L=65536", fixed_len=65536)
     check_column(torch, codec, ref, col, "b~45 L=4096", fixed_len=4096)
+
+
+@pytest.mark.parametrize("tile_log2", [8, 14])
+def test_fixed_tile_shapes(torch, ref, monkeypatch, tile_log2):
+    """Tile size fixed through the environment instead of picked per blob.
+    At 2^14 values per tile (4096 per wavefront) the 45-bit residuals and the
+    ~14-bit residuals of sorted keys overflow the wavefront's LDS slice and go
+    through the chunked path; at 2^8 a partition spans many wavefronts and
+    tiles."""
+    monkeypatch.setenv("LECO_TILE_LOG2", str(tile_log2))
+    c = P.Codec(0)
+    try:
+        rng = np.random.default_rng(13)
+        t = np.arange(150_000, dtype=np.uint64)
+        wide = t * np.uint64(2**20) + rng.integers(0, 2**45, 150_000, dtype=np.uint64)
+        check_column(torch, c, ref, wide, f"tile 2^{tile_log2} b~45", fixed_len=4096)
+        mid = W.linear_noise(150_003, 14, np.uint32)
+        check_column(torch, c, ref, mid, f"tile 2^{tile_log2} u32", fixed_len=1000)
+        var = W.lognormal_keys(60_000, 15)
+        check_column(torch, c, ref, var, f"tile 2^{tile_log2} variable",
+                     starts=random_partitioning(rng, 60_000, 3000))
+    finally:
+        c.close()
 
 
 # ---- slope arithmetic ------------------------------------------------------------
