@@ -172,7 +172,7 @@ def bench_batched(args):
     batch = P.leco_batch_create(codec.ctx, djobs)
     st, tl, bpc = P.leco_batch_tune(batch, P.LECO_BATCH_DECODE)
     codec.check("leco_batch_tune", st)
-    log(f"tuned shape: tile 2^{tl}, blocks/CU {bpc}")
+    log(f"tuned shape: tile {'per column' if tl == 0 else f'2^{tl}'}, blocks/CU {bpc}")
     run = lambda op: (lambda: codec.check("leco_batch_run", P.leco_batch_run(batch, op)))
     run(P.LECO_BATCH_DECODE)()
     codec.sync()

@@ -232,13 +232,16 @@ leco_status leco_batch_run_graph(leco_batch *batch, int op, hipStream_t stream);
 
 /* Times the candidate launch shapes (tile size, workgroups per CU) of this
  * batch for `op` and keeps the fastest; every candidate produces identical
- * results.  Writes the chosen shape to *tile_log2 and *blocks_per_cu if not
- * null.  [sync] */
+ * results.  Writes the chosen shape to *tile_log2 (0: each column's own) and
+ * *blocks_per_cu if not null.  [sync] */
 leco_status leco_batch_tune(leco_batch *batch, int op, hipStream_t stream,
                             uint32_t *tile_log2, uint32_t *blocks_per_cu);
 
-/* Sets the launch shape explicitly (tile of 2^tile_log2 values, 8..16;
- * blocks_per_cu = 0 for one workgroup per tile). */
+/* Sets the launch shape explicitly: tiles of 2^tile_log2 values (8..16) for
+ * every column, or 0 for each column's own size, the largest whose residual
+ * words (estimated from the column's blob bytes per value) fit one
+ * wavefront's LDS slice (the default); blocks_per_cu = 0 for one workgroup
+ * per tile.  EINVAL outside these ranges. */
 leco_status leco_batch_set_shape(leco_batch *batch, uint32_t tile_log2,
                                  uint32_t blocks_per_cu);
 

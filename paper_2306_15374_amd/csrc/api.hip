@@ -195,11 +195,11 @@ leco_status leco_create(int hip_device, leco_ctx** out) {
 
 leco_status leco_destroy(leco_ctx* ctx) {
   if (!ctx) return LECO_OK;
-  hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
-  if (ctx->scratch) hipFree(ctx->scratch);
-  if (ctx->err_dev) hipFree(ctx->err_dev);
-  if (ctx->err_host) hipHostFree(ctx->err_host);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->err_dev) (void)hipFree(ctx->err_dev);
+  if (ctx->err_host) (void)hipHostFree(ctx->err_host);
   delete ctx;
   return LECO_OK;
 }

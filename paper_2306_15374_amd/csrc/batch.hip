@@ -10,7 +10,8 @@
 namespace leco {
 
 // One column of a decode batch in device memory.  tile_base is the index of
-// the column's first tile in the flattened table.
+// the column's first tile in the flattened table; its tiles hold
+// 2^tile_log2 values each.
 struct DecCol {
   const uint8_t* blob;
   uint64_t blob_bytes;
@@ -19,6 +20,7 @@ struct DecCol {
   uint64_t lo, hi;
   uint64_t* sum3;
   uint64_t tile_base;
+  uint32_t tile_log2, pad;
 };
 
 // Stores each value (when kStore) and accumulates the filter sum (when
@@ -32,7 +34,7 @@ struct BatchSink {
     return kStore ? true : f.visit_segment(p, t0, t1);
   }
   __device__ void put(uint64_t g, uint64_t v) {
-    if (kStore) __builtin_nontemporal_store(OutT(v), out + g);
+    if (kStore) __builtin_nontemporal_store(OutT(v), global_ptr(out + g));
     if (kFilter) f.put(g, v);
   }
 };
@@ -41,8 +43,9 @@ struct BatchSink {
 // every thread of the workgroup then joins the exact sum (a workgroup
 // barrier, reached by all waves whatever their share held).
 template <typename OutT, bool kStore, bool kFilter>
-__device__ bool run_tile(const DecCol& c, const Header& h, uint64_t g0, uint64_t g1,
-                         uint32_t* stage) {
+__device__ __attribute__((always_inline)) bool run_tile(const DecCol& c, const Header& h,
+                                                        uint64_t g0, uint64_t g1,
+                                                        uint32_t* stage) {
   BatchSink<OutT, kStore, kFilter> sink{reinterpret_cast<OutT*>(c.out),
                                         FilterSink{c.lo, c.hi, 0, 0, 0, kStore ? 0 : 1}};
   const bool ok = g0 >= g1 || decode_tile(c.blob, h, g0, g1, stage, sink);
@@ -53,8 +56,7 @@ __device__ bool run_tile(const DecCol& c, const Header& h, uint64_t g0, uint64_t
 template <bool kStore, bool kFilter>
 __global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restrict__ cols,
                                                          const uint32_t* __restrict__ tile_col,
-                                                         uint64_t total_tiles, uint32_t tile_log2,
-                                                         int* err) {
+                                                         uint64_t total_tiles, int* err) {
   __shared__ uint4 stage_v[kWavesPerBlock * kWaveStageWords / 4];
   uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveStageWords;
   for (uint64_t k = blockIdx.x; k < total_tiles; k += gridDim.x) {
@@ -64,6 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restric
       if (threadIdx.x == 0) raise(err, kErrFormat);
       continue;
     }
+    const uint32_t tile_log2 = c.tile_log2;
     const uint64_t t0 = (k - c.tile_base) << tile_log2;
     uint64_t t1 = t0 + (uint64_t(1) << tile_log2);
     if (t1 > c.n) t1 = c.n;
@@ -106,7 +109,7 @@ struct leco_batch {
   uint32_t* tile_col_dev = nullptr;  // column of every tile
   uint64_t tile_col_cap = 0;
   uint64_t total_tiles = 0;
-  uint32_t tile_log2 = 12;
+  uint32_t tile_log2 = 0;  // 0 = each column's own, from its bits per value
   uint32_t blocks_per_cu = 0;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -122,12 +125,13 @@ leco_status bfail(leco_batch* b, leco_status st, const char* msg) {
 void drop_graphs(leco_batch* b) {
   for (auto& g : b->graphs)
     if (g) {
-      hipGraphExecDestroy(g);
+      (void)hipGraphExecDestroy(g);
       g = nullptr;
     }
 }
 
-// Rebuilds and uploads the flattened tile table for the batch's tile size.
+// Rebuilds and uploads the flattened tile table for the batch's tile size
+// (or each column's own).
 leco_status upload_table(leco_batch* b) {
   const uint64_t ncols = b->jobs.size();
   std::vector<leco::DecCol> cols(ncols);
@@ -143,7 +147,9 @@ leco_status upload_table(leco_batch* b) {
     c.hi = j.hi;
     c.sum3 = j.sum3_dev;
     c.tile_base = tiles;
-    tiles += (j.n + (uint64_t(1) << b->tile_log2) - 1) >> b->tile_log2;
+    c.tile_log2 = b->tile_log2 ? b->tile_log2 : leco::pick_tile_log2(leco::Tune{}, j.blob_bytes, j.n);
+    c.pad = 0;
+    tiles += (j.n + (uint64_t(1) << c.tile_log2) - 1) >> c.tile_log2;
   }
   b->total_tiles = tiles;
   if (ncols == 0) return LECO_OK;
@@ -156,7 +162,7 @@ leco_status upload_table(leco_batch* b) {
   if (!b->cols_dev && hipMalloc(&b->cols_dev, sizeof(leco::DecCol) * ncols) != hipSuccess)
     return bfail(b, LECO_ENOMEM, "batch table allocation failed");
   if (tile_col.size() > b->tile_col_cap) {
-    if (b->tile_col_dev) hipFree(b->tile_col_dev);
+    if (b->tile_col_dev) (void)hipFree(b->tile_col_dev);
     b->tile_col_dev = nullptr;
     b->tile_col_cap = 0;
     if (hipMalloc(&b->tile_col_dev, 4 * tile_col.size()) != hipSuccess)
@@ -172,10 +178,19 @@ leco_status upload_table(leco_batch* b) {
   return LECO_OK;
 }
 
+using BatchKernel = void (*)(const leco::DecCol*, const uint32_t*, uint64_t, int*);
+
+BatchKernel batch_kernel(int op) {
+  const bool filter = (op & LECO_BATCH_FILTER) != 0, store = (op & LECO_BATCH_DECODE) != 0;
+  return store && filter ? leco::k_batch_decode<true, true>
+         : store         ? leco::k_batch_decode<true, false>
+                         : leco::k_batch_decode<false, true>;
+}
+
 hipError_t launch_batch(leco_batch* b, int op, hipStream_t stream) {
   const uint64_t ncols = b->jobs.size();
   if (ncols == 0) return hipSuccess;
-  const bool filter = (op & LECO_BATCH_FILTER) != 0, store = (op & LECO_BATCH_DECODE) != 0;
+  const bool filter = (op & LECO_BATCH_FILTER) != 0;
   if (filter) {
     const uint64_t g = (ncols + 255) / 256;
     hipLaunchKernelGGL(leco::k_batch_zero_sums, dim3(uint32_t(g < 1024 ? g : 1024)), dim3(256), 0,
@@ -184,11 +199,9 @@ hipError_t launch_batch(leco_batch* b, int op, hipStream_t stream) {
   if (b->total_tiles == 0) return hipGetLastError();
   const uint64_t cap = uint64_t(b->ctx->num_cus) * b->blocks_per_cu;
   const uint64_t grid = (cap == 0 || b->total_tiles < cap) ? b->total_tiles : cap;
-  auto k = store && filter ? leco::k_batch_decode<true, true>
-           : store         ? leco::k_batch_decode<true, false>
-                           : leco::k_batch_decode<false, true>;
-  hipLaunchKernelGGL(k, dim3(uint32_t(grid)), dim3(leco::kBlock), 0, stream, b->cols_dev,
-                     b->tile_col_dev, b->total_tiles, b->tile_log2, b->ctx->err_dev);
+  hipLaunchKernelGGL(batch_kernel(op), dim3(uint32_t(grid)), dim3(leco::kBlock), 0, stream,
+                     b->cols_dev,
+                     b->tile_col_dev, b->total_tiles, b->ctx->err_dev);
   return hipGetLastError();
 }
 
@@ -216,12 +229,7 @@ leco_status leco_batch_create(leco_ctx* ctx, const leco_decode_job* jobs, uint64
   leco_batch* b = new leco_batch();
   b->ctx = ctx;
   b->jobs.assign(jobs, jobs + ncols);
-  uint64_t all_bytes = 0, all_n = 0;
-  for (uint64_t i = 0; i < ncols; ++i) {
-    all_bytes += jobs[i].blob_bytes;
-    all_n += jobs[i].n;
-  }
-  b->tile_log2 = leco::pick_tile_log2(ctx->tune, all_bytes, all_n);
+  b->tile_log2 = ctx->tune.tile_log2;
   b->blocks_per_cu = ctx->tune.decode_blocks_per_cu;
   if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     delete b;
@@ -238,19 +246,20 @@ leco_status leco_batch_create(leco_ctx* ctx, const leco_decode_job* jobs, uint64
 
 leco_status leco_batch_destroy(leco_batch* b) {
   if (!b) return LECO_OK;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   drop_graphs(b);
-  if (b->cols_dev) hipFree(b->cols_dev);
-  if (b->tile_col_dev) hipFree(b->tile_col_dev);
-  if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+  if (b->cols_dev) (void)hipFree(b->cols_dev);
+  if (b->tile_col_dev) (void)hipFree(b->tile_col_dev);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   delete b;
   return LECO_OK;
 }
 
 leco_status leco_batch_set_shape(leco_batch* b, uint32_t tile_log2, uint32_t blocks_per_cu) {
-  if (!b || tile_log2 < 8 || tile_log2 > 16 || blocks_per_cu > 64) return LECO_EINVAL;
+  if (!b || (tile_log2 != 0 && (tile_log2 < 8 || tile_log2 > 16)) || blocks_per_cu > 64)
+    return LECO_EINVAL;
   if (tile_log2 == b->tile_log2 && blocks_per_cu == b->blocks_per_cu) return LECO_OK;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   b->blocks_per_cu = blocks_per_cu;
   if (tile_log2 != b->tile_log2) {
     b->tile_log2 = tile_log2;
@@ -281,7 +290,7 @@ leco_status leco_batch_run_graph(leco_batch* b, int op, hipStream_t stream) {
     if (le != hipSuccess || ce != hipSuccess || !g)
       return bfail(b, LECO_EDEVICE, "batch capture failed");
     const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (ie != hipSuccess) {
       exec = nullptr;
       return bfail(b, LECO_EDEVICE, "graph instantiation failed");
@@ -294,27 +303,40 @@ leco_status leco_batch_run_graph(leco_batch* b, int op, hipStream_t stream) {
 leco_status leco_batch_tune(leco_batch* b, int op, hipStream_t stream, uint32_t* tile_log2,
                             uint32_t* blocks_per_cu) {
   if (!b || !valid_op(op)) return LECO_EINVAL;
-  static const uint32_t kTiles[] = {11, 12, 13, 14};
-  static const uint32_t kBpc[] = {0, 4, 8};
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  // persistent grids are tried at the number of workgroups a CU holds at
+  // once, so that no workgroup waits for another one to finish
+  int resident = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, batch_kernel(op), leco::kBlock, 0) !=
+          hipSuccess ||
+      resident < 1)
+    resident = 4;
+  static const uint32_t kTiles[] = {0, 12, 13, 14};
+  const uint32_t bpcs[] = {0, uint32_t(resident)};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  leco_status st = LECO_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = LECO_EDEVICE;
   float best = 1e30f;
   uint32_t bt = b->tile_log2, bb = b->blocks_per_cu;
   for (uint32_t tl : kTiles) {
-    for (uint32_t bpc : kBpc) {
-      leco_status st = leco_batch_set_shape(b, tl, bpc);
-      if (st != LECO_OK) return st;
-      launch_batch(b, op, stream);  // warm-up
+    for (uint32_t bpc : bpcs) {
+      if (st != LECO_OK) break;
+      st = leco_batch_set_shape(b, tl, bpc);
+      if (st != LECO_OK) break;
       float total = 0.0f;
-      for (int r = 0; r < 3; ++r) {
-        hipEventRecord(e0, stream);
-        launch_batch(b, op, stream);
-        hipEventRecord(e1, stream);
-        hipEventSynchronize(e1);
+      hipError_t e = launch_batch(b, op, stream);  // warm-up
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) {
         float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess ||
+            (e = launch_batch(b, op, stream)) != hipSuccess ||
+            (e = hipEventRecord(e1, stream)) != hipSuccess ||
+            (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+          break;
         total += ms;
+      }
+      if (e != hipSuccess) {
+        st = bfail(b, LECO_EDEVICE, hipGetErrorString(e));
+        break;
       }
       if (total < best) {
         best = total;
@@ -323,12 +345,12 @@ leco_status leco_batch_tune(leco_batch* b, int op, hipStream_t stream, uint32_t*
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  const leco_status st = leco_batch_set_shape(b, bt, bb);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  const leco_status st2 = leco_batch_set_shape(b, bt, bb);
   if (tile_log2) *tile_log2 = bt;
   if (blocks_per_cu) *blocks_per_cu = bb;
-  return st;
+  return st != LECO_OK ? st : st2;
 }
 
 }  // extern "C"

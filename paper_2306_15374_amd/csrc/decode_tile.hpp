@@ -85,26 +85,48 @@ __device__ inline void decode_values(const Part& p, uint32_t c0, uint32_t c1, in
   const uint32_t b = p.bits;
   const double theta1 = p.theta1;
   const uint32_t first = c0 + lane_id();
+  // Residual of round i starts at bit q0 + 64 b i of the stage.  64 b is a
+  // multiple of 32, so the bit offset within a word (sh) is the same in
+  // every round and the word index advances by 2 b per round.
   const uint32_t q0 = uint32_t(qoff + int64_t(b) * first);
-  const uint32_t dq = b * kWave;
+  const uint32_t* lw = stage + (q0 >> 5);
+  const uint32_t sh = q0 & 31, wstep = 2 * b;
+  // With a non-negative slope every product is >= 0 (or +-0), so the floor
+  // is the conversion's truncation toward zero.
+  const bool nonneg = !(theta1 < 0.0);
   auto pred32 = [=](uint32_t t) { return int64_t(predict32(theta1, t)); };
+  auto pred32_nn = [=](uint32_t t) { return int64_t(int32_t(__dmul_rn(theta1, double(t)))); };
   auto pred64 = [=](uint32_t t) { return predict(theta1, t); };
   auto zero = [](uint32_t) { return 0u; };
+  const bool fits32 = prediction_fits_i32(theta1, p.len);
   if (b == 0) {
-    if (prediction_fits_i32(theta1, p.len))
+    if (fits32 && nonneg)
+      decode_rounds(p, c0, c1, sink, zero, pred32_nn);
+    else if (fits32)
       decode_rounds(p, c0, c1, sink, zero, pred32);
     else
       decode_rounds(p, c0, c1, sink, zero, pred64);
   } else if (b <= 32) {
     const uint32_t mask = b == 32 ? 0xffffffffu : ((1u << b) - 1u);
-    auto res = [=](uint32_t i) { return extract32(stage, q0 + i * dq, mask); };
-    if (prediction_fits_i32(theta1, p.len))
+    auto res = [=](uint32_t i) {
+      const uint32_t* w = lw + i * wstep;
+      return __builtin_amdgcn_alignbit(w[1], w[0], sh) & mask;
+    };
+    if (fits32 && nonneg)
+      decode_rounds(p, c0, c1, sink, res, pred32_nn);
+    else if (fits32)
       decode_rounds(p, c0, c1, sink, res, pred32);
     else
       decode_rounds(p, c0, c1, sink, res, pred64);
   } else {
     const uint32_t mask_hi = b >= 64 ? 0xffffffffu : ((1u << (b - 32)) - 1u);
-    auto res = [=](uint32_t i) { return extract64(stage, q0 + i * dq, mask_hi); };
+    auto res = [=](uint32_t i) {
+      const uint32_t* w = lw + i * wstep;
+      const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+      const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, sh);
+      const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, sh) & mask_hi;
+      return (uint64_t(hi) << 32) | lo;
+    };
     decode_rounds(p, c0, c1, sink, res, pred64);
   }
 }
@@ -122,8 +144,9 @@ __device__ inline void word_span(const Part& p, uint32_t t0, uint32_t t1, uint64
 __device__ inline void stage_words(const uint32_t* __restrict__ words32, uint64_t a0,
                                    uint64_t w_end, uint32_t* stage) {
   const uint32_t nvec = uint32_t((w_end - a0 + 3) >> 2);
-  const uint4* src = reinterpret_cast<const uint4*>(words32 + a0);
-  uint4* dst = reinterpret_cast<uint4*>(stage);
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const auto src = global_ptr(reinterpret_cast<const u32x4*>(words32 + a0));
+  u32x4* dst = reinterpret_cast<u32x4*>(stage);
   for (uint32_t i = lane_id(); i < nvec; i += kWave) dst[i] = src[i];
 }
 
@@ -238,7 +261,7 @@ struct StoreSink {
   uint64_t origin;
   __device__ bool visit_segment(const Part&, uint32_t, uint32_t) { return true; }
   __device__ void put(uint64_t g, uint64_t v) {
-    __builtin_nontemporal_store(OutT(v), out + (g - origin));
+    __builtin_nontemporal_store(OutT(v), global_ptr(out + (g - origin)));
   }
 };
 

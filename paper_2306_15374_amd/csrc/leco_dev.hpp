@@ -22,6 +22,24 @@ constexpr int kErrDevice = 8;  // a bounded wait gave up (never expected)
 
 __host__ __device__ inline uint64_t align16(uint64_t x) { return (x + 15) & ~uint64_t(15); }
 
+// Blob metadata (header, records, starts) is read through the constant
+// address space: no kernel writes a blob while it decodes it, so loads whose
+// address is uniform across the wavefront can use scalar loads, also when
+// the blob pointer was itself read from a table in memory (batched and
+// served decoding), and their results stay in scalar registers.
+typedef const __attribute__((address_space(4))) uint64_t* MetaPtr;
+__device__ inline MetaPtr meta_words(const uint8_t* blob, uint64_t byte_off) {
+  return (MetaPtr)(blob + byte_off);
+}
+
+// Residual words and outputs live in global memory; saying so lets the
+// compiler use global instead of flat loads and stores where the pointer
+// came from a table in memory.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* global_ptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 struct Header {
   uint64_t n, m, fixed_len, starts_off, words_off, total_words;
   uint32_t dtype;     // 4 or 8
@@ -33,7 +51,7 @@ struct Header {
 // returns true and the per-record checks below pass.
 __device__ inline bool load_header(const uint8_t* blob, uint64_t blob_bytes, Header& h) {
   if (blob_bytes < kHeaderBytes) return false;
-  const uint64_t* q = reinterpret_cast<const uint64_t*>(blob);
+  const MetaPtr q = meta_words(blob, 0);
   uint64_t w0 = q[0];
   h.n = q[1];
   h.m = q[2];
@@ -74,7 +92,7 @@ struct Part {
 };
 
 __device__ inline uint64_t part_start(const uint8_t* blob, const Header& h, uint64_t j) {
-  if (h.variable) return reinterpret_cast<const uint64_t*>(blob + h.starts_off)[j];
+  if (h.variable) return meta_words(blob, h.starts_off)[j];
   uint64_t s = j * h.fixed_len;
   return s < h.n ? s : h.n;
 }
@@ -82,7 +100,7 @@ __device__ inline uint64_t part_start(const uint8_t* blob, const Header& h, uint
 // Loads partition j and checks it; false means the blob is corrupt.
 __device__ inline bool load_part(const uint8_t* blob, const Header& h, uint64_t j, Part& p) {
   if (j >= h.m) return false;
-  const uint64_t* r = reinterpret_cast<const uint64_t*>(blob + kHeaderBytes + kRecordBytes * j);
+  const MetaPtr r = meta_words(blob, kHeaderBytes + kRecordBytes * j);
   p.base = r[0];
   p.theta1 = __longlong_as_double(static_cast<long long>(r[1]));
   p.word_off = r[2];
@@ -109,7 +127,7 @@ __device__ inline uint64_t locate(const uint8_t* blob, const Header& h, uint64_t
     while ((j + 1) * L <= g) ++j;
     return j;
   }
-  const uint64_t* s = reinterpret_cast<const uint64_t*>(blob + h.starts_off);
+  const MetaPtr s = meta_words(blob, h.starts_off);
   uint64_t lo = 0, hi = h.m;  // answer in [lo, hi)
   while (hi - lo > 1) {
     uint64_t mid = lo + ((hi - lo) >> 1);

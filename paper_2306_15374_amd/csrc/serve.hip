@@ -157,7 +157,8 @@ struct Slot {
   leco::WorkItem* items_host = nullptr;  // pinned
   leco::WorkItem* items_dev = nullptr;
   bool busy = false;
-  std::vector<Pending> reqs;  // requests the running step completes
+  leco_status status = LECO_OK;  // EDEVICE if the step's launch failed
+  std::vector<Pending> reqs;     // requests the running step completes
   std::vector<uint64_t> offs;
 };
 
@@ -281,14 +282,22 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
   if (slot->reqs.empty()) return false;
   s->stats.steps += 1;
   lk.unlock();
+  hipError_t e = hipSuccess;
   if (nitems) {
-    hipMemcpyAsync(slot->items_dev, slot->items_host, sizeof(leco::WorkItem) * nitems,
-                   hipMemcpyHostToDevice, slot->stream);
-    hipLaunchKernelGGL(leco::k_serve_step, dim3(nitems), dim3(leco::kBlock), 0, slot->stream,
-                       s->cols_dev, slot->items_dev, s->ring_dev, s->arena_dev, s->ctx->err_dev);
+    e = hipMemcpyAsync(slot->items_dev, slot->items_host, sizeof(leco::WorkItem) * nitems,
+                       hipMemcpyHostToDevice, slot->stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(leco::k_serve_step, dim3(nitems), dim3(leco::kBlock), 0, slot->stream,
+                         s->cols_dev, slot->items_dev, s->ring_dev, s->arena_dev,
+                         s->ctx->err_dev);
+      e = hipGetLastError();
+    }
   }
-  hipEventRecord(slot->done, slot->stream);
+  if (e == hipSuccess) e = hipEventRecord(slot->done, slot->stream);
+  // a failed step completes its requests with EDEVICE once its stream drains
+  if (e != hipSuccess) (void)hipStreamSynchronize(slot->stream);
   lk.lock();
+  slot->status = e == hipSuccess ? LECO_OK : LECO_EDEVICE;
   slot->busy = true;
   return true;
 }
@@ -298,7 +307,7 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
 bool retire_steps(leco_server* s) {
   bool any = false;
   for (Slot& slot : s->slots) {
-    if (!slot.busy || hipEventQuery(slot.done) != hipSuccess) continue;
+    if (!slot.busy || (slot.status == LECO_OK && hipEventQuery(slot.done) != hipSuccess)) continue;
     const Clock::time_point now = Clock::now();
     for (size_t i = 0; i < slot.reqs.size(); ++i) {
       const Pending& p = slot.reqs[i];
@@ -307,7 +316,7 @@ bool retire_steps(leco_server* s) {
       if (it != s->results.end()) it->second.done = true;
       leco_completion c{};
       c.ticket = p.ticket;
-      c.status = LECO_OK;
+      c.status = slot.status;
       c.dtype = int32_t(s->cols[p.req.col].dtype);
       c.out_dev = s->arena_dev + slot.offs[i];
       c.count = p.count;
@@ -325,7 +334,7 @@ bool retire_steps(leco_server* s) {
 }
 
 void worker_main(leco_server* s) {
-  hipSetDevice(s->ctx->device);
+  (void)hipSetDevice(s->ctx->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
     retire_steps(s);
@@ -347,8 +356,8 @@ void worker_main(leco_server* s) {
 
 void free_server(leco_server* s) {
   for (Slot& slot : s->slots) {
-    if (slot.stream) hipStreamSynchronize(slot.stream);
-    if (slot.done) hipEventDestroy(slot.done);
+    if (slot.stream) (void)hipStreamSynchronize(slot.stream);
+    if (slot.done) (void)hipEventDestroy(slot.done);
     if (slot.stream) hipStreamDestroy(slot.stream);
     if (slot.items_host) hipHostFree(slot.items_host);
     if (slot.items_dev) hipFree(slot.items_dev);

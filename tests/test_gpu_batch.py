@@ -135,7 +135,7 @@ def test_every_launch_shape_gives_identical_results(torch, codec):
     blobs = [codec.encode(c, fixed_len=s["fixed_len"]) for s, c in zip(specs, cols)]
     batch, outs, sums, bounds = make_batch(torch, codec, specs, cols, blobs)
     try:
-        for tl in (9, 11, 12, 13, 14):
+        for tl in (0, 9, 11, 12, 13, 14):
             for bpc in (0, 1, 4, 8):
                 print(f"[shape] tile_log2={tl} blocks_per_cu={bpc}", flush=True)
                 codec.check("set_shape", P.leco_batch_set_shape(batch, tl, bpc))
@@ -146,7 +146,7 @@ def test_every_launch_shape_gives_identical_results(torch, codec):
                 check_outputs(torch, specs, cols, outs, sums, bounds)
         st, tl, bpc = P.leco_batch_tune(batch, 3)
         codec.check("leco_batch_tune", st)
-        assert tl in (11, 12, 13) and bpc in (0, 4, 8)
+        assert tl in (0, 12, 13, 14) and bpc in (0, 4, 8)
         codec.check("leco_batch_run", P.leco_batch_run(batch, 3))
         codec.sync()
         check_outputs(torch, specs, cols, outs, sums, bounds)
