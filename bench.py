@@ -47,23 +47,28 @@ def parse():
     ap.add_argument("--cols", type=int, default=4096)
     ap.add_argument("--served-n", type=int, default=39_062_500)
     ap.add_argument("--requests", type=int, default=20_000)
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched: skip the 4096-launch per-column comparison (for profiler runs)")
     return ap.parse_args()
 
 
 DECODER_SOURCES = ["paper_2306_15374_amd/csrc/decode.hip", "paper_2306_15374_amd/csrc/decode_tile.hpp",
                    "paper_2306_15374_amd/csrc/leco_dev.hpp"]
 TRAFFIC_PROFILE = "profiles/k_decode_sorted_keys_200M.md"
+BATCH_SOURCES = ["paper_2306_15374_amd/csrc/batch.hip", "paper_2306_15374_amd/csrc/decode_tile.hpp",
+                 "paper_2306_15374_amd/csrc/leco_dev.hpp"]
+BATCH_TRAFFIC_PROFILE = "profiles/k_batch_decode_4096_columns.md"
 
 
-def measured_traffic():
-    """HBM bytes per decode_all launch from the committed rocprofv3 counter
-    summary, or None if the decoder sources changed since it was taken."""
+def measured_traffic(sources=DECODER_SOURCES, profile=TRAFFIC_PROFILE):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None if the kernel's sources changed since it was taken."""
     import hashlib
     try:
         h = hashlib.sha256()
-        for f in DECODER_SOURCES:
+        for f in sources:
             h.update(open(os.path.join(ROOT, f), "rb").read())
-        for line in open(os.path.join(ROOT, TRAFFIC_PROFILE)):
+        for line in open(os.path.join(ROOT, profile)):
             line = line.strip()
             if line.startswith("{") and '"source_sha"' in line:
                 rec = json.loads(line)
@@ -197,7 +202,7 @@ def bench_batched(args):
     def plain():
         for b, o, s in zip(blobs, outs, specs):
             codec.check("leco_decode_all", P.leco_decode_all(codec.ctx, b, b.numel(), o, s["n"]))
-    t_plain = time_events(torch, stream, plain, 3)
+    t_plain = None if args.no_plain else time_events(torch, stream, plain, 3)
     codec.sync()
     P.leco_batch_destroy(batch)
     alg = blob_total + in_bytes
@@ -212,8 +217,8 @@ def bench_batched(args):
                    "tile_log2": tl, "blocks_per_cu": bpc},
         "batched_decode_ms": round(t_dec * 1e3, 3),
         "batched_decode_graph_ms": round(t_graph * 1e3, 3),
-        "plain_per_column_decode_ms": round(t_plain * 1e3, 3),
-        "speedup_vs_plain": round(t_plain / t_dec, 2),
+        "plain_per_column_decode_ms": None if t_plain is None else round(t_plain * 1e3, 3),
+        "speedup_vs_plain": None if t_plain is None else round(t_plain / t_dec, 2),
         "filter_sum_ms": round(t_filter * 1e3, 3),
         "filter_sum_values_per_s": round(n_total / t_filter, 1),
         "fused_decode_filter_ms": round(t_fused * 1e3, 3),
@@ -221,7 +226,9 @@ def bench_batched(args):
         "batched_encode_GBps": round(in_bytes / t_enc / 1e9, 2),
         "compression_ratio": round(blob_total / in_bytes, 5),
         "roofline": {"bound": "hbm", "achieved": round(alg / t_dec / 1e9, 1), "peak": HBM_PEAK / 1e9,
-                     "unit": "GB/s", "frac": round(alg / t_dec / HBM_PEAK, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(alg / t_dec / HBM_PEAK, 4),
+                     "traffic": (measured_traffic(BATCH_SOURCES, BATCH_TRAFFIC_PROFILE)
+                                 if args.cols == 4096 else None),
                      "kernel": "k_batch_decode", "bytes_per_launch": alg},
         "cpu_baseline": None,
     }
