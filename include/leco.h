@@ -268,7 +268,7 @@ typedef struct {
   uint32_t max_inflight;       /* admitted, not yet released requests      */
   uint32_t num_streams;        /* steps that may run concurrently (>= 1)   */
   uint32_t max_step_items;     /* workgroups per step launch               */
-  uint32_t max_step_positions; /* random-access positions staged per step  */
+  uint32_t max_step_positions; /* host-memory positions staged per step    */
   /* Batching: while a step is running, the next one is launched only once
    * its admitted requests produce min_step_bytes of results, fill half the
    * step, or the oldest of them has waited max_wait_us.  An idle GPU always
@@ -282,12 +282,20 @@ typedef struct {
   uint64_t position_ring_bytes;
 } leco_server_config;
 
-enum { LECO_REQ_RANDOM_ACCESS = 1, LECO_REQ_RANGE = 2 };
+/* Request kinds.  LECO_REQ_RANDOM_ACCESS: k positions in host memory,
+ * checked against n and copied into the position ring at submission (the
+ * caller's buffer is free again when submit returns).
+ * LECO_REQ_RANDOM_ACCESS_DEV: k positions in device memory (8-byte aligned),
+ * read in place by the step kernel; the buffer must stay valid and unchanged
+ * until the request completes.  They are checked on the device: a position
+ * >= n yields 0 and raises the context's range flag (leco_sync reports
+ * LECO_ERANGE).  LECO_REQ_RANGE: values [begin, end). */
+enum { LECO_REQ_RANDOM_ACCESS = 1, LECO_REQ_RANGE = 2, LECO_REQ_RANDOM_ACCESS_DEV = 3 };
 
 typedef struct {
-  uint32_t kind;                 /* LECO_REQ_RANDOM_ACCESS or LECO_REQ_RANGE   */
+  uint32_t kind;                 /* one of the request kinds above             */
   uint32_t col;                  /* resident column index                      */
-  const uint64_t *positions_host;/* random access: k positions, copied at submit */
+  const uint64_t *positions;     /* random access: k positions (host or device) */
   uint64_t k;
   uint64_t begin, end;           /* range: positions [begin, end)              */
 } leco_request;
@@ -310,12 +318,21 @@ typedef struct {
 leco_status leco_server_start(leco_ctx *ctx, const leco_resident_col *cols_host,
                               uint64_t ncols, const leco_server_config *cfg,
                               leco_server **out);
-/* Queues a request; never blocks on the GPU.  Positions are checked against
- * n and copied into the position ring here (LECO_ERANGE; LECO_ENOMEM when
- * the ring is momentarily full: retry once earlier requests complete); a
- * request larger than the whole budget is refused (LECO_ENOSPC). */
+/* Queues a request; never blocks on the GPU.  Host positions are checked
+ * against n and copied into the position ring here (LECO_ERANGE; LECO_ENOMEM
+ * when the ring is momentarily full: retry once earlier requests complete);
+ * a request larger than the whole budget is refused (LECO_ENOSPC), one
+ * larger than a step (max_step_items workgroups of 256 lookups or 4096
+ * range values) is LECO_EINVAL.  A request's latency runs from the start of
+ * this call. */
 leco_status leco_server_submit(leco_server *s, const leco_request *req,
                                uint64_t *ticket);
+/* Queues reqs[0..n) in order with one acquisition of the server's lock,
+ * stopping at the first request that fails (its status is returned;
+ * *accepted, if not null, receives how many were queued and tickets[0..
+ * *accepted) their tickets).  The checks and errors are leco_server_submit's. */
+leco_status leco_server_submit_batch(leco_server *s, const leco_request *reqs, uint64_t n,
+                                     uint64_t *tickets, uint64_t *accepted);
 /* Returns up to max completions (non-blocking). */
 leco_status leco_server_poll(leco_server *s, leco_completion *out, uint64_t max,
                              uint64_t *got);
@@ -328,8 +345,9 @@ leco_status leco_server_stop(leco_server *s);
 /* Open-loop load generator: submits reqs[i] at arrival_s[i] seconds after
  * the call (busy-waiting), releases each result as it completes, and waits
  * for all of them.  latency_us_out (n entries, may be null) receives each
- * request's latency; *elapsed_s the time from the first arrival to the last
- * completion. */
+ * request's latency from its scheduled arrival (so a generator that falls
+ * behind is charged for it) to the observed completion of its step;
+ * *elapsed_s the time from the first arrival to the last completion. */
 leco_status leco_server_replay(leco_server *s, const leco_request *reqs,
                                const double *arrival_s, uint64_t n,
                                double *latency_us_out, double *elapsed_s);

@@ -29,10 +29,11 @@ EXPORTS = [
     "leco_decode_all", "leco_decode_range", "leco_random_access", "leco_filter_sum",
     "leco_diag_slope", "leco_diag_copy", "leco_encode_batch", "leco_batch_create",
     "leco_batch_destroy", "leco_batch_run", "leco_batch_run_graph", "leco_batch_tune",
-    "leco_batch_set_shape", "leco_server_start", "leco_server_submit", "leco_server_poll",
-    "leco_server_release", "leco_server_stats_get", "leco_server_stop", "leco_server_replay",
+    "leco_batch_set_shape", "leco_server_start", "leco_server_submit", "leco_server_submit_batch",
+    "leco_server_poll", "leco_server_release", "leco_server_stats_get", "leco_server_stop",
+    "leco_server_replay",
 ]
-LECO_REQ_RANDOM_ACCESS, LECO_REQ_RANGE = 1, 2
+LECO_REQ_RANDOM_ACCESS, LECO_REQ_RANGE, LECO_REQ_RANDOM_ACCESS_DEV = 1, 2, 3
 LECO_BATCH_DECODE, LECO_BATCH_FILTER = 1, 2
 
 
@@ -68,7 +69,7 @@ class ServerConfig(C.Structure):
 
 
 class Request(C.Structure):
-    _fields_ = [("kind", C.c_uint32), ("col", C.c_uint32), ("positions_host", C.c_void_p),
+    _fields_ = [("kind", C.c_uint32), ("col", C.c_uint32), ("positions", C.c_void_p),
                 ("k", C.c_uint64), ("begin", C.c_uint64), ("end", C.c_uint64)]
 
 
@@ -131,6 +132,7 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_batch_set_shape": ([vp, C.c_uint32, C.c_uint32], i32),
         "leco_server_start": ([vp, vp, u64, P(ServerConfig), P(vp)], i32),
         "leco_server_submit": ([vp, P(Request), P(u64)], i32),
+        "leco_server_submit_batch": ([vp, P(Request), u64, P(u64), P(u64)], i32),
         "leco_server_poll": ([vp, vp, u64, P(u64)], i32),
         "leco_server_release": ([vp, u64], i32),
         "leco_server_stats_get": ([vp, P(ServerStats)], i32),
@@ -311,6 +313,16 @@ def leco_server_submit(server: int, req: Request) -> tuple[int, int]:
     st = lib().leco_server_submit(server, C.byref(req), C.byref(t))
     return st, t.value
 
+
+
+def leco_server_submit_batch(server: int, reqs) -> tuple[int, list[int]]:
+    """reqs: a ctypes Request array.  Returns (status, tickets of the
+    accepted prefix)."""
+    n = len(reqs)
+    tickets = (C.c_uint64 * max(n, 1))()
+    acc = C.c_uint64()
+    st = lib().leco_server_submit_batch(server, reqs, n, tickets, C.byref(acc))
+    return st, [int(tickets[i]) for i in range(acc.value)]
 
 def leco_server_poll(server: int, max_n: int = 256) -> list:
     arr = (Completion * max_n)()

@@ -27,9 +27,10 @@ struct ServeCol {
   uint32_t pad;
 };
 
-// One workgroup of a step.  Random access: positions[a, a + b) of the
-// position ring, results to out_off.  Range: values [a, b) of the column (at
-// most one workgroup tile), results to out_off.
+// One workgroup of a step.  Random access: b positions, at index a of the
+// position ring (LECO_REQ_RANDOM_ACCESS) or at device address a
+// (LECO_REQ_RANDOM_ACCESS_DEV), results to out_off.  Range: values [a, b)
+// of the column (at most one workgroup tile), results to out_off.
 struct WorkItem {
   uint32_t kind;
   uint32_t col;
@@ -40,8 +41,11 @@ struct WorkItem {
 constexpr uint32_t kServeTileLog2 = 12;
 constexpr uint64_t kServeTile = uint64_t(1) << kServeTileLog2;
 
-// positions lives in pinned host memory; the lanes of a workgroup read 256
-// consecutive positions, so each wave reads 512 contiguous bytes.
+// The position ring lives in pinned host memory; the lanes of a workgroup
+// read 256 consecutive positions (from the ring or from device memory), so
+// each wave reads 512 contiguous bytes.  Ring positions were checked against
+// n at submission, device positions are checked here: one >= n raises the
+// range flag and gives 0.
 __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restrict__ cols,
                                                        const WorkItem* __restrict__ items,
                                                        const uint64_t* __restrict__ positions,
@@ -56,10 +60,12 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
     return;
   }
   uint8_t* out = arena + it.out_off;
-  if (it.kind == LECO_REQ_RANDOM_ACCESS) {
+  if (it.kind != LECO_REQ_RANGE) {
     const uint64_t i = threadIdx.x;
     if (i >= it.b) return;
-    const uint64_t g = positions[it.a + i];
+    const uint64_t g = it.kind == LECO_REQ_RANDOM_ACCESS
+                           ? positions[it.a + i]
+                           : global_ptr(reinterpret_cast<const uint64_t*>(it.a))[i];
     uint64_t v = 0;
     if (g >= h.n || !lookup_value(c.blob, h, g, v)) raise(err, g >= h.n ? kErrRange : kErrFormat);
     if (h.dtype == 8)
@@ -140,7 +146,7 @@ class Arena {
 struct Pending {
   uint64_t ticket;
   leco_request req;
-  uint64_t pos_off;  // byte offset of the positions in the ring
+  uint64_t pos_off;  // byte offset of the positions in the ring (host positions)
   uint64_t count, out_bytes;
   Clock::time_point t_submit;
 };
@@ -156,7 +162,8 @@ struct Slot {
   hipEvent_t done = nullptr;
   leco::WorkItem* items_host = nullptr;  // pinned
   leco::WorkItem* items_dev = nullptr;
-  bool busy = false;
+  bool busy = false;              // admitted requests, step being built or running
+  bool launched = false;          // the step's completion event is recorded
   leco_status status = LECO_OK;  // EDEVICE if the step's launch failed
   std::vector<Pending> reqs;     // requests the running step completes
   std::vector<uint64_t> offs;
@@ -197,8 +204,8 @@ leco_status sfail(leco_server* s, leco_status st, const char* msg) {
 }
 
 uint64_t step_items(const Pending& p) {
-  return p.req.kind == LECO_REQ_RANDOM_ACCESS ? (p.count + leco::kBlock - 1) / leco::kBlock
-                                              : (p.count + leco::kServeTile - 1) / leco::kServeTile;
+  return p.req.kind != LECO_REQ_RANGE ? (p.count + leco::kBlock - 1) / leco::kBlock
+                                      : (p.count + leco::kServeTile - 1) / leco::kServeTile;
 }
 
 // While a step is running, the next one waits until the queued work that
@@ -213,7 +220,7 @@ bool batch_ready(const leco_server* s) {
   uint64_t bytes = 0, items = 0, pos = 0, admitted = 0;
   for (const Pending& p : s->queue) {
     const uint64_t it = step_items(p);
-    const bool ra = p.req.kind == LECO_REQ_RANDOM_ACCESS;
+    const bool ra = p.req.kind == LECO_REQ_RANDOM_ACCESS;  // positions in the ring
     if (items + it > cfg.max_step_items || (ra && pos + p.count > cfg.max_step_positions) ||
         s->inflight + admitted >= cfg.max_inflight)
       return true;  // the step is full
@@ -228,7 +235,10 @@ bool batch_ready(const leco_server* s) {
 }
 
 // Admits queued requests into a free slot and launches the step.  Called
-// by the worker with s->mu held; returns true if a step was launched.
+// by the worker with s->mu held; admission (memory, slots) happens under the
+// lock, the work items are built and the step launched without it (the slot
+// belongs to the worker until it is marked busy).  Returns true if a step
+// was launched.
 bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
   Slot* slot = nullptr;
   for (size_t i = 0; i < s->slots.size(); ++i) {
@@ -243,36 +253,20 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
   bool any_busy = false;
   for (const Slot& c : s->slots) any_busy = any_busy || c.busy;
   if (any_busy && !batch_ready(s)) return false;
-  uint32_t nitems = 0;
-  uint64_t npos = 0;
+  uint64_t nitems = 0, npos = 0;
   slot->reqs.clear();
   slot->offs.clear();
   while (!s->queue.empty()) {
     Pending& p = s->queue.front();
-    const bool ra = p.req.kind == LECO_REQ_RANDOM_ACCESS;
+    const bool ra = p.req.kind == LECO_REQ_RANDOM_ACCESS;  // positions in the ring
     const uint64_t items = step_items(p);
     if (nitems + items > s->cfg.max_step_items) break;
     if (ra && npos + p.count > s->cfg.max_step_positions) break;
     if (s->inflight >= s->cfg.max_inflight) break;
     uint64_t off = 0;
     if (!s->arena->alloc(p.out_bytes ? p.out_bytes : 1, &off)) break;  // wait for memory
-    const leco::ServeCol& col = s->cols[p.req.col];
-    if (ra) {
-      const uint64_t base = p.pos_off / 8;
-      for (uint64_t i = 0; i < items; ++i) {
-        const uint64_t first = i * leco::kBlock;
-        const uint64_t cnt = p.count - first < uint64_t(leco::kBlock) ? p.count - first : leco::kBlock;
-        slot->items_host[nitems++] = leco::WorkItem{LECO_REQ_RANDOM_ACCESS, p.req.col, base + first,
-                                                    cnt, off + first * col.dtype};
-      }
-      npos += p.count;
-    } else {
-      for (uint64_t g = p.req.begin; g < p.req.end; g += leco::kServeTile) {
-        const uint64_t e = g + leco::kServeTile < p.req.end ? g + leco::kServeTile : p.req.end;
-        slot->items_host[nitems++] = leco::WorkItem{LECO_REQ_RANGE, p.req.col, g, e,
-                                                    off + (g - p.req.begin) * col.dtype};
-      }
-    }
+    nitems += items;
+    if (ra) npos += p.count;
     s->results[p.ticket] = Result{off, p.out_bytes ? p.out_bytes : 1, false};
     ++s->inflight;
     slot->offs.push_back(off);
@@ -281,13 +275,37 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
   }
   if (slot->reqs.empty()) return false;
   s->stats.steps += 1;
+  slot->busy = true;  // keeps other launches off this slot while unlocked
   lk.unlock();
+  uint32_t k = 0;
+  for (size_t r = 0; r < slot->reqs.size(); ++r) {
+    const Pending& p = slot->reqs[r];
+    const uint64_t off = slot->offs[r];
+    const leco::ServeCol& col = s->cols[p.req.col];
+    if (p.req.kind != LECO_REQ_RANGE) {
+      const bool ra = p.req.kind == LECO_REQ_RANDOM_ACCESS;
+      // ring index, or device address, of the request's first position
+      const uint64_t base = ra ? p.pos_off / 8 : reinterpret_cast<uint64_t>(p.req.positions);
+      const uint64_t stride = ra ? 1 : 8;
+      for (uint64_t first = 0; first < p.count; first += leco::kBlock) {
+        const uint64_t cnt = p.count - first < uint64_t(leco::kBlock) ? p.count - first : leco::kBlock;
+        slot->items_host[k++] = leco::WorkItem{p.req.kind, p.req.col, base + first * stride, cnt,
+                                               off + first * col.dtype};
+      }
+    } else {
+      for (uint64_t g = p.req.begin; g < p.req.end; g += leco::kServeTile) {
+        const uint64_t e = g + leco::kServeTile < p.req.end ? g + leco::kServeTile : p.req.end;
+        slot->items_host[k++] = leco::WorkItem{LECO_REQ_RANGE, p.req.col, g, e,
+                                               off + (g - p.req.begin) * col.dtype};
+      }
+    }
+  }
   hipError_t e = hipSuccess;
-  if (nitems) {
-    e = hipMemcpyAsync(slot->items_dev, slot->items_host, sizeof(leco::WorkItem) * nitems,
+  if (k) {
+    e = hipMemcpyAsync(slot->items_dev, slot->items_host, sizeof(leco::WorkItem) * k,
                        hipMemcpyHostToDevice, slot->stream);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(leco::k_serve_step, dim3(nitems), dim3(leco::kBlock), 0, slot->stream,
+      hipLaunchKernelGGL(leco::k_serve_step, dim3(k), dim3(leco::kBlock), 0, slot->stream,
                          s->cols_dev, slot->items_dev, s->ring_dev, s->arena_dev,
                          s->ctx->err_dev);
       e = hipGetLastError();
@@ -298,7 +316,7 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
   if (e != hipSuccess) (void)hipStreamSynchronize(slot->stream);
   lk.lock();
   slot->status = e == hipSuccess ? LECO_OK : LECO_EDEVICE;
-  slot->busy = true;
+  slot->launched = true;
   return true;
 }
 
@@ -307,7 +325,9 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
 bool retire_steps(leco_server* s) {
   bool any = false;
   for (Slot& slot : s->slots) {
-    if (!slot.busy || (slot.status == LECO_OK && hipEventQuery(slot.done) != hipSuccess)) continue;
+    if (!slot.busy || !slot.launched ||
+        (slot.status == LECO_OK && hipEventQuery(slot.done) != hipSuccess))
+      continue;
     const Clock::time_point now = Clock::now();
     for (size_t i = 0; i < slot.reqs.size(); ++i) {
       const Pending& p = slot.reqs[i];
@@ -327,6 +347,7 @@ bool retire_steps(leco_server* s) {
     }
     slot.reqs.clear();
     slot.busy = false;
+    slot.launched = false;
     any = true;
   }
   if (any) s->cv.notify_all();
@@ -436,20 +457,28 @@ leco_status leco_server_start(leco_ctx* ctx, const leco_resident_col* cols, uint
   return LECO_OK;
 }
 
-leco_status leco_server_submit(leco_server* s, const leco_request* r, uint64_t* ticket) {
-  if (!s || !r) return LECO_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Validates one request and, for host positions, reserves ring space and
+// copies the positions into it (checking them on the way).  The request is
+// not queued yet.
+leco_status prepare_request(leco_server* s, const leco_request* r, Pending& p) {
   if (r->col >= s->cols.size()) return sfail(s, LECO_EINVAL, "no such resident column");
   const leco::ServeCol& col = s->cols[r->col];
-  Pending p;
   p.req = *r;
   p.pos_off = 0;
-  const bool ra = r->kind == LECO_REQ_RANDOM_ACCESS;
-  if (ra) {
-    if (r->k && !r->positions_host) return sfail(s, LECO_EINVAL, "positions are null");
-    if (r->k > s->cfg.max_step_positions || Arena::round(8 * r->k) > s->cfg.position_ring_bytes)
+  const bool ring = r->kind == LECO_REQ_RANDOM_ACCESS;
+  if (ring || r->kind == LECO_REQ_RANDOM_ACCESS_DEV) {
+    if (r->k && !r->positions) return sfail(s, LECO_EINVAL, "positions are null");
+    if (ring && (r->k > s->cfg.max_step_positions ||
+                 Arena::round(8 * r->k) > s->cfg.position_ring_bytes))
       return sfail(s, LECO_EINVAL, "more positions than a step or the position ring holds");
-    for (uint64_t i = 0; i < r->k; ++i)
-      if (r->positions_host[i] >= col.n) return sfail(s, LECO_ERANGE, "position >= n");
+    if (!ring && (reinterpret_cast<uintptr_t>(r->positions) & 7))
+      return sfail(s, LECO_EINVAL, "device positions must be 8-byte aligned");
+    if ((r->k + leco::kBlock - 1) / leco::kBlock > s->cfg.max_step_items)
+      return sfail(s, LECO_EINVAL, "more positions than a step holds");
     p.count = r->k;
   } else if (r->kind == LECO_REQ_RANGE) {
     if (r->begin > r->end || r->end > col.n) return sfail(s, LECO_ERANGE, "range outside [0, n)");
@@ -462,20 +491,78 @@ leco_status leco_server_submit(leco_server* s, const leco_request* r, uint64_t* 
   p.out_bytes = p.count * col.dtype;
   if (Arena::round(p.out_bytes) > s->cfg.out_budget_bytes)
     return sfail(s, LECO_ENOSPC, "request larger than the output budget");
-  std::unique_lock<std::mutex> lk(s->mu);
-  if (ra && p.count) {
-    if (!s->ring->alloc(8 * p.count, &p.pos_off))
-      return sfail(s, LECO_ENOMEM, "position ring full: retry after earlier requests complete");
-    memcpy(reinterpret_cast<uint8_t*>(s->ring_host) + p.pos_off, r->positions_host, 8 * p.count);
+  if (ring && p.count) {
+    // Reserve ring space under the lock, then check and copy the positions
+    // without it: the request is invisible to the loop until it is queued.
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (!s->ring->alloc(8 * p.count, &p.pos_off))
+        return sfail(s, LECO_ENOMEM, "position ring full: retry after earlier requests complete");
+    }
+    uint64_t* dst = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(s->ring_host) + p.pos_off);
+    uint64_t bad = 0;
+    for (uint64_t i = 0; i < p.count; ++i) {
+      const uint64_t g = r->positions[i];
+      bad |= uint64_t(g >= col.n);
+      dst[i] = g;
+    }
+    if (bad) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->ring->release(p.pos_off, 8 * p.count);
+      return sfail(s, LECO_ERANGE, "position >= n");
+    }
   }
-  p.t_submit = Clock::now();
-  p.ticket = s->next_ticket++;
-  if (ticket) *ticket = p.ticket;
-  s->stats.submitted += 1;
-  if (ra) s->stats.positions += r->k;
-  s->queue.push_back(p);
-  s->cv.notify_all();
   return LECO_OK;
+}
+
+// Frees a completed request's result memory; s->mu held.
+leco_status release_locked(leco_server* s, uint64_t ticket) {
+  auto it = s->results.find(ticket);
+  if (it == s->results.end() || !it->second.done)
+    return sfail(s, LECO_EINVAL, "ticket is not a completed, unreleased request");
+  s->arena->release(it->second.off, it->second.bytes);
+  s->results.erase(it);
+  --s->inflight;
+  return LECO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+leco_status leco_server_submit_batch(leco_server* s, const leco_request* reqs, uint64_t n,
+                                     uint64_t* tickets, uint64_t* accepted) {
+  if (accepted) *accepted = 0;
+  if (!s || (n && !reqs)) return LECO_EINVAL;
+  const Clock::time_point t_enter = Clock::now();  // latency counts the copies below
+  std::vector<Pending> ready;
+  ready.reserve(n);
+  leco_status st = LECO_OK;
+  for (uint64_t i = 0; i < n; ++i) {
+    Pending p;
+    if ((st = prepare_request(s, &reqs[i], p)) != LECO_OK) break;
+    ready.push_back(p);
+  }
+  if (!ready.empty()) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (uint64_t i = 0; i < ready.size(); ++i) {
+      Pending& p = ready[i];
+      p.t_submit = t_enter;
+      p.ticket = s->next_ticket++;
+      if (tickets) tickets[i] = p.ticket;
+      s->stats.submitted += 1;
+      if (p.req.kind != LECO_REQ_RANGE) s->stats.positions += p.count;
+      s->queue.push_back(p);
+    }
+    s->cv.notify_all();
+  }
+  if (accepted) *accepted = ready.size();
+  return st;
+}
+
+leco_status leco_server_submit(leco_server* s, const leco_request* r, uint64_t* ticket) {
+  if (!s || !r) return LECO_EINVAL;
+  return leco_server_submit_batch(s, r, 1, ticket, nullptr);
 }
 
 leco_status leco_server_poll(leco_server* s, leco_completion* out, uint64_t max, uint64_t* got) {
@@ -493,14 +580,9 @@ leco_status leco_server_poll(leco_server* s, leco_completion* out, uint64_t max,
 leco_status leco_server_release(leco_server* s, uint64_t ticket) {
   if (!s) return LECO_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->results.find(ticket);
-  if (it == s->results.end() || !it->second.done)
-    return sfail(s, LECO_EINVAL, "ticket is not a completed, unreleased request");
-  s->arena->release(it->second.off, it->second.bytes);
-  s->results.erase(it);
-  --s->inflight;
-  s->cv.notify_all();
-  return LECO_OK;
+  const leco_status st = release_locked(s, ticket);
+  if (st == LECO_OK) s->cv.notify_all();
+  return st;
 }
 
 leco_status leco_server_stats_get(leco_server* s, leco_server_stats* out) {
@@ -530,33 +612,54 @@ leco_status leco_server_replay(leco_server* s, const leco_request* reqs, const d
                                uint64_t n, double* latency_us_out, double* elapsed_s) {
   if (!s || (n && (!reqs || !arrival_s))) return LECO_EINVAL;
   std::unordered_map<uint64_t, uint64_t> index;  // ticket -> request number
-  std::vector<leco_completion> buf(256);
+  std::vector<double> lag_us(n, 0.0);            // submission start - scheduled arrival
+  std::vector<leco_completion> buf(1024);
+  std::vector<uint64_t> tickets(1024);
   uint64_t done = 0;
   const Clock::time_point t0 = Clock::now();
   Clock::time_point last = t0;
+  auto due_at = [&](uint64_t i) {
+    return t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+  };
+  // Polls completions and releases their results under one lock.
   auto drain = [&]() {
     uint64_t got = 0;
     leco_server_poll(s, buf.data(), buf.size(), &got);
+    if (!got) return;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (uint64_t i = 0; i < got; ++i) release_locked(s, buf[i].ticket);
+      s->cv.notify_all();
+    }
     for (uint64_t i = 0; i < got; ++i) {
       auto it = index.find(buf[i].ticket);
-      if (it != index.end() && latency_us_out) latency_us_out[it->second] = buf[i].latency_us;
-      leco_server_release(s, buf[i].ticket);
-      ++done;
-      last = Clock::now();
+      if (it != index.end() && latency_us_out)
+        latency_us_out[it->second] = lag_us[it->second] + buf[i].latency_us;
     }
+    done += got;
+    last = Clock::now();
   };
-  for (uint64_t i = 0; i < n; ++i) {
-    const Clock::time_point due =
-        t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
-    while (Clock::now() < due) drain();
-    uint64_t ticket = 0;
-    leco_status st;
-    while ((st = leco_server_submit(s, &reqs[i], &ticket)) == LECO_ENOMEM) {
+  uint64_t i = 0;
+  while (i < n) {
+    while (Clock::now() < due_at(i)) drain();
+    // every request already due goes in one batch
+    const Clock::time_point now = Clock::now();
+    uint64_t j = i + 1;
+    while (j < n && j - i < tickets.size() && due_at(j) <= now) ++j;
+    for (uint64_t q = i; q < j; ++q)
+      // latency runs from the scheduled arrival: the lag until the accepted
+      // submission, plus the server's submit-to-completion time
+      lag_us[q] = std::chrono::duration<double, std::micro>(now - due_at(q)).count();
+    uint64_t accepted = 0;
+    const leco_status st = leco_server_submit_batch(s, reqs + i, j - i, tickets.data(), &accepted);
+    for (uint64_t q = 0; q < accepted; ++q) index[tickets[q]] = i + q;
+    i += accepted;
+    if (st == LECO_ENOMEM) {
       drain();  // the position ring frees as earlier steps finish
       std::this_thread::yield();
+    } else if (st != LECO_OK) {
+      return st;
     }
-    if (st != LECO_OK) return st;
-    index[ticket] = i;
     drain();  // keep releasing results while submitting
   }
   while (done < n) {

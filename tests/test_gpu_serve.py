@@ -80,12 +80,16 @@ def expected(r, hosts):
     return h[r["begin"]: r["end"]]
 
 
-def run_all(torch, codec, server, reqs, release=True):
-    """Submits every request at once and collects results by ticket."""
+def run_all(torch, codec, server, reqs, release=True, built=None):
+    """Submits every request at once (as built Request structs when given)
+    and collects results by ticket."""
     keep, tickets = [], {}
     for i, r in enumerate(reqs):
-        req, pos = to_request(r)
-        keep.append(pos)
+        if built is None:
+            req, pos = to_request(r)
+            keep.append(pos)
+        else:
+            req = built[i]
         st, t = P.leco_server_submit(server, req)
         assert st == P.LECO_OK, P.leco_last_error(codec.ctx)
         tickets[t] = i
@@ -114,6 +118,70 @@ def test_mixed_requests_equal_the_column(torch, codec, columns):
     finally:
         P.leco_server_stop(server)
     assert codec.sync() is None
+
+
+def device_positions(torch, reqs):
+    """Random-access requests with their positions in device memory."""
+    devs = [torch.from_numpy(np.ascontiguousarray(r["positions"], dtype=np.uint64).view(np.int64)).cuda()
+            for r in reqs]
+    torch.cuda.synchronize()
+    built = [P.Request(P.LECO_REQ_RANDOM_ACCESS_DEV, r["col"], d.data_ptr(), d.numel(), 0, 0)
+             for r, d in zip(reqs, devs)]
+    return built, devs
+
+
+def test_device_positions_match_host_positions(torch, codec, columns):
+    """Positions read in place from device memory give the same results as
+    positions copied from host memory, at lane-count edges (1, 255, 256, 257)
+    and across several workgroups, for both widths."""
+    specs, cols, blobs, hosts = columns
+    rng = np.random.default_rng(64)
+    reqs = [dict(kind="ra", col=c, positions=rng.integers(0, specs[c]["n"], size=k, dtype=np.uint64))
+            for c in range(len(specs)) for k in (1, 255, 256, 257, 5000)]
+    reqs[0]["positions"][0] = specs[0]["n"] - 1
+    server = start(codec, columns)
+    try:
+        host = run_all(torch, codec, server, reqs)
+        built, devs = device_positions(torch, reqs)
+        got = run_all(torch, codec, server, reqs, built=built)
+        for i, r in enumerate(reqs):
+            assert np.array_equal(got[i], expected(r, hosts)), f"request {i}"
+            assert np.array_equal(got[i], host[i])
+        # and mixed with ranges and host-position requests in the same steps
+        mix = W.request_mix(80, [s["n"] for s in specs], seed=65, max_log2_k=11, range_exp=(1, 4.5))
+        mb, mdevs, keep = [], [], []
+        for j, r in enumerate(mix):
+            if r["kind"] == "ra" and j % 2:
+                b, d = device_positions(torch, [r])
+                mb.append(b[0])
+                mdevs += d
+            else:
+                req, pos = to_request(r)
+                mb.append(req)
+                keep.append(pos)
+        got = run_all(torch, codec, server, mix, built=mb)
+        for i, r in enumerate(mix):
+            assert np.array_equal(got[i], expected(r, hosts)), f"mixed request {i}"
+    finally:
+        P.leco_server_stop(server)
+    assert codec.sync() is None
+
+
+def test_device_positions_out_of_range_raise_the_flag(torch, codec, columns):
+    specs, cols, blobs, hosts = columns
+    n = specs[1]["n"]
+    reqs = [dict(kind="ra", col=1, positions=np.array([5, n, 7], dtype=np.uint64))]
+    server = start(codec, columns)
+    try:
+        built, devs = device_positions(torch, reqs)
+        got = run_all(torch, codec, server, reqs, built=built)
+        assert got[0][0] == hosts[1][5] and got[0][1] == 0 and got[0][2] == hosts[1][7]
+    finally:
+        P.leco_server_stop(server)
+    with pytest.raises(P.LecoError) as e:
+        codec.sync()
+    assert e.value.status == P.LECO_ERANGE
+    assert codec.sync() is None  # the flag is cleared once reported
 
 
 def test_alone_equals_in_the_mix(torch, codec, columns):
@@ -179,6 +247,40 @@ def test_submit_errors(torch, codec, columns):
         st, _ = P.leco_server_submit(server, P.Request(P.LECO_REQ_RANGE, 0, None, 0, 0, 100_000))
         assert st == P.LECO_ENOSPC
         assert P.leco_server_release(server, 12345) == P.LECO_EINVAL
+    finally:
+        P.leco_server_stop(server)
+
+
+def test_submit_batch_queues_the_accepted_prefix(torch, codec, columns):
+    """One batch call queues requests in order up to the first bad one,
+    whose status it returns; the accepted ones complete normally."""
+    specs, cols, blobs, hosts = columns
+    reqs = W.request_mix(40, [s["n"] for s in specs], seed=66, max_log2_k=10, range_exp=(1, 4))
+    arr = (P.Request * (len(reqs) + 1))()
+    keep = []
+    for i, r in enumerate(reqs[:25]):
+        arr[i], pos = to_request(r)
+        keep.append(pos)
+    arr[25] = P.Request(P.LECO_REQ_RANGE, 0, None, 0, 0, specs[0]["n"] + 1)  # outside [0, n)
+    for i, r in enumerate(reqs[25:]):
+        arr[26 + i], pos = to_request(r)
+        keep.append(pos)
+    server = start(codec, columns)
+    try:
+        st, tickets = P.leco_server_submit_batch(server, arr)
+        assert st == P.LECO_ERANGE and len(tickets) == 25
+        index = {t: i for i, t in enumerate(tickets)}
+        got = {}
+        deadline = time.time() + 30
+        while len(got) < 25:
+            assert time.time() < deadline
+            for c in P.leco_server_poll(server):
+                got[index[c.ticket]] = fetch(torch, codec, c)
+                assert P.leco_server_release(server, c.ticket) == P.LECO_OK
+        for i in range(25):
+            assert np.array_equal(got[i], expected(reqs[i], hosts)), f"request {i}"
+        st, tickets = P.leco_server_submit_batch(server, (P.Request * 0)())
+        assert st == P.LECO_OK and tickets == []
     finally:
         P.leco_server_stop(server)
 
