@@ -88,7 +88,7 @@ def _bind(L: C.CDLL) -> C.CDLL:
     L.leco_ref_partition_cost_bytes.argtypes = [vp, u64, u64]
     L.leco_ref_partition_cost_bytes.restype = u64
     L.leco_ref_partition_greedy.argtypes = [vp, u64, C.c_int, C.c_double, u64, u64, vp, P(u64)]
-    L.leco_ref_partition_merge.argtypes = [vp, u64, C.c_int, vp, P(u64), u64]
+    L.leco_ref_partition_merge.argtypes = [vp, u64, C.c_int, vp, P(u64), u64, u64]
     L.leco_ref_partition_dp.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
     L.leco_ref_partition_bruteforce.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
     L.leco_ref_partitioning_cost.argtypes = [vp, u64, C.c_int, vp, u64, P(u64)]
@@ -248,12 +248,13 @@ def partition_greedy(col: np.ndarray, tau: float = 0.1, sm_bits: int = 320,
     return starts[: m.value + 1].copy()
 
 
-def partition_merge(col: np.ndarray, starts, max_len: int = 1 << 20) -> np.ndarray:
+def partition_merge(col: np.ndarray, starts, max_len: int = 1 << 20,
+                    max_rounds: int = 0) -> np.ndarray:
     col = np.ascontiguousarray(col)
     s = np.array(starts, dtype=np.uint64)
     m = C.c_uint64(len(s) - 1)
     _check("leco_ref_partition_merge", lib().leco_ref_partition_merge(
-        _ptr(col), len(col), _dtype_code(col), _ptr(s), C.byref(m), max_len))
+        _ptr(col), len(col), _dtype_code(col), _ptr(s), C.byref(m), max_len, max_rounds))
     return s[: m.value + 1].copy()
 
 

@@ -609,33 +609,59 @@ static uint64_t *load_column(const void *col, uint64_t n, int dtype) {
   return v;
 }
 
-/* Merge phase: scan left to right; merge a partition with its right
- * neighbour when the merged partition is smaller than the two apart, then
- * retry the merged partition with its new neighbour; repeat full passes
- * until one makes no merge. */
+/* Merge phase, in rounds.  In each round every adjacent pair (j, j+1)
+ * whose union fits max_len has the gain
+ *   g_j = size(j) + size(j+1) - size(j u j+1)   (bytes, may be <= 0),
+ * and pair j is merged when g_j > 0 and its key (g_j, j even) is larger
+ * than the keys of pairs j-1 and j+1 (keys compare the gain first, then
+ * prefer the even pair; neighbouring keys never tie), so the merged pairs
+ * of a round never overlap.  Rounds repeat until one merges nothing, or
+ * max_rounds rounds have run (0: no limit). */
 static void merge_phase(const uint64_t *v, uint64_t *s, uint64_t *m_io,
-                        uint64_t max_len) {
+                        uint64_t max_len, uint64_t max_rounds) {
   uint64_t m = *m_io;
-  int changed = 1;
-  while (changed) {
-    changed = 0;
-    uint64_t j = 0;
-    while (j + 1 < m) {
-      uint64_t a = s[j], b = s[j + 1], c = s[j + 2];
-      int merged = 0;
-      if (c - a <= max_len) {
-        uint64_t apart = leco_ref_partition_cost_bytes(v, a, b) +
-                         leco_ref_partition_cost_bytes(v, b, c);
-        uint64_t joint = leco_ref_partition_cost_bytes(v, a, c);
-        if (joint < apart) {
-          for (uint64_t k = j + 1; k < m; k++) s[k] = s[k + 1];
-          m--;
-          changed = 1;
-          merged = 1;
-        }
-      }
-      if (!merged) j++;
+  for (uint64_t round = 0; max_rounds == 0 || round < max_rounds; round++) {
+    if (m < 2) break;
+    int64_t *gain = (int64_t *)malloc((m - 1) * sizeof(int64_t));
+    unsigned char *take = (unsigned char *)calloc(m - 1, 1);
+    if (!gain || !take) {
+      free(gain);
+      free(take);
+      break; /* the partitioning stays valid, only less merged */
     }
+    for (uint64_t j = 0; j + 1 < m; j++) {
+      uint64_t a = s[j], b = s[j + 1], c = s[j + 2];
+      if (c - a > max_len) {
+        gain[j] = 0;
+        continue;
+      }
+      uint64_t apart = leco_ref_partition_cost_bytes(v, a, b) +
+                       leco_ref_partition_cost_bytes(v, b, c);
+      uint64_t joint = leco_ref_partition_cost_bytes(v, a, c);
+      gain[j] = (int64_t)apart - (int64_t)joint;
+    }
+    uint64_t merges = 0;
+    for (uint64_t j = 0; j + 1 < m; j++) {
+      if (gain[j] <= 0) continue;
+      /* key(j) > key(k) for each neighbouring pair k */
+      int beats_left = j == 0 || gain[j] > gain[j - 1] ||
+                       (gain[j] == gain[j - 1] && j % 2 == 0);
+      int beats_right = j + 2 >= m || gain[j] > gain[j + 1] ||
+                        (gain[j] == gain[j + 1] && j % 2 == 0);
+      if (beats_left && beats_right) {
+        take[j] = 1;
+        merges++;
+      }
+    }
+    /* drop the start of partition j+1 for every merged pair j */
+    uint64_t w = 1;
+    for (uint64_t k = 1; k < m; k++)
+      if (!take[k - 1]) s[w++] = s[k];
+    s[w] = s[m];
+    m = w;
+    free(gain);
+    free(take);
+    if (merges == 0) break;
   }
   *m_io = m;
 }
@@ -654,9 +680,12 @@ int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau
   if (!v) return LREF_ENOMEM;
   double threshold = tau * (double)sm_bits;
 
-  /* Split phase, left to right from position 0: keep the running range of
-   * first differences of the current partition and include v[j] while
-   * C = (len+1) * Delta~new - len * Delta~old <= tau * S_M. */
+  /* Split phase, left to right: keep the running range of first
+   * differences of the current partition and include v[j] while
+   * C = (len+1) * Delta~new - len * Delta~old <= tau * S_M and the partition
+   * stays within max_len.  A partition also begins at every multiple of
+   * 2^20 (the longest partition the format allows), so the split of each
+   * 2^20-value segment depends on that segment alone. */
   uint64_t m = 0;
   uint64_t i = 0;
   starts_out[m++] = 0;
@@ -670,7 +699,7 @@ int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau
     uint64_t w_new = bitlen128((u128)(nmax - nmin));
     uint64_t len = j - i;
     double cost = (double)((int64_t)((len + 1) * w_new) - (int64_t)(len * w_old));
-    if (cost <= threshold && len < max_len) {
+    if (cost <= threshold && len < max_len && j % MAX_PART_LEN != 0) {
       dmin = nmin;
       dmax = nmax;
       have_diff = 1;
@@ -683,19 +712,20 @@ int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau
     }
   }
   starts_out[m] = n;
-  merge_phase(v, starts_out, &m, max_len);
+  merge_phase(v, starts_out, &m, max_len, 0);
   free(v);
   *m_out = m;
   return LREF_OK;
 }
 
 int leco_ref_partition_merge(const void *col, uint64_t n, int dtype,
-                             uint64_t *starts, uint64_t *m, uint64_t max_len) {
+                             uint64_t *starts, uint64_t *m, uint64_t max_len,
+                             uint64_t max_rounds) {
   if ((dtype != 4 && dtype != 8) || max_len == 0 || max_len > MAX_PART_LEN)
     return LREF_EINVAL;
   uint64_t *v = load_column(col, n, dtype);
   if (!v) return LREF_ENOMEM;
-  merge_phase(v, starts, m, max_len);
+  merge_phase(v, starts, m, max_len, max_rounds);
   free(v);
   return LREF_OK;
 }

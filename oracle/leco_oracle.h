@@ -114,15 +114,20 @@ uint64_t leco_ref_delta_partition_bits(const uint64_t *v, uint64_t i,
 uint64_t leco_ref_partition_cost_bytes(const uint64_t *v, uint64_t i,
                                        uint64_t j);
 
-/* Greedy split + merge.  starts_out needs room for n + 1 entries.
- * max_len caps partition length (<= 2^20). */
+/* Greedy split + merge (section 3.2.2).  starts_out needs room for n + 1
+ * entries.  max_len caps partition length (<= 2^20).  The split restarts at
+ * every multiple of 2^20; the merge runs in rounds (see merge below). */
 int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype,
                               double tau, uint64_t sm_bits, uint64_t max_len,
                               uint64_t *starts_out, uint64_t *m_out);
 
-/* Merge phase alone, applied to a given partitioning (in place). */
+/* Merge phase alone, applied to a given partitioning (in place).  Each
+ * round merges every adjacent pair whose size gain is positive and larger
+ * than that of both neighbouring pairs (equal gains: the even pair wins);
+ * rounds repeat until none merges or max_rounds have run (0: no limit). */
 int leco_ref_partition_merge(const void *col, uint64_t n, int dtype,
-                             uint64_t *starts, uint64_t *m, uint64_t max_len);
+                             uint64_t *starts, uint64_t *m, uint64_t max_len,
+                             uint64_t max_rounds);
 
 /* Optimal partitioning by dynamic programming (section 3.2), O(n^3). */
 int leco_ref_partition_dp(const void *col, uint64_t n, int dtype,

@@ -486,6 +486,63 @@ def test_merge_never_increases_size(ref):
     assert set(int(x) for x in merged) <= set(int(x) for x in fine)
 
 
+def test_merge_rounds_on_a_constant_column(ref):
+    """Every partition of a constant column has width 0 and costs one
+    40-byte model (32-byte record + 8-byte start), and so does any union of
+    them: every pair gains exactly 40 bytes.  With all gains equal, a round
+    merges the even pairs (0,1), (2,3), ...; the rounds halve the count
+    until one partition is left."""
+    col = np.full(80, 7, dtype=np.uint64)
+    eight = [0, 10, 20, 30, 40, 50, 60, 70, 80]
+    assert ref.partition_cost_bytes(col, 0, 10) == 40 == ref.partition_cost_bytes(col, 0, 80)
+    assert list(ref.partition_merge(col, eight, max_rounds=1)) == [0, 20, 40, 60, 80]
+    assert list(ref.partition_merge(col, eight, max_rounds=2)) == [0, 40, 80]
+    assert list(ref.partition_merge(col, eight, max_rounds=3)) == [0, 80]
+    assert list(ref.partition_merge(col, eight)) == [0, 80]
+    # seven partitions: pairs 0, 2, 4 merge; the last partition waits
+    seven = [0, 10, 20, 30, 40, 50, 60, 80]
+    assert list(ref.partition_merge(col, seven, max_rounds=1)) == [0, 20, 40, 60, 80]
+    # the cap stops a merge: unions longer than 30 values are not formed
+    assert list(ref.partition_merge(col, eight, max_len=30)) == [0, 20, 40, 60, 80]
+
+
+def test_merge_prefers_the_larger_gain(ref):
+    """Three partitions: a constant run of 7s (20 values), a constant run of
+    9s (20 values) and a constant run of 8s (20 values).  Merging the 7s and
+    9s gives width bitlen(2) = 2 over 40 values: 40 + 8 * ceil(80/64) = 56
+    bytes instead of 80, gain 24.  Merging the 9s and 8s gives width 1: 40 +
+    8 = 48 bytes, gain 32.  Only the larger gain merges in the first round;
+    the second round then merges the rest (width 2 over 60 values: 40 + 16 =
+    56 < 40 + 48 = 88)."""
+    col = np.array([7] * 20 + [9] * 20 + [8] * 20, dtype=np.uint64)
+    starts = [0, 20, 40, 60]
+    assert ref.partition_cost_bytes(col, 0, 40) == 56
+    assert ref.partition_cost_bytes(col, 20, 60) == 48
+    assert list(ref.partition_merge(col, starts, max_rounds=1)) == [0, 20, 60]
+    assert ref.partition_cost_bytes(col, 0, 60) == 56
+    assert list(ref.partition_merge(col, starts)) == [0, 60]
+
+
+def test_merge_fixed_point_has_no_positive_gain(ref):
+    rng = np.random.default_rng(12)
+    col = W.piecewise_linear(4000, 6, segments=10)
+    fine = random_partitioning(rng, len(col), 40)
+    merged = [int(x) for x in ref.partition_merge(col, fine)]
+    for a, b, c in zip(merged, merged[1:], merged[2:]):
+        apart = ref.partition_cost_bytes(col, a, b) + ref.partition_cost_bytes(col, b, c)
+        assert ref.partition_cost_bytes(col, a, c) >= apart
+
+
+def test_split_restarts_at_every_multiple_of_2_20(ref):
+    """A perfectly linear column never triggers a split by cost, so the
+    greedy's partitions are exactly the 2^20-value segments, and merging
+    across a segment boundary would exceed the 2^20 cap."""
+    n = 3 * (1 << 20) + 12345
+    col = np.arange(n, dtype=np.uint64) * np.uint64(3) + np.uint64(11)
+    starts = ref.partition_greedy(col)
+    assert list(starts) == [0, 1 << 20, 2 << 20, 3 << 20, n]
+
+
 def test_greedy_partitions_respect_cap_and_round_trip(ref):
     col = W.constant_runs(20_000, 3)
     starts = ref.partition_greedy(col, max_len=1000)
