@@ -245,6 +245,38 @@ leco_status leco_batch_tune(leco_batch *batch, int op, hipStream_t stream,
 leco_status leco_batch_set_shape(leco_batch *batch, uint32_t tile_log2,
                                  uint32_t blocks_per_cu);
 
+/* ---- Variable-length partitioning (section 3.2.2) --------------------------------
+ * Chooses partition starts for a column on the GPU, for use as
+ * leco_partitioning.starts_host:
+ *   split  left to right, a value joins the current partition while the
+ *          approximate cost C = (len + 1) * D~new - len * D~old of including
+ *          it stays within tau * sm_bits (compared in binary64), where
+ *          D~ = bitlen(max d - min d) over the partition's first differences
+ *          d, and the partition stays within max_len; a partition also
+ *          begins at every multiple of 2^20;
+ *   merge  in rounds: each adjacent pair whose union fits max_len has the
+ *          gain size(j) + size(j+1) - size(union), sizes being the exact
+ *          bytes a partition costs in a variable-length blob (32-byte
+ *          record, 8-byte start, residual words, with the model the encoder
+ *          chooses); a pair merges when its gain is positive and larger than
+ *          both neighbouring pairs' (equal gains: the even pair); rounds
+ *          repeat until one merges nothing or max_rounds have run.
+ * col_dev: n values of dtype in device memory, aligned to the dtype.  On
+ * success starts_host[0..m] holds the starts (starts_host[0] = 0,
+ * starts_host[m] = n) and *m_out = m; LECO_ENOSPC if starts_cap < m + 1
+ * (*m_out still set).  Scratch device memory is allocated and freed by the
+ * call.  [sync] */
+typedef struct {
+  double tau;          /* split threshold factor (the paper's range: 0..0.15) */
+  uint64_t sm_bits;    /* model size S_M in bits (320: record + start)        */
+  uint64_t max_len;    /* longest partition, 1..2^20                          */
+  uint64_t max_rounds; /* merge rounds at most (0: until none merges)         */
+} leco_partition_params;
+
+leco_status leco_partition(leco_ctx *ctx, const void *col_dev, uint64_t n, leco_dtype dtype,
+                           const leco_partition_params *params, uint64_t *starts_host,
+                           uint64_t starts_cap, uint64_t *m_out, hipStream_t stream);
+
 /* ---- Served mode --------------------------------------------------------------
  * Compressed columns stay resident in device memory while a request loop
  * answers point lookups and range scans (the decoder of section 3.3 for "one

@@ -87,7 +87,8 @@ def _bind(L: C.CDLL) -> C.CDLL:
     L.leco_ref_delta_partition_bits.restype = u64
     L.leco_ref_partition_cost_bytes.argtypes = [vp, u64, u64]
     L.leco_ref_partition_cost_bytes.restype = u64
-    L.leco_ref_partition_greedy.argtypes = [vp, u64, C.c_int, C.c_double, u64, u64, vp, P(u64)]
+    L.leco_ref_partition_greedy.argtypes = [vp, u64, C.c_int, C.c_double, u64, u64, u64, vp,
+                                            P(u64)]
     L.leco_ref_partition_merge.argtypes = [vp, u64, C.c_int, vp, P(u64), u64, u64]
     L.leco_ref_partition_dp.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
     L.leco_ref_partition_bruteforce.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
@@ -238,13 +239,13 @@ def partition_cost_bytes(values, i: int, j: int) -> int:
 
 
 def partition_greedy(col: np.ndarray, tau: float = 0.1, sm_bits: int = 320,
-                     max_len: int = 1 << 20) -> np.ndarray:
+                     max_len: int = 1 << 20, max_rounds: int = 0) -> np.ndarray:
     col = np.ascontiguousarray(col)
     starts = np.zeros(len(col) + 1, dtype=np.uint64)
     m = C.c_uint64()
     _check("leco_ref_partition_greedy", lib().leco_ref_partition_greedy(
-        _ptr(col), len(col), _dtype_code(col), tau, sm_bits, max_len, _ptr(starts),
-        C.byref(m)))
+        _ptr(col), len(col), _dtype_code(col), tau, sm_bits, max_len, max_rounds,
+        _ptr(starts), C.byref(m)))
     return starts[: m.value + 1].copy()
 
 

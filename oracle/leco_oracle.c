@@ -668,7 +668,8 @@ static void merge_phase(const uint64_t *v, uint64_t *s, uint64_t *m_io,
 
 int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau,
                               uint64_t sm_bits, uint64_t max_len,
-                              uint64_t *starts_out, uint64_t *m_out) {
+                              uint64_t max_rounds, uint64_t *starts_out,
+                              uint64_t *m_out) {
   if ((dtype != 4 && dtype != 8) || max_len == 0 || max_len > MAX_PART_LEN)
     return LREF_EINVAL;
   if (n == 0) {
@@ -712,7 +713,7 @@ int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau
     }
   }
   starts_out[m] = n;
-  merge_phase(v, starts_out, &m, max_len, 0);
+  merge_phase(v, starts_out, &m, max_len, max_rounds);
   free(v);
   *m_out = m;
   return LREF_OK;

@@ -116,10 +116,12 @@ uint64_t leco_ref_partition_cost_bytes(const uint64_t *v, uint64_t i,
 
 /* Greedy split + merge (section 3.2.2).  starts_out needs room for n + 1
  * entries.  max_len caps partition length (<= 2^20).  The split restarts at
- * every multiple of 2^20; the merge runs in rounds (see merge below). */
+ * every multiple of 2^20; the merge runs in rounds (see merge below), at
+ * most max_rounds of them (0: until none merges). */
 int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype,
                               double tau, uint64_t sm_bits, uint64_t max_len,
-                              uint64_t *starts_out, uint64_t *m_out);
+                              uint64_t max_rounds, uint64_t *starts_out,
+                              uint64_t *m_out);
 
 /* Merge phase alone, applied to a given partitioning (in place).  Each
  * round merges every adjacent pair whose size gain is positive and larger

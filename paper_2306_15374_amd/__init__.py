@@ -31,7 +31,7 @@ EXPORTS = [
     "leco_batch_destroy", "leco_batch_run", "leco_batch_run_graph", "leco_batch_tune",
     "leco_batch_set_shape", "leco_server_start", "leco_server_submit", "leco_server_submit_batch",
     "leco_server_poll", "leco_server_release", "leco_server_stats_get", "leco_server_stop",
-    "leco_server_replay",
+    "leco_server_replay", "leco_partition",
 ]
 LECO_REQ_RANDOM_ACCESS, LECO_REQ_RANGE, LECO_REQ_RANDOM_ACCESS_DEV = 1, 2, 3
 LECO_BATCH_DECODE, LECO_BATCH_FILTER = 1, 2
@@ -41,6 +41,11 @@ class LecoError(RuntimeError):
     def __init__(self, fn: str, status: int, detail: str = ""):
         super().__init__(f"{fn}: {STATUS_NAMES.get(status, status)} {detail}".strip())
         self.status = status
+
+
+class PartitionParams(C.Structure):
+    _fields_ = [("tau", C.c_double), ("sm_bits", C.c_uint64), ("max_len", C.c_uint64),
+                ("max_rounds", C.c_uint64)]
 
 
 class EncodeJob(C.Structure):
@@ -138,6 +143,7 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_server_stats_get": ([vp, P(ServerStats)], i32),
         "leco_server_stop": ([vp], i32),
         "leco_server_replay": ([vp, vp, vp, u64, vp, P(C.c_double)], i32),
+        "leco_partition": ([vp, vp, u64, i32, P(PartitionParams), vp, u64, P(u64), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -359,6 +365,15 @@ def leco_server_replay(server: int, reqs, arrival_s, latencies_out=None) -> tupl
     return st, el.value
 
 
+def leco_partition(ctx: int, col, n: int, dtype: int, params: PartitionParams,
+                   starts_out, stream=None) -> tuple[int, int]:
+    """starts_out: a uint64 numpy array with room for m + 1 starts."""
+    m = C.c_uint64()
+    st = lib().leco_partition(ctx, _ptr(col), n, dtype, C.byref(params), starts_out.ctypes.data,
+                              len(starts_out), C.byref(m), _stream(stream))
+    return st, m.value
+
+
 # ---- convenience wrapper --------------------------------------------------------------
 
 class Codec:
@@ -400,6 +415,22 @@ class Codec:
         del keep
         self.check("leco_encode", st)
         return buf[:size]
+
+    def partition(self, col, tau: float = 0.1, sm_bits: int = 320, max_len: int = 1 << 20,
+                  max_rounds: int = 0, stream=None):
+        """Variable-length partition starts of a CUDA tensor column (numpy
+        uint64 array of m + 1 starts)."""
+        import numpy as np
+        params = PartitionParams(tau, sm_bits, max_len, max_rounds)
+        cap = 1024
+        while True:
+            out = np.zeros(cap, dtype=np.uint64)
+            st, m = leco_partition(self.ctx, col, col.numel(), _dtype_code(col), params, out, stream)
+            if st == LECO_ENOSPC and m + 1 > cap:
+                cap = m + 1
+                continue
+            self.check("leco_partition", st)
+            return out[: m + 1].copy()
 
     def info(self, blob):
         return leco_blob_info(bytes(blob[:64].cpu().numpy().tobytes()))

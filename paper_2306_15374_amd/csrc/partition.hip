@@ -1,0 +1,491 @@
+// Variable-length partitioner (section 3.2.2) on the GPU.
+//
+// Split: the greedy of the paper, which includes the next value in the
+// current partition while the approximate cost of doing so,
+//   C = (len + 1) * D~new - len * D~old,  D~ = bitlen(max d - min d)
+// over the partition's first differences d, stays within tau * S_M.  A
+// partition begins at every multiple of 2^20 (the format's longest
+// partition), so each 2^20-value segment is split on its own by one
+// wavefront.  The wavefront tries 64 candidates at a time: lane l assumes
+// that the values before its own are all included, takes the inclusive
+// prefix min / max of the first differences over the lanes below it, and
+// evaluates C; the first lane that fails starts the next partition and the
+// lanes after it are retried from there.  This reproduces the sequential
+// greedy exactly.
+//
+// Merge: rounds over adjacent pairs.  Every pair's union is sized with the
+// encoder's own fit (exact bytes: 32-byte record, 8-byte start, residual
+// words); a pair merges when its gain is positive and beats both
+// neighbouring pairs (equal gains: the even pair), so merged pairs never
+// overlap; rounds repeat until one merges nothing.
+#include <math.h>
+
+#include <utility>
+#include <vector>
+
+#include "fit.hpp"
+#include "internal.hpp"
+#include "leco_dev.hpp"
+
+namespace leco {
+
+constexpr uint32_t kSegLog2 = 20;
+constexpr uint32_t kSplitWindow = 4096;  // values staged in LDS per window
+constexpr uint32_t kScanBlock = 256;
+constexpr uint32_t kItemsPerBlock = 1024;  // bitmap words or flags per scan block
+constexpr uint64_t kNoMerge = ~uint64_t(0);
+
+// A first difference d = v_j - v_{j-1} of (up to) 64-bit values as the
+// 65-bit unsigned number d + 2^64 = (hi, lo), which orders like d.
+struct DKey {
+  uint32_t hi;
+  uint64_t lo;
+};
+
+__device__ inline bool key_less(const DKey& a, const DKey& b) {
+  return a.hi != b.hi ? a.hi < b.hi : a.lo < b.lo;
+}
+
+__device__ inline DKey key_shfl_up(const DKey& k, int delta) {
+  DKey r;
+  r.hi = uint32_t(__shfl_up(int(k.hi), delta, 64));
+  r.lo = uint64_t(__shfl_up(static_cast<unsigned long long>(k.lo), delta, 64));
+  return r;
+}
+
+__device__ inline DKey key_readlane(const DKey& k, int lane) {
+  DKey r;
+  r.hi = uint32_t(__shfl(int(k.hi), lane, 64));
+  r.lo = uint64_t(__shfl(static_cast<unsigned long long>(k.lo), lane, 64));
+  return r;
+}
+
+// bitlen(max - min) of two keys (at most 65).
+__device__ inline uint32_t key_span_bits(const DKey& mn, const DKey& mx) {
+  const uint64_t lo = mx.lo - mn.lo;
+  const uint32_t hi = mx.hi - mn.hi - (mx.lo < mn.lo ? 1u : 0u);
+  return hi ? 65u : bitlen64(lo);
+}
+
+__device__ inline void mark(unsigned long long* bitmap, uint64_t j) {
+  atomicOr(bitmap + (j >> 6), 1ull << (j & 63));
+}
+
+// One 64-lane workgroup per 2^20-value segment; sets the bit of every
+// partition start in the bitmap (cleared by the caller).
+__global__ __launch_bounds__(64) void k_split(const uint8_t* __restrict__ col, uint32_t dtype,
+                                              uint64_t n, double thr, uint64_t max_len,
+                                              unsigned long long* __restrict__ bitmap) {
+  __shared__ uint64_t win[kSplitWindow + 1];  // win[k] = v[base - 1 + k]
+  const uint32_t lane = threadIdx.x;
+  const uint64_t a = uint64_t(blockIdx.x) << kSegLog2;
+  if (a >= n) return;
+  const uint64_t b = n - a < (uint64_t(1) << kSegLog2) ? n : a + (uint64_t(1) << kSegLog2);
+  if (lane == 0) mark(bitmap, a);
+  uint64_t i = a;     // first value of the current partition
+  bool have = false;  // whether it holds a first difference yet
+  DKey kmin{0, 0}, kmax{0, 0};
+  uint32_t w_old = 0;  // D~ of the current partition
+  uint64_t base = 0, wend = 0;  // the window holds v[base - 1, wend)
+  uint64_t p = a + 1;           // next candidate value
+  while (p < b) {
+    const uint64_t need = p + 64 < b ? p + 64 : b;
+    if (wend < need) {
+      __syncthreads();  // every lane is done with the old window
+      base = p;
+      wend = b - p < kSplitWindow ? b : p + kSplitWindow;
+      for (uint64_t k = lane; k <= wend - base; k += 64)
+        win[k] = load_value(col, dtype, base - 1 + k);
+      __syncthreads();
+    }
+    const uint64_t j = p + lane;
+    const bool valid = j < b;
+    DKey d{0, 0};
+    if (valid) {
+      const uint64_t vj = win[j - base + 1], vp = win[j - base];
+      d.lo = vj - vp;
+      d.hi = vj >= vp ? 1u : 0u;
+    }
+    // inclusive prefix min / max over the lanes up to this one; the invalid
+    // lanes are the last ones and never feed a valid lane
+    DKey mn = d, mx = d;
+#pragma unroll
+    for (int delta = 1; delta < 64; delta <<= 1) {
+      const DKey lo = key_shfl_up(mn, delta), hi = key_shfl_up(mx, delta);
+      if (int(lane) >= delta) {
+        if (key_less(lo, mn)) mn = lo;
+        if (key_less(mx, hi)) mx = hi;
+      }
+    }
+    if (have) {
+      if (key_less(kmin, mn)) mn = kmin;
+      if (key_less(mx, kmax)) mx = kmax;
+    }
+    const uint32_t w_new = key_span_bits(mn, mx);
+    uint32_t w_prev = uint32_t(__shfl_up(int(w_new), 1, 64));
+    if (lane == 0) w_prev = w_old;
+    const uint64_t len = j - i;
+    const int64_t cost = int64_t((len + 1) * w_new) - int64_t(len * w_prev);
+    const bool include = double(cost) <= thr && len < max_len;
+    const uint64_t split = __ballot(valid && !include);
+    if (split == 0) {
+      const int last = int(b - p - 1 < 63 ? b - p - 1 : 63);
+      kmin = key_readlane(mn, last);
+      kmax = key_readlane(mx, last);
+      w_old = uint32_t(__shfl(int(w_new), last, 64));
+      have = true;
+      p += uint64_t(last) + 1;
+    } else {
+      const uint64_t js = p + uint64_t(__ffsll(static_cast<long long>(split)) - 1);
+      if (lane == 0) mark(bitmap, js);
+      i = js;
+      have = false;
+      w_old = 0;
+      p = js + 1;
+    }
+  }
+}
+
+// ---- block-wide scan of counts -------------------------------------------------
+
+// Exclusive prefix sum of x over the workgroup's threads; *total receives
+// the workgroup sum.
+__device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* total) {
+  __shared__ uint32_t wsum[kScanBlock / 64];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int delta = 1; delta < 64; delta <<= 1) {
+    const uint32_t y = uint32_t(__shfl_up(int(inc), delta, 64));
+    if (int(lane) >= delta) inc += y;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kScanBlock / 64; ++w) {
+    if (w < wave) before += wsum[w];
+    all += wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - x;
+}
+
+// Set bits of bitmap words [blockIdx * 1024, +1024).
+__global__ __launch_bounds__(kScanBlock) void k_bitmap_count(const uint64_t* __restrict__ bitmap,
+                                                             uint64_t nwords,
+                                                             uint64_t* __restrict__ counts) {
+  const uint64_t w0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (w0 + k < nwords) c += uint32_t(__popcll(bitmap[w0 + k]));
+  uint32_t total;
+  block_exclusive_scan(c, &total);
+  if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// Writes the positions of the set bits, in order, from starts[offsets[block]].
+__global__ __launch_bounds__(kScanBlock) void k_bitmap_emit(const uint64_t* __restrict__ bitmap,
+                                                            uint64_t nwords,
+                                                            const uint64_t* __restrict__ offsets,
+                                                            uint64_t* __restrict__ starts) {
+  const uint64_t w0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
+  uint64_t words[4];
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    words[k] = w0 + k < nwords ? bitmap[w0 + k] : 0;
+    c += uint32_t(__popcll(words[k]));
+  }
+  uint32_t total;
+  uint64_t out = offsets[blockIdx.x] + block_exclusive_scan(c, &total);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint64_t w = words[k];
+    while (w) {
+      const int bit = __ffsll(static_cast<long long>(w)) - 1;
+      starts[out++] = (w0 + k) * 64 + uint64_t(bit);
+      w &= w - 1;
+    }
+  }
+}
+
+// ---- sizes -----------------------------------------------------------------------
+
+struct FitShared {
+  uint64_t red[kEncWaves][4];
+  double theta1;
+};
+
+// Bytes that the partition v[s, e) costs in a variable-length blob: its
+// 32-byte record, its 8-byte start and its residual words, with the model
+// the encoder would choose.  Called by every thread of the workgroup.
+__device__ uint64_t range_cost(FitShared& sh, const uint8_t* col, uint32_t dtype, uint64_t s,
+                               uint64_t e) {
+  const uint64_t len = e - s;
+  const uint8_t* src = col + s * dtype;
+  uint64_t vmin = ~uint64_t(0), vmax = 0;
+  U128 sv{0, 0}, stv{0, 0};
+  for (uint64_t t = threadIdx.x; t < len; t += kEncBlock) {
+    const uint64_t x = load_value(src, dtype, t);
+    vmin = x < vmin ? x : vmin;
+    vmax = x > vmax ? x : vmax;
+    sv = add128(sv, U128{x, 0});
+    stv = add128(stv, mul64x64(t, x));
+  }
+  block_minmax_u64(sh, vmin, vmax);
+  const uint64_t range = vmax - vmin;
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  if (len > 1 && range < (uint64_t(1) << 61)) {
+    block_sum_u128x2(sh, sv, stv);
+    const double th = block_slope(sh, len, sv, stv);
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+    for (uint64_t t = threadIdx.x; t < len; t += kEncBlock) {
+      const int64_t rr = int64_t(load_value(src, dtype, t) - vmin) - predict(th, uint32_t(t));
+      rmin = rr < rmin ? rr : rmin;
+      rmax = rr > rmax ? rr : rmax;
+    }
+    block_minmax_i64(sh, rmin, rmax);
+    choose_model(md, th, rmin, rmax);
+  }
+  return kRecordBytes + 8 + 8 * ((len * md.bits + 63) >> 6);
+}
+
+// out[j] = cost of v[starts[j], starts[j + span]) for j < count, or kNoMerge
+// when that is longer than max_len.
+__global__ __launch_bounds__(kEncBlock) void k_costs(const uint8_t* __restrict__ col,
+                                                     uint32_t dtype,
+                                                     const uint64_t* __restrict__ starts,
+                                                     uint64_t count, uint32_t span,
+                                                     uint64_t max_len, uint64_t* __restrict__ out) {
+  __shared__ FitShared sh;
+  for (uint64_t j = blockIdx.x; j < count; j += gridDim.x) {
+    const uint64_t s = starts[j], e = starts[j + span];
+    const uint64_t c = e - s > max_len ? kNoMerge : range_cost(sh, col, dtype, s, e);
+    if (threadIdx.x == 0) out[j] = c;
+  }
+}
+
+// ---- merge rounds ----------------------------------------------------------------
+
+__device__ inline int64_t pair_gain(const uint64_t* cost, const uint64_t* pair, uint64_t j) {
+  return pair[j] == kNoMerge ? 0 : int64_t(cost[j] + cost[j + 1]) - int64_t(pair[j]);
+}
+
+// key(j) > key(k): larger gain, or the same gain and j even.
+__device__ inline bool beats(int64_t gj, int64_t gk, uint64_t j) {
+  return gj > gk || (gj == gk && (j & 1) == 0);
+}
+
+// take[j] = 1 when pair j merges this round (j < m - 1); counts the merges.
+__global__ void k_select(const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair,
+                         uint64_t m, uint8_t* __restrict__ take,
+                         unsigned long long* __restrict__ merges) {
+  const uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j + 1 >= m) return;
+  const int64_t g = pair_gain(cost, pair, j);
+  bool t = g > 0;
+  if (t && j > 0) t = beats(g, pair_gain(cost, pair, j - 1), j);
+  if (t && j + 2 < m) t = beats(g, pair_gain(cost, pair, j + 1), j);
+  take[j] = t ? 1 : 0;
+  if (t) atomicAdd(merges, 1ull);
+}
+
+// Partition k survives unless the pair (k - 1, k) merged.
+__device__ inline uint32_t kept(const uint8_t* take, uint64_t k, uint64_t m) {
+  return k < m && (k == 0 || !take[k - 1]) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_keep_count(const uint8_t* __restrict__ take,
+                                                           uint64_t m,
+                                                           uint64_t* __restrict__ counts) {
+  const uint64_t k0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
+  uint32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c += kept(take, k0 + q, m);
+  uint32_t total;
+  block_exclusive_scan(c, &total);
+  if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// Copies the surviving starts (and their costs: a merged pair's union cost
+// for the partition that absorbed its neighbour) to their new places.
+__global__ __launch_bounds__(kScanBlock) void k_keep_emit(
+    const uint8_t* __restrict__ take, uint64_t m, const uint64_t* __restrict__ offsets,
+    const uint64_t* __restrict__ starts, const uint64_t* __restrict__ cost,
+    const uint64_t* __restrict__ pair, uint64_t* __restrict__ starts_out,
+    uint64_t* __restrict__ cost_out) {
+  const uint64_t k0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
+  uint32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c += kept(take, k0 + q, m);
+  uint32_t total;
+  uint64_t out = offsets[blockIdx.x] + block_exclusive_scan(c, &total);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint64_t k = k0 + q;
+    if (!kept(take, k, m)) continue;
+    starts_out[out] = starts[k];
+    cost_out[out] = (k + 1 < m && take[k]) ? pair[k] : cost[k];
+    ++out;
+  }
+}
+
+}  // namespace leco
+
+// ---- host side ------------------------------------------------------------------
+
+namespace {
+
+// Device buffers of one call, freed on every exit path.
+struct Buffers {
+  std::vector<void*> ptrs;
+  ~Buffers() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  bool alloc(T** p, uint64_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, count ? count * sizeof(T) : sizeof(T)) != hipSuccess) return false;
+    ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return true;
+  }
+};
+
+leco_status pfail(leco_ctx* ctx, leco_status st, const char* msg) {
+  ctx->last_error = msg;
+  return st;
+}
+
+// Exclusive scan of per-block counts on the host (a few thousand entries).
+hipError_t scan_counts(uint64_t* counts_dev, uint64_t nblocks, uint64_t* total,
+                       hipStream_t stream) {
+  std::vector<uint64_t> c(nblocks);
+  hipError_t e = hipMemcpyAsync(c.data(), counts_dev, 8 * nblocks, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return e;
+  uint64_t run = 0;
+  for (uint64_t i = 0; i < nblocks; ++i) {
+    const uint64_t x = c[i];
+    c[i] = run;
+    run += x;
+  }
+  *total = run;
+  e = hipMemcpyAsync(counts_dev, c.data(), 8 * nblocks, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // c is freed on return
+  return e;
+}
+
+}  // namespace
+
+#define P_TRY(call)                                                  \
+  do {                                                               \
+    const hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return pfail(ctx, LECO_EDEVICE, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" {
+
+leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_dtype dtype,
+                           const leco_partition_params* prm, uint64_t* starts_host,
+                           uint64_t starts_cap, uint64_t* m_out, hipStream_t stream) {
+  if (!ctx) return LECO_EINVAL;
+  if (!prm || !m_out || (dtype != LECO_U32 && dtype != LECO_U64))
+    return pfail(ctx, LECO_EINVAL, "partition: null argument or bad dtype");
+  if (prm->max_len == 0 || prm->max_len > leco::kMaxPartLen || !(prm->tau == prm->tau))
+    return pfail(ctx, LECO_EINVAL, "partition: max_len outside 1..2^20 or tau NaN");
+  if (n && (!col_dev || (reinterpret_cast<uintptr_t>(col_dev) & (uint64_t(dtype) - 1))))
+    return pfail(ctx, LECO_EINVAL, "partition: null or misaligned column");
+  if (starts_cap && !starts_host) return pfail(ctx, LECO_EINVAL, "partition: null starts buffer");
+  *m_out = 0;
+  if (n == 0) {
+    if (starts_cap < 1) return pfail(ctx, LECO_ENOSPC, "partition: starts buffer too small");
+    starts_host[0] = 0;
+    return LECO_OK;
+  }
+  P_TRY(hipSetDevice(ctx->device));
+  const uint8_t* col = static_cast<const uint8_t*>(col_dev);
+  const uint32_t w = uint32_t(dtype);
+  const double thr = prm->tau * double(prm->sm_bits);
+  Buffers buf;
+
+  // split: bitmap of partition starts
+  const uint64_t nwords = (n + 63) / 64;
+  const uint64_t nseg = (n + (uint64_t(1) << leco::kSegLog2) - 1) >> leco::kSegLog2;
+  unsigned long long* bitmap = nullptr;
+  if (!buf.alloc(&bitmap, nwords)) return pfail(ctx, LECO_ENOMEM, "partition: bitmap");
+  P_TRY(hipMemsetAsync(bitmap, 0, 8 * nwords, stream));
+  hipLaunchKernelGGL(leco::k_split, dim3(uint32_t(nseg)), dim3(64), 0, stream, col, w, n, thr,
+                     prm->max_len, bitmap);
+  P_TRY(hipGetLastError());
+
+  // starts from the bitmap
+  const uint64_t nb = (nwords + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
+  uint64_t* counts = nullptr;
+  if (!buf.alloc(&counts, nb)) return pfail(ctx, LECO_ENOMEM, "partition: counts");
+  hipLaunchKernelGGL(leco::k_bitmap_count, dim3(uint32_t(nb)), dim3(leco::kScanBlock), 0, stream,
+                     reinterpret_cast<const uint64_t*>(bitmap), nwords, counts);
+  P_TRY(hipGetLastError());
+  uint64_t m = 0;
+  P_TRY(scan_counts(counts, nb, &m, stream));
+  uint64_t *starts = nullptr, *starts2 = nullptr, *cost = nullptr, *cost2 = nullptr,
+           *pair = nullptr, *keep_counts = nullptr;
+  uint8_t* take = nullptr;
+  unsigned long long* merges = nullptr;
+  const uint64_t nbk = (m + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
+  if (!buf.alloc(&starts, m + 1) || !buf.alloc(&starts2, m + 1) || !buf.alloc(&cost, m) ||
+      !buf.alloc(&cost2, m) || !buf.alloc(&pair, m) || !buf.alloc(&take, m) ||
+      !buf.alloc(&keep_counts, nbk) || !buf.alloc(&merges, 1))
+    return pfail(ctx, LECO_ENOMEM, "partition: partition arrays");
+  hipLaunchKernelGGL(leco::k_bitmap_emit, dim3(uint32_t(nb)), dim3(leco::kScanBlock), 0, stream,
+                     reinterpret_cast<const uint64_t*>(bitmap), nwords, counts, starts);
+  P_TRY(hipGetLastError());
+  P_TRY(hipMemcpyAsync(starts + m, &n, 8, hipMemcpyHostToDevice, stream));
+
+  // merge rounds
+  const uint64_t grid_cap = uint64_t(ctx->num_cus) * 16;
+  auto costs = [&](const uint64_t* s, uint64_t count, uint32_t span, uint64_t* out) {
+    const uint64_t g = count < grid_cap ? count : grid_cap;
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(leco::k_costs, dim3(uint32_t(g)), dim3(leco::kEncBlock), 0, stream, col, w,
+                       s, count, span, prm->max_len, out);
+    return hipGetLastError();
+  };
+  P_TRY(costs(starts, m, 1, cost));
+  for (uint64_t round = 0; prm->max_rounds == 0 || round < prm->max_rounds; ++round) {
+    if (m < 2) break;
+    P_TRY(costs(starts, m - 1, 2, pair));
+    P_TRY(hipMemsetAsync(merges, 0, 8, stream));
+    hipLaunchKernelGGL(leco::k_select, dim3(uint32_t((m - 1 + 255) / 256)), dim3(256), 0, stream,
+                       cost, pair, m, take, merges);
+    P_TRY(hipGetLastError());
+    unsigned long long merged = 0;
+    P_TRY(hipMemcpyAsync(&merged, merges, 8, hipMemcpyDeviceToHost, stream));
+    P_TRY(hipStreamSynchronize(stream));
+    if (merged == 0) break;
+    const uint64_t blocks = (m + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
+    hipLaunchKernelGGL(leco::k_keep_count, dim3(uint32_t(blocks)), dim3(leco::kScanBlock), 0,
+                       stream, take, m, keep_counts);
+    P_TRY(hipGetLastError());
+    uint64_t m2 = 0;
+    P_TRY(scan_counts(keep_counts, blocks, &m2, stream));
+    hipLaunchKernelGGL(leco::k_keep_emit, dim3(uint32_t(blocks)), dim3(leco::kScanBlock), 0,
+                       stream, take, m, keep_counts, starts, cost, pair, starts2, cost2);
+    P_TRY(hipGetLastError());
+    P_TRY(hipMemcpyAsync(starts2 + m2, &n, 8, hipMemcpyHostToDevice, stream));
+    P_TRY(hipStreamSynchronize(stream));  // &n stays valid; the next round reads starts2
+    std::swap(starts, starts2);
+    std::swap(cost, cost2);
+    m = m2;
+  }
+  *m_out = m;
+  if (starts_cap < m + 1) return pfail(ctx, LECO_ENOSPC, "partition: starts buffer too small");
+  P_TRY(hipMemcpyAsync(starts_host, starts, 8 * (m + 1), hipMemcpyDeviceToHost, stream));
+  P_TRY(hipStreamSynchronize(stream));
+  return LECO_OK;
+}
+
+}  // extern "C"

@@ -146,7 +146,8 @@ def test_every_launch_shape_gives_identical_results(torch, codec):
                 check_outputs(torch, specs, cols, outs, sums, bounds)
         st, tl, bpc = P.leco_batch_tune(batch, 3)
         codec.check("leco_batch_tune", st)
-        assert tl in (0, 12, 13, 14) and bpc in (0, 4, 8)
+        # one workgroup per tile, or a persistent grid of the resident count
+        assert tl in (0, 12, 13, 14) and 0 <= bpc <= 64
         codec.check("leco_batch_run", P.leco_batch_run(batch, 3))
         codec.sync()
         check_outputs(torch, specs, cols, outs, sums, bounds)

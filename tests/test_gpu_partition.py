@@ -1,0 +1,105 @@
+"""GPU variable-length partitioner (section 3.2.2) against the oracle's
+greedy split + merge rounds: identical partition starts (integer work:
+exact), on the column shapes of the variable-partition workloads, both
+widths, first differences beyond 64 bits, several thresholds and caps, and
+columns longer than one 2^20-value split segment."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2306_15374_amd as P
+from paper_2306_15374_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def codec(torch):
+    c = P.Codec(0)
+    yield c
+    c.close()
+
+
+def check(torch, codec, ref, col: np.ndarray, name: str, **kw):
+    log(f"[partition] {name}: n={len(col)} dtype={col.dtype} {kw}")
+    expect = ref.partition_greedy(col, **kw)
+    got = codec.partition(torch.from_numpy(np.ascontiguousarray(col)).cuda(), **kw)
+    assert len(got) == len(expect), f"{name}: m {len(got) - 1} != {len(expect) - 1}"
+    if not np.array_equal(got, expect):
+        bad = np.flatnonzero(got != expect)
+        raise AssertionError(f"{name}: {len(bad)} starts differ, first at {bad[0]}: "
+                             f"{got[bad[0]]} != {expect[bad[0]]}")
+    return got
+
+
+@pytest.mark.parametrize("kind", ["sorted_normal", "piecewise_linear", "constant_runs"])
+def test_workload_shapes(torch, codec, ref, kind):
+    n = 200_000
+    col = {"sorted_normal": lambda: W.sorted_normal(n, W.C3_SEEDS[0]),
+           "piecewise_linear": lambda: W.piecewise_linear(n, W.C3_SEEDS[1], segments=50),
+           "constant_runs": lambda: W.constant_runs(n, W.C3_SEEDS[2])}[kind]()
+    starts = check(torch, codec, ref, col, kind)
+    # the GPU starts encode to the oracle's bytes and decode back
+    blob = codec.encode(torch.from_numpy(col).cuda(), starts=starts)
+    assert np.array_equal(blob.cpu().numpy(), ref.encode(col, starts=starts))
+
+
+def test_thresholds_caps_and_widths(torch, codec, ref):
+    rng = np.random.default_rng(71)
+    noise = W.linear_noise(50_000, 72)
+    keys32 = W.lognormal_keys(50_000, 73, np.uint32)
+    check(torch, codec, ref, noise, "noise tau 0", tau=0.0)
+    check(torch, codec, ref, noise, "noise tau 0.15", tau=0.15)
+    check(torch, codec, ref, noise, "noise sm 64", sm_bits=64)
+    check(torch, codec, ref, keys32, "keys u32 cap 1000", max_len=1000)
+    check(torch, codec, ref, keys32, "keys u32 cap 1", max_len=1)
+    check(torch, codec, ref, keys32[:3000], "keys u32 cap 7 tau 0.05", max_len=7, tau=0.05)
+    # first differences spanning more than 64 bits (v alternating near 0 and 2^64)
+    wide = rng.integers(0, 2**64 - 1, 20_000, dtype=np.uint64, endpoint=True)
+    wide[::3] = rng.integers(0, 16, len(wide[::3]), dtype=np.uint64)
+    wide[1::3] = np.uint64(2**64 - 1) - rng.integers(0, 16, len(wide[1::3]), dtype=np.uint64)
+    check(torch, codec, ref, wide, "65-bit differences")
+    mixed = np.concatenate([W.piecewise_linear(30_000, 74, segments=20),
+                            rng.integers(0, 2**40, 5_000, dtype=np.uint64),
+                            np.full(10_000, 123456789, dtype=np.uint64)])
+    check(torch, codec, ref, mixed, "mixed regimes")
+
+
+def test_merge_round_limits(torch, codec, ref):
+    col = W.piecewise_linear(60_000, 75, segments=30)
+    for r in (1, 2, 3):
+        check(torch, codec, ref, col, f"max_rounds {r}", max_rounds=r)
+
+
+def test_tiny_columns(torch, codec, ref):
+    for n in (1, 2, 3, 63, 64, 65, 127, 4097):
+        col = W.lognormal_keys(n, 76 + n)
+        check(torch, codec, ref, col, f"n={n}")
+    empty = codec.partition(torch.zeros(0, dtype=torch.int64, device="cuda"))
+    assert list(empty) == [0]
+
+
+def test_longer_than_one_segment(torch, codec, ref):
+    """Several 2^20-value split segments, a ragged last one, and merges that
+    would cross a segment boundary only when the union fits 2^20."""
+    n = 2 * (1 << 20) + 70_001
+    col = W.sorted_normal(n, 77)
+    check(torch, codec, ref, col, "sorted normal, 3 segments")
+    runs = W.constant_runs(n, 78)
+    check(torch, codec, ref, runs, "constant runs, 3 segments")
