@@ -422,7 +422,9 @@ class Codec:
         uint64 array of m + 1 starts)."""
         import numpy as np
         params = PartitionParams(tau, sm_bits, max_len, max_rounds)
-        cap = 1024
+        # room for a mean partition length down to 16; a finer result is
+        # computed again with the exact size
+        cap = max(1024, col.numel() // 16 + 2)
         while True:
             out = np.zeros(cap, dtype=np.uint64)
             st, m = leco_partition(self.ctx, col, col.numel(), _dtype_code(col), params, out, stream)

@@ -57,8 +57,8 @@ template <bool kStore, bool kFilter>
 __global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restrict__ cols,
                                                          const uint32_t* __restrict__ tile_col,
                                                          uint64_t total_tiles, int* err) {
-  __shared__ uint4 stage_v[kWavesPerBlock * kWaveStageWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveStageWords;
+  __shared__ uint4 stage_v[kWavesPerBlock * kWaveSlotWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveSlotWords;
   for (uint64_t k = blockIdx.x; k < total_tiles; k += gridDim.x) {
     const DecCol& c = cols[tile_col[k]];
     Header h;

@@ -39,8 +39,8 @@ __global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ b
                                                    uint64_t begin, uint64_t end, uint64_t out_cap,
                                                    uint32_t tile_log2, uint64_t num_tiles, int all,
                                                    int remap, int* err) {
-  __shared__ uint4 stage_v[kWavesPerBlock * kWaveStageWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveStageWords;
+  __shared__ uint4 stage_v[kWavesPerBlock * kWaveSlotWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveSlotWords;
   Header h;
   if (!load_header(blob, blob_bytes, h)) {
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
@@ -170,8 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict
                                                        uint64_t blob_bytes, uint64_t lo,
                                                        uint64_t hi, uint64_t* out3,
                                                        uint32_t tile_log2, int prune, int* err) {
-  __shared__ uint4 stage_v[kWavesPerBlock * kWaveStageWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveStageWords;
+  __shared__ uint4 stage_v[kWavesPerBlock * kWaveSlotWords / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveSlotWords;
   Header h;
   if (!load_header(blob, blob_bytes, h)) {
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);

@@ -17,10 +17,18 @@ namespace leco {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = kBlock / kWave;
-// 32-bit words of LDS per wavefront: 1024 words of residuals (1024 values
+// 32-bit words of LDS per wavefront for residuals: 1024 words (1024 values
 // at up to 32 bits) plus slack for the alignment of the first load and the
 // two words read past a field.
 constexpr uint32_t kWaveStageWords = 1024 + 16;
+// A piece of a tile covers at most this many partitions; their records sit
+// in LDS after the residual words while the piece is decoded.
+constexpr uint32_t kPieceSegs = 16;
+struct PieceRec {
+  uint64_t start, end, base, theta_bits, word_off, bits;
+};
+// LDS per wavefront: residual words, then the piece's records.
+constexpr uint32_t kWaveSlotWords = kWaveStageWords + kPieceSegs * sizeof(PieceRec) / 4;
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
 // Wavefront index, read from the first lane so the compiler treats it (and
@@ -150,59 +158,116 @@ __device__ inline void stage_words(const uint32_t* __restrict__ words32, uint64_
   for (uint32_t i = lane_id(); i < nvec; i += kWave) dst[i] = src[i];
 }
 
-constexpr uint32_t kMaxTileSegments = 64;
+// A value the wavefront holds in every lane, moved to scalar registers.
+__device__ inline uint64_t uniform_u64(uint64_t x) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x >> 32))));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// Lane k's value of x, k uniform across the wavefront.
+__device__ inline uint64_t lane_u64(uint64_t x, uint32_t k) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), int(k)));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), int(k)));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// Partition holding g (as locate), searched by the whole wavefront: each
+// round probes 64 evenly spaced starts at once, so a variable-length blob
+// of m partitions needs about log_65(m) dependent loads instead of
+// log_2(m).  Fixed lengths are located arithmetically.
+__device__ inline uint64_t locate_wave(const uint8_t* blob, const Header& h, uint64_t g) {
+  if (!h.variable) return locate(blob, h, g);
+  const MetaPtr s = meta_words(blob, h.starts_off);
+  const uint32_t lane = lane_id();
+  uint64_t lo = 0, hi = h.m;  // the last start <= g lies in [lo, hi)
+  while (hi - lo > kWave) {
+    const uint64_t q = lo + (hi - lo) * (lane + 1) / (kWave + 1);  // lo < q < hi
+    const uint64_t below = __ballot(s[q] <= g);
+    const uint32_t c = uint32_t(__popcll(below & (~0ull >> (64 - kWave))));
+    const uint64_t q_lo = lane_u64(q, c ? c - 1 : 0), q_hi = lane_u64(q, c < kWave ? c : 0);
+    if (c) lo = q_lo;
+    if (c < kWave) hi = q_hi;
+  }
+  const uint64_t q = lo + lane;
+  const uint64_t below = __ballot(q < hi && s[q] <= g);
+  const uint32_t c = uint32_t(__popcll(below));
+  return c ? lo + c - 1 : lo;
+}
 
 // Decodes one wavefront tile [g0, g1) of a blob into the sink.  Returns
 // false if the blob failed validation (the caller raises the flag); all
 // control flow is uniform across the wavefront.
 //
-// When the sink visits every segment (Sink::kWholeTile) and the words of
-// all segments fit the slice, they are staged in one round trip; otherwise
-// each segment is staged and decoded in chunks on its own.
+// When the sink visits every segment (Sink::kWholeTile) the tile goes in
+// pieces of up to kPieceSegs partitions: lane k loads and checks the
+// record of the piece's k-th partition (one round trip for all of them)
+// and parks it in the wavefront's LDS slot, the residual words of the whole
+// piece are staged in one round trip, and the segments are decoded from
+// the stage one after the other.  A piece whose words do not fit the slot,
+// and every tile of a sink that may skip segments, is decoded segment by
+// segment in chunks instead.
 template <class Sink>
 __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, uint64_t g0,
                             uint64_t g1, uint32_t* stage, Sink& sink) {
-  const uint64_t j0 = locate(blob, h, g0);
+  uint64_t j0 = locate_wave(blob, h, g0);
   const uint32_t* words32 = reinterpret_cast<const uint32_t*>(blob + h.words_off);
   if (Sink::kWholeTile) {
-    uint64_t j = j0, g = g0, span_lo = 0, span_hi = 0;
-    uint32_t nseg = 0;
-    bool one_round = true;
-    while (g < g1) {
-      Part p;
-      if (!load_part(blob, h, j, p)) return false;
-      if (g < p.start || g - p.start >= p.len) return false;
-      const uint64_t seg_end = (p.start + p.len < g1) ? p.start + p.len : g1;
-      uint64_t ws, we;
-      word_span(p, uint32_t(g - p.start), uint32_t(seg_end - p.start), ws, we);
-      if (nseg == 0) span_lo = ws;
-      else if (ws < span_hi) one_round = false;  // spans must follow each other
-      if (we > span_hi) span_hi = we;
-      g = seg_end;
-      ++j;
-      if (++nseg >= kMaxTileSegments && g < g1) {
-        one_round = false;
-        break;
-      }
-    }
-    const uint64_t a0 = span_lo & ~uint64_t(3);
-    if (one_round && span_hi - a0 + 8 <= kWaveStageWords) {
+    const uint32_t lane = lane_id();
+    PieceRec* table = reinterpret_cast<PieceRec*>(stage + kWaveStageWords);
+    while (g0 < g1) {
+      // lane k < kPieceSegs: partition j0 + k, a segment of the piece if it
+      // starts before g1
+      const uint64_t jl = j0 + lane;
+      const bool want =
+          lane < kPieceSegs && jl < h.m && (lane == 0 || part_start(blob, h, jl) < g1);
+      Part lp{0, 0, 0, 0.0, 0, 0};
+      const bool ok = want && load_part(blob, h, jl, lp);
+      if (__ballot(want && !ok)) return false;
+      const uint64_t segs = __ballot(want);
+      const uint32_t nseg = uint32_t(__popcll(segs));
+      if (nseg == 0 || segs != (~0ull >> (64 - nseg))) return false;  // starts must increase
+      const uint64_t end_l = lp.start + lp.len;
+      if (g0 < lane_u64(lp.start, 0) || g0 >= lane_u64(end_l, 0)) return false;
+      // the piece [g0, ge): its segments' residual word spans must follow
+      // each other for one staging round trip (partitions are contiguous by
+      // construction, each length coming from the next start; the spans
+      // are contiguous only in a valid blob)
+      const uint64_t last_end = lane_u64(end_l, nseg - 1);
+      const uint64_t ge = last_end < g1 ? last_end : g1;
+      const uint64_t t0 = (g0 > lp.start ? g0 : lp.start) - lp.start;
+      const uint64_t t1 = (ge < end_l ? ge : end_l) - lp.start;
+      uint64_t ws = 0, we = 0;
+      if (want) word_span(lp, uint32_t(t0), uint32_t(t1), ws, we);
+      const uint64_t prev_we = uint64_t(__shfl_up(static_cast<unsigned long long>(we), 1, kWave));
+      const bool gap = want && lane > 0 && ws < prev_we;
+      const uint64_t span_lo = lane_u64(ws, 0), span_hi = lane_u64(we, nseg - 1);
+      const uint64_t a0 = span_lo & ~uint64_t(3);
+      if (__ballot(gap) || span_hi - a0 + 8 > kWaveStageWords) break;  // chunked path
+      if (want)
+        table[lane] = PieceRec{lp.start, end_l, lp.base, uint64_t(__double_as_longlong(lp.theta1)),
+                               lp.word_off, lp.bits};
       if (span_hi > span_lo) stage_words(words32, a0, span_hi, stage);
       wave_sync();
-      j = j0;
-      g = g0;
-      while (g < g1) {
+      for (uint32_t k = 0; k < nseg; ++k) {
+        const PieceRec r = table[k];
         Part p;
-        load_part(blob, h, j, p);  // validated above
-        const uint64_t seg_end = (p.start + p.len < g1) ? p.start + p.len : g1;
+        p.start = uniform_u64(r.start);
+        p.len = uniform_u64(r.end) - p.start;
+        p.base = uniform_u64(r.base);
+        p.theta1 = __longlong_as_double(static_cast<long long>(uniform_u64(r.theta_bits)));
+        p.word_off = uniform_u64(r.word_off);
+        p.bits = uint32_t(uniform_u64(r.bits));
+        const uint64_t s0 = g0 > p.start ? g0 : p.start;
+        const uint64_t s1 = ge < p.start + p.len ? ge : p.start + p.len;
         const int64_t qoff = int64_t(64 * p.word_off) - int64_t(32 * a0);
-        decode_values(p, uint32_t(g - p.start), uint32_t(seg_end - p.start), qoff, stage, sink);
-        g = seg_end;
-        ++j;
+        decode_values(p, uint32_t(s0 - p.start), uint32_t(s1 - p.start), qoff, stage, sink);
       }
       wave_sync();
-      return true;
+      g0 = ge;
+      j0 += nseg;
     }
+    if (g0 >= g1) return true;
   }
   uint64_t j = j0;
   while (g0 < g1) {

@@ -5,13 +5,14 @@
 //   C = (len + 1) * D~new - len * D~old,  D~ = bitlen(max d - min d)
 // over the partition's first differences d, stays within tau * S_M.  A
 // partition begins at every multiple of 2^20 (the format's longest
-// partition), so each 2^20-value segment is split on its own by one
-// wavefront.  The wavefront tries 64 candidates at a time: lane l assumes
-// that the values before its own are all included, takes the inclusive
-// prefix min / max of the first differences over the lanes below it, and
-// evaluates C; the first lane that fails starts the next partition and the
-// lanes after it are retried from there.  This reproduces the sequential
-// greedy exactly.
+// partition), so each 2^20-value segment is split on its own.  Within a
+// segment, every 2^14-value sub-chunk is first split speculatively in
+// parallel, as if a partition began at its start; one wavefront per
+// segment then walks the sub-chunks in order from the true state, each
+// until the true run starts a partition where the speculative run did
+// (from there on the two runs are the same), rewriting the starts it
+// passes.  The wavefront walks 64 candidates at a time (see greedy_walk).
+// This reproduces the sequential greedy exactly.
 //
 // Merge: rounds over adjacent pairs.  Every pair's union is sized with the
 // encoder's own fit (exact bytes: 32-byte record, 8-byte start, residual
@@ -30,7 +31,8 @@
 namespace leco {
 
 constexpr uint32_t kSegLog2 = 20;
-constexpr uint32_t kSplitWindow = 4096;  // values staged in LDS per window
+constexpr uint32_t kSubLog2 = 14;  // speculative split sub-chunks of a segment
+constexpr uint32_t kSplitWindow = 1024;  // values staged in LDS per window
 constexpr uint32_t kScanBlock = 256;
 constexpr uint32_t kItemsPerBlock = 1024;  // bitmap words or flags per scan block
 constexpr uint64_t kNoMerge = ~uint64_t(0);
@@ -71,23 +73,54 @@ __device__ inline void mark(unsigned long long* bitmap, uint64_t j) {
   atomicOr(bitmap + (j >> 6), 1ull << (j & 63));
 }
 
-// One 64-lane workgroup per 2^20-value segment; sets the bit of every
-// partition start in the bitmap (cleared by the caller).
-__global__ __launch_bounds__(64) void k_split(const uint8_t* __restrict__ col, uint32_t dtype,
-                                              uint64_t n, double thr, uint64_t max_len,
-                                              unsigned long long* __restrict__ bitmap) {
-  __shared__ uint64_t win[kSplitWindow + 1];  // win[k] = v[base - 1 + k]
-  const uint32_t lane = threadIdx.x;
-  const uint64_t a = uint64_t(blockIdx.x) << kSegLog2;
-  if (a >= n) return;
-  const uint64_t b = n - a < (uint64_t(1) << kSegLog2) ? n : a + (uint64_t(1) << kSegLog2);
-  if (lane == 0) mark(bitmap, a);
-  uint64_t i = a;     // first value of the current partition
-  bool have = false;  // whether it holds a first difference yet
-  DKey kmin{0, 0}, kmax{0, 0};
-  uint32_t w_old = 0;  // D~ of the current partition
+// The greedy's state: the current partition's first value i, and whether
+// it has first differences yet with their min / max keys and D~.
+struct SplitState {
+  uint64_t i;
+  uint64_t kmin_lo, kmax_lo;
+  uint32_t kmin_hi, kmax_hi;
+  uint32_t w_old, have;
+};
+
+// Clears bits [x, y) of the bitmap (y - x <= 128, so at most three words).
+__device__ inline void clear_bits(unsigned long long* bitmap, uint64_t x, uint64_t y) {
+  while (x < y) {
+    const uint64_t w = x >> 6;
+    const uint64_t hi = (y - (w << 6)) < 64 ? y - (w << 6) : 64;  // bit bound in word w
+    const uint64_t lo = x & 63;
+    const uint64_t mask = (hi == 64 ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
+    atomicAnd(bitmap + w, ~mask);
+    x = (w + 1) << 6;
+  }
+}
+
+__device__ inline bool bit_set(unsigned long long* bitmap, uint64_t j) {
+  const unsigned long long word =
+      __hip_atomic_load(bitmap + (j >> 6), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (word >> (j & 63)) & 1ull;
+}
+
+// Runs the greedy over candidates [p, b) from state st, 64 candidates per
+// step: lane l assumes the values before its own are all included, takes
+// the inclusive prefix min / max of the first differences over the lanes
+// below it and evaluates C; the first lane that fails starts the next
+// partition and the lanes after it are retried from there.
+//
+// kFix = false: sets the bit of every start.  kFix = true: the bits in
+// [p, b) are a speculative run's, made from a different state; the walk
+// rewrites them until it starts a partition where the speculative run also
+// did (from there on both runs are the same), returning true at that point.
+template <bool kFix>
+__device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t p,
+                            uint64_t b, double thr, uint64_t max_len, SplitState& st,
+                            uint64_t* win, unsigned long long* __restrict__ bitmap) {
+  const uint32_t lane = threadIdx.x & 63;
+  DKey kmin{st.kmin_hi, st.kmin_lo}, kmax{st.kmax_hi, st.kmax_lo};
+  uint64_t i = st.i;
+  bool have = st.have != 0;
+  uint32_t w_old = st.w_old;
   uint64_t base = 0, wend = 0;  // the window holds v[base - 1, wend)
-  uint64_t p = a + 1;           // next candidate value
+  bool synced = false;
   while (p < b) {
     const uint64_t need = p + 64 < b ? p + 64 : b;
     if (wend < need) {
@@ -130,6 +163,7 @@ __global__ __launch_bounds__(64) void k_split(const uint8_t* __restrict__ col, u
     const uint64_t split = __ballot(valid && !include);
     if (split == 0) {
       const int last = int(b - p - 1 < 63 ? b - p - 1 : 63);
+      if (kFix && lane == 0) clear_bits(bitmap, p, p + uint64_t(last) + 1);
       kmin = key_readlane(mn, last);
       kmax = key_readlane(mx, last);
       w_old = uint32_t(__shfl(int(w_new), last, 64));
@@ -137,12 +171,73 @@ __global__ __launch_bounds__(64) void k_split(const uint8_t* __restrict__ col, u
       p += uint64_t(last) + 1;
     } else {
       const uint64_t js = p + uint64_t(__ffsll(static_cast<long long>(split)) - 1);
-      if (lane == 0) mark(bitmap, js);
+      if (kFix) {
+        bool hit = false;
+        if (lane == 0) {
+          clear_bits(bitmap, p, js);
+          hit = bit_set(bitmap, js);
+          if (!hit) mark(bitmap, js);
+        }
+        synced = __ballot(hit) != 0;
+      } else if (lane == 0) {
+        mark(bitmap, js);
+      }
       i = js;
       have = false;
       w_old = 0;
       p = js + 1;
+      if (synced) break;
     }
+  }
+  st.i = i;
+  st.have = have ? 1u : 0u;
+  st.kmin_hi = kmin.hi;
+  st.kmin_lo = kmin.lo;
+  st.kmax_hi = kmax.hi;
+  st.kmax_lo = kmax.lo;
+  st.w_old = w_old;
+  return synced;
+}
+
+// Speculative split: one 64-lane workgroup per 2^kSubLog2-value sub-chunk
+// of a 2^20-value segment.  Sub-chunk 0 begins at the segment start, where
+// a partition really begins; the others begin a partition at their own
+// start, which the fix-up pass corrects.  Each records its final state.
+__global__ __launch_bounds__(64) void k_split_spec(const uint8_t* __restrict__ col,
+                                                   uint32_t dtype, uint64_t n, double thr,
+                                                   uint64_t max_len,
+                                                   unsigned long long* __restrict__ bitmap,
+                                                   SplitState* __restrict__ states) {
+  __shared__ uint64_t win[kSplitWindow + 1];  // win[k] = v[base - 1 + k]
+  const uint64_t a = uint64_t(blockIdx.x) << kSubLog2;
+  if (a >= n) return;
+  const uint64_t b = n - a < (uint64_t(1) << kSubLog2) ? n : a + (uint64_t(1) << kSubLog2);
+  if (threadIdx.x == 0) mark(bitmap, a);
+  SplitState st{a, 0, 0, 0, 0, 0, 0};
+  greedy_walk<false>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap);
+  if (threadIdx.x == 0) states[blockIdx.x] = st;
+}
+
+// Fix-up: one workgroup per 2^20-value segment walks its sub-chunks in
+// order, each from the true state the previous one ends in, until its
+// starts meet the speculative ones.
+__global__ __launch_bounds__(64) void k_split_fix(const uint8_t* __restrict__ col,
+                                                  uint32_t dtype, uint64_t n, double thr,
+                                                  uint64_t max_len,
+                                                  unsigned long long* __restrict__ bitmap,
+                                                  const SplitState* __restrict__ states) {
+  __shared__ uint64_t win[kSplitWindow + 1];
+  constexpr uint64_t kSubs = uint64_t(1) << (kSegLog2 - kSubLog2);
+  const uint64_t a = uint64_t(blockIdx.x) << kSegLog2;
+  if (a >= n) return;
+  const uint64_t q0 = uint64_t(blockIdx.x) * kSubs;
+  SplitState st = states[q0];  // sub-chunk 0 began where a partition begins
+  for (uint64_t q = 1; q < kSubs; ++q) {
+    const uint64_t aq = a + (q << kSubLog2);
+    if (aq >= n) break;
+    const uint64_t bq = n - aq < (uint64_t(1) << kSubLog2) ? n : aq + (uint64_t(1) << kSubLog2);
+    const bool synced = greedy_walk<true>(col, dtype, aq, bq, thr, max_len, st, win, bitmap);
+    if (synced) st = states[q0 + q];  // the speculative run's end state is the true one
   }
 }
 
@@ -253,17 +348,147 @@ __device__ uint64_t range_cost(FitShared& sh, const uint8_t* col, uint32_t dtype
   return kRecordBytes + 8 + 8 * ((len * md.bits + 63) >> 6);
 }
 
-// out[j] = cost of v[starts[j], starts[j + span]) for j < count, or kNoMerge
-// when that is longer than max_len.
+// Ranges up to kLaneRangeMax values are sized by one lane, up to
+// kWaveRangeMax by one wavefront, longer ones by a whole workgroup.
+constexpr uint64_t kLaneRangeMax = 32;
+constexpr uint64_t kWaveRangeMax = 8192;
+
+// range_cost computed by one lane alone.
+__device__ uint64_t range_cost_lane(const uint8_t* col, uint32_t dtype, uint64_t s, uint64_t e) {
+  const uint64_t len = e - s;
+  const uint8_t* src = col + s * dtype;
+  uint64_t vmin = ~uint64_t(0), vmax = 0;
+  U128 sv{0, 0}, stv{0, 0};
+  for (uint64_t t = 0; t < len; ++t) {
+    const uint64_t x = load_value(src, dtype, t);
+    vmin = x < vmin ? x : vmin;
+    vmax = x > vmax ? x : vmax;
+    sv = add128(sv, U128{x, 0});
+    stv = add128(stv, mul64x64(t, x));
+  }
+  const uint64_t range = vmax - vmin;
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  if (len > 1 && range < (uint64_t(1) << 61)) {
+    const double th = ls_slope(len, sv, stv);
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+    for (uint64_t t = 0; t < len; ++t) {
+      const int64_t rr = int64_t(load_value(src, dtype, t) - vmin) - predict(th, uint32_t(t));
+      rmin = rr < rmin ? rr : rmin;
+      rmax = rr > rmax ? rr : rmax;
+    }
+    choose_model(md, th, rmin, rmax);
+  }
+  return kRecordBytes + 8 + 8 * ((len * md.bits + 63) >> 6);
+}
+
+// The ranges of at most kLaneRangeMax values (and the ones too long to
+// merge): one lane each.
+__global__ __launch_bounds__(kEncBlock) void k_costs_short(const uint8_t* __restrict__ col,
+                                                           uint32_t dtype,
+                                                           const uint64_t* __restrict__ starts,
+                                                           uint64_t count, uint32_t span,
+                                                           uint64_t max_len,
+                                                           const uint8_t* __restrict__ dirty,
+                                                           uint64_t* __restrict__ out) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < count; j += stride) {
+    if (dirty && !dirty[j]) continue;
+    const uint64_t s = starts[j], e = starts[j + span];
+    if (e - s > max_len) out[j] = kNoMerge;
+    else if (e - s <= kLaneRangeMax) out[j] = range_cost_lane(col, dtype, s, e);
+  }
+}
+
+// Wavefront-wide reductions (every lane receives the result).
+__device__ inline void wave_minmax_u64(uint64_t& mn, uint64_t& mx) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const uint64_t a = shfl_xor64(mn, m), b = shfl_xor64(mx, m);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+}
+
+__device__ inline void wave_sum_u128x2(U128& x, U128& y) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    x = add128(x, U128{shfl_xor64(x.lo, m), shfl_xor64(x.hi, m)});
+    y = add128(y, U128{shfl_xor64(y.lo, m), shfl_xor64(y.hi, m)});
+  }
+}
+
+// range_cost computed by one wavefront alone (no workgroup barrier), the
+// same arithmetic in the same order of operations where it matters: the
+// sums are exact and the slope is one function of them.
+__device__ uint64_t range_cost_wave(const uint8_t* col, uint32_t dtype, uint64_t s, uint64_t e) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t len = e - s;
+  const uint8_t* src = col + s * dtype;
+  uint64_t vmin = ~uint64_t(0), vmax = 0;
+  U128 sv{0, 0}, stv{0, 0};
+  for (uint64_t t = lane; t < len; t += 64) {
+    const uint64_t x = load_value(src, dtype, t);
+    vmin = x < vmin ? x : vmin;
+    vmax = x > vmax ? x : vmax;
+    sv = add128(sv, U128{x, 0});
+    stv = add128(stv, mul64x64(t, x));
+  }
+  wave_minmax_u64(vmin, vmax);
+  const uint64_t range = vmax - vmin;
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  if (len > 1 && range < (uint64_t(1) << 61)) {
+    wave_sum_u128x2(sv, stv);
+    const double th = ls_slope(len, sv, stv);
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+    for (uint64_t t = lane; t < len; t += 64) {
+      const int64_t rr = int64_t(load_value(src, dtype, t) - vmin) - predict(th, uint32_t(t));
+      rmin = rr < rmin ? rr : rmin;
+      rmax = rr > rmax ? rr : rmax;
+    }
+    // order-preserving map of int64 onto uint64 for the unsigned reduction
+    uint64_t a = uint64_t(rmin) ^ (1ull << 63), b = uint64_t(rmax) ^ (1ull << 63);
+    wave_minmax_u64(a, b);
+    choose_model(md, th, int64_t(a ^ (1ull << 63)), int64_t(b ^ (1ull << 63)));
+  }
+  return kRecordBytes + 8 + 8 * ((len * md.bits + 63) >> 6);
+}
+
+// out[j] = cost of v[starts[j], starts[j + span]) for j < count (only
+// where dirty[j], if dirty is given), or kNoMerge when that is longer than
+// max_len: one wavefront per range of more than kLaneRangeMax and at most
+// kWaveRangeMax values; the others are left to k_costs_short and
+// k_costs_long.
 __global__ __launch_bounds__(kEncBlock) void k_costs(const uint8_t* __restrict__ col,
                                                      uint32_t dtype,
                                                      const uint64_t* __restrict__ starts,
                                                      uint64_t count, uint32_t span,
-                                                     uint64_t max_len, uint64_t* __restrict__ out) {
+                                                     uint64_t max_len,
+                                                     const uint8_t* __restrict__ dirty,
+                                                     uint64_t* __restrict__ out) {
+  const uint64_t waves = uint64_t(gridDim.x) * kEncWaves;
+  for (uint64_t j = uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6); j < count; j += waves) {
+    if (dirty && !dirty[j]) continue;
+    const uint64_t s = starts[j], e = starts[j + span];
+    if (e - s > max_len || e - s <= kLaneRangeMax || e - s > kWaveRangeMax) continue;
+    const uint64_t c = range_cost_wave(col, dtype, s, e);
+    if ((threadIdx.x & 63) == 0) out[j] = c;
+  }
+}
+
+// The ranges k_costs left: one workgroup each.
+__global__ __launch_bounds__(kEncBlock) void k_costs_long(const uint8_t* __restrict__ col,
+                                                          uint32_t dtype,
+                                                          const uint64_t* __restrict__ starts,
+                                                          uint64_t count, uint32_t span,
+                                                          uint64_t max_len,
+                                                          const uint8_t* __restrict__ dirty,
+                                                          uint64_t* __restrict__ out) {
   __shared__ FitShared sh;
   for (uint64_t j = blockIdx.x; j < count; j += gridDim.x) {
+    if (dirty && !dirty[j]) continue;
     const uint64_t s = starts[j], e = starts[j + span];
-    const uint64_t c = e - s > max_len ? kNoMerge : range_cost(sh, col, dtype, s, e);
+    if (e - s > max_len || e - s <= kWaveRangeMax) continue;
+    const uint64_t c = range_cost(sh, col, dtype, s, e);
     if (threadIdx.x == 0) out[j] = c;
   }
 }
@@ -316,7 +541,8 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_emit(
     const uint8_t* __restrict__ take, uint64_t m, const uint64_t* __restrict__ offsets,
     const uint64_t* __restrict__ starts, const uint64_t* __restrict__ cost,
     const uint64_t* __restrict__ pair, uint64_t* __restrict__ starts_out,
-    uint64_t* __restrict__ cost_out) {
+    uint64_t* __restrict__ cost_out, uint8_t* __restrict__ changed_out,
+    uint64_t* __restrict__ old_out) {
   const uint64_t k0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
   uint32_t c = 0;
 #pragma unroll
@@ -327,10 +553,27 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_emit(
   for (int q = 0; q < 4; ++q) {
     const uint64_t k = k0 + q;
     if (!kept(take, k, m)) continue;
+    const bool absorbed = k + 1 < m && take[k];
     starts_out[out] = starts[k];
-    cost_out[out] = (k + 1 < m && take[k]) ? pair[k] : cost[k];
+    cost_out[out] = absorbed ? pair[k] : cost[k];
+    changed_out[out] = absorbed ? 1 : 0;
+    old_out[out] = k;
     ++out;
   }
+}
+
+// After a round: the pair (k, k+1) of the new partitions keeps its union
+// cost when neither partition absorbed a neighbour (they were adjacent
+// before, as old partitions old[k] and old[k] + 1); the others are marked
+// for sizing.
+__global__ void k_pair_reuse(uint64_t m, const uint8_t* __restrict__ changed,
+                             const uint64_t* __restrict__ old, const uint64_t* __restrict__ pair,
+                             uint64_t* __restrict__ pair_out, uint8_t* __restrict__ dirty) {
+  const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k + 1 >= m) return;
+  const bool fresh = changed[k] || changed[k + 1];
+  if (!fresh) pair_out[k] = pair[old[k]];
+  dirty[k] = fresh ? 1 : 0;
 }
 
 }  // namespace leco
@@ -418,8 +661,14 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   unsigned long long* bitmap = nullptr;
   if (!buf.alloc(&bitmap, nwords)) return pfail(ctx, LECO_ENOMEM, "partition: bitmap");
   P_TRY(hipMemsetAsync(bitmap, 0, 8 * nwords, stream));
-  hipLaunchKernelGGL(leco::k_split, dim3(uint32_t(nseg)), dim3(64), 0, stream, col, w, n, thr,
-                     prm->max_len, bitmap);
+  const uint64_t nsub = (n + (uint64_t(1) << leco::kSubLog2) - 1) >> leco::kSubLog2;
+  leco::SplitState* states = nullptr;
+  if (!buf.alloc(&states, nsub)) return pfail(ctx, LECO_ENOMEM, "partition: split states");
+  hipLaunchKernelGGL(leco::k_split_spec, dim3(uint32_t(nsub)), dim3(64), 0, stream, col, w, n,
+                     thr, prm->max_len, bitmap, states);
+  P_TRY(hipGetLastError());
+  hipLaunchKernelGGL(leco::k_split_fix, dim3(uint32_t(nseg)), dim3(64), 0, stream, col, w, n, thr,
+                     prm->max_len, bitmap, states);
   P_TRY(hipGetLastError());
 
   // starts from the bitmap
@@ -432,12 +681,14 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   uint64_t m = 0;
   P_TRY(scan_counts(counts, nb, &m, stream));
   uint64_t *starts = nullptr, *starts2 = nullptr, *cost = nullptr, *cost2 = nullptr,
-           *pair = nullptr, *keep_counts = nullptr;
-  uint8_t* take = nullptr;
+           *pair = nullptr, *pair2 = nullptr, *old = nullptr, *keep_counts = nullptr;
+  uint8_t *take = nullptr, *changed = nullptr, *dirty = nullptr;
   unsigned long long* merges = nullptr;
   const uint64_t nbk = (m + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
   if (!buf.alloc(&starts, m + 1) || !buf.alloc(&starts2, m + 1) || !buf.alloc(&cost, m) ||
-      !buf.alloc(&cost2, m) || !buf.alloc(&pair, m) || !buf.alloc(&take, m) ||
+      !buf.alloc(&cost2, m) || !buf.alloc(&pair, m) || !buf.alloc(&pair2, m) ||
+      !buf.alloc(&old, m) || !buf.alloc(&take, m) || !buf.alloc(&changed, m) ||
+      !buf.alloc(&dirty, m) ||
       !buf.alloc(&keep_counts, nbk) || !buf.alloc(&merges, 1))
     return pfail(ctx, LECO_ENOMEM, "partition: partition arrays");
   hipLaunchKernelGGL(leco::k_bitmap_emit, dim3(uint32_t(nb)), dim3(leco::kScanBlock), 0, stream,
@@ -447,17 +698,30 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
 
   // merge rounds
   const uint64_t grid_cap = uint64_t(ctx->num_cus) * 16;
-  auto costs = [&](const uint64_t* s, uint64_t count, uint32_t span, uint64_t* out) {
-    const uint64_t g = count < grid_cap ? count : grid_cap;
-    if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(leco::k_costs, dim3(uint32_t(g)), dim3(leco::kEncBlock), 0, stream, col, w,
-                       s, count, span, prm->max_len, out);
+  auto costs = [&](const uint64_t* s, uint64_t count, uint32_t span, const uint8_t* dirty,
+                   uint64_t* out) {
+    if (count == 0) return hipSuccess;
+    const uint64_t gs = (count + leco::kEncBlock - 1) / leco::kEncBlock;
+    hipLaunchKernelGGL(leco::k_costs_short, dim3(uint32_t(gs < grid_cap ? gs : grid_cap)),
+                       dim3(leco::kEncBlock), 0, stream, col, w, s, count, span, prm->max_len,
+                       dirty, out);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+    const uint64_t gw = (count + leco::kEncWaves - 1) / leco::kEncWaves;
+    hipLaunchKernelGGL(leco::k_costs, dim3(uint32_t(gw < grid_cap ? gw : grid_cap)),
+                       dim3(leco::kEncBlock), 0, stream, col, w, s, count, span, prm->max_len,
+                       dirty, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint64_t gl = count < grid_cap ? count : grid_cap;
+    hipLaunchKernelGGL(leco::k_costs_long, dim3(uint32_t(gl)), dim3(leco::kEncBlock), 0, stream,
+                       col, w, s, count, span, prm->max_len, dirty, out);
     return hipGetLastError();
   };
-  P_TRY(costs(starts, m, 1, cost));
+  P_TRY(costs(starts, m, 1, nullptr, cost));
+  if (m >= 2) P_TRY(costs(starts, m - 1, 2, nullptr, pair));
   for (uint64_t round = 0; prm->max_rounds == 0 || round < prm->max_rounds; ++round) {
     if (m < 2) break;
-    P_TRY(costs(starts, m - 1, 2, pair));
     P_TRY(hipMemsetAsync(merges, 0, 8, stream));
     hipLaunchKernelGGL(leco::k_select, dim3(uint32_t((m - 1 + 255) / 256)), dim3(256), 0, stream,
                        cost, pair, m, take, merges);
@@ -473,12 +737,21 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
     uint64_t m2 = 0;
     P_TRY(scan_counts(keep_counts, blocks, &m2, stream));
     hipLaunchKernelGGL(leco::k_keep_emit, dim3(uint32_t(blocks)), dim3(leco::kScanBlock), 0,
-                       stream, take, m, keep_counts, starts, cost, pair, starts2, cost2);
+                       stream, take, m, keep_counts, starts, cost, pair, starts2, cost2, changed,
+                       old);
     P_TRY(hipGetLastError());
     P_TRY(hipMemcpyAsync(starts2 + m2, &n, 8, hipMemcpyHostToDevice, stream));
-    P_TRY(hipStreamSynchronize(stream));  // &n stays valid; the next round reads starts2
+    if (m2 >= 2) {
+      // pair costs for the next round: reused, or sized where a merge happened
+      hipLaunchKernelGGL(leco::k_pair_reuse, dim3(uint32_t((m2 - 1 + 255) / 256)), dim3(256), 0,
+                         stream, m2, changed, old, pair, pair2, dirty);
+      P_TRY(hipGetLastError());
+      P_TRY(costs(starts2, m2 - 1, 2, dirty, pair2));
+    }
+    P_TRY(hipStreamSynchronize(stream));  // &n stays valid until the copy is done
     std::swap(starts, starts2);
     std::swap(cost, cost2);
+    std::swap(pair, pair2);
     m = m2;
   }
   *m_out = m;
