@@ -58,7 +58,7 @@ leco_status get_scratch(leco_ctx* ctx, size_t bytes, void** out) {
 
 // Partition count and validation of a partitioning for n values.
 leco_status check_partitioning(leco_ctx* ctx, uint64_t n, const leco_partitioning* part,
-                               uint64_t* m_out) {
+                               uint64_t* m_out, uint64_t* max_len_out = nullptr) {
   if (!part) return fail(ctx, LECO_EINVAL, "partitioning is null");
   if (part->reserved != 0) return fail(ctx, LECO_EINVAL, "reserved field must be 0");
   if (part->fixed_len > 0) {
@@ -66,6 +66,7 @@ leco_status check_partitioning(leco_ctx* ctx, uint64_t n, const leco_partitionin
       return fail(ctx, LECO_EINVAL, "fixed_len %llu exceeds 2^20",
                   (unsigned long long)part->fixed_len);
     *m_out = n / part->fixed_len + (n % part->fixed_len != 0);
+    if (max_len_out) *max_len_out = n < part->fixed_len ? n : part->fixed_len;
     return LECO_OK;
   }
   const uint64_t m = part->num_partitions;
@@ -73,14 +74,17 @@ leco_status check_partitioning(leco_ctx* ctx, uint64_t n, const leco_partitionin
   if (!s) return fail(ctx, LECO_EINVAL, "starts_host is null for variable partitioning");
   if (s[0] != 0 || s[m] != n)
     return fail(ctx, LECO_EINVAL, "starts must begin at 0 and end at n");
+  uint64_t longest = 0;
   for (uint64_t j = 0; j < m; ++j) {
     if (s[j + 1] <= s[j])
       return fail(ctx, LECO_EINVAL, "starts not strictly increasing at %llu",
                   (unsigned long long)j);
     if (s[j + 1] - s[j] > kMaxPartLen)
       return fail(ctx, LECO_EINVAL, "partition %llu longer than 2^20", (unsigned long long)j);
+    if (s[j + 1] - s[j] > longest) longest = s[j + 1] - s[j];
   }
   *m_out = m;
+  if (max_len_out) *max_len_out = longest;
   return LECO_OK;
 }
 
@@ -93,6 +97,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // One single-column encode: the column descriptor plus its scratch.
 struct EncodeCall {
   leco::EncColumn col;
+  uint64_t max_len;             // longest partition
   uint64_t* status;             // m look-back words
   unsigned long long* ticket;   // partition ticket counter
   uint64_t* size_dev;           // blob size (scratch; used when the caller gives none)
@@ -109,7 +114,7 @@ leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtyp
     return fail(ctx, LECO_EINVAL, "blob must be 16-byte aligned and column dtype-aligned");
   if (cap < leco::kHeaderBytes) return fail(ctx, LECO_ENOSPC, "blob capacity below 64 bytes");
   uint64_t m = 0;
-  leco_status st = check_partitioning(ctx, n, part, &m);
+  leco_status st = check_partitioning(ctx, n, part, &m, &call->max_len);
   if (st != LECO_OK) return st;
   if (m >= (uint64_t(1) << 31)) return fail(ctx, LECO_EINVAL, "too many partitions");
   const bool variable = part->fixed_len == 0;
@@ -313,8 +318,8 @@ static leco_status encode_common(leco_ctx* ctx, const void* col, uint64_t n, lec
   leco_status st = prepare_encode(ctx, col, n, dtype, part, blob, cap, stream, call);
   if (st != LECO_OK) return st;
   if (size_dev) call->col.size_out = size_dev;
-  HIP_TRY(ctx, leco::launch_encode_columns(ctx, nullptr, 1, call->col, call->col.m, call->status,
-                                           call->ticket, stream));
+  HIP_TRY(ctx, leco::launch_encode_columns(ctx, nullptr, 1, call->col, call->col.m, call->max_len,
+                                           call->status, call->ticket, stream));
   return LECO_OK;
 }
 
@@ -354,8 +359,11 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
                               hipStream_t stream) {
   if (!ctx) return LECO_EINVAL;
   if (ncols && !jobs) return fail(ctx, LECO_EINVAL, "jobs is null");
-  std::vector<leco::EncColumn> cols(ncols);
-  uint64_t parts = 0;
+  // Columns whose partitions fit one wavefront go to one launch, the others
+  // to a second; the look-back runs within a column, so the two are
+  // independent.
+  std::vector<leco::EncColumn> cols[2];
+  uint64_t parts[2] = {0, 0}, longest[2] = {0, 0};
   for (uint64_t i = 0; i < ncols; ++i) {
     const leco_encode_job& j = jobs[i];
     if (j.dtype != LECO_U32 && j.dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "job %llu: bad dtype", (unsigned long long)i);
@@ -370,7 +378,9 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
     if (j.blob_cap < bound)
       return fail(ctx, LECO_ENOSPC, "job %llu: capacity below %llu", (unsigned long long)i,
                   (unsigned long long)bound);
-    leco::EncColumn& c = cols[i];
+    const uint64_t len = j.n < j.fixed_len ? j.n : j.fixed_len;
+    const int g = len <= leco::kWaveEncodeMax ? 0 : 1;
+    leco::EncColumn c;
     c.col = static_cast<const uint8_t*>(j.col_dev);
     c.blob = static_cast<uint8_t*>(j.blob_dev);
     c.starts = nullptr;
@@ -380,28 +390,37 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
     c.fixed_len = j.fixed_len;
     c.cap = j.blob_cap;
     c.words_off = meta_words_off(c.m, false);
-    c.part_base = parts;
+    c.part_base = parts[g];
     c.dtype = uint32_t(j.dtype);
     c.force_constant = j.force_constant_model ? 1 : 0;
-    parts += c.m;
+    parts[g] += c.m;
+    if (len > longest[g]) longest[g] = len;
+    cols[g].push_back(c);
   }
   if (ncols == 0) return LECO_OK;
-  if (parts >= (uint64_t(1) << 31)) return fail(ctx, LECO_EINVAL, "too many partitions in one batch");
-  size_t off = 0;
-  const size_t o_status = off; off = align256(off + 8 * (parts ? parts : 1));
-  const size_t o_ticket = off; off = align256(off + 8);
-  const size_t o_cols = off;   off = align256(off + sizeof(leco::EncColumn) * ncols);
+  if (parts[0] >= (uint64_t(1) << 31) || parts[1] >= (uint64_t(1) << 31))
+    return fail(ctx, LECO_EINVAL, "too many partitions in one batch");
+  size_t off = 0, o_status[2], o_ticket[2], o_cols[2];
+  for (int g = 0; g < 2; ++g) {
+    o_status[g] = off; off = align256(off + 8 * (parts[g] ? parts[g] : 1));
+    o_ticket[g] = off; off = align256(off + 8);
+    o_cols[g] = off;   off = align256(off + sizeof(leco::EncColumn) * (cols[g].size() + 1));
+  }
   void* scr = nullptr;
   leco_status st = get_scratch(ctx, off, &scr);
   if (st != LECO_OK) return st;
   char* b = static_cast<char*>(scr);
-  leco::EncColumn* cols_dev = reinterpret_cast<leco::EncColumn*>(b + o_cols);
-  HIP_TRY(ctx, hipMemcpyAsync(cols_dev, cols.data(), sizeof(leco::EncColumn) * ncols,
-                              hipMemcpyHostToDevice, stream));
-  HIP_TRY(ctx, leco::launch_encode_columns(ctx, cols_dev, ncols, cols[0], parts,
-                                           reinterpret_cast<uint64_t*>(b + o_status),
-                                           reinterpret_cast<unsigned long long*>(b + o_ticket),
-                                           stream));
+  for (int g = 0; g < 2; ++g) {
+    if (cols[g].empty()) continue;
+    leco::EncColumn* cols_dev = reinterpret_cast<leco::EncColumn*>(b + o_cols[g]);
+    HIP_TRY(ctx, hipMemcpyAsync(cols_dev, cols[g].data(), sizeof(leco::EncColumn) * cols[g].size(),
+                                hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, leco::launch_encode_columns(ctx, cols_dev, cols[g].size(), cols[g][0], parts[g],
+                                             longest[g],
+                                             reinterpret_cast<uint64_t*>(b + o_status[g]),
+                                             reinterpret_cast<unsigned long long*>(b + o_ticket[g]),
+                                             stream));
+  }
   return LECO_OK;
 }
 

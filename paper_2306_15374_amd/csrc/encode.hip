@@ -102,11 +102,11 @@ __device__ inline void finish_column(const EncColumn& c, uint64_t total_words, i
 // count as an inclusive prefix of 0), so the inclusive-prefix frontier
 // advances kRows * 64 partitions per global-memory round trip.  The status
 // words carry their own value, so relaxed device-scope atomics suffice.
-__device__ uint64_t publish_and_look_back(EncShared& sh, const EncColumn& c, uint64_t P,
-                                          uint64_t j, uint64_t start, uint64_t nwords,
-                                          const Model& md, uint64_t* status, int* err) {
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (wave == 0) {
+// Run by one whole wavefront; every lane receives the word offset.
+__device__ uint64_t look_back_wave(const EncColumn& c, uint64_t P, uint64_t j, uint64_t start,
+                                  uint64_t nwords, const Model& md, uint64_t* status, int* err) {
+  const uint32_t lane = threadIdx.x & 63;
+  {
     if (lane == 0)
       __hip_atomic_store(&status[P], (j == 0 ? kFlagPrefix : kFlagAgg) | nwords, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
@@ -168,7 +168,6 @@ __device__ uint64_t publish_and_look_back(EncShared& sh, const EncColumn& c, uin
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
-      sh.word_off = excl;
       const uint64_t rec = kHeaderBytes + kRecordBytes * j;
       if (rec + kRecordBytes <= c.cap) {
         uint64_t* r = reinterpret_cast<uint64_t*>(c.blob + rec);
@@ -183,6 +182,17 @@ __device__ uint64_t publish_and_look_back(EncShared& sh, const EncColumn& c, uin
       }
       if (j + 1 == c.m) finish_column(c, excl + nwords, err);
     }
+    return excl;
+  }
+}
+
+// The workgroup version: wave 0 looks back, every thread gets the offset.
+__device__ uint64_t publish_and_look_back(EncShared& sh, const EncColumn& c, uint64_t P,
+                                          uint64_t j, uint64_t start, uint64_t nwords,
+                                          const Model& md, uint64_t* status, int* err) {
+  if ((threadIdx.x >> 6) == 0) {
+    const uint64_t excl = look_back_wave(c, P, j, start, nwords, md, status, err);
+    if ((threadIdx.x & 63) == 0) sh.word_off = excl;
   }
   __syncthreads();
   return sh.word_off;
@@ -406,6 +416,161 @@ __global__ __launch_bounds__(kEncBlock) void k_encode(const EncColumn* __restric
   }
 }
 
+// ---- one wavefront per partition ------------------------------------------------
+
+// Partitions of at most kWaveEncMax values are encoded by one wavefront
+// each (16 values per lane in registers, shuffle reductions, no workgroup
+// barrier), four per workgroup.
+constexpr uint32_t kWaveEncMax = uint32_t(kWaveEncodeMax);
+constexpr int kWaveRegs = int(kWaveEncMax / 64);
+
+__device__ inline void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Same model, bytes and look-back as k_encode for every partition of the
+// launch, which the host only sends here when none is longer than
+// kWaveEncMax.  Packing goes one round of 64 residuals at a time: round k
+// holds residuals 64k .. 64k + 63, which fill exactly 2b 32-bit words, so
+// the rounds never share a word; the round is assembled in the
+// wavefront's LDS buffer and stored.
+__global__ __launch_bounds__(kEncBlock) void k_encode_wave(const EncColumn* __restrict__ cols,
+                                                          uint64_t ncols, EncColumn single,
+                                                          uint64_t* __restrict__ status,
+                                                          unsigned long long* __restrict__ ticket,
+                                                          uint64_t nparts, int* err) {
+  __shared__ uint32_t pack_lds[kEncWaves][128];
+  __shared__ unsigned long long block_ticket;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // one ticket per workgroup for its four partitions: same-address atomics
+  // serialize, so fewer of them shorten the launch
+  uint64_t P;
+  if (ticket) {
+    if (threadIdx.x == 0) block_ticket = atomicAdd(ticket, 1ull);
+    __syncthreads();
+    P = uint64_t(block_ticket) * kEncWaves + wave;
+  } else {
+    P = uint64_t(blockIdx.x) * kEncWaves + wave;
+  }
+  if (P >= nparts) return;
+  const EncColumn& c = column_of(cols, ncols, single, P);
+  const uint64_t j = P - c.part_base;
+  uint64_t start, len;
+  if (c.fixed_len) {
+    start = j * c.fixed_len;
+    len = (start + c.fixed_len < c.n ? start + c.fixed_len : c.n) - start;
+  } else {
+    start = c.starts[j];
+    len = c.starts[j + 1] - start;
+  }
+  if (len > kWaveEncMax) {  // the host routes such partitions to k_encode
+    if (lane == 0) raise(err, kErrDevice);
+    return;
+  }
+  const uint8_t* src = c.col + start * c.dtype;
+  const bool fit_allowed = !(len == 1 || c.force_constant);
+  uint32_t* gw32 = reinterpret_cast<uint32_t*>(c.blob + c.words_off);
+  const uint64_t cap_w32 = c.cap > c.words_off ? (c.cap - c.words_off) / 4 : 0;
+  uint32_t* w32 = pack_lds[wave];
+
+  uint64_t v[kWaveRegs];
+  uint64_t vmin = ~uint64_t(0), vmax = 0;
+#pragma unroll
+  for (int k = 0; k < kWaveRegs; ++k) {
+    const uint32_t t = lane + 64 * k;
+    v[k] = t < len ? load_value(src, c.dtype, t) : 0;
+    if (t < len) {
+      vmin = v[k] < vmin ? v[k] : vmin;
+      vmax = v[k] > vmax ? v[k] : vmax;
+    }
+  }
+  wave_minmax_u64(vmin, vmax);
+  const uint64_t range = vmax - vmin;
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  const bool fit = fit_allowed && range < (uint64_t(1) << 61);
+  const bool narrow = range < kNarrowRange;
+  bool small = false;
+  if (fit) {
+    double th;
+    if (narrow) {
+      uint64_t sy = 0, sty = 0;  // < 2^40 and < 2^50
+#pragma unroll
+      for (int k = 0; k < kWaveRegs; ++k) {
+        const uint32_t t = lane + 64 * k;
+        if (t < len) {
+          const uint64_t y = uint32_t(v[k]) - uint32_t(vmin);
+          sy += y;
+          sty += uint64_t(t) * y;
+        }
+      }
+      wave_sum_u64x2(sy, sty);
+      th = ls_slope(len, U128{sy, 0}, U128{sty, 0});
+    } else {
+      U128 sv{0, 0}, stv{0, 0};
+#pragma unroll
+      for (int k = 0; k < kWaveRegs; ++k) {
+        const uint32_t t = lane + 64 * k;
+        if (t < len) {
+          sv = add128(sv, U128{v[k], 0});
+          stv = add128(stv, mul64x64(t, v[k]));
+        }
+      }
+      wave_sum_u128x2(sv, stv);
+      th = ls_slope(len, sv, stv);
+    }
+    // |floor(theta1 t)| < 2^30 for every t < len: predictions fit int32
+    small = narrow && __dmul_rn(fabs(th), double(len)) < 1073741824.0;
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+#pragma unroll
+    for (int k = 0; k < kWaveRegs; ++k) {
+      const uint32_t t = lane + 64 * k;
+      if (t < len) {
+        const int64_t rr = small ? int64_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t))
+                                 : int64_t(v[k] - vmin) - predict(th, t);
+        rmin = rr < rmin ? rr : rmin;
+        rmax = rr > rmax ? rr : rmax;
+      }
+    }
+    wave_minmax_i64(rmin, rmax);
+    choose_model(md, th, rmin, rmax);
+  }
+  const uint32_t b = md.bits;
+  const uint64_t nwords = (len * b + 63) >> 6;
+  const uint64_t word_off = look_back_wave(c, P, j, start, nwords, md, status, err);
+  if (b == 0) return;
+  const uint64_t w0 = 2 * word_off;  // first 32-bit word of the span
+  const uint32_t rounds = uint32_t((len + 63) / 64);
+#pragma unroll
+  for (int k = 0; k < kWaveRegs; ++k) {
+    if (uint32_t(k) >= rounds) break;
+    w32[lane] = 0;
+    w32[lane + 64] = 0;
+    wave_fence();
+    const uint32_t t = lane + 64 * k;
+    if (t < len) {
+      uint64_t u;
+      if (!md.linear) u = v[k] - md.vmin;
+      else if (small)
+        u = uint64_t(uint32_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(md.theta1, t) -
+                              int32_t(md.rmin)));
+      else u = (v[k] - md.base) - uint64_t(predict(md.theta1, t));
+      or_bits(w32, lane * b, b, u);
+    }
+    wave_fence();
+    // 32-bit words of this round: 2b, the last round up to the span's end
+    const uint64_t first = uint64_t(2 * b) * k;
+    const uint64_t count = (first + 2 * b <= 2 * nwords) ? 2 * b : 2 * nwords - first;
+    for (uint32_t q = lane; q < count; q += 64) {
+      const uint64_t dst = w0 + first + q;
+      if (dst < cap_w32) gw32[dst] = w32[q];
+    }
+    wave_fence();
+  }
+}
+
 // Clears the look-back state and ticket, and writes the complete blob of
 // every empty column (no partitions, so no workgroup of k_encode sees it).
 __global__ void k_encode_prepare(const EncColumn* __restrict__ cols, uint64_t ncols,
@@ -423,8 +588,9 @@ __global__ void k_encode_prepare(const EncColumn* __restrict__ cols, uint64_t nc
 }
 
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
-                                 const EncColumn& single, uint64_t nparts, uint64_t* status,
-                                 unsigned long long* ticket, hipStream_t stream) {
+                                 const EncColumn& single, uint64_t nparts, uint64_t max_len,
+                                 uint64_t* status, unsigned long long* ticket,
+                                 hipStream_t stream) {
   const uint64_t pg = (nparts + 255) / 256;
   const uint64_t cg = (ncols + 255) / 256;
   uint64_t g = pg > cg ? pg : cg;
@@ -432,10 +598,15 @@ hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint6
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_encode_prepare, dim3(uint32_t(g)), dim3(256), 0, stream, cols_dev, ncols,
                      single, status, nparts, ticket, ctx->err_dev);
-  if (nparts > 0)
-    hipLaunchKernelGGL(k_encode, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
-                       ncols, single, status, ctx->tune.encode_ticket ? ticket : nullptr,
+  if (nparts == 0) return hipGetLastError();
+  unsigned long long* tk = ctx->tune.encode_ticket ? ticket : nullptr;
+  if (max_len <= kWaveEncMax && ctx->tune.encode_wave)
+    hipLaunchKernelGGL(k_encode_wave, dim3(uint32_t((nparts + kEncWaves - 1) / kEncWaves)),
+                       dim3(kEncBlock), 0, stream, cols_dev, ncols, single, status, tk, nparts,
                        ctx->err_dev);
+  else
+    hipLaunchKernelGGL(k_encode, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
+                       ncols, single, status, tk, ctx->err_dev);
   return hipGetLastError();
 }
 

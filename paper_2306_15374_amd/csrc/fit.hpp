@@ -23,6 +23,40 @@ __device__ inline uint64_t shfl_xor64(uint64_t x, int m) {
   return static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(x), m, 64));
 }
 
+// Wavefront-wide reductions (every lane receives the result, no barrier).
+__device__ inline void wave_minmax_u64(uint64_t& mn, uint64_t& mx) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const uint64_t a = shfl_xor64(mn, m), b = shfl_xor64(mx, m);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+}
+
+__device__ inline void wave_minmax_i64(int64_t& mn, int64_t& mx) {
+  // order-preserving map of int64 onto uint64
+  uint64_t a = uint64_t(mn) ^ (1ull << 63), b = uint64_t(mx) ^ (1ull << 63);
+  wave_minmax_u64(a, b);
+  mn = int64_t(a ^ (1ull << 63));
+  mx = int64_t(b ^ (1ull << 63));
+}
+
+__device__ inline void wave_sum_u128x2(U128& x, U128& y) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    x = add128(x, U128{shfl_xor64(x.lo, m), shfl_xor64(x.hi, m)});
+    y = add128(y, U128{shfl_xor64(y.lo, m), shfl_xor64(y.hi, m)});
+  }
+}
+
+__device__ inline void wave_sum_u64x2(uint64_t& x, uint64_t& y) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    x += shfl_xor64(x, m);
+    y += shfl_xor64(y, m);
+  }
+}
+
 // Every thread receives the workgroup's min and max (two barriers).
 template <class Sh>
 __device__ inline void block_minmax_u64(Sh& sh, uint64_t& mn, uint64_t& mx) {

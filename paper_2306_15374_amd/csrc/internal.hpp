@@ -17,6 +17,7 @@ struct Tune {
   uint32_t xcd_remap = 0;            // 1 = contiguous tile runs per XCD
   uint32_t ra_lookups_per_lane = 1;  // 1, 2, 4 or 8 positions per lane
   uint32_t encode_ticket = 1;        // 1 = partition order from a ticket counter
+  uint32_t encode_wave = 1;          // 1 = one wavefront per partition when all are short
 };
 
 // Reads LECO_TILE_LOG2, LECO_DECODE_BLOCKS_PER_CU, LECO_XCD_REMAP and
@@ -53,9 +54,13 @@ hipError_t launch_filter_sum(leco_ctx* ctx, const void* blob, uint64_t blob_byte
 hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream);
 // Encodes ncols columns (table cols_dev, or `single` when cols_dev is null)
 // with nparts partitions in total; status holds nparts look-back words.
+// Partitions of at most this many values are encoded one per wavefront.
+constexpr uint64_t kWaveEncodeMax = 1024;
+// max_len: the longest partition of the launch (selects the kernel).
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
-                                 const EncColumn& single, uint64_t nparts, uint64_t* status,
-                                 unsigned long long* ticket, hipStream_t stream);
+                                 const EncColumn& single, uint64_t nparts, uint64_t max_len,
+                                 uint64_t* status, unsigned long long* ticket,
+                                 hipStream_t stream);
 hipError_t launch_diag_slope(const uint64_t* in, uint64_t k, double* out, hipStream_t stream);
 hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t bytes,
                             hipStream_t stream);

@@ -399,24 +399,6 @@ __global__ __launch_bounds__(kEncBlock) void k_costs_short(const uint8_t* __rest
   }
 }
 
-// Wavefront-wide reductions (every lane receives the result).
-__device__ inline void wave_minmax_u64(uint64_t& mn, uint64_t& mx) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) {
-    const uint64_t a = shfl_xor64(mn, m), b = shfl_xor64(mx, m);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  }
-}
-
-__device__ inline void wave_sum_u128x2(U128& x, U128& y) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) {
-    x = add128(x, U128{shfl_xor64(x.lo, m), shfl_xor64(x.hi, m)});
-    y = add128(y, U128{shfl_xor64(y.lo, m), shfl_xor64(y.hi, m)});
-  }
-}
-
 // range_cost computed by one wavefront alone (no workgroup barrier), the
 // same arithmetic in the same order of operations where it matters: the
 // sums are exact and the slope is one function of them.
@@ -445,10 +427,8 @@ __device__ uint64_t range_cost_wave(const uint8_t* col, uint32_t dtype, uint64_t
       rmin = rr < rmin ? rr : rmin;
       rmax = rr > rmax ? rr : rmax;
     }
-    // order-preserving map of int64 onto uint64 for the unsigned reduction
-    uint64_t a = uint64_t(rmin) ^ (1ull << 63), b = uint64_t(rmax) ^ (1ull << 63);
-    wave_minmax_u64(a, b);
-    choose_model(md, th, int64_t(a ^ (1ull << 63)), int64_t(b ^ (1ull << 63)));
+    wave_minmax_i64(rmin, rmax);
+    choose_model(md, th, rmin, rmax);
   }
   return kRecordBytes + 8 + 8 * ((len * md.bits + 63) >> 6);
 }
