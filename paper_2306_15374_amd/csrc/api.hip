@@ -98,8 +98,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct EncodeCall {
   leco::EncColumn col;
   uint64_t max_len;             // longest partition
-  uint64_t* status;             // m look-back words
-  unsigned long long* ticket;   // partition ticket counter
+  leco::EncScratch scr;         // models, word counts and offsets
   uint64_t* size_dev;           // blob size (scratch; used when the caller gives none)
 };
 
@@ -119,7 +118,7 @@ leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtyp
   if (m >= (uint64_t(1) << 31)) return fail(ctx, LECO_EINVAL, "too many partitions");
   const bool variable = part->fixed_len == 0;
   size_t off = 0;
-  const size_t o_status = off; off = align256(off + 8 * (m ? m : 1));
+  const size_t o_enc = off;    off = align256(off + leco::encode_scratch_bytes(m));
   const size_t o_misc = off;   off = align256(off + 16);
   const size_t o_starts = off; off = align256(off + (variable ? 8 * (m + 1) : 8));
   void* scr = nullptr;
@@ -138,9 +137,8 @@ leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtyp
   c.part_base = 0;
   c.dtype = uint32_t(dtype);
   c.force_constant = part->force_constant_model ? 1 : 0;
-  call->status = reinterpret_cast<uint64_t*>(b + o_status);
-  call->ticket = reinterpret_cast<unsigned long long*>(b + o_misc);
-  call->size_dev = reinterpret_cast<uint64_t*>(b + o_misc + 8);
+  call->scr = leco::carve_encode_scratch(b + o_enc, m);
+  call->size_dev = reinterpret_cast<uint64_t*>(b + o_misc);
   c.size_out = call->size_dev;
   if (variable) {
     uint64_t* sd = reinterpret_cast<uint64_t*>(b + o_starts);
@@ -319,7 +317,7 @@ static leco_status encode_common(leco_ctx* ctx, const void* col, uint64_t n, lec
   if (st != LECO_OK) return st;
   if (size_dev) call->col.size_out = size_dev;
   HIP_TRY(ctx, leco::launch_encode_columns(ctx, nullptr, 1, call->col, call->col.m, call->max_len,
-                                           call->status, call->ticket, stream));
+                                           call->scr, stream));
   return LECO_OK;
 }
 
@@ -359,9 +357,8 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
                               hipStream_t stream) {
   if (!ctx) return LECO_EINVAL;
   if (ncols && !jobs) return fail(ctx, LECO_EINVAL, "jobs is null");
-  // Columns whose partitions fit one wavefront go to one launch, the others
-  // to a second; the look-back runs within a column, so the two are
-  // independent.
+  // Columns whose partitions fit one wavefront go to one sequence of
+  // launches, the others to a second.
   std::vector<leco::EncColumn> cols[2];
   uint64_t parts[2] = {0, 0}, longest[2] = {0, 0};
   for (uint64_t i = 0; i < ncols; ++i) {
@@ -400,11 +397,10 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
   if (ncols == 0) return LECO_OK;
   if (parts[0] >= (uint64_t(1) << 31) || parts[1] >= (uint64_t(1) << 31))
     return fail(ctx, LECO_EINVAL, "too many partitions in one batch");
-  size_t off = 0, o_status[2], o_ticket[2], o_cols[2];
+  size_t off = 0, o_enc[2], o_cols[2];
   for (int g = 0; g < 2; ++g) {
-    o_status[g] = off; off = align256(off + 8 * (parts[g] ? parts[g] : 1));
-    o_ticket[g] = off; off = align256(off + 8);
-    o_cols[g] = off;   off = align256(off + sizeof(leco::EncColumn) * (cols[g].size() + 1));
+    o_enc[g] = off;  off = align256(off + leco::encode_scratch_bytes(parts[g]));
+    o_cols[g] = off; off = align256(off + sizeof(leco::EncColumn) * (cols[g].size() + 1));
   }
   void* scr = nullptr;
   leco_status st = get_scratch(ctx, off, &scr);
@@ -417,8 +413,7 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
                                 hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, leco::launch_encode_columns(ctx, cols_dev, cols[g].size(), cols[g][0], parts[g],
                                              longest[g],
-                                             reinterpret_cast<uint64_t*>(b + o_status[g]),
-                                             reinterpret_cast<unsigned long long*>(b + o_ticket[g]),
+                                             leco::carve_encode_scratch(b + o_enc[g], parts[g]),
                                              stream));
   }
   return LECO_OK;

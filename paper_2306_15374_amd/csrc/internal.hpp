@@ -16,12 +16,11 @@ struct Tune {
   uint32_t decode_blocks_per_cu = 0; // 0 = one workgroup per tile
   uint32_t xcd_remap = 0;            // 1 = contiguous tile runs per XCD
   uint32_t ra_lookups_per_lane = 1;  // 1, 2, 4 or 8 positions per lane
-  uint32_t encode_ticket = 1;        // 1 = partition order from a ticket counter
   uint32_t encode_wave = 1;          // 1 = one wavefront per partition when all are short
 };
 
 // Reads LECO_TILE_LOG2, LECO_DECODE_BLOCKS_PER_CU, LECO_XCD_REMAP and
-// LECO_RA_LPT, LECO_ENCODE_TICKET overrides from the environment.
+// LECO_RA_LPT, LECO_ENCODE_WAVE overrides from the environment.
 void tune_from_env(Tune& t);
 
 // One column for the encoder: input, partitioning, output blob.  A table of
@@ -56,11 +55,24 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream);
 // with nparts partitions in total; status holds nparts look-back words.
 // Partitions of at most this many values are encoded one per wavefront.
 constexpr uint64_t kWaveEncodeMax = 1024;
-// max_len: the longest partition of the launch (selects the kernel).
+
+// Device scratch of one encode launch (nparts partitions): the fitted
+// models, their word counts and offsets, and the scan's per-workgroup sums.
+struct EncScratch {
+  uint64_t* nwords;
+  uint64_t* woff;
+  uint64_t* base;
+  uint64_t* theta;  // bits of the binary64 slope
+  uint64_t* bsum;
+  uint32_t* bits;
+};
+uint64_t encode_scratch_bytes(uint64_t nparts);
+EncScratch carve_encode_scratch(void* p, uint64_t nparts);
+
+// max_len: the longest partition of the launch (selects the kernels).
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                                  const EncColumn& single, uint64_t nparts, uint64_t max_len,
-                                 uint64_t* status, unsigned long long* ticket,
-                                 hipStream_t stream);
+                                 const EncScratch& scr, hipStream_t stream);
 hipError_t launch_diag_slope(const uint64_t* in, uint64_t k, double* out, hipStream_t stream);
 hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t bytes,
                             hipStream_t stream);
