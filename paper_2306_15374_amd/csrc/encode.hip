@@ -54,15 +54,46 @@ __device__ inline void or_bits(uint32_t* w, uint32_t q, uint32_t b, uint64_t u) 
   if (s + b > 64) atomicOr(&w[i + 2], uint32_t(u >> (64 - s)));
 }
 
-__device__ inline const EncColumn& column_of(const EncColumn* cols, uint64_t ncols,
-                                             const EncColumn& single, uint64_t P) {
+// p[i] read through the constant address space: a scalar load when i is
+// uniform across the wavefront.  Only for data written before the launch.
+template <class T>
+__device__ inline T meta_load(const T* p, uint64_t i) {
+  return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
+constexpr uint32_t kColWords = sizeof(EncColumn) / 8;
+static_assert(sizeof(EncColumn) == 88 && offsetof(EncColumn, part_base) == 72 &&
+                  offsetof(EncColumn, dtype) == 80,
+              "column entry layout");
+
+// The column holding partition P: the kernel argument of a one-column
+// launch, else the last table entry with part_base <= P, read word by word
+// with scalar loads when P is uniform.
+__device__ inline EncColumn column_of(const EncColumn* cols, uint64_t ncols,
+                                      const EncColumn& single, uint64_t P) {
   if (cols == nullptr) return single;
-  uint64_t lo = 0, hi = ncols;  // last column with part_base <= P
+  const uint64_t* t = reinterpret_cast<const uint64_t*>(cols);
+  uint64_t lo = 0, hi = ncols;
   while (hi - lo > 1) {
     const uint64_t mid = lo + ((hi - lo) >> 1);
-    if (cols[mid].part_base <= P) lo = mid; else hi = mid;
+    if (meta_load(t, mid * kColWords + 9) <= P) lo = mid; else hi = mid;
   }
-  return cols[lo];
+  const uint64_t e = lo * kColWords;
+  EncColumn c;
+  c.col = reinterpret_cast<const uint8_t*>(meta_load(t, e + 0));
+  c.blob = reinterpret_cast<uint8_t*>(meta_load(t, e + 1));
+  c.starts = reinterpret_cast<const uint64_t*>(meta_load(t, e + 2));
+  c.size_out = reinterpret_cast<uint64_t*>(meta_load(t, e + 3));
+  c.n = meta_load(t, e + 4);
+  c.m = meta_load(t, e + 5);
+  c.fixed_len = meta_load(t, e + 6);
+  c.cap = meta_load(t, e + 7);
+  c.words_off = meta_load(t, e + 8);
+  c.part_base = meta_load(t, e + 9);
+  const uint64_t w = meta_load(t, e + 10);
+  c.dtype = uint32_t(w);
+  c.force_constant = uint32_t(w >> 32);
+  return c;
 }
 
 // First value and length of partition j of column c.
@@ -72,8 +103,8 @@ __device__ inline void part_bounds(const EncColumn& c, uint64_t j, uint64_t& sta
     start = j * c.fixed_len;
     len = (start + c.fixed_len < c.n ? start + c.fixed_len : c.n) - start;
   } else {
-    start = c.starts[j];
-    len = c.starts[j + 1] - start;
+    start = meta_load(c.starts, j);
+    len = meta_load(c.starts, j + 1) - start;
   }
 }
 
@@ -119,37 +150,31 @@ __device__ inline void store_model(const EncScratch& s, uint64_t P, const Model&
 
 // ---- fit: one wavefront per partition ---------------------------------------------
 
-__global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restrict__ cols,
-                                                       uint64_t ncols, EncColumn single,
-                                                       uint64_t nparts, EncScratch scr,
-                                                       int* err) {
+// Loads of value t of a partition of len values: the index is clamped so
+// every lane loads (no branch between loads), and callers mask t >= len.
+template <class T>
+__device__ inline uint64_t load_clamped(const T* src, uint32_t t, uint64_t len) {
+  return uint64_t(global_ptr(src)[t < len ? t : uint32_t(len - 1)]);
+}
+
+// The model of a partition of len <= kWaveEncMax values, by one wavefront.
+template <class T>
+__device__ inline Model fit_wave(const T* src, uint64_t len, bool force_constant) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t P =
-      uint64_t(blockIdx.x) * kEncWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (P >= nparts) return;
-  const EncColumn& c = column_of(cols, ncols, single, P);
-  uint64_t start, len;
-  part_bounds(c, P - c.part_base, start, len);
-  if (len > kWaveEncMax) {  // the host sends such partitions to k_fit_block
-    if (lane == 0) raise(err, kErrDevice);
-    return;
-  }
-  const uint8_t* src = c.col + start * c.dtype;
   uint64_t v[kWaveRegs];
-  uint64_t vmin = ~uint64_t(0), vmax = 0;
 #pragma unroll
-  for (int k = 0; k < kWaveRegs; ++k) {
-    const uint32_t t = lane + 64 * k;
-    v[k] = t < len ? load_value(src, c.dtype, t) : 0;
-    if (t < len) {
-      vmin = v[k] < vmin ? v[k] : vmin;
-      vmax = v[k] > vmax ? v[k] : vmax;
-    }
+  for (int k = 0; k < kWaveRegs; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
+  // clamped lanes hold the last value, which leaves min and max unchanged
+  uint64_t vmin = v[0], vmax = v[0];
+#pragma unroll
+  for (int k = 1; k < kWaveRegs; ++k) {
+    vmin = v[k] < vmin ? v[k] : vmin;
+    vmax = v[k] > vmax ? v[k] : vmax;
   }
   wave_minmax_u64(vmin, vmax);
   const uint64_t range = vmax - vmin;
   Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
-  if (len > 1 && !c.force_constant && range < (uint64_t(1) << 61)) {
+  if (len > 1 && !force_constant && range < (uint64_t(1) << 61)) {
     const bool narrow = range < kNarrowRange;
     double th;
     if (narrow) {
@@ -157,11 +182,9 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restr
 #pragma unroll
       for (int k = 0; k < kWaveRegs; ++k) {
         const uint32_t t = lane + 64 * k;
-        if (t < len) {
-          const uint64_t y = uint32_t(v[k]) - uint32_t(vmin);
-          sy += y;
-          sty += uint64_t(t) * y;
-        }
+        const uint64_t y = t < len ? uint32_t(v[k]) - uint32_t(vmin) : 0;
+        sy += y;
+        sty += uint64_t(t) * y;
       }
       wave_sum_u64x2(sy, sty);
       th = ls_slope(len, U128{sy, 0}, U128{sty, 0});
@@ -170,10 +193,9 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restr
 #pragma unroll
       for (int k = 0; k < kWaveRegs; ++k) {
         const uint32_t t = lane + 64 * k;
-        if (t < len) {
-          sv = add128(sv, U128{v[k], 0});
-          stv = add128(stv, mul64x64(t, v[k]));
-        }
+        const uint64_t x = t < len ? v[k] : 0;
+        sv = add128(sv, U128{x, 0});
+        stv = add128(stv, mul64x64(t, x));
       }
       wave_sum_u128x2(sv, stv);
       th = ls_slope(len, sv, stv);
@@ -184,9 +206,9 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restr
 #pragma unroll
     for (int k = 0; k < kWaveRegs; ++k) {
       const uint32_t t = lane + 64 * k;
+      const int64_t rr = small ? int64_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t))
+                               : int64_t(v[k] - vmin) - predict(th, t);
       if (t < len) {
-        const int64_t rr = small ? int64_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t))
-                                 : int64_t(v[k] - vmin) - predict(th, t);
         rmin = rr < rmin ? rr : rmin;
         rmax = rr > rmax ? rr : rmax;
       }
@@ -194,40 +216,56 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restr
     wave_minmax_i64(rmin, rmax);
     choose_model(md, th, rmin, rmax);
   }
+  return md;
+}
+
+__global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restrict__ cols,
+                                                       uint64_t ncols, EncColumn single,
+                                                       uint64_t nparts, EncScratch scr,
+                                                       int* err) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t P =
+      uint64_t(blockIdx.x) * kEncWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (P >= nparts) return;
+  const EncColumn c = column_of(cols, ncols, single, P);
+  uint64_t start, len;
+  part_bounds(c, P - c.part_base, start, len);
+  if (len > kWaveEncMax) {  // the host sends such partitions to k_fit_block
+    if (lane == 0) raise(err, kErrDevice);
+    return;
+  }
+  const Model md = c.dtype == 8
+                       ? fit_wave(reinterpret_cast<const uint64_t*>(c.col) + start, len, c.force_constant)
+                       : fit_wave(reinterpret_cast<const uint32_t*>(c.col) + start, len, c.force_constant);
   if (lane == 0) store_model(scr, P, md, len);
 }
 
 // ---- fit: one workgroup per partition ----------------------------------------------
 
-__global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __restrict__ cols,
-                                                        uint64_t ncols, EncColumn single,
-                                                        uint64_t nparts, EncScratch scr) {
-  __shared__ FitShared sh;
+// The model of one partition, by the whole workgroup (identical in every
+// thread).  Partitions of at most kEncRegLen values are held in registers;
+// longer ones are streamed twice.
+template <class T>
+__device__ inline Model fit_block(FitShared& sh, const T* src, uint64_t len, bool force_constant) {
   const uint32_t tid = threadIdx.x;
-  const uint64_t P = blockIdx.x;
-  if (P >= nparts) return;
-  const EncColumn& c = column_of(cols, ncols, single, P);
-  uint64_t start, len;
-  part_bounds(c, P - c.part_base, start, len);
-  const uint8_t* src = c.col + start * c.dtype;
   const bool in_regs = len <= kEncRegLen;
+  const auto gsrc = global_ptr(src);
   uint64_t v[kEncRegs];
   uint64_t vmin = ~uint64_t(0), vmax = 0;
   U128 sv{0, 0}, stv{0, 0};
   if (in_regs) {
 #pragma unroll
-    for (int k = 0; k < kEncRegs; ++k) {
-      const uint32_t t = tid + k * kEncBlock;
-      v[k] = t < len ? load_value(src, c.dtype, t) : 0;
-      if (t < len) {
-        vmin = v[k] < vmin ? v[k] : vmin;
-        vmax = v[k] > vmax ? v[k] : vmax;
-      }
+    for (int k = 0; k < kEncRegs; ++k) v[k] = load_clamped(src, tid + k * kEncBlock, len);
+    vmin = vmax = v[0];
+#pragma unroll
+    for (int k = 1; k < kEncRegs; ++k) {
+      vmin = v[k] < vmin ? v[k] : vmin;
+      vmax = v[k] > vmax ? v[k] : vmax;
     }
   } else {
     // streamed: range and raw sums in one pass
     for (uint64_t t = tid; t < len; t += kEncBlock) {
-      const uint64_t x = load_value(src, c.dtype, t);
+      const uint64_t x = uint64_t(gsrc[t]);
       vmin = x < vmin ? x : vmin;
       vmax = x > vmax ? x : vmax;
       sv = add128(sv, U128{x, 0});
@@ -237,7 +275,7 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __rest
   block_minmax_u64(sh, vmin, vmax);
   const uint64_t range = vmax - vmin;
   Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
-  if (len > 1 && !c.force_constant && range < (uint64_t(1) << 61)) {
+  if (len > 1 && !force_constant && range < (uint64_t(1) << 61)) {
     double th;
     bool small = false;
     if (in_regs && range < kNarrowRange) {
@@ -245,11 +283,9 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __rest
 #pragma unroll
       for (int k = 0; k < kEncRegs; ++k) {
         const uint32_t t = tid + k * kEncBlock;
-        if (t < len) {
-          const uint64_t y = uint32_t(v[k]) - uint32_t(vmin);
-          sy += y;
-          sty += uint64_t(t) * y;
-        }
+        const uint64_t y = t < len ? uint32_t(v[k]) - uint32_t(vmin) : 0;
+        sy += y;
+        sty += uint64_t(t) * y;
       }
       block_sum_u64x2(sh, sy, sty);
       th = block_slope(sh, len, U128{sy, 0}, U128{sty, 0});
@@ -259,10 +295,9 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __rest
 #pragma unroll
         for (int k = 0; k < kEncRegs; ++k) {
           const uint32_t t = tid + k * kEncBlock;
-          if (t < len) {
-            sv = add128(sv, U128{v[k], 0});
-            stv = add128(stv, mul64x64(t, v[k]));
-          }
+          const uint64_t x = t < len ? v[k] : 0;
+          sv = add128(sv, U128{x, 0});
+          stv = add128(stv, mul64x64(t, x));
         }
       }
       block_sum_u128x2(sh, sv, stv);
@@ -273,17 +308,17 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __rest
 #pragma unroll
       for (int k = 0; k < kEncRegs; ++k) {
         const uint32_t t = tid + k * kEncBlock;
+        const int64_t rr = small
+                               ? int64_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t))
+                               : int64_t(v[k] - vmin) - predict(th, t);
         if (t < len) {
-          const int64_t rr = small
-                                 ? int64_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t))
-                                 : int64_t(v[k] - vmin) - predict(th, t);
           rmin = rr < rmin ? rr : rmin;
           rmax = rr > rmax ? rr : rmax;
         }
       }
     } else {
       for (uint64_t t = tid; t < len; t += kEncBlock) {
-        const int64_t rr = int64_t(load_value(src, c.dtype, t) - vmin) - predict(th, uint32_t(t));
+        const int64_t rr = int64_t(uint64_t(gsrc[t]) - vmin) - predict(th, uint32_t(t));
         rmin = rr < rmin ? rr : rmin;
         rmax = rr > rmax ? rr : rmax;
       }
@@ -291,7 +326,23 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __rest
     block_minmax_i64(sh, rmin, rmax);
     choose_model(md, th, rmin, rmax);
   }
-  if (tid == 0) store_model(scr, P, md, len);
+  return md;
+}
+
+__global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __restrict__ cols,
+                                                        uint64_t ncols, EncColumn single,
+                                                        uint64_t nparts, EncScratch scr) {
+  __shared__ FitShared sh;
+  const uint64_t P = blockIdx.x;
+  if (P >= nparts) return;
+  const EncColumn c = column_of(cols, ncols, single, P);
+  uint64_t start, len;
+  part_bounds(c, P - c.part_base, start, len);
+  const Model md =
+      c.dtype == 8
+          ? fit_block(sh, reinterpret_cast<const uint64_t*>(c.col) + start, len, c.force_constant)
+          : fit_block(sh, reinterpret_cast<const uint32_t*>(c.col) + start, len, c.force_constant);
+  if (threadIdx.x == 0) store_model(scr, P, md, len);
 }
 
 // ---- scan: word offsets ------------------------------------------------------------
@@ -371,7 +422,7 @@ __global__ __launch_bounds__(kEncBlock) void k_records(const EncColumn* __restri
                                                       uint64_t nparts, EncScratch scr, int* err) {
   const uint64_t P = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (P >= nparts) return;
-  const EncColumn& c = column_of(cols, ncols, single, P);
+  const EncColumn c = column_of(cols, ncols, single, P);
   const uint64_t j = P - c.part_base;
   const uint64_t word_off = scr.woff[P] - scr.woff[c.part_base];
   const uint64_t rec = kHeaderBytes + kRecordBytes * j;
@@ -391,64 +442,86 @@ __global__ __launch_bounds__(kEncBlock) void k_records(const EncColumn* __restri
 
 // ---- pack ----------------------------------------------------------------------------
 
-// Packs rounds r0, r0 + step, ... of partition v[0, len) into its span,
-// from the stored model: u = (v - base) - floor(theta1 t), the encoder's
+constexpr uint32_t kPackBatch = 8;  // rounds of 64 residuals per batch
+
+// Packs rounds [k_begin, k_end) of partition v[0, len) into its words, from
+// the stored model: u = (v - base) - floor(theta1 t), the encoder's
 // residual for both models (the constant model has theta1 = +0).  Round k
-// holds residuals 64k .. 64k + 63, which fill exactly 2b 32-bit words, so
-// rounds never share a word; each is assembled in the wavefront's 128-word
-// LDS buffer and stored.  Called by one wavefront.
-__device__ inline void pack_rounds(const uint8_t* src, uint32_t dtype, uint64_t len,
-                                   uint64_t base, double theta1, uint32_t b, uint64_t w0,
-                                   uint32_t* gw32, uint64_t cap_w32, uint64_t r0, uint64_t step,
-                                   uint32_t* w32) {
+// holds residuals 64k .. 64k + 63, which fill exactly 2b 32-bit words, so a
+// batch of consecutive rounds fills 2b words per round with no word shared
+// with another batch.  A batch's values are loaded together, its words
+// assembled in the wavefront's LDS buffer (kPackBatch * 128 words) and
+// stored as one contiguous run; words at or beyond `limit` (the span's end,
+// or the blob's capacity) are not stored.  Called by one wavefront.
+template <class T>
+__device__ inline void pack_rounds(const T* src, uint64_t len, uint64_t base, double theta1,
+                                   uint32_t b, uint32_t* gw32, uint64_t limit, uint64_t k_begin,
+                                   uint64_t k_end, uint32_t* w32) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t nwords32 = 2 * ((len * b + 63) >> 6);
-  const uint64_t rounds = (len + 63) / 64;
   const bool fits32 = prediction_fits_i32(theta1, len);
-  for (uint64_t k = r0; k < rounds; k += step) {
-    w32[lane] = 0;
-    w32[lane + 64] = 0;
-    wave_fence();
-    const uint64_t t = 64 * k + lane;
-    if (t < len) {
-      const uint64_t y = load_value(src, dtype, t) - base;
-      const uint64_t p = fits32 ? uint64_t(int64_t(predict32(theta1, uint32_t(t))))
-                                : uint64_t(predict(theta1, uint32_t(t)));
-      or_bits(w32, lane * b, b, y - p);
+  const auto gdst = global_ptr(gw32);
+  for (uint64_t k0 = k_begin; k0 < k_end; k0 += kPackBatch) {
+    const uint32_t nr = uint32_t(k_end - k0 < kPackBatch ? k_end - k0 : kPackBatch);
+    uint64_t u[kPackBatch];
+#pragma unroll
+    for (uint32_t r = 0; r < kPackBatch; ++r) u[r] = load_clamped(src, uint32_t(64 * (k0 + r) + lane), len);
+#pragma unroll
+    for (uint32_t r = 0; r < kPackBatch; ++r) {
+      const uint32_t t = uint32_t(64 * (k0 + r) + lane);
+      const uint64_t p = fits32 ? uint64_t(int64_t(predict32(theta1, t))) : uint64_t(predict(theta1, t));
+      u[r] = t < len ? (u[r] - base) - p : 0;
     }
+    const uint32_t nw = 2 * b * nr;  // <= 1024
+    for (uint32_t q = lane; q < nw; q += 64) w32[q] = 0;
     wave_fence();
-    // 32-bit words of this round: 2b, the last round up to the span's end
-    const uint64_t first = uint64_t(2 * b) * k;
-    const uint64_t count = first + 2 * b <= nwords32 ? 2 * b : nwords32 - first;
-    for (uint64_t q = lane; q < count; q += 64) {
-      const uint64_t dst = w0 + first + q;
-      if (dst < cap_w32) gw32[dst] = w32[q];
-    }
+#pragma unroll
+    for (uint32_t r = 0; r < kPackBatch; ++r)
+      if (r < nr) or_bits(w32, (64 * r + lane) * b, b, u[r]);
+    wave_fence();
+    const uint64_t first = 2 * b * k0;
+    const uint64_t count = first >= limit ? 0 : (limit - first < nw ? limit - first : nw);
+    for (uint32_t q = lane; q < count; q += 64) gdst[first + q] = w32[q];
     wave_fence();
   }
 }
 
 // One wavefront per partition (kWave, four per workgroup), or one workgroup
-// per partition whose four wavefronts take every fourth round.
+// per partition whose four wavefronts take consecutive quarters of its
+// rounds (each a whole number of batches).
 template <bool kWave>
 __global__ __launch_bounds__(kEncBlock) void k_pack(const EncColumn* __restrict__ cols,
                                                    uint64_t ncols, EncColumn single,
                                                    uint64_t nparts, EncScratch scr) {
-  __shared__ uint32_t lds[kEncWaves][128];
+  __shared__ uint32_t lds[kEncWaves][kPackBatch * 128];
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t P = kWave ? uint64_t(blockIdx.x) * kEncWaves + wave : uint64_t(blockIdx.x);
   if (P >= nparts) return;
-  const uint32_t b = scr.bits[P];
+  const uint32_t b = meta_load(scr.bits, P);
   if (b == 0) return;
-  const EncColumn& c = column_of(cols, ncols, single, P);
+  const EncColumn c = column_of(cols, ncols, single, P);
   uint64_t start, len;
   part_bounds(c, P - c.part_base, start, len);
-  const uint64_t w0 = 2 * (scr.woff[P] - scr.woff[c.part_base]);
-  uint32_t* gw32 = reinterpret_cast<uint32_t*>(c.blob + c.words_off);
+  const uint64_t w0 = 2 * (meta_load(scr.woff, P) - meta_load(scr.woff, c.part_base));
+  uint32_t* gw32 = reinterpret_cast<uint32_t*>(c.blob + c.words_off) + w0;
   const uint64_t cap_w32 = c.cap > c.words_off ? (c.cap - c.words_off) / 4 : 0;
-  const double theta1 = __longlong_as_double(static_cast<long long>(scr.theta[P]));
-  pack_rounds(c.col + start * c.dtype, c.dtype, len, scr.base[P], theta1, b, w0, gw32, cap_w32,
-              kWave ? 0 : wave, kWave ? 1 : kEncWaves, lds[wave]);
+  const uint64_t nwords32 = 2 * ((len * b + 63) >> 6);
+  const uint64_t avail = cap_w32 > w0 ? cap_w32 - w0 : 0;
+  const uint64_t limit = nwords32 < avail ? nwords32 : avail;
+  const uint64_t rounds = (len + 63) / 64;
+  uint64_t k_begin = 0, k_end = rounds;
+  if (!kWave) {
+    const uint64_t quarter = ((rounds + kEncWaves - 1) / kEncWaves + kPackBatch - 1) / kPackBatch * kPackBatch;
+    k_begin = wave * quarter < rounds ? wave * quarter : rounds;
+    k_end = k_begin + quarter < rounds ? k_begin + quarter : rounds;
+  }
+  const double theta1 = __longlong_as_double(static_cast<long long>(meta_load(scr.theta, P)));
+  const uint64_t base = meta_load(scr.base, P);
+  if (c.dtype == 8)
+    pack_rounds(reinterpret_cast<const uint64_t*>(c.col) + start, len, base, theta1, b, gw32,
+                limit, k_begin, k_end, lds[wave]);
+  else
+    pack_rounds(reinterpret_cast<const uint32_t*>(c.col) + start, len, base, theta1, b, gw32,
+                limit, k_begin, k_end, lds[wave]);
 }
 
 // Writes the complete blob of every empty column (no partitions, so no
