@@ -51,7 +51,20 @@ class _Model(C.Structure):
         ("theta1_ls", C.c_double), ("r_min", C.c_int64), ("r_max", C.c_int64),
         ("b_ls", C.c_uint64), ("theta1", C.c_double), ("base", C.c_uint64),
         ("bits", C.c_uint64),
+        ("mm_fitted", C.c_int32), ("mm_pad", C.c_int32),
+        ("mm_dy", C.c_int64), ("mm_dt", C.c_uint64), ("theta1_mm", C.c_double),
+        ("r_min_mm", C.c_int64), ("r_max_mm", C.c_int64), ("b_mm", C.c_uint64),
     ]
+
+
+REGRESSORS = {"ls": 0, "minimax": 1}
+
+
+def _regressor(name: str) -> int:
+    try:
+        return REGRESSORS[name]
+    except KeyError:
+        raise ValueError(f"regressor must be one of {sorted(REGRESSORS)}, got {name!r}") from None
 
 
 _lib = None
@@ -70,10 +83,13 @@ def _bind(L: C.CDLL) -> C.CDLL:
     u64, vp, P = C.c_uint64, C.c_void_p, C.POINTER
     L.leco_ref_bitlen.argtypes = [u64]
     L.leco_ref_bitlen.restype = u64
-    L.leco_ref_fit.argtypes = [vp, u64, C.c_int, P(_Model)]
+    L.leco_ref_fit.argtypes = [vp, u64, C.c_int, C.c_int, P(_Model)]
     L.leco_ref_fit.restype = C.c_int
-    L.leco_ref_blob_bytes.argtypes = [vp, u64, C.c_int, u64, vp, u64, C.c_int, P(u64)]
-    L.leco_ref_encode.argtypes = [vp, u64, C.c_int, u64, vp, u64, C.c_int, vp, u64, P(u64)]
+    L.leco_ref_minimax_slope.argtypes = [vp, u64, P(C.c_int64), P(u64)]
+    L.leco_ref_minimax_slope.restype = C.c_int
+    L.leco_ref_blob_bytes.argtypes = [vp, u64, C.c_int, u64, vp, u64, C.c_int, C.c_int, P(u64)]
+    L.leco_ref_encode.argtypes = [vp, u64, C.c_int, u64, vp, u64, C.c_int, C.c_int, vp, u64,
+                                  P(u64)]
     L.leco_ref_blob_info.argtypes = [vp, u64, P(u64), P(C.c_int), P(u64)]
     L.leco_ref_blob_record.argtypes = [vp, u64, u64, P(u64), P(C.c_double), P(u64),
                                        P(u64), P(u64), P(u64)]
@@ -135,41 +151,52 @@ def bitlen(x: int) -> int:
     return int(lib().leco_ref_bitlen(x))
 
 
-def fit(values, force_constant: bool = False) -> dict:
+def fit(values, force_constant: bool = False, regressor: str = "ls") -> dict:
     v = np.ascontiguousarray(values, dtype=np.uint64)
     md = _Model()
-    _check("leco_ref_fit", lib().leco_ref_fit(_ptr(v), len(v), int(force_constant), C.byref(md)))
+    _check("leco_ref_fit", lib().leco_ref_fit(_ptr(v), len(v), int(force_constant),
+                                              _regressor(regressor), C.byref(md)))
     d = {name: getattr(md, name) for name, _ in _Model._fields_}
     d["N"] = (d["N_hi"] << 64) | d["N_lo"]
     d["D"] = (d["D_hi"] << 64) | d["D_lo"]
     return d
 
 
+def minimax_slope(values) -> tuple[int, int]:
+    """Exact minimax slope (dy, dt) of the points (t, values[t])."""
+    v = np.ascontiguousarray(values, dtype=np.uint64)
+    dy, dt = C.c_int64(), C.c_uint64()
+    _check("leco_ref_minimax_slope",
+           lib().leco_ref_minimax_slope(_ptr(v), len(v), C.byref(dy), C.byref(dt)))
+    return dy.value, dt.value
+
+
 def blob_bytes(col: np.ndarray, fixed_len: int = 0, starts=None,
-               force_constant: bool = False) -> int:
+               force_constant: bool = False, regressor: str = "ls") -> int:
     col = np.ascontiguousarray(col)
     fl, s, m = _starts_arg(fixed_len, starts)
     out = C.c_uint64()
     _check("leco_ref_blob_bytes", lib().leco_ref_blob_bytes(
         _ptr(col), len(col), _dtype_code(col), fl, _ptr(s), m, int(force_constant),
-        C.byref(out)))
+        _regressor(regressor), C.byref(out)))
     return out.value
 
 
 def encode(col: np.ndarray, fixed_len: int = 0, starts=None,
-           force_constant: bool = False) -> np.ndarray:
+           force_constant: bool = False, regressor: str = "ls") -> np.ndarray:
     """Encode a uint32/uint64 column; returns the blob as a uint8 array."""
     col = np.ascontiguousarray(col)
     fl, s, m = _starts_arg(fixed_len, starts)
     size = C.c_uint64()
     L = lib()
+    reg = _regressor(regressor)
     st = L.leco_ref_encode(_ptr(col), len(col), _dtype_code(col), fl, _ptr(s), m,
-                           int(force_constant), None, 0, C.byref(size))
+                           int(force_constant), reg, None, 0, C.byref(size))
     if st != ENOSPC:
         _check("leco_ref_encode", st)
     blob = np.zeros(size.value, dtype=np.uint8)
     _check("leco_ref_encode", L.leco_ref_encode(
-        _ptr(col), len(col), _dtype_code(col), fl, _ptr(s), m, int(force_constant),
+        _ptr(col), len(col), _dtype_code(col), fl, _ptr(s), m, int(force_constant), reg,
         _ptr(blob), len(blob), C.byref(size)))
     return blob
 

@@ -10,6 +10,10 @@
  *  - widths use bitlen(x) = floor(log2 x) + 1, bitlen(0) = 0;
  *  - the regressor is least squares with exact integer sums (section 3.1
  *    states the closed form), slope = fl(N) / fl(D) in binary64;
+ *  - the optional minimax regressor takes the smallest slope minimising the
+ *    strip width (section 3.1's fixed-width objective, solved exactly from
+ *    the convex hulls), slope = fl(dy) / fl(dt) of the hull edge it lies on,
+ *    and replaces the stored model only when strictly narrower;
  *  - residuals are stored as unsigned offsets from their minimum, which is
  *    folded into an integer intercept "base" (the paper's theta0);
  *  - a partition falls back to the constant (FOR) model when that is not
@@ -102,13 +106,125 @@ static unsigned get_stream_bit(const uint8_t *words, uint64_t k) {
 
 /* ---- Regressor (section 3.1) ------------------------------------------------ */
 
+/* ---- Minimax regressor (section 3.1 objective) -----------------------------
+ *
+ * The fixed-width objective of section 3.1 asks for the line with the
+ * smallest maximum deviation |F(t) - v_t|.  For a slope theta the best
+ * intercept sits midway, so the deviation is half the vertical width
+ *   W(theta) = max_t (v_t - theta t) - min_t (v_t - theta t)
+ * of the strip that holds every point (t, v_t).  W is convex and piecewise
+ * linear; it bends only at the edge slopes of the upper and lower convex
+ * hulls of the points.  Its right derivative is t_lo - t_up, where t_up is
+ * the position of the upper-hull vertex maximising v_t - theta t just above
+ * theta and t_lo the lower-hull vertex maximising theta t - v_t.  Starting
+ * below every bend (t_up = n - 1, t_lo = 0) and passing the bends in
+ * increasing order, the smallest minimiser of W is the first bend after
+ * which t_lo >= t_up.  Reading: an upper and a lower edge of equal slope
+ * give the bend as the upper edge's fraction. */
+
+/* Sign of (q - p) x (r - p) for points p < q < r: > 0 when r lies above the
+ * line through p and q.  Values differ by less than 2^61, so differences are
+ * exact in int64 and products exact in int128. */
+static int turn(const uint64_t *v, uint64_t p, uint64_t q, uint64_t r) {
+  i128 a = (i128)(q - p) * (i128)(int64_t)(v[r] - v[p]);
+  i128 b = (i128)(int64_t)(v[q] - v[p]) * (i128)(r - p);
+  return a > b ? 1 : (a < b ? -1 : 0);
+}
+
+/* Upper (upper = 1) or lower hull of the points (t, v_t), left to right,
+ * with no vertex lying on an edge (Andrew's monotone chain). */
+static uint64_t hull_chain(const uint64_t *v, uint64_t n, int upper, uint64_t *h) {
+  uint64_t k = 0;
+  for (uint64_t t = 0; t < n; t++) {
+    while (k >= 2) {
+      int s = turn(v, h[k - 2], h[k - 1], t);
+      if (upper ? s >= 0 : s <= 0)
+        k--;
+      else
+        break;
+    }
+    h[k++] = t;
+  }
+  return k;
+}
+
+/* Compares the slope of edge a0 -> a1 with that of edge b0 -> b1. */
+static int slope_cmp(const uint64_t *v, uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1) {
+  i128 l = (i128)(int64_t)(v[a1] - v[a0]) * (i128)(b1 - b0);
+  i128 r = (i128)(int64_t)(v[b1] - v[b0]) * (i128)(a1 - a0);
+  return l < r ? -1 : (l > r ? 1 : 0);
+}
+
+int leco_ref_minimax_slope(const uint64_t *v, uint64_t n, int64_t *dy, uint64_t *dt) {
+  if (v == NULL || dy == NULL || dt == NULL || n < 2 || n > MAX_PART_LEN) return LREF_EINVAL;
+  uint64_t vmin = v[0], vmax = v[0];
+  for (uint64_t t = 1; t < n; t++) {
+    if (v[t] < vmin) vmin = v[t];
+    if (v[t] > vmax) vmax = v[t];
+  }
+  if (vmax - vmin >= (1ull << 61)) return LREF_EINVAL;
+  uint64_t *up = (uint64_t *)malloc(n * sizeof(uint64_t));
+  uint64_t *lo = (uint64_t *)malloc(n * sizeof(uint64_t));
+  if (!up || !lo) {
+    free(up);
+    free(lo);
+    return LREF_ENOMEM;
+  }
+  uint64_t nu = hull_chain(v, n, 1, up);
+  uint64_t nl = hull_chain(v, n, 0, lo);
+  uint64_t iu = nu - 1, il = 0; /* below every bend: t_up = n - 1, t_lo = 0 */
+  uint64_t e0 = 0, e1 = 1;
+  for (;;) {
+    /* the next bend: upper edge up[iu-1] -> up[iu] or lower edge lo[il] -> lo[il+1] */
+    int take_up;
+    if (iu == 0)
+      take_up = 0;
+    else if (il + 1 == nl)
+      take_up = 1;
+    else
+      take_up = slope_cmp(v, up[iu - 1], up[iu], lo[il], lo[il + 1]) <= 0;
+    if (take_up) {
+      e0 = up[iu - 1];
+      e1 = up[iu];
+    } else {
+      e0 = lo[il];
+      e1 = lo[il + 1];
+    }
+    /* pass every bend not above it */
+    while (iu > 0 && slope_cmp(v, up[iu - 1], up[iu], e0, e1) <= 0) iu--;
+    while (il + 1 < nl && slope_cmp(v, lo[il], lo[il + 1], e0, e1) <= 0) il++;
+    if (lo[il] >= up[iu]) break;
+  }
+  *dy = (int64_t)(v[e1] - v[e0]);
+  *dt = e1 - e0;
+  free(up);
+  free(lo);
+  return LREF_OK;
+}
+
+/* Residual extremes of the line with slope theta1 (section 3.1):
+ * r_t = (v_t - vmin) - floor(theta1 * t). */
+static void residual_range(const uint64_t *v, uint64_t n, uint64_t vmin, double theta1,
+                           int64_t *r_min, int64_t *r_max) {
+  for (uint64_t t = 0; t < n; t++) {
+    double prod = theta1 * (double)t;
+    int64_t p = (int64_t)floor(prod);
+    int64_t r = (int64_t)(v[t] - vmin) - p;
+    if (t == 0 || r < *r_min) *r_min = r;
+    if (t == 0 || r > *r_max) *r_max = r;
+  }
+}
+
 /* Least-squares line through (t, y_t), t = 0..n-1, from exact sums:
  *   slope = (n*S_ty - S_t*S_y) / (n*S_tt - S_t^2).
  * Then residuals r_t = y_t - floor(slope * t) and their width (section 3.1,
- * fixed-width deltas).  The constant model is kept when it is not wider. */
-int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant,
+ * fixed-width deltas).  The constant model is kept when it is not wider.
+ * With the minimax regressor the minimax line replaces the stored model
+ * when it is strictly narrower. */
+int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant, int regressor,
                  leco_ref_model *out) {
   if (n == 0 || n > MAX_PART_LEN || out == NULL) return LREF_EINVAL;
+  if (regressor != LREF_REG_LS && regressor != LREF_REG_MINIMAX) return LREF_EINVAL;
   memset(out, 0, sizeof(*out));
 
   uint64_t vmin = v[0], vmax = v[0];
@@ -155,23 +271,40 @@ int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant,
   out->theta1_ls = slope;
 
   int64_t r_min = 0, r_max = 0;
-  for (uint64_t t = 0; t < n; t++) {
-    double prod = slope * (double)t;
-    int64_t p = (int64_t)floor(prod);
-    int64_t r = (int64_t)(v[t] - vmin) - p;
-    if (t == 0 || r < r_min) r_min = r;
-    if (t == 0 || r > r_max) r_max = r;
-  }
+  residual_range(v, n, vmin, slope, &r_min, &r_max);
   out->r_min = r_min;
   out->r_max = r_max;
   out->b_ls = leco_ref_bitlen((uint64_t)r_max - (uint64_t)r_min);
 
-  if (out->b_for <= out->b_ls) return LREF_OK; /* ties keep the constant model */
+  if (out->b_ls < out->b_for) { /* ties keep the constant model */
+    out->mode = 1;
+    out->theta1 = slope;
+    out->base = vmin + (uint64_t)r_min;
+    out->bits = out->b_ls;
+  }
+  if (regressor != LREF_REG_MINIMAX) return LREF_OK;
 
-  out->mode = 1;
-  out->theta1 = slope;
-  out->base = vmin + (uint64_t)r_min;
-  out->bits = out->b_ls;
+  int64_t dy;
+  uint64_t dt;
+  int st = leco_ref_minimax_slope(v, n, &dy, &dt);
+  if (st != LREF_OK) return st;
+  double mm = (double)dy / (double)dt; /* one correctly rounded division */
+  if (mm == 0.0) mm = 0.0;
+  out->mm_fitted = 1;
+  out->mm_dy = dy;
+  out->mm_dt = dt;
+  out->theta1_mm = mm;
+  int64_t m_min = 0, m_max = 0;
+  residual_range(v, n, vmin, mm, &m_min, &m_max);
+  out->r_min_mm = m_min;
+  out->r_max_mm = m_max;
+  out->b_mm = leco_ref_bitlen((uint64_t)m_max - (uint64_t)m_min);
+  if (out->b_mm < out->bits) { /* ties keep the constant or least-squares model */
+    out->mode = 2;
+    out->theta1 = mm;
+    out->base = vmin + (uint64_t)m_min;
+    out->bits = out->b_mm;
+  }
   return LREF_OK;
 }
 
@@ -226,7 +359,7 @@ typedef struct {
 /* Fits every partition; fills codes[] and the section offsets. */
 static int plan_blob(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
                      const uint64_t *starts_in, uint64_t m_in, int force_constant,
-                     uint64_t **starts_out, uint64_t *m_out, part_code **codes_out,
+                     int regressor, uint64_t **starts_out, uint64_t *m_out, part_code **codes_out,
                      uint64_t *words_off, uint64_t *total_words,
                      uint64_t *blob_bytes) {
   if (dtype != 4 && dtype != 8) return LREF_EINVAL;
@@ -247,7 +380,13 @@ static int plan_blob(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
     uint64_t len = s[j + 1] - s[j];
     for (uint64_t t = 0; t < len; t++) buf[t] = load_value(col, dtype, s[j] + t);
     leco_ref_model md;
-    leco_ref_fit(buf, len, force_constant, &md);
+    st = leco_ref_fit(buf, len, force_constant, regressor, &md);
+    if (st != LREF_OK) {
+      free(s);
+      free(codes);
+      free(buf);
+      return st;
+    }
     codes[j].base = md.base;
     codes[j].theta1 = md.theta1;
     codes[j].bits = md.bits;
@@ -268,10 +407,10 @@ static int plan_blob(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
 
 int leco_ref_blob_bytes(const void *col, uint64_t n, int dtype,
                         uint64_t fixed_len, const uint64_t *starts, uint64_t m,
-                        int force_constant, uint64_t *bytes) {
+                        int force_constant, int regressor, uint64_t *bytes) {
   uint64_t *s, mm, wo, tw;
   part_code *codes;
-  int st = plan_blob(col, n, dtype, fixed_len, starts, m, force_constant, &s,
+  int st = plan_blob(col, n, dtype, fixed_len, starts, m, force_constant, regressor, &s,
                      &mm, &codes, &wo, &tw, bytes);
   if (st != LREF_OK) return st;
   free(s);
@@ -281,10 +420,10 @@ int leco_ref_blob_bytes(const void *col, uint64_t n, int dtype,
 
 int leco_ref_encode(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
                     const uint64_t *starts, uint64_t m_in, int force_constant,
-                    uint8_t *blob, uint64_t cap, uint64_t *blob_bytes) {
+                    int regressor, uint8_t *blob, uint64_t cap, uint64_t *blob_bytes) {
   uint64_t *s, m, words_off, total_words, size;
   part_code *codes;
-  int st = plan_blob(col, n, dtype, fixed_len, starts, m_in, force_constant, &s,
+  int st = plan_blob(col, n, dtype, fixed_len, starts, m_in, force_constant, regressor, &s,
                      &m, &codes, &words_off, &total_words, &size);
   if (st != LREF_OK) return st;
   if (blob_bytes) *blob_bytes = size;
@@ -598,7 +737,7 @@ uint64_t leco_ref_delta_partition_bits(const uint64_t *v, uint64_t i, uint64_t j
 
 uint64_t leco_ref_partition_cost_bytes(const uint64_t *v, uint64_t i, uint64_t j) {
   leco_ref_model md;
-  leco_ref_fit(v + i, j - i, 0, &md);
+  leco_ref_fit(v + i, j - i, 0, LREF_REG_LS, &md);
   return RECORD_BYTES + 8 + 8 * (((j - i) * md.bits + 63) / 64);
 }
 

@@ -39,7 +39,8 @@ typedef struct {
   uint64_t vmin, vmax;
   uint64_t b_for;      /* bitlen(vmax - vmin)                               */
   int32_t fitted;      /* 1 when the least-squares fit was evaluated        */
-  int32_t mode;        /* 0 = FOR (slope +0.0), 1 = linear                  */
+  int32_t mode;        /* 0 = FOR (slope +0.0), 1 = least-squares line,
+                          2 = minimax line                                 */
   uint64_t N_lo;       /* N = n*S_ty - S_t*S_y as two's-complement int128   */
   int64_t N_hi;
   uint64_t D_lo;       /* D = n*S_tt - S_t^2 as uint128                     */
@@ -47,30 +48,52 @@ typedef struct {
   double theta1_ls;    /* fl(N)/fl(D), the fitted slope (0 if not fitted)   */
   int64_t r_min, r_max;/* residual extremes of the linear model             */
   uint64_t b_ls;       /* bitlen(r_max - r_min)                             */
-  double theta1;       /* stored slope: theta1_ls in linear mode, else +0.0 */
+  double theta1;       /* stored slope: theta1_ls or theta1_mm, else +0.0   */
   uint64_t base;       /* stored integer intercept                          */
   uint64_t bits;       /* stored residual width b                           */
+  /* Minimax line (evaluated only with LREF_REG_MINIMAX). */
+  int32_t mm_fitted;   /* 1 when the minimax slope was evaluated            */
+  int32_t mm_pad;
+  int64_t mm_dy;       /* exact minimax slope mm_dy / mm_dt, mm_dt > 0      */
+  uint64_t mm_dt;
+  double theta1_mm;    /* fl(mm_dy) / fl(mm_dt)                             */
+  int64_t r_min_mm, r_max_mm;
+  uint64_t b_mm;       /* bitlen(r_max_mm - r_min_mm)                       */
 } leco_ref_model;
 
 /* bitlen(x) = floor(log2 x) + 1, bitlen(0) = 0 (the paper's ceil(log2 .)
  * read as "bits needed to store x"). */
 uint64_t leco_ref_bitlen(uint64_t x);
 
+/* Regressors (section 3.1).  LREF_REG_LS fits the least-squares line.
+ * LREF_REG_MINIMAX also fits the line of smallest maximum deviation (the
+ * fixed-width objective of section 3.1) and stores whichever of the
+ * constant model, the least-squares line and the minimax line is narrowest,
+ * ties going in that order. */
+enum { LREF_REG_LS = 0, LREF_REG_MINIMAX = 1 };
+
 /* Fit one partition of n values (section 3.1, section 3.3). */
 int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant,
-                 leco_ref_model *out);
+                 int regressor, leco_ref_model *out);
+
+/* Minimax slope of y_t = v_t, t = 0..n-1 (section 3.1 objective): the
+ * smallest theta minimising max_t (v_t - theta t) - min_t (v_t - theta t),
+ * as the exact fraction *dy / *dt (dt > 0).  Needs 2 <= n <= 2^20 and
+ * max(v) - min(v) < 2^61. */
+int leco_ref_minimax_slope(const uint64_t *v, uint64_t n, int64_t *dy,
+                           uint64_t *dt);
 
 /* Exact compressed size in bytes for a column under the given partitioning.
  * fixed_len > 0 selects fixed partitions; otherwise starts[0..m] is used. */
 int leco_ref_blob_bytes(const void *col, uint64_t n, int dtype,
                         uint64_t fixed_len, const uint64_t *starts, uint64_t m,
-                        int force_constant, uint64_t *bytes);
+                        int force_constant, int regressor, uint64_t *bytes);
 
 /* Encode a column into a self-describing blob (section 3, section 3.3).
  * On LREF_ENOSPC *blob_bytes holds the required size. */
 int leco_ref_encode(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
                     const uint64_t *starts, uint64_t m, int force_constant,
-                    uint8_t *blob, uint64_t cap, uint64_t *blob_bytes);
+                    int regressor, uint8_t *blob, uint64_t cap, uint64_t *blob_bytes);
 
 /* Blob header fields. */
 int leco_ref_blob_info(const uint8_t *blob, uint64_t blob_bytes, uint64_t *n,
