@@ -93,13 +93,25 @@ typedef enum { LECO_U32 = 4, LECO_U64 = 8 } leco_dtype;
  *                  starts_host[0] = 0 and starts_host[num_partitions] = n.
  *   Every partition holds 1..2^20 values.
  *   force_constant_model = 1 stores every partition with slope +0.0, which is
- *   exactly frame-of-reference encoding (section 2). */
+ *   exactly frame-of-reference encoding (section 2).
+ *   regressor (section 3.1): LECO_REGRESSOR_LS fits the least-squares line;
+ *   LECO_REGRESSOR_MINIMAX also fits the line of smallest maximum deviation
+ *   (the fixed-width objective of section 3.1: the smallest slope that
+ *   minimises the vertical width of the strip holding the partition's
+ *   points, taken exactly from their convex hulls, stored as fl(dy)/fl(dt)
+ *   of the hull edge it lies on) and stores it when its residual width is
+ *   strictly below both the constant model's and the least-squares line's.
+ *   Blobs of either regressor have the same format and decoder.  Minimax
+ *   partitions longer than 4096 values need 8 bytes of device scratch per
+ *   value of the column. */
+typedef enum { LECO_REGRESSOR_LS = 0, LECO_REGRESSOR_MINIMAX = 1 } leco_regressor;
+
 typedef struct {
   uint64_t fixed_len;
   const uint64_t *starts_host;
   uint64_t num_partitions;
   int32_t force_constant_model;
-  int32_t reserved; /* must be 0 */
+  int32_t regressor; /* leco_regressor; any other value is LECO_EINVAL */
 } leco_partitioning;
 
 /* Context on HIP device `hip_device`.  Owns the device error flag, scratch
@@ -189,12 +201,17 @@ typedef struct {
   void *blob_dev;
   uint64_t blob_cap;
   uint64_t *blob_bytes_dev;
+  int32_t regressor; /* leco_regressor, as in leco_partitioning */
+  int32_t reserved;  /* must be 0 */
 } leco_encode_job;
 
-/* Encodes every job in one launch (plus a clearing launch): partitions of
- * all columns are taken in ticket order by workgroups, and each column's
- * word offsets come from a look-back confined to that column.  Enqueues
- * only; jobs_host is copied before the call returns. */
+/* Encodes every job with one sequence of launches per group of columns
+ * (columns whose partitions fit one wavefront, and the others): a fit
+ * launch writes every partition's model and word count, a scan gives the
+ * word offsets within each column, and a pack launch writes the residual
+ * words; no partition waits for another.  Produces exactly the blobs of
+ * leco_encode.  Enqueues only; jobs_host is copied before the call
+ * returns. */
 leco_status leco_encode_batch(leco_ctx *ctx, const leco_encode_job *jobs_host,
                               uint64_t ncols, hipStream_t stream);
 

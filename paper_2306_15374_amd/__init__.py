@@ -52,7 +52,8 @@ class EncodeJob(C.Structure):
     _fields_ = [("col_dev", C.c_void_p), ("n", C.c_uint64), ("dtype", C.c_int),
                 ("force_constant_model", C.c_int32), ("fixed_len", C.c_uint64),
                 ("blob_dev", C.c_void_p), ("blob_cap", C.c_uint64),
-                ("blob_bytes_dev", C.c_void_p)]
+                ("blob_bytes_dev", C.c_void_p), ("regressor", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class DecodeJob(C.Structure):
@@ -92,7 +93,7 @@ class ServerStats(C.Structure):
 class Partitioning(C.Structure):
     _fields_ = [("fixed_len", C.c_uint64), ("starts_host", C.c_void_p),
                 ("num_partitions", C.c_uint64), ("force_constant_model", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("regressor", C.c_int32)]
 
 
 _lib = None
@@ -175,13 +176,25 @@ def _dtype_code(t) -> int:
     raise TypeError(f"column dtype must be 32- or 64-bit integer, got {t.dtype}")
 
 
-def make_partitioning(fixed_len: int = 0, starts=None, force_constant: bool = False):
+REGRESSORS = {"ls": 0, "minimax": 1}  # leco_regressor
+
+
+def regressor_code(name: str) -> int:
+    try:
+        return REGRESSORS[name]
+    except KeyError:
+        raise ValueError(f"regressor must be one of {sorted(REGRESSORS)}, got {name!r}") from None
+
+
+def make_partitioning(fixed_len: int = 0, starts=None, force_constant: bool = False,
+                      regressor: str = "ls"):
     """Returns (Partitioning, keepalive) for a fixed length or host starts."""
     import numpy as np
+    reg = regressor_code(regressor)
     if fixed_len:
-        return Partitioning(fixed_len, None, 0, int(force_constant), 0), None
+        return Partitioning(fixed_len, None, 0, int(force_constant), reg), None
     s = np.ascontiguousarray(starts, dtype=np.uint64)
-    return Partitioning(0, s.ctypes.data, len(s) - 1, int(force_constant), 0), s
+    return Partitioning(0, s.ctypes.data, len(s) - 1, int(force_constant), reg), s
 
 
 # ---- C-named wrappers ----------------------------------------------------------
@@ -404,11 +417,11 @@ class Codec:
         self.check("leco_sync", leco_sync(self.ctx, stream))
 
     def encode(self, col, fixed_len: int = 0, starts=None, force_constant: bool = False,
-               stream=None):
+               stream=None, regressor: str = "ls"):
         """Encodes a CUDA tensor column; returns the blob (uint8 tensor)."""
         import torch
         dt = _dtype_code(col)
-        part, keep = make_partitioning(fixed_len, starts, force_constant)
+        part, keep = make_partitioning(fixed_len, starts, force_constant, regressor)
         cap = leco_max_blob_bytes(col.numel(), dt, part)
         buf = torch.empty(cap, dtype=torch.uint8, device=col.device)
         st, size = leco_encode(self.ctx, col, col.numel(), dt, part, buf, cap, stream)

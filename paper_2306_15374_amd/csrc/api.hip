@@ -60,7 +60,8 @@ leco_status get_scratch(leco_ctx* ctx, size_t bytes, void** out) {
 leco_status check_partitioning(leco_ctx* ctx, uint64_t n, const leco_partitioning* part,
                                uint64_t* m_out, uint64_t* max_len_out = nullptr) {
   if (!part) return fail(ctx, LECO_EINVAL, "partitioning is null");
-  if (part->reserved != 0) return fail(ctx, LECO_EINVAL, "reserved field must be 0");
+  if (part->regressor != LECO_REGRESSOR_LS && part->regressor != LECO_REGRESSOR_MINIMAX)
+    return fail(ctx, LECO_EINVAL, "unknown regressor %d", int(part->regressor));
   if (part->fixed_len > 0) {
     if (part->fixed_len > kMaxPartLen)
       return fail(ctx, LECO_EINVAL, "fixed_len %llu exceeds 2^20",
@@ -121,6 +122,8 @@ leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtyp
   const size_t o_enc = off;    off = align256(off + leco::encode_scratch_bytes(m));
   const size_t o_misc = off;   off = align256(off + 16);
   const size_t o_starts = off; off = align256(off + (variable ? 8 * (m + 1) : 8));
+  const bool hulls = part->regressor == LECO_REGRESSOR_MINIMAX && call->max_len > leco::kHullTileValues;
+  const size_t o_hull = off;   off = align256(off + (hulls ? 8 * n : 0));
   void* scr = nullptr;
   st = get_scratch(ctx, off, &scr);
   if (st != LECO_OK) return st;
@@ -137,7 +140,14 @@ leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtyp
   c.part_base = 0;
   c.dtype = uint32_t(dtype);
   c.force_constant = part->force_constant_model ? 1 : 0;
+  c.regressor = uint32_t(part->regressor);
+  c.pad = 0;
+  c.val_base = 0;
   call->scr = leco::carve_encode_scratch(b + o_enc, m);
+  if (hulls) {
+    call->scr.hull = reinterpret_cast<uint32_t*>(b + o_hull);
+    call->scr.hull_values = n;
+  }
   call->size_dev = reinterpret_cast<uint64_t*>(b + o_misc);
   c.size_out = call->size_dev;
   if (variable) {
@@ -317,7 +327,7 @@ static leco_status encode_common(leco_ctx* ctx, const void* col, uint64_t n, lec
   if (st != LECO_OK) return st;
   if (size_dev) call->col.size_out = size_dev;
   HIP_TRY(ctx, leco::launch_encode_columns(ctx, nullptr, 1, call->col, call->col.m, call->max_len,
-                                           call->scr, stream));
+                                           call->col.regressor != 0, call->scr, stream));
   return LECO_OK;
 }
 
@@ -360,7 +370,8 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
   // Columns whose partitions fit one wavefront go to one sequence of
   // launches, the others to a second.
   std::vector<leco::EncColumn> cols[2];
-  uint64_t parts[2] = {0, 0}, longest[2] = {0, 0};
+  uint64_t parts[2] = {0, 0}, longest[2] = {0, 0}, values[2] = {0, 0};
+  bool minimax[2] = {false, false};
   for (uint64_t i = 0; i < ncols; ++i) {
     const leco_encode_job& j = jobs[i];
     if (j.dtype != LECO_U32 && j.dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "job %llu: bad dtype", (unsigned long long)i);
@@ -369,7 +380,9 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
     if ((j.n && !j.col_dev) || !j.blob_dev || !j.blob_bytes_dev || !aligned16(j.blob_dev) ||
         (reinterpret_cast<uintptr_t>(j.col_dev) % j.dtype))
       return fail(ctx, LECO_EINVAL, "job %llu: null or misaligned buffer", (unsigned long long)i);
-    leco_partitioning part{j.fixed_len, nullptr, 0, j.force_constant_model, 0};
+    if ((j.regressor != LECO_REGRESSOR_LS && j.regressor != LECO_REGRESSOR_MINIMAX) || j.reserved != 0)
+      return fail(ctx, LECO_EINVAL, "job %llu: bad regressor or reserved field", (unsigned long long)i);
+    leco_partitioning part{j.fixed_len, nullptr, 0, j.force_constant_model, j.regressor};
     uint64_t bound = 0;
     leco_max_blob_bytes(j.n, j.dtype, &part, &bound);
     if (j.blob_cap < bound)
@@ -390,17 +403,25 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
     c.part_base = parts[g];
     c.dtype = uint32_t(j.dtype);
     c.force_constant = j.force_constant_model ? 1 : 0;
+    c.regressor = uint32_t(j.regressor);
+    c.pad = 0;
+    c.val_base = values[g];
     parts[g] += c.m;
+    values[g] += c.n;
     if (len > longest[g]) longest[g] = len;
+    if (j.regressor == LECO_REGRESSOR_MINIMAX) minimax[g] = true;
     cols[g].push_back(c);
   }
   if (ncols == 0) return LECO_OK;
   if (parts[0] >= (uint64_t(1) << 31) || parts[1] >= (uint64_t(1) << 31))
     return fail(ctx, LECO_EINVAL, "too many partitions in one batch");
-  size_t off = 0, o_enc[2], o_cols[2];
+  size_t off = 0, o_enc[2], o_cols[2], o_hull[2];
+  bool hulls[2];
   for (int g = 0; g < 2; ++g) {
+    hulls[g] = minimax[g] && longest[g] > leco::kHullTileValues;
     o_enc[g] = off;  off = align256(off + leco::encode_scratch_bytes(parts[g]));
     o_cols[g] = off; off = align256(off + sizeof(leco::EncColumn) * (cols[g].size() + 1));
+    o_hull[g] = off; off = align256(off + (hulls[g] ? 8 * values[g] : 0));
   }
   void* scr = nullptr;
   leco_status st = get_scratch(ctx, off, &scr);
@@ -411,10 +432,13 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
     leco::EncColumn* cols_dev = reinterpret_cast<leco::EncColumn*>(b + o_cols[g]);
     HIP_TRY(ctx, hipMemcpyAsync(cols_dev, cols[g].data(), sizeof(leco::EncColumn) * cols[g].size(),
                                 hipMemcpyHostToDevice, stream));
+    leco::EncScratch es = leco::carve_encode_scratch(b + o_enc[g], parts[g]);
+    if (hulls[g]) {
+      es.hull = reinterpret_cast<uint32_t*>(b + o_hull[g]);
+      es.hull_values = values[g];
+    }
     HIP_TRY(ctx, leco::launch_encode_columns(ctx, cols_dev, cols[g].size(), cols[g][0], parts[g],
-                                             longest[g],
-                                             leco::carve_encode_scratch(b + o_enc[g], parts[g]),
-                                             stream));
+                                             longest[g], minimax[g], es, stream));
   }
   return LECO_OK;
 }

@@ -22,6 +22,7 @@
 #include "fit.hpp"
 #include "internal.hpp"
 #include "leco_dev.hpp"
+#include "minimax.hpp"
 
 namespace leco {
 
@@ -62,9 +63,11 @@ __device__ inline T meta_load(const T* p, uint64_t i) {
 }
 
 constexpr uint32_t kColWords = sizeof(EncColumn) / 8;
-static_assert(sizeof(EncColumn) == 88 && offsetof(EncColumn, part_base) == 72 &&
-                  offsetof(EncColumn, dtype) == 80,
+static_assert(sizeof(EncColumn) == 104 && offsetof(EncColumn, part_base) == 72 &&
+                  offsetof(EncColumn, dtype) == 80 && offsetof(EncColumn, regressor) == 88 &&
+                  offsetof(EncColumn, val_base) == 96,
               "column entry layout");
+static_assert(kHullTile == kHullTileValues, "hull tile");
 
 // The column holding partition P: the kernel argument of a one-column
 // launch, else the last table entry with part_base <= P, read word by word
@@ -93,6 +96,9 @@ __device__ inline EncColumn column_of(const EncColumn* cols, uint64_t ncols,
   const uint64_t w = meta_load(t, e + 10);
   c.dtype = uint32_t(w);
   c.force_constant = uint32_t(w >> 32);
+  c.regressor = uint32_t(meta_load(t, e + 11));
+  c.pad = 0;
+  c.val_base = meta_load(t, e + 12);
   return c;
 }
 
@@ -345,6 +351,140 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __rest
   if (threadIdx.x == 0) store_model(scr, P, md, len);
 }
 
+// ---- fit with the minimax regressor: one workgroup per partition ------------------
+
+// The least-squares model of fit_block, then (minimax) the minimax line
+// of section 3.1's fixed-width objective, stored instead when its residual
+// width is strictly smaller.  run_up / run_lo: the partition's running hulls
+// when it spans several hull tiles.
+template <class T>
+__device__ inline Model fit_minimax(FitShared& fs, HullShared& hs, const T* src, uint64_t len,
+                                    bool force_constant, bool minimax, uint32_t* run_up,
+                                    uint32_t* run_lo) {
+  Model md = fit_block(fs, src, len, force_constant);
+  // the same partitions as the least-squares line: len > 1, range < 2^61
+  if (!minimax || len < 2 || force_constant || !(md.linear || md.bits <= 61)) return md;
+  const auto gsrc = global_ptr(src);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t ntiles = uint32_t((len + kHullTile - 1) / kHullTile);
+  for (uint32_t k = 0; k < ntiles; ++k) {
+    const uint32_t t0 = k * kHullTile;
+    const uint32_t cnt = uint32_t(len - t0 < kHullTile ? len - t0 : kHullTile);
+    for (uint32_t x = tid; x < cnt; x += kEncBlock) hs.v[x] = uint64_t(gsrc[t0 + x]);
+    __syncthreads();
+    tile_hulls(hs, cnt);
+    if (ntiles == 1) break;
+    uint32_t keep[2], from[2], c[2];
+    for (uint32_t side = 0; side < 2; ++side) c[side] = hs.cnt[side][0];
+    if (k == 0) {
+      keep[0] = keep[1] = from[0] = from[1] = 0;
+    } else {
+      if (tid < 2) {
+        const uint32_t side = tid;
+        const uint32_t* R = side ? run_lo : run_up;
+        const auto A = [&](uint32_t i) {
+          const uint32_t t = R[i];
+          return HullPoint{t, uint64_t(gsrc[t])};
+        };
+        const auto B = [&](uint32_t j) {
+          const uint32_t x = hs.h[side][j];
+          return HullPoint{t0 + x, hs.v[x]};
+        };
+        uint32_t kp, fr;
+        hull_bridge(side == 0, A, hs.rcnt[side], B, c[side], kp, fr);
+        hs.rkeep[side] = kp;
+        hs.rfrom[side] = fr;
+      }
+      __syncthreads();
+      for (uint32_t side = 0; side < 2; ++side) {
+        keep[side] = hs.rkeep[side];
+        from[side] = hs.rfrom[side];
+      }
+    }
+    for (uint32_t side = 0; side < 2; ++side) {
+      uint32_t* R = side ? run_lo : run_up;
+      for (uint32_t x = tid; x < c[side] - from[side]; x += kEncBlock)
+        R[keep[side] + x] = t0 + hs.h[side][from[side] + x];
+    }
+    __syncthreads();
+    if (tid < 2) hs.rcnt[tid] = keep[tid] + c[tid] - from[tid];
+    __syncthreads();
+  }
+  EdgeSlope th;
+  if (ntiles == 1) {
+    const auto U = [&](uint32_t i) {
+      const uint32_t t = hs.h[0][i];
+      return HullPoint{t, hs.v[t]};
+    };
+    const auto L = [&](uint32_t i) {
+      const uint32_t t = hs.h[1][i];
+      return HullPoint{t, hs.v[t]};
+    };
+    th = minimax_bend(hs, U, hs.cnt[0][0], L, hs.cnt[1][0]);
+  } else {
+    const auto U = [&](uint32_t i) {
+      const uint32_t t = run_up[i];
+      return HullPoint{t, uint64_t(gsrc[t])};
+    };
+    const auto L = [&](uint32_t i) {
+      const uint32_t t = run_lo[i];
+      return HullPoint{t, uint64_t(gsrc[t])};
+    };
+    th = minimax_bend(hs, U, hs.rcnt[0], L, hs.rcnt[1]);
+  }
+  // one correctly rounded division of the exact edge fraction
+  double theta = static_cast<double>(th.dy) / static_cast<double>(th.dt);
+  if (theta == 0.0) theta = 0.0;  // +0.0, never -0.0
+  int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+  for (uint32_t t = tid; t < len; t += kEncBlock) {
+    const uint64_t x = ntiles == 1 ? hs.v[t] : uint64_t(gsrc[t]);
+    const int64_t rr = int64_t(x - md.vmin) - predict(theta, t);
+    rmin = rr < rmin ? rr : rmin;
+    rmax = rr > rmax ? rr : rmax;
+  }
+  block_minmax_i64(fs, rmin, rmax);
+  const uint32_t b = bitlen64(uint64_t(rmax) - uint64_t(rmin));
+  if (b < md.bits) {
+    md.linear = true;
+    md.theta1 = theta;
+    md.base = md.vmin + uint64_t(rmin);
+    md.bits = b;
+    md.rmin = rmin;
+  }
+  return md;
+}
+
+__global__ __launch_bounds__(kEncBlock) void k_fit_minimax(const EncColumn* __restrict__ cols,
+                                                          uint64_t ncols, EncColumn single,
+                                                          uint64_t nparts, EncScratch scr,
+                                                          int* err) {
+  __shared__ FitShared fs;
+  __shared__ HullShared hs;
+  const uint64_t P = blockIdx.x;
+  if (P >= nparts) return;
+  const EncColumn c = column_of(cols, ncols, single, P);
+  uint64_t start, len;
+  part_bounds(c, P - c.part_base, start, len);
+  bool minimax = c.regressor != 0;
+  uint32_t *run_up = nullptr, *run_lo = nullptr;
+  if (minimax && len > kHullTile) {
+    if (scr.hull == nullptr) {  // the host allocates running hulls for such launches
+      if (threadIdx.x == 0) raise(err, kErrDevice);
+      minimax = false;
+    } else {
+      run_up = scr.hull + c.val_base + start;
+      run_lo = scr.hull + scr.hull_values + c.val_base + start;
+    }
+  }
+  const Model md =
+      c.dtype == 8
+          ? fit_minimax(fs, hs, reinterpret_cast<const uint64_t*>(c.col) + start, len,
+                        c.force_constant, minimax, run_up, run_lo)
+          : fit_minimax(fs, hs, reinterpret_cast<const uint32_t*>(c.col) + start, len,
+                        c.force_constant, minimax, run_up, run_lo);
+  if (threadIdx.x == 0) store_model(scr, P, md, len);
+}
+
 // ---- scan: word offsets ------------------------------------------------------------
 
 // Exclusive prefix sum of x over the workgroup's threads; *total receives
@@ -553,19 +693,24 @@ EncScratch carve_encode_scratch(void* p, uint64_t nparts) {
   s.theta = q + 3 * k;
   s.bsum = q + 4 * k;
   s.bits = reinterpret_cast<uint32_t*>(q + 4 * k + ng + 1);
+  s.hull = nullptr;
+  s.hull_values = 0;
   return s;
 }
 
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                                  const EncColumn& single, uint64_t nparts, uint64_t max_len,
-                                 const EncScratch& scr, hipStream_t stream) {
+                                 bool minimax, const EncScratch& scr, hipStream_t stream) {
   const uint64_t cg = (ncols + 255) / 256;
   hipLaunchKernelGGL(k_encode_prepare, dim3(uint32_t(cg < 4096 ? cg : 4096)), dim3(256), 0,
                      stream, cols_dev, ncols, single, ctx->err_dev);
   if (nparts == 0) return hipGetLastError();
   const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave;
   const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
-  if (wave)
+  if (minimax)
+    hipLaunchKernelGGL(k_fit_minimax, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
+                       ncols, single, nparts, scr, ctx->err_dev);
+  else if (wave)
     hipLaunchKernelGGL(k_fit_wave, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream, cols_dev, ncols,
                        single, nparts, scr, ctx->err_dev);
   else

@@ -34,6 +34,9 @@ struct EncColumn {
   uint64_t words_off;      // offset of the words section
   uint64_t part_base;      // index of the column's first partition in the launch
   uint32_t dtype, force_constant;
+  uint32_t regressor;      // 0 least squares, 1 minimax as well
+  uint32_t pad;
+  uint64_t val_base;       // index of the column's first value in the launch
 };
 
 // Decode tile size (log2 of values per workgroup tile) for a blob of
@@ -51,10 +54,11 @@ hipError_t launch_random_access(leco_ctx* ctx, const void* blob, uint64_t blob_b
 hipError_t launch_filter_sum(leco_ctx* ctx, const void* blob, uint64_t blob_bytes, uint64_t lo,
                              uint64_t hi, uint64_t* out3, bool prune, hipStream_t stream);
 hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t stream);
-// Encodes ncols columns (table cols_dev, or `single` when cols_dev is null)
-// with nparts partitions in total; status holds nparts look-back words.
 // Partitions of at most this many values are encoded one per wavefront.
 constexpr uint64_t kWaveEncodeMax = 1024;
+// Minimax partitions longer than this many values keep running hulls in
+// EncScratch::hull.
+constexpr uint64_t kHullTileValues = 4096;
 
 // Device scratch of one encode launch (nparts partitions): the fitted
 // models, their word counts and offsets, and the scan's per-workgroup sums.
@@ -65,14 +69,22 @@ struct EncScratch {
   uint64_t* theta;  // bits of the binary64 slope
   uint64_t* bsum;
   uint32_t* bits;
+  // running hulls of minimax partitions longer than one hull tile: upper
+  // vertex k of the partition at launch value s is hull[s + k], lower is
+  // hull[hull_values + s + k]; null when no such partition is encoded
+  uint32_t* hull;
+  uint64_t hull_values;
 };
 uint64_t encode_scratch_bytes(uint64_t nparts);
 EncScratch carve_encode_scratch(void* p, uint64_t nparts);
 
-// max_len: the longest partition of the launch (selects the kernels).
+// Encodes ncols columns (table cols_dev, or `single` when cols_dev is null)
+// with nparts partitions in total.  max_len: the longest partition of the
+// launch (selects the kernels); minimax: some column asks for the minimax
+// regressor (fits every partition with the minimax kernel).
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                                  const EncColumn& single, uint64_t nparts, uint64_t max_len,
-                                 const EncScratch& scr, hipStream_t stream);
+                                 bool minimax, const EncScratch& scr, hipStream_t stream);
 hipError_t launch_diag_slope(const uint64_t* in, uint64_t k, double* out, hipStream_t stream);
 hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t bytes,
                             hipStream_t stream);

@@ -1,0 +1,255 @@
+// Minimax line of a partition (section 3.1's fixed-width objective): the
+// smallest slope minimising the vertical width of the strip that holds every
+// point (t, v_t).  The width, as a function of the slope, is convex and bends
+// only at edge slopes of the upper and lower convex hulls of the points; its
+// right derivative there is t_lo - t_up, the positions of the lower-hull and
+// upper-hull vertices that touch the strip just above the bend.  The answer
+// is the smallest bend at which t_lo >= t_up, as the exact fraction dy / dt of
+// the hull edge it comes from (an upper edge when an upper and a lower edge
+// have the same slope).
+//
+// GPU layout, one workgroup per partition, tiles of 4096 points:
+//   * every thread builds the hulls of its 16 consecutive points in LDS;
+//   * eight rounds merge neighbouring hulls pairwise: one thread per pair
+//     and side walks to the bridge (the common tangent), then the group
+//     moves the right hull's kept vertices next to the left hull's;
+//   * a partition of several tiles merges each tile's hulls into a running
+//     hull held in global scratch, in the same way;
+//   * every hull edge is tested as the answer at once: its right-derivative
+//     sign needs one binary search over the other hull; a workgroup
+//     minimum picks the smallest passing edge.
+// Cross products are exact: positions differ by less than 2^20 and values by
+// less than 2^61, so differences fit int64 and products int128.
+#pragma once
+
+#include "fit.hpp"
+
+namespace leco {
+
+constexpr uint32_t kHullChunk = 16;                        // points per thread
+constexpr uint32_t kHullTile = kEncBlock * kHullChunk;     // points per tile
+
+struct HullPoint {
+  uint32_t t;   // position in the partition
+  uint64_t v;   // value
+};
+
+// Whether q leaves the upper (lower) hull of p, q, r with p.t < q.t < r.t:
+// r lies on or above (on or below) the line through p and q.
+__device__ inline bool hull_drops(bool upper, HullPoint p, HullPoint q, HullPoint r) {
+  const __int128 a = __int128(int64_t(q.t - p.t)) * int64_t(r.v - p.v);
+  const __int128 b = __int128(int64_t(q.v - p.v)) * int64_t(r.t - p.t);
+  return upper ? a >= b : a <= b;
+}
+
+struct EdgeSlope {
+  int64_t dy;
+  uint32_t dt;  // > 0
+};
+
+__device__ inline EdgeSlope edge_slope(HullPoint a, HullPoint b) {
+  return EdgeSlope{int64_t(b.v - a.v), b.t - a.t};
+}
+
+__device__ inline bool slope_le(EdgeSlope a, EdgeSlope b) {
+  return __int128(a.dy) * b.dt <= __int128(b.dy) * a.dt;
+}
+
+__device__ inline bool slope_lt(EdgeSlope a, EdgeSlope b) {
+  return __int128(a.dy) * b.dt < __int128(b.dy) * a.dt;
+}
+
+// Bridge of hull A (p vertices) and hull B (q vertices), A entirely left of
+// B: the union's hull is A[0, keep) followed by B[from, q).  A(i) and B(j)
+// return vertices.  Walks inwards from the facing ends until neither end
+// can move.
+template <class PA, class PB>
+__device__ inline void hull_bridge(bool upper, const PA& A, uint32_t p, const PB& B, uint32_t q,
+                                   uint32_t& keep, uint32_t& from) {
+  uint32_t i = p - 1, j = 0;
+  HullPoint a = A(i), b = B(j);
+  for (;;) {
+    bool moved = false;
+    while (i > 0) {
+      const HullPoint a0 = A(i - 1);
+      if (!hull_drops(upper, a0, a, b)) break;
+      a = a0;
+      --i;
+      moved = true;
+    }
+    while (j + 1 < q) {
+      const HullPoint b1 = B(j + 1);
+      if (!hull_drops(upper, a, b, b1)) break;
+      b = b1;
+      ++j;
+      moved = true;
+    }
+    if (!moved) break;
+  }
+  keep = i + 1;
+  from = j;
+}
+
+struct HullShared {
+  uint64_t v[kHullTile];            // the tile's values
+  uint16_t h[2][kHullTile];         // upper, lower hull vertices (tile positions)
+  uint16_t cnt[2][kEncBlock];       // hull sizes, at each group's first thread
+  uint16_t keep[2][kEncBlock];      // bridge results, at each group's first thread
+  uint16_t from[2][kEncBlock];
+  uint32_t rcnt[2];                 // running hull sizes (partitions of several tiles)
+  uint32_t rkeep[2], rfrom[2];      // bridge of the running hull and the tile's
+  int64_t red_dy[kEncWaves];
+  uint32_t red_dt[kEncWaves];
+  uint32_t red_flag[kEncWaves];
+};
+
+// Upper and lower hulls of the tile's points 0 .. cnt-1 (values in sh.v),
+// left in sh.h[side][0 .. sh.cnt[side][0]).  Called by the whole workgroup.
+__device__ inline void tile_hulls(HullShared& sh, uint32_t cnt) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t c0 = tid * kHullChunk;
+  const uint32_t c1 = c0 + kHullChunk < cnt ? c0 + kHullChunk : (c0 < cnt ? cnt : c0);
+  for (uint32_t side = 0; side < 2; ++side) {
+    uint16_t* H = sh.h[side] + c0;
+    uint32_t k = 0;
+    for (uint32_t t = c0; t < c1; ++t) {
+      const HullPoint r{t, sh.v[t]};
+      while (k >= 2 && hull_drops(side == 0, HullPoint{H[k - 2], sh.v[H[k - 2]]},
+                                  HullPoint{H[k - 1], sh.v[H[k - 1]]}, r))
+        --k;
+      H[k++] = uint16_t(t);
+    }
+    sh.cnt[side][tid] = uint16_t(k);
+  }
+  __syncthreads();
+  for (uint32_t G = 2; G <= uint32_t(kEncBlock); G <<= 1) {
+    const uint32_t half = G >> 1, r = tid & (G - 1), g = tid - r;
+    if (r < 2) {
+      const uint32_t side = r;
+      const uint32_t p = sh.cnt[side][g], q = sh.cnt[side][g + half];
+      uint32_t keep = p, from = q;  // an empty right hull adds nothing
+      if (q > 0 && p == 0) {
+        keep = 0;
+        from = 0;
+      } else if (q > 0) {
+        const uint16_t* HA = sh.h[side] + kHullChunk * g;
+        const uint16_t* HB = sh.h[side] + kHullChunk * (g + half);
+        const auto A = [&](uint32_t i) { return HullPoint{HA[i], sh.v[HA[i]]}; };
+        const auto B = [&](uint32_t j) { return HullPoint{HB[j], sh.v[HB[j]]}; };
+        hull_bridge(side == 0, A, p, B, q, keep, from);
+      }
+      sh.keep[side][g] = uint16_t(keep);
+      sh.from[side][g] = uint16_t(from);
+    }
+    __syncthreads();
+    // the right hull's kept vertices, staged so that moving them left never
+    // overwrites one not yet read: at most 16 * half / G = 8 per thread
+    constexpr uint32_t kStage = kHullChunk / 2;
+    uint16_t stage[2][kStage];
+    uint32_t moved[2];
+    for (uint32_t side = 0; side < 2; ++side) {
+      const uint32_t q = sh.cnt[side][g + half], from = sh.from[side][g];
+      moved[side] = q - from;
+      const uint16_t* HB = sh.h[side] + kHullChunk * (g + half) + from;
+#pragma unroll
+      for (uint32_t s = 0; s < kStage; ++s) {
+        const uint32_t x = r + s * G;
+        stage[side][s] = x < moved[side] ? HB[x] : 0;
+      }
+    }
+    __syncthreads();
+    for (uint32_t side = 0; side < 2; ++side) {
+      const uint32_t keep = sh.keep[side][g];
+      uint16_t* HA = sh.h[side] + kHullChunk * g + keep;
+#pragma unroll
+      for (uint32_t s = 0; s < kStage; ++s) {
+        const uint32_t x = r + s * G;
+        if (x < moved[side]) HA[x] = stage[side][s];
+      }
+      if (r == side) sh.cnt[side][g] = uint16_t(keep + moved[side]);
+    }
+    __syncthreads();
+  }
+}
+
+// The smallest hull edge slope at which the strip width stops decreasing,
+// over hulls U (nu vertices) and L (nl vertices) given by accessors.  Every
+// thread receives the answer.  Called by the whole workgroup.
+template <class PU, class PL>
+__device__ inline EdgeSlope minimax_bend(HullShared& sh, const PU& U, uint32_t nu, const PL& L,
+                                         uint32_t nl) {
+  const uint32_t tid = threadIdx.x;
+  bool found = false, from_upper = false;
+  EdgeSlope best{0, 1};
+  const uint32_t edges = (nu - 1) + (nl - 1);
+  for (uint32_t e = tid; e < edges; e += kEncBlock) {
+    EdgeSlope th;
+    uint32_t t_up, t_lo;
+    bool upper_edge;
+    if (e < nu - 1) {
+      // upper edge e: just above its slope the strip touches U[e] from above
+      upper_edge = true;
+      const HullPoint a = U(e);
+      th = edge_slope(a, U(e + 1));
+      t_up = a.t;
+      // and L[c] from below, c = number of lower edges with slope <= th
+      uint32_t lo = 0, hi = nl - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (slope_le(edge_slope(L(mid), L(mid + 1)), th)) lo = mid + 1; else hi = mid;
+      }
+      t_lo = L(lo).t;
+    } else {
+      upper_edge = false;
+      const uint32_t j = e - (nu - 1);
+      const HullPoint b = L(j + 1);
+      th = edge_slope(L(j), b);
+      t_lo = b.t;
+      // U[k], k = first upper edge with slope <= th (upper slopes decrease)
+      uint32_t lo = 0, hi = nu - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (slope_le(edge_slope(U(mid), U(mid + 1)), th)) hi = mid; else lo = mid + 1;
+      }
+      t_up = U(lo).t;
+    }
+    if (t_lo >= t_up) {
+      const bool better = !found || slope_lt(th, best) || (!slope_lt(best, th) && upper_edge && !from_upper);
+      if (better) {
+        found = true;
+        best = th;
+        from_upper = upper_edge;
+      }
+    }
+  }
+  // workgroup minimum: by value, upper edges first among equal values
+  uint32_t flag = (found ? 2u : 0u) | (from_upper ? 1u : 0u);
+  const auto take = [&](int64_t dy, uint32_t dt, uint32_t f) {
+    if (!(f & 2)) return;
+    const EdgeSlope o{dy, dt};
+    if (!(flag & 2) || slope_lt(o, best) || (!slope_lt(best, o) && (f & 1) && !(flag & 1))) {
+      best = o;
+      flag = f;
+    }
+  };
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const int64_t dy = static_cast<int64_t>(__shfl_xor(static_cast<long long>(best.dy), m, 64));
+    const uint32_t dt = static_cast<uint32_t>(__shfl_xor(static_cast<int>(best.dt), m, 64));
+    const uint32_t f = static_cast<uint32_t>(__shfl_xor(static_cast<int>(flag), m, 64));
+    take(dy, dt, f);
+  }
+  const uint32_t lane = tid & 63, wave = tid >> 6;
+  if (lane == 0) {
+    sh.red_dy[wave] = best.dy;
+    sh.red_dt[wave] = best.dt;
+    sh.red_flag[wave] = flag;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kEncWaves; ++w) take(sh.red_dy[w], sh.red_dt[w], sh.red_flag[w]);
+  __syncthreads();
+  return best;
+}
+
+}  // namespace leco
