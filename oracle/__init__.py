@@ -67,6 +67,8 @@ def _regressor(name: str) -> int:
         raise ValueError(f"regressor must be one of {sorted(REGRESSORS)}, got {name!r}") from None
 
 
+COST_FN = C.CFUNCTYPE(C.c_uint64, C.c_void_p, C.c_uint64)
+
 _lib = None
 
 
@@ -109,12 +111,17 @@ def _bind(L: C.CDLL) -> C.CDLL:
     L.leco_ref_partition_dp.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
     L.leco_ref_partition_bruteforce.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
     L.leco_ref_partitioning_cost.argtypes = [vp, u64, C.c_int, vp, u64, P(u64)]
+    L.leco_ref_fixed_cost.argtypes = [vp, u64, C.c_int, vp, u64, u64, u64, C.c_int, P(u64)]
+    L.leco_ref_size_search_fn.argtypes = [u64, COST_FN, vp, P(u64), P(u64), vp, u64, P(u64)]
+    L.leco_ref_size_search.argtypes = [vp, u64, C.c_int, vp, u64, u64, C.c_int, P(u64), P(u64),
+                                       vp, u64, P(u64)]
     for name in ("leco_ref_blob_bytes", "leco_ref_encode", "leco_ref_blob_info",
                  "leco_ref_blob_record", "leco_ref_decode_all", "leco_ref_decode_range",
                  "leco_ref_random_access", "leco_ref_filter_sum",
                  "leco_ref_partition_greedy", "leco_ref_partition_merge",
                  "leco_ref_partition_dp", "leco_ref_partition_bruteforce",
-                 "leco_ref_partitioning_cost"):
+                 "leco_ref_partitioning_cost", "leco_ref_fixed_cost",
+                 "leco_ref_size_search_fn", "leco_ref_size_search"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -313,3 +320,42 @@ def partitioning_cost(col: np.ndarray, starts) -> int:
     _check("leco_ref_partitioning_cost", lib().leco_ref_partitioning_cost(
         _ptr(col), len(col), _dtype_code(col), _ptr(s), len(s) - 1, C.byref(b)))
     return b.value
+
+
+def fixed_cost(col: np.ndarray, starts, window: int, L: int, regressor: str = "ls") -> int:
+    """Sampled cost of fixed partitions of length L (record + word bytes of
+    every partition of every window)."""
+    col = np.ascontiguousarray(col)
+    s = np.ascontiguousarray(starts, dtype=np.uint64)
+    out = C.c_uint64()
+    _check("leco_ref_fixed_cost", lib().leco_ref_fixed_cost(
+        _ptr(col), len(col), _dtype_code(col), _ptr(s), len(s), window, L,
+        _regressor(regressor), C.byref(out)))
+    return out.value
+
+
+def _search_result(L, cost, trace, tl) -> dict:
+    steps = [(int(trace[2 * i]), int(trace[2 * i + 1])) for i in range(min(tl.value, len(trace) // 2))]
+    return {"L": L.value, "cost": cost.value, "trace": steps}
+
+
+def size_search_fn(window: int, cost) -> dict:
+    """The size search over a Python cost function L -> int."""
+    cb = COST_FN(lambda _ctx, L: int(cost(int(L))))
+    L, c, tl = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    trace = np.zeros(2 * 4096, dtype=np.uint64)
+    _check("leco_ref_size_search_fn", lib().leco_ref_size_search_fn(
+        window, cb, None, C.byref(L), C.byref(c), _ptr(trace), len(trace), C.byref(tl)))
+    return _search_result(L, c, trace, tl)
+
+
+def size_search(col: np.ndarray, starts, window: int, regressor: str = "ls") -> dict:
+    """Fixed partition size search (section 3.2.1) over sampled windows."""
+    col = np.ascontiguousarray(col)
+    s = np.ascontiguousarray(starts, dtype=np.uint64)
+    L, c, tl = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    trace = np.zeros(2 * 4096, dtype=np.uint64)
+    _check("leco_ref_size_search", lib().leco_ref_size_search(
+        _ptr(col), len(col), _dtype_code(col), _ptr(s), len(s), window, _regressor(regressor),
+        C.byref(L), C.byref(c), _ptr(trace), len(trace), C.byref(tl)))
+    return _search_result(L, c, trace, tl)

@@ -962,3 +962,133 @@ int leco_ref_partition_bruteforce(const void *col, uint64_t n, int dtype,
   free(v);
   return LREF_OK;
 }
+
+/* ---- Fixed partition size search (section 3.2.1) --------------------------- */
+
+int leco_ref_fixed_cost(const void *col, uint64_t n, int dtype,
+                        const uint64_t *starts, uint64_t k, uint64_t window,
+                        uint64_t L, int regressor, uint64_t *cost) {
+  if (col == NULL || starts == NULL || cost == NULL || (dtype != 4 && dtype != 8)) return LREF_EINVAL;
+  if (k == 0 || window == 0 || window > n || L == 0 || L > window || L > MAX_PART_LEN)
+    return LREF_EINVAL;
+  for (uint64_t i = 0; i < k; i++)
+    if (starts[i] > n - window) return LREF_EINVAL;
+  uint64_t *buf = (uint64_t *)malloc(L * sizeof(uint64_t));
+  if (!buf) return LREF_ENOMEM;
+  uint64_t total = 0;
+  for (uint64_t i = 0; i < k; i++) {
+    for (uint64_t p = 0; p < window; p += L) {
+      uint64_t len = window - p < L ? window - p : L;
+      for (uint64_t t = 0; t < len; t++) buf[t] = load_value(col, dtype, starts[i] + p + t);
+      leco_ref_model md;
+      int st = leco_ref_fit(buf, len, 0, regressor, &md);
+      if (st != LREF_OK) {
+        free(buf);
+        return st;
+      }
+      total += RECORD_BYTES + 8 * ((len * md.bits + 63) / 64);
+    }
+  }
+  free(buf);
+  *cost = total;
+  return LREF_OK;
+}
+
+typedef struct {
+  leco_ref_cost_fn fn;
+  void *ctx;
+  uint64_t *trace, cap, len;
+  uint64_t *seen; /* costs of evaluated lengths, UINT64_MAX if none */
+} search_state;
+
+static uint64_t evaluate(search_state *ss, uint64_t L) {
+  if (ss->seen[L] != UINT64_MAX) return ss->seen[L];
+  uint64_t c = ss->fn(ss->ctx, L);
+  ss->seen[L] = c;
+  if (2 * ss->len + 2 <= ss->cap) {
+    ss->trace[2 * ss->len] = L;
+    ss->trace[2 * ss->len + 1] = c;
+  }
+  ss->len++;
+  return c;
+}
+
+int leco_ref_size_search_fn(uint64_t window, leco_ref_cost_fn cost_fn, void *ctx,
+                            uint64_t *L_out, uint64_t *cost_out, uint64_t *trace,
+                            uint64_t trace_cap, uint64_t *trace_len) {
+  if (window == 0 || window > MAX_PART_LEN || cost_fn == NULL || L_out == NULL || cost_out == NULL)
+    return LREF_EINVAL;
+  search_state ss = {cost_fn, ctx, trace, trace ? trace_cap : 0, 0, NULL};
+  ss.seen = (uint64_t *)malloc((window + 1) * sizeof(uint64_t));
+  if (!ss.seen) return LREF_ENOMEM;
+  for (uint64_t L = 0; L <= window; L++) ss.seen[L] = UINT64_MAX;
+
+  /* Step 2, exponential phase: double L until the cost rises. */
+  uint64_t best = 1, best_cost = evaluate(&ss, 1), prev = best_cost;
+  for (uint64_t L = 1; L < window;) {
+    L = 2 * L <= window ? 2 * L : window;
+    uint64_t c = evaluate(&ss, L);
+    if (c < best_cost) {
+      best = L;
+      best_cost = c;
+    }
+    if (c > prev) break;
+    prev = c;
+  }
+  /* Step 2, back search with halving steps; step 3, convergence. */
+  for (uint64_t s = best / 2; s >= 1; s /= 2) {
+    uint64_t cand[2] = {best > s ? best - s : 0, best + s <= window ? best + s : 0};
+    uint64_t nb = best, nc = best_cost;
+    for (int q = 0; q < 2; q++) {
+      if (cand[q] == 0) continue;
+      uint64_t c = evaluate(&ss, cand[q]);
+      if (c < nc) {
+        nb = cand[q];
+        nc = c;
+      }
+    }
+    if (nb != best) {
+      int converged = (best_cost - nc) * 10000 < best_cost; /* < 0.01% */
+      best = nb;
+      best_cost = nc;
+      if (converged) break;
+    }
+  }
+  free(ss.seen);
+  *L_out = best;
+  *cost_out = best_cost;
+  if (trace_len) *trace_len = ss.len;
+  return LREF_OK;
+}
+
+typedef struct {
+  const void *col;
+  uint64_t n;
+  int dtype;
+  const uint64_t *starts;
+  uint64_t k, window;
+  int regressor;
+  int status;
+} column_cost_ctx;
+
+static uint64_t column_cost(void *p, uint64_t L) {
+  column_cost_ctx *c = (column_cost_ctx *)p;
+  uint64_t cost = UINT64_MAX;
+  int st = leco_ref_fixed_cost(c->col, c->n, c->dtype, c->starts, c->k, c->window, L,
+                               c->regressor, &cost);
+  if (st != LREF_OK && c->status == LREF_OK) c->status = st;
+  return cost;
+}
+
+int leco_ref_size_search(const void *col, uint64_t n, int dtype,
+                         const uint64_t *starts, uint64_t k, uint64_t window,
+                         int regressor, uint64_t *L_out, uint64_t *cost_out,
+                         uint64_t *trace, uint64_t trace_cap, uint64_t *trace_len) {
+  uint64_t probe;
+  int st = leco_ref_fixed_cost(col, n, dtype, starts, k, window, 1, regressor, &probe);
+  if (st != LREF_OK) return st;
+  column_cost_ctx c = {col, n, dtype, starts, k, window, regressor, LREF_OK};
+  st = leco_ref_size_search_fn(window, column_cost, &c, L_out, cost_out, trace, trace_cap,
+                               trace_len);
+  return st != LREF_OK ? st : c.status;
+}

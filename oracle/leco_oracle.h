@@ -169,6 +169,41 @@ int leco_ref_partitioning_cost(const void *col, uint64_t n, int dtype,
                                const uint64_t *starts, uint64_t m,
                                uint64_t *bytes_out);
 
+/* ---- Fixed partition size search (section 3.2.1) ---------------------------
+ *
+ * Sampled cost of fixed partitions of length L: the windows
+ * [starts[i], starts[i] + window), i < k, each cut into partitions of L
+ * values (the last one shorter), and
+ *   cost(L) = sum over all those partitions of 32 + 8 * ceil(len * b / 64),
+ * the record and residual words each partition adds to a blob (b from
+ * leco_ref_fit with `regressor`).  The random window starts are inputs. */
+int leco_ref_fixed_cost(const void *col, uint64_t n, int dtype,
+                        const uint64_t *starts, uint64_t k, uint64_t window,
+                        uint64_t L, int regressor, uint64_t *cost);
+
+/* Search of L in [1, window] for the smallest cost (section 3.2.1, steps
+ * 2-3).  Reading of the steps:
+ *   exponential phase: L = 1, 2, 4, ... up to window, then window itself if
+ *     it is not a power of two, stopping after the first L whose cost is
+ *     strictly above the previous one; best = the cheapest L seen (the
+ *     smallest on ties);
+ *   back search: for s = best / 2, best / 4, ..., 1 evaluate best - s and
+ *     then best + s (those in [1, window] not evaluated before) and move to
+ *     the cheapest when strictly cheaper than best; stop after s = 1, or
+ *     after a move that lowers the cost by less than 0.01% of it.
+ * Every evaluation is appended to trace[] as (L, cost) pairs while
+ * 2 * *trace_len < trace_cap.  cost_fn(ctx, L) supplies the costs. */
+typedef uint64_t (*leco_ref_cost_fn)(void *ctx, uint64_t L);
+int leco_ref_size_search_fn(uint64_t window, leco_ref_cost_fn cost_fn, void *ctx,
+                            uint64_t *L_out, uint64_t *cost_out, uint64_t *trace,
+                            uint64_t trace_cap, uint64_t *trace_len);
+
+/* The search over leco_ref_fixed_cost of a column's sampled windows. */
+int leco_ref_size_search(const void *col, uint64_t n, int dtype,
+                         const uint64_t *starts, uint64_t k, uint64_t window,
+                         int regressor, uint64_t *L_out, uint64_t *cost_out,
+                         uint64_t *trace, uint64_t trace_cap, uint64_t *trace_len);
+
 #ifdef __cplusplus
 }
 #endif
