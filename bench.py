@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--lookups", type=int, default=100_000_000)
     ap.add_argument("--cpu-sample", type=int, default=24 * 4096 * 1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["sorted_keys", "batched", "served", "variable"],
+    ap.add_argument("--workload", choices=["sorted_keys", "batched", "served", "variable",
+                                           "encode_options"],
                     default="sorted_keys")
     ap.add_argument("--var-n", type=int, default=100_000_000)
     ap.add_argument("--tau", type=float, default=0.03,
@@ -479,6 +480,83 @@ def bench_variable(args):
     codec.close()
 
 
+def bench_encode_options(args):
+    """The encoder's options on two 2e8-value uint64 columns (sorted keys,
+    linear noise): the fixed partition size search of section 3.2.1 on a 1%
+    sample of 10,000-value windows, and the minimax regressor, each with the
+    blob sizes it leads to."""
+    import torch
+    import paper_2306_15374_amd as P
+    from paper_2306_15374_amd import workloads as W
+
+    codec = P.Codec(0)
+    stream = torch.cuda.current_stream()
+    n = args.n
+    cols = {}
+    for name, gen, L0 in (("sorted_keys", W.lognormal_keys_device, W.C2_L),
+                          ("linear_noise", W.linear_noise_device, W.C1_L)):
+        log(f"{name}: generating {n} values")
+        d = gen(n, 5, np.uint64)
+        torch.cuda.synchronize()
+        window = 10_000
+        starts = W.sample_window_starts(n, window, fraction=0.01, seed=61)
+        t = []
+        res = None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            res = codec.size_search(d, starts, window)
+            t.append(time.perf_counter() - t0)
+        t_search = float(np.median(t))
+        Ls = res["L"]
+        sizes = {L: codec.encode(d, fixed_len=L).numel() for L in sorted({Ls, 1024, 4096})}
+        part_ls, _ = P.make_partitioning(fixed_len=L0)
+        part_mm, _ = P.make_partitioning(fixed_len=L0, regressor="minimax")
+        cap = P.leco_max_blob_bytes(n, P.LECO_U64, part_ls)
+        buf = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        size = torch.zeros(1, dtype=torch.uint64, device="cuda")
+        enc = {}
+        for reg, part in (("ls", part_ls), ("minimax", part_mm)):
+            f = lambda: codec.check("leco_encode_async", P.leco_encode_async(
+                codec.ctx, d, n, P.LECO_U64, part, buf, cap, size))
+            f()
+            codec.sync()
+            ms = time_events(torch, stream, f, max(1, min(args.steps, 5))) * 1e3
+            codec.sync()
+            enc[reg] = {"encode_ms": round(ms, 3), "blob_bytes": int(size.item())}
+        blob = codec.encode(d, fixed_len=L0, regressor="minimax")
+        assert torch.equal(codec.decode_all(blob, out=torch.empty_like(d)), d), \
+            f"{name}: minimax round trip"
+        cols[name] = {
+            "size_search": {"window": window, "windows": len(starts), "sampled_values": len(starts) * window,
+                            "evaluations": len(res["trace"]), "ms": round(t_search * 1e3, 2),
+                            "L": Ls, "sampled_cost": res["cost"],
+                            "ratio_at_L": round(sizes[Ls] / (8 * n), 5),
+                            "ratio_fixed_1024": round(sizes[1024] / (8 * n), 5),
+                            "ratio_fixed_4096": round(sizes[4096] / (8 * n), 5)},
+            "minimax": {"L": L0, **{f"{k}_{r}": v for r, e in enc.items() for k, v in e.items()},
+                        "smaller_by_pct": round(100 * (enc["ls"]["blob_bytes"] - enc["minimax"]["blob_bytes"])
+                                                / enc["ls"]["blob_bytes"], 3)},
+        }
+        log(f"{name}: {cols[name]}")
+        del d, buf, blob
+        torch.cuda.empty_cache()
+    t_all = sum(c["minimax"]["encode_ms_minimax"] for c in cols.values()) / 1e3
+    res = {
+        "metric": "decoded GB/s + lookups/s vs HBM roofline (batched/served vs plain); p99 latency",
+        "value": round(2 * 8 * n / t_all / 1e9, 2), "unit": "GB/s encoded (minimax regressor, input bytes)",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(t_all * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic (seeded lognormal-gap sorted keys, linear column with uniform noise)",
+        "config": {"workload": f"encoder options: 2 uint64 columns x {n} values; size search over 1% "
+                               "of the column in 10,000-value windows; minimax regressor"},
+        "columns": cols,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+    codec.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -491,6 +569,8 @@ def main():
         return bench_served(args)
     if args.workload == "variable":
         return bench_variable(args)
+    if args.workload == "encode_options":
+        return bench_encode_options(args)
     import torch
     import paper_2306_15374_amd as P
     from paper_2306_15374_amd import workloads as W

@@ -294,6 +294,40 @@ leco_status leco_partition(leco_ctx *ctx, const void *col_dev, uint64_t n, leco_
                            const leco_partition_params *params, uint64_t *starts_host,
                            uint64_t starts_cap, uint64_t *m_out, hipStream_t stream);
 
+/* ---- Fixed partition size search (section 3.2.1) ------------------------------
+ * Picks the fixed partition length from a sample of the column: k windows
+ * of `window` values at starts_host[0..k) (the caller draws the random
+ * starts; the paper samples under 1% of the data), and for a length L
+ *   cost(L) = sum, over every length-L partition of every window (the last
+ *             one of a window shorter), of 32 + 8 * ceil(len * b / 64):
+ * the record and residual words the partition adds to a blob, b being the
+ * encoder's width with `regressor` (exactly what leco_encode stores).
+ * Requires 1 <= window <= min(n, 2^20) and starts_host[i] + window <= n;
+ * col_dev is aligned to the dtype.  Scratch device memory comes from the
+ * context.  [sync] */
+leco_status leco_fixed_cost(leco_ctx *ctx, const void *col_dev, uint64_t n, leco_dtype dtype,
+                            const uint64_t *starts_host, uint64_t k, uint64_t window,
+                            uint64_t L, int32_t regressor, uint64_t *cost_host,
+                            hipStream_t stream);
+
+/* The search of section 3.2.1 over cost(L), L in [1, window]:
+ *   exponential phase: L = 1, 2, 4, ... up to window, then window itself if
+ *     it is not a power of two, stopping after the first L whose cost is
+ *     strictly above the previous one; best = the cheapest L seen (the
+ *     smallest on ties);
+ *   back search: for s = best/2, best/4, ..., 1 evaluate best - s, then
+ *     best + s (those in [1, window] not evaluated yet), move to the
+ *     cheapest when strictly cheaper than best, and stop after s = 1 or
+ *     after a move that lowers the cost by less than 0.01% of it.
+ * *L_out and *cost_out receive the result; the evaluations, in order, go to
+ * trace_host as (L, cost) pairs while 2 * *trace_len < trace_cap (trace_host
+ * may be null).  One device evaluation per length.  [sync] */
+leco_status leco_size_search(leco_ctx *ctx, const void *col_dev, uint64_t n, leco_dtype dtype,
+                             const uint64_t *starts_host, uint64_t k, uint64_t window,
+                             int32_t regressor, uint64_t *L_out, uint64_t *cost_out,
+                             uint64_t *trace_host, uint64_t trace_cap, uint64_t *trace_len,
+                             hipStream_t stream);
+
 /* ---- Served mode --------------------------------------------------------------
  * Compressed columns stay resident in device memory while a request loop
  * answers point lookups and range scans (the decoder of section 3.3 for "one

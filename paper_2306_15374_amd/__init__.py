@@ -31,7 +31,7 @@ EXPORTS = [
     "leco_batch_destroy", "leco_batch_run", "leco_batch_run_graph", "leco_batch_tune",
     "leco_batch_set_shape", "leco_server_start", "leco_server_submit", "leco_server_submit_batch",
     "leco_server_poll", "leco_server_release", "leco_server_stats_get", "leco_server_stop",
-    "leco_server_replay", "leco_partition",
+    "leco_server_replay", "leco_partition", "leco_fixed_cost", "leco_size_search",
 ]
 LECO_REQ_RANDOM_ACCESS, LECO_REQ_RANGE, LECO_REQ_RANDOM_ACCESS_DEV = 1, 2, 3
 LECO_BATCH_DECODE, LECO_BATCH_FILTER = 1, 2
@@ -145,6 +145,9 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_server_stop": ([vp], i32),
         "leco_server_replay": ([vp, vp, vp, u64, vp, P(C.c_double)], i32),
         "leco_partition": ([vp, vp, u64, i32, P(PartitionParams), vp, u64, P(u64), vp], i32),
+        "leco_fixed_cost": ([vp, vp, u64, i32, vp, u64, u64, u64, i32, P(u64), vp], i32),
+        "leco_size_search": ([vp, vp, u64, i32, vp, u64, u64, i32, P(u64), P(u64), vp, u64,
+                              P(u64), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -387,6 +390,29 @@ def leco_partition(ctx: int, col, n: int, dtype: int, params: PartitionParams,
     return st, m.value
 
 
+def leco_fixed_cost(ctx: int, col, n: int, dtype: int, starts, window: int, L: int,
+                    regressor: int = 0, stream=None) -> tuple[int, int]:
+    """starts: a uint64 numpy array of window starts (host)."""
+    cost = C.c_uint64()
+    st = lib().leco_fixed_cost(ctx, _ptr(col), n, dtype, starts.ctypes.data if len(starts) else None,
+                               len(starts), window, L, regressor, C.byref(cost), _stream(stream))
+    return st, cost.value
+
+
+def leco_size_search(ctx: int, col, n: int, dtype: int, starts, window: int, regressor: int = 0,
+                     trace_out=None, stream=None) -> tuple[int, int, int, int]:
+    """Returns (status, L, cost, evaluations); trace_out (uint64 numpy array,
+    optional) receives (L, cost) pairs."""
+    L, cost, tl = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    st = lib().leco_size_search(ctx, _ptr(col), n, dtype,
+                                starts.ctypes.data if len(starts) else None, len(starts), window,
+                                regressor, C.byref(L), C.byref(cost),
+                                None if trace_out is None else trace_out.ctypes.data,
+                                0 if trace_out is None else len(trace_out), C.byref(tl),
+                                _stream(stream))
+    return st, L.value, cost.value, tl.value
+
+
 # ---- convenience wrapper --------------------------------------------------------------
 
 class Codec:
@@ -446,6 +472,28 @@ class Codec:
                 continue
             self.check("leco_partition", st)
             return out[: m + 1].copy()
+
+    def fixed_cost(self, col, starts, window: int, L: int, regressor: str = "ls", stream=None):
+        """Sampled record + word bytes of fixed partitions of length L over
+        the windows [starts[i], starts[i] + window)."""
+        import numpy as np
+        s = np.ascontiguousarray(starts, dtype=np.uint64)
+        st, cost = leco_fixed_cost(self.ctx, col, col.numel(), _dtype_code(col), s, window, L,
+                                   regressor_code(regressor), stream)
+        self.check("leco_fixed_cost", st)
+        return cost
+
+    def size_search(self, col, starts, window: int, regressor: str = "ls", stream=None) -> dict:
+        """Fixed partition length search over sampled windows (section
+        3.2.1); returns {"L", "cost", "trace": [(L, cost), ...]}."""
+        import numpy as np
+        s = np.ascontiguousarray(starts, dtype=np.uint64)
+        trace = np.zeros(2 * 4096, dtype=np.uint64)
+        st, L, cost, n = leco_size_search(self.ctx, col, col.numel(), _dtype_code(col), s, window,
+                                          regressor_code(regressor), trace, stream)
+        self.check("leco_size_search", st)
+        steps = [(int(trace[2 * i]), int(trace[2 * i + 1])) for i in range(min(n, len(trace) // 2))]
+        return {"L": L, "cost": cost, "trace": steps}
 
     def info(self, blob):
         return leco_blob_info(bytes(blob[:64].cpu().numpy().tobytes()))

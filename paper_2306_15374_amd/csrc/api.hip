@@ -483,6 +483,159 @@ leco_status leco_filter_sum(leco_ctx* ctx, const void* blob_dev, uint64_t blob_b
   return LECO_OK;
 }
 
+// ---- fixed partition size search (section 3.2.1) ----------------------------------
+
+static leco_status check_windows(leco_ctx* ctx, const void* col, uint64_t n, leco_dtype dtype,
+                                 const uint64_t* starts, uint64_t k, uint64_t window,
+                                 int32_t regressor) {
+  if (!ctx) return LECO_EINVAL;
+  if (dtype != LECO_U32 && dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "bad dtype");
+  if (!col || (reinterpret_cast<uintptr_t>(col) % dtype) != 0)
+    return fail(ctx, LECO_EINVAL, "column is null or misaligned");
+  if (regressor != LECO_REGRESSOR_LS && regressor != LECO_REGRESSOR_MINIMAX)
+    return fail(ctx, LECO_EINVAL, "unknown regressor %d", int(regressor));
+  if (k == 0 || !starts) return fail(ctx, LECO_EINVAL, "no sample windows");
+  if (window == 0 || window > n || window > kMaxPartLen)
+    return fail(ctx, LECO_EINVAL, "window must be in [1, min(n, 2^20)]");
+  if (k > (uint64_t(1) << 31) / window) return fail(ctx, LECO_EINVAL, "too many sampled values");
+  for (uint64_t i = 0; i < k; ++i)
+    if (starts[i] > n - window)
+      return fail(ctx, LECO_EINVAL, "window %llu runs past the column", (unsigned long long)i);
+  return LECO_OK;
+}
+
+// cost(L) over the windows: every window is a column of the fit launch.
+static leco_status sampled_cost(leco_ctx* ctx, const void* col, leco_dtype dtype,
+                                const uint64_t* starts, uint64_t k, uint64_t window, uint64_t L,
+                                int32_t regressor, hipStream_t stream, uint64_t* cost) {
+  const uint64_t m = window / L + (window % L != 0);
+  const uint64_t nparts = k * m;
+  if (nparts >= (uint64_t(1) << 31)) return fail(ctx, LECO_EINVAL, "too many sampled partitions");
+  const bool minimax = regressor == LECO_REGRESSOR_MINIMAX;
+  const bool hulls = minimax && L > leco::kHullTileValues;
+  size_t off = 0;
+  const size_t o_enc = off;  off = align256(off + leco::encode_scratch_bytes(nparts));
+  const size_t o_cols = off; off = align256(off + sizeof(leco::EncColumn) * k);
+  const size_t o_sum = off;  off = align256(off + 8);
+  const size_t o_hull = off; off = align256(off + (hulls ? 8 * k * window : 0));
+  void* scr = nullptr;
+  leco_status st = get_scratch(ctx, off, &scr);
+  if (st != LECO_OK) return st;
+  char* b = static_cast<char*>(scr);
+  std::vector<leco::EncColumn> cols(k);
+  for (uint64_t i = 0; i < k; ++i) {
+    leco::EncColumn& c = cols[i];
+    c.col = static_cast<const uint8_t*>(col) + starts[i] * uint64_t(dtype);
+    c.blob = nullptr;
+    c.starts = nullptr;
+    c.size_out = nullptr;
+    c.n = window;
+    c.m = m;
+    c.fixed_len = L;
+    c.cap = 0;
+    c.words_off = 0;
+    c.part_base = i * m;
+    c.dtype = uint32_t(dtype);
+    c.force_constant = 0;
+    c.regressor = uint32_t(regressor);
+    c.pad = 0;
+    c.val_base = i * window;
+  }
+  leco::EncScratch es = leco::carve_encode_scratch(b + o_enc, nparts);
+  if (hulls) {
+    es.hull = reinterpret_cast<uint32_t*>(b + o_hull);
+    es.hull_values = k * window;
+  }
+  auto* cols_dev = reinterpret_cast<leco::EncColumn*>(b + o_cols);
+  auto* sum_dev = reinterpret_cast<uint64_t*>(b + o_sum);
+  HIP_TRY(ctx, hipMemcpyAsync(cols_dev, cols.data(), sizeof(leco::EncColumn) * k,
+                              hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipMemsetAsync(sum_dev, 0, 8, stream));
+  HIP_TRY(ctx, leco::launch_fit_columns(ctx, cols_dev, k, cols[0], nparts, L, minimax, es, stream));
+  HIP_TRY(ctx, leco::launch_cost_sum(es, nparts, sum_dev, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned_u64, sum_dev, 8, hipMemcpyDeviceToHost, stream));
+  st = leco_sync(ctx, stream);  // also waits for the table's copy before `cols` goes
+  if (st != LECO_OK) return st;
+  *cost = *ctx->pinned_u64;
+  return LECO_OK;
+}
+
+leco_status leco_fixed_cost(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_dtype dtype,
+                            const uint64_t* starts_host, uint64_t k, uint64_t window, uint64_t L,
+                            int32_t regressor, uint64_t* cost_host, hipStream_t stream) {
+  leco_status st = check_windows(ctx, col_dev, n, dtype, starts_host, k, window, regressor);
+  if (st != LECO_OK) return st;
+  if (L == 0 || L > window) return fail(ctx, LECO_EINVAL, "L must be in [1, window]");
+  if (!cost_host) return fail(ctx, LECO_EINVAL, "cost_host is null");
+  return sampled_cost(ctx, col_dev, dtype, starts_host, k, window, L, regressor, stream, cost_host);
+}
+
+leco_status leco_size_search(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_dtype dtype,
+                             const uint64_t* starts_host, uint64_t k, uint64_t window,
+                             int32_t regressor, uint64_t* L_out, uint64_t* cost_out,
+                             uint64_t* trace_host, uint64_t trace_cap, uint64_t* trace_len,
+                             hipStream_t stream) {
+  leco_status st = check_windows(ctx, col_dev, n, dtype, starts_host, k, window, regressor);
+  if (st != LECO_OK) return st;
+  if (!L_out || !cost_out) return fail(ctx, LECO_EINVAL, "outputs are null");
+  // known[L] = cost(L) once evaluated (UINT64_MAX before)
+  std::vector<uint64_t> known(window + 1, UINT64_MAX);
+  uint64_t evaluated = 0;
+  leco_status err = LECO_OK;
+  auto cost = [&](uint64_t L) -> uint64_t {
+    if (known[L] != UINT64_MAX || err != LECO_OK) return known[L];
+    uint64_t c = UINT64_MAX;
+    err = sampled_cost(ctx, col_dev, dtype, starts_host, k, window, L, regressor, stream, &c);
+    known[L] = c;
+    if (trace_host && 2 * evaluated + 2 <= trace_cap) {
+      trace_host[2 * evaluated] = L;
+      trace_host[2 * evaluated + 1] = c;
+    }
+    ++evaluated;
+    return c;
+  };
+  // exponential phase: past the bottom of the U
+  uint64_t best = 1, best_cost = cost(1);
+  for (uint64_t L = 1, prev = best_cost; L < window && err == LECO_OK;) {
+    L = L <= window / 2 ? 2 * L : window;
+    const uint64_t c = cost(L);
+    if (c < best_cost) {
+      best_cost = c;
+      best = L;
+    }
+    if (c > prev) break;
+    prev = c;
+  }
+  // back search with halving steps until the gain converges
+  for (uint64_t s = best / 2; s > 0 && err == LECO_OK; s /= 2) {
+    uint64_t to = best, to_cost = best_cost;
+    if (best > s) {
+      const uint64_t c = cost(best - s);
+      if (c < to_cost) {
+        to = best - s;
+        to_cost = c;
+      }
+    }
+    if (best + s <= window) {
+      const uint64_t c = cost(best + s);
+      if (c < to_cost) {
+        to = best + s;
+        to_cost = c;
+      }
+    }
+    if (to == best) continue;
+    const bool converged = (best_cost - to_cost) * 10000 < best_cost;
+    best = to;
+    best_cost = to_cost;
+    if (converged) break;
+  }
+  if (err != LECO_OK) return err;
+  *L_out = best;
+  *cost_out = best_cost;
+  if (trace_len) *trace_len = evaluated;
+  return LECO_OK;
+}
+
 leco_status leco_diag_slope(leco_ctx* ctx, const uint64_t* in_dev, uint64_t k, double* out_dev,
                             hipStream_t stream) {
   if (!ctx) return LECO_EINVAL;

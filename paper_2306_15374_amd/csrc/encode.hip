@@ -698,13 +698,10 @@ EncScratch carve_encode_scratch(void* p, uint64_t nparts) {
   return s;
 }
 
-hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
-                                 const EncColumn& single, uint64_t nparts, uint64_t max_len,
-                                 bool minimax, const EncScratch& scr, hipStream_t stream) {
-  const uint64_t cg = (ncols + 255) / 256;
-  hipLaunchKernelGGL(k_encode_prepare, dim3(uint32_t(cg < 4096 ? cg : 4096)), dim3(256), 0,
-                     stream, cols_dev, ncols, single, ctx->err_dev);
-  if (nparts == 0) return hipGetLastError();
+hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
+                              const EncColumn& single, uint64_t nparts, uint64_t max_len,
+                              bool minimax, const EncScratch& scr, hipStream_t stream) {
+  if (nparts == 0) return hipSuccess;
   const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave;
   const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
   if (minimax)
@@ -716,6 +713,21 @@ hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint6
   else
     hipLaunchKernelGGL(k_fit_block, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
+                                 const EncColumn& single, uint64_t nparts, uint64_t max_len,
+                                 bool minimax, const EncScratch& scr, hipStream_t stream) {
+  const uint64_t cg = (ncols + 255) / 256;
+  hipLaunchKernelGGL(k_encode_prepare, dim3(uint32_t(cg < 4096 ? cg : 4096)), dim3(256), 0,
+                     stream, cols_dev, ncols, single, ctx->err_dev);
+  if (nparts == 0) return hipGetLastError();
+  const hipError_t e = launch_fit_columns(ctx, cols_dev, ncols, single, nparts, max_len, minimax,
+                                          scr, stream);
+  if (e != hipSuccess) return e;
+  const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave;
+  const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
   const uint64_t ng = (nparts + kScanItems - 1) / kScanItems;
   hipLaunchKernelGGL(k_scan_sums, dim3(uint32_t(ng)), dim3(kEncBlock), 0, stream, scr, nparts);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kEncBlock), 0, stream, scr, ng);
@@ -728,6 +740,37 @@ hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint6
   else
     hipLaunchKernelGGL(k_pack<false>, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr);
+  return hipGetLastError();
+}
+
+// ---- sampled cost of a partitioning -------------------------------------------------
+
+// *out += sum over P < nparts of 32 + 8 * nwords[P]: the record and word
+// bytes the fitted partitions add to a blob.
+__global__ __launch_bounds__(kEncBlock) void k_cost_sum(EncScratch scr, uint64_t nparts,
+                                                       unsigned long long* out) {
+  __shared__ uint64_t part[kEncWaves];
+  uint64_t x = 0;
+  const uint64_t stride = uint64_t(gridDim.x) * kEncBlock;
+  for (uint64_t P = uint64_t(blockIdx.x) * kEncBlock + threadIdx.x; P < nparts; P += stride)
+    x += kRecordBytes + 8 * scr.nwords[P];
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) x += shfl_xor64(x, m);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kEncWaves; ++w) t += part[w];
+    atomicAdd(out, static_cast<unsigned long long>(t));
+  }
+}
+
+hipError_t launch_cost_sum(const EncScratch& scr, uint64_t nparts, uint64_t* out,
+                           hipStream_t stream) {
+  uint64_t blocks = (nparts + kEncBlock - 1) / kEncBlock;
+  blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+  hipLaunchKernelGGL(k_cost_sum, dim3(uint32_t(blocks)), dim3(kEncBlock), 0, stream, scr, nparts,
+                     reinterpret_cast<unsigned long long*>(out));
   return hipGetLastError();
 }
 

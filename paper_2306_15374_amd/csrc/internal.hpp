@@ -85,6 +85,13 @@ EncScratch carve_encode_scratch(void* p, uint64_t nparts);
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                                  const EncColumn& single, uint64_t nparts, uint64_t max_len,
                                  bool minimax, const EncScratch& scr, hipStream_t stream);
+// *out += the record and word bytes of the nparts partitions fitted in scr.
+hipError_t launch_cost_sum(const EncScratch& scr, uint64_t nparts, uint64_t* out,
+                           hipStream_t stream);
+// The fit step alone: every partition's model, width and word count in scr.
+hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
+                              const EncColumn& single, uint64_t nparts, uint64_t max_len,
+                              bool minimax, const EncScratch& scr, hipStream_t stream);
 hipError_t launch_diag_slope(const uint64_t* in, uint64_t k, double* out, hipStream_t stream);
 hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t bytes,
                             hipStream_t stream);

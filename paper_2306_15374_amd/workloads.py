@@ -223,3 +223,12 @@ def request_mix(num: int, col_lens, seed: int, max_log2_k: float = 16.0,
             b = int(rng.integers(0, n - ln + 1))
             reqs.append(dict(t=float(t[q]), kind="range", col=c, begin=b, end=b + ln))
     return reqs
+
+
+def sample_window_starts(n: int, window: int, fraction: float = 0.01, seed: int = 61) -> np.ndarray:
+    """Starts of the sampled windows of the fixed partition size search: k =
+    max(1, floor(fraction * n / window)) uniform starts in [0, n - window]
+    (sorted), so about `fraction` of the column is sampled."""
+    k = max(1, int(fraction * n) // window)
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.integers(0, n - window + 1, size=k)).astype(np.uint64)
