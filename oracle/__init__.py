@@ -54,10 +54,12 @@ class _Model(C.Structure):
         ("mm_fitted", C.c_int32), ("mm_pad", C.c_int32),
         ("mm_dy", C.c_int64), ("mm_dt", C.c_uint64), ("theta1_mm", C.c_double),
         ("r_min_mm", C.c_int64), ("r_max_mm", C.c_int64), ("b_mm", C.c_uint64),
+        ("poly_fitted", C.c_int32), ("poly_degree", C.c_int32), ("pc", C.c_double * 3),
+        ("b_p2", C.c_uint64), ("b_p3", C.c_uint64), ("stored_c", C.c_double * 3),
     ]
 
 
-REGRESSORS = {"ls": 0, "minimax": 1}
+REGRESSORS = {"ls": 0, "minimax": 1, "poly": 2}
 
 
 def _regressor(name: str) -> int:
@@ -164,6 +166,7 @@ def fit(values, force_constant: bool = False, regressor: str = "ls") -> dict:
     _check("leco_ref_fit", lib().leco_ref_fit(_ptr(v), len(v), int(force_constant),
                                               _regressor(regressor), C.byref(md)))
     d = {name: getattr(md, name) for name, _ in _Model._fields_}
+    d["pc"], d["stored_c"] = list(md.pc), list(md.stored_c)
     d["N"] = (d["N_hi"] << 64) | d["N_lo"]
     d["D"] = (d["D_hi"] << 64) | d["D_lo"]
     return d

@@ -36,6 +36,10 @@ typedef __int128 i128;
 #define MAX_PART_LEN (1ull << 20)
 #define MAGIC 0x4F43454Cu /* bytes 'L','E','C','O' */
 #define VERSION 1u
+#define FLAG_VARIABLE 1u
+#define FLAG_POLY 2u
+#define POLY_MAX_LEN 4096u
+#define POLY_MAX_RANGE (1ull << 50)
 
 /* ---- small helpers -------------------------------------------------------- */
 
@@ -215,6 +219,56 @@ static void residual_range(const uint64_t *v, uint64_t n, uint64_t vmin, double 
   }
 }
 
+/* ---- Polynomial regressor (Gram basis, see leco_oracle.h) ------------------ */
+
+/* g_k(t) for positions 0..n-1; |g_k| < 2^37 for n <= 4096. */
+static int64_t gram(int k, int64_t t, int64_t n) {
+  switch (k) {
+    case 1: return 2 * t - (n - 1);
+    case 2: return 6 * t * t - 6 * (n - 1) * t + (n - 1) * (n - 2);
+    default:
+      return 20 * t * t * t - 30 * (n - 1) * t * t + (12 * n * n - 30 * n + 22) * t -
+             (n - 1) * (n - 2) * (n - 3);
+  }
+}
+
+/* c_k = fl(S_k) / fl(Q_k) for k = 1, 2, 3 (0 where Q_k = 0). */
+static void poly_coefficients(const uint64_t *v, uint64_t n, uint64_t vmin, double c[3]) {
+  i128 S[3] = {0, 0, 0}, Q[3] = {0, 0, 0};
+  for (uint64_t t = 0; t < n; t++) {
+    i128 y = (i128)(v[t] - vmin);
+    for (int k = 1; k <= 3; k++) {
+      i128 g = gram(k, (int64_t)t, (int64_t)n);
+      S[k - 1] += y * g;
+      Q[k - 1] += g * g;
+    }
+  }
+  for (int k = 0; k < 3; k++) {
+    double q = (double)Q[k];
+    c[k] = Q[k] != 0 ? (double)S[k] / q : 0.0;
+    if (c[k] == 0.0) c[k] = 0.0; /* +0.0, never -0.0 */
+  }
+}
+
+/* p_t = floor(fl(fl(fl(c1 g1) + fl(c2 g2)) + fl(c3 g3))). */
+static int64_t poly_predict(const double c[3], uint64_t t, uint64_t n) {
+  double a = c[0] * (double)gram(1, (int64_t)t, (int64_t)n);
+  double b = c[1] * (double)gram(2, (int64_t)t, (int64_t)n);
+  double d = c[2] * (double)gram(3, (int64_t)t, (int64_t)n);
+  double s = a + b;
+  s = s + d;
+  return (int64_t)floor(s);
+}
+
+static void poly_residual_range(const uint64_t *v, uint64_t n, uint64_t vmin, const double c[3],
+                                int64_t *r_min, int64_t *r_max) {
+  for (uint64_t t = 0; t < n; t++) {
+    int64_t r = (int64_t)(v[t] - vmin) - poly_predict(c, t, n);
+    if (t == 0 || r < *r_min) *r_min = r;
+    if (t == 0 || r > *r_max) *r_max = r;
+  }
+}
+
 /* Least-squares line through (t, y_t), t = 0..n-1, from exact sums:
  *   slope = (n*S_ty - S_t*S_y) / (n*S_tt - S_t^2).
  * Then residuals r_t = y_t - floor(slope * t) and their width (section 3.1,
@@ -224,7 +278,8 @@ static void residual_range(const uint64_t *v, uint64_t n, uint64_t vmin, double 
 int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant, int regressor,
                  leco_ref_model *out) {
   if (n == 0 || n > MAX_PART_LEN || out == NULL) return LREF_EINVAL;
-  if (regressor != LREF_REG_LS && regressor != LREF_REG_MINIMAX) return LREF_EINVAL;
+  if (regressor != LREF_REG_LS && regressor != LREF_REG_MINIMAX && regressor != LREF_REG_POLY)
+    return LREF_EINVAL;
   memset(out, 0, sizeof(*out));
 
   uint64_t vmin = v[0], vmax = v[0];
@@ -281,6 +336,31 @@ int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant, int regresso
     out->theta1 = slope;
     out->base = vmin + (uint64_t)r_min;
     out->bits = out->b_ls;
+  }
+  if (regressor == LREF_REG_POLY) {
+    out->b_p2 = out->b_p3 = 99;
+    if (n < 3 || n > POLY_MAX_LEN || range >= POLY_MAX_RANGE) return LREF_OK;
+    double c[3];
+    poly_coefficients(v, n, vmin, c);
+    out->poly_fitted = 1;
+    for (int k = 0; k < 3; k++) out->pc[k] = c[k];
+    for (int deg = 2; deg <= 3; deg++) {
+      if (deg == 3 && n < 4) break;
+      double cd[3] = {c[0], c[1], deg == 3 ? c[2] : 0.0};
+      int64_t p_min = 0, p_max = 0;
+      poly_residual_range(v, n, vmin, cd, &p_min, &p_max);
+      uint64_t b = leco_ref_bitlen((uint64_t)p_max - (uint64_t)p_min);
+      if (deg == 2) out->b_p2 = b; else out->b_p3 = b;
+      if (b < out->bits) { /* ties keep the simpler model */
+        out->mode = 3;
+        out->poly_degree = deg;
+        for (int k = 0; k < 3; k++) out->stored_c[k] = cd[k];
+        out->theta1 = cd[0];
+        out->base = vmin + (uint64_t)p_min;
+        out->bits = b;
+      }
+    }
+    return LREF_OK;
   }
   if (regressor != LREF_REG_MINIMAX) return LREF_OK;
 
@@ -351,9 +431,11 @@ static int make_starts(uint64_t n, uint64_t fixed_len, const uint64_t *starts,
 
 typedef struct {
   uint64_t base;
-  double theta1;
+  double theta1; /* slope, or c1 of a polynomial */
   uint64_t bits;
   uint64_t words;
+  int kind;      /* 0 line or constant, 1 polynomial */
+  double c2, c3;
 } part_code;
 
 /* Fits every partition; fills codes[] and the section offsets. */
@@ -391,11 +473,15 @@ static int plan_blob(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
     codes[j].theta1 = md.theta1;
     codes[j].bits = md.bits;
     codes[j].words = (len * md.bits + 63) / 64;
+    codes[j].kind = md.mode == 3;
+    codes[j].c2 = md.mode == 3 ? md.stored_c[1] : 0.0;
+    codes[j].c3 = md.mode == 3 ? md.stored_c[2] : 0.0;
     tw += codes[j].words;
   }
   free(buf);
   uint64_t after_meta = HEADER_BYTES + RECORD_BYTES * m;
   if (fixed_len == 0) after_meta += 8 * (m + 1);
+  if (regressor == LREF_REG_POLY) after_meta = align16(after_meta) + 16 * m; /* (c2, c3) pairs */
   *words_off = align16(after_meta);
   *total_words = tw;
   *blob_bytes = align16(*words_off + 8 * tw);
@@ -439,7 +525,7 @@ int leco_ref_encode(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
   put_u32(blob + 0, MAGIC);
   put_u16(blob + 4, VERSION);
   blob[6] = (uint8_t)dtype;
-  blob[7] = fixed_len > 0 ? 0 : 1;
+  blob[7] = (uint8_t)((fixed_len > 0 ? 0 : FLAG_VARIABLE) | (regressor == LREF_REG_POLY ? FLAG_POLY : 0));
   put_u64(blob + 8, n);
   put_u64(blob + 16, m);
   put_u64(blob + 24, fixed_len);
@@ -456,10 +542,18 @@ int leco_ref_encode(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
     put_u64(r + 8, bits_from_f64(codes[j].theta1));
     put_u64(r + 16, woff);
     r[24] = (uint8_t)codes[j].bits;
+    r[25] = (uint8_t)codes[j].kind;
     woff += codes[j].words;
   }
   if (fixed_len == 0)
     for (uint64_t j = 0; j <= m; j++) put_u64(blob + starts_off + 8 * j, s[j]);
+  if (regressor == LREF_REG_POLY) {
+    uint64_t coef_off = align16(HEADER_BYTES + RECORD_BYTES * m + (fixed_len == 0 ? 8 * (m + 1) : 0));
+    for (uint64_t j = 0; j < m; j++) {
+      put_u64(blob + coef_off + 16 * j, bits_from_f64(codes[j].c2));
+      put_u64(blob + coef_off + 16 * j + 8, bits_from_f64(codes[j].c3));
+    }
+  }
 
   /* Delta array: residual t of partition j at bits [b*t, b*t + b) of the
    * partition's word span, least-significant bit first. */
@@ -468,9 +562,12 @@ int leco_ref_encode(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
   for (uint64_t j = 0; j < m; j++) {
     uint64_t len = s[j + 1] - s[j];
     uint64_t b = codes[j].bits;
+    double pc[3] = {codes[j].theta1, codes[j].c2, codes[j].c3};
     for (uint64_t t = 0; t < len && b > 0; t++) {
       uint64_t v = load_value(col, dtype, s[j] + t);
-      uint64_t u = v - codes[j].base - model_predict(codes[j].theta1, t);
+      uint64_t p = codes[j].kind ? (uint64_t)poly_predict(pc, t, len)
+                                 : model_predict(codes[j].theta1, t);
+      uint64_t u = v - codes[j].base - p;
       uint64_t first = 64 * woff + b * t;
       for (uint64_t k = 0; k < b; k++)
         if ((u >> k) & 1u) set_stream_bit(words, first + k);
@@ -485,8 +582,8 @@ int leco_ref_encode(const void *col, uint64_t n, int dtype, uint64_t fixed_len,
 /* ---- Blob parsing ----------------------------------------------------------- */
 
 typedef struct {
-  uint64_t n, m, fixed_len, starts_off, words_off, total_words;
-  int dtype, variable;
+  uint64_t n, m, fixed_len, starts_off, words_off, total_words, coef_off;
+  int dtype, variable, poly;
   const uint8_t *blob;
 } blob_view;
 
@@ -495,9 +592,10 @@ static int parse_blob(const uint8_t *blob, uint64_t bytes, blob_view *bv) {
   if (get_u32(blob) != MAGIC) return LREF_EFORMAT;
   if ((blob[4] | (blob[5] << 8)) != VERSION) return LREF_EFORMAT;
   bv->dtype = blob[6];
-  bv->variable = blob[7];
+  if (blob[7] > (FLAG_VARIABLE | FLAG_POLY)) return LREF_EFORMAT;
+  bv->variable = blob[7] & FLAG_VARIABLE;
+  bv->poly = (blob[7] & FLAG_POLY) != 0;
   if (bv->dtype != 4 && bv->dtype != 8) return LREF_EFORMAT;
-  if (bv->variable > 1) return LREF_EFORMAT;
   bv->n = get_u64(blob + 8);
   bv->m = get_u64(blob + 16);
   bv->fixed_len = get_u64(blob + 24);
@@ -519,6 +617,11 @@ static int parse_blob(const uint8_t *blob, uint64_t bytes, blob_view *bv) {
     uint64_t m = bv->n / bv->fixed_len + (bv->n % bv->fixed_len != 0);
     if (m != bv->m) return LREF_EFORMAT;
   }
+  bv->coef_off = 0;
+  if (bv->poly) {
+    bv->coef_off = align16(meta_end);
+    meta_end = bv->coef_off + 16 * bv->m;
+  }
   if (bv->words_off != align16(meta_end)) return LREF_EFORMAT;
   if (bv->total_words > bytes / 8) return LREF_EFORMAT;
   if (bv->words_off + 8 * bv->total_words > bytes) return LREF_EFORMAT;
@@ -534,6 +637,7 @@ static int parse_blob(const uint8_t *blob, uint64_t bytes, blob_view *bv) {
     const uint8_t *r = blob + HEADER_BYTES + RECORD_BYTES * j;
     uint64_t bits = r[24];
     if (bits > 8u * (uint64_t)bv->dtype) return LREF_EFORMAT;
+    if (r[25] > (bv->poly ? 1 : 0)) return LREF_EFORMAT;
     uint64_t start, len;
     if (bv->variable) {
       start = get_u64(blob + bv->starts_off + 8 * j);
@@ -586,7 +690,15 @@ static uint64_t decode_one(const blob_view *bv, uint64_t i) {
   uint64_t first = 64 * woff + b * t;
   for (uint64_t k = 0; k < b; k++)
     if (get_stream_bit(words, first + k)) u |= (uint64_t)1 << k;
-  uint64_t v = base + model_predict(theta1, t) + u;
+  uint64_t p;
+  if (r[25] == 1) {
+    const uint8_t *cp = bv->blob + bv->coef_off + 16 * j;
+    double c[3] = {theta1, f64_from_bits(get_u64(cp)), f64_from_bits(get_u64(cp + 8))};
+    p = (uint64_t)poly_predict(c, t, part_start(bv, j + 1) - part_start(bv, j));
+  } else {
+    p = model_predict(theta1, t);
+  }
+  uint64_t v = base + p + u;
   if (bv->dtype == 4) v &= 0xffffffffull;
   return v;
 }

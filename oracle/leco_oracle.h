@@ -59,6 +59,12 @@ typedef struct {
   double theta1_mm;    /* fl(mm_dy) / fl(mm_dt)                             */
   int64_t r_min_mm, r_max_mm;
   uint64_t b_mm;       /* bitlen(r_max_mm - r_min_mm)                       */
+  /* Polynomials (evaluated only with LREF_REG_POLY). */
+  int32_t poly_fitted; /* 1 when the degree-2 (and -3) fits were evaluated  */
+  int32_t poly_degree; /* degree of the stored polynomial (mode 3), else 0  */
+  double pc[3];        /* fitted Gram coefficients c1, c2, c3               */
+  uint64_t b_p2, b_p3; /* widths of the degree-2 and degree-3 fits (99 = none) */
+  double stored_c[3];  /* stored coefficients (c3 = 0 for degree 2)         */
 } leco_ref_model;
 
 /* bitlen(x) = floor(log2 x) + 1, bitlen(0) = 0 (the paper's ceil(log2 .)
@@ -70,7 +76,27 @@ uint64_t leco_ref_bitlen(uint64_t x);
  * fixed-width objective of section 3.1) and stores whichever of the
  * constant model, the least-squares line and the minimax line is narrowest,
  * ties going in that order. */
-enum { LREF_REG_LS = 0, LREF_REG_MINIMAX = 1 };
+enum { LREF_REG_LS = 0, LREF_REG_MINIMAX = 1, LREF_REG_POLY = 2 };
+
+/* Polynomial regressor (section 3.1 model terms; the higher-order models of
+ * the evaluation).  For a partition of 3..4096 values whose range is below
+ * 2^50, the least-squares polynomials of degree 2 and 3 (degree 3 from 4
+ * values) are fitted in the basis of the discrete orthogonal (Gram)
+ * polynomials of the positions t = 0..n-1:
+ *   g1(t) = 2t - (n-1)
+ *   g2(t) = 6t^2 - 6(n-1)t + (n-1)(n-2)
+ *   g3(t) = 20t^3 - 30(n-1)t^2 + (12n^2 - 30n + 22)t - (n-1)(n-2)(n-3),
+ * exactly orthogonal over those positions, so each coefficient is
+ *   c_k = fl(S_k) / fl(Q_k),  S_k = sum y_t g_k(t),  Q_k = sum g_k(t)^2,
+ * with exact integer sums (y_t = v_t - min v) each rounded to nearest-even
+ * binary64 and one division; degree 2 stores c3 = 0.  Prediction:
+ *   p_t = floor(fl(fl(fl(c1 * g1(t)) + fl(c2 * g2(t))) + fl(c3 * g3(t)))).
+ * The stored model is the narrowest of the constant model, the
+ * least-squares line, degree 2 and degree 3 (ties in that order).  A blob
+ * encoded with this regressor sets header flag bit 1 and carries, after the
+ * records (and starts), a 16-byte-aligned section of m (c2, c3) binary64
+ * pairs; a polynomial partition's record has kind byte 25 = 1 and c1 in
+ * the slope field. */
 
 /* Fit one partition of n values (section 3.1, section 3.3). */
 int leco_ref_fit(const uint64_t *v, uint64_t n, int force_constant,

@@ -232,3 +232,35 @@ def sample_window_starts(n: int, window: int, fraction: float = 0.01, seed: int 
     k = max(1, int(fraction * n) // window)
     rng = np.random.default_rng(seed)
     return np.sort(rng.integers(0, n - window + 1, size=k)).astype(np.uint64)
+
+
+def cosmos(n: int, seed: int = 71) -> np.ndarray:
+    """Higher-order signal of the evaluation's non-linear data (a cosmic-ray
+    like mixture of two sines plus Gaussian noise):
+    (sin((x + 10) / (60 pi)) + sin(3 (x + 10) / (60 pi)) / 10) * 10^6 +
+    N(0, 100) (read as standard deviation 100), shifted by 2^21 so every
+    value is a non-negative uint32."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(n, dtype=np.float64) + 10.0
+    w = 60.0 * np.pi
+    y = (np.sin(x / w) + np.sin(3.0 * x / w) / 10.0) * 1e6 + rng.normal(0.0, 100.0, n)
+    return np.rint(y + float(1 << 21)).astype(np.uint32)
+
+
+def poly_blocks(n: int, seed: int = 72, lo: int = 1000, hi: int = 8000) -> np.ndarray:
+    """Blocks of U[lo, hi) values, each following its own cubic polynomial
+    a + b t + c t^2 + d t^3 of the block-local index (b in [0, 1000), c in
+    [-0.05, 0.05), d in [-1e-5, 1e-5), a continuing from the previous block)
+    plus U{0..15} noise; 64-bit values offset by 2^40."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(n, dtype=np.uint64)
+    i, a = 0, float(1 << 40)
+    while i < n:
+        ln = min(n - i, int(rng.integers(lo, hi)))
+        t = np.arange(ln, dtype=np.float64)
+        b, c, d = rng.uniform(0, 1000), rng.uniform(-0.05, 0.05), rng.uniform(-1e-5, 1e-5)
+        y = a + b * t + c * t * t + d * t * t * t
+        out[i:i + ln] = np.rint(y).astype(np.uint64) + rng.integers(0, 16, ln).astype(np.uint64)
+        a = float(y[-1])
+        i += ln
+    return out
