@@ -101,10 +101,32 @@ typedef enum { LECO_U32 = 4, LECO_U64 = 8 } leco_dtype;
  *   points, taken exactly from their convex hulls, stored as fl(dy)/fl(dt)
  *   of the hull edge it lies on) and stores it when its residual width is
  *   strictly below both the constant model's and the least-squares line's.
- *   Blobs of either regressor have the same format and decoder.  Minimax
- *   partitions longer than 4096 values need 8 bytes of device scratch per
- *   value of the column. */
-typedef enum { LECO_REGRESSOR_LS = 0, LECO_REGRESSOR_MINIMAX = 1 } leco_regressor;
+ *   Minimax partitions longer than 4096 values need 8 bytes of device
+ *   scratch per value of the column.
+ *   LECO_REGRESSOR_POLY (section 3.1's model terms; the higher-order models
+ *   of the evaluation) also fits, for partitions of 3..4096 values whose
+ *   range is below 2^50, the least-squares polynomials of degree 2 and 3
+ *   (degree 3 from 4 values) in the discrete orthogonal (Gram) basis of the
+ *   positions t = 0..n-1:
+ *     g1 = 2t - (n-1), g2 = 6t^2 - 6(n-1)t + (n-1)(n-2),
+ *     g3 = 20t^3 - 30(n-1)t^2 + (12n^2 - 30n + 22)t - (n-1)(n-2)(n-3);
+ *   c_k = fl(S_k) / fl(Q_k) with S_k = sum (v_t - min v) g_k(t) and
+ *   Q_k = sum g_k(t)^2 exact integers, degree 2 storing c3 = 0; prediction
+ *   floor(fl(fl(fl(c1 g1) + fl(c2 g2)) + fl(c3 g3))).  The narrowest of the
+ *   constant model, the line, degree 2 and degree 3 is stored (ties: the
+ *   simpler).  Its blobs set header flag bit 1 and hold, 16-byte aligned
+ *   after the records (and starts), one (c2, c3) binary64 pair per
+ *   partition (zero for a line); a polynomial record has kind byte 25 = 1
+ *   and c1 in the slope field.  Such blobs are decoded by leco_decode_all,
+ *   leco_decode_range, leco_random_access and leco_filter_sum (value by
+ *   value, without model-bound pruning); batched and served decoding reject
+ *   them with LECO_EFORMAT.  Least-squares and minimax blobs keep flag bit
+ *   1 clear and every kind byte 0. */
+typedef enum {
+  LECO_REGRESSOR_LS = 0,
+  LECO_REGRESSOR_MINIMAX = 1,
+  LECO_REGRESSOR_POLY = 2
+} leco_regressor;
 
 typedef struct {
   uint64_t fixed_len;
@@ -201,7 +223,8 @@ typedef struct {
   void *blob_dev;
   uint64_t blob_cap;
   uint64_t *blob_bytes_dev;
-  int32_t regressor; /* leco_regressor, as in leco_partitioning */
+  int32_t regressor; /* leco_regressor, as in leco_partitioning (batched
+                        decoding does not take polynomial blobs) */
   int32_t reserved;  /* must be 0 */
 } leco_encode_job;
 
@@ -301,7 +324,8 @@ leco_status leco_partition(leco_ctx *ctx, const void *col_dev, uint64_t n, leco_
  *   cost(L) = sum, over every length-L partition of every window (the last
  *             one of a window shorter), of 32 + 8 * ceil(len * b / 64):
  * the record and residual words the partition adds to a blob, b being the
- * encoder's width with `regressor` (exactly what leco_encode stores).
+ * encoder's width with `regressor` (exactly what leco_encode stores), plus
+ * 16 coefficient bytes per partition with LECO_REGRESSOR_POLY.
  * Requires 1 <= window <= min(n, 2^20) and starts_host[i] + window <= n;
  * col_dev is aligned to the dtype.  Scratch device memory comes from the
  * context.  [sync] */

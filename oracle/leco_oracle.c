@@ -1098,7 +1098,7 @@ int leco_ref_fixed_cost(const void *col, uint64_t n, int dtype,
         free(buf);
         return st;
       }
-      total += RECORD_BYTES + 8 * ((len * md.bits + 63) / 64);
+      total += RECORD_BYTES + (regressor == LREF_REG_POLY ? 16 : 0) + 8 * ((len * md.bits + 63) / 64);
     }
   }
   free(buf);

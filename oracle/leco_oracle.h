@@ -202,7 +202,8 @@ int leco_ref_partitioning_cost(const void *col, uint64_t n, int dtype,
  * values (the last one shorter), and
  *   cost(L) = sum over all those partitions of 32 + 8 * ceil(len * b / 64),
  * the record and residual words each partition adds to a blob (b from
- * leco_ref_fit with `regressor`).  The random window starts are inputs. */
+ * leco_ref_fit with `regressor`; the polynomial regressor adds its 16
+ * coefficient bytes per partition).  The random window starts are inputs. */
 int leco_ref_fixed_cost(const void *col, uint64_t n, int dtype,
                         const uint64_t *starts, uint64_t k, uint64_t window,
                         uint64_t L, int regressor, uint64_t *cost);

@@ -179,7 +179,7 @@ def _dtype_code(t) -> int:
     raise TypeError(f"column dtype must be 32- or 64-bit integer, got {t.dtype}")
 
 
-REGRESSORS = {"ls": 0, "minimax": 1}  # leco_regressor
+REGRESSORS = {"ls": 0, "minimax": 1, "poly": 2}  # leco_regressor
 
 
 def regressor_code(name: str) -> int:

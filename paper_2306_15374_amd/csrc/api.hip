@@ -56,11 +56,15 @@ leco_status get_scratch(leco_ctx* ctx, size_t bytes, void** out) {
   return LECO_OK;
 }
 
+bool valid_regressor(int32_t r) {
+  return r == LECO_REGRESSOR_LS || r == LECO_REGRESSOR_MINIMAX || r == LECO_REGRESSOR_POLY;
+}
+
 // Partition count and validation of a partitioning for n values.
 leco_status check_partitioning(leco_ctx* ctx, uint64_t n, const leco_partitioning* part,
                                uint64_t* m_out, uint64_t* max_len_out = nullptr) {
   if (!part) return fail(ctx, LECO_EINVAL, "partitioning is null");
-  if (part->regressor != LECO_REGRESSOR_LS && part->regressor != LECO_REGRESSOR_MINIMAX)
+  if (!valid_regressor(part->regressor))
     return fail(ctx, LECO_EINVAL, "unknown regressor %d", int(part->regressor));
   if (part->fixed_len > 0) {
     if (part->fixed_len > kMaxPartLen)
@@ -89,8 +93,12 @@ leco_status check_partitioning(leco_ctx* ctx, uint64_t n, const leco_partitionin
   return LECO_OK;
 }
 
-uint64_t meta_words_off(uint64_t m, bool variable) {
-  return leco::align16(leco::kHeaderBytes + leco::kRecordBytes * m + (variable ? 8 * (m + 1) : 0));
+// Offset of the words section: header, records, starts (variable), and the
+// (c2, c3) coefficient section of the polynomial regressor.
+uint64_t meta_words_off(uint64_t m, bool variable, bool poly) {
+  uint64_t end = leco::kHeaderBytes + leco::kRecordBytes * m + (variable ? 8 * (m + 1) : 0);
+  if (poly) end = leco::align16(end) + 16 * m;
+  return leco::align16(end);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -136,7 +144,7 @@ leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtyp
   c.m = m;
   c.fixed_len = part->fixed_len;
   c.cap = cap;
-  c.words_off = meta_words_off(m, variable);
+  c.words_off = meta_words_off(m, variable, part->regressor == LECO_REGRESSOR_POLY);
   c.part_base = 0;
   c.dtype = uint32_t(dtype);
   c.force_constant = part->force_constant_model ? 1 : 0;
@@ -244,7 +252,8 @@ leco_status leco_max_blob_bytes(uint64_t n, leco_dtype dtype, const leco_partiti
   if (st != LECO_OK) return st;
   // every partition at full width: ceil(n_j * 8w / 64) <= n_j * w / 8 + 1
   const uint64_t words = (n * uint64_t(dtype) + 7) / 8 + m;
-  *bytes = leco::align16(meta_words_off(m, part->fixed_len == 0) + 8 * words);
+  *bytes = leco::align16(meta_words_off(m, part->fixed_len == 0,
+                                        part->regressor == LECO_REGRESSOR_POLY) + 8 * words);
   return LECO_OK;
 }
 
@@ -272,13 +281,15 @@ leco_status leco_validate_blob(leco_ctx* ctx, const void* blob_dev, uint64_t blo
   uint32_t magic;
   memcpy(&magic, hdr, 4);
   const uint16_t version = uint16_t(hdr[4] | (hdr[5] << 8));
-  const uint32_t dtype = hdr[6], variable = hdr[7];
+  const uint32_t dtype = hdr[6], flags = hdr[7];
+  const uint32_t variable = flags & leco::kFlagVariable;
+  const bool poly = (flags & leco::kFlagPoly) != 0;
   const uint64_t n = rd64(hdr + 8), m = rd64(hdr + 16), L = rd64(hdr + 24);
   const uint64_t rec_off = rd64(hdr + 32), st_off = rd64(hdr + 40), w_off = rd64(hdr + 48),
                  tw = rd64(hdr + 56);
   if (magic != leco::kMagic || version != leco::kVersion)
     return fail(ctx, LECO_EFORMAT, "bad magic or version");
-  if ((dtype != 4 && dtype != 8) || variable > 1 || rec_off != 64)
+  if ((dtype != 4 && dtype != 8) || flags > (leco::kFlagVariable | leco::kFlagPoly) || rec_off != 64)
     return fail(ctx, LECO_EFORMAT, "bad dtype, flags or records offset");
   if (m > blob_bytes / 32) return fail(ctx, LECO_EFORMAT, "partition count exceeds blob");
   if (variable) {
@@ -287,7 +298,7 @@ leco_status leco_validate_blob(leco_ctx* ctx, const void* blob_dev, uint64_t blo
     if (L == 0 || L > kMaxPartLen || st_off != 0 || m != n / L + (n % L != 0))
       return fail(ctx, LECO_EFORMAT, "bad fixed partitioning");
   }
-  if (w_off != meta_words_off(m, variable)) return fail(ctx, LECO_EFORMAT, "bad words offset");
+  if (w_off != meta_words_off(m, variable, poly)) return fail(ctx, LECO_EFORMAT, "bad words offset");
   if (tw > blob_bytes / 8 || leco::align16(w_off + 8 * tw) > blob_bytes)
     return fail(ctx, LECO_EFORMAT, "words section exceeds blob");
   std::vector<uint8_t> meta(w_off);
@@ -308,7 +319,10 @@ leco_status leco_validate_blob(leco_ctx* ctx, const void* blob_dev, uint64_t blo
     }
     const uint64_t bits = r[24];
     if (bits > 8 * dtype) return fail(ctx, LECO_EFORMAT, "width too large in partition %llu", (unsigned long long)j);
-    for (int k = 25; k < 32; ++k)
+    if (r[25] > (poly ? 1 : 0)) return fail(ctx, LECO_EFORMAT, "bad model kind in partition %llu", (unsigned long long)j);
+    if (r[25] && s1 - s0 > leco::kPolyMaxLen)
+      return fail(ctx, LECO_EFORMAT, "polynomial partition %llu longer than 4096", (unsigned long long)j);
+    for (int k = 26; k < 32; ++k)
       if (r[k]) return fail(ctx, LECO_EFORMAT, "nonzero record padding");
     if (rd64(r + 16) != expect_off) return fail(ctx, LECO_EFORMAT, "word offsets not contiguous");
     expect_off += ((s1 - s0) * bits + 63) / 64;
@@ -327,7 +341,8 @@ static leco_status encode_common(leco_ctx* ctx, const void* col, uint64_t n, lec
   if (st != LECO_OK) return st;
   if (size_dev) call->col.size_out = size_dev;
   HIP_TRY(ctx, leco::launch_encode_columns(ctx, nullptr, 1, call->col, call->col.m, call->max_len,
-                                           call->col.regressor != 0, call->scr, stream));
+                                           leco::regressor_bit(call->col.regressor), call->scr,
+                                           stream));
   return LECO_OK;
 }
 
@@ -368,10 +383,13 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
   if (!ctx) return LECO_EINVAL;
   if (ncols && !jobs) return fail(ctx, LECO_EINVAL, "jobs is null");
   // Columns whose partitions fit one wavefront go to one sequence of
-  // launches, the others to a second.
-  std::vector<leco::EncColumn> cols[2];
-  uint64_t parts[2] = {0, 0}, longest[2] = {0, 0}, values[2] = {0, 0};
-  bool minimax[2] = {false, false};
+  // launches, the others to a second, columns with the polynomial regressor
+  // to a third.
+  constexpr int kGroups = 3;
+  std::vector<leco::EncColumn> cols[kGroups];
+  uint64_t parts[kGroups] = {0, 0, 0}, longest[kGroups] = {0, 0, 0}, values[kGroups] = {0, 0, 0};
+  bool minimax[kGroups] = {false, false, false};
+  uint32_t regs[kGroups] = {0, 0, 0};
   for (uint64_t i = 0; i < ncols; ++i) {
     const leco_encode_job& j = jobs[i];
     if (j.dtype != LECO_U32 && j.dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "job %llu: bad dtype", (unsigned long long)i);
@@ -380,7 +398,7 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
     if ((j.n && !j.col_dev) || !j.blob_dev || !j.blob_bytes_dev || !aligned16(j.blob_dev) ||
         (reinterpret_cast<uintptr_t>(j.col_dev) % j.dtype))
       return fail(ctx, LECO_EINVAL, "job %llu: null or misaligned buffer", (unsigned long long)i);
-    if ((j.regressor != LECO_REGRESSOR_LS && j.regressor != LECO_REGRESSOR_MINIMAX) || j.reserved != 0)
+    if (!valid_regressor(j.regressor) || j.reserved != 0)
       return fail(ctx, LECO_EINVAL, "job %llu: bad regressor or reserved field", (unsigned long long)i);
     leco_partitioning part{j.fixed_len, nullptr, 0, j.force_constant_model, j.regressor};
     uint64_t bound = 0;
@@ -389,7 +407,7 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
       return fail(ctx, LECO_ENOSPC, "job %llu: capacity below %llu", (unsigned long long)i,
                   (unsigned long long)bound);
     const uint64_t len = j.n < j.fixed_len ? j.n : j.fixed_len;
-    const int g = len <= leco::kWaveEncodeMax ? 0 : 1;
+    const int g = j.regressor == LECO_REGRESSOR_POLY ? 2 : len <= leco::kWaveEncodeMax ? 0 : 1;
     leco::EncColumn c;
     c.col = static_cast<const uint8_t*>(j.col_dev);
     c.blob = static_cast<uint8_t*>(j.blob_dev);
@@ -399,7 +417,7 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
     c.m = j.n / j.fixed_len + (j.n % j.fixed_len != 0);
     c.fixed_len = j.fixed_len;
     c.cap = j.blob_cap;
-    c.words_off = meta_words_off(c.m, false);
+    c.words_off = meta_words_off(c.m, false, j.regressor == LECO_REGRESSOR_POLY);
     c.part_base = parts[g];
     c.dtype = uint32_t(j.dtype);
     c.force_constant = j.force_constant_model ? 1 : 0;
@@ -410,14 +428,16 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
     values[g] += c.n;
     if (len > longest[g]) longest[g] = len;
     if (j.regressor == LECO_REGRESSOR_MINIMAX) minimax[g] = true;
+    regs[g] |= leco::regressor_bit(uint32_t(j.regressor));
     cols[g].push_back(c);
   }
   if (ncols == 0) return LECO_OK;
-  if (parts[0] >= (uint64_t(1) << 31) || parts[1] >= (uint64_t(1) << 31))
-    return fail(ctx, LECO_EINVAL, "too many partitions in one batch");
-  size_t off = 0, o_enc[2], o_cols[2], o_hull[2];
-  bool hulls[2];
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < kGroups; ++g)
+    if (parts[g] >= (uint64_t(1) << 31))
+      return fail(ctx, LECO_EINVAL, "too many partitions in one batch");
+  size_t off = 0, o_enc[kGroups], o_cols[kGroups], o_hull[kGroups];
+  bool hulls[kGroups];
+  for (int g = 0; g < kGroups; ++g) {
     hulls[g] = minimax[g] && longest[g] > leco::kHullTileValues;
     o_enc[g] = off;  off = align256(off + leco::encode_scratch_bytes(parts[g]));
     o_cols[g] = off; off = align256(off + sizeof(leco::EncColumn) * (cols[g].size() + 1));
@@ -427,7 +447,7 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
   leco_status st = get_scratch(ctx, off, &scr);
   if (st != LECO_OK) return st;
   char* b = static_cast<char*>(scr);
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < kGroups; ++g) {
     if (cols[g].empty()) continue;
     leco::EncColumn* cols_dev = reinterpret_cast<leco::EncColumn*>(b + o_cols[g]);
     HIP_TRY(ctx, hipMemcpyAsync(cols_dev, cols[g].data(), sizeof(leco::EncColumn) * cols[g].size(),
@@ -438,7 +458,7 @@ leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64
       es.hull_values = values[g];
     }
     HIP_TRY(ctx, leco::launch_encode_columns(ctx, cols_dev, cols[g].size(), cols[g][0], parts[g],
-                                             longest[g], minimax[g], es, stream));
+                                             longest[g], regs[g], es, stream));
   }
   return LECO_OK;
 }
@@ -492,7 +512,7 @@ static leco_status check_windows(leco_ctx* ctx, const void* col, uint64_t n, lec
   if (dtype != LECO_U32 && dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "bad dtype");
   if (!col || (reinterpret_cast<uintptr_t>(col) % dtype) != 0)
     return fail(ctx, LECO_EINVAL, "column is null or misaligned");
-  if (regressor != LECO_REGRESSOR_LS && regressor != LECO_REGRESSOR_MINIMAX)
+  if (!valid_regressor(regressor))
     return fail(ctx, LECO_EINVAL, "unknown regressor %d", int(regressor));
   if (k == 0 || !starts) return fail(ctx, LECO_EINVAL, "no sample windows");
   if (window == 0 || window > n || window > kMaxPartLen)
@@ -551,8 +571,11 @@ static leco_status sampled_cost(leco_ctx* ctx, const void* col, leco_dtype dtype
   HIP_TRY(ctx, hipMemcpyAsync(cols_dev, cols.data(), sizeof(leco::EncColumn) * k,
                               hipMemcpyHostToDevice, stream));
   HIP_TRY(ctx, hipMemsetAsync(sum_dev, 0, 8, stream));
-  HIP_TRY(ctx, leco::launch_fit_columns(ctx, cols_dev, k, cols[0], nparts, L, minimax, es, stream));
-  HIP_TRY(ctx, leco::launch_cost_sum(es, nparts, sum_dev, stream));
+  HIP_TRY(ctx, leco::launch_fit_columns(ctx, cols_dev, k, cols[0], nparts, L,
+                                        leco::regressor_bit(uint32_t(regressor)), es, stream));
+  // a polynomial blob also stores 16 coefficient bytes per partition
+  HIP_TRY(ctx, leco::launch_cost_sum(es, nparts, regressor == LECO_REGRESSOR_POLY ? 16 : 0, sum_dev,
+                                     stream));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned_u64, sum_dev, 8, hipMemcpyDeviceToHost, stream));
   st = leco_sync(ctx, stream);  // also waits for the table's copy before `cols` goes
   if (st != LECO_OK) return st;

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restric
   for (uint64_t k = blockIdx.x; k < total_tiles; k += gridDim.x) {
     const DecCol& c = cols[tile_col[k]];
     Header h;
-    if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n) {
+    if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n || h.poly) {
       if (threadIdx.x == 0) raise(err, kErrFormat);
       continue;
     }

@@ -34,6 +34,29 @@ __device__ void decode_tiles(const uint8_t* __restrict__ blob, const Header& h,
   }
 }
 
+// The tiles of decode_tiles for a blob with coefficient section, each
+// wavefront's share decoded value by value.
+template <typename OutT>
+__device__ void decode_tiles_poly(const uint8_t* __restrict__ blob, const Header& h,
+                                  OutT* __restrict__ out, uint64_t begin, uint64_t e,
+                                  uint32_t tile_log2, uint64_t num_tiles, int* err) {
+  StoreSink<OutT> sink{out, begin};
+  const uint64_t first = begin >> tile_log2;
+  for (uint64_t k = blockIdx.x; k < num_tiles; k += gridDim.x) {
+    uint64_t t0 = (first + k) << tile_log2;
+    uint64_t t1 = t0 + (uint64_t(1) << tile_log2);
+    if (t0 < begin) t0 = begin;
+    if (t1 > e) t1 = e;
+    if (t0 >= t1) break;
+    uint64_t g0, g1;
+    wave_share(t0, t1, tile_log2, g0, g1);
+    if (g0 < g1 && !decode_range_poly(blob, h, g0, g1, sink)) {
+      if (lane_id() == 0) raise(err, kErrFormat);
+      return;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ blob,
                                                    uint64_t blob_bytes, uint8_t* __restrict__ out,
                                                    uint64_t begin, uint64_t end, uint64_t out_cap,
@@ -55,6 +78,15 @@ __global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ b
     e = h.n;
   } else if (end > h.n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrRange);
+    return;
+  }
+  if (h.poly) {
+    if (h.dtype == 8)
+      decode_tiles_poly(blob, h, reinterpret_cast<uint64_t*>(out), begin, e, tile_log2, num_tiles,
+                        err);
+    else
+      decode_tiles_poly(blob, h, reinterpret_cast<uint32_t*>(out), begin, e, tile_log2, num_tiles,
+                        err);
     return;
   }
   if (h.dtype == 8)
@@ -82,6 +114,21 @@ __global__ __launch_bounds__(kBlock) void k_random_access(const uint8_t* __restr
     return;
   }
   const uint64_t i0 = uint64_t(blockIdx.x) * (kBlock * kLpt) + threadIdx.x;
+  if (h.poly) {
+    for (int r = 0; r < kLpt; ++r) {
+      const uint64_t i = i0 + uint64_t(r) * kBlock;
+      if (i >= k) break;
+      const uint64_t g = pos[i];
+      uint64_t v = 0;
+      if (g >= h.n) raise(err, kErrRange);
+      else if (!lookup_value_poly(blob, h, g, v)) raise(err, kErrFormat);
+      if (h.dtype == 8)
+        reinterpret_cast<uint64_t*>(out)[i] = v;
+      else
+        reinterpret_cast<uint32_t*>(out)[i] = uint32_t(v);
+    }
+    return;
+  }
   const uint64_t* words = reinterpret_cast<const uint64_t*>(blob + h.words_off);
   uint64_t g[kLpt];
   bool ok[kLpt];
@@ -187,7 +234,10 @@ __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict
     if (t1 > h.n) t1 = h.n;
     uint64_t g0, g1;
     wave_share(t0, t1, tile_log2, g0, g1);
-    if (!bad && g0 < g1 && !decode_tile(blob, h, g0, g1, stage, sink)) bad = true;
+    // blobs with polynomial partitions: every value decoded, no pruning
+    if (!bad && g0 < g1 &&
+        !(h.poly ? decode_range_poly(blob, h, g0, g1, sink) : decode_tile(blob, h, g0, g1, stage, sink)))
+      bad = true;
   }
   if (bad && lane_id() == 0) raise(err, kErrFormat);
   block_add_sum(sink.sum_lo, sink.sum_hi, sink.count, out3);

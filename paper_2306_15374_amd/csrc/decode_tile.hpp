@@ -363,6 +363,86 @@ __device__ inline bool lookup_value(const uint8_t* __restrict__ blob, const Head
   return true;
 }
 
+// ---- blobs with a polynomial coefficient section -----------------------------------
+//
+// Such blobs (header flag kFlagPoly) mix linear records (kind 0) and
+// polynomial ones (kind 1: c1 in the slope field, c2 and c3 in the
+// coefficient section).  They are decoded value by value from global
+// memory: one wavefront walks the partitions of its share, reading each
+// record and its coefficients with scalar loads, and its lanes take
+// consecutive values of the partition.
+
+// Kind and coefficients of partition j (kind 1 needs the coefficient
+// section and at most kPolyMaxLen values); false if malformed.
+__device__ inline bool load_model_kind(const uint8_t* blob, const Header& h, uint64_t j,
+                                       const Part& p, uint32_t& kind, double& c2, double& c3) {
+  kind = uint32_t(meta_words(blob, kHeaderBytes + kRecordBytes * j)[3] >> 8) & 0xff;
+  c2 = c3 = 0.0;
+  if (kind == 0) return true;
+  if (kind > 1 || !h.poly || p.len > kPolyMaxLen) return false;
+  const MetaPtr cf = meta_words(blob, h.coef_off + 16 * j);
+  c2 = __longlong_as_double(static_cast<long long>(cf[0]));
+  c3 = __longlong_as_double(static_cast<long long>(cf[1]));
+  return true;
+}
+
+// The residual of position t of partition p, read from global memory.
+__device__ inline uint64_t residual_at(const uint64_t* words, const Part& p, uint64_t t) {
+  if (p.bits == 0) return 0;
+  const uint64_t q = 64 * p.word_off + uint64_t(p.bits) * t;
+  const uint32_t s = uint32_t(q & 63);
+  const uint64_t lo = words[q >> 6];
+  const uint64_t hi = (s + p.bits > 64) ? words[(q >> 6) + 1] : 0;
+  uint64_t u = (lo >> s) | ((hi << 1) << (63 - s));
+  if (p.bits < 64) u &= (uint64_t(1) << p.bits) - 1;
+  return u;
+}
+
+// Values [g0, g1) of a blob with coefficient section, by one wavefront;
+// false if a record is malformed.
+template <class Sink>
+__device__ bool decode_range_poly(const uint8_t* __restrict__ blob, const Header& h, uint64_t g0,
+                                  uint64_t g1, Sink& sink) {
+  const uint64_t* words = reinterpret_cast<const uint64_t*>(blob + h.words_off);
+  const uint32_t lane = lane_id();
+  uint64_t j = uniform_u64(locate(blob, h, g0));
+  for (uint64_t g = g0; g < g1; ++j) {
+    Part p;
+    uint32_t kind;
+    double c2, c3;
+    if (!load_part(blob, h, j, p) || g < p.start || g - p.start >= p.len ||
+        !load_model_kind(blob, h, j, p, kind, c2, c3))
+      return false;
+    const uint64_t end = p.start + p.len < g1 ? p.start + p.len : g1;
+    for (uint64_t x = g + lane; x < end; x += kWave) {
+      const uint32_t t = uint32_t(x - p.start);
+      const int64_t pred = kind ? poly_predict(p.theta1, c2, c3, t, uint32_t(p.len))
+                                : predict(p.theta1, t);
+      sink.put(x, p.base + uint64_t(pred) + residual_at(words, p, t));
+    }
+    g = end;
+  }
+  return true;
+}
+
+// Random access into a blob with coefficient section.
+__device__ inline bool lookup_value_poly(const uint8_t* __restrict__ blob, const Header& h,
+                                         uint64_t g, uint64_t& v) {
+  const uint64_t j = locate(blob, h, g);
+  Part p;
+  uint32_t kind;
+  double c2, c3;
+  if (!load_part(blob, h, j, p) || g < p.start || g - p.start >= p.len ||
+      !load_model_kind(blob, h, j, p, kind, c2, c3))
+    return false;
+  const uint32_t t = uint32_t(g - p.start);
+  const int64_t pred = kind ? poly_predict(p.theta1, c2, c3, t, uint32_t(p.len))
+                            : predict(p.theta1, t);
+  v = p.base + uint64_t(pred) + residual_at(reinterpret_cast<const uint64_t*>(blob + h.words_off),
+                                            p, t);
+  return true;
+}
+
 // Accumulates sum and count of values in [lo, hi).  A segment is skipped
 // without reading its residuals when the model bounds its values outside
 // [lo, hi): values of a partition lie in

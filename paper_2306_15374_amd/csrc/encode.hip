@@ -117,8 +117,9 @@ __device__ inline void part_bounds(const EncColumn& c, uint64_t j, uint64_t& sta
 __device__ inline void write_header(const EncColumn& c, uint64_t total_words) {
   uint64_t* hd = reinterpret_cast<uint64_t*>(c.blob);
   const bool variable = c.fixed_len == 0;
+  const uint64_t flags = (variable ? kFlagVariable : 0) | (c.regressor == 2 ? kFlagPoly : 0);
   hd[0] = uint64_t(kMagic) | (uint64_t(kVersion) << 32) | (uint64_t(c.dtype) << 48) |
-          (uint64_t(variable ? 1 : 0) << 56);
+          (flags << 56);
   hd[1] = c.n;
   hd[2] = c.m;
   hd[3] = c.fixed_len;
@@ -141,7 +142,11 @@ __device__ inline void finish_column(const EncColumn& c, uint64_t total_words, i
   const bool variable = c.fixed_len == 0;
   const uint64_t meta_end = kHeaderBytes + kRecordBytes * c.m + (variable ? 8 * (c.m + 1) : 0);
   if (variable) reinterpret_cast<uint64_t*>(c.blob + kHeaderBytes + kRecordBytes * c.m)[c.m] = c.n;
-  for (uint64_t i = meta_end; i < c.words_off; ++i) c.blob[i] = 0;
+  // padding around the coefficient section, which k_records fills
+  const uint64_t coef = c.regressor == 2 ? align16(meta_end) : c.words_off;
+  const uint64_t coef_end = c.regressor == 2 ? coef + 16 * c.m : c.words_off;
+  for (uint64_t i = meta_end; i < coef; ++i) c.blob[i] = 0;
+  for (uint64_t i = coef_end; i < c.words_off; ++i) c.blob[i] = 0;
   for (uint64_t i = c.words_off + 8 * total_words; i < size; ++i) c.blob[i] = 0;
 }
 
@@ -165,7 +170,7 @@ __device__ inline uint64_t load_clamped(const T* src, uint32_t t, uint64_t len) 
 
 // The model of a partition of len <= kWaveEncMax values, by one wavefront.
 template <class T>
-__device__ inline Model fit_wave(const T* src, uint64_t len, bool force_constant) {
+__device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, uint64_t len, bool force_constant) {
   const uint32_t lane = threadIdx.x & 63;
   uint64_t v[kWaveRegs];
 #pragma unroll
@@ -179,7 +184,7 @@ __device__ inline Model fit_wave(const T* src, uint64_t len, bool force_constant
   }
   wave_minmax_u64(vmin, vmax);
   const uint64_t range = vmax - vmin;
-  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
   if (len > 1 && !force_constant && range < (uint64_t(1) << 61)) {
     const bool narrow = range < kNarrowRange;
     double th;
@@ -233,6 +238,7 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restr
   const uint64_t P =
       uint64_t(blockIdx.x) * kEncWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (P >= nparts) return;
+  // launches holding polynomial columns (k_fit_poly) never use this kernel
   const EncColumn c = column_of(cols, ncols, single, P);
   uint64_t start, len;
   part_bounds(c, P - c.part_base, start, len);
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restr
 // thread).  Partitions of at most kEncRegLen values are held in registers;
 // longer ones are streamed twice.
 template <class T>
-__device__ inline Model fit_block(FitShared& sh, const T* src, uint64_t len, bool force_constant) {
+__device__ __attribute__((always_inline)) inline Model fit_block(FitShared& sh, const T* src, uint64_t len, bool force_constant) {
   const uint32_t tid = threadIdx.x;
   const bool in_regs = len <= kEncRegLen;
   const auto gsrc = global_ptr(src);
@@ -280,7 +286,7 @@ __device__ inline Model fit_block(FitShared& sh, const T* src, uint64_t len, boo
   }
   block_minmax_u64(sh, vmin, vmax);
   const uint64_t range = vmax - vmin;
-  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
   if (len > 1 && !force_constant && range < (uint64_t(1) << 61)) {
     double th;
     bool small = false;
@@ -342,6 +348,7 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __rest
   const uint64_t P = blockIdx.x;
   if (P >= nparts) return;
   const EncColumn c = column_of(cols, ncols, single, P);
+  if (c.regressor == 2) return;  // k_fit_poly
   uint64_t start, len;
   part_bounds(c, P - c.part_base, start, len);
   const Model md =
@@ -358,7 +365,7 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __rest
 // width is strictly smaller.  run_up / run_lo: the partition's running hulls
 // when it spans several hull tiles.
 template <class T>
-__device__ inline Model fit_minimax(FitShared& fs, HullShared& hs, const T* src, uint64_t len,
+__device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs, HullShared& hs, const T* src, uint64_t len,
                                     bool force_constant, bool minimax, uint32_t* run_up,
                                     uint32_t* run_lo) {
   Model md = fit_block(fs, src, len, force_constant);
@@ -463,9 +470,10 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_minimax(const EncColumn* __re
   const uint64_t P = blockIdx.x;
   if (P >= nparts) return;
   const EncColumn c = column_of(cols, ncols, single, P);
+  if (c.regressor == 2) return;  // k_fit_poly
   uint64_t start, len;
   part_bounds(c, P - c.part_base, start, len);
-  bool minimax = c.regressor != 0;
+  bool minimax = c.regressor == 1;
   uint32_t *run_up = nullptr, *run_lo = nullptr;
   if (minimax && len > kHullTile) {
     if (scr.hull == nullptr) {  // the host allocates running hulls for such launches
@@ -483,6 +491,124 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_minimax(const EncColumn* __re
           : fit_minimax(fs, hs, reinterpret_cast<const uint32_t*>(c.col) + start, len,
                         c.force_constant, minimax, run_up, run_lo);
   if (threadIdx.x == 0) store_model(scr, P, md, len);
+}
+
+// ---- fit with the polynomial regressor: one workgroup per partition ---------------
+
+// Exact workgroup sum of a two's-complement 128-bit value per thread (the
+// true sum fits, so sums modulo 2^128 are exact).
+__device__ inline __int128 block_sum_i128(FitShared& fs, __int128 a, __int128 b, __int128& bsum) {
+  U128 x{uint64_t(a), uint64_t(static_cast<unsigned __int128>(a) >> 64)};
+  U128 y{uint64_t(b), uint64_t(static_cast<unsigned __int128>(b) >> 64)};
+  block_sum_u128x2(fs, x, y);
+  bsum = static_cast<__int128>((static_cast<unsigned __int128>(y.hi) << 64) | y.lo);
+  return static_cast<__int128>((static_cast<unsigned __int128>(x.hi) << 64) | x.lo);
+}
+
+__device__ inline double i128_to_double(__int128 x) {
+  return i128_to_f64(U128{uint64_t(x), uint64_t(static_cast<unsigned __int128>(x) >> 64)});
+}
+
+// The least-squares model of fit_block, then (for 3 <= len <= 4096 values
+// of range below 2^50) the degree-2 and degree-3 least-squares polynomials
+// in the Gram basis: c_k = fl(S_k) / fl(Q_k), S_k = sum y_t g_k(t),
+// Q_k = sum g_k(t)^2 exactly in int128 (|y g3| < 2^87, 4096 terms), stored
+// when strictly narrower than every simpler model.
+template <class T>
+__device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, const T* src, uint64_t len, bool force_constant,
+                                 uint32_t& kind, double& c2_out, double& c3_out) {
+  Model md = fit_block(fs, src, len, force_constant);
+  kind = 0;
+  c2_out = c3_out = 0.0;
+  if (force_constant || len < 3 || len > kPolyMaxLen || md.range >= kPolyMaxRange) return md;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n = uint32_t(len);
+  const int64_t N = n, a = N - 1;
+  const int64_t k3 = 12 * N * N - 30 * N + 22, e2 = a * (N - 2), e3 = a * (N - 2) * (N - 3);
+  uint64_t y[kEncRegs];
+  __int128 s1 = 0, s2 = 0, s3 = 0, q1 = 0, q2 = 0, q3 = 0;
+#pragma unroll
+  for (int k = 0; k < kEncRegs; ++k) y[k] = load_clamped(src, tid + k * kEncBlock, len) - md.vmin;
+#pragma unroll
+  for (int k = 0; k < kEncRegs; ++k) {
+    const int64_t x = tid + k * kEncBlock;
+    if (x < N) {
+      const int64_t g1 = 2 * x - a;
+      const int64_t g2 = 6 * x * x - 6 * a * x + e2;
+      const int64_t g3 = 20 * x * x * x - 30 * a * x * x + k3 * x - e3;
+      const __int128 yy = __int128(y[k]);
+      s1 += yy * g1;
+      s2 += yy * g2;
+      s3 += yy * g3;
+      q1 += __int128(g1) * g1;
+      q2 += __int128(g2) * g2;
+      q3 += __int128(g3) * g3;
+    }
+  }
+  __int128 S2, Q1, Q3;
+  const __int128 S1 = block_sum_i128(fs, s1, s2, S2);
+  const __int128 S3 = block_sum_i128(fs, s3, q1, Q1);
+  const __int128 Q2 = block_sum_i128(fs, q2, q3, Q3);
+  double c[3];
+  const __int128 S[3] = {S1, S2, S3}, Q[3] = {Q1, Q2, Q3};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    c[k] = Q[k] != 0 ? i128_to_double(S[k]) / i128_to_double(Q[k]) : 0.0;
+    if (c[k] == 0.0) c[k] = 0.0;  // +0.0, never -0.0
+  }
+  for (int deg = 2; deg <= 3; ++deg) {
+    if (deg == 3 && len < 4) break;
+    const double c3 = deg == 3 ? c[2] : 0.0;
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+#pragma unroll
+    for (int k = 0; k < kEncRegs; ++k) {
+      const uint32_t t = tid + k * kEncBlock;
+      if (t < n) {
+        const int64_t rr = int64_t(y[k]) - poly_predict(c[0], c[1], c3, t, n);
+        rmin = rr < rmin ? rr : rmin;
+        rmax = rr > rmax ? rr : rmax;
+      }
+    }
+    block_minmax_i64(fs, rmin, rmax);
+    const uint32_t b = bitlen64(uint64_t(rmax) - uint64_t(rmin));
+    if (b < md.bits) {
+      md.linear = true;
+      md.theta1 = c[0];
+      md.base = md.vmin + uint64_t(rmin);
+      md.bits = b;
+      md.rmin = rmin;
+      kind = 1;
+      c2_out = c[1];
+      c3_out = c3;
+    }
+  }
+  return md;
+}
+
+__global__ __launch_bounds__(kEncBlock) void k_fit_poly(const EncColumn* __restrict__ cols,
+                                                       uint64_t ncols, EncColumn single,
+                                                       uint64_t nparts, EncScratch scr) {
+  __shared__ FitShared fs;
+  const uint64_t P = blockIdx.x;
+  if (P >= nparts) return;
+  const EncColumn c = column_of(cols, ncols, single, P);
+  if (c.regressor != 2) return;  // the other fit kernels
+  uint64_t start, len;
+  part_bounds(c, P - c.part_base, start, len);
+  uint32_t kind;
+  double c2, c3;
+  const Model md =
+      c.dtype == 8
+          ? fit_poly(fs, reinterpret_cast<const uint64_t*>(c.col) + start, len, c.force_constant,
+                     kind, c2, c3)
+          : fit_poly(fs, reinterpret_cast<const uint32_t*>(c.col) + start, len, c.force_constant,
+                     kind, c2, c3);
+  if (threadIdx.x == 0) {
+    store_model(scr, P, md, len);
+    scr.kind[P] = kind;
+    scr.c2[P] = uint64_t(__double_as_longlong(c2));
+    scr.c3[P] = uint64_t(__double_as_longlong(c3));
+  }
 }
 
 // ---- scan: word offsets ------------------------------------------------------------
@@ -571,11 +697,21 @@ __global__ __launch_bounds__(kEncBlock) void k_records(const EncColumn* __restri
     r[0] = scr.base[P];
     r[1] = scr.theta[P];
     r[2] = word_off;
-    r[3] = uint64_t(scr.bits[P]);
+    r[3] = uint64_t(scr.bits[P]) | (c.regressor == 2 ? uint64_t(scr.kind[P]) << 8 : 0);
   }
   if (c.fixed_len == 0) {
     const uint64_t so = kHeaderBytes + kRecordBytes * c.m + 8 * j;
     if (so + 8 <= c.cap) *reinterpret_cast<uint64_t*>(c.blob + so) = c.starts[j];
+  }
+  if (c.regressor == 2) {  // (c2, c3), zero for a line or constant
+    const uint64_t meta_end =
+        kHeaderBytes + kRecordBytes * c.m + (c.fixed_len == 0 ? 8 * (c.m + 1) : 0);
+    const uint64_t co = align16(meta_end) + 16 * j;
+    if (co + 16 <= c.cap) {
+      uint64_t* q = reinterpret_cast<uint64_t*>(c.blob + co);
+      q[0] = scr.kind[P] ? scr.c2[P] : 0;
+      q[1] = scr.kind[P] ? scr.c3[P] : 0;
+    }
   }
   if (j + 1 == c.m) finish_column(c, word_off + scr.nwords[P], err);
 }
@@ -592,10 +728,12 @@ constexpr uint32_t kPackBatch = 8;  // rounds of 64 residuals per batch
 // with another batch.  A batch's values are loaded together, its words
 // assembled in the wavefront's LDS buffer (kPackBatch * 128 words) and
 // stored as one contiguous run; words at or beyond `limit` (the span's end,
-// or the blob's capacity) are not stored.  Called by one wavefront.
+// or the blob's capacity) are not stored.  Called by one wavefront.  A
+// polynomial partition (kind 1) predicts with poly_predict(theta1, c2, c3).
 template <class T>
-__device__ inline void pack_rounds(const T* src, uint64_t len, uint64_t base, double theta1,
-                                   uint32_t b, uint32_t* gw32, uint64_t limit, uint64_t k_begin,
+__device__ __attribute__((always_inline)) inline void pack_rounds(const T* src, uint64_t len, uint64_t base, double theta1,
+                                   uint32_t kind, double c2, double c3, uint32_t b,
+                                   uint32_t* gw32, uint64_t limit, uint64_t k_begin,
                                    uint64_t k_end, uint32_t* w32) {
   const uint32_t lane = threadIdx.x & 63;
   const bool fits32 = prediction_fits_i32(theta1, len);
@@ -608,7 +746,9 @@ __device__ inline void pack_rounds(const T* src, uint64_t len, uint64_t base, do
 #pragma unroll
     for (uint32_t r = 0; r < kPackBatch; ++r) {
       const uint32_t t = uint32_t(64 * (k0 + r) + lane);
-      const uint64_t p = fits32 ? uint64_t(int64_t(predict32(theta1, t))) : uint64_t(predict(theta1, t));
+      const uint64_t p = kind ? uint64_t(poly_predict(theta1, c2, c3, t, uint32_t(len)))
+                              : fits32 ? uint64_t(int64_t(predict32(theta1, t)))
+                                       : uint64_t(predict(theta1, t));
       u[r] = t < len ? (u[r] - base) - p : 0;
     }
     const uint32_t nw = 2 * b * nr;  // <= 1024
@@ -656,12 +796,19 @@ __global__ __launch_bounds__(kEncBlock) void k_pack(const EncColumn* __restrict_
   }
   const double theta1 = __longlong_as_double(static_cast<long long>(meta_load(scr.theta, P)));
   const uint64_t base = meta_load(scr.base, P);
+  uint32_t kind = 0;
+  double c2 = 0.0, c3 = 0.0;
+  if (c.regressor == 2) {
+    kind = meta_load(scr.kind, P);
+    c2 = __longlong_as_double(static_cast<long long>(meta_load(scr.c2, P)));
+    c3 = __longlong_as_double(static_cast<long long>(meta_load(scr.c3, P)));
+  }
   if (c.dtype == 8)
-    pack_rounds(reinterpret_cast<const uint64_t*>(c.col) + start, len, base, theta1, b, gw32,
-                limit, k_begin, k_end, lds[wave]);
+    pack_rounds(reinterpret_cast<const uint64_t*>(c.col) + start, len, base, theta1, kind, c2, c3,
+                b, gw32, limit, k_begin, k_end, lds[wave]);
   else
-    pack_rounds(reinterpret_cast<const uint32_t*>(c.col) + start, len, base, theta1, b, gw32,
-                limit, k_begin, k_end, lds[wave]);
+    pack_rounds(reinterpret_cast<const uint32_t*>(c.col) + start, len, base, theta1, kind, c2, c3,
+                b, gw32, limit, k_begin, k_end, lds[wave]);
 }
 
 // Writes the complete blob of every empty column (no partitions, so no
@@ -679,7 +826,7 @@ __global__ void k_encode_prepare(const EncColumn* __restrict__ cols, uint64_t nc
 uint64_t encode_scratch_bytes(uint64_t nparts) {
   const uint64_t k = nparts ? nparts : 1;
   const uint64_t ng = (k + kScanItems - 1) / kScanItems;
-  return 8 * (4 * k + ng + 1) + 4 * k + 64;
+  return 8 * (6 * k + ng + 1) + 8 * k + 64;
 }
 
 EncScratch carve_encode_scratch(void* p, uint64_t nparts) {
@@ -692,7 +839,10 @@ EncScratch carve_encode_scratch(void* p, uint64_t nparts) {
   s.base = q + 2 * k;
   s.theta = q + 3 * k;
   s.bsum = q + 4 * k;
-  s.bits = reinterpret_cast<uint32_t*>(q + 4 * k + ng + 1);
+  s.c2 = q + 4 * k + ng + 1;
+  s.c3 = q + 5 * k + ng + 1;
+  s.bits = reinterpret_cast<uint32_t*>(q + 6 * k + ng + 1);
+  s.kind = s.bits + k;
   s.hull = nullptr;
   s.hull_values = 0;
   return s;
@@ -700,11 +850,16 @@ EncScratch carve_encode_scratch(void* p, uint64_t nparts) {
 
 hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                               const EncColumn& single, uint64_t nparts, uint64_t max_len,
-                              bool minimax, const EncScratch& scr, hipStream_t stream) {
+                              uint32_t regs, const EncScratch& scr, hipStream_t stream) {
   if (nparts == 0) return hipSuccess;
-  const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave;
+  // each fit kernel fits the columns of its regressors and skips the others
+  if (regs & kRegPoly)
+    hipLaunchKernelGGL(k_fit_poly, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
+                       ncols, single, nparts, scr);
+  if (!(regs & (kRegLS | kRegMinimax))) return hipGetLastError();
+  const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave && !(regs & kRegPoly);
   const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
-  if (minimax)
+  if (regs & kRegMinimax)
     hipLaunchKernelGGL(k_fit_minimax, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr, ctx->err_dev);
   else if (wave)
@@ -718,15 +873,15 @@ hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t
 
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                                  const EncColumn& single, uint64_t nparts, uint64_t max_len,
-                                 bool minimax, const EncScratch& scr, hipStream_t stream) {
+                                 uint32_t regs, const EncScratch& scr, hipStream_t stream) {
   const uint64_t cg = (ncols + 255) / 256;
   hipLaunchKernelGGL(k_encode_prepare, dim3(uint32_t(cg < 4096 ? cg : 4096)), dim3(256), 0,
                      stream, cols_dev, ncols, single, ctx->err_dev);
   if (nparts == 0) return hipGetLastError();
-  const hipError_t e = launch_fit_columns(ctx, cols_dev, ncols, single, nparts, max_len, minimax,
+  const hipError_t e = launch_fit_columns(ctx, cols_dev, ncols, single, nparts, max_len, regs,
                                           scr, stream);
   if (e != hipSuccess) return e;
-  const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave;
+  const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave;  // pack only
   const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
   const uint64_t ng = (nparts + kScanItems - 1) / kScanItems;
   hipLaunchKernelGGL(k_scan_sums, dim3(uint32_t(ng)), dim3(kEncBlock), 0, stream, scr, nparts);
@@ -748,12 +903,12 @@ hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint6
 // *out += sum over P < nparts of 32 + 8 * nwords[P]: the record and word
 // bytes the fitted partitions add to a blob.
 __global__ __launch_bounds__(kEncBlock) void k_cost_sum(EncScratch scr, uint64_t nparts,
-                                                       unsigned long long* out) {
+                                                       uint64_t extra, unsigned long long* out) {
   __shared__ uint64_t part[kEncWaves];
   uint64_t x = 0;
   const uint64_t stride = uint64_t(gridDim.x) * kEncBlock;
   for (uint64_t P = uint64_t(blockIdx.x) * kEncBlock + threadIdx.x; P < nparts; P += stride)
-    x += kRecordBytes + 8 * scr.nwords[P];
+    x += kRecordBytes + extra + 8 * scr.nwords[P];
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) x += shfl_xor64(x, m);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
@@ -765,12 +920,12 @@ __global__ __launch_bounds__(kEncBlock) void k_cost_sum(EncScratch scr, uint64_t
   }
 }
 
-hipError_t launch_cost_sum(const EncScratch& scr, uint64_t nparts, uint64_t* out,
-                           hipStream_t stream) {
+hipError_t launch_cost_sum(const EncScratch& scr, uint64_t nparts, uint64_t extra_per_part,
+                           uint64_t* out, hipStream_t stream) {
   uint64_t blocks = (nparts + kEncBlock - 1) / kEncBlock;
   blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
   hipLaunchKernelGGL(k_cost_sum, dim3(uint32_t(blocks)), dim3(kEncBlock), 0, stream, scr, nparts,
-                     reinterpret_cast<unsigned long long*>(out));
+                     extra_per_part, reinterpret_cast<unsigned long long*>(out));
   return hipGetLastError();
 }
 

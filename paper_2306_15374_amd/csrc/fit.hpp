@@ -170,6 +170,7 @@ struct Model {
   uint32_t bits;
   bool linear;
   int64_t rmin;
+  uint64_t range;  // vmax - vmin
 };
 
 // Chooses between the constant model and the fitted line (ties keep the

@@ -34,7 +34,7 @@ struct EncColumn {
   uint64_t words_off;      // offset of the words section
   uint64_t part_base;      // index of the column's first partition in the launch
   uint32_t dtype, force_constant;
-  uint32_t regressor;      // 0 least squares, 1 minimax as well
+  uint32_t regressor;      // 0 least squares, 1 minimax as well, 2 polynomials as well
   uint32_t pad;
   uint64_t val_base;       // index of the column's first value in the launch
 };
@@ -74,24 +74,33 @@ struct EncScratch {
   // hull[hull_values + s + k]; null when no such partition is encoded
   uint32_t* hull;
   uint64_t hull_values;
+  // polynomial models (columns with the polynomial regressor): kind 0/1 and
+  // the bits of c2, c3 per partition
+  uint32_t* kind;
+  uint64_t* c2;
+  uint64_t* c3;
 };
 uint64_t encode_scratch_bytes(uint64_t nparts);
 EncScratch carve_encode_scratch(void* p, uint64_t nparts);
 
+// Regressors present in a launch, as bits of a mask.
+constexpr uint32_t kRegLS = 1, kRegMinimax = 2, kRegPoly = 4;
+inline uint32_t regressor_bit(uint32_t regressor) { return 1u << regressor; }
+
 // Encodes ncols columns (table cols_dev, or `single` when cols_dev is null)
 // with nparts partitions in total.  max_len: the longest partition of the
-// launch (selects the kernels); minimax: some column asks for the minimax
-// regressor (fits every partition with the minimax kernel).
+// launch; regs: the regressors its columns ask for (selects the kernels).
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                                  const EncColumn& single, uint64_t nparts, uint64_t max_len,
-                                 bool minimax, const EncScratch& scr, hipStream_t stream);
-// *out += the record and word bytes of the nparts partitions fitted in scr.
-hipError_t launch_cost_sum(const EncScratch& scr, uint64_t nparts, uint64_t* out,
-                           hipStream_t stream);
+                                 uint32_t regs, const EncScratch& scr, hipStream_t stream);
+// *out += the record and word bytes (plus extra_per_part) of the nparts
+// partitions fitted in scr.
+hipError_t launch_cost_sum(const EncScratch& scr, uint64_t nparts, uint64_t extra_per_part,
+                           uint64_t* out, hipStream_t stream);
 // The fit step alone: every partition's model, width and word count in scr.
 hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                               const EncColumn& single, uint64_t nparts, uint64_t max_len,
-                              bool minimax, const EncScratch& scr, hipStream_t stream);
+                              uint32_t regs, const EncScratch& scr, hipStream_t stream);
 hipError_t launch_diag_slope(const uint64_t* in, uint64_t k, double* out, hipStream_t stream);
 hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t bytes,
                             hipStream_t stream);

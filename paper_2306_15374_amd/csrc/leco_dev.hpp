@@ -13,6 +13,12 @@ constexpr uint32_t kVersion = 1;
 constexpr uint64_t kHeaderBytes = 64;
 constexpr uint64_t kRecordBytes = 32;
 constexpr uint64_t kMaxPartLen = 1ull << 20;
+// Header flag bits (byte 7).
+constexpr uint32_t kFlagVariable = 1;  // starts section present
+constexpr uint32_t kFlagPoly = 2;      // (c2, c3) coefficient section present
+// Polynomial partitions: at most this many values, range below 2^50.
+constexpr uint64_t kPolyMaxLen = 4096;
+constexpr uint64_t kPolyMaxRange = 1ull << 50;
 
 // Device error bits, reported by leco_sync.
 constexpr int kErrRange = 1;
@@ -44,6 +50,8 @@ struct Header {
   uint64_t n, m, fixed_len, starts_off, words_off, total_words;
   uint32_t dtype;     // 4 or 8
   uint32_t variable;  // 1 = variable-length partitions
+  uint32_t poly;      // 1 = polynomial coefficient section present
+  uint64_t coef_off;  // its offset (poly only)
 };
 
 // Reads and checks the 64-byte header against the caller-supplied blob size.
@@ -63,10 +71,12 @@ __device__ inline bool load_header(const uint8_t* blob, uint64_t blob_bytes, Hea
   uint32_t magic = uint32_t(w0);
   uint32_t version = uint32_t(w0 >> 32) & 0xffff;
   h.dtype = uint32_t(w0 >> 48) & 0xff;
-  h.variable = uint32_t(w0 >> 56);
+  const uint32_t flags = uint32_t(w0 >> 56);
+  h.variable = flags & kFlagVariable;
+  h.poly = (flags & kFlagPoly) ? 1u : 0u;
   if (magic != kMagic || version != kVersion) return false;
   if (h.dtype != 4 && h.dtype != 8) return false;
-  if (h.variable > 1 || records_off != kHeaderBytes) return false;
+  if (flags > (kFlagVariable | kFlagPoly) || records_off != kHeaderBytes) return false;
   if (h.m > blob_bytes / kRecordBytes) return false;
   uint64_t meta_end = kHeaderBytes + kRecordBytes * h.m;
   if (h.variable) {
@@ -76,6 +86,11 @@ __device__ inline bool load_header(const uint8_t* blob, uint64_t blob_bytes, Hea
   } else {
     if (h.fixed_len == 0 || h.fixed_len > kMaxPartLen || h.starts_off != 0) return false;
     if (h.n / h.fixed_len + (h.n % h.fixed_len != 0) != h.m) return false;
+  }
+  h.coef_off = 0;
+  if (h.poly) {
+    h.coef_off = align16(meta_end);
+    meta_end = h.coef_off + 16 * h.m;
   }
   if (h.words_off != align16(meta_end)) return false;
   if (h.total_words > blob_bytes / 8) return false;
@@ -214,6 +229,22 @@ __device__ inline int32_t predict32(double theta1, uint32_t t) {
 // monotone, so |fl(theta1 * t)| <= fl(|theta1| * len) for t < len.
 __device__ inline bool prediction_fits_i32(double theta1, uint64_t len) {
   return __dmul_rn(fabs(theta1), double(len)) < 2147483648.0;
+}
+
+// Polynomial prediction of a partition of n <= 4096 values: the Gram
+// polynomials of the positions, g1 = 2t - (n-1), g2 = 6t^2 - 6(n-1)t +
+// (n-1)(n-2), g3 = 20t^3 - 30(n-1)t^2 + (12n^2 - 30n + 22)t - (n-1)(n-2)(n-3),
+// are exact integers below 2^37 in magnitude (so exact in binary64), and
+//   p_t = floor(fl(fl(fl(c1 g1) + fl(c2 g2)) + fl(c3 g3))).
+__device__ inline int64_t poly_predict(double c1, double c2, double c3, uint32_t t, uint32_t n) {
+  const int64_t x = t, N = n, a = N - 1;
+  const int64_t g1 = 2 * x - a;
+  const int64_t g2 = 6 * x * x - 6 * a * x + a * (N - 2);
+  const int64_t g3 = 20 * x * x * x - 30 * a * x * x + (12 * N * N - 30 * N + 22) * x -
+                     a * (N - 2) * (N - 3);
+  double s = __dadd_rn(__dmul_rn(c1, double(g1)), __dmul_rn(c2, double(g2)));
+  s = __dadd_rn(s, __dmul_rn(c3, double(g3)));
+  return static_cast<int64_t>(floor(s));
 }
 
 // ---- residual extraction from 32-bit words ---------------------------------

@@ -64,7 +64,7 @@ __device__ inline bool slope_lt(EdgeSlope a, EdgeSlope b) {
 // return vertices.  Walks inwards from the facing ends until neither end
 // can move.
 template <class PA, class PB>
-__device__ inline void hull_bridge(bool upper, const PA& A, uint32_t p, const PB& B, uint32_t q,
+__device__ __attribute__((always_inline)) inline void hull_bridge(bool upper, const PA& A, uint32_t p, const PB& B, uint32_t q,
                                    uint32_t& keep, uint32_t& from) {
   uint32_t i = p - 1, j = 0;
   HullPoint a = A(i), b = B(j);
@@ -105,7 +105,7 @@ struct HullShared {
 
 // Upper and lower hulls of the tile's points 0 .. cnt-1 (values in sh.v),
 // left in sh.h[side][0 .. sh.cnt[side][0]).  Called by the whole workgroup.
-__device__ inline void tile_hulls(HullShared& sh, uint32_t cnt) {
+__device__ __attribute__((always_inline)) inline void tile_hulls(HullShared& sh, uint32_t cnt) {
   const uint32_t tid = threadIdx.x;
   const uint32_t c0 = tid * kHullChunk;
   const uint32_t c1 = c0 + kHullChunk < cnt ? c0 + kHullChunk : (c0 < cnt ? cnt : c0);
@@ -176,7 +176,7 @@ __device__ inline void tile_hulls(HullShared& sh, uint32_t cnt) {
 // over hulls U (nu vertices) and L (nl vertices) given by accessors.  Every
 // thread receives the answer.  Called by the whole workgroup.
 template <class PU, class PL>
-__device__ inline EdgeSlope minimax_bend(HullShared& sh, const PU& U, uint32_t nu, const PL& L,
+__device__ __attribute__((always_inline)) inline EdgeSlope minimax_bend(HullShared& sh, const PU& U, uint32_t nu, const PL& L,
                                          uint32_t nl) {
   const uint32_t tid = threadIdx.x;
   bool found = false, from_upper = false;

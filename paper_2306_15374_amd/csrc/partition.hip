@@ -332,7 +332,7 @@ __device__ uint64_t range_cost(FitShared& sh, const uint8_t* col, uint32_t dtype
   }
   block_minmax_u64(sh, vmin, vmax);
   const uint64_t range = vmax - vmin;
-  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
   if (len > 1 && range < (uint64_t(1) << 61)) {
     block_sum_u128x2(sh, sv, stv);
     const double th = block_slope(sh, len, sv, stv);
@@ -367,7 +367,7 @@ __device__ uint64_t range_cost_lane(const uint8_t* col, uint32_t dtype, uint64_t
     stv = add128(stv, mul64x64(t, x));
   }
   const uint64_t range = vmax - vmin;
-  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
   if (len > 1 && range < (uint64_t(1) << 61)) {
     const double th = ls_slope(len, sv, stv);
     int64_t rmin = INT64_MAX, rmax = INT64_MIN;
@@ -417,7 +417,7 @@ __device__ uint64_t range_cost_wave(const uint8_t* col, uint32_t dtype, uint64_t
   }
   wave_minmax_u64(vmin, vmax);
   const uint64_t range = vmax - vmin;
-  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0};
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
   if (len > 1 && range < (uint64_t(1) << 61)) {
     wave_sum_u128x2(sv, stv);
     const double th = ls_slope(len, sv, stv);

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
   const WorkItem it = items[blockIdx.x];
   const ServeCol c = cols[it.col];
   Header h;
-  if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n) {
+  if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n || h.poly) {
     if (threadIdx.x == 0) raise(err, kErrFormat);
     return;
   }

@@ -162,7 +162,7 @@ def test_batch_mixes_regressors(torch, codec, ref):
 def test_unknown_regressor_is_rejected(torch, codec):
     col = dev(torch, W.linear_noise(1000, 24))
     part, _ = P.make_partitioning(fixed_len=100)
-    part.regressor = 2
+    part.regressor = 3
     cap = 1 << 16
     buf = torch.zeros(cap, dtype=torch.uint8, device="cuda")
     st, _ = P.leco_encode(codec.ctx, col, 1000, P.LECO_U64, part, buf, cap, None)
