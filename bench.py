@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=24 * 4096 * 1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["sorted_keys", "batched", "served", "variable",
-                                           "encode_options"],
+                                           "encode_options", "higher_order"],
                     default="sorted_keys")
     ap.add_argument("--var-n", type=int, default=100_000_000)
     ap.add_argument("--tau", type=float, default=0.03,
@@ -557,6 +557,90 @@ def bench_encode_options(args):
     codec.close()
 
 
+def bench_higher_order(args):
+    """The polynomial regressor on the evaluation's higher-order data: a
+    two-sine signal with Gaussian noise (1e8 uint32 values, partitions of
+    1000) and blocks of random cubics (2e8 uint64 values, partitions of
+    2000).  Sizes, encode and decode times against the least-squares line."""
+    import torch
+    import paper_2306_15374_amd as P
+    from paper_2306_15374_amd import workloads as W
+
+    codec = P.Codec(0)
+    stream = torch.cuda.current_stream()
+    cols = {}
+    t_dec_all = out_all = alg_all = 0.0
+    for name, gen, n, L in (("cosmos", W.cosmos, 100_000_000, 1000),
+                            ("poly_blocks", W.poly_blocks, 200_000_000, 2000)):
+        log(f"{name}: drawing {n} values")
+        col = gen(n, 71)
+        d = torch.from_numpy(col).cuda()
+        w = col.dtype.itemsize
+        dt = P.LECO_U32 if w == 4 else P.LECO_U64
+        res = {"n": n, "dtype": col.dtype.name, "L": L}
+        pos = torch.from_numpy(W.uniform_positions(n, 10_000_000, 81)).cuda()
+        for reg in ("ls", "poly"):
+            part, _ = P.make_partitioning(fixed_len=L, regressor=reg)
+            cap = P.leco_max_blob_bytes(n, dt, part)
+            buf = torch.empty(cap, dtype=torch.uint8, device="cuda")
+            size = torch.zeros(1, dtype=torch.uint64, device="cuda")
+            enc = lambda: codec.check("leco_encode_async", P.leco_encode_async(
+                codec.ctx, d, n, dt, part, buf, cap, size))
+            enc()
+            codec.sync()
+            t_enc = time_events(torch, stream, enc, 3)
+            codec.sync()
+            nbytes = int(size.item())
+            blob = buf[:nbytes]
+            out = torch.empty_like(d)
+            dec = lambda: codec.check("leco_decode_all", P.leco_decode_all(
+                codec.ctx, blob, nbytes, out, n))
+            dec()
+            codec.sync()
+            assert torch.equal(out, d), f"{name} {reg}: round trip"
+            t_dec = time_events(torch, stream, dec, max(3, min(args.steps, 10)))
+            ra_out = torch.empty(pos.numel(), dtype=d.dtype, device="cuda")
+            ra = lambda: codec.check("leco_random_access", P.leco_random_access(
+                codec.ctx, blob, nbytes, pos, pos.numel(), ra_out))
+            ra()
+            codec.sync()
+            t_ra = time_events(torch, stream, ra, 3)
+            codec.sync()
+            res[reg] = {"blob_bytes": nbytes, "ratio": round(nbytes / (w * n), 5),
+                        "encode_ms": round(t_enc * 1e3, 3), "decode_all_ms": round(t_dec * 1e3, 3),
+                        "decode_GBps": round(w * n / t_dec / 1e9, 1),
+                        "decode_hbm_frac": round((nbytes + w * n) / t_dec / HBM_PEAK, 4),
+                        "lookups_per_s": round(pos.numel() / t_ra, 1)}
+            if reg == "poly":
+                t_dec_all += t_dec
+                out_all += w * n
+                alg_all += nbytes + w * n
+            del buf, blob, out
+        res["poly_smaller_pct"] = round(100 * (res["ls"]["blob_bytes"] - res["poly"]["blob_bytes"])
+                                        / res["ls"]["blob_bytes"], 2)
+        log(f"{name}: {res}")
+        cols[name] = res
+        del d, pos
+        torch.cuda.empty_cache()
+    res = {
+        "metric": "decoded GB/s + lookups/s vs HBM roofline (batched/served vs plain); p99 latency",
+        "value": round(out_all / t_dec_all / 1e9, 2), "unit": "GB/s decoded (decode_all, polynomial blobs)",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(t_dec_all * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64",
+        "data": "synthetic (seeded two-sine signal with Gaussian noise; blocks of random cubics)",
+        "config": {"workload": "polynomial regressor: 1e8 uint32 two-sine values (L 1000) and "
+                               "2e8 uint64 cubic-block values (L 2000)"},
+        "columns": cols,
+        "roofline": {"bound": "hbm", "achieved": round(alg_all / t_dec_all / 1e9, 1),
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": round(alg_all / t_dec_all / HBM_PEAK, 4), "traffic": None,
+                     "kernel": "k_decode (polynomial path)", "bytes_per_launch": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+    codec.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -571,6 +655,8 @@ def main():
         return bench_variable(args)
     if args.workload == "encode_options":
         return bench_encode_options(args)
+    if args.workload == "higher_order":
+        return bench_higher_order(args)
     import torch
     import paper_2306_15374_amd as P
     from paper_2306_15374_amd import workloads as W
