@@ -234,16 +234,22 @@ __device__ inline bool prediction_fits_i32(double theta1, uint64_t len) {
 // Polynomial prediction of a partition of n <= 4096 values: the Gram
 // polynomials of the positions, g1 = 2t - (n-1), g2 = 6t^2 - 6(n-1)t +
 // (n-1)(n-2), g3 = 20t^3 - 30(n-1)t^2 + (12n^2 - 30n + 22)t - (n-1)(n-2)(n-3),
-// are exact integers below 2^37 in magnitude (so exact in binary64), and
+// are integers below 2^37 in magnitude, and
 //   p_t = floor(fl(fl(fl(c1 g1) + fl(c2 g2)) + fl(c3 g3))).
+// The g_k are evaluated in binary64 in Horner form: for t, n <= 4096 every
+// intermediate is an integer below 2^42, so each operation is exact and the
+// values equal the integer polynomials.
 __device__ inline int64_t poly_predict(double c1, double c2, double c3, uint32_t t, uint32_t n) {
-  const int64_t x = t, N = n, a = N - 1;
-  const int64_t g1 = 2 * x - a;
-  const int64_t g2 = 6 * x * x - 6 * a * x + a * (N - 2);
-  const int64_t g3 = 20 * x * x * x - 30 * a * x * x + (12 * N * N - 30 * N + 22) * x -
-                     a * (N - 2) * (N - 3);
-  double s = __dadd_rn(__dmul_rn(c1, double(g1)), __dmul_rn(c2, double(g2)));
-  s = __dadd_rn(s, __dmul_rn(c3, double(g3)));
+  const double x = double(t), N = double(n), a = N - 1.0;
+  const double g1 = __dadd_rn(__dmul_rn(2.0, x), -a);
+  const double e2 = __dmul_rn(a, N - 2.0);
+  const double g2 = __dadd_rn(__dmul_rn(__dadd_rn(__dmul_rn(6.0, x), __dmul_rn(-6.0, a)), x), e2);
+  const double k3 = __dadd_rn(__dmul_rn(__dadd_rn(__dmul_rn(12.0, N), -30.0), N), 22.0);
+  const double e3 = __dmul_rn(e2, N - 3.0);
+  const double h3 = __dadd_rn(__dmul_rn(20.0, x), __dmul_rn(-30.0, a));
+  const double g3 = __dadd_rn(__dmul_rn(__dadd_rn(__dmul_rn(h3, x), k3), x), -e3);
+  double s = __dadd_rn(__dmul_rn(c1, g1), __dmul_rn(c2, g2));
+  s = __dadd_rn(s, __dmul_rn(c3, g3));
   return static_cast<int64_t>(floor(s));
 }
 
