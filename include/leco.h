@@ -117,11 +117,10 @@ typedef enum { LECO_U32 = 4, LECO_U64 = 8 } leco_dtype;
  *   simpler).  Its blobs set header flag bit 1 and hold, 16-byte aligned
  *   after the records (and starts), one (c2, c3) binary64 pair per
  *   partition (zero for a line); a polynomial record has kind byte 25 = 1
- *   and c1 in the slope field.  Such blobs are decoded by leco_decode_all,
- *   leco_decode_range, leco_random_access and leco_filter_sum (value by
- *   value, without model-bound pruning); batched and served decoding reject
- *   them with LECO_EFORMAT.  Least-squares and minimax blobs keep flag bit
- *   1 clear and every kind byte 0. */
+ *   and c1 in the slope field.  Every decoder (single-column, batched and
+ *   served) decodes such blobs, value by value and without model-bound
+ *   pruning.  Least-squares and minimax blobs keep flag bit 1 clear and
+ *   every kind byte 0. */
 typedef enum {
   LECO_REGRESSOR_LS = 0,
   LECO_REGRESSOR_MINIMAX = 1,
@@ -223,8 +222,7 @@ typedef struct {
   void *blob_dev;
   uint64_t blob_cap;
   uint64_t *blob_bytes_dev;
-  int32_t regressor; /* leco_regressor, as in leco_partitioning (batched
-                        decoding does not take polynomial blobs) */
+  int32_t regressor; /* leco_regressor, as in leco_partitioning */
   int32_t reserved;  /* must be 0 */
 } leco_encode_job;
 

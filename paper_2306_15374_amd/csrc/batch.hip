@@ -48,7 +48,9 @@ __device__ __attribute__((always_inline)) bool run_tile(const DecCol& c, const H
                                                         uint32_t* stage) {
   BatchSink<OutT, kStore, kFilter> sink{reinterpret_cast<OutT*>(c.out),
                                         FilterSink{c.lo, c.hi, 0, 0, 0, kStore ? 0 : 1}};
-  const bool ok = g0 >= g1 || decode_tile(c.blob, h, g0, g1, stage, sink);
+  // blobs with polynomial partitions: value by value, every value decoded
+  const bool ok = g0 >= g1 || (h.poly ? decode_range_poly(c.blob, h, g0, g1, sink)
+                                      : decode_tile(c.blob, h, g0, g1, stage, sink));
   if (kFilter) block_add_sum(sink.f.sum_lo, sink.f.sum_hi, sink.f.count, c.sum3);
   return ok;
 }
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restric
   for (uint64_t k = blockIdx.x; k < total_tiles; k += gridDim.x) {
     const DecCol& c = cols[tile_col[k]];
     Header h;
-    if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n || h.poly) {
+    if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n) {
       if (threadIdx.x == 0) raise(err, kErrFormat);
       continue;
     }

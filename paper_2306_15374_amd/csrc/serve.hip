@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
   const WorkItem it = items[blockIdx.x];
   const ServeCol c = cols[it.col];
   Header h;
-  if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n || h.poly) {
+  if (!load_header(c.blob, c.blob_bytes, h) || h.n != c.n) {
     if (threadIdx.x == 0) raise(err, kErrFormat);
     return;
   }
@@ -67,7 +67,8 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
                            ? positions[it.a + i]
                            : global_ptr(reinterpret_cast<const uint64_t*>(it.a))[i];
     uint64_t v = 0;
-    if (g >= h.n || !lookup_value(c.blob, h, g, v)) raise(err, g >= h.n ? kErrRange : kErrFormat);
+    if (g >= h.n || !(h.poly ? lookup_value_poly(c.blob, h, g, v) : lookup_value(c.blob, h, g, v)))
+      raise(err, g >= h.n ? kErrRange : kErrFormat);
     if (h.dtype == 8)
       reinterpret_cast<uint64_t*>(out)[i] = v;
     else
@@ -80,10 +81,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
   bool ok;
   if (h.dtype == 8) {
     StoreSink<uint64_t> sink{reinterpret_cast<uint64_t*>(out), it.a};
-    ok = decode_tile(c.blob, h, g0, g1, stage, sink);
+    ok = h.poly ? decode_range_poly(c.blob, h, g0, g1, sink) : decode_tile(c.blob, h, g0, g1, stage, sink);
   } else {
     StoreSink<uint32_t> sink{reinterpret_cast<uint32_t*>(out), it.a};
-    ok = decode_tile(c.blob, h, g0, g1, stage, sink);
+    ok = h.poly ? decode_range_poly(c.blob, h, g0, g1, sink) : decode_tile(c.blob, h, g0, g1, stage, sink);
   }
   if (!ok && lane_id() == 0) raise(err, kErrFormat);
 }

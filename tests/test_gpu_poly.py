@@ -138,15 +138,38 @@ def test_batch_mixes_regressors(torch, codec, ref):
         assert np.array_equal(got, ref.encode(col, fixed_len=L, regressor=name)), f"L={L} {name}"
 
 
-def test_batched_decode_refuses_polynomial_blobs(torch, codec):
-    col = W.cosmos(10_000, 30)
-    blob = codec.encode(dev(torch, col), fixed_len=1000, regressor="poly")
-    out = torch.empty(len(col), dtype=torch.uint32, device="cuda")
-    job = P.DecodeJob(blob.data_ptr(), blob.numel(), len(col), out.data_ptr(), 0, 0)
-    handle = P.leco_batch_create(codec.ctx, [job])
+def test_batched_decode_and_filter_of_polynomial_blobs(torch, codec, ref):
+    """One batch of polynomial and linear blobs: decoded values and fused
+    filter sums equal the columns (polynomial tiles take the value-by-value
+    path inside the same launch)."""
+    cols = [W.cosmos(50_000, 40), W.poly_blocks(80_000, 41), W.linear_noise(30_000, 42),
+            W.cosmos(7_777, 43)]
+    regs = ["poly", "poly", "ls", "poly"]
+    blobs, outs, sums, jobs = [], [], [], []
+    for col, reg in zip(cols, regs):
+        b = codec.encode(dev(torch, col), fixed_len=1000, regressor=reg)
+        o = torch.zeros(len(col), dtype=torch.uint32 if col.dtype == np.uint32 else torch.uint64,
+                        device="cuda")
+        s3 = torch.zeros(3, dtype=torch.uint64, device="cuda")
+        lo = int(col.min()) + (int(col.max()) - int(col.min())) // 3
+        hi = lo + (int(col.max()) - int(col.min())) // 3
+        jobs.append(P.DecodeJob(b.data_ptr(), b.numel(), len(col), o.data_ptr(), lo, hi, s3.data_ptr()))
+        blobs.append(b)
+        outs.append(o)
+        sums.append((s3, lo, hi))
+    handle = P.leco_batch_create(codec.ctx, jobs)
     try:
-        assert P.leco_batch_run(handle, P.LECO_BATCH_DECODE) == P.LECO_OK
-        assert P.leco_sync(codec.ctx) == P.LECO_EFORMAT
+        for op in (P.LECO_BATCH_DECODE, P.LECO_BATCH_DECODE | P.LECO_BATCH_FILTER):
+            for o in outs:
+                o.zero_()
+            assert P.leco_batch_run(handle, op) == P.LECO_OK
+            codec.sync()
+            for col, o in zip(cols, outs):
+                assert np.array_equal(o.cpu().numpy(), col)
+        for col, (s3, lo, hi) in zip(cols, sums):
+            v = [int(x) for x in s3.cpu().numpy()]
+            sel = col[(col >= lo) & (col < hi)].astype(object)
+            assert ((v[1] << 64) | v[0], v[2]) == (int(sum(sel)), len(sel))
     finally:
         P.leco_batch_destroy(handle)
 

@@ -303,3 +303,22 @@ def test_open_loop_replay_reports_latencies(torch, codec, columns):
         assert np.all(lat > 0) and elapsed > 0
     finally:
         P.leco_server_stop(server)
+
+
+def test_polynomial_blobs_are_served(torch, codec):
+    """Resident columns encoded with the polynomial regressor: lookups and
+    range scans equal the columns."""
+    hosts_np = [W.cosmos(400_000, 71), W.poly_blocks(300_003, 72)]
+    specs = [dict(n=len(h)) for h in hosts_np]
+    cols = [torch.from_numpy(h).cuda() for h in hosts_np]
+    blobs = [codec.encode(c, fixed_len=1000, regressor="poly") for c in cols]
+    columns = (specs, cols, blobs, hosts_np)
+    reqs = W.request_mix(120, [s["n"] for s in specs], seed=73, max_log2_k=12, range_exp=(1, 5.3))
+    server = start(codec, columns)
+    try:
+        got = run_all(torch, codec, server, reqs)
+        for i, r in enumerate(reqs):
+            assert np.array_equal(got[i], expected(r, hosts_np)), f"request {i} {r['kind']}"
+    finally:
+        P.leco_server_stop(server)
+    assert codec.sync() is None
