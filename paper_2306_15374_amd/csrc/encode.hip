@@ -379,7 +379,7 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
     const uint32_t cnt = uint32_t(len - t0 < kHullTile ? len - t0 : kHullTile);
     for (uint32_t x = tid; x < cnt; x += kEncBlock) hs.v[x] = uint64_t(gsrc[t0 + x]);
     __syncthreads();
-    tile_hulls(hs, cnt);
+    tile_hulls<kEncBlock>(hs, cnt, tid);
     if (ntiles == 1) break;
     uint32_t keep[2], from[2], c[2];
     for (uint32_t side = 0; side < 2; ++side) c[side] = hs.cnt[side][0];
@@ -427,7 +427,7 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
       const uint32_t t = hs.h[1][i];
       return HullPoint{t, hs.v[t]};
     };
-    th = minimax_bend(hs, U, hs.cnt[0][0], L, hs.cnt[1][0]);
+    th = minimax_bend<kEncBlock>(hs, U, hs.cnt[0][0], L, hs.cnt[1][0], tid);
   } else {
     const auto U = [&](uint32_t i) {
       const uint32_t t = run_up[i];
@@ -437,7 +437,7 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
       const uint32_t t = run_lo[i];
       return HullPoint{t, uint64_t(gsrc[t])};
     };
-    th = minimax_bend(hs, U, hs.rcnt[0], L, hs.rcnt[1]);
+    th = minimax_bend<kEncBlock>(hs, U, hs.rcnt[0], L, hs.rcnt[1], tid);
   }
   // one correctly rounded division of the exact edge fraction
   double theta = static_cast<double>(th.dy) / static_cast<double>(th.dt);
@@ -491,6 +491,78 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_minimax(const EncColumn* __re
           : fit_minimax(fs, hs, reinterpret_cast<const uint32_t*>(c.col) + start, len,
                         c.force_constant, minimax, run_up, run_lo);
   if (threadIdx.x == 0) store_model(scr, P, md, len);
+}
+
+// The same with one wavefront per partition of at most kWaveEncMax values
+// (four per workgroup, no workgroup barrier): the least-squares model of
+// fit_wave, then the minimax line from the partition's hulls in the
+// wavefront's own LDS slice.  Launches holding polynomial columns never use
+// this kernel.
+template <class T>
+__device__ __attribute__((always_inline)) inline Model fit_minimax_wave(HullSharedT<64>& hs,
+                                                                        const T* src, uint64_t len,
+                                                                        bool force_constant,
+                                                                        bool minimax) {
+  Model md = fit_wave(src, len, force_constant);
+  if (!minimax || len < 2 || force_constant || md.range >= (uint64_t(1) << 61)) return md;
+  const uint32_t lane = threadIdx.x & 63;
+  const auto gsrc = global_ptr(src);
+  for (uint32_t x = lane; x < len; x += 64) hs.v[x] = uint64_t(gsrc[x]);
+  group_sync<64>();
+  tile_hulls<64>(hs, uint32_t(len), lane);
+  const auto U = [&](uint32_t i) {
+    const uint32_t t = hs.h[0][i];
+    return HullPoint{t, hs.v[t]};
+  };
+  const auto L = [&](uint32_t i) {
+    const uint32_t t = hs.h[1][i];
+    return HullPoint{t, hs.v[t]};
+  };
+  const EdgeSlope th = minimax_bend<64>(hs, U, hs.cnt[0][0], L, hs.cnt[1][0], lane);
+  double theta = static_cast<double>(th.dy) / static_cast<double>(th.dt);
+  if (theta == 0.0) theta = 0.0;  // +0.0, never -0.0
+  int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+  for (uint32_t t = lane; t < len; t += 64) {
+    const int64_t rr = int64_t(hs.v[t] - md.vmin) - predict(theta, t);
+    rmin = rr < rmin ? rr : rmin;
+    rmax = rr > rmax ? rr : rmax;
+  }
+  wave_minmax_i64(rmin, rmax);
+  const uint32_t b = bitlen64(uint64_t(rmax) - uint64_t(rmin));
+  if (b < md.bits) {
+    md.linear = true;
+    md.theta1 = theta;
+    md.base = md.vmin + uint64_t(rmin);
+    md.bits = b;
+    md.rmin = rmin;
+  }
+  return md;
+}
+
+__global__ __launch_bounds__(kEncBlock) void k_fit_minimax_wave(const EncColumn* __restrict__ cols,
+                                                               uint64_t ncols, EncColumn single,
+                                                               uint64_t nparts, EncScratch scr,
+                                                               int* err) {
+  __shared__ HullSharedT<64> hs[kEncWaves];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t P = uint64_t(blockIdx.x) * kEncWaves + wave;
+  if (P >= nparts) return;
+  const EncColumn c = column_of(cols, ncols, single, P);
+  uint64_t start, len;
+  part_bounds(c, P - c.part_base, start, len);
+  if (len > kWaveEncMax) {  // the host sends such partitions to k_fit_minimax
+    if (lane == 0) raise(err, kErrDevice);
+    return;
+  }
+  const bool minimax = c.regressor == 1;
+  const Model md =
+      c.dtype == 8
+          ? fit_minimax_wave(hs[wave], reinterpret_cast<const uint64_t*>(c.col) + start, len,
+                             c.force_constant, minimax)
+          : fit_minimax_wave(hs[wave], reinterpret_cast<const uint32_t*>(c.col) + start, len,
+                             c.force_constant, minimax);
+  if (lane == 0) store_model(scr, P, md, len);
 }
 
 // ---- fit with the polynomial regressor: one workgroup per partition ---------------
@@ -859,7 +931,10 @@ hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t
   if (!(regs & (kRegLS | kRegMinimax))) return hipGetLastError();
   const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave && !(regs & kRegPoly);
   const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
-  if (regs & kRegMinimax)
+  if ((regs & kRegMinimax) && wave)
+    hipLaunchKernelGGL(k_fit_minimax_wave, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream, cols_dev,
+                       ncols, single, nparts, scr, ctx->err_dev);
+  else if (regs & kRegMinimax)
     hipLaunchKernelGGL(k_fit_minimax, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr, ctx->err_dev);
   else if (wave)

@@ -8,9 +8,10 @@
 // the hull edge it comes from (an upper edge when an upper and a lower edge
 // have the same slope).
 //
-// GPU layout, one workgroup per partition, tiles of 4096 points:
+// GPU layout, a group of kT threads per partition (a workgroup of 256, tiles
+// of 4096 points, or one wavefront of 64, partitions of at most 1024):
 //   * every thread builds the hulls of its 16 consecutive points in LDS;
-//   * eight rounds merge neighbouring hulls pairwise: one thread per pair
+//   * log2(kT) rounds merge neighbouring hulls pairwise: one thread per pair
 //     and side walks to the bridge (the common tangent), then the group
 //     moves the right hull's kept vertices next to the left hull's;
 //   * a partition of several tiles merges each tile's hulls into a running
@@ -90,23 +91,41 @@ __device__ __attribute__((always_inline)) inline void hull_bridge(bool upper, co
   from = j;
 }
 
-struct HullShared {
-  uint64_t v[kHullTile];            // the tile's values
-  uint16_t h[2][kHullTile];         // upper, lower hull vertices (tile positions)
-  uint16_t cnt[2][kEncBlock];       // hull sizes, at each group's first thread
-  uint16_t keep[2][kEncBlock];      // bridge results, at each group's first thread
-  uint16_t from[2][kEncBlock];
+template <int kT>
+struct HullSharedT {
+  static constexpr uint32_t kTile = kT * kHullChunk;
+  uint64_t v[kTile];                // the tile's values
+  uint16_t h[2][kTile];             // upper, lower hull vertices (tile positions)
+  uint16_t cnt[2][kT];              // hull sizes, at each group's first thread
+  uint16_t keep[2][kT];             // bridge results, at each group's first thread
+  uint16_t from[2][kT];
   uint32_t rcnt[2];                 // running hull sizes (partitions of several tiles)
   uint32_t rkeep[2], rfrom[2];      // bridge of the running hull and the tile's
-  int64_t red_dy[kEncWaves];
-  uint32_t red_dt[kEncWaves];
-  uint32_t red_flag[kEncWaves];
+  int64_t red_dy[kT / 64];
+  uint32_t red_dt[kT / 64];
+  uint32_t red_flag[kT / 64];
 };
+using HullShared = HullSharedT<kEncBlock>;
+
+// Makes the group's LDS writes visible to the whole group: a workgroup
+// barrier, or for a single wavefront a wave barrier with wavefront fences.
+template <int kT>
+__device__ __attribute__((always_inline)) inline void group_sync() {
+  if constexpr (kT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
 
 // Upper and lower hulls of the tile's points 0 .. cnt-1 (values in sh.v),
-// left in sh.h[side][0 .. sh.cnt[side][0]).  Called by the whole workgroup.
-__device__ __attribute__((always_inline)) inline void tile_hulls(HullShared& sh, uint32_t cnt) {
-  const uint32_t tid = threadIdx.x;
+// left in sh.h[side][0 .. sh.cnt[side][0]).  Called by every thread tid of
+// the group.
+template <int kT>
+__device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>& sh, uint32_t cnt,
+                                                                 uint32_t tid) {
   const uint32_t c0 = tid * kHullChunk;
   const uint32_t c1 = c0 + kHullChunk < cnt ? c0 + kHullChunk : (c0 < cnt ? cnt : c0);
   for (uint32_t side = 0; side < 2; ++side) {
@@ -121,8 +140,8 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullShared& sh,
     }
     sh.cnt[side][tid] = uint16_t(k);
   }
-  __syncthreads();
-  for (uint32_t G = 2; G <= uint32_t(kEncBlock); G <<= 1) {
+  group_sync<kT>();
+  for (uint32_t G = 2; G <= uint32_t(kT); G <<= 1) {
     const uint32_t half = G >> 1, r = tid & (G - 1), g = tid - r;
     if (r < 2) {
       const uint32_t side = r;
@@ -141,7 +160,7 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullShared& sh,
       sh.keep[side][g] = uint16_t(keep);
       sh.from[side][g] = uint16_t(from);
     }
-    __syncthreads();
+    group_sync<kT>();
     // the right hull's kept vertices, staged so that moving them left never
     // overwrites one not yet read: at most 16 * half / G = 8 per thread
     constexpr uint32_t kStage = kHullChunk / 2;
@@ -157,7 +176,7 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullShared& sh,
         stage[side][s] = x < moved[side] ? HB[x] : 0;
       }
     }
-    __syncthreads();
+    group_sync<kT>();
     for (uint32_t side = 0; side < 2; ++side) {
       const uint32_t keep = sh.keep[side][g];
       uint16_t* HA = sh.h[side] + kHullChunk * g + keep;
@@ -168,21 +187,22 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullShared& sh,
       }
       if (r == side) sh.cnt[side][g] = uint16_t(keep + moved[side]);
     }
-    __syncthreads();
+    group_sync<kT>();
   }
 }
 
 // The smallest hull edge slope at which the strip width stops decreasing,
 // over hulls U (nu vertices) and L (nl vertices) given by accessors.  Every
-// thread receives the answer.  Called by the whole workgroup.
-template <class PU, class PL>
-__device__ __attribute__((always_inline)) inline EdgeSlope minimax_bend(HullShared& sh, const PU& U, uint32_t nu, const PL& L,
-                                         uint32_t nl) {
-  const uint32_t tid = threadIdx.x;
+// thread receives the answer.  Called by every thread tid of the group.
+template <int kT, class PU, class PL>
+__device__ __attribute__((always_inline)) inline EdgeSlope minimax_bend(HullSharedT<kT>& sh,
+                                                                        const PU& U, uint32_t nu,
+                                                                        const PL& L, uint32_t nl,
+                                                                        uint32_t tid) {
   bool found = false, from_upper = false;
   EdgeSlope best{0, 1};
   const uint32_t edges = (nu - 1) + (nl - 1);
-  for (uint32_t e = tid; e < edges; e += kEncBlock) {
+  for (uint32_t e = tid; e < edges; e += kT) {
     EdgeSlope th;
     uint32_t t_up, t_lo;
     bool upper_edge;
@@ -239,16 +259,18 @@ __device__ __attribute__((always_inline)) inline EdgeSlope minimax_bend(HullShar
     const uint32_t f = static_cast<uint32_t>(__shfl_xor(static_cast<int>(flag), m, 64));
     take(dy, dt, f);
   }
-  const uint32_t lane = tid & 63, wave = tid >> 6;
-  if (lane == 0) {
-    sh.red_dy[wave] = best.dy;
-    sh.red_dt[wave] = best.dt;
-    sh.red_flag[wave] = flag;
-  }
-  __syncthreads();
+  if constexpr (kT > 64) {
+    const uint32_t lane = tid & 63, wave = tid >> 6;
+    if (lane == 0) {
+      sh.red_dy[wave] = best.dy;
+      sh.red_dt[wave] = best.dt;
+      sh.red_flag[wave] = flag;
+    }
+    __syncthreads();
 #pragma unroll
-  for (int w = 0; w < kEncWaves; ++w) take(sh.red_dy[w], sh.red_dt[w], sh.red_flag[w]);
-  __syncthreads();
+    for (int w = 0; w < kT / 64; ++w) take(sh.red_dy[w], sh.red_dt[w], sh.red_flag[w]);
+    __syncthreads();
+  }
   return best;
 }
 
