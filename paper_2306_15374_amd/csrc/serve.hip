@@ -380,13 +380,14 @@ void free_server(leco_server* s) {
   for (Slot& slot : s->slots) {
     if (slot.stream) (void)hipStreamSynchronize(slot.stream);
     if (slot.done) (void)hipEventDestroy(slot.done);
-    if (slot.stream) hipStreamDestroy(slot.stream);
-    if (slot.items_host) hipHostFree(slot.items_host);
-    if (slot.items_dev) hipFree(slot.items_dev);
+    // teardown: an error here leaves nothing to undo, so it is not reported
+    if (slot.stream) (void)hipStreamDestroy(slot.stream);
+    if (slot.items_host) (void)hipHostFree(slot.items_host);
+    if (slot.items_dev) (void)hipFree(slot.items_dev);
   }
-  if (s->cols_dev) hipFree(s->cols_dev);
-  if (s->arena_dev) hipFree(s->arena_dev);
-  if (s->ring_host) hipHostFree(s->ring_host);
+  if (s->cols_dev) (void)hipFree(s->cols_dev);
+  if (s->arena_dev) (void)hipFree(s->arena_dev);
+  if (s->ring_host) (void)hipHostFree(s->ring_host);
   delete s->arena;
   delete s->ring;
   delete s;
@@ -410,7 +411,10 @@ leco_status leco_server_start(leco_ctx* ctx, const leco_resident_col* cols, uint
   s->cfg = *cfg;
   if (s->cfg.max_step_positions == 0) s->cfg.max_step_positions = 1u << 20;
   if (s->cfg.position_ring_bytes == 0) s->cfg.position_ring_bytes = uint64_t(64) << 20;
-  hipSetDevice(ctx->device);
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    delete s;
+    return LECO_EDEVICE;
+  }
   for (uint64_t i = 0; i < ncols; ++i) {
     uint8_t hdr[64];
     if (!cols[i].blob_dev || (reinterpret_cast<uintptr_t>(cols[i].blob_dev) & 15) ||
@@ -604,7 +608,7 @@ leco_status leco_server_stop(leco_server* s) {
     s->cv.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
-  hipSetDevice(s->ctx->device);
+  (void)hipSetDevice(s->ctx->device);  // teardown continues either way
   free_server(s);
   return LECO_OK;
 }
