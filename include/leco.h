@@ -227,7 +227,8 @@ typedef struct {
 } leco_encode_job;
 
 /* Encodes every job with one sequence of launches per group of columns
- * (columns whose partitions fit one wavefront, and the others): a fit
+ * (columns whose partitions fit one wavefront, the other least-squares and
+ * minimax columns, and the polynomial-regressor columns): a fit
  * launch writes every partition's model and word count, a scan gives the
  * word offsets within each column, and a pack launch writes the residual
  * words; no partition waits for another.  Produces exactly the blobs of
