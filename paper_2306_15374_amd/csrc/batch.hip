@@ -28,6 +28,9 @@ struct DecCol {
 template <typename OutT, bool kStore, bool kFilter>
 struct BatchSink {
   static constexpr bool kWholeTile = kStore;
+  // runs of short partitions in full rounds when only storing: the fused
+  // filter's accumulators would push the kernel past its register budget
+  static constexpr bool kFlat = kStore && !kFilter;
   OutT* out;
   FilterSink f;
   __device__ bool visit_segment(const Part& p, uint32_t t0, uint32_t t1) {
@@ -55,12 +58,15 @@ __device__ __attribute__((always_inline)) bool run_tile(const DecCol& c, const H
   return ok;
 }
 
+// Six waves per SIMD: the register allocator is held to 80 VGPRs.
 template <bool kStore, bool kFilter>
-__global__ __launch_bounds__(kBlock) void k_batch_decode(const DecCol* __restrict__ cols,
-                                                         const uint32_t* __restrict__ tile_col,
-                                                         uint64_t total_tiles, int* err) {
-  __shared__ uint4 stage_v[kWavesPerBlock * kWaveSlotWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveSlotWords;
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_decode(
+    const DecCol* __restrict__ cols, const uint32_t* __restrict__ tile_col, uint64_t total_tiles,
+    int* err) {
+  // (the sink's type does not depend on the column's width)
+  constexpr uint32_t kSlot = slot_words<BatchSink<uint32_t, kStore, kFilter>>();
+  __shared__ uint4 stage_v[kWavesPerBlock * kSlot / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kSlot;
   for (uint64_t k = blockIdx.x; k < total_tiles; k += gridDim.x) {
     const DecCol& c = cols[tile_col[k]];
     Header h;

@@ -57,13 +57,15 @@ __device__ void decode_tiles_poly(const uint8_t* __restrict__ blob, const Header
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_decode(const uint8_t* __restrict__ blob,
-                                                   uint64_t blob_bytes, uint8_t* __restrict__ out,
-                                                   uint64_t begin, uint64_t end, uint64_t out_cap,
-                                                   uint32_t tile_log2, uint64_t num_tiles, int all,
-                                                   int remap, int* err) {
-  __shared__ uint4 stage_v[kWavesPerBlock * kWaveSlotWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveSlotWords;
+// Six waves per SIMD: the register allocator is held to 80 VGPRs, which
+// the decode paths fit without spilling.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_decode(
+    const uint8_t* __restrict__ blob, uint64_t blob_bytes, uint8_t* __restrict__ out,
+    uint64_t begin, uint64_t end, uint64_t out_cap, uint32_t tile_log2, uint64_t num_tiles,
+    int all, int remap, int* err) {
+  constexpr uint32_t kSlot = slot_words<StoreSink<uint64_t>>();
+  __shared__ uint4 stage_v[kWavesPerBlock * kSlot / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kSlot;
   Header h;
   if (!load_header(blob, blob_bytes, h)) {
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
@@ -217,8 +219,9 @@ __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict
                                                        uint64_t blob_bytes, uint64_t lo,
                                                        uint64_t hi, uint64_t* out3,
                                                        uint32_t tile_log2, int prune, int* err) {
-  __shared__ uint4 stage_v[kWavesPerBlock * kWaveSlotWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveSlotWords;
+  constexpr uint32_t kSlot = slot_words<FilterSink>();
+  __shared__ uint4 stage_v[kWavesPerBlock * kSlot / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kSlot;
   Header h;
   if (!load_header(blob, blob_bytes, h)) {
     if (threadIdx.x == 0 && blockIdx.x == 0) raise(err, kErrFormat);
@@ -236,7 +239,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict
     wave_share(t0, t1, tile_log2, g0, g1);
     // blobs with polynomial partitions: every value decoded, no pruning
     if (!bad && g0 < g1 &&
-        !(h.poly ? decode_range_poly(blob, h, g0, g1, sink) : decode_tile(blob, h, g0, g1, stage, sink)))
+        !(h.poly ? decode_range_poly(blob, h, g0, g1, sink)
+                 : decode_tile(blob, h, g0, g1, stage, sink)))
       bad = true;
   }
   if (bad && lane_id() == 0) raise(err, kErrFormat);
@@ -245,16 +249,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict
 
 // ---- diagnostics: streaming copy / fill for HBM calibration -----------------------
 
+// 16 bytes per lane and iteration, four workgroups per CU (the fastest
+// shape of a sweep over 1-16 bytes per lane, 256-1024 threads per
+// workgroup and 2-32 workgroups per CU on MI355X: about 5.5 TB/s of
+// read + write for a 2 GiB copy).
 __global__ __launch_bounds__(256) void k_diag_copy(const uint4* __restrict__ src,
                                                    uint4* __restrict__ dst, uint64_t n16) {
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride) {
-    const uint4 v = src ? src[i] : make_uint4(0, 0, 0, 0);
-    __builtin_nontemporal_store(v.x, &dst[i].x);
-    __builtin_nontemporal_store(v.y, &dst[i].y);
-    __builtin_nontemporal_store(v.z, &dst[i].z);
-    __builtin_nontemporal_store(v.w, &dst[i].w);
-  }
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
+    dst[i] = src ? src[i] : make_uint4(0, 0, 0, 0);
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -340,7 +343,7 @@ hipError_t launch_diag_copy(leco_ctx* ctx, const void* src, void* dst, uint64_t 
                             hipStream_t stream) {
   const uint64_t n16 = bytes / 16;
   if (n16 == 0) return hipSuccess;
-  const uint64_t grid = uint64_t(ctx->num_cus) * 8;
+  const uint64_t grid = uint64_t(ctx->num_cus) * 4;
   hipLaunchKernelGGL(k_diag_copy, dim3(uint32_t(grid)), dim3(256), 0, stream,
                      static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
   return hipGetLastError();

@@ -21,14 +21,40 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 // at up to 32 bits) plus slack for the alignment of the first load and the
 // two words read past a field.
 constexpr uint32_t kWaveStageWords = 1024 + 16;
-// A piece of a tile covers at most this many partitions; their records sit
-// in LDS after the residual words while the piece is decoded.
+// A piece of a tile covers at most kPieceSegs partitions (kFlatPieceSegs
+// when runs of short partitions may be decoded in full rounds); their
+// records sit in LDS after the residual words while the piece is decoded.
 constexpr uint32_t kPieceSegs = 16;
+constexpr uint32_t kFlatPieceSegs = 64;
 struct PieceRec {
-  uint64_t start, end, base, theta_bits, word_off, bits;
+  uint64_t base, theta_bits;
+  int32_t start;  // partition start minus the piece's first position
+  uint32_t len;
+  int32_t qoff;   // stage bit of residual t = 0 (0 when b = 0)
+  uint32_t bits;
 };
-// LDS per wavefront: residual words, then the piece's records.
-constexpr uint32_t kWaveSlotWords = kWaveStageWords + kPieceSegs * sizeof(PieceRec) / 4;
+static_assert(sizeof(PieceRec) == 32, "two 16-byte LDS reads per record");
+// Pieces of at most kFlatSpan values whose partitions are shorter than
+// kFlatMeanLen on average are decoded lane by lane across partition
+// boundaries, with a bitmap of the piece's partition starts in LDS.
+constexpr uint32_t kFlatSpan = 4096;
+constexpr uint32_t kFlatMeanLen = 256;
+constexpr uint32_t kBitmapWords = kFlatSpan / 32;
+constexpr uint32_t kFlatUnroll = 4;
+// LDS per wavefront: residual words, the piece's records and, for a sink
+// that allows full-round decoding (Sink::kFlat), the start bitmap.  A sink
+// that may skip segments decodes segment by segment and needs the residual
+// words only.
+template <class Sink>
+constexpr uint32_t piece_segs() {
+  return Sink::kFlat ? kFlatPieceSegs : kPieceSegs;
+}
+template <class Sink>
+constexpr uint32_t slot_words() {
+  return !Sink::kWholeTile ? kWaveStageWords
+                           : kWaveStageWords + piece_segs<Sink>() * sizeof(PieceRec) / 4 +
+                                 (Sink::kFlat ? kBitmapWords : 0);
+}
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
 // Wavefront index, read from the first lane so the compiler treats it (and
@@ -139,6 +165,98 @@ __device__ inline void decode_values(const Part& p, uint32_t c0, uint32_t c1, in
   }
 }
 
+// Decodes the piece [g0, g0 + span) whose records are in `table` and whose
+// residual words are staged, 64 consecutive values per round whatever the
+// partition boundaries: bit x of `starts` marks a partition start at g0 + x
+// (the first partition, which holds g0, has none), so the partition of
+// value x is the number of marked bits at or below x, counted for the
+// whole round from the wavefront's ballot.
+//
+// kRes: 0 when every width is 0 (no residual), 1 when every width is at
+// most 32, 2 otherwise; kFast: every slope is >= 0 and every prediction
+// below 2^31; kConst: every width and slope is 0 (runs of one value), so
+// each value is its partition's intercept.  kN rounds from r0 are decoded with their LDS reads grouped;
+// kMasked: the last round of the piece, where lanes past the span decode
+// its last value and store nothing.
+constexpr uint32_t kResZero = 0, kResNarrow = 1, kResWide = 2;
+
+template <uint32_t kN, bool kMasked, uint32_t kRes, bool kFast, bool kConst, class Sink>
+__device__ inline void flat_rounds(uint32_t r0, uint32_t& k_before, uint64_t g0, uint32_t span,
+                                   const PieceRec* table, const uint32_t* starts,
+                                   const uint32_t* stage, Sink& sink) {
+  const uint32_t lane = lane_id();
+  uint32_t x[kN], k[kN];
+#pragma unroll
+  for (uint32_t i = 0; i < kN; ++i) {
+    x[i] = (r0 + i) * kWave + lane;
+    k[i] = __builtin_amdgcn_ubfe(starts[x[i] >> 5], x[i] & 31, 1);
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < kN; ++i) {
+    const uint64_t m = __ballot(k[i]);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+        uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    k[i] += k_before + below;
+    k_before += uint32_t(__popcll(m));
+  }
+  if (kConst) {
+    uint64_t base[kN];
+#pragma unroll
+    for (uint32_t i = 0; i < kN; ++i) base[i] = table[k[i]].base;
+#pragma unroll
+    for (uint32_t i = 0; i < kN; ++i)
+      if (!kMasked || x[i] < span) sink.put(g0 + x[i], base[i]);
+    return;
+  }
+  PieceRec rec[kN];
+#pragma unroll
+  for (uint32_t i = 0; i < kN; ++i) rec[i] = table[k[i]];
+  uint32_t t[kN];
+  uint64_t u[kN];
+#pragma unroll
+  for (uint32_t i = 0; i < kN; ++i) {
+    const uint32_t xc = (kMasked && x[i] >= span) ? span - 1 : x[i];
+    t[i] = uint32_t(int32_t(xc) - rec[i].start);
+    const uint32_t b = rec[i].bits;
+    const uint32_t q = uint32_t(rec[i].qoff) + b * t[i];
+    const uint32_t* w = stage + (q >> 5);
+    const uint32_t sh = q & 31;
+    if (kRes == kResZero) {
+      u[i] = 0;
+    } else if (kRes == kResWide) {
+      const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+      const uint64_t v = (uint64_t(__builtin_amdgcn_alignbit(w2, w1, sh)) << 32) |
+                         __builtin_amdgcn_alignbit(w1, w0, sh);
+      u[i] = b >= 64 ? v : v & ((uint64_t(1) << b) - 1);
+    } else {
+      const uint32_t v = __builtin_amdgcn_alignbit(w[1], w[0], sh);
+      u[i] = b >= 32 ? v : v & ((1u << b) - 1u);
+    }
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < kN; ++i) {
+    const double th = __longlong_as_double(static_cast<long long>(rec[i].theta_bits));
+    const int64_t p = kFast ? int64_t(int32_t(__dmul_rn(th, double(t[i])))) : predict(th, t[i]);
+    if (!kMasked || x[i] < span) sink.put(g0 + x[i], rec[i].base + uint64_t(p) + u[i]);
+  }
+}
+
+template <uint32_t kRes, bool kFast, bool kConst = false, class Sink>
+__device__ inline void decode_piece_flat(uint64_t g0, uint32_t span, const PieceRec* table,
+                                         const uint32_t* starts, const uint32_t* stage,
+                                         Sink& sink) {
+  const uint32_t full = span / kWave;
+  uint32_t k_before = 0;  // partition of the value before the round, uniform
+  uint32_t r = 0;
+  for (; r + kFlatUnroll <= full; r += kFlatUnroll)
+    flat_rounds<kFlatUnroll, false, kRes, kFast, kConst>(r, k_before, g0, span, table, starts,
+                                                         stage, sink);
+  for (; r < full; ++r)
+    flat_rounds<1, false, kRes, kFast, kConst>(r, k_before, g0, span, table, starts, stage, sink);
+  if (span % kWave)
+    flat_rounds<1, true, kRes, kFast, kConst>(r, k_before, g0, span, table, starts, stage, sink);
+}
+
 // 32-bit word range [ws, we) (relative to the words section) holding the
 // residuals t in [t0, t1) of partition p.
 __device__ inline void word_span(const Part& p, uint32_t t0, uint32_t t1, uint64_t& ws,
@@ -200,11 +318,13 @@ __device__ inline uint64_t locate_wave(const uint8_t* blob, const Header& h, uin
 // control flow is uniform across the wavefront.
 //
 // When the sink visits every segment (Sink::kWholeTile) the tile goes in
-// pieces of up to kPieceSegs partitions: lane k loads and checks the
+// pieces of up to piece_segs<Sink>() partitions: lane k loads and checks the
 // record of the piece's k-th partition (one round trip for all of them)
 // and parks it in the wavefront's LDS slot, the residual words of the whole
 // piece are staged in one round trip, and the segments are decoded from
-// the stage one after the other.  A piece whose words do not fit the slot,
+// the stage one after the other, or, for a piece of short partitions and a
+// sink that allows it (Sink::kFlat), lane by lane across the partition
+// boundaries (decode_piece_flat).  A piece whose words do not fit the slot,
 // and every tile of a sink that may skip segments, is decoded segment by
 // segment in chunks instead.
 template <class Sink>
@@ -215,12 +335,13 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
   if (Sink::kWholeTile) {
     const uint32_t lane = lane_id();
     PieceRec* table = reinterpret_cast<PieceRec*>(stage + kWaveStageWords);
+    constexpr uint32_t kSegs = piece_segs<Sink>();
+    uint32_t* bitmap = stage + kWaveStageWords + kSegs * sizeof(PieceRec) / 4;
     while (g0 < g1) {
-      // lane k < kPieceSegs: partition j0 + k, a segment of the piece if it
+      // lane k < kSegs: partition j0 + k, a segment of the piece if it
       // starts before g1
       const uint64_t jl = j0 + lane;
-      const bool want =
-          lane < kPieceSegs && jl < h.m && (lane == 0 || part_start(blob, h, jl) < g1);
+      const bool want = lane < kSegs && jl < h.m && (lane == 0 || part_start(blob, h, jl) < g1);
       Part lp{0, 0, 0, 0.0, 0, 0};
       const bool ok = want && load_part(blob, h, jl, lp);
       if (__ballot(want && !ok)) return false;
@@ -244,24 +365,59 @@ __device__ bool decode_tile(const uint8_t* __restrict__ blob, const Header& h, u
       const uint64_t span_lo = lane_u64(ws, 0), span_hi = lane_u64(we, nseg - 1);
       const uint64_t a0 = span_lo & ~uint64_t(3);
       if (__ballot(gap) || span_hi - a0 + 8 > kWaveStageWords) break;  // chunked path
-      if (want)
-        table[lane] = PieceRec{lp.start, end_l, lp.base, uint64_t(__double_as_longlong(lp.theta1)),
-                               lp.word_off, lp.bits};
+      const uint32_t span = uint32_t(ge - g0);
+      const bool flat =
+          Sink::kFlat && nseg > 1 && span <= kFlatSpan && span < kFlatMeanLen * nseg;
+      if (flat) {
+        for (uint32_t i = lane; i < kBitmapWords; i += kWave) bitmap[i] = 0;
+        wave_sync();
+      }
+      if (want) {
+        // lane 0's partition holds g0; the others start inside the piece
+        const int32_t qoff = lp.bits ? int32_t(int64_t(64 * lp.word_off) - int64_t(32 * a0)) : 0;
+        table[lane] = PieceRec{lp.base, uint64_t(__double_as_longlong(lp.theta1)),
+                               int32_t(int64_t(lp.start) - int64_t(g0)), uint32_t(lp.len), qoff,
+                               lp.bits};
+        if (flat && lane > 0) {
+          const uint32_t x = uint32_t(lp.start - g0);
+          atomicOr(&bitmap[x >> 5], 1u << (x & 31));
+        }
+      }
+      const bool wide = flat && __ballot(want && lp.bits > 32) != 0;
+      const bool zero = flat && __ballot(want && lp.bits != 0) == 0;
+      const bool cnst = zero && __ballot(want && lp.theta1 != 0.0) == 0;
+      const bool fast =
+          flat && __ballot(want && (lp.theta1 < 0.0 || !prediction_fits_i32(lp.theta1, lp.len))) == 0;
       if (span_hi > span_lo) stage_words(words32, a0, span_hi, stage);
       wave_sync();
-      for (uint32_t k = 0; k < nseg; ++k) {
-        const PieceRec r = table[k];
-        Part p;
-        p.start = uniform_u64(r.start);
-        p.len = uniform_u64(r.end) - p.start;
-        p.base = uniform_u64(r.base);
-        p.theta1 = __longlong_as_double(static_cast<long long>(uniform_u64(r.theta_bits)));
-        p.word_off = uniform_u64(r.word_off);
-        p.bits = uint32_t(uniform_u64(r.bits));
-        const uint64_t s0 = g0 > p.start ? g0 : p.start;
-        const uint64_t s1 = ge < p.start + p.len ? ge : p.start + p.len;
-        const int64_t qoff = int64_t(64 * p.word_off) - int64_t(32 * a0);
-        decode_values(p, uint32_t(s0 - p.start), uint32_t(s1 - p.start), qoff, stage, sink);
+      if (flat) {
+        if (wide)
+          decode_piece_flat<kResWide, false>(g0, span, table, bitmap, stage, sink);
+        else if (cnst)
+          decode_piece_flat<kResZero, true, true>(g0, span, table, bitmap, stage, sink);
+        else if (zero && fast)
+          decode_piece_flat<kResZero, true>(g0, span, table, bitmap, stage, sink);
+        else if (zero)
+          decode_piece_flat<kResZero, false>(g0, span, table, bitmap, stage, sink);
+        else if (fast)
+          decode_piece_flat<kResNarrow, true>(g0, span, table, bitmap, stage, sink);
+        else
+          decode_piece_flat<kResNarrow, false>(g0, span, table, bitmap, stage, sink);
+      } else {
+        for (uint32_t k = 0; k < nseg; ++k) {
+          const PieceRec r = table[k];
+          Part p;
+          p.start = uint64_t(int64_t(g0) + int32_t(__builtin_amdgcn_readfirstlane(r.start)));
+          p.len = uint32_t(__builtin_amdgcn_readfirstlane(int(r.len)));
+          p.base = uniform_u64(r.base);
+          p.theta1 = __longlong_as_double(static_cast<long long>(uniform_u64(r.theta_bits)));
+          p.word_off = 0;  // the stage offset is qoff
+          p.bits = uint32_t(__builtin_amdgcn_readfirstlane(int(r.bits)));
+          const int64_t qoff = int32_t(__builtin_amdgcn_readfirstlane(r.qoff));
+          const uint64_t s0 = g0 > p.start ? g0 : p.start;
+          const uint64_t s1 = ge < p.start + p.len ? ge : p.start + p.len;
+          decode_values(p, uint32_t(s0 - p.start), uint32_t(s1 - p.start), qoff, stage, sink);
+        }
       }
       wave_sync();
       g0 = ge;
@@ -322,6 +478,7 @@ __device__ inline void wave_share(uint64_t t0, uint64_t t1, uint32_t tile_log2, 
 template <typename OutT>
 struct StoreSink {
   static constexpr bool kWholeTile = true;
+  static constexpr bool kFlat = true;
   OutT* out;
   uint64_t origin;
   __device__ bool visit_segment(const Part&, uint32_t, uint32_t) { return true; }
@@ -451,6 +608,7 @@ __device__ inline bool lookup_value_poly(const uint8_t* __restrict__ blob, const
 // interval, evaluated exactly, lies inside [0, 2^64) so that no value wraps.
 struct FilterSink {
   static constexpr bool kWholeTile = false;  // may skip segments by their model bounds
+  static constexpr bool kFlat = false;
   uint64_t lo, hi;
   uint64_t sum_lo, sum_hi, count;
   int prune;
@@ -481,27 +639,39 @@ struct FilterSink {
 // every thread of the workgroup.
 __device__ inline void block_add_sum(uint64_t sum_lo, uint64_t sum_hi, uint64_t count,
                                      uint64_t* out3) {
-  __shared__ uint64_t red[3][kBlock];
-  const uint32_t tid = threadIdx.x;
-  red[0][tid] = sum_lo;
-  red[1][tid] = sum_hi;
-  red[2][tid] = count;
-  __syncthreads();
-  for (uint32_t s = kBlock / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const uint64_t a = red[0][tid], b = red[0][tid + s];
-      red[0][tid] = a + b;
-      red[1][tid] += red[1][tid + s] + (a + b < a);
-      red[2][tid] += red[2][tid + s];
-    }
-    __syncthreads();
+  // wavefront sums by butterfly shuffles (128-bit adds with carry), then
+  // the workgroup's kWavesPerBlock partials through LDS
+  __shared__ uint64_t red[kWavesPerBlock][3];
+  for (int m = kWave / 2; m > 0; m >>= 1) {
+    const uint64_t lo = __shfl_xor(static_cast<unsigned long long>(sum_lo), m, kWave);
+    const uint64_t hi = __shfl_xor(static_cast<unsigned long long>(sum_hi), m, kWave);
+    const uint64_t c = __shfl_xor(static_cast<unsigned long long>(count), m, kWave);
+    const uint64_t s = sum_lo + lo;
+    sum_hi += hi + (s < sum_lo ? 1 : 0);
+    sum_lo = s;
+    count += c;
   }
-  if (tid == 0 && (red[0][0] | red[1][0] | red[2][0])) {
-    const uint64_t x = red[0][0];
-    const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(out3), x);
-    const uint64_t carry = (old + x < old) ? 1 : 0;
-    atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 1), red[1][0] + carry);
-    atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 2), red[2][0]);
+  const uint32_t w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    red[w][0] = sum_lo;
+    red[w][1] = sum_hi;
+    red[w][2] = count;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t lo = 0, hi = 0, c = 0;
+    for (uint32_t i = 0; i < kWavesPerBlock; ++i) {
+      const uint64_t s = lo + red[i][0];
+      hi += red[i][1] + (s < lo ? 1 : 0);
+      lo = s;
+      c += red[i][2];
+    }
+    if (lo | hi | c) {
+      const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(out3), lo);
+      const uint64_t carry = (old + lo < old) ? 1 : 0;
+      atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 1), hi + carry);
+      atomicAdd(reinterpret_cast<unsigned long long*>(out3 + 2), c);
+    }
   }
   __syncthreads();
 }

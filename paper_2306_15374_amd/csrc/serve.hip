@@ -50,8 +50,9 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
                                                        const WorkItem* __restrict__ items,
                                                        const uint64_t* __restrict__ positions,
                                                        uint8_t* __restrict__ arena, int* err) {
-  __shared__ uint4 stage_v[kWavesPerBlock * kWaveSlotWords / 4];
-  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kWaveSlotWords;
+  constexpr uint32_t kSlot = slot_words<StoreSink<uint64_t>>();
+  __shared__ uint4 stage_v[kWavesPerBlock * kSlot / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kSlot;
   const WorkItem it = items[blockIdx.x];
   const ServeCol c = cols[it.col];
   Header h;

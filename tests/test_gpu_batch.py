@@ -129,6 +129,38 @@ def test_batch_decode_filter_fused_and_graph(torch, codec):
         P.leco_batch_destroy(batch)
 
 
+def test_batch_decode_short_partitions(torch, codec):
+    """Columns of short partitions (variable lengths 1..80, fixed L = 24):
+    the batched decoder's pieces cross partition boundaries within a round."""
+    rng = np.random.default_rng(17)
+    specs, cols, blobs = [], [], []
+    for i, (n, dtype) in enumerate([(30_000, np.uint64), (25_001, np.uint32), (9_000, np.uint64),
+                                    (40_000, np.uint32)]):
+        host = W.linear_noise(n, 80 + i, dtype) if i % 2 else W.constant_runs(n, 80 + i).astype(dtype)
+        c = torch.from_numpy(host).cuda()
+        if i < 2:
+            s = [0]
+            while s[-1] < n:
+                s.append(min(n, s[-1] + int(rng.integers(1, 81))))
+            blobs.append(codec.encode(c, starts=np.array(s, np.uint64)))
+        else:
+            blobs.append(codec.encode(c, fixed_len=24))
+        specs.append(dict(n=n, dtype=dtype))
+        cols.append(c)
+    batch, outs, sums, bounds = make_batch(torch, codec, specs, cols, blobs)
+    try:
+        for tl in (0, 10, 14):
+            codec.check("set_shape", P.leco_batch_set_shape(batch, tl, 0))
+            for op in (P.LECO_BATCH_DECODE, P.LECO_BATCH_DECODE | P.LECO_BATCH_FILTER):
+                for o in outs:
+                    o.zero_()
+                codec.check("leco_batch_run", P.leco_batch_run(batch, op))
+                codec.sync()
+                check_outputs(torch, specs, cols, outs, sums, bounds, summed=bool(op & 2))
+    finally:
+        P.leco_batch_destroy(batch)
+
+
 def test_every_launch_shape_gives_identical_results(torch, codec):
     specs = small_specs(ncols=24, seed=9)
     cols = [W.make_column_device(s) for s in specs]

@@ -185,6 +185,79 @@ def test_fixed_tile_shapes(torch, ref, monkeypatch, tile_log2):
         c.close()
 
 
+# ---- short partitions: pieces decoded lane by lane across partition boundaries ----
+
+def short_partition_cases(rng):
+    """Columns whose partitions are short enough (tens to a few hundred values)
+    for a wavefront to decode a run of them in full 64-value rounds."""
+    n = 40_000
+    t = np.arange(n, dtype=np.uint64)
+    decreasing = (np.uint64(2**63) - t * np.uint64(977) - rng.integers(0, 300, n, dtype=np.uint64))
+    wide = t * np.uint64(2**40) + rng.integers(0, 2**38, n, dtype=np.uint64)
+    runs = W.constant_runs(n, 34)
+    full32 = rng.integers(0, 2**32 - 1, 5000, np.uint64, endpoint=True).astype(np.uint32)
+    mixed = np.concatenate([W.linear_noise(10_000, 35), np.sort(rng.integers(0, 2**62, 10_000,
+                                                                            dtype=np.uint64)),
+                            np.full(10_000, 42, np.uint64), decreasing[:10_000]])
+    return [
+        ("short decreasing u64 (negative slopes)", decreasing,
+         dict(starts=random_partitioning(rng, n, 40))),
+        ("short wide u64 (b~38, large predictions)", wide,
+         dict(starts=random_partitioning(rng, n, 60))),
+        ("short constant runs u32 (greedy)", runs, dict(starts=None)),
+        ("L=7 full range u32 (b=32)", full32, dict(fixed_len=7)),
+        ("L=200 linear noise u64", W.linear_noise(50_001, 36), dict(fixed_len=200)),
+        ("L=33 linear noise u32", W.linear_noise(30_000, 37, np.uint32), dict(fixed_len=33)),
+        ("short mixed generators u64", mixed, dict(starts=random_partitioning(rng, len(mixed), 300))),
+    ]
+
+
+def test_short_partitions(torch, codec, ref):
+    rng = np.random.default_rng(33)
+    for name, col, kw in short_partition_cases(rng):
+        if "starts" in kw and kw["starts"] is None:
+            kw = dict(starts=ref.partition_greedy(col, tau=0.1, sm_bits=320))
+        check_column(torch, codec, ref, col, name, **kw)
+
+
+@pytest.mark.parametrize("tile_log2", [8, 11, 14])
+def test_short_partitions_tile_shapes(torch, ref, monkeypatch, tile_log2):
+    """Wavefront shares of 64, 512 and 4096 values: pieces start inside a
+    partition, end at the share's end, and span up to the bitmap's size."""
+    monkeypatch.setenv("LECO_TILE_LOG2", str(tile_log2))
+    c = P.Codec(0)
+    try:
+        rng = np.random.default_rng(34)
+        for name, col, kw in short_partition_cases(rng)[:2] + short_partition_cases(rng)[4:5]:
+            check_column(torch, c, ref, col, f"tile 2^{tile_log2} {name}", **kw)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("env", [{"LECO_TILE_LOG2": "8"}, {"LECO_TILE_LOG2": "9"},
+                                 {"LECO_TILE_LOG2": "11", "LECO_DECODE_BLOCKS_PER_CU": "1"}])
+def test_variable_blob_tile_shapes(torch, ref, monkeypatch, env):
+    """Variable-length blobs with short and long partitions at tiles of 256
+    and 512 values, and with a persistent grid of one workgroup per CU that
+    walks many tiles: decode_all, ranges and the filter sum."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    c = P.Codec(0)
+    try:
+        rng = np.random.default_rng(35)
+        n = 1_200_000
+        runs = W.constant_runs(n, 36)
+        check_column(torch, c, ref, runs, f"{env} constant runs greedy",
+                     starts=ref.partition_greedy(runs, tau=0.1, sm_bits=320))
+        noise = W.linear_noise(n, 37)
+        check_column(torch, c, ref, noise, f"{env} linear noise 1..3000",
+                     starts=random_partitioning(rng, n, 3000))
+        check_column(torch, c, ref, noise[:400_000], f"{env} linear noise 1..20",
+                     starts=random_partitioning(rng, 400_000, 20))
+    finally:
+        c.close()
+
+
 # ---- slope arithmetic ------------------------------------------------------------
 
 def test_device_slope_matches_host_rounding(torch, codec):

@@ -322,3 +322,26 @@ def test_polynomial_blobs_are_served(torch, codec):
     finally:
         P.leco_server_stop(server)
     assert codec.sync() is None
+
+
+def test_short_partition_blobs_are_served(torch, codec):
+    """Resident columns of short partitions (variable lengths 1..100 and
+    fixed L = 30): range scans decode runs of partitions in full rounds."""
+    rng = np.random.default_rng(74)
+    hosts_np = [W.constant_runs(300_000, 75).astype(np.uint64), W.linear_noise(200_003, 76, np.uint32)]
+    specs = [dict(n=len(h)) for h in hosts_np]
+    cols = [torch.from_numpy(h).cuda() for h in hosts_np]
+    s = [0]
+    while s[-1] < len(hosts_np[0]):
+        s.append(min(len(hosts_np[0]), s[-1] + int(rng.integers(1, 101))))
+    blobs = [codec.encode(cols[0], starts=np.array(s, np.uint64)), codec.encode(cols[1], fixed_len=30)]
+    columns = (specs, cols, blobs, hosts_np)
+    reqs = W.request_mix(120, [s["n"] for s in specs], seed=77, max_log2_k=12, range_exp=(1, 5.3))
+    server = start(codec, columns)
+    try:
+        got = run_all(torch, codec, server, reqs)
+        for i, r in enumerate(reqs):
+            assert np.array_equal(got[i], expected(r, hosts_np)), f"request {i} {r['kind']}"
+    finally:
+        P.leco_server_stop(server)
+    assert codec.sync() is None
