@@ -475,10 +475,12 @@ __device__ inline void wave_share(uint64_t t0, uint64_t t1, uint32_t tile_log2, 
 
 // Writes each value to out[g - origin] with the column's width, bypassing
 // the caches (outputs are written once and not read back by the kernel).
-template <typename OutT>
+// kFlatRuns: runs of short partitions may be decoded in full rounds (which
+// costs the kernel LDS and registers).
+template <typename OutT, bool kFlatRuns = true>
 struct StoreSink {
   static constexpr bool kWholeTile = true;
-  static constexpr bool kFlat = true;
+  static constexpr bool kFlat = kFlatRuns;
   OutT* out;
   uint64_t origin;
   __device__ bool visit_segment(const Part&, uint32_t, uint32_t) { return true; }

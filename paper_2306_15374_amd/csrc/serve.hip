@@ -50,7 +50,9 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
                                                        const WorkItem* __restrict__ items,
                                                        const uint64_t* __restrict__ positions,
                                                        uint8_t* __restrict__ arena, int* err) {
-  constexpr uint32_t kSlot = slot_words<StoreSink<uint64_t>>();
+  // range work items decode partition by partition: the full-round decoder
+  // of short partitions would cost the step kernel a wave per SIMD
+  constexpr uint32_t kSlot = slot_words<StoreSink<uint64_t, false>>();
   __shared__ uint4 stage_v[kWavesPerBlock * kSlot / 4];
   uint32_t* stage = reinterpret_cast<uint32_t*>(stage_v) + wave_id() * kSlot;
   const WorkItem it = items[blockIdx.x];
@@ -81,10 +83,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
   if (g0 >= g1) return;
   bool ok;
   if (h.dtype == 8) {
-    StoreSink<uint64_t> sink{reinterpret_cast<uint64_t*>(out), it.a};
+    StoreSink<uint64_t, false> sink{reinterpret_cast<uint64_t*>(out), it.a};
     ok = h.poly ? decode_range_poly(c.blob, h, g0, g1, sink) : decode_tile(c.blob, h, g0, g1, stage, sink);
   } else {
-    StoreSink<uint32_t> sink{reinterpret_cast<uint32_t*>(out), it.a};
+    StoreSink<uint32_t, false> sink{reinterpret_cast<uint32_t*>(out), it.a};
     ok = h.poly ? decode_range_poly(c.blob, h, g0, g1, sink) : decode_tile(c.blob, h, g0, g1, stage, sink);
   }
   if (!ok && lane_id() == 0) raise(err, kErrFormat);

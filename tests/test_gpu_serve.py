@@ -326,7 +326,7 @@ def test_polynomial_blobs_are_served(torch, codec):
 
 def test_short_partition_blobs_are_served(torch, codec):
     """Resident columns of short partitions (variable lengths 1..100 and
-    fixed L = 30): range scans decode runs of partitions in full rounds."""
+    fixed L = 30): lookups and range scans equal the columns."""
     rng = np.random.default_rng(74)
     hosts_np = [W.constant_runs(300_000, 75).astype(np.uint64), W.linear_noise(200_003, 76, np.uint32)]
     specs = [dict(n=len(h)) for h in hosts_np]
