@@ -52,7 +52,7 @@ __device__ __attribute__((always_inline)) bool run_tile(const DecCol& c, const H
   BatchSink<OutT, kStore, kFilter> sink{reinterpret_cast<OutT*>(c.out),
                                         FilterSink{c.lo, c.hi, 0, 0, 0, kStore ? 0 : 1}};
   // blobs with polynomial partitions: value by value, every value decoded
-  const bool ok = g0 >= g1 || (h.poly ? decode_range_poly(c.blob, h, g0, g1, sink)
+  const bool ok = g0 >= g1 || (h.poly ? decode_range_poly(c.blob, h, g0, g1, stage, sink)
                                       : decode_tile(c.blob, h, g0, g1, stage, sink));
   if (kFilter) block_add_sum(sink.f.sum_lo, sink.f.sum_hi, sink.f.count, c.sum3);
   return ok;

@@ -39,7 +39,8 @@ __device__ void decode_tiles(const uint8_t* __restrict__ blob, const Header& h,
 template <typename OutT>
 __device__ void decode_tiles_poly(const uint8_t* __restrict__ blob, const Header& h,
                                   OutT* __restrict__ out, uint64_t begin, uint64_t e,
-                                  uint32_t tile_log2, uint64_t num_tiles, int* err) {
+                                  uint32_t tile_log2, uint64_t num_tiles, uint32_t* stage,
+                                  int* err) {
   StoreSink<OutT> sink{out, begin};
   const uint64_t first = begin >> tile_log2;
   for (uint64_t k = blockIdx.x; k < num_tiles; k += gridDim.x) {
@@ -50,7 +51,7 @@ __device__ void decode_tiles_poly(const uint8_t* __restrict__ blob, const Header
     if (t0 >= t1) break;
     uint64_t g0, g1;
     wave_share(t0, t1, tile_log2, g0, g1);
-    if (g0 < g1 && !decode_range_poly(blob, h, g0, g1, sink)) {
+    if (g0 < g1 && !decode_range_poly(blob, h, g0, g1, stage, sink)) {
       if (lane_id() == 0) raise(err, kErrFormat);
       return;
     }
@@ -85,10 +86,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
   if (h.poly) {
     if (h.dtype == 8)
       decode_tiles_poly(blob, h, reinterpret_cast<uint64_t*>(out), begin, e, tile_log2, num_tiles,
-                        err);
+                        stage, err);
     else
       decode_tiles_poly(blob, h, reinterpret_cast<uint32_t*>(out), begin, e, tile_log2, num_tiles,
-                        err);
+                        stage, err);
     return;
   }
   if (h.dtype == 8)
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_sum(const uint8_t* __restrict
     wave_share(t0, t1, tile_log2, g0, g1);
     // blobs with polynomial partitions: every value decoded, no pruning
     if (!bad && g0 < g1 &&
-        !(h.poly ? decode_range_poly(blob, h, g0, g1, sink)
+        !(h.poly ? decode_range_poly(blob, h, g0, g1, stage, sink)
                  : decode_tile(blob, h, g0, g1, stage, sink)))
       bad = true;
   }

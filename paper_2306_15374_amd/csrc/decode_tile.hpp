@@ -558,11 +558,14 @@ __device__ inline uint64_t residual_at(const uint64_t* words, const Part& p, uin
 }
 
 // Values [g0, g1) of a blob with coefficient section, by one wavefront;
-// false if a record is malformed.
+// false if a record is malformed.  Each partition's residual words are
+// staged in the wavefront's LDS slice (in chunks that fit it) with
+// coalesced 16-byte loads, then lane l decodes t = c0 + l, c0 + l + 64, ...
+// from the stage, so no lane waits on a global load of its own.
 template <class Sink>
 __device__ bool decode_range_poly(const uint8_t* __restrict__ blob, const Header& h, uint64_t g0,
-                                  uint64_t g1, Sink& sink) {
-  const uint64_t* words = reinterpret_cast<const uint64_t*>(blob + h.words_off);
+                                  uint64_t g1, uint32_t* stage, Sink& sink) {
+  const uint32_t* words32 = reinterpret_cast<const uint32_t*>(blob + h.words_off);
   const uint32_t lane = lane_id();
   uint64_t j = uniform_u64(locate(blob, h, g0));
   for (uint64_t g = g0; g < g1; ++j) {
@@ -573,11 +576,37 @@ __device__ bool decode_range_poly(const uint8_t* __restrict__ blob, const Header
         !load_model_kind(blob, h, j, p, kind, c2, c3))
       return false;
     const uint64_t end = p.start + p.len < g1 ? p.start + p.len : g1;
-    for (uint64_t x = g + lane; x < end; x += kWave) {
-      const uint32_t t = uint32_t(x - p.start);
-      const int64_t pred = kind ? poly_predict(p.theta1, c2, c3, t, uint32_t(p.len))
-                                : predict(p.theta1, t);
-      sink.put(x, p.base + uint64_t(pred) + residual_at(words, p, t));
+    const uint32_t b = p.bits, t_end = uint32_t(end - p.start);
+    const uint64_t mask = b >= 64 ? ~uint64_t(0) : (uint64_t(1) << b) - 1;
+    const uint32_t step = chunk_values(b);
+    for (uint32_t c0 = uint32_t(g - p.start); c0 < t_end;) {
+      const uint32_t c1 = (t_end - c0 > step) ? c0 + step : t_end;
+      int64_t qoff = 0;
+      if (b != 0) {
+        uint64_t ws, we;
+        word_span(p, c0, c1, ws, we);
+        const uint64_t a0 = ws & ~uint64_t(3);
+        stage_words(words32, a0, we, stage);
+        qoff = int64_t(64 * p.word_off) - int64_t(32 * a0);
+        wave_sync();
+      }
+      for (uint32_t t = c0 + lane; t < c1; t += kWave) {
+        uint64_t u = 0;
+        if (b != 0) {
+          // three words cover any field of up to 64 bits; the words past
+          // the staged ones only meet masked bits
+          const uint32_t q = uint32_t(qoff + int64_t(b) * t);
+          const uint32_t* w = stage + (q >> 5);
+          const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+          u = ((uint64_t(__builtin_amdgcn_alignbit(w2, w1, q & 31)) << 32) |
+               __builtin_amdgcn_alignbit(w1, w0, q & 31)) & mask;
+        }
+        const int64_t pred = kind ? poly_predict(p.theta1, c2, c3, t, uint32_t(p.len))
+                                  : predict(p.theta1, t);
+        sink.put(p.start + t, p.base + uint64_t(pred) + u);
+      }
+      if (b != 0) wave_sync();
+      c0 = c1;
     }
     g = end;
   }

@@ -84,10 +84,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
   bool ok;
   if (h.dtype == 8) {
     StoreSink<uint64_t, false> sink{reinterpret_cast<uint64_t*>(out), it.a};
-    ok = h.poly ? decode_range_poly(c.blob, h, g0, g1, sink) : decode_tile(c.blob, h, g0, g1, stage, sink);
+    ok = h.poly ? decode_range_poly(c.blob, h, g0, g1, stage, sink) : decode_tile(c.blob, h, g0, g1, stage, sink);
   } else {
     StoreSink<uint32_t, false> sink{reinterpret_cast<uint32_t*>(out), it.a};
-    ok = h.poly ? decode_range_poly(c.blob, h, g0, g1, sink) : decode_tile(c.blob, h, g0, g1, stage, sink);
+    ok = h.poly ? decode_range_poly(c.blob, h, g0, g1, stage, sink) : decode_tile(c.blob, h, g0, g1, stage, sink);
   }
   if (!ok && lane_id() == 0) raise(err, kErrFormat);
 }
