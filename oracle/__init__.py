@@ -107,8 +107,11 @@ def _bind(L: C.CDLL) -> C.CDLL:
     L.leco_ref_delta_partition_bits.restype = u64
     L.leco_ref_partition_cost_bytes.argtypes = [vp, u64, u64]
     L.leco_ref_partition_cost_bytes.restype = u64
-    L.leco_ref_partition_greedy.argtypes = [vp, u64, C.c_int, C.c_double, u64, u64, u64, vp,
-                                            P(u64)]
+    L.leco_ref_partition_greedy.argtypes = [vp, u64, C.c_int, C.c_double, u64, u64, u64,
+                                            C.c_int, vp, P(u64)]
+    L.leco_ref_partition_split.argtypes = [vp, u64, C.c_int, C.c_double, u64, u64, C.c_int, vp,
+                                           P(u64)]
+    L.leco_ref_start_positions.argtypes = [vp, u64, C.c_int, vp, P(u64)]
     L.leco_ref_partition_merge.argtypes = [vp, u64, C.c_int, vp, P(u64), u64, u64]
     L.leco_ref_partition_dp.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
     L.leco_ref_partition_bruteforce.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
@@ -121,6 +124,7 @@ def _bind(L: C.CDLL) -> C.CDLL:
                  "leco_ref_blob_record", "leco_ref_decode_all", "leco_ref_decode_range",
                  "leco_ref_random_access", "leco_ref_filter_sum",
                  "leco_ref_partition_greedy", "leco_ref_partition_merge",
+                 "leco_ref_partition_split", "leco_ref_start_positions",
                  "leco_ref_partition_dp", "leco_ref_partition_bruteforce",
                  "leco_ref_partitioning_cost", "leco_ref_fixed_cost",
                  "leco_ref_size_search_fn", "leco_ref_size_search"):
@@ -276,14 +280,37 @@ def partition_cost_bytes(values, i: int, j: int) -> int:
 
 
 def partition_greedy(col: np.ndarray, tau: float = 0.1, sm_bits: int = 320,
-                     max_len: int = 1 << 20, max_rounds: int = 0) -> np.ndarray:
+                     max_len: int = 1 << 20, max_rounds: int = 0,
+                     start_positions: bool = False) -> np.ndarray:
     col = np.ascontiguousarray(col)
     starts = np.zeros(len(col) + 1, dtype=np.uint64)
     m = C.c_uint64()
     _check("leco_ref_partition_greedy", lib().leco_ref_partition_greedy(
         _ptr(col), len(col), _dtype_code(col), tau, sm_bits, max_len, max_rounds,
+        int(start_positions), _ptr(starts), C.byref(m)))
+    return starts[: m.value + 1].copy()
+
+
+def partition_split(col: np.ndarray, tau: float = 0.1, sm_bits: int = 320,
+                    max_len: int = 1 << 20, start_positions: bool = False) -> np.ndarray:
+    """The split phase alone (section 3.2.2)."""
+    col = np.ascontiguousarray(col)
+    starts = np.zeros(len(col) + 1, dtype=np.uint64)
+    m = C.c_uint64()
+    _check("leco_ref_partition_split", lib().leco_ref_partition_split(
+        _ptr(col), len(col), _dtype_code(col), tau, sm_bits, max_len, int(start_positions),
         _ptr(starts), C.byref(m)))
     return starts[: m.value + 1].copy()
+
+
+def start_positions(col: np.ndarray) -> np.ndarray:
+    """First values of the starting partitions (section 3.2.2)."""
+    col = np.ascontiguousarray(col)
+    pos = np.zeros(max(len(col), 1), dtype=np.uint64)
+    c = C.c_uint64()
+    _check("leco_ref_start_positions", lib().leco_ref_start_positions(
+        _ptr(col), len(col), _dtype_code(col), _ptr(pos), C.byref(c)))
+    return pos[: c.value].copy()
 
 
 def partition_merge(col: np.ndarray, starts, max_len: int = 1 << 20,

@@ -917,27 +917,62 @@ static void merge_phase(const uint64_t *v, uint64_t *s, uint64_t *m_io,
   *m_io = m;
 }
 
-int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau,
-                              uint64_t sm_bits, uint64_t max_len,
-                              uint64_t max_rounds, uint64_t *starts_out,
-                              uint64_t *m_out) {
-  if ((dtype != 4 && dtype != 8) || max_len == 0 || max_len > MAX_PART_LEN)
-    return LREF_EINVAL;
-  if (n == 0) {
-    starts_out[0] = 0;
-    *m_out = 0;
-    return LREF_OK;
+/* Good starting positions (section 3.2.2, "Selecting Good Starting
+ * Positions", and the partitioning figure), read for the first differences
+ * the split works on (reading R27):
+ *   required bits  rb_k = signed width of d_k = bitlen(|d_k|) + 1, k >= 1;
+ *   delta bits     db_k = |rb_k - rb_{k-1}|, k >= 2;
+ * the positions whose delta bits equal the smallest over the column are
+ * good; each maximal run of good positions k..k' is one starting partition
+ * v[k-2, k'+1) (at least the three values a line needs).  forced[p] = 1 at
+ * the first value p = k - 2 of every starting partition; n < 3 has none. */
+static void starting_positions(const uint64_t *v, uint64_t n, unsigned char *forced) {
+  memset(forced, 0, n ? n : 1);
+  if (n < 3) return;
+  uint64_t best = ~(uint64_t)0;
+  for (uint64_t k = 2; k < n; k++) {
+    uint64_t a = signed_width(first_diff(v, k)), b = signed_width(first_diff(v, k - 1));
+    uint64_t db = a > b ? a - b : b - a;
+    if (db < best) best = db;
   }
-  uint64_t *v = load_column(col, n, dtype);
-  if (!v) return LREF_ENOMEM;
-  double threshold = tau * (double)sm_bits;
+  int prev_good = 0;
+  for (uint64_t k = 2; k < n; k++) {
+    uint64_t a = signed_width(first_diff(v, k)), b = signed_width(first_diff(v, k - 1));
+    int good = (a > b ? a - b : b - a) == best;
+    if (good && !prev_good) forced[k - 2] = 1;
+    prev_good = good;
+  }
+}
 
-  /* Split phase, left to right: keep the running range of first
-   * differences of the current partition and include v[j] while
-   * C = (len+1) * Delta~new - len * Delta~old <= tau * S_M and the partition
-   * stays within max_len.  A partition also begins at every multiple of
-   * 2^20 (the longest partition the format allows), so the split of each
-   * 2^20-value segment depends on that segment alone. */
+int leco_ref_start_positions(const void *col, uint64_t n, int dtype, uint64_t *pos_out,
+                             uint64_t *count_out) {
+  if (dtype != 4 && dtype != 8) return LREF_EINVAL;
+  uint64_t *v = load_column(col, n, dtype);
+  unsigned char *forced = (unsigned char *)malloc(n ? n : 1);
+  if (!v || !forced) {
+    free(v);
+    free(forced);
+    return LREF_ENOMEM;
+  }
+  starting_positions(v, n, forced);
+  uint64_t c = 0;
+  for (uint64_t p = 0; p < n; p++)
+    if (forced[p]) pos_out[c++] = p;
+  *count_out = c;
+  free(v);
+  free(forced);
+  return LREF_OK;
+}
+
+/* Split phase, left to right: keep the running range of first differences
+ * of the current partition and include v[j] while
+ * C = (len+1) * Delta~new - len * Delta~old <= tau * S_M and the partition
+ * stays within max_len.  A partition also begins at every multiple of 2^20
+ * (the longest partition the format allows), so the split of each
+ * 2^20-value segment depends on that segment alone, and, when forced is
+ * given, at the first value of every starting partition. */
+static uint64_t split_phase(const uint64_t *v, uint64_t n, double threshold, uint64_t max_len,
+                            const unsigned char *forced, uint64_t *starts_out) {
   uint64_t m = 0;
   uint64_t i = 0;
   starts_out[m++] = 0;
@@ -951,7 +986,8 @@ int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau
     uint64_t w_new = bitlen128((u128)(nmax - nmin));
     uint64_t len = j - i;
     double cost = (double)((int64_t)((len + 1) * w_new) - (int64_t)(len * w_old));
-    if (cost <= threshold && len < max_len && j % MAX_PART_LEN != 0) {
+    if (cost <= threshold && len < max_len && j % MAX_PART_LEN != 0 &&
+        !(forced && forced[j])) {
       dmin = nmin;
       dmax = nmax;
       have_diff = 1;
@@ -964,10 +1000,49 @@ int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau
     }
   }
   starts_out[m] = n;
-  merge_phase(v, starts_out, &m, max_len, max_rounds);
+  return m;
+}
+
+static int partition_common(const void *col, uint64_t n, int dtype, double tau,
+                            uint64_t sm_bits, uint64_t max_len, int merge,
+                            uint64_t max_rounds, int start_positions, uint64_t *starts_out,
+                            uint64_t *m_out) {
+  if ((dtype != 4 && dtype != 8) || max_len == 0 || max_len > MAX_PART_LEN)
+    return LREF_EINVAL;
+  if (n == 0) {
+    starts_out[0] = 0;
+    *m_out = 0;
+    return LREF_OK;
+  }
+  uint64_t *v = load_column(col, n, dtype);
+  unsigned char *forced = start_positions ? (unsigned char *)malloc(n) : NULL;
+  if (!v || (start_positions && !forced)) {
+    free(v);
+    free(forced);
+    return LREF_ENOMEM;
+  }
+  if (forced) starting_positions(v, n, forced);
+  uint64_t m = split_phase(v, n, tau * (double)sm_bits, max_len, forced, starts_out);
+  if (merge) merge_phase(v, starts_out, &m, max_len, max_rounds);
+  free(forced);
   free(v);
   *m_out = m;
   return LREF_OK;
+}
+
+int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau,
+                              uint64_t sm_bits, uint64_t max_len,
+                              uint64_t max_rounds, int start_positions,
+                              uint64_t *starts_out, uint64_t *m_out) {
+  return partition_common(col, n, dtype, tau, sm_bits, max_len, 1, max_rounds,
+                          start_positions, starts_out, m_out);
+}
+
+int leco_ref_partition_split(const void *col, uint64_t n, int dtype, double tau,
+                             uint64_t sm_bits, uint64_t max_len, int start_positions,
+                             uint64_t *starts_out, uint64_t *m_out) {
+  return partition_common(col, n, dtype, tau, sm_bits, max_len, 0, 0, start_positions,
+                          starts_out, m_out);
 }
 
 int leco_ref_partition_merge(const void *col, uint64_t n, int dtype,

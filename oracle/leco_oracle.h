@@ -165,12 +165,27 @@ uint64_t leco_ref_partition_cost_bytes(const uint64_t *v, uint64_t i,
 
 /* Greedy split + merge (section 3.2.2).  starts_out needs room for n + 1
  * entries.  max_len caps partition length (<= 2^20).  The split restarts at
- * every multiple of 2^20; the merge runs in rounds (see merge below), at
- * most max_rounds of them (0: until none merges). */
+ * every multiple of 2^20 and, with start_positions, at the first value of
+ * every starting partition (leco_ref_start_positions); the merge runs in
+ * rounds (see merge below), at most max_rounds of them (0: until none
+ * merges). */
 int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype,
                               double tau, uint64_t sm_bits, uint64_t max_len,
-                              uint64_t max_rounds, uint64_t *starts_out,
-                              uint64_t *m_out);
+                              uint64_t max_rounds, int start_positions,
+                              uint64_t *starts_out, uint64_t *m_out);
+
+/* The split phase of leco_ref_partition_greedy alone. */
+int leco_ref_partition_split(const void *col, uint64_t n, int dtype, double tau,
+                             uint64_t sm_bits, uint64_t max_len, int start_positions,
+                             uint64_t *starts_out, uint64_t *m_out);
+
+/* First values of the starting partitions (section 3.2.2, selecting good
+ * starting positions): with rb_k the signed width of d_k = v_k - v_{k-1}
+ * and db_k = |rb_k - rb_{k-1}|, each maximal run k..k' of positions whose
+ * db equals the column's smallest db starts a partition at k - 2.
+ * pos_out needs room for n entries; *count_out receives their number. */
+int leco_ref_start_positions(const void *col, uint64_t n, int dtype, uint64_t *pos_out,
+                             uint64_t *count_out);
 
 /* Merge phase alone, applied to a given partitioning (in place).  Each
  * round merges every adjacent pair whose size gain is positive and larger

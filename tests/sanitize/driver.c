@@ -162,7 +162,10 @@ int main(void) {
         }
         if (n >= 2) {
           uint64_t *st = (uint64_t *)malloc((n + 1) * 8), m = 0, bytes = 0;
-          CHECK(leco_ref_partition_greedy(col, n, dt, 0.05, 320, 1u << 20, 0, st, &m) == LREF_OK);
+          CHECK(leco_ref_partition_greedy(col, n, dt, 0.05, 320, 1u << 20, 0, 0, st, &m) == LREF_OK);
+          CHECK(leco_ref_partition_greedy(col, n, dt, 0.05, 320, 1u << 20, 0, 1, st, &m) == LREF_OK);
+          CHECK(leco_ref_partition_split(col, n, dt, 0.05, 320, 1u << 20, 1, st, &m) == LREF_OK);
+          CHECK(leco_ref_start_positions(col, n, dt, st, &m) == LREF_OK);
           CHECK(leco_ref_partitioning_cost(col, n, dt, st, m, &bytes) == LREF_OK);
           CHECK(leco_ref_partition_merge(col, n, dt, st, &m, 1u << 20, 2) == LREF_OK);
           (void)leco_ref_split_cost(v, 0, n - 1, 0);
