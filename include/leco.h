@@ -310,6 +310,14 @@ typedef struct {
   uint64_t sm_bits;    /* model size S_M in bits (320: record + start)        */
   uint64_t max_len;    /* longest partition, 1..2^20                          */
   uint64_t max_rounds; /* merge rounds at most (0: until none merges)         */
+  /* 1: the split also begins a partition at every starting position
+   * (section 3.2.2, selecting good starting positions): with rb_k =
+   * bitlen(|d_k|) + 1 the signed width of d_k = v_k - v_{k-1} and
+   * db_k = |rb_k - rb_{k-1}|, positions whose db is the column's smallest
+   * are good, and each maximal run k..k' of them is a starting partition
+   * v[k-2, k'+1) that begins a partition at k - 2.  0: plain split. */
+  int32_t start_positions;
+  int32_t reserved;    /* must be 0 */
 } leco_partition_params;
 
 leco_status leco_partition(leco_ctx *ctx, const void *col_dev, uint64_t n, leco_dtype dtype,

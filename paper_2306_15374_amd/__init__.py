@@ -45,7 +45,8 @@ class LecoError(RuntimeError):
 
 class PartitionParams(C.Structure):
     _fields_ = [("tau", C.c_double), ("sm_bits", C.c_uint64), ("max_len", C.c_uint64),
-                ("max_rounds", C.c_uint64)]
+                ("max_rounds", C.c_uint64), ("start_positions", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class EncodeJob(C.Structure):
@@ -456,11 +457,11 @@ class Codec:
         return buf[:size]
 
     def partition(self, col, tau: float = 0.1, sm_bits: int = 320, max_len: int = 1 << 20,
-                  max_rounds: int = 0, stream=None):
+                  max_rounds: int = 0, stream=None, start_positions: bool = False):
         """Variable-length partition starts of a CUDA tensor column (numpy
         uint64 array of m + 1 starts)."""
         import numpy as np
-        params = PartitionParams(tau, sm_bits, max_len, max_rounds)
+        params = PartitionParams(tau, sm_bits, max_len, max_rounds, int(start_positions), 0)
         # room for a mean partition length down to 16; a finer result is
         # computed again with the exact size
         cap = max(1024, col.numel() // 16 + 2)

@@ -110,10 +110,14 @@ __device__ inline bool bit_set(unsigned long long* bitmap, uint64_t j) {
 // [p, b) are a speculative run's, made from a different state; the walk
 // rewrites them until it starts a partition where the speculative run also
 // did (from there on both runs are the same), returning true at that point.
+//
+// forced (or null): bit j set means a partition begins at j (the first
+// value of a starting partition), whatever the cost.
 template <bool kFix>
 __device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t p,
                             uint64_t b, double thr, uint64_t max_len, SplitState& st,
-                            uint64_t* win, unsigned long long* __restrict__ bitmap) {
+                            uint64_t* win, unsigned long long* __restrict__ bitmap,
+                            const uint64_t* __restrict__ forced) {
   const uint32_t lane = threadIdx.x & 63;
   DKey kmin{st.kmin_hi, st.kmin_lo}, kmax{st.kmax_hi, st.kmax_lo};
   uint64_t i = st.i;
@@ -159,7 +163,8 @@ __device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uin
     if (lane == 0) w_prev = w_old;
     const uint64_t len = j - i;
     const int64_t cost = int64_t((len + 1) * w_new) - int64_t(len * w_prev);
-    const bool include = double(cost) <= thr && len < max_len;
+    const bool start_here = forced && valid && ((forced[j >> 6] >> (j & 63)) & 1ull);
+    const bool include = double(cost) <= thr && len < max_len && !start_here;
     const uint64_t split = __ballot(valid && !include);
     if (split == 0) {
       const int last = int(b - p - 1 < 63 ? b - p - 1 : 63);
@@ -207,14 +212,15 @@ __global__ __launch_bounds__(64) void k_split_spec(const uint8_t* __restrict__ c
                                                    uint32_t dtype, uint64_t n, double thr,
                                                    uint64_t max_len,
                                                    unsigned long long* __restrict__ bitmap,
-                                                   SplitState* __restrict__ states) {
+                                                   SplitState* __restrict__ states,
+                                                   const uint64_t* __restrict__ forced) {
   __shared__ uint64_t win[kSplitWindow + 1];  // win[k] = v[base - 1 + k]
   const uint64_t a = uint64_t(blockIdx.x) << kSubLog2;
   if (a >= n) return;
   const uint64_t b = n - a < (uint64_t(1) << kSubLog2) ? n : a + (uint64_t(1) << kSubLog2);
   if (threadIdx.x == 0) mark(bitmap, a);
   SplitState st{a, 0, 0, 0, 0, 0, 0};
-  greedy_walk<false>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap);
+  greedy_walk<false>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap, forced);
   if (threadIdx.x == 0) states[blockIdx.x] = st;
 }
 
@@ -225,7 +231,8 @@ __global__ __launch_bounds__(64) void k_split_fix(const uint8_t* __restrict__ co
                                                   uint32_t dtype, uint64_t n, double thr,
                                                   uint64_t max_len,
                                                   unsigned long long* __restrict__ bitmap,
-                                                  const SplitState* __restrict__ states) {
+                                                  const SplitState* __restrict__ states,
+                                                  const uint64_t* __restrict__ forced) {
   __shared__ uint64_t win[kSplitWindow + 1];
   constexpr uint64_t kSubs = uint64_t(1) << (kSegLog2 - kSubLog2);
   const uint64_t a = uint64_t(blockIdx.x) << kSegLog2;
@@ -236,8 +243,67 @@ __global__ __launch_bounds__(64) void k_split_fix(const uint8_t* __restrict__ co
     const uint64_t aq = a + (q << kSubLog2);
     if (aq >= n) break;
     const uint64_t bq = n - aq < (uint64_t(1) << kSubLog2) ? n : aq + (uint64_t(1) << kSubLog2);
-    const bool synced = greedy_walk<true>(col, dtype, aq, bq, thr, max_len, st, win, bitmap);
+    const bool synced =
+        greedy_walk<true>(col, dtype, aq, bq, thr, max_len, st, win, bitmap, forced);
     if (synced) st = states[q0 + q];  // the speculative run's end state is the true one
+  }
+}
+
+// ---- starting positions ----------------------------------------------------------
+//
+// Required bits rb_k = bitlen(|d_k|) + 1 of the first difference
+// d_k = v_k - v_{k-1} (k >= 1), delta bits db_k = |rb_k - rb_{k-1}|
+// (k >= 2); positions whose db is the column's smallest are good, and a
+// partition begins two values before the first of every run of good
+// positions (section 3.2.2, selecting good starting positions).
+
+__device__ inline uint32_t required_bits(const uint8_t* col, uint32_t dtype, uint64_t k) {
+  const uint64_t a = load_value(col, dtype, k), b = load_value(col, dtype, k - 1);
+  return bitlen64(a >= b ? a - b : b - a) + 1;
+}
+
+__device__ inline uint32_t delta_bits(const uint8_t* col, uint32_t dtype, uint64_t k) {
+  const uint32_t x = required_bits(col, dtype, k), y = required_bits(col, dtype, k - 1);
+  return x > y ? x - y : y - x;
+}
+
+// *min_db = the smallest db_k over k = 2 .. n-1 (it starts at ~0).
+__global__ __launch_bounds__(kScanBlock) void k_delta_bits_min(const uint8_t* __restrict__ col,
+                                                               uint32_t dtype, uint64_t n,
+                                                               uint32_t* __restrict__ min_db) {
+  uint32_t best = ~0u;
+  for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x + 2; k < n;
+       k += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t db = delta_bits(col, dtype, k);
+    best = db < best ? db : best;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = uint32_t(__shfl_xor(int(best), off, 64));
+    best = o < best ? o : best;
+  }
+  if ((threadIdx.x & 63) == 0 && best != ~0u) atomicMin(min_db, best);
+}
+
+// forced[w] bit l: a partition begins at p = 64 w + l, i.e. position p + 2
+// is good and p + 1 is not.  One lane per position; the wavefront's ballot
+// is the word.
+__global__ __launch_bounds__(kScanBlock) void k_mark_starts(const uint8_t* __restrict__ col,
+                                                            uint32_t dtype, uint64_t n,
+                                                            const uint32_t* __restrict__ min_db,
+                                                            uint64_t* __restrict__ forced) {
+  const uint32_t best = *min_db;
+  const uint64_t nwords = (n + 63) / 64;
+  for (uint64_t p0 = (uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u));
+       p0 < nwords * 64; p0 += uint64_t(gridDim.x) * blockDim.x) {
+    const uint64_t p = p0 + (threadIdx.x & 63);
+    bool start = false;
+    if (p + 2 < n) {
+      const bool good_next = delta_bits(col, dtype, p + 2) == best;
+      const bool good_here = p >= 1 && delta_bits(col, dtype, p + 1) == best;
+      start = good_next && !good_here;
+    }
+    const uint64_t word = __ballot(start);
+    if ((threadIdx.x & 63) == 0) forced[p0 >> 6] = word;
   }
 }
 
@@ -620,6 +686,8 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
     return pfail(ctx, LECO_EINVAL, "partition: null argument or bad dtype");
   if (prm->max_len == 0 || prm->max_len > leco::kMaxPartLen || !(prm->tau == prm->tau))
     return pfail(ctx, LECO_EINVAL, "partition: max_len outside 1..2^20 or tau NaN");
+  if ((prm->start_positions != 0 && prm->start_positions != 1) || prm->reserved != 0)
+    return pfail(ctx, LECO_EINVAL, "partition: start_positions not 0 or 1, or reserved not 0");
   if (n && (!col_dev || (reinterpret_cast<uintptr_t>(col_dev) & (uint64_t(dtype) - 1))))
     return pfail(ctx, LECO_EINVAL, "partition: null or misaligned column");
   if (starts_cap && !starts_host) return pfail(ctx, LECO_EINVAL, "partition: null starts buffer");
@@ -644,11 +712,27 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   const uint64_t nsub = (n + (uint64_t(1) << leco::kSubLog2) - 1) >> leco::kSubLog2;
   leco::SplitState* states = nullptr;
   if (!buf.alloc(&states, nsub)) return pfail(ctx, LECO_ENOMEM, "partition: split states");
+  // starting positions: a bitmap of forced partition starts
+  uint64_t* forced = nullptr;
+  if (prm->start_positions) {
+    uint32_t* min_db = nullptr;
+    if (!buf.alloc(&forced, nwords) || !buf.alloc(&min_db, 1))
+      return pfail(ctx, LECO_ENOMEM, "partition: starting positions");
+    P_TRY(hipMemsetAsync(min_db, 0xff, sizeof(uint32_t), stream));
+    const uint64_t cap = uint64_t(ctx->num_cus) * 8;
+    const uint64_t gd = (n + leco::kScanBlock - 1) / leco::kScanBlock;
+    hipLaunchKernelGGL(leco::k_delta_bits_min, dim3(uint32_t(gd < cap ? gd : cap)),
+                       dim3(leco::kScanBlock), 0, stream, col, w, n, min_db);
+    P_TRY(hipGetLastError());
+    hipLaunchKernelGGL(leco::k_mark_starts, dim3(uint32_t(gd < cap ? gd : cap)),
+                       dim3(leco::kScanBlock), 0, stream, col, w, n, min_db, forced);
+    P_TRY(hipGetLastError());
+  }
   hipLaunchKernelGGL(leco::k_split_spec, dim3(uint32_t(nsub)), dim3(64), 0, stream, col, w, n,
-                     thr, prm->max_len, bitmap, states);
+                     thr, prm->max_len, bitmap, states, forced);
   P_TRY(hipGetLastError());
   hipLaunchKernelGGL(leco::k_split_fix, dim3(uint32_t(nseg)), dim3(64), 0, stream, col, w, n, thr,
-                     prm->max_len, bitmap, states);
+                     prm->max_len, bitmap, states, forced);
   P_TRY(hipGetLastError());
 
   // starts from the bitmap

@@ -103,3 +103,48 @@ def test_longer_than_one_segment(torch, codec, ref):
     check(torch, codec, ref, col, "sorted normal, 3 segments")
     runs = W.constant_runs(n, 78)
     check(torch, codec, ref, runs, "constant runs, 3 segments")
+
+
+def test_starting_positions(torch, codec, ref):
+    """With starting positions (section 3.2.2) the split also begins a
+    partition at the first value of every starting partition: identical
+    starts on the workload shapes, both widths, a column whose smallest
+    delta bits are 2, differences beyond 64 bits, tiny columns and several
+    2^20-value split segments (starting positions near segment and
+    sub-chunk boundaries)."""
+    rng = np.random.default_rng(81)
+    n = 200_000
+    for kind, col in [("sorted_normal", W.sorted_normal(n, W.C3_SEEDS[0])),
+                      ("piecewise_linear", W.piecewise_linear(n, W.C3_SEEDS[1], segments=50)),
+                      ("constant_runs", W.constant_runs(n, W.C3_SEEDS[2])),
+                      ("noise u64", W.linear_noise(100_000, 82)),
+                      ("keys u32", W.lognormal_keys(100_000, 83, np.uint32))]:
+        starts = check(torch, codec, ref, col, f"{kind} with starting positions",
+                       start_positions=True, tau=0.05)
+        assert set(int(p) for p in ref.start_positions(col)) <= set(
+            int(s) for s in ref.partition_split(col, tau=0.05, start_positions=True))
+        if kind == "constant_runs":
+            blob = codec.encode(torch.from_numpy(col).cuda(), starts=starts)
+            assert np.array_equal(blob.cpu().numpy(), ref.encode(col, starts=starts))
+    d = np.tile(np.array([1, 4], np.uint64), 20_000)
+    alternating = np.concatenate([[np.uint64(7)], np.uint64(7) + np.cumsum(d)]).astype(np.uint64)
+    check(torch, codec, ref, alternating, "delta bits all 2", start_positions=True)
+    wide = rng.integers(0, 2**64 - 1, 20_000, dtype=np.uint64, endpoint=True)
+    wide[::3] = rng.integers(0, 16, len(wide[::3]), dtype=np.uint64)
+    check(torch, codec, ref, wide, "65-bit differences", start_positions=True)
+    for m in (1, 2, 3, 4, 5, 63, 64, 65, 127, 129):
+        check(torch, codec, ref, W.constant_runs(m, 84 + m), f"n={m}", start_positions=True)
+    big = 2 * (1 << 20) + 70_001
+    check(torch, codec, ref, W.constant_runs(big, 85), "constant runs, 3 segments",
+          start_positions=True)
+    check(torch, codec, ref, W.piecewise_linear(big, 86, segments=300), "polyline, 3 segments",
+          start_positions=True, tau=0.03)
+
+
+def test_partition_params_are_checked(torch, codec):
+    col = torch.from_numpy(W.linear_noise(1000, 87)).cuda()
+    out = np.zeros(1001, dtype=np.uint64)
+    for sp, res in ((2, 0), (-1, 0), (0, 1)):
+        params = P.PartitionParams(0.1, 320, 1 << 20, 0, sp, res)
+        st, _ = P.leco_partition(codec.ctx, col, 1000, P.LECO_U64, params, out)
+        assert st == P.LECO_EINVAL
