@@ -449,6 +449,13 @@ def bench_variable(args):
         t_dec = time_events(torch, stream, dec, args.steps)
         codec.sync()
         fixed = {L: codec.encode(d, fixed_len=L).numel() for L in (1024, 4096)}
+        # the split also beginning partitions at the starting positions
+        t_sp = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            starts_sp = codec.partition(d, tau=args.tau, start_positions=True)
+            t_sp.append(time.perf_counter() - t0)
+        blob_sp = codec.encode(d, starts=starts_sp)
         lens = np.diff(starts.astype(np.int64))
         per[name] = {"partitions": m, "mean_len": round(float(lens.mean()), 1),
                      "max_len": int(lens.max()), "blob_bytes": nbytes,
@@ -458,7 +465,11 @@ def bench_variable(args):
                      "partition_ms": round(t_part * 1e3, 2),
                      "partition_values_per_s": round(n / t_part, 1),
                      "encode_ms": round(t_enc * 1e3, 3), "decode_all_ms": round(t_dec * 1e3, 3),
-                     "decode_hbm_frac": round((nbytes + 4 * n) / t_dec / HBM_PEAK, 4)}
+                     "decode_hbm_frac": round((nbytes + 4 * n) / t_dec / HBM_PEAK, 4),
+                     "start_positions": {"partitions": len(starts_sp) - 1,
+                                         "ratio": round(blob_sp.numel() / (4 * n), 5),
+                                         "partition_ms": round(float(np.median(t_sp)) * 1e3, 2)}}
+        del blob_sp
         log(f"{name}: {per[name]}")
         t_dec_all += t_dec
         alg_all += nbytes + 4 * n
