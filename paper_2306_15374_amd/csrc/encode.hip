@@ -344,9 +344,13 @@ __device__ __attribute__((always_inline)) inline Model fit_block(FitShared& sh, 
   return md;
 }
 
-__global__ __launch_bounds__(kEncBlock) void k_fit_block(const EncColumn* __restrict__ cols,
-                                                        uint64_t ncols, EncColumn single,
-                                                        uint64_t nparts, EncScratch scr) {
+// Five waves per SIMD (at most 96 VGPRs): the 16 values each thread holds
+// leave 114 otherwise, and the extra wave of loads in flight outweighs the
+// few spilled registers of the 128-bit-sum path (C2 encode 0.76 -> 0.71 ms
+// with k_pack below).
+__global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_fit_block(
+    const EncColumn* __restrict__ cols, uint64_t ncols, EncColumn single, uint64_t nparts,
+    EncScratch scr) {
   __shared__ FitShared sh;
   const uint64_t P = blockIdx.x;
   if (P >= nparts) return;
@@ -842,11 +846,12 @@ __device__ __attribute__((always_inline)) inline void pack_rounds(const T* src, 
 
 // One wavefront per partition (kWave, four per workgroup), or one workgroup
 // per partition whose four wavefronts take consecutive quarters of its
-// rounds (each a whole number of batches).
+// rounds (each a whole number of batches).  Five waves per SIMD, as
+// k_fit_block (95 VGPRs instead of 105, no spills).
 template <bool kWave>
-__global__ __launch_bounds__(kEncBlock) void k_pack(const EncColumn* __restrict__ cols,
-                                                   uint64_t ncols, EncColumn single,
-                                                   uint64_t nparts, EncScratch scr) {
+__global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_pack(
+    const EncColumn* __restrict__ cols, uint64_t ncols, EncColumn single, uint64_t nparts,
+    EncScratch scr) {
   __shared__ uint32_t lds[kEncWaves][kPackBatch * 128];
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t P = kWave ? uint64_t(blockIdx.x) * kEncWaves + wave : uint64_t(blockIdx.x);
