@@ -51,6 +51,12 @@ def parse():
     ap.add_argument("--cols", type=int, default=4096)
     ap.add_argument("--served-n", type=int, default=39_062_500)
     ap.add_argument("--requests", type=int, default=20_000)
+    ap.add_argument("--served-streams", type=int, default=8,
+                    help="served workload: step streams")
+    ap.add_argument("--served-min-step-mb", type=int, default=64,
+                    help="served workload: result MiB that make a step worth launching early")
+    ap.add_argument("--served-inflight", type=int, default=2048,
+                    help="served workload: admitted, unreleased requests at most")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched: skip the 4096-launch per-column comparison (for profiler runs)")
     return ap.parse_args()
@@ -283,7 +289,8 @@ def bench_served(args):
     compressed = sum(b.numel() for b in blobs)
     raw = sum(s["n"] * 8 for s in specs)
     res = [P.ResidentCol(b.data_ptr(), b.numel(), s["n"]) for s, b in zip(specs, blobs)]
-    cfg = P.ServerConfig(8 << 30, 2048, 8, 1 << 16, 1 << 20, 64 << 20, 100, 0, 256 << 20)
+    cfg = P.ServerConfig(8 << 30, args.served_inflight, args.served_streams, 1 << 16, 1 << 20,
+                         args.served_min_step_mb << 20, 100, 0, 256 << 20)
     server = P.leco_server_start(codec.ctx, res, cfg)
     lens = [s["n"] for s in specs]
 
@@ -380,7 +387,9 @@ def bench_served(args):
         "data": "synthetic (device-drawn linear-noise and lognormal-key columns)",
         "config": {"workload": f"served: {len(specs)} resident uint64 columns x {specs[0]['n']} "
                                f"values ({raw / 1e9:.1f} GB), {num} mixed requests",
-                   "out_budget_bytes": 8 << 30, "streams": 8, "max_inflight": 2048, "min_step_bytes": 64 << 20, "max_wait_us": 100},
+                   "out_budget_bytes": 8 << 30, "streams": args.served_streams,
+                   "max_inflight": args.served_inflight,
+                   "min_step_bytes": args.served_min_step_mb << 20, "max_wait_us": 100},
         "saturation_req_per_s": round(sat, 1),
         "saturation_req_per_s_host_positions": round(num / h_elapsed, 1),
         "lookups_per_s": round(lookups / elapsed, 1),
