@@ -499,6 +499,25 @@ __device__ uint64_t range_cost_wave(const uint8_t* col, uint32_t dtype, uint64_t
   return kRecordBytes + 8 + 8 * ((len * md.bits + 63) >> 6);
 }
 
+// Ranges are screened `chunk` (at most kCostChunk) at a time: the chunk's
+// lanes read their dirty flag and bounds together (one round trip), and the
+// wavefront or workgroup then sizes the chunk's ranges of its class one
+// after another.  (Walking one range per iteration made every idle launch
+// cost a chain of dependent loads per range.)  The host picks the chunk so
+// that there are at least as many chunks as resident wavefronts or
+// workgroups: few, long ranges still get one each.
+constexpr uint32_t kCostChunk = 16;
+
+// Bounds of range j0 + lane for lanes below kCostChunk; true if it needs
+// sizing by the caller's class [lo_len, hi_len] (and is within max_len).
+__device__ inline bool cost_candidate(const uint64_t* starts, uint64_t count, uint32_t span,
+                                      uint64_t max_len, const uint8_t* dirty, uint64_t j,
+                                      uint64_t lo_len, uint64_t hi_len) {
+  if (j >= count || (dirty && !dirty[j])) return false;
+  const uint64_t len = starts[j + span] - starts[j];
+  return len <= max_len && len > lo_len && len <= hi_len;
+}
+
 // out[j] = cost of v[starts[j], starts[j + span]) for j < count (only
 // where dirty[j], if dirty is given), or kNoMerge when that is longer than
 // max_len: one wavefront per range of more than kLaneRangeMax and at most
@@ -510,14 +529,21 @@ __global__ __launch_bounds__(kEncBlock) void k_costs(const uint8_t* __restrict__
                                                      uint64_t count, uint32_t span,
                                                      uint64_t max_len,
                                                      const uint8_t* __restrict__ dirty,
-                                                     uint64_t* __restrict__ out) {
+                                                     uint64_t* __restrict__ out, uint32_t chunk) {
+  const uint32_t lane = threadIdx.x & 63;
   const uint64_t waves = uint64_t(gridDim.x) * kEncWaves;
-  for (uint64_t j = uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6); j < count; j += waves) {
-    if (dirty && !dirty[j]) continue;
-    const uint64_t s = starts[j], e = starts[j + span];
-    if (e - s > max_len || e - s <= kLaneRangeMax || e - s > kWaveRangeMax) continue;
-    const uint64_t c = range_cost_wave(col, dtype, s, e);
-    if ((threadIdx.x & 63) == 0) out[j] = c;
+  for (uint64_t j0 = (uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6)) * chunk;
+       j0 < count; j0 += waves * chunk) {
+    const bool mine = lane < chunk &&
+                      cost_candidate(starts, count, span, max_len, dirty, j0 + lane,
+                                     kLaneRangeMax, kWaveRangeMax);
+    uint64_t todo = __ballot(mine);
+    while (todo) {
+      const uint64_t j = j0 + uint64_t(__ffsll(static_cast<long long>(todo)) - 1);
+      todo &= todo - 1;
+      const uint64_t c = range_cost_wave(col, dtype, starts[j], starts[j + span]);
+      if (lane == 0) out[j] = c;
+    }
   }
 }
 
@@ -528,14 +554,28 @@ __global__ __launch_bounds__(kEncBlock) void k_costs_long(const uint8_t* __restr
                                                           uint64_t count, uint32_t span,
                                                           uint64_t max_len,
                                                           const uint8_t* __restrict__ dirty,
-                                                          uint64_t* __restrict__ out) {
+                                                          uint64_t* __restrict__ out,
+                                                          uint32_t chunk) {
   __shared__ FitShared sh;
-  for (uint64_t j = blockIdx.x; j < count; j += gridDim.x) {
-    if (dirty && !dirty[j]) continue;
-    const uint64_t s = starts[j], e = starts[j + span];
-    if (e - s > max_len || e - s <= kWaveRangeMax) continue;
-    const uint64_t c = range_cost(sh, col, dtype, s, e);
-    if (threadIdx.x == 0) out[j] = c;
+  __shared__ uint64_t todo_sh;
+  for (uint64_t j0 = uint64_t(blockIdx.x) * chunk; j0 < count;
+       j0 += uint64_t(gridDim.x) * chunk) {
+    if (threadIdx.x < 64) {
+      const bool mine =
+          threadIdx.x < chunk && cost_candidate(starts, count, span, max_len, dirty,
+                                                     j0 + threadIdx.x, kWaveRangeMax, max_len);
+      const uint64_t b = __ballot(mine);
+      if (threadIdx.x == 0) todo_sh = b;
+    }
+    __syncthreads();
+    uint64_t todo = todo_sh;
+    while (todo) {
+      const uint64_t j = j0 + uint64_t(__ffsll(static_cast<long long>(todo)) - 1);
+      todo &= todo - 1;
+      const uint64_t c = range_cost(sh, col, dtype, starts[j], starts[j + span]);
+      if (threadIdx.x == 0) out[j] = c;
+    }
+    __syncthreads();  // todo_sh is rewritten by the next chunk
   }
 }
 
@@ -561,7 +601,12 @@ __global__ void k_select(const uint64_t* __restrict__ cost, const uint64_t* __re
   if (t && j > 0) t = beats(g, pair_gain(cost, pair, j - 1), j);
   if (t && j + 2 < m) t = beats(g, pair_gain(cost, pair, j + 1), j);
   take[j] = t ? 1 : 0;
-  if (t) atomicAdd(merges, 1ull);
+  // one atomic per wavefront (per pair, the single counter serialised
+  // millions of them)
+  const uint64_t b = __ballot(t);
+  const uint64_t active = __ballot(true);
+  if (b && (threadIdx.x & 63) == uint32_t(__ffsll(static_cast<long long>(active)) - 1))
+    atomicAdd(merges, static_cast<unsigned long long>(__popcll(b)));
 }
 
 // Partition k survives unless the pair (k - 1, k) merged.
@@ -771,15 +816,25 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
                        dirty, out);
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
-    const uint64_t gw = (count + leco::kEncWaves - 1) / leco::kEncWaves;
+    // chunks of ranges: at least one per resident wavefront (k_costs) or
+    // workgroup (k_costs_long), at most kCostChunk ranges each
+    auto chunk_for = [&](uint64_t units) {
+      const uint64_t c = count / units;
+      return uint32_t(c < 1 ? 1 : (c > leco::kCostChunk ? leco::kCostChunk : c));
+    };
+    const uint32_t cw = chunk_for(grid_cap * leco::kEncWaves);
+    const uint64_t chunks_w = (count + cw - 1) / cw;
+    const uint64_t gw = (chunks_w + leco::kEncWaves - 1) / leco::kEncWaves;
     hipLaunchKernelGGL(leco::k_costs, dim3(uint32_t(gw < grid_cap ? gw : grid_cap)),
                        dim3(leco::kEncBlock), 0, stream, col, w, s, count, span, prm->max_len,
-                       dirty, out);
+                       dirty, out, cw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const uint64_t gl = count < grid_cap ? count : grid_cap;
+    const uint32_t cl = chunk_for(grid_cap);
+    const uint64_t chunks_l = (count + cl - 1) / cl;
+    const uint64_t gl = chunks_l < grid_cap ? chunks_l : grid_cap;
     hipLaunchKernelGGL(leco::k_costs_long, dim3(uint32_t(gl)), dim3(leco::kEncBlock), 0, stream,
-                       col, w, s, count, span, prm->max_len, dirty, out);
+                       col, w, s, count, span, prm->max_len, dirty, out, cl);
     return hipGetLastError();
   };
   P_TRY(costs(starts, m, 1, nullptr, cost));
