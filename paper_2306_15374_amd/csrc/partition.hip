@@ -591,22 +591,34 @@ __device__ inline bool beats(int64_t gj, int64_t gk, uint64_t j) {
 }
 
 // take[j] = 1 when pair j merges this round (j < m - 1); counts the merges.
-__global__ void k_select(const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair,
-                         uint64_t m, uint8_t* __restrict__ take,
-                         unsigned long long* __restrict__ merges) {
-  const uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j + 1 >= m) return;
-  const int64_t g = pair_gain(cost, pair, j);
-  bool t = g > 0;
-  if (t && j > 0) t = beats(g, pair_gain(cost, pair, j - 1), j);
-  if (t && j + 2 < m) t = beats(g, pair_gain(cost, pair, j + 1), j);
-  take[j] = t ? 1 : 0;
-  // one atomic per wavefront (per pair, the single counter serialised
-  // millions of them)
-  const uint64_t b = __ballot(t);
-  const uint64_t active = __ballot(true);
-  if (b && (threadIdx.x & 63) == uint32_t(__ffsll(static_cast<long long>(active)) - 1))
-    atomicAdd(merges, static_cast<unsigned long long>(__popcll(b)));
+__global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ cost,
+                                                const uint64_t* __restrict__ pair, uint64_t m,
+                                                uint8_t* __restrict__ take,
+                                                unsigned long long* __restrict__ merges) {
+  // A grid-stride loop with every load of a pair's test issued at once (the
+  // neighbours' indices clamped, their result then ignored): one round trip
+  // per pair instead of six dependent ones, and far fewer workgroups to
+  // dispatch.
+  uint32_t taken = 0;
+  for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j + 1 < m;
+       j += uint64_t(gridDim.x) * blockDim.x) {
+    const bool has_left = j > 0, has_right = j + 2 < m;
+    const uint64_t jl = has_left ? j - 1 : j, jr = has_right ? j + 1 : j;
+    const uint64_t p_l = pair[jl], p_c = pair[j], p_r = pair[jr];
+    const uint64_t c_l = cost[jl], c_c = cost[j], c_n = cost[j + 1], c_r = cost[jr + 1];
+    auto gain = [](uint64_t p, uint64_t a, uint64_t b) {
+      return p == kNoMerge ? int64_t(0) : int64_t(a + b) - int64_t(p);
+    };
+    const int64_t g = gain(p_c, c_c, c_n);
+    bool t = g > 0;
+    if (t && has_left) t = beats(g, gain(p_l, c_l, c_c), j);
+    if (t && has_right) t = beats(g, gain(p_r, c_n, c_r), j);
+    take[j] = t ? 1 : 0;
+    taken += t ? 1u : 0u;
+  }
+  // one atomic per wavefront
+  for (int off = 32; off > 0; off >>= 1) taken += uint32_t(__shfl_xor(int(taken), off, 64));
+  if ((threadIdx.x & 63) == 0 && taken) atomicAdd(merges, static_cast<unsigned long long>(taken));
 }
 
 // Partition k survives unless the pair (k - 1, k) merged.
@@ -842,8 +854,9 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   for (uint64_t round = 0; prm->max_rounds == 0 || round < prm->max_rounds; ++round) {
     if (m < 2) break;
     P_TRY(hipMemsetAsync(merges, 0, 8, stream));
-    hipLaunchKernelGGL(leco::k_select, dim3(uint32_t((m - 1 + 255) / 256)), dim3(256), 0, stream,
-                       cost, pair, m, take, merges);
+    const uint64_t gsel = (m - 1 + 255) / 256;
+    hipLaunchKernelGGL(leco::k_select, dim3(uint32_t(gsel < grid_cap ? gsel : grid_cap)),
+                       dim3(256), 0, stream, cost, pair, m, take, merges);
     P_TRY(hipGetLastError());
     unsigned long long merged = 0;
     P_TRY(hipMemcpyAsync(&merged, merges, 8, hipMemcpyDeviceToHost, stream));
