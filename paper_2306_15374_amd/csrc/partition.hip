@@ -69,6 +69,31 @@ __device__ inline uint32_t key_span_bits(const DKey& mn, const DKey& mx) {
   return hi ? 65u : bitlen64(lo);
 }
 
+// For 32-bit columns a first difference fits 33 bits: the key d + 2^32 is
+// one 64-bit word (two 32-bit shuffles instead of three).
+__device__ inline bool key_less(uint64_t a, uint64_t b) { return a < b; }
+__device__ inline uint64_t key_shfl_up(uint64_t k, int delta) {
+  return uint64_t(__shfl_up(static_cast<unsigned long long>(k), delta, 64));
+}
+__device__ inline uint64_t key_readlane(uint64_t k, int lane) {
+  return uint64_t(__shfl(static_cast<unsigned long long>(k), lane, 64));
+}
+__device__ inline uint32_t key_span_bits(uint64_t mn, uint64_t mx) { return bitlen64(mx - mn); }
+
+// Key of the first difference v_j - v_{j-1}, and the state's stored form.
+__device__ inline DKey make_key(DKey*, uint64_t vj, uint64_t vp) {
+  return DKey{vj >= vp ? 1u : 0u, vj - vp};
+}
+__device__ inline uint64_t make_key(uint64_t*, uint64_t vj, uint64_t vp) {
+  return vj - vp + (uint64_t(1) << 32);  // v < 2^32
+}
+__device__ inline DKey key_from(DKey*, uint32_t hi, uint64_t lo) { return DKey{hi, lo}; }
+__device__ inline uint64_t key_from(uint64_t*, uint32_t, uint64_t lo) { return lo; }
+__device__ inline uint32_t key_hi(const DKey& k) { return k.hi; }
+__device__ inline uint32_t key_hi(uint64_t) { return 0; }
+__device__ inline uint64_t key_lo(const DKey& k) { return k.lo; }
+__device__ inline uint64_t key_lo(uint64_t k) { return k; }
+
 __device__ inline void mark(unsigned long long* bitmap, uint64_t j) {
   atomicOr(bitmap + (j >> 6), 1ull << (j & 63));
 }
@@ -113,13 +138,16 @@ __device__ inline bool bit_set(unsigned long long* bitmap, uint64_t j) {
 //
 // forced (or null): bit j set means a partition begins at j (the first
 // value of a starting partition), whatever the cost.
-template <bool kFix>
+//
+// K: the key type, DKey for 64-bit columns, one 64-bit word for 32-bit ones.
+template <bool kFix, class K>
 __device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t p,
                             uint64_t b, double thr, uint64_t max_len, SplitState& st,
                             uint64_t* win, unsigned long long* __restrict__ bitmap,
                             const uint64_t* __restrict__ forced) {
   const uint32_t lane = threadIdx.x & 63;
-  DKey kmin{st.kmin_hi, st.kmin_lo}, kmax{st.kmax_hi, st.kmax_lo};
+  K kmin = key_from(static_cast<K*>(nullptr), st.kmin_hi, st.kmin_lo);
+  K kmax = key_from(static_cast<K*>(nullptr), st.kmax_hi, st.kmax_lo);
   uint64_t i = st.i;
   bool have = st.have != 0;
   uint32_t w_old = st.w_old;
@@ -137,18 +165,14 @@ __device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uin
     }
     const uint64_t j = p + lane;
     const bool valid = j < b;
-    DKey d{0, 0};
-    if (valid) {
-      const uint64_t vj = win[j - base + 1], vp = win[j - base];
-      d.lo = vj - vp;
-      d.hi = vj >= vp ? 1u : 0u;
-    }
+    K d = make_key(static_cast<K*>(nullptr), 0, 0);
+    if (valid) d = make_key(static_cast<K*>(nullptr), win[j - base + 1], win[j - base]);
     // inclusive prefix min / max over the lanes up to this one; the invalid
     // lanes are the last ones and never feed a valid lane
-    DKey mn = d, mx = d;
+    K mn = d, mx = d;
 #pragma unroll
     for (int delta = 1; delta < 64; delta <<= 1) {
-      const DKey lo = key_shfl_up(mn, delta), hi = key_shfl_up(mx, delta);
+      const K lo = key_shfl_up(mn, delta), hi = key_shfl_up(mx, delta);
       if (int(lane) >= delta) {
         if (key_less(lo, mn)) mn = lo;
         if (key_less(mx, hi)) mx = hi;
@@ -196,10 +220,10 @@ __device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uin
   }
   st.i = i;
   st.have = have ? 1u : 0u;
-  st.kmin_hi = kmin.hi;
-  st.kmin_lo = kmin.lo;
-  st.kmax_hi = kmax.hi;
-  st.kmax_lo = kmax.lo;
+  st.kmin_hi = key_hi(kmin);
+  st.kmin_lo = key_lo(kmin);
+  st.kmax_hi = key_hi(kmax);
+  st.kmax_lo = key_lo(kmax);
   st.w_old = w_old;
   return synced;
 }
@@ -220,7 +244,10 @@ __global__ __launch_bounds__(64) void k_split_spec(const uint8_t* __restrict__ c
   const uint64_t b = n - a < (uint64_t(1) << kSubLog2) ? n : a + (uint64_t(1) << kSubLog2);
   if (threadIdx.x == 0) mark(bitmap, a);
   SplitState st{a, 0, 0, 0, 0, 0, 0};
-  greedy_walk<false>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap, forced);
+  if (dtype == 4)
+    greedy_walk<false, uint64_t>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap, forced);
+  else
+    greedy_walk<false, DKey>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap, forced);
   if (threadIdx.x == 0) states[blockIdx.x] = st;
 }
 
@@ -244,7 +271,9 @@ __global__ __launch_bounds__(64) void k_split_fix(const uint8_t* __restrict__ co
     if (aq >= n) break;
     const uint64_t bq = n - aq < (uint64_t(1) << kSubLog2) ? n : aq + (uint64_t(1) << kSubLog2);
     const bool synced =
-        greedy_walk<true>(col, dtype, aq, bq, thr, max_len, st, win, bitmap, forced);
+        dtype == 4
+            ? greedy_walk<true, uint64_t>(col, dtype, aq, bq, thr, max_len, st, win, bitmap, forced)
+            : greedy_walk<true, DKey>(col, dtype, aq, bq, thr, max_len, st, win, bitmap, forced);
     if (synced) st = states[q0 + q];  // the speculative run's end state is the true one
   }
 }
