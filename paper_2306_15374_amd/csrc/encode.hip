@@ -605,7 +605,7 @@ __device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, c
   const int64_t N = n, a = N - 1;
   const int64_t k3 = 12 * N * N - 30 * N + 22, e2 = a * (N - 2), e3 = a * (N - 2) * (N - 3);
   uint64_t y[kEncRegs];
-  __int128 s1 = 0, s2 = 0, s3 = 0, q1 = 0, q2 = 0, q3 = 0;
+  __int128 s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
   for (int k = 0; k < kEncRegs; ++k) y[k] = load_clamped(src, tid + k * kEncBlock, len) - md.vmin;
 #pragma unroll
@@ -619,15 +619,30 @@ __device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, c
       s1 += yy * g1;
       s2 += yy * g2;
       s3 += yy * g3;
-      q1 += __int128(g1) * g1;
-      q2 += __int128(g2) * g2;
-      q3 += __int128(g3) * g3;
     }
   }
-  __int128 S2, Q1, Q3;
+  __int128 S2, unused;
   const __int128 S1 = block_sum_i128(fs, s1, s2, S2);
-  const __int128 S3 = block_sum_i128(fs, s3, q1, Q1);
-  const __int128 Q2 = block_sum_i128(fs, q2, q3, Q3);
+  const __int128 S3 = block_sum_i128(fs, s3, 0, unused);
+  // The norms sum g_k(t)^2 over t < n have closed forms (the Gram
+  // polynomials' squared norms, exact integers): (n-1)n(n+1)/3,
+  // (n-2)...(n+2)/5 and (n-3)...(n+3)/7, below 2^84 for n <= 4096.  Each is
+  // a run of 3, 5 or 7 consecutive integers, one of which the divisor
+  // divides: that factor is divided first, so no 128-bit division is needed.
+  auto norm = [](int64_t nv, int64_t half, int64_t d) {
+    __int128 q = 1;
+    bool divided = false;
+    for (int64_t f = nv - half; f <= nv + half; ++f) {
+      int64_t x = f;
+      if (!divided && x % d == 0) {
+        x /= d;
+        divided = true;
+      }
+      q *= x;
+    }
+    return q;
+  };
+  const __int128 Q1 = norm(N, 1, 3), Q2 = norm(N, 2, 5), Q3 = norm(N, 3, 7);
   double c[3];
   const __int128 S[3] = {S1, S2, S3}, Q[3] = {Q1, Q2, Q3};
 #pragma unroll
