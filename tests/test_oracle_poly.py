@@ -187,3 +187,22 @@ def test_round_trip_and_size(ref):
         ls = ref.encode(col, fixed_len=L)
         m = -(-len(col) // L)
         assert len(blob) <= len(ls) + 16 * m + 16
+
+
+def test_gram_norms_have_closed_forms():
+    """The squared norms of the Gram polynomials over t = 0..n-1 (summed
+    exactly here) equal the closed forms the GPU fit uses instead of
+    summing: (n-1)n(n+1)/3, (n-2)...(n+2)/5, (n-3)...(n+3)/7."""
+    for n in list(range(3, 130)) + [1000, 4095, 4096]:
+        a = n - 1
+        q = [0, 0, 0]
+        for t in range(n):
+            g1 = 2 * t - a
+            g2 = 6 * t * t - 6 * a * t + a * (n - 2)
+            g3 = 20 * t ** 3 - 30 * a * t * t + (12 * n * n - 30 * n + 22) * t - a * (n - 2) * (n - 3)
+            q[0] += g1 * g1
+            q[1] += g2 * g2
+            q[2] += g3 * g3
+        assert q == [(n - 1) * n * (n + 1) // 3,
+                     (n - 2) * (n - 1) * n * (n + 1) * (n + 2) // 5,
+                     (n - 3) * (n - 2) * (n - 1) * n * (n + 1) * (n + 2) * (n + 3) // 7], n
