@@ -590,9 +590,9 @@ __device__ inline double i128_to_double(__int128 x) {
 
 // The least-squares model of fit_block, then (for 3 <= len <= 4096 values
 // of range below 2^50) the degree-2 and degree-3 least-squares polynomials
-// in the Gram basis: c_k = fl(S_k) / fl(Q_k), S_k = sum y_t g_k(t),
-// Q_k = sum g_k(t)^2 exactly in int128 (|y g3| < 2^87, 4096 terms), stored
-// when strictly narrower than every simpler model.
+// in the Gram basis: c_k = fl(S_k) / fl(Q_k), S_k = sum y_t g_k(t) exactly
+// in int128 (|y g3| < 2^87, 4096 terms), Q_k = sum g_k(t)^2 from its closed
+// form, stored when strictly narrower than every simpler model.
 template <class T>
 __device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, const T* src, uint64_t len, bool force_constant,
                                  uint32_t& kind, double& c2_out, double& c3_out) {
