@@ -497,10 +497,64 @@ __global__ __launch_bounds__(kEncBlock) void k_costs_short(const uint8_t* __rest
 // range_cost computed by one wavefront alone (no workgroup barrier), the
 // same arithmetic in the same order of operations where it matters: the
 // sums are exact and the slope is one function of them.
+//
+// Ranges of at most 64 kCostRegs values are held in registers: every load
+// is issued before any is used and the residual pass reads the registers
+// (a loop of dependent loads per pass made the wavefront wait once per 64
+// values, twice).  The sums are exact, so their order does not matter.
+constexpr int kCostRegs = 8;
+
+template <class T>
+__device__ uint64_t range_cost_wave_regs(const T* src, uint64_t len) {
+  const uint32_t lane = threadIdx.x & 63;
+  const auto g = global_ptr(src);
+  uint64_t x[kCostRegs];
+#pragma unroll
+  for (int k = 0; k < kCostRegs; ++k) {
+    const uint32_t t = lane + 64u * k;
+    x[k] = uint64_t(g[t < len ? t : len - 1]);
+  }
+  uint64_t vmin = ~uint64_t(0), vmax = 0;
+  U128 sv{0, 0}, stv{0, 0};
+#pragma unroll
+  for (int k = 0; k < kCostRegs; ++k) {
+    const uint32_t t = lane + 64u * k;
+    if (t < len) {
+      vmin = x[k] < vmin ? x[k] : vmin;
+      vmax = x[k] > vmax ? x[k] : vmax;
+      sv = add128(sv, U128{x[k], 0});
+      stv = add128(stv, mul64x64(t, x[k]));
+    }
+  }
+  wave_minmax_u64(vmin, vmax);
+  const uint64_t range = vmax - vmin;
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
+  if (len > 1 && range < (uint64_t(1) << 61)) {
+    wave_sum_u128x2(sv, stv);
+    const double th = ls_slope(len, sv, stv);
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+#pragma unroll
+    for (int k = 0; k < kCostRegs; ++k) {
+      const uint32_t t = lane + 64u * k;
+      if (t < len) {
+        const int64_t rr = int64_t(x[k] - vmin) - predict(th, t);
+        rmin = rr < rmin ? rr : rmin;
+        rmax = rr > rmax ? rr : rmax;
+      }
+    }
+    wave_minmax_i64(rmin, rmax);
+    choose_model(md, th, rmin, rmax);
+  }
+  return kRecordBytes + 8 + 8 * ((len * md.bits + 63) >> 6);
+}
+
 __device__ uint64_t range_cost_wave(const uint8_t* col, uint32_t dtype, uint64_t s, uint64_t e) {
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t len = e - s;
   const uint8_t* src = col + s * dtype;
+  if (len <= 64u * kCostRegs)
+    return dtype == 8 ? range_cost_wave_regs(reinterpret_cast<const uint64_t*>(src), len)
+                      : range_cost_wave_regs(reinterpret_cast<const uint32_t*>(src), len);
   uint64_t vmin = ~uint64_t(0), vmax = 0;
   U128 sv{0, 0}, stv{0, 0};
   for (uint64_t t = lane; t < len; t += 64) {
@@ -535,16 +589,18 @@ __device__ uint64_t range_cost_wave(const uint8_t* col, uint32_t dtype, uint64_t
 // cost a chain of dependent loads per range.)  The host picks the chunk so
 // that there are at least as many chunks as resident wavefronts or
 // workgroups: few, long ranges still get one each.
-constexpr uint32_t kCostChunk = 16;
+constexpr uint32_t kCostChunk = 64;
 
 // Bounds of range j0 + lane for lanes below kCostChunk; true if it needs
 // sizing by the caller's class [lo_len, hi_len] (and is within max_len).
 __device__ inline bool cost_candidate(const uint64_t* starts, uint64_t count, uint32_t span,
                                       uint64_t max_len, const uint8_t* dirty, uint64_t j,
                                       uint64_t lo_len, uint64_t hi_len) {
-  if (j >= count || (dirty && !dirty[j])) return false;
+  if (j >= count) return false;
+  // the flag and both bounds in one round trip
+  const bool d = !dirty || dirty[j];
   const uint64_t len = starts[j + span] - starts[j];
-  return len <= max_len && len > lo_len && len <= hi_len;
+  return d && len <= max_len && len > lo_len && len <= hi_len;
 }
 
 // out[j] = cost of v[starts[j], starts[j + span]) for j < count (only
