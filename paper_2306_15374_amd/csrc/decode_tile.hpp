@@ -1,13 +1,15 @@
 // The LeCo decoder's inner loop (section 3.3, range decompression), built
 // around wavefront tiles: each 64-lane wavefront decodes the values of
-// global positions [g0, g1) (1024 of them by default) on its own, with its
-// own slice of LDS and no workgroup barrier.  The tile is cut at partition
-// boundaries into segments; the residual words of all its segments (which
-// lie back to back in the blob) are copied once into the wavefront's LDS
-// slice with coalesced 16-byte loads, then each lane decodes values
-// t = c0 + lane, c0 + lane + 64, ... so that every store of the wavefront
-// covers 64 consecutive outputs.  Tiles whose words do not fit the slice
-// are decoded segment by segment in chunks.
+// global positions [g0, g1) (up to 4096 of them, as many as the blob's bits
+// per value let its words fit the slice) on its own, with its own slice of
+// LDS and no workgroup barrier.  The tile is cut at partition boundaries
+// into segments; the residual words of all its segments (which lie back to
+// back in the blob) are copied once into the wavefront's LDS slice with
+// coalesced 16-byte loads, then each lane decodes values t = c0 + lane,
+// c0 + lane + 64, ... so that every store of the wavefront covers 64
+// consecutive outputs; runs of short partitions are decoded in full
+// 64-value rounds across their boundaries.  Tiles whose words do not fit
+// the slice are decoded segment by segment in chunks.
 #pragma once
 
 #include "leco_dev.hpp"

@@ -12,7 +12,9 @@
 // until the true run starts a partition where the speculative run did
 // (from there on the two runs are the same), rewriting the starts it
 // passes.  The wavefront walks 64 candidates at a time (see greedy_walk).
-// This reproduces the sequential greedy exactly.
+// This reproduces the sequential greedy exactly.  Optionally a partition
+// also begins at every starting position (section 3.2.2, selecting good
+// starting positions), marked in a bitmap before the split.
 //
 // Merge: rounds over adjacent pairs.  Every pair's union is sized with the
 // encoder's own fit (exact bytes: 32-byte record, 8-byte start, residual
