@@ -574,56 +574,54 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_minimax_wave(const EncColumn*
 
 // ---- fit with the polynomial regressor: one workgroup per partition ---------------
 
-// Exact workgroup sum of a two's-complement 128-bit value per thread (the
-// true sum fits, so sums modulo 2^128 are exact).
-__device__ inline __int128 block_sum_i128(FitShared& fs, __int128 a, __int128 b, __int128& bsum) {
-  U128 x{uint64_t(a), uint64_t(static_cast<unsigned __int128>(a) >> 64)};
-  U128 y{uint64_t(b), uint64_t(static_cast<unsigned __int128>(b) >> 64)};
-  block_sum_u128x2(fs, x, y);
-  bsum = static_cast<__int128>((static_cast<unsigned __int128>(y.hi) << 64) | y.lo);
-  return static_cast<__int128>((static_cast<unsigned __int128>(x.hi) << 64) | x.lo);
-}
-
 __device__ inline double i128_to_double(__int128 x) {
   return i128_to_f64(U128{uint64_t(x), uint64_t(static_cast<unsigned __int128>(x) >> 64)});
 }
 
-// The least-squares model of fit_block, then (for 3 <= len <= 4096 values
-// of range below 2^50) the degree-2 and degree-3 least-squares polynomials
-// in the Gram basis: c_k = fl(S_k) / fl(Q_k), S_k = sum y_t g_k(t) exactly
-// in int128 (|y g3| < 2^87, 4096 terms), Q_k = sum g_k(t)^2 from its closed
-// form, stored when strictly narrower than every simpler model.
-template <class T>
-__device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, const T* src, uint64_t len, bool force_constant,
-                                 uint32_t& kind, double& c2_out, double& c3_out) {
-  Model md = fit_block(fs, src, len, force_constant);
-  kind = 0;
-  c2_out = c3_out = 0.0;
-  if (force_constant || len < 3 || len > kPolyMaxLen || md.range >= kPolyMaxRange) return md;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t n = uint32_t(len);
+// The degree-2 and degree-3 least-squares polynomials of a partition of
+// 3 <= n <= 4096 values of range below 2^50, in the Gram basis:
+// c_k = fl(S_k) / fl(Q_k), S_k = sum y_t g_k(t) exact in int128 and
+// Q_k = sum g_k(t)^2 from its closed form; md takes the narrower of them when
+// strictly narrower than every simpler model.  Each of the group's kT
+// threads holds kR <= 16 offsets y = v - vmin, at positions t = u + kT k
+// (u = tid, k < kR); sum4 and minmax reduce over the group.
+//
+// S_k comes from the moments M_j = sum_t y_t t^j, j <= 3, by the
+// coefficients of g_k:
+//   S1 = 2 M1 - a M0,  S2 = 6 M2 - 6a M1 + e2 M0,
+//   S3 = 20 M3 - 30a M2 + k3 M1 - e3 M0        (a = n - 1).
+// A thread's share of M_j expands (u + kT k)^j binomially over its sums
+// T_i = sum_k y_k k^i, so the loop over values multiplies only by the
+// constants k^i; T_3 <= 2^50 (0^3 + ... + 15^3) < 2^64, so every T_i fits
+// 64 bits.  The group totals stay below 2^103 in magnitude.
+template <int kT, int kR, class Sum4, class MinMax>
+__device__ __attribute__((always_inline)) inline void poly_stage(
+    Model& md, const uint64_t (&y)[kR], uint32_t tid, uint32_t n, const Sum4& sum4,
+    const MinMax& minmax, uint32_t& kind, double& c2_out, double& c3_out) {
+  static_assert(kR <= 16, "per-thread moment sums must fit 64 bits");
+  uint64_t T0 = 0, T1 = 0, T2 = 0, T3 = 0;
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    const uint64_t yk = tid + uint32_t(k * kT) < n ? y[k] : 0;
+    T0 += yk;
+    T1 += yk * uint64_t(k);
+    T2 += yk * uint64_t(k * k);
+    T3 += yk * uint64_t(k * k * k);
+  }
+  using u128 = unsigned __int128;
+  const uint64_t u = tid, S = kT;
+  u128 M0 = T0;
+  u128 M1 = u128(T0) * u + u128(T1) * S;
+  u128 M2 = u128(T0) * (u * u) + u128(T1) * (2 * u * S) + u128(T2) * (S * S);
+  u128 M3 = u128(T0) * (u * u * u) + u128(T1) * (3 * u * u * S) + u128(T2) * (3 * u * S * S) +
+            u128(T3) * (S * S * S);
+  sum4(M0, M1, M2, M3);
   const int64_t N = n, a = N - 1;
   const int64_t k3 = 12 * N * N - 30 * N + 22, e2 = a * (N - 2), e3 = a * (N - 2) * (N - 3);
-  uint64_t y[kEncRegs];
-  __int128 s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll
-  for (int k = 0; k < kEncRegs; ++k) y[k] = load_clamped(src, tid + k * kEncBlock, len) - md.vmin;
-#pragma unroll
-  for (int k = 0; k < kEncRegs; ++k) {
-    const int64_t x = tid + k * kEncBlock;
-    if (x < N) {
-      const int64_t g1 = 2 * x - a;
-      const int64_t g2 = 6 * x * x - 6 * a * x + e2;
-      const int64_t g3 = 20 * x * x * x - 30 * a * x * x + k3 * x - e3;
-      const __int128 yy = __int128(y[k]);
-      s1 += yy * g1;
-      s2 += yy * g2;
-      s3 += yy * g3;
-    }
-  }
-  __int128 S2, unused;
-  const __int128 S1 = block_sum_i128(fs, s1, s2, S2);
-  const __int128 S3 = block_sum_i128(fs, s3, 0, unused);
+  const __int128 m0 = __int128(M0), m1 = __int128(M1), m2 = __int128(M2), m3 = __int128(M3);
+  const __int128 S1 = 2 * m1 - a * m0;
+  const __int128 S2 = 6 * m2 - 6 * a * m1 + e2 * m0;
+  const __int128 S3 = 20 * m3 - 30 * a * m2 + k3 * m1 - e3 * m0;
   // The norms sum g_k(t)^2 over t < n have closed forms (the Gram
   // polynomials' squared norms, exact integers): (n-1)n(n+1)/3,
   // (n-2)...(n+2)/5 and (n-3)...(n+3)/7, below 2^84 for n <= 4096.  Each is
@@ -644,26 +642,32 @@ __device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, c
   };
   const __int128 Q1 = norm(N, 1, 3), Q2 = norm(N, 2, 5), Q3 = norm(N, 3, 7);
   double c[3];
-  const __int128 S[3] = {S1, S2, S3}, Q[3] = {Q1, Q2, Q3};
+  const __int128 Sk[3] = {S1, S2, S3}, Q[3] = {Q1, Q2, Q3};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    c[k] = Q[k] != 0 ? i128_to_double(S[k]) / i128_to_double(Q[k]) : 0.0;
+    c[k] = Q[k] != 0 ? i128_to_double(Sk[k]) / i128_to_double(Q[k]) : 0.0;
     if (c[k] == 0.0) c[k] = 0.0;  // +0.0, never -0.0
   }
-  for (int deg = 2; deg <= 3; ++deg) {
-    if (deg == 3 && len < 4) break;
-    const double c3 = deg == 3 ? c[2] : 0.0;
-    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+  // the residuals of both degrees in one pass (the degree-2 prediction is
+  // the degree-3 one with c3 = 0: the two share their Gram values)
+  int64_t mn2 = INT64_MAX, mx2 = INT64_MIN, mn3 = INT64_MAX, mx3 = INT64_MIN;
 #pragma unroll
-    for (int k = 0; k < kEncRegs; ++k) {
-      const uint32_t t = tid + k * kEncBlock;
-      if (t < n) {
-        const int64_t rr = int64_t(y[k]) - poly_predict(c[0], c[1], c3, t, n);
-        rmin = rr < rmin ? rr : rmin;
-        rmax = rr > rmax ? rr : rmax;
-      }
+  for (int k = 0; k < kR; ++k) {
+    const uint32_t t = tid + k * kT;
+    if (t < n) {
+      const int64_t r2 = int64_t(y[k]) - poly_predict(c[0], c[1], 0.0, t, n);
+      const int64_t r3 = int64_t(y[k]) - poly_predict(c[0], c[1], c[2], t, n);
+      mn2 = r2 < mn2 ? r2 : mn2;
+      mx2 = r2 > mx2 ? r2 : mx2;
+      mn3 = r3 < mn3 ? r3 : mn3;
+      mx3 = r3 > mx3 ? r3 : mx3;
     }
-    block_minmax_i64(fs, rmin, rmax);
+  }
+  minmax(mn2, mx2);
+  minmax(mn3, mx3);
+  for (int deg = 2; deg <= 3; ++deg) {
+    if (deg == 3 && n < 4) break;
+    const int64_t rmin = deg == 2 ? mn2 : mn3, rmax = deg == 2 ? mx2 : mx3;
     const uint32_t b = bitlen64(uint64_t(rmax) - uint64_t(rmin));
     if (b < md.bits) {
       md.linear = true;
@@ -673,10 +677,80 @@ __device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, c
       md.rmin = rmin;
       kind = 1;
       c2_out = c[1];
-      c3_out = c3;
+      c3_out = deg == 3 ? c[2] : 0.0;
     }
   }
+}
+
+__device__ inline U128 to_u128(unsigned __int128 x) { return U128{uint64_t(x), uint64_t(x >> 64)}; }
+__device__ inline unsigned __int128 from_u128(U128 x) {
+  return (static_cast<unsigned __int128>(x.hi) << 64) | x.lo;
+}
+
+// The least-squares model of fit_block, then the polynomial stage, by the
+// whole workgroup.
+template <class T>
+__device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, const T* src, uint64_t len, bool force_constant,
+                                 uint32_t& kind, double& c2_out, double& c3_out) {
+  Model md = fit_block(fs, src, len, force_constant);
+  kind = 0;
+  c2_out = c3_out = 0.0;
+  if (force_constant || len < 3 || len > kPolyMaxLen || md.range >= kPolyMaxRange) return md;
+  const uint32_t tid = threadIdx.x;
+  uint64_t y[kEncRegs];
+#pragma unroll
+  for (int k = 0; k < kEncRegs; ++k) y[k] = load_clamped(src, tid + k * kEncBlock, len) - md.vmin;
+  const auto sum4 = [&](unsigned __int128& m0, unsigned __int128& m1, unsigned __int128& m2,
+                        unsigned __int128& m3) {
+    U128 x = to_u128(m0), w = to_u128(m1);
+    block_sum_u128x2(fs, x, w);
+    m0 = from_u128(x);
+    m1 = from_u128(w);
+    x = to_u128(m2);
+    w = to_u128(m3);
+    block_sum_u128x2(fs, x, w);
+    m2 = from_u128(x);
+    m3 = from_u128(w);
+  };
+  const auto minmax = [&](int64_t& mn, int64_t& mx) { block_minmax_i64(fs, mn, mx); };
+  poly_stage<kEncBlock, kEncRegs>(md, y, tid, uint32_t(len), sum4, minmax, kind, c2_out, c3_out);
   return md;
+}
+
+// The same by one wavefront, for partitions of at most kWaveEncMax values:
+// the model of fit_wave, then the polynomial stage with wavefront
+// reductions (no barrier).
+template <class T>
+__device__ __attribute__((always_inline)) inline Model fit_poly_wave(const T* src, uint64_t len, bool force_constant,
+                                      uint32_t& kind, double& c2_out, double& c3_out) {
+  Model md = fit_wave(src, len, force_constant);
+  kind = 0;
+  c2_out = c3_out = 0.0;
+  if (force_constant || len < 3 || md.range >= kPolyMaxRange) return md;
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t y[kWaveRegs];
+#pragma unroll
+  for (int k = 0; k < kWaveRegs; ++k) y[k] = load_clamped(src, lane + 64 * k, len) - md.vmin;
+  const auto sum4 = [](unsigned __int128& m0, unsigned __int128& m1, unsigned __int128& m2,
+                       unsigned __int128& m3) {
+    U128 x = to_u128(m0), w = to_u128(m1), z = to_u128(m2), q = to_u128(m3);
+    wave_sum_u128x2(x, w);
+    wave_sum_u128x2(z, q);
+    m0 = from_u128(x);
+    m1 = from_u128(w);
+    m2 = from_u128(z);
+    m3 = from_u128(q);
+  };
+  const auto minmax = [](int64_t& mn, int64_t& mx) { wave_minmax_i64(mn, mx); };
+  poly_stage<64, kWaveRegs>(md, y, lane, uint32_t(len), sum4, minmax, kind, c2_out, c3_out);
+  return md;
+}
+
+__device__ inline void store_poly(const EncScratch& s, uint64_t P, uint32_t kind, double c2,
+                                  double c3) {
+  s.kind[P] = kind;
+  s.c2[P] = uint64_t(__double_as_longlong(c2));
+  s.c3[P] = uint64_t(__double_as_longlong(c3));
 }
 
 __global__ __launch_bounds__(kEncBlock) void k_fit_poly(const EncColumn* __restrict__ cols,
@@ -699,9 +773,37 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_poly(const EncColumn* __restr
                      kind, c2, c3);
   if (threadIdx.x == 0) {
     store_model(scr, P, md, len);
-    scr.kind[P] = kind;
-    scr.c2[P] = uint64_t(__double_as_longlong(c2));
-    scr.c3[P] = uint64_t(__double_as_longlong(c3));
+    store_poly(scr, P, kind, c2, c3);
+  }
+}
+
+__global__ __launch_bounds__(kEncBlock) void k_fit_poly_wave(const EncColumn* __restrict__ cols,
+                                                            uint64_t ncols, EncColumn single,
+                                                            uint64_t nparts, EncScratch scr,
+                                                            int* err) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t P =
+      uint64_t(blockIdx.x) * kEncWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (P >= nparts) return;
+  const EncColumn c = column_of(cols, ncols, single, P);
+  if (c.regressor != 2) return;  // the other fit kernels
+  uint64_t start, len;
+  part_bounds(c, P - c.part_base, start, len);
+  if (len > kWaveEncMax) {  // the host sends such partitions to k_fit_poly
+    if (lane == 0) raise(err, kErrDevice);
+    return;
+  }
+  uint32_t kind;
+  double c2, c3;
+  const Model md =
+      c.dtype == 8
+          ? fit_poly_wave(reinterpret_cast<const uint64_t*>(c.col) + start, len, c.force_constant,
+                          kind, c2, c3)
+          : fit_poly_wave(reinterpret_cast<const uint32_t*>(c.col) + start, len, c.force_constant,
+                          kind, c2, c3);
+  if (lane == 0) {
+    store_model(scr, P, md, len);
+    store_poly(scr, P, kind, c2, c3);
   }
 }
 
@@ -948,12 +1050,17 @@ hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t
                               uint32_t regs, const EncScratch& scr, hipStream_t stream) {
   if (nparts == 0) return hipSuccess;
   // each fit kernel fits the columns of its regressors and skips the others
-  if (regs & kRegPoly)
+  const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
+  const bool short_parts = max_len <= kWaveEncMax && ctx->tune.encode_wave;
+  if ((regs & kRegPoly) && short_parts)
+    hipLaunchKernelGGL(k_fit_poly_wave, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream, cols_dev,
+                       ncols, single, nparts, scr, ctx->err_dev);
+  else if (regs & kRegPoly)
     hipLaunchKernelGGL(k_fit_poly, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr);
   if (!(regs & (kRegLS | kRegMinimax))) return hipGetLastError();
-  const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave && !(regs & kRegPoly);
-  const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
+  // k_fit_wave fits every column it is given: not with polynomial columns
+  const bool wave = short_parts && !(regs & kRegPoly);
   if ((regs & kRegMinimax) && wave)
     hipLaunchKernelGGL(k_fit_minimax_wave, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr, ctx->err_dev);

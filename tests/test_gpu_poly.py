@@ -75,6 +75,16 @@ def wide(n, seed):
     return np.random.default_rng(seed).integers(0, 1 << 52, n, dtype=np.uint64)
 
 
+def big_cubic(n, seed, L):
+    """Cubic pieces of amplitude near 2^49.6 over an offset of 2^62, plus
+    small noise: ranges just below the 2^50 limit of the polynomial fit, so
+    its integer sums take their largest magnitudes."""
+    rng = np.random.default_rng(seed)
+    t = (np.arange(n) % L) / L
+    v = np.floor((2.0 ** 49) * (t ** 3 + 0.5 * t)).astype(np.uint64)
+    return v + rng.integers(0, 1000, n, dtype=np.uint64) + np.uint64(1 << 62)
+
+
 FIXED = [
     ("cosmos_u32", lambda: W.cosmos(300_000, 1), 1000),
     ("cosmos_4096", lambda: W.cosmos(100_000, 2), 4096),
@@ -85,6 +95,8 @@ FIXED = [
     ("constant_runs", lambda: W.constant_runs(100_000, 7), 512),
     ("longer_than_4096", lambda: W.cosmos(60_000, 8), 5000),
     ("range_2_50", lambda: wide(30_000, 9), 1000),
+    ("range_below_2_50_wave", lambda: big_cubic(50_000, 16, 1000), 1000),
+    ("range_below_2_50_block", lambda: big_cubic(50_000, 17, 4096), 4096),
     ("tiny_3", lambda: W.cosmos(5_000, 10), 3),
     ("tiny_4", lambda: W.cosmos(5_001, 11), 4),
     ("pairs", lambda: W.cosmos(4_001, 12), 2),
