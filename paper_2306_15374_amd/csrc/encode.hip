@@ -12,9 +12,10 @@
 //   pack   every partition's residuals, recomputed from its stored model,
 //          are bit-packed into its word span (section 3.3 storage format).
 //
-// Partitions of at most kWaveEncodeMax values go one per wavefront (values
-// in registers, shuffle reductions, no workgroup barrier); longer ones get
-// a whole workgroup.  Works on a table of columns, so one sequence of
+// The fits take one wavefront per partition when every partition holds at
+// most kWaveEncodeMax values (16 per lane) or twice that (32 per lane; not
+// the minimax fit): values in registers, shuffle reductions, no workgroup
+// barrier.  Longer partitions get a whole workgroup.  Works on a table of columns, so one sequence of
 // launches encodes one column or thousands.  The column is read twice; in
 // exchange no partition waits on another.
 //
@@ -171,17 +172,17 @@ __device__ inline uint64_t load_clamped(const T* src, uint32_t t, uint64_t len) 
   return uint64_t(global_ptr(src)[t < len ? t : uint32_t(len - 1)]);
 }
 
-// The model of a partition of len <= kWaveEncMax values, by one wavefront.
-template <class T>
+// The model of a partition of len <= 64 kR values, by one wavefront.
+template <int kR, class T>
 __device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, uint64_t len, bool force_constant) {
   const uint32_t lane = threadIdx.x & 63;
-  uint64_t v[kWaveRegs];
+  uint64_t v[kR];
 #pragma unroll
-  for (int k = 0; k < kWaveRegs; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
+  for (int k = 0; k < kR; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
   // clamped lanes hold the last value, which leaves min and max unchanged
   uint64_t vmin = v[0], vmax = v[0];
 #pragma unroll
-  for (int k = 1; k < kWaveRegs; ++k) {
+  for (int k = 1; k < kR; ++k) {
     vmin = v[k] < vmin ? v[k] : vmin;
     vmax = v[k] > vmax ? v[k] : vmax;
   }
@@ -194,7 +195,7 @@ __device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, ui
     if (narrow) {
       uint64_t sy = 0, sty = 0;  // < 2^40 and < 2^50
 #pragma unroll
-      for (int k = 0; k < kWaveRegs; ++k) {
+      for (int k = 0; k < kR; ++k) {
         const uint32_t t = lane + 64 * k;
         const uint64_t y = t < len ? uint32_t(v[k]) - uint32_t(vmin) : 0;
         sy += y;
@@ -205,7 +206,7 @@ __device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, ui
     } else {
       U128 sv{0, 0}, stv{0, 0};
 #pragma unroll
-      for (int k = 0; k < kWaveRegs; ++k) {
+      for (int k = 0; k < kR; ++k) {
         const uint32_t t = lane + 64 * k;
         const uint64_t x = t < len ? v[k] : 0;
         sv = add128(sv, U128{x, 0});
@@ -218,7 +219,7 @@ __device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, ui
     const bool small = narrow && __dmul_rn(fabs(th), double(len)) < 1073741824.0;
     int64_t rmin = INT64_MAX, rmax = INT64_MIN;
 #pragma unroll
-    for (int k = 0; k < kWaveRegs; ++k) {
+    for (int k = 0; k < kR; ++k) {
       const uint32_t t = lane + 64 * k;
       const int64_t rr = small ? int64_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t))
                                : int64_t(v[k] - vmin) - predict(th, t);
@@ -233,6 +234,7 @@ __device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, ui
   return md;
 }
 
+template <int kR>
 __global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restrict__ cols,
                                                        uint64_t ncols, EncColumn single,
                                                        uint64_t nparts, EncScratch scr,
@@ -245,13 +247,13 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_wave(const EncColumn* __restr
   const EncColumn c = column_of(cols, ncols, single, P);
   uint64_t start, len;
   part_bounds(c, P - c.part_base, start, len);
-  if (len > kWaveEncMax) {  // the host sends such partitions to k_fit_block
+  if (len > 64 * kR) {  // the host sends such partitions to k_fit_block
     if (lane == 0) raise(err, kErrDevice);
     return;
   }
   const Model md = c.dtype == 8
-                       ? fit_wave(reinterpret_cast<const uint64_t*>(c.col) + start, len, c.force_constant)
-                       : fit_wave(reinterpret_cast<const uint32_t*>(c.col) + start, len, c.force_constant);
+                       ? fit_wave<kR>(reinterpret_cast<const uint64_t*>(c.col) + start, len, c.force_constant)
+                       : fit_wave<kR>(reinterpret_cast<const uint32_t*>(c.col) + start, len, c.force_constant);
   if (lane == 0) store_model(scr, P, md, len);
 }
 
@@ -510,7 +512,7 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax_wave(HullShar
                                                                         const T* src, uint64_t len,
                                                                         bool force_constant,
                                                                         bool minimax) {
-  Model md = fit_wave(src, len, force_constant);
+  Model md = fit_wave<kWaveRegs>(src, len, force_constant);
   if (!minimax || len < 2 || force_constant || md.range >= (uint64_t(1) << 61)) return md;
   const uint32_t lane = threadIdx.x & 63;
   const auto gsrc = global_ptr(src);
@@ -590,31 +592,39 @@ __device__ inline double i128_to_double(__int128 x) {
 // coefficients of g_k:
 //   S1 = 2 M1 - a M0,  S2 = 6 M2 - 6a M1 + e2 M0,
 //   S3 = 20 M3 - 30a M2 + k3 M1 - e3 M0        (a = n - 1).
-// A thread's share of M_j expands (u + kT k)^j binomially over its sums
-// T_i = sum_k y_k k^i, so the loop over values multiplies only by the
-// constants k^i; T_3 <= 2^50 (0^3 + ... + 15^3) < 2^64, so every T_i fits
-// 64 bits.  The group totals stay below 2^103 in magnitude.
+// A thread's positions come in chunks of up to 16 registers, t = u' + kT j
+// (u' = u + 16 kT h for chunk h, j < 16); its share of M_j expands
+// (u' + kT j)^j binomially over the chunk's sums T_i = sum_j y_j j^i, so
+// the loop over values multiplies only by the constants j^i;
+// T_3 <= 2^50 (0^3 + ... + 15^3) < 2^64, so every T_i fits 64 bits.  The
+// group totals stay below 2^103 in magnitude.
 template <int kT, int kR, class Sum4, class MinMax>
 __device__ __attribute__((always_inline)) inline void poly_stage(
     Model& md, const uint64_t (&y)[kR], uint32_t tid, uint32_t n, const Sum4& sum4,
     const MinMax& minmax, uint32_t& kind, double& c2_out, double& c3_out) {
-  static_assert(kR <= 16, "per-thread moment sums must fit 64 bits");
-  uint64_t T0 = 0, T1 = 0, T2 = 0, T3 = 0;
-#pragma unroll
-  for (int k = 0; k < kR; ++k) {
-    const uint64_t yk = tid + uint32_t(k * kT) < n ? y[k] : 0;
-    T0 += yk;
-    T1 += yk * uint64_t(k);
-    T2 += yk * uint64_t(k * k);
-    T3 += yk * uint64_t(k * k * k);
-  }
+  constexpr int kC = kR < 16 ? kR : 16;  // registers per chunk
+  static_assert(kR % kC == 0, "whole chunks");
   using u128 = unsigned __int128;
-  const uint64_t u = tid, S = kT;
-  u128 M0 = T0;
-  u128 M1 = u128(T0) * u + u128(T1) * S;
-  u128 M2 = u128(T0) * (u * u) + u128(T1) * (2 * u * S) + u128(T2) * (S * S);
-  u128 M3 = u128(T0) * (u * u * u) + u128(T1) * (3 * u * u * S) + u128(T2) * (3 * u * S * S) +
-            u128(T3) * (S * S * S);
+  u128 M0 = 0, M1 = 0, M2 = 0, M3 = 0;
+#pragma unroll
+  for (int h = 0; h < kR / kC; ++h) {
+    uint64_t T0 = 0, T1 = 0, T2 = 0, T3 = 0;
+#pragma unroll
+    for (int j = 0; j < kC; ++j) {
+      const int k = h * kC + j;
+      const uint64_t yk = tid + uint32_t(k * kT) < n ? y[k] : 0;
+      T0 += yk;
+      T1 += yk * uint64_t(j);
+      T2 += yk * uint64_t(j * j);
+      T3 += yk * uint64_t(j * j * j);
+    }
+    const uint64_t u = tid + uint64_t(h) * kC * kT, S = kT;
+    M0 += T0;
+    M1 += u128(T0) * u + u128(T1) * S;
+    M2 += u128(T0) * (u * u) + u128(T1) * (2 * u * S) + u128(T2) * (S * S);
+    M3 += u128(T0) * (u * u * u) + u128(T1) * (3 * u * u * S) + u128(T2) * (3 * u * S * S) +
+          u128(T3) * (S * S * S);
+  }
   sum4(M0, M1, M2, M3);
   const int64_t N = n, a = N - 1;
   const int64_t k3 = 12 * N * N - 30 * N + 22, e2 = a * (N - 2), e3 = a * (N - 2) * (N - 3);
@@ -717,20 +727,20 @@ __device__ __attribute__((always_inline)) inline Model fit_poly(FitShared& fs, c
   return md;
 }
 
-// The same by one wavefront, for partitions of at most kWaveEncMax values:
-// the model of fit_wave, then the polynomial stage with wavefront
-// reductions (no barrier).
-template <class T>
+// The same by one wavefront, for partitions of at most 64 kR values: the
+// model of fit_wave, then the polynomial stage with wavefront reductions (no
+// barrier).
+template <int kR, class T>
 __device__ __attribute__((always_inline)) inline Model fit_poly_wave(const T* src, uint64_t len, bool force_constant,
                                       uint32_t& kind, double& c2_out, double& c3_out) {
-  Model md = fit_wave(src, len, force_constant);
+  Model md = fit_wave<kR>(src, len, force_constant);
   kind = 0;
   c2_out = c3_out = 0.0;
   if (force_constant || len < 3 || md.range >= kPolyMaxRange) return md;
   const uint32_t lane = threadIdx.x & 63;
-  uint64_t y[kWaveRegs];
+  uint64_t y[kR];
 #pragma unroll
-  for (int k = 0; k < kWaveRegs; ++k) y[k] = load_clamped(src, lane + 64 * k, len) - md.vmin;
+  for (int k = 0; k < kR; ++k) y[k] = load_clamped(src, lane + 64 * k, len) - md.vmin;
   const auto sum4 = [](unsigned __int128& m0, unsigned __int128& m1, unsigned __int128& m2,
                        unsigned __int128& m3) {
     U128 x = to_u128(m0), w = to_u128(m1), z = to_u128(m2), q = to_u128(m3);
@@ -742,7 +752,7 @@ __device__ __attribute__((always_inline)) inline Model fit_poly_wave(const T* sr
     m3 = from_u128(q);
   };
   const auto minmax = [](int64_t& mn, int64_t& mx) { wave_minmax_i64(mn, mx); };
-  poly_stage<64, kWaveRegs>(md, y, lane, uint32_t(len), sum4, minmax, kind, c2_out, c3_out);
+  poly_stage<64, kR>(md, y, lane, uint32_t(len), sum4, minmax, kind, c2_out, c3_out);
   return md;
 }
 
@@ -777,6 +787,7 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_poly(const EncColumn* __restr
   }
 }
 
+template <int kR>
 __global__ __launch_bounds__(kEncBlock) void k_fit_poly_wave(const EncColumn* __restrict__ cols,
                                                             uint64_t ncols, EncColumn single,
                                                             uint64_t nparts, EncScratch scr,
@@ -789,7 +800,7 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_poly_wave(const EncColumn* __
   if (c.regressor != 2) return;  // the other fit kernels
   uint64_t start, len;
   part_bounds(c, P - c.part_base, start, len);
-  if (len > kWaveEncMax) {  // the host sends such partitions to k_fit_poly
+  if (len > 64 * kR) {  // the host sends such partitions to k_fit_poly
     if (lane == 0) raise(err, kErrDevice);
     return;
   }
@@ -797,10 +808,10 @@ __global__ __launch_bounds__(kEncBlock) void k_fit_poly_wave(const EncColumn* __
   double c2, c3;
   const Model md =
       c.dtype == 8
-          ? fit_poly_wave(reinterpret_cast<const uint64_t*>(c.col) + start, len, c.force_constant,
-                          kind, c2, c3)
-          : fit_poly_wave(reinterpret_cast<const uint32_t*>(c.col) + start, len, c.force_constant,
-                          kind, c2, c3);
+          ? fit_poly_wave<kR>(reinterpret_cast<const uint64_t*>(c.col) + start, len,
+                              c.force_constant, kind, c2, c3)
+          : fit_poly_wave<kR>(reinterpret_cast<const uint32_t*>(c.col) + start, len,
+                              c.force_constant, kind, c2, c3);
   if (lane == 0) {
     store_model(scr, P, md, len);
     store_poly(scr, P, kind, c2, c3);
@@ -1051,25 +1062,35 @@ hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t
   if (nparts == 0) return hipSuccess;
   // each fit kernel fits the columns of its regressors and skips the others
   const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
-  const bool short_parts = max_len <= kWaveEncMax && ctx->tune.encode_wave;
-  if ((regs & kRegPoly) && short_parts)
-    hipLaunchKernelGGL(k_fit_poly_wave, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream, cols_dev,
-                       ncols, single, nparts, scr, ctx->err_dev);
+  // one wavefront per partition: 16 values per lane up to 1024 values, 32
+  // up to 2048 (not the minimax fit, whose hull slice holds 1024)
+  const bool wave16 = max_len <= kWaveEncMax && ctx->tune.encode_wave;
+  const bool wave32 =
+      max_len <= 2 * kWaveEncMax && ctx->tune.encode_wave && ctx->tune.encode_wave32;
+  if ((regs & kRegPoly) && wave16)
+    hipLaunchKernelGGL(k_fit_poly_wave<kWaveRegs>, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream,
+                       cols_dev, ncols, single, nparts, scr, ctx->err_dev);
+  else if ((regs & kRegPoly) && wave32)
+    hipLaunchKernelGGL(k_fit_poly_wave<2 * kWaveRegs>, dim3(uint32_t(pw)), dim3(kEncBlock), 0,
+                       stream, cols_dev, ncols, single, nparts, scr, ctx->err_dev);
   else if (regs & kRegPoly)
     hipLaunchKernelGGL(k_fit_poly, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr);
   if (!(regs & (kRegLS | kRegMinimax))) return hipGetLastError();
   // k_fit_wave fits every column it is given: not with polynomial columns
-  const bool wave = short_parts && !(regs & kRegPoly);
-  if ((regs & kRegMinimax) && wave)
+  const bool poly = regs & kRegPoly;
+  if ((regs & kRegMinimax) && wave16 && !poly)
     hipLaunchKernelGGL(k_fit_minimax_wave, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr, ctx->err_dev);
   else if (regs & kRegMinimax)
     hipLaunchKernelGGL(k_fit_minimax, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr, ctx->err_dev);
-  else if (wave)
-    hipLaunchKernelGGL(k_fit_wave, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream, cols_dev, ncols,
-                       single, nparts, scr, ctx->err_dev);
+  else if (wave16 && !poly)
+    hipLaunchKernelGGL(k_fit_wave<kWaveRegs>, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream,
+                       cols_dev, ncols, single, nparts, scr, ctx->err_dev);
+  else if (wave32 && !poly)
+    hipLaunchKernelGGL(k_fit_wave<2 * kWaveRegs>, dim3(uint32_t(pw)), dim3(kEncBlock), 0, stream,
+                       cols_dev, ncols, single, nparts, scr, ctx->err_dev);
   else
     hipLaunchKernelGGL(k_fit_block, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr);

@@ -17,10 +17,12 @@ struct Tune {
   uint32_t xcd_remap = 0;            // 1 = contiguous tile runs per XCD
   uint32_t ra_lookups_per_lane = 1;  // 1, 2, 4 or 8 positions per lane
   uint32_t encode_wave = 1;          // 1 = one wavefront per partition when all are short
+  uint32_t encode_wave32 = 1;        // 1 = the same up to 2048 values (32 per lane)
 };
 
-// Reads LECO_TILE_LOG2, LECO_DECODE_BLOCKS_PER_CU, LECO_XCD_REMAP and
-// LECO_RA_LPT, LECO_ENCODE_WAVE overrides from the environment.
+// Reads LECO_TILE_LOG2, LECO_DECODE_BLOCKS_PER_CU, LECO_XCD_REMAP,
+// LECO_RA_LPT, LECO_ENCODE_WAVE and LECO_ENCODE_WAVE32 overrides from the
+// environment.
 void tune_from_env(Tune& t);
 
 // One column for the encoder: input, partitioning, output blob.  A table of

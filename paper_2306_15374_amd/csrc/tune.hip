@@ -20,6 +20,7 @@ void tune_from_env(Tune& t) {
   env_u32("LECO_DECODE_BLOCKS_PER_CU", 0, 64, &t.decode_blocks_per_cu);
   env_u32("LECO_XCD_REMAP", 0, 1, &t.xcd_remap);
   env_u32("LECO_ENCODE_WAVE", 0, 1, &t.encode_wave);
+  env_u32("LECO_ENCODE_WAVE32", 0, 1, &t.encode_wave32);
   uint32_t lpt = t.ra_lookups_per_lane;
   if (env_u32("LECO_RA_LPT", 1, 8, &lpt) && (lpt == 1 || lpt == 2 || lpt == 4 || lpt == 8))
     t.ra_lookups_per_lane = lpt;

@@ -147,6 +147,11 @@ def test_edge_cases(torch, codec, ref):
          dict(starts=np.array([0, 1, 2, 30_000, 69_999, 70_000], np.uint64))),
         ("max partition", W.lognormal_keys((1 << 20) + 5, 3), dict(fixed_len=1 << 20)),
         ("L=4097 ragged", W.lognormal_keys(100_000, 10, np.uint32), dict(fixed_len=4097)),
+        # one wavefront per partition with 32 values per lane (1025..2048)
+        ("L=1025 u32", W.lognormal_keys(60_000, 11, np.uint32), dict(fixed_len=1025)),
+        ("L=2048 full range", rng.integers(0, 2**64 - 1, 9000, np.uint64, endpoint=True),
+         dict(fixed_len=2048)),
+        ("L=2049", W.linear_noise(30_000, 12), dict(fixed_len=2049)),
     ]
     for name, col, kw in cases:
         check_column(torch, codec, ref, col, name, **kw)

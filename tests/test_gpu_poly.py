@@ -97,6 +97,9 @@ FIXED = [
     ("range_2_50", lambda: wide(30_000, 9), 1000),
     ("range_below_2_50_wave", lambda: big_cubic(50_000, 16, 1000), 1000),
     ("range_below_2_50_block", lambda: big_cubic(50_000, 17, 4096), 4096),
+    ("range_below_2_50_wave32", lambda: big_cubic(50_000, 18, 2048), 2048),
+    ("cosmos_1025", lambda: W.cosmos(50_000, 19), 1025),
+    ("cosmos_2049", lambda: W.cosmos(50_000, 25), 2049),
     ("tiny_3", lambda: W.cosmos(5_000, 10), 3),
     ("tiny_4", lambda: W.cosmos(5_001, 11), 4),
     ("pairs", lambda: W.cosmos(4_001, 12), 2),
