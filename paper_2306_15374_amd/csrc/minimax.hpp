@@ -128,15 +128,29 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
                                                                  uint32_t tid) {
   const uint32_t c0 = tid * kHullChunk;
   const uint32_t c1 = c0 + kHullChunk < cnt ? c0 + kHullChunk : (c0 < cnt ? cnt : c0);
+  // the thread's points in registers; the chain keeps its top two vertices
+  // in registers too, so a test reads no LDS and a removal reads one vertex
+  uint64_t pv[kHullChunk];
+#pragma unroll
+  for (uint32_t j = 0; j < kHullChunk; ++j) pv[j] = c0 + j < c1 ? sh.v[c0 + j] : 0;
   for (uint32_t side = 0; side < 2; ++side) {
     uint16_t* H = sh.h[side] + c0;
     uint32_t k = 0;
-    for (uint32_t t = c0; t < c1; ++t) {
-      const HullPoint r{t, sh.v[t]};
-      while (k >= 2 && hull_drops(side == 0, HullPoint{H[k - 2], sh.v[H[k - 2]]},
-                                  HullPoint{H[k - 1], sh.v[H[k - 1]]}, r))
-        --k;
-      H[k++] = uint16_t(t);
+    HullPoint below{0, 0}, top{0, 0};  // H[k-2] and H[k-1] when k >= 2
+#pragma unroll
+    for (uint32_t j = 0; j < kHullChunk; ++j) {
+      const uint32_t t = c0 + j;
+      if (t < c1) {
+        const HullPoint r{t, pv[j]};
+        while (k >= 2 && hull_drops(side == 0, below, top, r)) {
+          --k;
+          top = below;
+          if (k >= 2) below = HullPoint{H[k - 2], sh.v[H[k - 2]]};
+        }
+        H[k++] = uint16_t(t);
+        below = top;
+        top = r;
+      }
     }
     sh.cnt[side][tid] = uint16_t(k);
   }
