@@ -386,7 +386,19 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
   for (uint32_t k = 0; k < ntiles; ++k) {
     const uint32_t t0 = k * kHullTile;
     const uint32_t cnt = uint32_t(len - t0 < kHullTile ? len - t0 : kHullTile);
-    for (uint32_t x = tid; x < cnt; x += kEncBlock) hs.v[x] = uint64_t(gsrc[t0 + x]);
+    {  // the tile's loads issued at once
+      uint64_t tv[kHullChunk];
+#pragma unroll
+      for (uint32_t j = 0; j < kHullChunk; ++j) {
+        const uint32_t x = tid + j * kEncBlock;
+        tv[j] = x < cnt ? uint64_t(gsrc[t0 + x]) : 0;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kHullChunk; ++j) {
+        const uint32_t x = tid + j * kEncBlock;
+        if (x < cnt) hs.v[x] = tv[j];
+      }
+    }
     __syncthreads();
     tile_hulls<kEncBlock>(hs, cnt, tid);
     if (ntiles == 1) break;
@@ -452,11 +464,17 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
   double theta = static_cast<double>(th.dy) / static_cast<double>(th.dt);
   if (theta == 0.0) theta = 0.0;  // +0.0, never -0.0
   int64_t rmin = INT64_MAX, rmax = INT64_MIN;
-  for (uint32_t t = tid; t < len; t += kEncBlock) {
-    const uint64_t x = ntiles == 1 ? hs.v[t] : uint64_t(gsrc[t]);
-    const int64_t rr = int64_t(x - md.vmin) - predict(theta, t);
-    rmin = rr < rmin ? rr : rmin;
-    rmax = rr > rmax ? rr : rmax;
+  for (uint32_t t0 = 0; t0 < len; t0 += kHullTile) {
+#pragma unroll
+    for (uint32_t j = 0; j < kHullChunk; ++j) {
+      const uint32_t t = t0 + tid + j * kEncBlock;
+      if (t < len) {
+        const uint64_t x = ntiles == 1 ? hs.v[t] : uint64_t(gsrc[t]);
+        const int64_t rr = int64_t(x - md.vmin) - predict(theta, t);
+        rmin = rr < rmin ? rr : rmin;
+        rmax = rr > rmax ? rr : rmax;
+      }
+    }
   }
   block_minmax_i64(fs, rmin, rmax);
   const uint32_t b = bitlen64(uint64_t(rmax) - uint64_t(rmin));
@@ -515,8 +533,13 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax_wave(HullShar
   Model md = fit_wave<kWaveRegs>(src, len, force_constant);
   if (!minimax || len < 2 || force_constant || md.range >= (uint64_t(1) << 61)) return md;
   const uint32_t lane = threadIdx.x & 63;
-  const auto gsrc = global_ptr(src);
-  for (uint32_t x = lane; x < len; x += 64) hs.v[x] = uint64_t(gsrc[x]);
+  // all loads issued at once (the same addresses fit_wave read)
+  uint64_t v[kWaveRegs];
+#pragma unroll
+  for (int k = 0; k < kWaveRegs; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
+#pragma unroll
+  for (int k = 0; k < kWaveRegs; ++k)
+    if (lane + 64 * k < len) hs.v[lane + 64 * k] = v[k];
   group_sync<64>();
   tile_hulls<64>(hs, uint32_t(len), lane);
   const auto U = [&](uint32_t i) {
@@ -531,10 +554,14 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax_wave(HullShar
   double theta = static_cast<double>(th.dy) / static_cast<double>(th.dt);
   if (theta == 0.0) theta = 0.0;  // +0.0, never -0.0
   int64_t rmin = INT64_MAX, rmax = INT64_MIN;
-  for (uint32_t t = lane; t < len; t += 64) {
-    const int64_t rr = int64_t(hs.v[t] - md.vmin) - predict(theta, t);
-    rmin = rr < rmin ? rr : rmin;
-    rmax = rr > rmax ? rr : rmax;
+#pragma unroll
+  for (int k = 0; k < kWaveRegs; ++k) {
+    const uint32_t t = lane + 64 * k;
+    if (t < len) {
+      const int64_t rr = int64_t(v[k] - md.vmin) - predict(theta, t);
+      rmin = rr < rmin ? rr : rmin;
+      rmax = rr > rmax ? rr : rmax;
+    }
   }
   wave_minmax_i64(rmin, rmax);
   const uint32_t b = bitlen64(uint64_t(rmax) - uint64_t(rmin));
