@@ -211,3 +211,24 @@ def test_size_search_with_polynomials(torch, codec, ref):
             ref.fixed_cost(col, starts, 8_000, L, regressor="poly")
     assert codec.size_search(d, starts, 8_000, regressor="poly") == \
         ref.size_search(col, starts, 8_000, regressor="poly")
+
+
+@pytest.mark.parametrize("env", [{"LECO_ENCODE_WAVE32": "0"}, {"LECO_ENCODE_WAVE": "0"}])
+def test_fit_kernel_choice_keeps_bytes(torch, ref, monkeypatch, env):
+    """Partitions of 1025..2048 values fitted one per workgroup (wavefronts
+    of 32 values per lane switched off) and of at most 1024 (wavefronts
+    switched off): the same bytes as the oracle, least squares and
+    polynomials."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    c = P.Codec(0)
+    try:
+        for name, col, L in [("cosmos", W.cosmos(60_000, 26), 2000),
+                             ("poly_blocks", W.poly_blocks(60_000, 27), 1000)]:
+            for reg in ("ls", "poly"):
+                log(f"[poly] {env} {name} L={L} {reg}")
+                expect = ref.encode(col, fixed_len=L, regressor=reg)
+                got = c.encode(dev(torch, col), fixed_len=L, regressor=reg).cpu().numpy()
+                assert np.array_equal(got, expect), f"{env} {name} {reg}"
+    finally:
+        c.close()
