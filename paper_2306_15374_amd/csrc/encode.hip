@@ -6,7 +6,7 @@
 //          model (section 3.1), hence its width b and its word count; with
 //          the minimax regressor also the minimax line (k_fit_minimax*,
 //          hulls in minimax.hpp), with the polynomial regressor the
-//          degree-2 and degree-3 polynomials (k_fit_poly);
+//          degree-2 and degree-3 polynomials (k_fit_poly*);
 //   scan   the exclusive prefix of the word counts gives every partition's
 //          word offset; the records, starts, header and padding are written;
 //   pack   every partition's residuals, recomputed from its stored model,
