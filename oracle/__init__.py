@@ -111,7 +111,11 @@ def _bind(L: C.CDLL) -> C.CDLL:
                                             C.c_int, vp, P(u64)]
     L.leco_ref_partition_split.argtypes = [vp, u64, C.c_int, C.c_double, u64, u64, C.c_int, vp,
                                            P(u64)]
-    L.leco_ref_start_positions.argtypes = [vp, u64, C.c_int, vp, P(u64)]
+    L.leco_ref_start_positions.argtypes = [vp, u64, C.c_int, vp, vp, P(u64)]
+    L.leco_ref_start_positions_delta.argtypes = [vp, u64, C.c_int, vp, P(u64)]
+    L.leco_ref_delta_fix_bytes.argtypes = [vp, u64, C.c_int, u64, P(u64)]
+    L.leco_ref_delta_fix_encode.argtypes = [vp, u64, C.c_int, u64, vp, u64, P(u64)]
+    L.leco_ref_delta_fix_decode.argtypes = [vp, u64, vp, u64]
     L.leco_ref_partition_merge.argtypes = [vp, u64, C.c_int, vp, P(u64), u64, u64]
     L.leco_ref_partition_dp.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
     L.leco_ref_partition_bruteforce.argtypes = [vp, u64, C.c_int, u64, vp, P(u64), P(u64)]
@@ -125,6 +129,8 @@ def _bind(L: C.CDLL) -> C.CDLL:
                  "leco_ref_random_access", "leco_ref_filter_sum",
                  "leco_ref_partition_greedy", "leco_ref_partition_merge",
                  "leco_ref_partition_split", "leco_ref_start_positions",
+                 "leco_ref_start_positions_delta", "leco_ref_delta_fix_bytes",
+                 "leco_ref_delta_fix_encode", "leco_ref_delta_fix_decode",
                  "leco_ref_partition_dp", "leco_ref_partition_bruteforce",
                  "leco_ref_partitioning_cost", "leco_ref_fixed_cost",
                  "leco_ref_size_search_fn", "leco_ref_size_search"):
@@ -280,13 +286,14 @@ def partition_cost_bytes(values, i: int, j: int) -> int:
 
 
 def partition_greedy(col: np.ndarray, tau: float = 0.1, sm_bits: int = 320,
-                     max_len: int = 1 << 20, max_rounds: int = 0,
+                     max_len: int = 1 << 20, max_passes: int = 0,
                      start_positions: bool = False) -> np.ndarray:
+    """Greedy split + merge scan (section 3.2.2); the partition starts."""
     col = np.ascontiguousarray(col)
     starts = np.zeros(len(col) + 1, dtype=np.uint64)
     m = C.c_uint64()
     _check("leco_ref_partition_greedy", lib().leco_ref_partition_greedy(
-        _ptr(col), len(col), _dtype_code(col), tau, sm_bits, max_len, max_rounds,
+        _ptr(col), len(col), _dtype_code(col), tau, sm_bits, max_len, max_passes,
         int(start_positions), _ptr(starts), C.byref(m)))
     return starts[: m.value + 1].copy()
 
@@ -303,24 +310,71 @@ def partition_split(col: np.ndarray, tau: float = 0.1, sm_bits: int = 320,
     return starts[: m.value + 1].copy()
 
 
+def starting_partitions(col: np.ndarray) -> list[tuple[int, int]]:
+    """Starting partitions of the linear regressor (section 3.2.2) as
+    half-open [first, end) value ranges."""
+    col = np.ascontiguousarray(col)
+    first = np.zeros(max(len(col), 1), dtype=np.uint64)
+    end = np.zeros(max(len(col), 1), dtype=np.uint64)
+    c = C.c_uint64()
+    _check("leco_ref_start_positions", lib().leco_ref_start_positions(
+        _ptr(col), len(col), _dtype_code(col), _ptr(first), _ptr(end), C.byref(c)))
+    return [(int(a), int(b)) for a, b in zip(first[: c.value], end[: c.value])]
+
+
 def start_positions(col: np.ndarray) -> np.ndarray:
-    """First values of the starting partitions (section 3.2.2)."""
+    """First values of the linear regressor's starting partitions."""
+    return np.array([a for a, _ in starting_partitions(col)], dtype=np.uint64)
+
+
+def start_positions_delta(col: np.ndarray) -> np.ndarray:
+    """First values of Delta encoding's starting partitions (section 3.2.2,
+    required bits and delta bits)."""
     col = np.ascontiguousarray(col)
     pos = np.zeros(max(len(col), 1), dtype=np.uint64)
     c = C.c_uint64()
-    _check("leco_ref_start_positions", lib().leco_ref_start_positions(
+    _check("leco_ref_start_positions_delta", lib().leco_ref_start_positions_delta(
         _ptr(col), len(col), _dtype_code(col), _ptr(pos), C.byref(c)))
     return pos[: c.value].copy()
 
 
 def partition_merge(col: np.ndarray, starts, max_len: int = 1 << 20,
-                    max_rounds: int = 0) -> np.ndarray:
+                    max_passes: int = 0) -> np.ndarray:
+    """Merge scan (section 3.2.2) applied to the partitioning `starts`."""
     col = np.ascontiguousarray(col)
     s = np.array(starts, dtype=np.uint64)
     m = C.c_uint64(len(s) - 1)
     _check("leco_ref_partition_merge", lib().leco_ref_partition_merge(
-        _ptr(col), len(col), _dtype_code(col), _ptr(s), C.byref(m), max_len, max_rounds))
+        _ptr(col), len(col), _dtype_code(col), _ptr(s), C.byref(m), max_len, max_passes))
     return s[: m.value + 1].copy()
+
+
+def delta_fix_bytes(col: np.ndarray, L: int) -> int:
+    """Size of the Delta-fix encoding (section 2, Delta over fixed partitions)."""
+    col = np.ascontiguousarray(col)
+    b = C.c_uint64()
+    _check("leco_ref_delta_fix_bytes", lib().leco_ref_delta_fix_bytes(
+        _ptr(col), len(col), _dtype_code(col), L, C.byref(b)))
+    return b.value
+
+
+def delta_fix_encode(col: np.ndarray, L: int) -> np.ndarray:
+    col = np.ascontiguousarray(col)
+    size = delta_fix_bytes(col, L)
+    out = np.zeros(max(size, 1), dtype=np.uint8)
+    b = C.c_uint64()
+    _check("leco_ref_delta_fix_encode", lib().leco_ref_delta_fix_encode(
+        _ptr(col), len(col), _dtype_code(col), L, _ptr(out), size, C.byref(b)))
+    return out[: b.value].copy()
+
+
+def delta_fix_decode(blob: np.ndarray) -> np.ndarray:
+    blob = np.ascontiguousarray(blob, dtype=np.uint8)
+    n = int(blob[8:16].view(np.uint64)[0])
+    out = np.zeros(max(n, 1), dtype=_np_dtype(int(blob[6])))
+    _check("leco_ref_delta_fix_decode", lib().leco_ref_delta_fix_decode(
+        _ptr(blob), len(blob), _ptr(out), n))
+    return out[:n].copy()
 
 
 def partition_dp(col: np.ndarray, max_len: int = 1 << 20) -> tuple[np.ndarray, int]:

@@ -860,73 +860,190 @@ static uint64_t *load_column(const void *col, uint64_t n, int dtype) {
   return v;
 }
 
-/* Merge phase, in rounds.  In each round every adjacent pair (j, j+1)
- * whose union fits max_len has the gain
- *   g_j = size(j) + size(j+1) - size(j u j+1)   (bytes, may be <= 0),
- * and pair j is merged when g_j > 0 and its key (g_j, j even) is larger
- * than the keys of pairs j-1 and j+1 (keys compare the gain first, then
- * prefer the even pair; neighbouring keys never tie), so the merged pairs
- * of a round never overlap.  Rounds repeat until one merges nothing, or
- * max_rounds rounds have run (0: no limit). */
+/* ---- Delta-fix special-case codec (section 2, Delta encoding; the
+ * evaluation's Delta-fix baseline) ---------------------------------------------
+ *
+ * Delta encoding over fixed-length partitions: a partition stores its first
+ * value (the implicit step model of section 3.2.2) and the first differences
+ * d_k = v_k - v_{k-1} of its other values, bit-packed at one fixed width.
+ * Read for bit-packing as LeCo packs residuals: the differences are stored
+ * as offsets e_k = d_k - d_min >= 0 from the partition's smallest
+ * difference, width bitlen(d_max - d_min) (at most 65 bits), residual t
+ * (t = 0 for the partition's second value) at bits [w t, w t + w) of the
+ * partition's word span, least-significant bit first.
+ * Layout: 32-byte header {magic "DLTF" u32, version u16 = 1, dtype u8,
+ * 0 u8, n u64, L u64, m u64}; m 32-byte records {v_first u64, d_min mod
+ * 2^64 u64, word_off u64, width u8, 0xff if d_min < 0 else 0 u8, 6 zero
+ * bytes}; then the words (word_off in 64-bit words from the section start).
+ * Decoding is sequential inside a partition: v_k = v_{k-1} + d_min + e_k. */
+
+#define DF_MAGIC 0x46544C44u /* bytes 'D','L','T','F' */
+#define DF_HEADER 32u
+#define DF_RECORD 32u
+
+/* Smallest and largest first difference of v[a, b) (b - a >= 2). */
+static void diff_range(const uint64_t *v, uint64_t a, uint64_t b, i128 *dmin, i128 *dmax) {
+  *dmin = *dmax = first_diff(v, a + 1);
+  for (uint64_t k = a + 2; k < b; k++) {
+    i128 d = first_diff(v, k);
+    if (d < *dmin) *dmin = d;
+    if (d > *dmax) *dmax = d;
+  }
+}
+
+static int delta_fix_plan(const uint64_t *v, uint64_t n, uint64_t L, uint64_t *words) {
+  uint64_t total = 0;
+  for (uint64_t a = 0; a < n; a += L) {
+    uint64_t b = a + L < n ? a + L : n;
+    if (b - a < 2) continue;
+    i128 dmin, dmax;
+    diff_range(v, a, b, &dmin, &dmax);
+    uint64_t w = bitlen128((u128)(dmax - dmin));
+    total += ((b - a - 1) * w + 63) / 64;
+  }
+  *words = total;
+  return LREF_OK;
+}
+
+int leco_ref_delta_fix_bytes(const void *col, uint64_t n, int dtype, uint64_t L,
+                             uint64_t *bytes) {
+  if ((dtype != 4 && dtype != 8) || L == 0 || L > MAX_PART_LEN || bytes == NULL)
+    return LREF_EINVAL;
+  uint64_t *v = load_column(col, n, dtype);
+  if (!v) return LREF_ENOMEM;
+  uint64_t words = 0;
+  delta_fix_plan(v, n, L, &words);
+  uint64_t m = (n + L - 1) / L;
+  *bytes = DF_HEADER + DF_RECORD * m + 8 * words;
+  free(v);
+  return LREF_OK;
+}
+
+int leco_ref_delta_fix_encode(const void *col, uint64_t n, int dtype, uint64_t L,
+                              uint8_t *blob, uint64_t cap, uint64_t *blob_bytes) {
+  uint64_t need = 0;
+  int st = leco_ref_delta_fix_bytes(col, n, dtype, L, &need);
+  if (st != LREF_OK) return st;
+  *blob_bytes = need;
+  if (cap < need || blob == NULL) return LREF_ENOSPC;
+  uint64_t *v = load_column(col, n, dtype);
+  if (!v) return LREF_ENOMEM;
+  memset(blob, 0, need);
+  uint64_t m = (n + L - 1) / L;
+  put_u32(blob, DF_MAGIC);
+  put_u16(blob + 4, 1);
+  blob[6] = (uint8_t)dtype;
+  put_u64(blob + 8, n);
+  put_u64(blob + 16, L);
+  put_u64(blob + 24, m);
+  uint8_t *words = blob + DF_HEADER + DF_RECORD * m;
+  uint64_t word_off = 0;
+  for (uint64_t j = 0; j < m; j++) {
+    uint64_t a = j * L, b = a + L < n ? a + L : n;
+    uint8_t *rec = blob + DF_HEADER + DF_RECORD * j;
+    put_u64(rec, v[a]);
+    put_u64(rec + 16, word_off);
+    if (b - a < 2) continue;
+    i128 dmin, dmax;
+    diff_range(v, a, b, &dmin, &dmax);
+    uint64_t w = bitlen128((u128)(dmax - dmin));
+    put_u64(rec + 8, (uint64_t)dmin);
+    rec[24] = (uint8_t)w;
+    rec[25] = dmin < 0 ? 0xff : 0;
+    uint8_t *span = words + 8 * word_off;
+    for (uint64_t k = a + 1; k < b; k++) {
+      u128 e = (u128)(first_diff(v, k) - dmin);
+      uint64_t t = k - a - 1;
+      for (uint64_t bit = 0; bit < w; bit++)
+        if ((e >> bit) & 1u) set_stream_bit(span, w * t + bit);
+    }
+    word_off += ((b - a - 1) * w + 63) / 64;
+  }
+  free(v);
+  return LREF_OK;
+}
+
+int leco_ref_delta_fix_decode(const uint8_t *blob, uint64_t blob_bytes, void *out,
+                              uint64_t out_cap_elems) {
+  if (blob == NULL || blob_bytes < DF_HEADER || get_u32(blob) != DF_MAGIC) return LREF_EFORMAT;
+  int dtype = blob[6];
+  uint64_t n = get_u64(blob + 8), L = get_u64(blob + 16), m = get_u64(blob + 24);
+  if ((dtype != 4 && dtype != 8) || L == 0 || L > MAX_PART_LEN || m != (n + L - 1) / L ||
+      m > (blob_bytes - DF_HEADER) / DF_RECORD)
+    return LREF_EFORMAT;
+  if (out_cap_elems < n) return LREF_ENOSPC;
+  const uint8_t *words = blob + DF_HEADER + DF_RECORD * m;
+  uint64_t nwords = (blob_bytes - DF_HEADER - DF_RECORD * m) / 8;
+  for (uint64_t j = 0; j < m; j++) {
+    const uint8_t *rec = blob + DF_HEADER + DF_RECORD * j;
+    uint64_t a = j * L, b = a + L < n ? a + L : n;
+    uint64_t x = get_u64(rec);
+    uint64_t dmin_lo = get_u64(rec + 8), off = get_u64(rec + 16), w = rec[24];
+    if (w > 65 || off > nwords || ((b - a - 1) * w + 63) / 64 > nwords - off)
+      return LREF_EFORMAT;
+    const uint8_t *span = words + 8 * off;
+    store_value(out, dtype, a, x);
+    for (uint64_t k = a + 1; k < b; k++) {
+      uint64_t t = k - a - 1;
+      u128 e = 0;
+      for (uint64_t bit = 0; bit < w; bit++)
+        e |= (u128)get_stream_bit(span, w * t + bit) << bit;
+      /* v_k = v_{k-1} + d_min + e_k, taken mod 2^64 (exact: the true v_k is
+       * a value of the column) */
+      x = x + dmin_lo + (uint64_t)e;
+      store_value(out, dtype, k, x);
+    }
+  }
+  return LREF_OK;
+}
+
+/* Merge phase (section 3.2.2): scan the partition list from the left; the
+ * current partition tries to merge with its right neighbour, and the merge
+ * is accepted when the merged partition is strictly smaller than the two
+ * apart (sizes: leco_ref_partition_cost_bytes) and stays within max_len.
+ * After an accepted merge the merged partition is the current one and tries
+ * its new right neighbour; after a refused one the neighbour becomes the
+ * current partition.  Passes over the list repeat until one accepts no
+ * merge, or max_passes passes have run (0: no limit).  The list is
+ * rewritten in place. */
 static void merge_phase(const uint64_t *v, uint64_t *s, uint64_t *m_io,
-                        uint64_t max_len, uint64_t max_rounds) {
+                        uint64_t max_len, uint64_t max_passes) {
   uint64_t m = *m_io;
-  for (uint64_t round = 0; max_rounds == 0 || round < max_rounds; round++) {
+  for (uint64_t pass = 0; max_passes == 0 || pass < max_passes; pass++) {
     if (m < 2) break;
-    int64_t *gain = (int64_t *)malloc((m - 1) * sizeof(int64_t));
-    unsigned char *take = (unsigned char *)calloc(m - 1, 1);
-    if (!gain || !take) {
-      free(gain);
-      free(take);
-      break; /* the partitioning stays valid, only less merged */
-    }
-    for (uint64_t j = 0; j + 1 < m; j++) {
-      uint64_t a = s[j], b = s[j + 1], c = s[j + 2];
-      if (c - a > max_len) {
-        gain[j] = 0;
-        continue;
-      }
-      uint64_t apart = leco_ref_partition_cost_bytes(v, a, b) +
-                       leco_ref_partition_cost_bytes(v, b, c);
-      uint64_t joint = leco_ref_partition_cost_bytes(v, a, c);
-      gain[j] = (int64_t)apart - (int64_t)joint;
-    }
     uint64_t merges = 0;
-    for (uint64_t j = 0; j + 1 < m; j++) {
-      if (gain[j] <= 0) continue;
-      /* key(j) > key(k) for each neighbouring pair k */
-      int beats_left = j == 0 || gain[j] > gain[j - 1] ||
-                       (gain[j] == gain[j - 1] && j % 2 == 0);
-      int beats_right = j + 2 >= m || gain[j] > gain[j + 1] ||
-                        (gain[j] == gain[j + 1] && j % 2 == 0);
-      if (beats_left && beats_right) {
-        take[j] = 1;
-        merges++;
+    uint64_t w = 0; /* s[0..w] are the kept starts; the current partition begins at s[w] */
+    uint64_t cur = leco_ref_partition_cost_bytes(v, s[0], s[1]);
+    for (uint64_t k = 1; k < m; k++) {
+      uint64_t a = s[w], b = s[k], c = s[k + 1];
+      uint64_t right = leco_ref_partition_cost_bytes(v, b, c);
+      if (c - a <= max_len) {
+        uint64_t joint = leco_ref_partition_cost_bytes(v, a, c);
+        if (joint < cur + right) {
+          cur = joint;
+          merges++;
+          continue;
+        }
       }
+      s[++w] = b;
+      cur = right;
     }
-    /* drop the start of partition j+1 for every merged pair j */
-    uint64_t w = 1;
-    for (uint64_t k = 1; k < m; k++)
-      if (!take[k - 1]) s[w++] = s[k];
-    s[w] = s[m];
-    m = w;
-    free(gain);
-    free(take);
+    s[w + 1] = s[m];
+    m = w + 1;
     if (merges == 0) break;
   }
   *m_io = m;
 }
 
-/* Good starting positions (section 3.2.2, "Selecting Good Starting
- * Positions", and the partitioning figure), read for the first differences
- * the split works on (reading R27):
+/* Good starting positions for Delta encoding (section 3.2.2, "Selecting
+ * Good Starting Positions", and the Delta-encoding partitioning figure):
  *   required bits  rb_k = signed width of d_k = bitlen(|d_k|) + 1, k >= 1;
  *   delta bits     db_k = |rb_k - rb_{k-1}|, k >= 2;
  * the positions whose delta bits equal the smallest over the column are
  * good; each maximal run of good positions k..k' is one starting partition
- * v[k-2, k'+1) (at least the three values a line needs).  forced[p] = 1 at
- * the first value p = k - 2 of every starting partition; n < 3 has none. */
-static void starting_positions(const uint64_t *v, uint64_t n, unsigned char *forced) {
+ * v[k-2, k'+1).  forced[p] = 1 at the first value p = k - 2 of every
+ * starting partition; n < 3 has none.  Used with the Delta-encoding cost. */
+static void starting_positions_delta(const uint64_t *v, uint64_t n, unsigned char *forced) {
   memset(forced, 0, n ? n : 1);
   if (n < 3) return;
   uint64_t best = ~(uint64_t)0;
@@ -944,8 +1061,73 @@ static void starting_positions(const uint64_t *v, uint64_t n, unsigned char *for
   }
 }
 
-int leco_ref_start_positions(const void *col, uint64_t n, int dtype, uint64_t *pos_out,
-                             uint64_t *count_out) {
+/* |dd_k| for the second-order delta dd_k = d_k - d_{k-1}
+ * = v_k - 2 v_{k-1} + v_{k-2}, k >= 2 (exact). */
+static u128 second_order_magnitude(const uint64_t *v, uint64_t k) {
+  i128 dd = first_diff(v, k) - first_diff(v, k - 1);
+  return dd < 0 ? (u128)(-dd) : (u128)dd;
+}
+
+/* Starting partitions for the linear regressor (section 3.2.2, "Selecting
+ * Good Starting Positions": for a model of degree k, the segments where the
+ * (k+1)-th order deltas are smallest; degree 1 here).  Position k >= 2 is
+ * good when |dd_k| equals the smallest |dd| over the column.  Each maximal
+ * run of good positions k..k' is one starting partition v[k-2, k'+1): the
+ * three values a second-order delta spans, which is also the paper's
+ * minimum for a linear regressor.  When two runs are one position apart
+ * they would share a value; the later starting partition takes it.
+ * mark[p] = 1 at the first value of a starting partition, 2 at its other
+ * values, 0 elsewhere; n < 3 has none. */
+static void starting_partitions_linear(const uint64_t *v, uint64_t n, unsigned char *mark) {
+  memset(mark, 0, n ? n : 1);
+  if (n < 3) return;
+  u128 best = second_order_magnitude(v, 2);
+  for (uint64_t k = 3; k < n; k++) {
+    u128 x = second_order_magnitude(v, k);
+    if (x < best) best = x;
+  }
+  uint64_t k = 2;
+  while (k < n) {
+    if (second_order_magnitude(v, k) != best) {
+      k++;
+      continue;
+    }
+    uint64_t last = k;
+    while (last + 1 < n && second_order_magnitude(v, last + 1) == best) last++;
+    mark[k - 2] = 1;
+    for (uint64_t p = k - 1; p <= last; p++) mark[p] = 2;
+    k = last + 1;
+  }
+}
+
+int leco_ref_start_positions(const void *col, uint64_t n, int dtype, uint64_t *first_out,
+                             uint64_t *end_out, uint64_t *count_out) {
+  if (dtype != 4 && dtype != 8) return LREF_EINVAL;
+  uint64_t *v = load_column(col, n, dtype);
+  unsigned char *mark = (unsigned char *)malloc(n ? n : 1);
+  if (!v || !mark) {
+    free(v);
+    free(mark);
+    return LREF_ENOMEM;
+  }
+  starting_partitions_linear(v, n, mark);
+  uint64_t c = 0;
+  for (uint64_t p = 0; p < n; p++) {
+    if (mark[p] != 1) continue;
+    uint64_t e = p + 1;
+    while (e < n && mark[e] == 2) e++;
+    first_out[c] = p;
+    if (end_out) end_out[c] = e;
+    c++;
+  }
+  *count_out = c;
+  free(v);
+  free(mark);
+  return LREF_OK;
+}
+
+int leco_ref_start_positions_delta(const void *col, uint64_t n, int dtype, uint64_t *pos_out,
+                                   uint64_t *count_out) {
   if (dtype != 4 && dtype != 8) return LREF_EINVAL;
   uint64_t *v = load_column(col, n, dtype);
   unsigned char *forced = (unsigned char *)malloc(n ? n : 1);
@@ -954,7 +1136,7 @@ int leco_ref_start_positions(const void *col, uint64_t n, int dtype, uint64_t *p
     free(forced);
     return LREF_ENOMEM;
   }
-  starting_positions(v, n, forced);
+  starting_positions_delta(v, n, forced);
   uint64_t c = 0;
   for (uint64_t p = 0; p < n; p++)
     if (forced[p]) pos_out[c++] = p;
@@ -964,15 +1146,16 @@ int leco_ref_start_positions(const void *col, uint64_t n, int dtype, uint64_t *p
   return LREF_OK;
 }
 
-/* Split phase, left to right: keep the running range of first differences
- * of the current partition and include v[j] while
- * C = (len+1) * Delta~new - len * Delta~old <= tau * S_M and the partition
- * stays within max_len.  A partition also begins at every multiple of 2^20
- * (the longest partition the format allows), so the split of each
- * 2^20-value segment depends on that segment alone, and, when forced is
- * given, at the first value of every starting partition. */
+/* Split phase (section 3.2.2), left to right from position 0: keep the
+ * running range of first differences of the current partition v[i, j) and
+ * include v[j] while C = (len+1) * Delta~new - len * Delta~old <= tau * S_M,
+ * len = j - i; otherwise v[j] begins a new partition.  A partition that
+ * holds max_len values takes no further value.  With starting partitions
+ * (mark, or null): the first value of each begins a partition and its other
+ * values are included without the cost test (the partition is grown from
+ * there by the test), the cap still applying. */
 static uint64_t split_phase(const uint64_t *v, uint64_t n, double threshold, uint64_t max_len,
-                            const unsigned char *forced, uint64_t *starts_out) {
+                            const unsigned char *mark, uint64_t *starts_out) {
   uint64_t m = 0;
   uint64_t i = 0;
   starts_out[m++] = 0;
@@ -986,8 +1169,9 @@ static uint64_t split_phase(const uint64_t *v, uint64_t n, double threshold, uin
     uint64_t w_new = bitlen128((u128)(nmax - nmin));
     uint64_t len = j - i;
     double cost = (double)((int64_t)((len + 1) * w_new) - (int64_t)(len * w_old));
-    if (cost <= threshold && len < max_len && j % MAX_PART_LEN != 0 &&
-        !(forced && forced[j])) {
+    int begins = mark && mark[j] == 1;
+    int inside = mark && mark[j] == 2;
+    if (len < max_len && !begins && (inside || cost <= threshold)) {
       dmin = nmin;
       dmax = nmax;
       have_diff = 1;
@@ -1005,7 +1189,7 @@ static uint64_t split_phase(const uint64_t *v, uint64_t n, double threshold, uin
 
 static int partition_common(const void *col, uint64_t n, int dtype, double tau,
                             uint64_t sm_bits, uint64_t max_len, int merge,
-                            uint64_t max_rounds, int start_positions, uint64_t *starts_out,
+                            uint64_t max_passes, int start_positions, uint64_t *starts_out,
                             uint64_t *m_out) {
   if ((dtype != 4 && dtype != 8) || max_len == 0 || max_len > MAX_PART_LEN)
     return LREF_EINVAL;
@@ -1015,16 +1199,16 @@ static int partition_common(const void *col, uint64_t n, int dtype, double tau,
     return LREF_OK;
   }
   uint64_t *v = load_column(col, n, dtype);
-  unsigned char *forced = start_positions ? (unsigned char *)malloc(n) : NULL;
-  if (!v || (start_positions && !forced)) {
+  unsigned char *mark = start_positions ? (unsigned char *)malloc(n) : NULL;
+  if (!v || (start_positions && !mark)) {
     free(v);
-    free(forced);
+    free(mark);
     return LREF_ENOMEM;
   }
-  if (forced) starting_positions(v, n, forced);
-  uint64_t m = split_phase(v, n, tau * (double)sm_bits, max_len, forced, starts_out);
-  if (merge) merge_phase(v, starts_out, &m, max_len, max_rounds);
-  free(forced);
+  if (mark) starting_partitions_linear(v, n, mark);
+  uint64_t m = split_phase(v, n, tau * (double)sm_bits, max_len, mark, starts_out);
+  if (merge) merge_phase(v, starts_out, &m, max_len, max_passes);
+  free(mark);
   free(v);
   *m_out = m;
   return LREF_OK;
@@ -1032,9 +1216,9 @@ static int partition_common(const void *col, uint64_t n, int dtype, double tau,
 
 int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype, double tau,
                               uint64_t sm_bits, uint64_t max_len,
-                              uint64_t max_rounds, int start_positions,
+                              uint64_t max_passes, int start_positions,
                               uint64_t *starts_out, uint64_t *m_out) {
-  return partition_common(col, n, dtype, tau, sm_bits, max_len, 1, max_rounds,
+  return partition_common(col, n, dtype, tau, sm_bits, max_len, 1, max_passes,
                           start_positions, starts_out, m_out);
 }
 
@@ -1047,12 +1231,12 @@ int leco_ref_partition_split(const void *col, uint64_t n, int dtype, double tau,
 
 int leco_ref_partition_merge(const void *col, uint64_t n, int dtype,
                              uint64_t *starts, uint64_t *m, uint64_t max_len,
-                             uint64_t max_rounds) {
+                             uint64_t max_passes) {
   if ((dtype != 4 && dtype != 8) || max_len == 0 || max_len > MAX_PART_LEN)
     return LREF_EINVAL;
   uint64_t *v = load_column(col, n, dtype);
   if (!v) return LREF_ENOMEM;
-  merge_phase(v, starts, m, max_len, max_rounds);
+  merge_phase(v, starts, m, max_len, max_passes);
   free(v);
   return LREF_OK;
 }

@@ -164,14 +164,16 @@ uint64_t leco_ref_partition_cost_bytes(const uint64_t *v, uint64_t i,
                                        uint64_t j);
 
 /* Greedy split + merge (section 3.2.2).  starts_out needs room for n + 1
- * entries.  max_len caps partition length (<= 2^20).  The split restarts at
- * every multiple of 2^20 and, with start_positions, at the first value of
- * every starting partition (leco_ref_start_positions); the merge runs in
- * rounds (see merge below), at most max_rounds of them (0: until none
- * merges). */
+ * entries.  max_len caps partition length (<= 2^20): a partition holding
+ * max_len values takes no further value.  With start_positions the split
+ * also begins a partition at the first value of every starting partition
+ * (leco_ref_start_positions) and includes that starting partition's other
+ * values without the cost test.  The merge then scans the partition list
+ * (see leco_ref_partition_merge), at most max_passes passes (0: until a
+ * pass merges nothing). */
 int leco_ref_partition_greedy(const void *col, uint64_t n, int dtype,
                               double tau, uint64_t sm_bits, uint64_t max_len,
-                              uint64_t max_rounds, int start_positions,
+                              uint64_t max_passes, int start_positions,
                               uint64_t *starts_out, uint64_t *m_out);
 
 /* The split phase of leco_ref_partition_greedy alone. */
@@ -179,21 +181,49 @@ int leco_ref_partition_split(const void *col, uint64_t n, int dtype, double tau,
                              uint64_t sm_bits, uint64_t max_len, int start_positions,
                              uint64_t *starts_out, uint64_t *m_out);
 
-/* First values of the starting partitions (section 3.2.2, selecting good
- * starting positions): with rb_k the signed width of d_k = v_k - v_{k-1}
- * and db_k = |rb_k - rb_{k-1}|, each maximal run k..k' of positions whose
- * db equals the column's smallest db starts a partition at k - 2.
- * pos_out needs room for n entries; *count_out receives their number. */
-int leco_ref_start_positions(const void *col, uint64_t n, int dtype, uint64_t *pos_out,
-                             uint64_t *count_out);
+/* Starting partitions for the linear regressor (section 3.2.2, selecting
+ * good starting positions: the segments where the second-order deltas,
+ * dd_k = v_k - 2 v_{k-1} + v_{k-2}, are smallest).  Each maximal run k..k'
+ * of positions whose |dd_k| equals the column's smallest |dd| is one
+ * starting partition v[k-2, k'+1) (when two runs are one position apart
+ * the later one takes the shared value).  first_out[i] and end_out[i] (end
+ * may be null) receive the first value and one past the last value of the
+ * i-th starting partition; both need room for n entries; *count_out
+ * receives their number.  n < 3 has none. */
+int leco_ref_start_positions(const void *col, uint64_t n, int dtype, uint64_t *first_out,
+                             uint64_t *end_out, uint64_t *count_out);
 
-/* Merge phase alone, applied to a given partitioning (in place).  Each
- * round merges every adjacent pair whose size gain is positive and larger
- * than that of both neighbouring pairs (equal gains: the even pair wins);
- * rounds repeat until none merges or max_rounds have run (0: no limit). */
+/* Starting positions for Delta encoding (section 3.2.2 and the Delta
+ * partitioning figure): with rb_k the signed width of d_k = v_k - v_{k-1}
+ * ("required bits") and db_k = |rb_k - rb_{k-1}| ("delta bits"), each
+ * maximal run k..k' of positions whose db equals the column's smallest db
+ * starts a partition at k - 2.  pos_out needs room for n entries. */
+int leco_ref_start_positions_delta(const void *col, uint64_t n, int dtype, uint64_t *pos_out,
+                                   uint64_t *count_out);
+
+/* Merge phase alone, applied to a given partitioning (in place): the
+ * partition list is scanned from the left; the current partition merges
+ * with its right neighbour when the merged partition costs strictly fewer
+ * bytes than the two apart (leco_ref_partition_cost_bytes) and holds at
+ * most max_len values, and the merged partition then tries its new right
+ * neighbour; after a refusal the neighbour becomes the current partition.
+ * Passes repeat until one merges nothing or max_passes have run (0: no
+ * limit). */
 int leco_ref_partition_merge(const void *col, uint64_t n, int dtype,
                              uint64_t *starts, uint64_t *m, uint64_t max_len,
-                             uint64_t max_rounds);
+                             uint64_t max_passes);
+
+/* ---- Delta-fix codec (section 2, Delta encoding over fixed partitions) -----
+ * Partitions of L values; each stores its first value and the offsets
+ * e_k = d_k - d_min of its first differences d_k = v_k - v_{k-1} at width
+ * w = bitlen(d_max - d_min) (w <= 65), least-significant bit first.
+ * Size: 32 + 32 m + 8 * sum_j ceil((n_j - 1) w_j / 64) bytes. */
+int leco_ref_delta_fix_bytes(const void *col, uint64_t n, int dtype, uint64_t L,
+                             uint64_t *bytes);
+int leco_ref_delta_fix_encode(const void *col, uint64_t n, int dtype, uint64_t L,
+                              uint8_t *blob, uint64_t cap, uint64_t *blob_bytes);
+int leco_ref_delta_fix_decode(const uint8_t *blob, uint64_t blob_bytes, void *out,
+                              uint64_t out_cap_elems);
 
 /* Optimal partitioning by dynamic programming (section 3.2), O(n^3). */
 int leco_ref_partition_dp(const void *col, uint64_t n, int dtype,

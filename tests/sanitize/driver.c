@@ -165,8 +165,34 @@ int main(void) {
           CHECK(leco_ref_partition_greedy(col, n, dt, 0.05, 320, 1u << 20, 0, 0, st, &m) == LREF_OK);
           CHECK(leco_ref_partition_greedy(col, n, dt, 0.05, 320, 1u << 20, 0, 1, st, &m) == LREF_OK);
           CHECK(leco_ref_partition_split(col, n, dt, 0.05, 320, 1u << 20, 1, st, &m) == LREF_OK);
-          CHECK(leco_ref_start_positions(col, n, dt, st, &m) == LREF_OK);
+          CHECK(leco_ref_partition_split(col, n, dt, 0.0, 320, 5, 1, st, &m) == LREF_OK);
           CHECK(leco_ref_partitioning_cost(col, n, dt, st, m, &bytes) == LREF_OK);
+          {
+            uint64_t *en = (uint64_t *)malloc(n * 8), c = 0;
+            CHECK(leco_ref_start_positions(col, n, dt, st, en, &c) == LREF_OK);
+            CHECK(leco_ref_start_positions(col, n, dt, st, NULL, &c) == LREF_OK);
+            CHECK(leco_ref_start_positions_delta(col, n, dt, en, &c) == LREF_OK);
+            free(en);
+          }
+          for (uint64_t L = 1; L <= 4096; L *= 8) {
+            uint64_t need = 0;
+            CHECK(leco_ref_delta_fix_bytes(col, n, dt, L, &need) == LREF_OK);
+            uint8_t *df = (uint8_t *)malloc(need);
+            void *back = malloc(n * (uint64_t)dt);
+            CHECK(leco_ref_delta_fix_encode(col, n, dt, L, df, need, &need) == LREF_OK);
+            CHECK(leco_ref_delta_fix_decode(df, need, back, n) == LREF_OK);
+            CHECK(memcmp(back, col, n * (uint64_t)dt) == 0);
+            for (int f = 0; f < 8; f++) { /* damaged copies must not read out of bounds */
+              uint64_t cut = need - (next() % (need < 64 ? need : 64));
+              uint8_t *bad = (uint8_t *)malloc(cut ? cut : 1);
+              memcpy(bad, df, cut);
+              if (cut > 32) bad[next() % cut] ^= (uint8_t)(1u << (next() & 7));
+              (void)leco_ref_delta_fix_decode(bad, cut, back, n);
+              free(bad);
+            }
+            free(back);
+            free(df);
+          }
           CHECK(leco_ref_partition_merge(col, n, dt, st, &m, 1u << 20, 2) == LREF_OK);
           (void)leco_ref_split_cost(v, 0, n - 1, 0);
           (void)leco_ref_split_cost(v, 0, n - 1, 1);

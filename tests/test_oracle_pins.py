@@ -14,6 +14,8 @@ import pytest
 
 from paper_2306_15374_amd import workloads as W
 
+import partition_defs as PD
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 HEADER, RECORD = 64, 32
 
@@ -486,41 +488,81 @@ def test_merge_never_increases_size(ref):
     assert set(int(x) for x in merged) <= set(int(x) for x in fine)
 
 
-def test_merge_rounds_on_a_constant_column(ref):
+def test_merge_scan_on_a_constant_column(ref):
     """Every partition of a constant column has width 0 and costs one
     40-byte model (32-byte record + 8-byte start), and so does any union of
-    them: every pair gains exactly 40 bytes.  With all gains equal, a round
-    merges the even pairs (0,1), (2,3), ...; the rounds halve the count
-    until one partition is left."""
+    them, so every merge the scan tries gains 40 bytes: after each merge the
+    merged partition tries its next neighbour, and one pass leaves a single
+    partition.  With a cap of 30 values the scan merges 0-10-20-30, is
+    refused at 40 (40 values), restarts at 30, merges up to 60, is refused
+    at 70, and merges the last two: 0, 30, 60, 80."""
     col = np.full(80, 7, dtype=np.uint64)
     eight = [0, 10, 20, 30, 40, 50, 60, 70, 80]
     assert ref.partition_cost_bytes(col, 0, 10) == 40 == ref.partition_cost_bytes(col, 0, 80)
-    assert list(ref.partition_merge(col, eight, max_rounds=1)) == [0, 20, 40, 60, 80]
-    assert list(ref.partition_merge(col, eight, max_rounds=2)) == [0, 40, 80]
-    assert list(ref.partition_merge(col, eight, max_rounds=3)) == [0, 80]
+    assert list(ref.partition_merge(col, eight, max_passes=1)) == [0, 80]
     assert list(ref.partition_merge(col, eight)) == [0, 80]
-    # seven partitions: pairs 0, 2, 4 merge; the last partition waits
-    seven = [0, 10, 20, 30, 40, 50, 60, 80]
-    assert list(ref.partition_merge(col, seven, max_rounds=1)) == [0, 20, 40, 60, 80]
-    # the cap stops a merge: unions longer than 30 values are not formed
-    assert list(ref.partition_merge(col, eight, max_len=30)) == [0, 20, 40, 60, 80]
+    assert list(ref.partition_merge(col, eight, max_len=30)) == [0, 30, 60, 80]
 
 
-def test_merge_prefers_the_larger_gain(ref):
-    """Three partitions: a constant run of 7s (20 values), a constant run of
-    9s (20 values) and a constant run of 8s (20 values).  Merging the 7s and
-    9s gives width bitlen(2) = 2 over 40 values: 40 + 8 * ceil(80/64) = 56
-    bytes instead of 80, gain 24.  Merging the 9s and 8s gives width 1: 40 +
-    8 = 48 bytes, gain 32.  Only the larger gain merges in the first round;
-    the second round then merges the rest (width 2 over 60 values: 40 + 16 =
-    56 < 40 + 48 = 88)."""
-    col = np.array([7] * 20 + [9] * 20 + [8] * 20, dtype=np.uint64)
-    starts = [0, 20, 40, 60]
-    assert ref.partition_cost_bytes(col, 0, 40) == 56
-    assert ref.partition_cost_bytes(col, 20, 60) == 48
-    assert list(ref.partition_merge(col, starts, max_rounds=1)) == [0, 20, 60]
-    assert ref.partition_cost_bytes(col, 0, 60) == 56
-    assert list(ref.partition_merge(col, starts)) == [0, 60]
+def test_merge_scan_order_by_hand(ref):
+    """Runs A = 16 x 1200, B = 16 x 1001, C = 40 x 1000.  Alone each costs
+    40 bytes (width 0).  A+B: range 199, width 8 (a line does not narrow a
+    step this high), 32 values x 8 bits = 4 words: 72 < 80, merge.  The
+    scan then tries AB+C: range 200, width 8, 72 x 8 bits = 9 words: 112,
+    not below 72 + 40 = 112, refused.  Result: [0, 32, 72].  (B+C alone
+    would be the larger gain: width 1, one word, 48 < 80; a rule that merges
+    the largest gain first would end at [0, 16, 72], since A+BC = 112 is not
+    below 40 + 48.)"""
+    col = np.array([1200] * 16 + [1001] * 16 + [1000] * 40, np.uint64)
+    c = lambda a, b: ref.partition_cost_bytes(col, a, b)
+    assert (c(0, 16), c(16, 32), c(32, 72)) == (40, 40, 40)
+    assert (c(0, 32), c(16, 72), c(0, 72)) == (40 + 8 * 4, 40 + 8 * 1, 40 + 8 * 9)
+    assert list(ref.partition_merge(col, [0, 16, 32, 72])) == [0, 32, 72]
+
+
+def test_merge_second_pass_by_hand(ref):
+    """Runs P = 20 x 0, Q = 20 x 255, R = 20 x 200.  Pass one: P+Q has range
+    255, width 8, 40 x 8 = 320 bits = 5 words: 80, not below 40 + 40,
+    refused; Q+R has range 55, width 6, 240 bits = 4 words: 72 < 80, merged.
+    Pass two: P+QR has range 255, width 8, 60 x 8 = 480 bits = 8 words: 104
+    < 40 + 72 = 112, merged.  Pass three merges nothing."""
+    col = np.array([0] * 20 + [255] * 20 + [200] * 20, np.uint64)
+    c = lambda a, b: ref.partition_cost_bytes(col, a, b)
+    assert (c(0, 40), c(20, 60), c(0, 60)) == (40 + 8 * 5, 40 + 8 * 4, 40 + 8 * 8)
+    assert list(ref.partition_merge(col, [0, 20, 40, 60], max_passes=1)) == [0, 20, 60]
+    assert list(ref.partition_merge(col, [0, 20, 40, 60])) == [0, 60]
+
+
+def test_python_size_definition_matches_oracle(ref):
+    """The size a partition costs, recomputed in Python integers and floats
+    from the definitions (exact sums, fl(N)/fl(D), floor predictions,
+    constant model when not wider), equals the oracle's on random ranges."""
+    rng = np.random.default_rng(31)
+    cols = [W.piecewise_linear(3000, 5, segments=8).astype(np.uint64),
+            W.lognormal_keys(3000, 6), W.constant_runs(3000, 7).astype(np.uint64),
+            rng.integers(0, 2**64 - 1, 3000, dtype=np.uint64, endpoint=True)]
+    for col in cols:
+        for _ in range(60):
+            a = int(rng.integers(0, 2990))
+            b = int(rng.integers(a + 1, min(3000, a + 400) + 1))
+            assert PD.size_bytes(col, a, b) == ref.partition_cost_bytes(col, a, b)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_merge_equals_python_scan(ref, seed):
+    """The merge scan recomputed from scratch in Python (its own sizes) on
+    random partitionings of mixed-regime columns, with and without a cap and
+    a pass limit."""
+    rng = np.random.default_rng(100 + seed)
+    n = 1500
+    col = np.concatenate([W.piecewise_linear(n // 3, 200 + seed, segments=4).astype(np.uint64),
+                          W.constant_runs(n // 3, 300 + seed, mean_run=30).astype(np.uint64),
+                          rng.integers(0, 2**20, n - 2 * (n // 3), dtype=np.uint64)])
+    fine = [int(x) for x in random_partitioning(rng, n, 60)]
+    for max_len, passes in ((1 << 20, 0), (150, 0), (1 << 20, 1), (400, 2)):
+        expect = PD.merge(col, fine, max_len=max_len, max_passes=passes)
+        got = [int(x) for x in ref.partition_merge(col, fine, max_len=max_len, max_passes=passes)]
+        assert got == expect, (max_len, passes)
 
 
 def test_merge_fixed_point_has_no_positive_gain(ref):
@@ -533,14 +575,64 @@ def test_merge_fixed_point_has_no_positive_gain(ref):
         assert ref.partition_cost_bytes(col, a, c) >= apart
 
 
-def test_split_restarts_at_every_multiple_of_2_20(ref):
-    """A perfectly linear column never triggers a split by cost, so the
-    greedy's partitions are exactly the 2^20-value segments, and merging
-    across a segment boundary would exceed the 2^20 cap."""
-    n = 3 * (1 << 20) + 12345
-    col = np.arange(n, dtype=np.uint64) * np.uint64(3) + np.uint64(11)
-    starts = ref.partition_greedy(col)
-    assert list(starts) == [0, 1 << 20, 2 << 20, 3 << 20, n]
+def test_split_by_hand(ref):
+    """v = 10 12 14 17 19 23 24 25 26 90 91 92, tau * S_M = 0.1 * 40 = 4.
+    First differences 2 2 3 2 4 1 1 1 64 1 1.  From 0: v1, v2 join at C = 0
+    (D~ = 0); v3 makes the range of {2,2,3} 1, D~ = 1, C = 4 * 1 - 3 * 0 =
+    4 <= 4, joins; v4: D~ stays 1, C = 5 - 4 = 1, joins; v5 (d = 4): range
+    2, D~ = 2, C = 6 * 2 - 5 * 1 = 7 > 4, starts a partition.  From 5: v6,
+    v7, v8 join at C = 0; v9 (d = 64): range 63, D~ = 6, C = 5 * 6 = 30,
+    starts one; v10, v11 join.  Starts 0, 5, 9.  With a cap of 3 values: v3
+    starts one (length 3); v4 joins (one difference, D~ = 0); v5 has range
+    {2, 4} = 2, D~ = 2, C = 3 * 2 = 6 > 4; 6, 7 join, v8 hits the cap; v9
+    joins v8 (one difference); v10: range {64, 1} = 63, C = 3 * 6 = 18;
+    v11 joins.  Starts 0, 3, 5, 8, 10."""
+    v = np.array([10, 12, 14, 17, 19, 23, 24, 25, 26, 90, 91, 92], np.uint64)
+    assert list(ref.partition_split(v, tau=0.1, sm_bits=40)) == [0, 5, 9, 12]
+    assert list(ref.partition_split(v, tau=0.1, sm_bits=40, max_len=3)) == [0, 3, 5, 8, 10, 12]
+    assert PD.split(v, 0.1, 40) == [0, 5, 9, 12]
+    assert PD.split(v, 0.1, 40, max_len=3) == [0, 3, 5, 8, 10, 12]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_split_equals_python_definition(ref, seed):
+    """The split recomputed in Python from the definition (D~ of each
+    prefix from scratch, no running minima or widths) on random small
+    columns of every shape, thresholds from 0 to 0.15 of S_M, caps, and with
+    and without starting partitions."""
+    rng = np.random.default_rng(400 + seed)
+    n = int(rng.integers(2, 400))
+    kind = seed % 5
+    if kind == 0:
+        col = W.piecewise_linear(n, 500 + seed, segments=3).astype(np.uint64)
+    elif kind == 1:
+        col = W.constant_runs(n, 500 + seed, mean_run=6)
+    elif kind == 2:
+        col = np.cumsum(rng.integers(0, 9, n, dtype=np.uint64))
+    elif kind == 3:
+        col = rng.integers(0, 2**64 - 1, n, dtype=np.uint64, endpoint=True)
+        col[::2] = rng.integers(0, 8, len(col[::2]), dtype=np.uint64)
+    else:
+        col = (np.arange(n, dtype=np.uint64) * np.uint64(5) + rng.integers(0, 4, n, dtype=np.uint64))
+    for tau, sm, cap in ((0.0, 320, 1 << 20), (0.03, 320, 1 << 20), (0.15, 320, 37), (0.1, 64, 5)):
+        assert [int(x) for x in ref.partition_split(col, tau=tau, sm_bits=sm, max_len=cap)] == \
+            PD.split(col, tau, sm, cap)
+        sp = PD.starting_partitions(col)
+        assert [int(x) for x in ref.partition_split(col, tau=tau, sm_bits=sm, max_len=cap,
+                                                    start_positions=True)] == \
+            PD.split(col, tau, sm, cap, starting=sp)
+
+
+def test_split_cap_counts_from_the_partition_start(ref):
+    """A partition is cut only when it reaches 2^20 values: 1000 values of
+    one line, a jump, then 2^20 + 5000 values of another line: the cost cuts
+    at 1000, the cap at 1000 + 2^20, and no partition starts at 2^20."""
+    n2 = (1 << 20) + 5000
+    col = np.concatenate([np.arange(1000, dtype=np.uint64) * np.uint64(3),
+                          np.uint64(10**9) + np.arange(n2, dtype=np.uint64) * np.uint64(3)])
+    n = len(col)
+    assert list(ref.partition_split(col)) == [0, 1000, 1000 + (1 << 20), n]
+    assert list(ref.partition_greedy(col)) == [0, 1000, 1000 + (1 << 20), n]
 
 
 def test_greedy_partitions_respect_cap_and_round_trip(ref):
