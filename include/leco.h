@@ -291,15 +291,16 @@ leco_status leco_batch_set_shape(leco_batch *batch, uint32_t tile_log2,
  *          approximate cost C = (len + 1) * D~new - len * D~old of including
  *          it stays within tau * sm_bits (compared in binary64), where
  *          D~ = bitlen(max d - min d) over the partition's first differences
- *          d, and the partition stays within max_len; a partition also
- *          begins at every multiple of 2^20;
- *   merge  in rounds: each adjacent pair whose union fits max_len has the
- *          gain size(j) + size(j+1) - size(union), sizes being the exact
- *          bytes a partition costs in a variable-length blob (32-byte
- *          record, 8-byte start, residual words, with the model the encoder
- *          chooses); a pair merges when its gain is positive and larger than
- *          both neighbouring pairs' (equal gains: the even pair); rounds
- *          repeat until one merges nothing or max_rounds have run.
+ *          d, and while the partition holds fewer than max_len values;
+ *   merge  the paper's scan over the partition list: the current partition
+ *          merges with its right neighbour when the union costs strictly
+ *          fewer bytes than the two apart and holds at most max_len values,
+ *          sizes being the exact bytes a partition costs in a
+ *          variable-length blob (32-byte record, 8-byte start, residual
+ *          words, with the model the encoder chooses); after a merge the
+ *          merged partition tries its next neighbour, after a refusal the
+ *          neighbour becomes the current partition; passes repeat until one
+ *          merges nothing or max_passes have run.
  * col_dev: n values of dtype in device memory, aligned to the dtype.  On
  * success starts_host[0..m] holds the starts (starts_host[0] = 0,
  * starts_host[m] = n) and *m_out = m; LECO_ENOSPC if starts_cap < m + 1
@@ -309,13 +310,14 @@ typedef struct {
   double tau;          /* split threshold factor (the paper's range: 0..0.15) */
   uint64_t sm_bits;    /* model size S_M in bits (320: record + start)        */
   uint64_t max_len;    /* longest partition, 1..2^20                          */
-  uint64_t max_rounds; /* merge rounds at most (0: until none merges)         */
-  /* 1: the split also begins a partition at every starting position
-   * (section 3.2.2, selecting good starting positions): with rb_k =
-   * bitlen(|d_k|) + 1 the signed width of d_k = v_k - v_{k-1} and
-   * db_k = |rb_k - rb_{k-1}|, positions whose db is the column's smallest
-   * are good, and each maximal run k..k' of them is a starting partition
-   * v[k-2, k'+1) that begins a partition at k - 2.  0: plain split. */
+  uint64_t max_passes; /* merge passes at most (0: until one merges nothing)  */
+  /* 1: the split honours starting partitions (section 3.2.2, selecting good
+   * starting positions, for the linear regressor): with the second-order
+   * deltas dd_k = v_k - 2 v_{k-1} + v_{k-2}, each maximal run k..k' of
+   * positions whose |dd_k| is the column's smallest is a starting partition
+   * v[k-2, k'+1) (the later of two that would share a value keeps it); its
+   * first value begins a partition and its other values join it without
+   * the cost test (max_len still applies).  0: plain split. */
   int32_t start_positions;
   int32_t reserved;    /* must be 0 */
 } leco_partition_params;
@@ -426,6 +428,20 @@ typedef struct {
 typedef struct {
   uint64_t submitted, completed, steps, values_out, positions;
   uint64_t out_bytes_in_use, out_bytes_peak, queued;
+  uint64_t items; /* work items launched (workgroups of the step kernels) */
+  /* Host time of the request loop in nanoseconds: submission (checks,
+   * position copies, queueing), admission of queued requests into a step
+   * (under the server's lock), building the step's work items, launching it
+   * (work-item copy, kernel launch, events), retiring finished steps
+   * (event queries, completions), and the loop's waits for work or for a
+   * step to finish. */
+  uint64_t host_submit_ns, host_admit_ns, host_build_ns, host_launch_ns, host_retire_ns,
+      host_wait_ns;
+  /* Device time from timing events recorded around each step on its
+   * stream: the sum of the steps' durations, the time covered by at least
+   * one step (the union of their intervals) and the span from the earliest
+   * start to the latest end, in nanoseconds, over the steps retired. */
+  uint64_t gpu_step_ns, gpu_busy_ns, gpu_span_ns;
 } leco_server_stats;
 
 /* Starts the request loop (one host thread) over resident columns. [sync] */
@@ -453,6 +469,9 @@ leco_status leco_server_poll(leco_server *s, leco_completion *out, uint64_t max,
 /* Frees a completed request's result memory. */
 leco_status leco_server_release(leco_server *s, uint64_t ticket);
 leco_status leco_server_stats_get(leco_server *s, leco_server_stats *out);
+/* Zeroes the counters and timers above (not out_bytes_in_use or queued) and
+ * forgets the step intervals retired so far. */
+leco_status leco_server_stats_reset(leco_server *s);
 /* Waits for every admitted step, stops the loop and frees the server. */
 leco_status leco_server_stop(leco_server *s);
 
@@ -465,6 +484,22 @@ leco_status leco_server_stop(leco_server *s);
 leco_status leco_server_replay(leco_server *s, const leco_request *reqs,
                                const double *arrival_s, uint64_t n,
                                double *latency_us_out, double *elapsed_s);
+
+/* The plain path, the baseline the served loop is measured against: the
+ * same request stream replayed at arrival_s[i] seconds after the call
+ * (busy-waiting), each request as its own leco_random_access or
+ * leco_decode_range launch on `stream` (no batching, no overlap), in
+ * arrival order, with an event after each.  Requests are ranges or
+ * random-access batches with device positions (LECO_REQ_RANDOM_ACCESS_DEV)
+ * on cols_host[req.col]; every result goes to out_dev, which must hold the
+ * largest request's values (out_bytes; LECO_ENOSPC otherwise).
+ * latency_us_out[i] (may be null) receives the time from request i's
+ * scheduled arrival to the observed completion of its event; *elapsed_s
+ * the time from the first arrival to the last completion.  [sync] */
+leco_status leco_plain_replay(leco_ctx *ctx, const leco_resident_col *cols_host, uint64_t ncols,
+                              const leco_request *reqs, const double *arrival_s, uint64_t n,
+                              void *out_dev, uint64_t out_bytes, hipStream_t stream,
+                              double *latency_us_out, double *elapsed_s);
 
 /* ---- Diagnostics ------------------------------------------------------------
  * Evaluates the slope arithmetic of the encoder (section 3.1, least-squares

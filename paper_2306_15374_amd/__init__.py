@@ -31,7 +31,8 @@ EXPORTS = [
     "leco_batch_destroy", "leco_batch_run", "leco_batch_run_graph", "leco_batch_tune",
     "leco_batch_set_shape", "leco_server_start", "leco_server_submit", "leco_server_submit_batch",
     "leco_server_poll", "leco_server_release", "leco_server_stats_get", "leco_server_stop",
-    "leco_server_replay", "leco_partition", "leco_fixed_cost", "leco_size_search",
+    "leco_server_replay", "leco_server_stats_reset", "leco_plain_replay", "leco_partition",
+    "leco_fixed_cost", "leco_size_search",
 ]
 LECO_REQ_RANDOM_ACCESS, LECO_REQ_RANGE, LECO_REQ_RANDOM_ACCESS_DEV = 1, 2, 3
 LECO_BATCH_DECODE, LECO_BATCH_FILTER = 1, 2
@@ -45,7 +46,7 @@ class LecoError(RuntimeError):
 
 class PartitionParams(C.Structure):
     _fields_ = [("tau", C.c_double), ("sm_bits", C.c_uint64), ("max_len", C.c_uint64),
-                ("max_rounds", C.c_uint64), ("start_positions", C.c_int32),
+                ("max_passes", C.c_uint64), ("start_positions", C.c_int32),
                 ("reserved", C.c_int32)]
 
 
@@ -88,7 +89,9 @@ class Completion(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [(name, C.c_uint64) for name in
                 ("submitted", "completed", "steps", "values_out", "positions",
-                 "out_bytes_in_use", "out_bytes_peak", "queued")]
+                 "out_bytes_in_use", "out_bytes_peak", "queued", "items",
+                 "host_submit_ns", "host_admit_ns", "host_build_ns", "host_launch_ns",
+                 "host_retire_ns", "host_wait_ns", "gpu_step_ns", "gpu_busy_ns", "gpu_span_ns")]
 
 
 class Partitioning(C.Structure):
@@ -145,6 +148,8 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_server_stats_get": ([vp, P(ServerStats)], i32),
         "leco_server_stop": ([vp], i32),
         "leco_server_replay": ([vp, vp, vp, u64, vp, P(C.c_double)], i32),
+        "leco_server_stats_reset": ([vp], i32),
+        "leco_plain_replay": ([vp, vp, u64, vp, vp, u64, vp, u64, vp, vp, P(C.c_double)], i32),
         "leco_partition": ([vp, vp, u64, i32, P(PartitionParams), vp, u64, P(u64), vp], i32),
         "leco_fixed_cost": ([vp, vp, u64, i32, vp, u64, u64, u64, i32, P(u64), vp], i32),
         "leco_size_search": ([vp, vp, u64, i32, vp, u64, u64, i32, P(u64), P(u64), vp, u64,
@@ -368,6 +373,23 @@ def leco_server_stats_get(server: int) -> dict:
     return {name: getattr(s, name) for name, _ in ServerStats._fields_}
 
 
+def leco_server_stats_reset(server: int) -> int:
+    return lib().leco_server_stats_reset(server)
+
+
+def leco_plain_replay(ctx: int, cols, reqs, arrival_s, out, out_bytes: int, stream=None,
+                      latencies_out=None) -> tuple[int, float]:
+    """The plain one-launch-per-request path over the same request stream
+    (reqs: a ctypes Request array of ranges and device-position lookups)."""
+    arr = (ResidentCol * len(cols))(*cols)
+    el = C.c_double()
+    st = lib().leco_plain_replay(ctx, arr, len(cols), reqs, arrival_s.ctypes.data, len(arrival_s),
+                                 _ptr(out), out_bytes, _stream(stream),
+                                 None if latencies_out is None else latencies_out.ctypes.data,
+                                 C.byref(el))
+    return st, el.value
+
+
 def leco_server_stop(server: int) -> int:
     return lib().leco_server_stop(server)
 
@@ -457,11 +479,11 @@ class Codec:
         return buf[:size]
 
     def partition(self, col, tau: float = 0.1, sm_bits: int = 320, max_len: int = 1 << 20,
-                  max_rounds: int = 0, stream=None, start_positions: bool = False):
+                  max_passes: int = 0, stream=None, start_positions: bool = False):
         """Variable-length partition starts of a CUDA tensor column (numpy
         uint64 array of m + 1 starts)."""
         import numpy as np
-        params = PartitionParams(tau, sm_bits, max_len, max_rounds, int(start_positions), 0)
+        params = PartitionParams(tau, sm_bits, max_len, max_passes, int(start_positions), 0)
         # room for a mean partition length down to 16; a finer result is
         # computed again with the exact size
         cap = max(1024, col.numel() // 16 + 2)

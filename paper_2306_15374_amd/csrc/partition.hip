@@ -3,24 +3,30 @@
 // Split: the greedy of the paper, which includes the next value in the
 // current partition while the approximate cost of doing so,
 //   C = (len + 1) * D~new - len * D~old,  D~ = bitlen(max d - min d)
-// over the partition's first differences d, stays within tau * S_M.  A
-// partition begins at every multiple of 2^20 (the format's longest
-// partition), so each 2^20-value segment is split on its own.  Within a
-// segment, every 2^14-value sub-chunk is first split speculatively in
-// parallel, as if a partition began at its start; one wavefront per
-// segment then walks the sub-chunks in order from the true state, each
-// until the true run starts a partition where the speculative run did
+// over the partition's first differences d, stays within tau * S_M, and
+// the partition holds fewer than max_len values.  The column is cut into
+// 2^14-value sub-chunks that are first split speculatively in parallel, as
+// if a partition began at each one's start.  One wavefront per 2^20-value
+// segment then walks the segment's sub-chunks in order from the true state,
+// each until the true run starts a partition where the speculative run did
 // (from there on the two runs are the same), rewriting the starts it
-// passes.  The wavefront walks 64 candidates at a time (see greedy_walk).
-// This reproduces the sequential greedy exactly.  Optionally a partition
-// also begins at every starting position (section 3.2.2, selecting good
-// starting positions), marked in a bitmap before the split.
+// passes; a last wavefront does the same across segments, from the end
+// state of each segment to the next.  The wavefront walks 64 candidates at a
+// time (see greedy_walk).  This reproduces the sequential greedy exactly.
+// Optionally the split also honours starting partitions (section 3.2.2,
+// selecting good starting positions): runs of smallest second-order delta,
+// whose first value begins a partition and whose other values join it
+// without the cost test.
 //
-// Merge: rounds over adjacent pairs.  Every pair's union is sized with the
-// encoder's own fit (exact bytes: 32-byte record, 8-byte start, residual
-// words); a pair merges when its gain is positive and beats both
-// neighbouring pairs (equal gains: the even pair), so merged pairs never
-// overlap; rounds repeat until one merges nothing.
+// Merge: the paper's scan.  The current partition merges with its right
+// neighbour when the union (sized with the encoder's own fit: 32-byte
+// record, 8-byte start, residual words) is strictly smaller than the two
+// apart and fits max_len, and then tries the next neighbour; passes repeat
+// until one merges nothing.  The scan's state is the current partition
+// (its first index and size), and it is reset by every refused merge, so
+// the same speculation applies: chunks of the partition list are scanned
+// in parallel as if a partition began at each chunk's start, then walked in
+// order from the true state until both runs keep the same boundary.
 #include <math.h>
 
 #include <utility>
@@ -138,15 +144,19 @@ __device__ inline bool bit_set(unsigned long long* bitmap, uint64_t j) {
 // rewrites them until it starts a partition where the speculative run also
 // did (from there on both runs are the same), returning true at that point.
 //
-// forced (or null): bit j set means a partition begins at j (the first
-// value of a starting partition), whatever the cost.
+// forced and inside (both null, or both bitmaps over the column): bit j of
+// forced set means a partition begins at j (the first value of a starting
+// partition), whatever the cost; bit j of inside set means v[j] joins the
+// current partition without the cost test (a later value of a starting
+// partition).  The length cap applies to both.
 //
 // K: the key type, DKey for 64-bit columns, one 64-bit word for 32-bit ones.
 template <bool kFix, class K>
 __device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t p,
                             uint64_t b, double thr, uint64_t max_len, SplitState& st,
                             uint64_t* win, unsigned long long* __restrict__ bitmap,
-                            const uint64_t* __restrict__ forced) {
+                            const uint64_t* __restrict__ forced,
+                            const uint64_t* __restrict__ inside) {
   const uint32_t lane = threadIdx.x & 63;
   K kmin = key_from(static_cast<K*>(nullptr), st.kmin_hi, st.kmin_lo);
   K kmax = key_from(static_cast<K*>(nullptr), st.kmax_hi, st.kmax_lo);
@@ -190,7 +200,8 @@ __device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uin
     const uint64_t len = j - i;
     const int64_t cost = int64_t((len + 1) * w_new) - int64_t(len * w_prev);
     const bool start_here = forced && valid && ((forced[j >> 6] >> (j & 63)) & 1ull);
-    const bool include = double(cost) <= thr && len < max_len && !start_here;
+    const bool in_start = forced && valid && ((inside[j >> 6] >> (j & 63)) & 1ull);
+    const bool include = len < max_len && !start_here && (in_start || double(cost) <= thr);
     const uint64_t split = __ballot(valid && !include);
     if (split == 0) {
       const int last = int(b - p - 1 < 63 ? b - p - 1 : 63);
@@ -230,16 +241,17 @@ __device__ bool greedy_walk(const uint8_t* __restrict__ col, uint32_t dtype, uin
   return synced;
 }
 
-// Speculative split: one 64-lane workgroup per 2^kSubLog2-value sub-chunk
-// of a 2^20-value segment.  Sub-chunk 0 begins at the segment start, where
-// a partition really begins; the others begin a partition at their own
-// start, which the fix-up pass corrects.  Each records its final state.
+// Speculative split: one 64-lane workgroup per 2^kSubLog2-value sub-chunk.
+// Sub-chunk 0 of the column begins where a partition really begins; the
+// others begin a partition at their own start, which the fix-up passes
+// correct.  Each records its final state.
 __global__ __launch_bounds__(64) void k_split_spec(const uint8_t* __restrict__ col,
                                                    uint32_t dtype, uint64_t n, double thr,
                                                    uint64_t max_len,
                                                    unsigned long long* __restrict__ bitmap,
                                                    SplitState* __restrict__ states,
-                                                   const uint64_t* __restrict__ forced) {
+                                                   const uint64_t* __restrict__ forced,
+                                                   const uint64_t* __restrict__ inside) {
   __shared__ uint64_t win[kSplitWindow + 1];  // win[k] = v[base - 1 + k]
   const uint64_t a = uint64_t(blockIdx.x) << kSubLog2;
   if (a >= n) return;
@@ -247,94 +259,192 @@ __global__ __launch_bounds__(64) void k_split_spec(const uint8_t* __restrict__ c
   if (threadIdx.x == 0) mark(bitmap, a);
   SplitState st{a, 0, 0, 0, 0, 0, 0};
   if (dtype == 4)
-    greedy_walk<false, uint64_t>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap, forced);
+    greedy_walk<false, uint64_t>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap, forced,
+                                 inside);
   else
-    greedy_walk<false, DKey>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap, forced);
+    greedy_walk<false, DKey>(col, dtype, a + 1, b, thr, max_len, st, win, bitmap, forced, inside);
   if (threadIdx.x == 0) states[blockIdx.x] = st;
 }
 
-// Fix-up: one workgroup per 2^20-value segment walks its sub-chunks in
-// order, each from the true state the previous one ends in, until its
-// starts meet the speculative ones.
+// Walks sub-chunks [q, q_end) of the column in order from state st (fix
+// mode), each from the state the previous one ends in; returns at the
+// first sub-chunk where the walk meets the starts already there (st is
+// then that meeting's state, and the caller continues from the run already
+// recorded), or after the last one with st its end state.
+__device__ bool walk_subchunks(const uint8_t* col, uint32_t dtype, uint64_t n, double thr,
+                               uint64_t max_len, uint64_t q, uint64_t q_end, SplitState& st,
+                               uint64_t* win, unsigned long long* bitmap, const uint64_t* forced,
+                               const uint64_t* inside) {
+  for (; q < q_end; ++q) {
+    const uint64_t aq = q << kSubLog2;
+    if (aq >= n) break;
+    const uint64_t bq = n - aq < (uint64_t(1) << kSubLog2) ? n : aq + (uint64_t(1) << kSubLog2);
+    const bool synced =
+        dtype == 4
+            ? greedy_walk<true, uint64_t>(col, dtype, aq, bq, thr, max_len, st, win, bitmap, forced,
+                                          inside)
+            : greedy_walk<true, DKey>(col, dtype, aq, bq, thr, max_len, st, win, bitmap, forced,
+                                      inside);
+    if (synced) return true;
+  }
+  return false;
+}
+
+// Fix-up within segments: one workgroup per 2^20-value segment walks its
+// sub-chunks 1.. in order, each from the state the previous one ends in,
+// until its starts meet the speculative ones; the segment's end state (as
+// if a partition began at the segment start) goes to seg_states.
 __global__ __launch_bounds__(64) void k_split_fix(const uint8_t* __restrict__ col,
                                                   uint32_t dtype, uint64_t n, double thr,
                                                   uint64_t max_len,
                                                   unsigned long long* __restrict__ bitmap,
                                                   const SplitState* __restrict__ states,
-                                                  const uint64_t* __restrict__ forced) {
+                                                  SplitState* __restrict__ seg_states,
+                                                  const uint64_t* __restrict__ forced,
+                                                  const uint64_t* __restrict__ inside) {
   __shared__ uint64_t win[kSplitWindow + 1];
   constexpr uint64_t kSubs = uint64_t(1) << (kSegLog2 - kSubLog2);
   const uint64_t a = uint64_t(blockIdx.x) << kSegLog2;
   if (a >= n) return;
   const uint64_t q0 = uint64_t(blockIdx.x) * kSubs;
-  SplitState st = states[q0];  // sub-chunk 0 began where a partition begins
-  for (uint64_t q = 1; q < kSubs; ++q) {
-    const uint64_t aq = a + (q << kSubLog2);
-    if (aq >= n) break;
-    const uint64_t bq = n - aq < (uint64_t(1) << kSubLog2) ? n : aq + (uint64_t(1) << kSubLog2);
-    const bool synced =
-        dtype == 4
-            ? greedy_walk<true, uint64_t>(col, dtype, aq, bq, thr, max_len, st, win, bitmap, forced)
-            : greedy_walk<true, DKey>(col, dtype, aq, bq, thr, max_len, st, win, bitmap, forced);
-    if (synced) st = states[q0 + q];  // the speculative run's end state is the true one
+  const uint64_t nsub = (n + (uint64_t(1) << kSubLog2) - 1) >> kSubLog2;
+  const uint64_t q_end = q0 + kSubs < nsub ? q0 + kSubs : nsub;
+  SplitState st = states[q0];
+  for (uint64_t q = q0 + 1; q < q_end; ++q) {
+    // a meeting makes the rest of sub-chunk q the speculative run's
+    if (walk_subchunks(col, dtype, n, thr, max_len, q, q + 1, st, win, bitmap, forced, inside))
+      st = states[q];
+  }
+  if (threadIdx.x == 0) seg_states[blockIdx.x] = st;
+}
+
+// Fix-up across segments: one wavefront walks each segment from the true
+// state the previous segment ends in, until it meets the starts already
+// there (from then on the segment's run, and its end state, are right).
+__global__ __launch_bounds__(64) void k_split_join(const uint8_t* __restrict__ col,
+                                                   uint32_t dtype, uint64_t n, double thr,
+                                                   uint64_t max_len,
+                                                   unsigned long long* __restrict__ bitmap,
+                                                   const SplitState* __restrict__ seg_states,
+                                                   uint64_t nseg, const uint64_t* __restrict__ forced,
+                                                   const uint64_t* __restrict__ inside) {
+  __shared__ uint64_t win[kSplitWindow + 1];
+  constexpr uint64_t kSubs = uint64_t(1) << (kSegLog2 - kSubLog2);
+  const uint64_t nsub = (n + (uint64_t(1) << kSubLog2) - 1) >> kSubLog2;
+  SplitState st = seg_states[0];
+  for (uint64_t g = 1; g < nseg; ++g) {
+    const uint64_t q0 = g * kSubs, q_end = q0 + kSubs < nsub ? q0 + kSubs : nsub;
+    if (walk_subchunks(col, dtype, n, thr, max_len, q0, q_end, st, win, bitmap, forced, inside))
+      st = seg_states[g];
   }
 }
 
-// ---- starting positions ----------------------------------------------------------
+// ---- starting partitions ---------------------------------------------------------
 //
-// Required bits rb_k = bitlen(|d_k|) + 1 of the first difference
-// d_k = v_k - v_{k-1} (k >= 1), delta bits db_k = |rb_k - rb_{k-1}|
-// (k >= 2); positions whose db is the column's smallest are good, and a
-// partition begins two values before the first of every run of good
-// positions (section 3.2.2, selecting good starting positions).
+// Second-order deltas dd_k = v_k - 2 v_{k-1} + v_{k-2} (k >= 2, exact in
+// 128 bits, |dd| < 2^66).  Positions whose |dd| is the column's smallest
+// are good; a maximal run k..k' of them is the starting partition
+// v[k-2, k'+1), and of two that would share a value the later keeps it
+// (section 3.2.2, selecting good starting positions, for a degree-1 model).
 
-__device__ inline uint32_t required_bits(const uint8_t* col, uint32_t dtype, uint64_t k) {
-  const uint64_t a = load_value(col, dtype, k), b = load_value(col, dtype, k - 1);
-  return bitlen64(a >= b ? a - b : b - a) + 1;
+typedef unsigned __int128 u128_t;
+
+__device__ inline u128_t dd_magnitude(const uint8_t* col, uint32_t dtype, uint64_t k) {
+  const __int128 a = __int128(load_value(col, dtype, k));
+  const __int128 b = __int128(load_value(col, dtype, k - 1));
+  const __int128 c = __int128(load_value(col, dtype, k - 2));
+  const __int128 dd = a - 2 * b + c;
+  return dd < 0 ? u128_t(-dd) : u128_t(dd);
 }
 
-__device__ inline uint32_t delta_bits(const uint8_t* col, uint32_t dtype, uint64_t k) {
-  const uint32_t x = required_bits(col, dtype, k), y = required_bits(col, dtype, k - 1);
-  return x > y ? x - y : y - x;
+__device__ inline u128_t wave_min_u128(u128_t x) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t lo = uint64_t(__shfl_xor(static_cast<unsigned long long>(uint64_t(x)), off, 64));
+    const uint64_t hi =
+        uint64_t(__shfl_xor(static_cast<unsigned long long>(uint64_t(x >> 64)), off, 64));
+    const u128_t y = (u128_t(hi) << 64) | lo;
+    x = y < x ? y : x;
+  }
+  return x;
 }
 
-// *min_db = the smallest db_k over k = 2 .. n-1 (it starts at ~0).
-__global__ __launch_bounds__(kScanBlock) void k_delta_bits_min(const uint8_t* __restrict__ col,
-                                                               uint32_t dtype, uint64_t n,
-                                                               uint32_t* __restrict__ min_db) {
-  uint32_t best = ~0u;
+// partial[block] = the smallest |dd_k| over the block's grid-stride share of
+// k = 2 .. n-1 (all ones when it has none), as (low, high) words.
+__global__ __launch_bounds__(kScanBlock) void k_dd_min(const uint8_t* __restrict__ col,
+                                                      uint32_t dtype, uint64_t n,
+                                                      uint64_t* __restrict__ partial) {
+  __shared__ uint64_t red[kScanBlock / 64][2];
+  u128_t best = ~u128_t(0);
   for (uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x + 2; k < n;
        k += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t db = delta_bits(col, dtype, k);
-    best = db < best ? db : best;
+    const u128_t x = dd_magnitude(col, dtype, k);
+    best = x < best ? x : best;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t o = uint32_t(__shfl_xor(int(best), off, 64));
-    best = o < best ? o : best;
+  best = wave_min_u128(best);
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wave][0] = uint64_t(best);
+    red[wave][1] = uint64_t(best >> 64);
   }
-  if ((threadIdx.x & 63) == 0 && best != ~0u) atomicMin(min_db, best);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < kScanBlock / 64; ++w) {
+      const u128_t y = (u128_t(red[w][1]) << 64) | red[w][0];
+      best = y < best ? y : best;
+    }
+    partial[2 * blockIdx.x] = uint64_t(best);
+    partial[2 * blockIdx.x + 1] = uint64_t(best >> 64);
+  }
 }
 
-// forced[w] bit l: a partition begins at p = 64 w + l, i.e. position p + 2
-// is good and p + 1 is not.  One lane per position; the wavefront's ballot
-// is the word.
-__global__ __launch_bounds__(kScanBlock) void k_mark_starts(const uint8_t* __restrict__ col,
-                                                            uint32_t dtype, uint64_t n,
-                                                            const uint32_t* __restrict__ min_db,
-                                                            uint64_t* __restrict__ forced) {
-  const uint32_t best = *min_db;
+// out[0..1] = the smallest of `count` partial minima (one wavefront).
+__global__ __launch_bounds__(64) void k_dd_min_final(const uint64_t* __restrict__ partial,
+                                                    uint64_t count, uint64_t* __restrict__ out) {
+  u128_t best = ~u128_t(0);
+  for (uint64_t i = threadIdx.x; i < count; i += 64) {
+    const u128_t y = (u128_t(partial[2 * i + 1]) << 64) | partial[2 * i];
+    best = y < best ? y : best;
+  }
+  best = wave_min_u128(best);
+  if (threadIdx.x == 0) {
+    out[0] = uint64_t(best);
+    out[1] = uint64_t(best >> 64);
+  }
+}
+
+// good(k): k >= 2 and |dd_k| is the smallest.
+__device__ inline bool dd_good(const uint8_t* col, uint32_t dtype, uint64_t n, uint64_t k,
+                               u128_t best) {
+  return k >= 2 && k < n && dd_magnitude(col, dtype, k) == best;
+}
+
+// first[w] bit l: value p = 64 w + l begins a starting partition (p + 2 is
+// good, p + 1 is not); inside[w] bit l: p is a later value of one (p or
+// p + 1 is good, and p does not begin one).  One lane per value; the
+// wavefront's ballots are the words.
+__global__ __launch_bounds__(kScanBlock) void k_mark_starting(const uint8_t* __restrict__ col,
+                                                             uint32_t dtype, uint64_t n,
+                                                             const uint64_t* __restrict__ best_dd,
+                                                             uint64_t* __restrict__ first,
+                                                             uint64_t* __restrict__ inside) {
+  const u128_t best = (u128_t(best_dd[1]) << 64) | best_dd[0];
   const uint64_t nwords = (n + 63) / 64;
   for (uint64_t p0 = (uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u));
        p0 < nwords * 64; p0 += uint64_t(gridDim.x) * blockDim.x) {
     const uint64_t p = p0 + (threadIdx.x & 63);
-    bool start = false;
-    if (p + 2 < n) {
-      const bool good_next = delta_bits(col, dtype, p + 2) == best;
-      const bool good_here = p >= 1 && delta_bits(col, dtype, p + 1) == best;
-      start = good_next && !good_here;
+    bool begins = false, in = false;
+    if (p < n) {
+      const bool g0 = dd_good(col, dtype, n, p, best);
+      const bool g1 = dd_good(col, dtype, n, p + 1, best);
+      const bool g2 = dd_good(col, dtype, n, p + 2, best);
+      begins = g2 && !g1;
+      in = !begins && (g0 || g1);
     }
-    const uint64_t word = __ballot(start);
-    if ((threadIdx.x & 63) == 0) forced[p0 >> 6] = word;
+    const uint64_t wb = __ballot(begins), wi = __ballot(in);
+    if ((threadIdx.x & 63) == 0) {
+      first[p0 >> 6] = wb;
+      inside[p0 >> 6] = wi;
+    }
   }
 }
 
@@ -666,96 +776,251 @@ __global__ __launch_bounds__(kEncBlock) void k_costs_long(const uint8_t* __restr
   }
 }
 
-// ---- merge rounds ----------------------------------------------------------------
+// ---- merge scan -------------------------------------------------------------------
+//
+// Boundary k (1 <= k < m) is the start of partition k.  Step k of a pass
+// tries to merge the current partition, which begins at boundary a (a < k)
+// and costs cc bytes, with partition k:
+//   union = pair[k - 1] when a = k - 1 (two unmerged partitions, sized in
+//           advance), else the size of v[s[a], s[k+1]) fitted now; none
+//           when longer than max_len;
+//   merge when union < cc + cost[k]: the current partition grows (cc =
+//   union); else boundary k is kept, and partition k is the current one
+//   (a = k, cc = cost[k]).
+// The pass keeps a bitmap of kept boundaries (bit 0 always set) and, for a
+// current partition that absorbed others, its size in pcost[a] when it
+// closes.
 
-__device__ inline int64_t pair_gain(const uint64_t* cost, const uint64_t* pair, uint64_t j) {
-  return pair[j] == kNoMerge ? 0 : int64_t(cost[j] + cost[j + 1]) - int64_t(pair[j]);
+constexpr uint32_t kMergeChunkLog2 = 8;  // boundaries per speculative chunk
+constexpr uint64_t kMergeChunk = uint64_t(1) << kMergeChunkLog2;
+constexpr uint64_t kMergeGroup = 64;     // chunks per first-level fix-up walk
+
+struct MergeState {
+  uint64_t a;   // boundary where the current partition begins
+  uint64_t cc;  // its size in bytes
+};
+
+__device__ inline void set_bits(unsigned long long* bits, uint64_t k, uint64_t mask) {
+  const uint64_t w = k >> 6, off = k & 63;
+  atomicOr(bits + w, static_cast<unsigned long long>(mask << off));
+  if (off && (mask >> (64 - off))) atomicOr(bits + w + 1, static_cast<unsigned long long>(mask >> (64 - off)));
 }
 
-// key(j) > key(k): larger gain, or the same gain and j even.
-__device__ inline bool beats(int64_t gj, int64_t gk, uint64_t j) {
-  return gj > gk || (gj == gk && (j & 1) == 0);
+__device__ inline void clear_bit(unsigned long long* bits, uint64_t k) {
+  atomicAnd(bits + (k >> 6), ~(1ull << (k & 63)));
 }
 
-// take[j] = 1 when pair j merges this round (j < m - 1); counts the merges.
-__global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ cost,
-                                                const uint64_t* __restrict__ pair, uint64_t m,
-                                                uint8_t* __restrict__ take,
-                                                unsigned long long* __restrict__ merges) {
-  // A grid-stride loop with every load of a pair's test issued at once (the
-  // neighbours' indices clamped, their result then ignored): one round trip
-  // per pair instead of six dependent ones, and far fewer workgroups to
-  // dispatch.
-  uint32_t taken = 0;
-  for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j + 1 < m;
-       j += uint64_t(gridDim.x) * blockDim.x) {
-    const bool has_left = j > 0, has_right = j + 2 < m;
-    const uint64_t jl = has_left ? j - 1 : j, jr = has_right ? j + 1 : j;
-    const uint64_t p_l = pair[jl], p_c = pair[j], p_r = pair[jr];
-    const uint64_t c_l = cost[jl], c_c = cost[j], c_n = cost[j + 1], c_r = cost[jr + 1];
-    auto gain = [](uint64_t p, uint64_t a, uint64_t b) {
-      return p == kNoMerge ? int64_t(0) : int64_t(a + b) - int64_t(p);
-    };
-    const int64_t g = gain(p_c, c_c, c_n);
-    bool t = g > 0;
-    if (t && has_left) t = beats(g, gain(p_l, c_l, c_c), j);
-    if (t && has_right) t = beats(g, gain(p_r, c_n, c_r), j);
-    take[j] = t ? 1 : 0;
-    taken += t ? 1u : 0u;
+// Runs steps [kb, ke) from state st.  kFix = false: the bitmap holds zeros
+// there and the walk sets the kept bits.  kFix = true: the bits are another
+// run's, made from a different state; the walk rewrites them until it keeps
+// a boundary that run also kept (from there on both runs are the same) and
+// returns true at that point.  Called by a whole wavefront.
+template <bool kFix>
+__device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
+                           const uint64_t* __restrict__ s, const uint64_t* __restrict__ cost,
+                           const uint64_t* __restrict__ pair, uint64_t max_len, uint64_t kb,
+                           uint64_t ke, MergeState& st, unsigned long long* __restrict__ keep,
+                           uint64_t* __restrict__ pcost) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t k = kb;
+  while (k < ke) {
+    if (st.a + 1 == k) {
+      // No merge pending: the next 64 steps are decided from the sizes
+      // known in advance, each as if the steps before it kept their
+      // boundary; the first merge (or meeting) ends the batch.
+      const uint64_t kk = k + lane;
+      const bool valid = kk < ke;
+      bool merge = false, met = false;
+      if (valid) {
+        const uint64_t u = pair[kk - 1];
+        merge = u != kNoMerge && u < cost[kk - 1] + cost[kk];
+        if (kFix && !merge) met = bit_set(keep, kk);
+      }
+      const uint64_t vmask = __ballot(valid), mmask = __ballot(merge),
+                     smask = kFix ? __ballot(met) : 0;
+      const int fm = mmask ? __ffsll(static_cast<long long>(mmask)) - 1 : 64;
+      const int fs = smask ? __ffsll(static_cast<long long>(smask)) - 1 : 64;
+      const int stop = fm < fs ? fm : fs;
+      const uint64_t kept = stop >= 64 ? vmask : vmask & ((1ull << stop) - 1);
+      if (lane == 0 && kept) set_bits(keep, k, kept);
+      if (fs < fm) return true;  // kFix: both runs keep boundary k + fs
+      if (fm == 64) {            // every valid step kept its boundary
+        const uint64_t last = uint64_t(63 - __clzll(static_cast<long long>(vmask)));
+        st.a = k + last;
+        st.cc = cost[st.a];
+        k += last + 1;
+        continue;
+      }
+      const uint64_t km = k + uint64_t(fm);
+      if (kFix && lane == 0) clear_bit(keep, km);
+      st.a = km - 1;
+      st.cc = pair[km - 1];
+      k = km + 1;
+      continue;
+    }
+    // The current partition absorbed others: size its union with partition
+    // k now, with the encoder's fit.
+    const uint64_t lo = s[st.a], hi = s[k + 1], ck = cost[k];
+    const uint64_t u = hi - lo <= max_len ? range_cost_wave(col, dtype, lo, hi) : kNoMerge;
+    if (u != kNoMerge && u < st.cc + ck) {
+      if (kFix && lane == 0) clear_bit(keep, k);
+      st.cc = u;
+      ++k;
+      continue;
+    }
+    bool met = false;
+    if (lane == 0) {
+      pcost[st.a] = st.cc;
+      if (kFix) met = bit_set(keep, k);
+      if (!met) set_bits(keep, k, 1);
+    }
+    met = __ballot(met) != 0;
+    st.a = k;
+    st.cc = ck;
+    ++k;
+    if (met) return true;
   }
-  // one atomic per wavefront
-  for (int off = 32; off > 0; off >>= 1) taken += uint32_t(__shfl_xor(int(taken), off, 64));
-  if ((threadIdx.x & 63) == 0 && taken) atomicAdd(merges, static_cast<unsigned long long>(taken));
+  return false;
 }
 
-// Partition k survives unless the pair (k - 1, k) merged.
-__device__ inline uint32_t kept(const uint8_t* take, uint64_t k, uint64_t m) {
-  return k < m && (k == 0 || !take[k - 1]) ? 1u : 0u;
+// Speculative pass: one wavefront per chunk of kMergeChunk boundaries,
+// scanned as if its first boundary were kept (chunk 0 from the true start);
+// each chunk's end state goes to states.
+__global__ __launch_bounds__(kEncBlock) void k_merge_spec(
+    const uint8_t* __restrict__ col, uint32_t dtype, const uint64_t* __restrict__ s,
+    const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair, uint64_t m,
+    uint64_t max_len, unsigned long long* __restrict__ keep, uint64_t* __restrict__ pcost,
+    MergeState* __restrict__ states) {
+  const uint64_t q = uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6);
+  const uint64_t k0 = q << kMergeChunkLog2;
+  if (k0 >= m) return;
+  const uint64_t ke = m - k0 < kMergeChunk ? m : k0 + kMergeChunk;
+  MergeState st;
+  uint64_t kb = k0;
+  if (q == 0) {
+    if ((threadIdx.x & 63) == 0) set_bits(keep, 0, 1);
+    st = MergeState{0, cost[0]};
+    kb = 1;
+  } else {
+    st = MergeState{k0 - 1, cost[k0 - 1]};
+  }
+  merge_walk<false>(col, dtype, s, cost, pair, max_len, kb, ke, st, keep, pcost);
+  if ((threadIdx.x & 63) == 0) states[q] = st;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_keep_count(const uint8_t* __restrict__ take,
-                                                           uint64_t m,
-                                                           uint64_t* __restrict__ counts) {
-  const uint64_t k0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
+// Walks chunks [q, q_end) in order from state st (fix mode); returns true
+// at the first meeting (the rest of that chunk, and of the run, is then the
+// recorded one), else false with st the state after the last chunk.
+__device__ bool walk_chunks(const uint8_t* col, uint32_t dtype, const uint64_t* s,
+                            const uint64_t* cost, const uint64_t* pair, uint64_t m,
+                            uint64_t max_len, uint64_t q, uint64_t q_end, MergeState& st,
+                            unsigned long long* keep, uint64_t* pcost) {
+  for (; q < q_end; ++q) {
+    const uint64_t kb = q << kMergeChunkLog2;
+    if (kb >= m) break;
+    const uint64_t ke = m - kb < kMergeChunk ? m : kb + kMergeChunk;
+    if (merge_walk<true>(col, dtype, s, cost, pair, max_len, kb, ke, st, keep, pcost)) return true;
+  }
+  return false;
+}
+
+// First-level fix-up: one wavefront per group of kMergeGroup chunks walks
+// chunks 1.. of its group in order from the state the previous chunk ends
+// in; the group's end state (as if its first chunk began as assumed) goes
+// to gstates.
+__global__ __launch_bounds__(64) void k_merge_fix(
+    const uint8_t* __restrict__ col, uint32_t dtype, const uint64_t* __restrict__ s,
+    const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair, uint64_t m,
+    uint64_t max_len, unsigned long long* __restrict__ keep, uint64_t* __restrict__ pcost,
+    const MergeState* __restrict__ states, uint64_t nchunks, MergeState* __restrict__ gstates) {
+  const uint64_t q0 = uint64_t(blockIdx.x) * kMergeGroup;
+  if (q0 >= nchunks) return;
+  const uint64_t q_end = q0 + kMergeGroup < nchunks ? q0 + kMergeGroup : nchunks;
+  MergeState st = states[q0];
+  for (uint64_t q = q0 + 1; q < q_end; ++q)
+    if (walk_chunks(col, dtype, s, cost, pair, m, max_len, q, q + 1, st, keep, pcost))
+      st = states[q];
+  if (threadIdx.x == 0) gstates[blockIdx.x] = st;
+}
+
+// Second-level fix-up: one wavefront walks each group from the true state
+// the previous group ends in, until it meets the recorded run; then records
+// the size of the last partition.
+__global__ __launch_bounds__(64) void k_merge_join(
+    const uint8_t* __restrict__ col, uint32_t dtype, const uint64_t* __restrict__ s,
+    const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair, uint64_t m,
+    uint64_t max_len, unsigned long long* __restrict__ keep, uint64_t* __restrict__ pcost,
+    const MergeState* __restrict__ gstates, uint64_t nchunks) {
+  const uint64_t ngroups = (nchunks + kMergeGroup - 1) / kMergeGroup;
+  MergeState st = gstates[0];
+  for (uint64_t g = 1; g < ngroups; ++g) {
+    const uint64_t q0 = g * kMergeGroup;
+    const uint64_t q_end = q0 + kMergeGroup < nchunks ? q0 + kMergeGroup : nchunks;
+    if (walk_chunks(col, dtype, s, cost, pair, m, max_len, q0, q_end, st, keep, pcost))
+      st = gstates[g];
+  }
+  if (threadIdx.x == 0) pcost[st.a] = st.cc;
+}
+
+// ---- compaction after a pass --------------------------------------------------------
+
+__device__ inline uint32_t kept_bit(const unsigned long long* keep, uint64_t k, uint64_t m) {
+  return k < m && ((keep[k >> 6] >> (k & 63)) & 1ull) ? 1u : 0u;
+}
+
+// Kept boundaries in words [blockIdx * 1024, +1024) of the bitmap.
+__global__ __launch_bounds__(kScanBlock) void k_keep_count(const unsigned long long* __restrict__ keep,
+                                                           uint64_t m, uint64_t* __restrict__ counts) {
+  const uint64_t nwords = (m + 63) / 64;
+  const uint64_t w0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
   uint32_t c = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) c += kept(take, k0 + q, m);
+  for (int q = 0; q < 4; ++q) {
+    const uint64_t w = w0 + q;
+    if (w < nwords) {
+      uint64_t x = keep[w];
+      if ((w + 1) * 64 > m) x &= (m & 63) ? ((1ull << (m & 63)) - 1) : ~0ull;
+      c += uint32_t(__popcll(x));
+    }
+  }
   uint32_t total;
   block_exclusive_scan(c, &total);
   if (threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
-// Copies the surviving starts (and their costs: a merged pair's union cost
-// for the partition that absorbed its neighbour) to their new places.
+// Copies the kept starts to their new places with their sizes (the size
+// recorded at close for a partition that absorbed others, its own
+// otherwise), whether it absorbed others, and its old index.
 __global__ __launch_bounds__(kScanBlock) void k_keep_emit(
-    const uint8_t* __restrict__ take, uint64_t m, const uint64_t* __restrict__ offsets,
+    const unsigned long long* __restrict__ keep, uint64_t m, const uint64_t* __restrict__ offsets,
     const uint64_t* __restrict__ starts, const uint64_t* __restrict__ cost,
-    const uint64_t* __restrict__ pair, uint64_t* __restrict__ starts_out,
+    const uint64_t* __restrict__ pcost, uint64_t* __restrict__ starts_out,
     uint64_t* __restrict__ cost_out, uint8_t* __restrict__ changed_out,
     uint64_t* __restrict__ old_out) {
-  const uint64_t k0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
+  const uint64_t w0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
   uint32_t c = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) c += kept(take, k0 + q, m);
+  for (int q = 0; q < 4; ++q)
+    for (uint64_t k = (w0 + q) * 64; k < (w0 + q + 1) * 64 && k < m; ++k) c += kept_bit(keep, k, m);
   uint32_t total;
   uint64_t out = offsets[blockIdx.x] + block_exclusive_scan(c, &total);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const uint64_t k = k0 + q;
-    if (!kept(take, k, m)) continue;
-    const bool absorbed = k + 1 < m && take[k];
-    starts_out[out] = starts[k];
-    cost_out[out] = absorbed ? pair[k] : cost[k];
-    changed_out[out] = absorbed ? 1 : 0;
-    old_out[out] = k;
-    ++out;
+    for (uint64_t k = (w0 + q) * 64; k < (w0 + q + 1) * 64 && k < m; ++k) {
+      if (!kept_bit(keep, k, m)) continue;
+      const bool absorbed = k + 1 < m && !kept_bit(keep, k + 1, m);
+      starts_out[out] = starts[k];
+      cost_out[out] = absorbed ? pcost[k] : cost[k];
+      changed_out[out] = absorbed ? 1 : 0;
+      old_out[out] = k;
+      ++out;
+    }
   }
 }
 
-// After a round: the pair (k, k+1) of the new partitions keeps its union
-// cost when neither partition absorbed a neighbour (they were adjacent
-// before, as old partitions old[k] and old[k] + 1); the others are marked
-// for sizing.
+// After a pass: the pair (k, k+1) of the new partitions keeps its union
+// size when neither absorbed a neighbour (they were adjacent before, as old
+// partitions old[k] and old[k] + 1); the others are marked for sizing.
 __global__ void k_pair_reuse(uint64_t m, const uint8_t* __restrict__ changed,
                              const uint64_t* __restrict__ old, const uint64_t* __restrict__ pair,
                              uint64_t* __restrict__ pair_out, uint8_t* __restrict__ dirty) {
@@ -854,30 +1119,39 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   if (!buf.alloc(&bitmap, nwords)) return pfail(ctx, LECO_ENOMEM, "partition: bitmap");
   P_TRY(hipMemsetAsync(bitmap, 0, 8 * nwords, stream));
   const uint64_t nsub = (n + (uint64_t(1) << leco::kSubLog2) - 1) >> leco::kSubLog2;
-  leco::SplitState* states = nullptr;
-  if (!buf.alloc(&states, nsub)) return pfail(ctx, LECO_ENOMEM, "partition: split states");
-  // starting positions: a bitmap of forced partition starts
-  uint64_t* forced = nullptr;
+  leco::SplitState *states = nullptr, *seg_states = nullptr;
+  if (!buf.alloc(&states, nsub) || !buf.alloc(&seg_states, nseg))
+    return pfail(ctx, LECO_ENOMEM, "partition: split states");
+  // starting partitions: bitmaps of their first and later values
+  uint64_t *first = nullptr, *inside = nullptr;
   if (prm->start_positions) {
-    uint32_t* min_db = nullptr;
-    if (!buf.alloc(&forced, nwords) || !buf.alloc(&min_db, 1))
-      return pfail(ctx, LECO_ENOMEM, "partition: starting positions");
-    P_TRY(hipMemsetAsync(min_db, 0xff, sizeof(uint32_t), stream));
     const uint64_t cap = uint64_t(ctx->num_cus) * 8;
-    const uint64_t gd = (n + leco::kScanBlock - 1) / leco::kScanBlock;
-    hipLaunchKernelGGL(leco::k_delta_bits_min, dim3(uint32_t(gd < cap ? gd : cap)),
-                       dim3(leco::kScanBlock), 0, stream, col, w, n, min_db);
+    const uint64_t gd0 = (n + leco::kScanBlock - 1) / leco::kScanBlock;
+    const uint64_t gd = gd0 < cap ? gd0 : cap;
+    uint64_t *partial = nullptr, *best = nullptr;
+    if (!buf.alloc(&first, nwords) || !buf.alloc(&inside, nwords) ||
+        !buf.alloc(&partial, 2 * gd) || !buf.alloc(&best, 2))
+      return pfail(ctx, LECO_ENOMEM, "partition: starting partitions");
+    hipLaunchKernelGGL(leco::k_dd_min, dim3(uint32_t(gd)), dim3(leco::kScanBlock), 0, stream, col,
+                       w, n, partial);
     P_TRY(hipGetLastError());
-    hipLaunchKernelGGL(leco::k_mark_starts, dim3(uint32_t(gd < cap ? gd : cap)),
-                       dim3(leco::kScanBlock), 0, stream, col, w, n, min_db, forced);
+    hipLaunchKernelGGL(leco::k_dd_min_final, dim3(1), dim3(64), 0, stream, partial, gd, best);
+    P_TRY(hipGetLastError());
+    hipLaunchKernelGGL(leco::k_mark_starting, dim3(uint32_t(gd)), dim3(leco::kScanBlock), 0, stream,
+                       col, w, n, best, first, inside);
     P_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(leco::k_split_spec, dim3(uint32_t(nsub)), dim3(64), 0, stream, col, w, n,
-                     thr, prm->max_len, bitmap, states, forced);
+                     thr, prm->max_len, bitmap, states, first, inside);
   P_TRY(hipGetLastError());
   hipLaunchKernelGGL(leco::k_split_fix, dim3(uint32_t(nseg)), dim3(64), 0, stream, col, w, n, thr,
-                     prm->max_len, bitmap, states, forced);
+                     prm->max_len, bitmap, states, seg_states, first, inside);
   P_TRY(hipGetLastError());
+  if (nseg > 1) {
+    hipLaunchKernelGGL(leco::k_split_join, dim3(1), dim3(64), 0, stream, col, w, n, thr,
+                       prm->max_len, bitmap, seg_states, nseg, first, inside);
+    P_TRY(hipGetLastError());
+  }
 
   // starts from the bitmap
   const uint64_t nb = (nwords + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
@@ -889,22 +1163,27 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   uint64_t m = 0;
   P_TRY(scan_counts(counts, nb, &m, stream));
   uint64_t *starts = nullptr, *starts2 = nullptr, *cost = nullptr, *cost2 = nullptr,
-           *pair = nullptr, *pair2 = nullptr, *old = nullptr, *keep_counts = nullptr;
-  uint8_t *take = nullptr, *changed = nullptr, *dirty = nullptr;
-  unsigned long long* merges = nullptr;
-  const uint64_t nbk = (m + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
+           *pair = nullptr, *pair2 = nullptr, *old = nullptr, *keep_counts = nullptr,
+           *pcost = nullptr;
+  uint8_t *changed = nullptr, *dirty = nullptr;
+  unsigned long long* keep = nullptr;
+  leco::MergeState *mstates = nullptr, *gstates = nullptr;
+  const uint64_t kwords = (m + 63) / 64;
+  const uint64_t nbk = (kwords + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
+  const uint64_t nchunks0 = (m + leco::kMergeChunk - 1) / leco::kMergeChunk;
+  const uint64_t ngroups0 = (nchunks0 + leco::kMergeGroup - 1) / leco::kMergeGroup;
   if (!buf.alloc(&starts, m + 1) || !buf.alloc(&starts2, m + 1) || !buf.alloc(&cost, m) ||
       !buf.alloc(&cost2, m) || !buf.alloc(&pair, m) || !buf.alloc(&pair2, m) ||
-      !buf.alloc(&old, m) || !buf.alloc(&take, m) || !buf.alloc(&changed, m) ||
-      !buf.alloc(&dirty, m) ||
-      !buf.alloc(&keep_counts, nbk) || !buf.alloc(&merges, 1))
+      !buf.alloc(&old, m) || !buf.alloc(&pcost, m) || !buf.alloc(&changed, m) ||
+      !buf.alloc(&dirty, m) || !buf.alloc(&keep, kwords) || !buf.alloc(&keep_counts, nbk) ||
+      !buf.alloc(&mstates, nchunks0) || !buf.alloc(&gstates, ngroups0))
     return pfail(ctx, LECO_ENOMEM, "partition: partition arrays");
   hipLaunchKernelGGL(leco::k_bitmap_emit, dim3(uint32_t(nb)), dim3(leco::kScanBlock), 0, stream,
                      reinterpret_cast<const uint64_t*>(bitmap), nwords, counts, starts);
   P_TRY(hipGetLastError());
   P_TRY(hipMemcpyAsync(starts + m, &n, 8, hipMemcpyHostToDevice, stream));
 
-  // merge rounds
+  // merge passes
   const uint64_t grid_cap = uint64_t(ctx->num_cus) * 16;
   auto costs = [&](const uint64_t* s, uint64_t count, uint32_t span, const uint8_t* dirty,
                    uint64_t* out) {
@@ -938,30 +1217,37 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   };
   P_TRY(costs(starts, m, 1, nullptr, cost));
   if (m >= 2) P_TRY(costs(starts, m - 1, 2, nullptr, pair));
-  for (uint64_t round = 0; prm->max_rounds == 0 || round < prm->max_rounds; ++round) {
+  for (uint64_t pass = 0; prm->max_passes == 0 || pass < prm->max_passes; ++pass) {
     if (m < 2) break;
-    P_TRY(hipMemsetAsync(merges, 0, 8, stream));
-    const uint64_t gsel = (m - 1 + 255) / 256;
-    hipLaunchKernelGGL(leco::k_select, dim3(uint32_t(gsel < grid_cap ? gsel : grid_cap)),
-                       dim3(256), 0, stream, cost, pair, m, take, merges);
+    const uint64_t words = (m + 63) / 64;
+    const uint64_t nchunks = (m + leco::kMergeChunk - 1) / leco::kMergeChunk;
+    const uint64_t ngroups = (nchunks + leco::kMergeGroup - 1) / leco::kMergeGroup;
+    P_TRY(hipMemsetAsync(keep, 0, 8 * words, stream));
+    hipLaunchKernelGGL(leco::k_merge_spec,
+                       dim3(uint32_t((nchunks + leco::kEncWaves - 1) / leco::kEncWaves)),
+                       dim3(leco::kEncBlock), 0, stream, col, w, starts, cost, pair, m,
+                       prm->max_len, keep, pcost, mstates);
     P_TRY(hipGetLastError());
-    unsigned long long merged = 0;
-    P_TRY(hipMemcpyAsync(&merged, merges, 8, hipMemcpyDeviceToHost, stream));
-    P_TRY(hipStreamSynchronize(stream));
-    if (merged == 0) break;
-    const uint64_t blocks = (m + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
+    hipLaunchKernelGGL(leco::k_merge_fix, dim3(uint32_t(ngroups)), dim3(64), 0, stream, col, w,
+                       starts, cost, pair, m, prm->max_len, keep, pcost, mstates, nchunks, gstates);
+    P_TRY(hipGetLastError());
+    hipLaunchKernelGGL(leco::k_merge_join, dim3(1), dim3(64), 0, stream, col, w, starts, cost,
+                       pair, m, prm->max_len, keep, pcost, gstates, nchunks);
+    P_TRY(hipGetLastError());
+    const uint64_t blocks = (words + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
     hipLaunchKernelGGL(leco::k_keep_count, dim3(uint32_t(blocks)), dim3(leco::kScanBlock), 0,
-                       stream, take, m, keep_counts);
+                       stream, keep, m, keep_counts);
     P_TRY(hipGetLastError());
     uint64_t m2 = 0;
     P_TRY(scan_counts(keep_counts, blocks, &m2, stream));
+    if (m2 == m) break;  // the pass merged nothing
     hipLaunchKernelGGL(leco::k_keep_emit, dim3(uint32_t(blocks)), dim3(leco::kScanBlock), 0,
-                       stream, take, m, keep_counts, starts, cost, pair, starts2, cost2, changed,
+                       stream, keep, m, keep_counts, starts, cost, pcost, starts2, cost2, changed,
                        old);
     P_TRY(hipGetLastError());
     P_TRY(hipMemcpyAsync(starts2 + m2, &n, 8, hipMemcpyHostToDevice, stream));
     if (m2 >= 2) {
-      // pair costs for the next round: reused, or sized where a merge happened
+      // pair sizes for the next pass: reused, or sized where a merge happened
       hipLaunchKernelGGL(leco::k_pair_reuse, dim3(uint32_t((m2 - 1 + 255) / 256)), dim3(256), 0,
                          stream, m2, changed, old, pair, pair2, dirty);
       P_TRY(hipGetLastError());

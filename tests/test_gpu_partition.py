@@ -1,8 +1,10 @@
 """GPU variable-length partitioner (section 3.2.2) against the oracle's
-greedy split + merge rounds: identical partition starts (integer work:
+greedy split + merge scan: identical partition starts (integer work:
 exact), on the column shapes of the variable-partition workloads, both
-widths, first differences beyond 64 bits, several thresholds and caps, and
-columns longer than one 2^20-value split segment."""
+widths, first differences beyond 64 bits, several thresholds and caps,
+columns longer than one 2^20-value split segment, partitions crossing
+segment boundaries, and merge chains across the speculative chunks (256
+partitions) and fix-up groups (64 chunks) of the merge scan."""
 from __future__ import annotations
 
 import sys
@@ -81,10 +83,38 @@ def test_thresholds_caps_and_widths(torch, codec, ref):
     check(torch, codec, ref, mixed, "mixed regimes")
 
 
-def test_merge_round_limits(torch, codec, ref):
+def test_merge_pass_limits(torch, codec, ref):
     col = W.piecewise_linear(60_000, 75, segments=30)
     for r in (1, 2, 3):
-        check(torch, codec, ref, col, f"max_rounds {r}", max_rounds=r)
+        check(torch, codec, ref, col, f"max_passes {r}", max_passes=r)
+
+
+def test_merge_chains_across_chunks_and_groups(torch, codec, ref):
+    """tau = 0 splits noisy columns into partitions of two or three values,
+    about 150,000 of them: the merge scan then runs chains of merges across
+    its 256-partition chunks and 64-chunk groups (until widening the
+    residuals by a bit costs more than a record), over several passes."""
+    rng = np.random.default_rng(88)
+    poly = W.piecewise_linear(300_000, 91, segments=150).astype(np.uint64)
+    check(torch, codec, ref, poly, "polyline u64 tau 0", tau=0.0)
+    poly32 = W.piecewise_linear(300_000, 92, segments=150)
+    check(torch, codec, ref, poly32, "polyline u32 tau 0, sm 96", tau=0.0, sm_bits=96)
+    check(torch, codec, ref, poly, "polyline tau 0, one pass", tau=0.0, max_passes=1)
+    noise = (np.arange(300_000, dtype=np.uint64) * np.uint64(9)
+             + rng.integers(0, 8, 300_000, dtype=np.uint64))
+    check(torch, codec, ref, noise, "noise tau 0, cap 500", tau=0.0, max_len=500)
+    runs = W.constant_runs(300_000, 89, mean_run=5)
+    check(torch, codec, ref, runs, "short runs tau 0", tau=0.0)
+
+
+def test_cap_counts_from_the_partition_start(torch, codec, ref):
+    """One line cut by the cost at 1000, then 2^20 + 5000 values of another
+    line: the cap cuts at 1000 + 2^20, inside the second split segment."""
+    n2 = (1 << 20) + 5000
+    col = np.concatenate([np.arange(1000, dtype=np.uint64) * np.uint64(3),
+                          np.uint64(10**9) + np.arange(n2, dtype=np.uint64) * np.uint64(3)])
+    got = check(torch, codec, ref, col, "line across a segment boundary")
+    assert list(got) == [0, 1000, 1000 + (1 << 20), len(col)]
 
 
 def test_tiny_columns(torch, codec, ref):
@@ -106,12 +136,14 @@ def test_longer_than_one_segment(torch, codec, ref):
 
 
 def test_starting_positions(torch, codec, ref):
-    """With starting positions (section 3.2.2) the split also begins a
-    partition at the first value of every starting partition: identical
+    """With starting partitions (section 3.2.2, runs of smallest
+    second-order delta) the split begins a partition at the first value of
+    each and includes its other values without the cost test: identical
     starts on the workload shapes, both widths, a column whose smallest
-    delta bits are 2, differences beyond 64 bits, tiny columns and several
-    2^20-value split segments (starting positions near segment and
-    sub-chunk boundaries)."""
+    second-order delta is 3 (one starting partition over the whole column),
+    differences beyond 64 bits, tiny columns and several 2^20-value split
+    segments (starting partitions across segment and sub-chunk
+    boundaries)."""
     rng = np.random.default_rng(81)
     n = 200_000
     for kind, col in [("sorted_normal", W.sorted_normal(n, W.C3_SEEDS[0])),
@@ -123,12 +155,16 @@ def test_starting_positions(torch, codec, ref):
                        start_positions=True, tau=0.05)
         assert set(int(p) for p in ref.start_positions(col)) <= set(
             int(s) for s in ref.partition_split(col, tau=0.05, start_positions=True))
+        check(torch, codec, ref, col[:60_000], f"{kind} with starting positions, tau 0",
+              start_positions=True, tau=0.0)
         if kind == "constant_runs":
             blob = codec.encode(torch.from_numpy(col).cuda(), starts=starts)
             assert np.array_equal(blob.cpu().numpy(), ref.encode(col, starts=starts))
     d = np.tile(np.array([1, 4], np.uint64), 20_000)
     alternating = np.concatenate([[np.uint64(7)], np.uint64(7) + np.cumsum(d)]).astype(np.uint64)
-    check(torch, codec, ref, alternating, "delta bits all 2", start_positions=True)
+    check(torch, codec, ref, alternating, "second-order deltas all 3", start_positions=True)
+    check(torch, codec, ref, alternating, "second-order deltas all 3, tau 0, cap 3000",
+          start_positions=True, tau=0.0, max_len=3000)
     wide = rng.integers(0, 2**64 - 1, 20_000, dtype=np.uint64, endpoint=True)
     wide[::3] = rng.integers(0, 16, len(wide[::3]), dtype=np.uint64)
     check(torch, codec, ref, wide, "65-bit differences", start_positions=True)
