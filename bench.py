@@ -12,6 +12,15 @@ HIP events around each decode_all launch on the stream it runs on;
 `roofline` prices that kernel's algorithmic bytes (compressed bytes read
 plus output bytes written) against the 8 TB/s HBM peak.  `cpu_baseline`
 times the CPU oracle on the first 100,663,296 values of the same column.
+
+After that step the default run frees its buffers and adds two more
+workloads to the same line: `batched` (4,096 columns of lognormal lengths,
+about 2e9 values, one persistent decode launch, against one decode_all
+launch per column) and `served` (64 resident columns, 20 GB, a Poisson
+stream of mixed lookups and range scans through the served loop, against
+the same stream served one launch per request), each with its roofline
+fraction, and the served one with p50/p99 latency and the host/device time
+split of its request loop.  `--c2-only` skips them.
 """
 from __future__ import annotations
 
@@ -27,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+HOST_CPUS_PER_GPU = 16  # host CPU share of one GPU on the benchmark machines
 
 
 def log(msg: str):
@@ -59,6 +69,11 @@ def parse():
                     help="served workload: admitted, unreleased requests at most")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched: skip the 4096-launch per-column comparison (for profiler runs)")
+    ap.add_argument("--sat-requests", type=int, default=60_000,
+                    help="served workload: requests of the closed-loop saturation run")
+    ap.add_argument("--c2-only", action="store_true",
+                    help="default run: only the sorted-keys step, without the batched and served "
+                         "workloads")
     return ap.parse_args()
 
 
@@ -119,11 +134,11 @@ def cpu_baseline(col: np.ndarray, pos: np.ndarray, sample: int, L: int, gpu_blob
     # the same sample on every host core: static chunks of whole partitions,
     # one oracle call per chunk and thread (the C calls release the GIL)
     from concurrent.futures import ThreadPoolExecutor
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16, m))
+    host = host_facts()
+    # one thread per CPU the process may use, within its cgroup quota and the
+    # host share of one GPU on this machine (16 CPUs per GPU)
+    cap = min(host["usable_cpus"], int(host["cgroup_cpus"] or host["usable_cpus"]), HOST_CPUS_PER_GPU)
+    cores = max(1, min(cap, m))
     bounds = [(m * i // cores) * L for i in range(cores + 1)]
     chunks = [part[bounds[i]:bounds[i + 1]] for i in range(cores)]
     with ThreadPoolExecutor(cores) as ex:
@@ -135,6 +150,8 @@ def cpu_baseline(col: np.ndarray, pos: np.ndarray, sample: int, L: int, gpu_blob
         t_dec_mt = time.perf_counter() - t0
     assert all(np.array_equal(o, c) for o, c in zip(outs, chunks))
     return dict(value=sample * 8 / t_dec_mt / 1e9, unit="GB/s", cores=cores, kind="oracle",
+                nproc=host["nproc"], usable_cpus=host["usable_cpus"],
+                cgroup_cpus=host["cgroup_cpus"], cpu_model=host["cpu_model"],
                 sample=f"first {sample} values ({m} partitions of {L}) in {cores} static chunks, "
                        f"one thread each: decode_all {t_dec_mt:.2f} s, encode {t_enc_mt:.2f} s; "
                        f"one thread: decode_all {t_dec:.2f} s; encode {t_enc:.2f} s; "
@@ -144,6 +161,32 @@ def cpu_baseline(col: np.ndarray, pos: np.ndarray, sample: int, L: int, gpu_blob
                 single_thread={"decode_GBps": sample * 8 / t_dec / 1e9,
                                "encode_GBps": sample * 8 / t_enc / 1e9,
                                "lookups_per_s": len(p) / t_ra})
+
+
+def host_facts() -> dict:
+    """Host CPU facts for the CPU baseline: nproc, the CPUs this process may
+    run on, and the model string from /proc/cpuinfo."""
+    nproc = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = nproc
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    quota = None  # CPUs granted by the cgroup's cpu.max, if it sets one
+    try:
+        q, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = int(q) / int(period)
+    except (OSError, ValueError):
+        pass
+    return {"nproc": nproc, "usable_cpus": usable, "cgroup_cpus": quota, "cpu_model": model}
 
 
 def time_events(torch, stream, fn, reps: int) -> float:
@@ -159,18 +202,20 @@ def time_events(torch, stream, fn, reps: int) -> float:
     return float(np.median(ts))
 
 
-def bench_batched(args):
+def bench_batched(args, codec=None):
     """4,096 columns (lognormal lengths 1e3..1e7, ~2.0e9 values, half uint32)
-    encoded in one launch and decoded in one persistent launch, against the
-    plain path of one decode_all launch per column on one stream."""
+    encoded in one launch sequence and decoded in one persistent launch,
+    against the plain path of one decode_all launch per column on one
+    stream.  Returns the result dict."""
     import torch
     import paper_2306_15374_amd as P
     from paper_2306_15374_amd import workloads as W
 
     specs = W.batched_columns(args.cols)
-    codec = P.Codec(0)
+    own = codec is None
+    codec = codec or P.Codec(0)
     stream = torch.cuda.current_stream()
-    log(f"drawing {len(specs)} columns on the device")
+    log(f"batched: drawing {len(specs)} columns on the device")
     cols = [W.make_column_device(s) for s in specs]
     n_total = sum(s["n"] for s in specs)
     in_bytes = sum(s["n"] * (4 if s["dtype"] == np.uint32 else 8) for s in specs)
@@ -185,7 +230,7 @@ def bench_batched(args):
         jobs.append(P.EncodeJob(c.data_ptr(), s["n"], dt, 0, s["fixed_len"], buf.data_ptr(), cap,
                                 sizes.data_ptr() + 8 * i))
     torch.cuda.synchronize()
-    log(f"{n_total} values, {in_bytes / 1e9:.2f} GB; batched encode")
+    log(f"batched: {n_total} values, {in_bytes / 1e9:.2f} GB; batched encode")
     enc = lambda: codec.check("leco_encode_batch", P.leco_encode_batch(codec.ctx, jobs))
     enc()
     codec.sync()
@@ -209,7 +254,7 @@ def bench_batched(args):
     batch = P.leco_batch_create(codec.ctx, djobs)
     st, tl, bpc = P.leco_batch_tune(batch, P.LECO_BATCH_DECODE)
     codec.check("leco_batch_tune", st)
-    log(f"tuned shape: tile {'per column' if tl == 0 else f'2^{tl}'}, blocks/CU {bpc}")
+    log(f"batched: tuned shape: tile {'per column' if tl == 0 else f'2^{tl}'}, blocks/CU {bpc}")
     run = lambda op: (lambda: codec.check("leco_batch_run", P.leco_batch_run(batch, op)))
     run(P.LECO_BATCH_DECODE)()
     codec.sync()
@@ -234,7 +279,13 @@ def bench_batched(args):
     def plain():
         for b, o, s in zip(blobs, outs, specs):
             codec.check("leco_decode_all", P.leco_decode_all(codec.ctx, b, b.numel(), o, s["n"]))
-    t_plain = None if args.no_plain else time_events(torch, stream, plain, 3)
+    t_plain = None
+    if not args.no_plain:
+        plain()
+        codec.sync()
+        for s, c, o in zip(specs, cols, outs):
+            assert torch.equal(o, c), f"plain decode mismatch {s}"
+        t_plain = time_events(torch, stream, plain, 3)
     codec.sync()
     P.leco_batch_destroy(batch)
     alg = blob_total + in_bytes
@@ -251,11 +302,13 @@ def bench_batched(args):
         "batched_decode_graph_ms": round(t_graph * 1e3, 3),
         "plain_per_column_decode_ms": None if t_plain is None else round(t_plain * 1e3, 3),
         "speedup_vs_plain": None if t_plain is None else round(t_plain / t_dec, 2),
+        "plain_hbm_frac": None if t_plain is None else round(alg / t_plain / HBM_PEAK, 4),
         "filter_sum_ms": round(t_filter * 1e3, 3),
         "filter_sum_values_per_s": round(n_total / t_filter, 1),
         "fused_decode_filter_ms": round(t_fused * 1e3, 3),
         "batched_encode_ms": round(t_enc * 1e3, 3),
         "batched_encode_GBps": round(in_bytes / t_enc / 1e9, 2),
+        "batched_encode_hbm_frac": round((in_bytes + blob_total) / t_enc / HBM_PEAK, 4),
         "compression_ratio": round(blob_total / in_bytes, 5),
         "roofline": {"bound": "hbm", "achieved": round(alg / t_dec / 1e9, 1), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(alg / t_dec / HBM_PEAK, 4),
@@ -264,23 +317,58 @@ def bench_batched(args):
                      "kernel": "k_batch_decode", "bytes_per_launch": alg},
         "cpu_baseline": None,
     }
-    print(json.dumps(res), flush=True)
-    codec.close()
+    del cols, outs, bufs, blobs, sums, sizes
+    if own:
+        codec.close()
+    torch.cuda.empty_cache()
+    return res
 
 
-def bench_served(args):
+def served_requests(torch, P, W, lens, num, seed, rate, device_positions=True):
+    """The served request stream; random-access positions either resident
+    in device memory before the run (read in place by the step kernel) or in
+    host memory (copied into the server's pinned ring at submit)."""
+    reqs = W.request_mix(num, lens, seed, rate=rate)
+    arr = (P.Request * num)()
+    keep = []
+    ra = [r for r in reqs if r["kind"] == "ra"]
+    if device_positions and ra:
+        flat = torch.from_numpy(np.concatenate([r["positions"] for r in ra]).view(np.int64)).cuda()
+        torch.cuda.synchronize()
+        keep.append(flat)
+        base, off = flat.data_ptr(), 0
+    for i, r in enumerate(reqs):
+        if r["kind"] == "ra":
+            k = len(r["positions"])
+            if device_positions:
+                arr[i] = P.Request(P.LECO_REQ_RANDOM_ACCESS_DEV, r["col"], base + 8 * off, k, 0, 0)
+                off += k
+            else:
+                pos = np.ascontiguousarray(r["positions"])
+                keep.append(pos)
+                arr[i] = P.Request(P.LECO_REQ_RANDOM_ACCESS, r["col"], pos.ctypes.data, k, 0, 0)
+        else:
+            arr[i] = P.Request(P.LECO_REQ_RANGE, r["col"], None, 0, r["begin"], r["end"])
+    arrival = np.array([r["t"] for r in reqs]) - reqs[0]["t"]
+    return reqs, arr, keep, arrival
+
+
+def bench_served(args, codec=None):
     """64 resident uint64 columns of 39,062,500 values (20 GB uncompressed),
     a Poisson stream mixing random-access batches of floor(2^U[0,16])
     positions and range scans of floor(10^U[3,7]) values.  Saturation is
     measured closed-loop (all requests queued at once), then open-loop at
-    0.3, 0.6 and 0.9 of it, each with p50/p99 latency."""
+    0.3, 0.6 and 0.9 of it, each with p50/p99 latency; the plain path (one
+    launch per request, same streams of requests) is measured the same way.
+    Returns the result dict."""
     import torch
     import paper_2306_15374_amd as P
     from paper_2306_15374_amd import workloads as W
 
     specs = W.served_columns(args.cols if args.cols != 4096 else W.C5_COLS, args.served_n)
-    codec = P.Codec(0)
-    log(f"drawing and encoding {len(specs)} columns of {specs[0]['n']} values")
+    own = codec is None
+    codec = codec or P.Codec(0)
+    log(f"served: drawing and encoding {len(specs)} columns of {specs[0]['n']} values")
     cols, blobs = [], []
     for s in specs:
         c = W.make_column_device(s)
@@ -288,42 +376,16 @@ def bench_served(args):
         cols.append(c)
     compressed = sum(b.numel() for b in blobs)
     raw = sum(s["n"] * 8 for s in specs)
+    ratio = compressed / raw
     res = [P.ResidentCol(b.data_ptr(), b.numel(), s["n"]) for s, b in zip(specs, blobs)]
     cfg = P.ServerConfig(8 << 30, args.served_inflight, args.served_streams, 1 << 16, 1 << 20,
                          args.served_min_step_mb << 20, 100, 0, 256 << 20)
     server = P.leco_server_start(codec.ctx, res, cfg)
     lens = [s["n"] for s in specs]
-
-    def requests(num, seed, rate, device_positions=True):
-        """The request stream; random-access positions either resident in
-        device memory before the run (read in place by the step kernel) or
-        in host memory (copied into the server's pinned ring at submit)."""
-        reqs = W.request_mix(num, lens, seed, rate=rate)
-        arr = (P.Request * num)()
-        keep = []
-        ra = [r for r in reqs if r["kind"] == "ra"]
-        if device_positions and ra:
-            flat = torch.from_numpy(np.concatenate([r["positions"] for r in ra]).view(np.int64)).cuda()
-            torch.cuda.synchronize()
-            keep.append(flat)
-            base, off = flat.data_ptr(), 0
-        for i, r in enumerate(reqs):
-            if r["kind"] == "ra":
-                k = len(r["positions"])
-                if device_positions:
-                    arr[i] = P.Request(P.LECO_REQ_RANDOM_ACCESS_DEV, r["col"], base + 8 * off, k, 0, 0)
-                    off += k
-                else:
-                    pos = np.ascontiguousarray(r["positions"])
-                    keep.append(pos)
-                    arr[i] = P.Request(P.LECO_REQ_RANDOM_ACCESS, r["col"], pos.ctypes.data, k, 0, 0)
-            else:
-                arr[i] = P.Request(P.LECO_REQ_RANGE, r["col"], None, 0, r["begin"], r["end"])
-        arrival = np.array([r["t"] for r in reqs]) - reqs[0]["t"]
-        return reqs, arr, keep, arrival
+    mk = lambda num, seed, rate, dev=True: served_requests(torch, P, W, lens, num, seed, rate, dev)
 
     # correctness on a sample: alone results equal the resident column
-    sreqs, sarr, skeep, _ = requests(64, W.C5_SEED + 7, 1.0, device_positions=False)
+    sreqs, sarr, skeep, _ = mk(64, W.C5_SEED + 7, 1.0, dev=False)
     for i, r in enumerate(sreqs):
         st, t = P.leco_server_submit(server, sarr[i])
         codec.check("submit", st)
@@ -342,43 +404,90 @@ def bench_served(args):
             else col[r["begin"]: r["end"]]
         assert torch.equal(got, exp), f"served request {i} mismatch"
         P.leco_server_release(server, c.ticket)
-    log("sampled served results equal the resident columns")
+    log("served: sampled results equal the resident columns")
 
-    num = args.requests
+    def traffic(reqs):
+        lookups = sum(len(r["positions"]) for r in reqs if r["kind"] == "ra")
+        scanned = sum(r["end"] - r["begin"] for r in reqs if r["kind"] == "range")
+        # bytes a request moves: its values out, plus the compressed bytes
+        # read (range: ratio * 8 per value; random access: one 8-byte word
+        # and the 8-byte position)
+        return lookups, scanned, scanned * 8 * (1 + ratio) + lookups * (8 + 8 + 8)
+
+    def split(stats, elapsed):
+        """Where the request loop's time went (per step, microseconds) and
+        how much of the run the device was busy."""
+        steps = max(stats["steps"], 1)
+        return {"steps": stats["steps"], "items_per_step": round(stats["items"] / steps, 1),
+                "requests_per_step": round(stats["completed"] / steps, 2),
+                "host_us_per_step": {k: round(stats[f"host_{k}_ns"] / steps / 1e3, 2)
+                                     for k in ("submit", "admit", "build", "launch", "retire", "wait")},
+                "gpu_step_us_mean": round(stats["gpu_step_ns"] / steps / 1e3, 2),
+                "gpu_busy_frac_of_elapsed": round(stats["gpu_busy_ns"] / 1e9 / elapsed, 4),
+                "gpu_steps_in_flight_mean": round(stats["gpu_step_ns"] / max(stats["gpu_busy_ns"], 1), 2)}
+
     # saturation with positions in host memory (copied at submit), for reference
-    hreqs, harr, hkeep, _ = requests(num, W.C5_SEED + 1, 1.0, device_positions=False)
+    num = args.requests
+    hreqs, harr, hkeep, _ = mk(num, W.C5_SEED + 1, 1.0, dev=False)
     st, h_elapsed = P.leco_server_replay(server, harr, np.zeros(num), None)
     codec.check("replay", st)
-    log(f"closed loop, host positions: {num / h_elapsed:.0f} req/s")
-    del hkeep
+    log(f"served: closed loop, host positions: {num / h_elapsed:.0f} req/s")
+    del hkeep, harr, hreqs
     # the measured runs: every input (columns and positions) resident in HBM
-    reqs, arr, keep, arrival = requests(num, W.C5_SEED + 1, 1.0)
-    lookups = sum(len(r["positions"]) for r in reqs if r["kind"] == "ra")
-    scanned = sum(r["end"] - r["begin"] for r in reqs if r["kind"] == "range")
-    lat = np.zeros(num)
-    st, elapsed = P.leco_server_replay(server, arr, np.zeros(num), lat)
+    nsat = args.sat_requests
+    reqs, arr, keep, _ = mk(nsat, W.C5_SEED + 1, 1.0)
+    lookups, scanned, alg = traffic(reqs)
+    lat = np.zeros(nsat)
+    P.leco_server_stats_reset(server)
+    st, elapsed = P.leco_server_replay(server, arr, np.zeros(nsat), lat)
     codec.check("replay", st)
-    sat = num / elapsed
-    log(f"closed loop: {num} requests in {elapsed:.3f} s = {sat:.0f} req/s")
-    points = {}
+    sat_split = split(P.leco_server_stats_get(server), elapsed)
+    sat = nsat / elapsed
+    log(f"served: closed loop: {nsat} requests in {elapsed:.3f} s = {sat:.0f} req/s, "
+        f"{alg / elapsed / HBM_PEAK:.3f} of peak; {sat_split}")
+    # the plain path over the same closed-loop stream
+    # room for the largest request the stream can hold: 2^16 positions or a
+    # range of 10^7 values
+    out_bytes = 8 * max(1 << 16, 10_000_000)
+    pbuf = torch.empty(out_bytes, dtype=torch.uint8, device="cuda")
+    plat = np.zeros(nsat)
+    st, p_elapsed = P.leco_plain_replay(codec.ctx, res, arr, np.zeros(nsat), pbuf, pbuf.numel(),
+                                        latencies_out=plat)
+    codec.check("plain replay", st)
+    codec.sync()
+    p_sat = nsat / p_elapsed
+    log(f"served: plain closed loop: {p_sat:.0f} req/s, {alg / p_elapsed / HBM_PEAK:.3f} of peak")
+    del keep, arr
+    points, plain_points = {}, {}
     for frac in (0.3, 0.6, 0.9):
         rate = frac * sat
-        reqs_f, arr_f, keep_f, arr_t = requests(num, W.C5_SEED + 2 + int(frac * 10), rate)
-        lat_f = np.zeros(num)
+        reqs_f, arr_f, keep_f, arr_t = mk(args.requests, W.C5_SEED + 2 + int(frac * 10), rate)
+        n_f = len(reqs_f)
+        lat_f = np.zeros(n_f)
+        P.leco_server_stats_reset(server)
         st, el = P.leco_server_replay(server, arr_f, arr_t, lat_f)
         codec.check("replay", st)
-        points[str(frac)] = {"offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(num / el, 1),
+        _, _, alg_f = traffic(reqs_f)
+        points[str(frac)] = {"offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(n_f / el, 1),
                              "p50_us": round(float(np.percentile(lat_f, 50)), 1),
-                             "p99_us": round(float(np.percentile(lat_f, 99)), 1)}
-        log(f"open loop {frac}: {points[str(frac)]}")
+                             "p99_us": round(float(np.percentile(lat_f, 99)), 1),
+                             "hbm_frac": round(alg_f / el / HBM_PEAK, 4),
+                             "split": split(P.leco_server_stats_get(server), el)}
+        log(f"served: open loop {frac}: {points[str(frac)]}")
+        lat_p = np.zeros(n_f)
+        st, el_p = P.leco_plain_replay(codec.ctx, res, arr_f, arr_t, pbuf, pbuf.numel(),
+                                       latencies_out=lat_p)
+        codec.check("plain replay", st)
+        codec.sync()
+        plain_points[str(frac)] = {"offered_req_per_s": round(rate, 1),
+                                   "achieved_req_per_s": round(n_f / el_p, 1),
+                                   "p50_us": round(float(np.percentile(lat_p, 50)), 1),
+                                   "p99_us": round(float(np.percentile(lat_p, 99)), 1)}
+        log(f"served: plain open loop {frac}: {plain_points[str(frac)]}")
+        del keep_f, arr_f
     stats = P.leco_server_stats_get(server)
     P.leco_server_stop(server)
     codec.sync()
-    # bytes a request moves: its values out, plus the compressed bytes read
-    # (range: ratio * 8 per value; random access: one 8-byte word and the
-    # 8-byte position)
-    ratio = compressed / raw
-    alg = scanned * 8 * (1 + ratio) + lookups * (8 + 8 + 8)
     out = {
         "metric": "decoded GB/s + lookups/s vs HBM roofline (batched/served vs plain); p99 latency",
         "value": round(scanned * 8 / elapsed / 1e9, 2), "unit": "GB/s decoded (served range scans, saturated)",
@@ -386,16 +495,25 @@ def bench_served(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic (device-drawn linear-noise and lognormal-key columns)",
         "config": {"workload": f"served: {len(specs)} resident uint64 columns x {specs[0]['n']} "
-                               f"values ({raw / 1e9:.1f} GB), {num} mixed requests",
+                               f"values ({raw / 1e9:.1f} GB), {nsat} mixed requests closed loop, "
+                               f"{args.requests} per open-loop point",
                    "out_budget_bytes": 8 << 30, "streams": args.served_streams,
                    "max_inflight": args.served_inflight,
                    "min_step_bytes": args.served_min_step_mb << 20, "max_wait_us": 100},
         "saturation_req_per_s": round(sat, 1),
         "saturation_req_per_s_host_positions": round(num / h_elapsed, 1),
         "lookups_per_s": round(lookups / elapsed, 1),
+        "scan_GBps_decoded": round(scanned * 8 / elapsed / 1e9, 2),
         "closed_loop_p50_us": round(float(np.percentile(lat, 50)), 1),
         "closed_loop_p99_us": round(float(np.percentile(lat, 99)), 1),
+        "closed_loop_split": sat_split,
         "open_loop": points,
+        "plain": {"saturation_req_per_s": round(p_sat, 1),
+                  "hbm_frac": round(alg / p_elapsed / HBM_PEAK, 4),
+                  "closed_loop_p50_us": round(float(np.percentile(plat, 50)), 1),
+                  "closed_loop_p99_us": round(float(np.percentile(plat, 99)), 1),
+                  "open_loop": plain_points},
+        "speedup_vs_plain": round(sat / p_sat, 2),
         "steps_launched": stats["steps"],
         "compression_ratio": round(ratio, 5),
         "roofline": {"bound": "hbm", "achieved": round(alg / elapsed / 1e9, 1), "peak": HBM_PEAK / 1e9,
@@ -403,8 +521,11 @@ def bench_served(args):
                      "kernel": "k_serve_step", "bytes_per_launch": None},
         "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
-    codec.close()
+    del cols, blobs, pbuf
+    if own:
+        codec.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_variable(args):
@@ -690,9 +811,11 @@ def main():
               "no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
-        return bench_batched(args)
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
     if args.workload == "served":
-        return bench_served(args)
+        print(json.dumps(bench_served(args)), flush=True)
+        return
     if args.workload == "variable":
         return bench_variable(args)
     if args.workload == "encode_options":
@@ -780,18 +903,25 @@ def main():
 
     # HBM reference: the library's plain streaming copy and fill kernels over
     # the same 1.6 GB buffers (also the known-size kernel for the traffic
-    # counters).
+    # counters), and the runtime's own device-to-device copy of them.
     cal = {}
-    for name, src, nbytes in (("copy", d_col, out_bytes), ("fill", None, out_bytes)):
+    out_u8, col_u8 = out.view(torch.uint8), d_col.view(torch.uint8)
+    for name, fn, moved in (
+            ("copy", lambda: codec.check("leco_diag_copy", P.leco_diag_copy(
+                codec.ctx, d_col, out, out_bytes)), 2 * out_bytes),
+            ("fill", lambda: codec.check("leco_diag_copy", P.leco_diag_copy(
+                codec.ctx, None, out, out_bytes)), out_bytes),
+            ("runtime_d2d_copy", lambda: out_u8.copy_(col_u8), 2 * out_bytes)):
+        fn()
+        torch.cuda.synchronize()
         ts = []
         for _ in range(5):
             c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             c0.record(stream)
-            codec.check("leco_diag_copy", P.leco_diag_copy(codec.ctx, src, out, nbytes))
+            fn()
             c1.record(stream)
             torch.cuda.synchronize()
             ts.append(c0.elapsed_time(c1) / 1e3)
-        moved = nbytes * (2 if src is not None else 1)
         cal[f"{name}_GBps"] = round(moved / float(np.median(ts)) / 1e9, 1)
     log(f"HBM reference: {cal}")
 
@@ -827,8 +957,23 @@ def main():
         "hbm_reference": cal,
         "cpu_baseline": cpu,
     }
+    if not args.c2_only:
+        # the other two workloads of the same run, on the freed device
+        del out, ra_out, d_col, d_pos, blob, buf, out_u8, col_u8
+        del col, pos
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        res["batched"] = strip(bench_batched(args, codec))
+        res["served"] = strip(bench_served(args, codec))
     print(json.dumps(res), flush=True)
     codec.close()
+
+
+def strip(res: dict) -> dict:
+    """A workload's result without the keys the headline line already has."""
+    drop = {"metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+            "cpu_baseline", "data"}
+    return {k: v for k, v in res.items() if k not in drop}
 
 
 if __name__ == "__main__":

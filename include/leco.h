@@ -276,6 +276,20 @@ leco_status leco_batch_run_graph(leco_batch *batch, int op, hipStream_t stream);
 leco_status leco_batch_tune(leco_batch *batch, int op, hipStream_t stream,
                             uint32_t *tile_log2, uint32_t *blocks_per_cu);
 
+/* leco_batch_tune with its choice kept in a file (the tuner cache): the
+ * shape chosen for a key of the device (architecture name and CU count),
+ * op and batch shape (column count, total values, total blob bytes) is
+ * stored as a member "<key>": {"tile_log2": T, "blocks_per_cu": B} of a
+ * JSON object in cache_path (or, when cache_path is null, the file named by
+ * the environment variable LECO_AUTOTUNE_CACHE; with neither this is
+ * leco_batch_tune).  A key found in the file is applied without timing and
+ * *from_cache (if not null) is set to 1; otherwise the batch is tuned and
+ * the file rewritten with the new member (LECO_EINVAL if it cannot be
+ * written).  [sync] */
+leco_status leco_batch_tune_cached(leco_batch *batch, int op, const char *cache_path,
+                                   hipStream_t stream, uint32_t *tile_log2,
+                                   uint32_t *blocks_per_cu, int32_t *from_cache);
+
 /* Sets the launch shape explicitly: tiles of 2^tile_log2 values (8..16) for
  * every column, or 0 for each column's own size, the largest whose residual
  * words (estimated from the column's blob bytes per value) fit one
@@ -452,9 +466,10 @@ leco_status leco_server_start(leco_ctx *ctx, const leco_resident_col *cols_host,
  * against n and copied into the position ring here (LECO_ERANGE; LECO_ENOMEM
  * when the ring is momentarily full: retry once earlier requests complete);
  * a request larger than the whole budget is refused (LECO_ENOSPC), one
- * larger than a step (max_step_items workgroups of 256 lookups or 4096
- * range values) is LECO_EINVAL.  A request's latency runs from the start of
- * this call. */
+ * larger than a step (max_step_items workgroups of 256 lookups, or of one
+ * decode tile of range values: 2^8 to 2^14 values, the most whose residual
+ * words fit a workgroup's staging memory at the column's bits per value) is
+ * LECO_EINVAL.  A request's latency runs from the start of this call. */
 leco_status leco_server_submit(leco_server *s, const leco_request *req,
                                uint64_t *ticket);
 /* Queues reqs[0..n) in order with one acquisition of the server's lock,

@@ -29,6 +29,7 @@ EXPORTS = [
     "leco_decode_all", "leco_decode_range", "leco_random_access", "leco_filter_sum",
     "leco_diag_slope", "leco_diag_copy", "leco_encode_batch", "leco_batch_create",
     "leco_batch_destroy", "leco_batch_run", "leco_batch_run_graph", "leco_batch_tune",
+    "leco_batch_tune_cached",
     "leco_batch_set_shape", "leco_server_start", "leco_server_submit", "leco_server_submit_batch",
     "leco_server_poll", "leco_server_release", "leco_server_stats_get", "leco_server_stop",
     "leco_server_replay", "leco_server_stats_reset", "leco_plain_replay", "leco_partition",
@@ -139,6 +140,7 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_batch_run": ([vp, i32, vp], i32),
         "leco_batch_run_graph": ([vp, i32, vp], i32),
         "leco_batch_tune": ([vp, i32, vp, P(C.c_uint32), P(C.c_uint32)], i32),
+        "leco_batch_tune_cached": ([vp, i32, C.c_char_p, vp, P(C.c_uint32), P(C.c_uint32), P(C.c_int32)], i32),
         "leco_batch_set_shape": ([vp, C.c_uint32, C.c_uint32], i32),
         "leco_server_start": ([vp, vp, u64, P(ServerConfig), P(vp)], i32),
         "leco_server_submit": ([vp, P(Request), P(u64)], i32),
@@ -321,6 +323,17 @@ def leco_batch_tune(batch: int, op: int, stream=None) -> tuple[int, int, int]:
     t, b = C.c_uint32(), C.c_uint32()
     st = lib().leco_batch_tune(batch, op, _stream(stream), C.byref(t), C.byref(b))
     return st, t.value, b.value
+
+
+def leco_batch_tune_cached(batch: int, op: int, cache_path: str | None,
+                           stream=None) -> tuple[int, int, int, bool]:
+    """(status, tile_log2, blocks_per_cu, whether the shape came from the
+    tuner cache file)."""
+    t, b, hit = C.c_uint32(), C.c_uint32(), C.c_int32()
+    path = None if cache_path is None else cache_path.encode()
+    st = lib().leco_batch_tune_cached(batch, op, path, _stream(stream), C.byref(t), C.byref(b),
+                                      C.byref(hit))
+    return st, t.value, b.value, bool(hit.value)
 
 
 def leco_batch_set_shape(batch: int, tile_log2: int, blocks_per_cu: int) -> int:

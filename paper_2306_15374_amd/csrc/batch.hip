@@ -2,6 +2,11 @@
 // tiles of thousands of columns (flattened into one table, mixed uint32 and
 // uint64, optional fused range-filter sum), HIP-graph replay, a launch-shape
 // tuner, and a one-launch encoder over a table of columns.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
 #include <vector>
 
 #include "decode_tile.hpp"
@@ -359,6 +364,105 @@ leco_status leco_batch_tune(leco_batch* b, int op, hipStream_t stream, uint32_t*
   if (tile_log2) *tile_log2 = bt;
   if (blocks_per_cu) *blocks_per_cu = bb;
   return st != LECO_OK ? st : st2;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The tuner's cache file: a JSON object with one member per line,
+//   "<key>": {"tile_log2": T, "blocks_per_cu": B},
+// keyed by device, operation and batch shape.
+std::string tune_key(const leco_batch* b, int op) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, b->ctx->device) == hipSuccess) arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == '"' || ch == '\\') ch = '_';
+  uint64_t values = 0, bytes = 0;
+  for (const leco_decode_job& j : b->jobs) {
+    values += j.n;
+    bytes += j.blob_bytes;
+  }
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s cu%d op%d cols%llu values%llu bytes%llu", arch.c_str(),
+           b->ctx->num_cus, op, (unsigned long long)b->jobs.size(), (unsigned long long)values,
+           (unsigned long long)bytes);
+  return buf;
+}
+
+struct TuneEntry {
+  std::string key;
+  uint32_t tile_log2, blocks_per_cu;
+};
+
+std::vector<TuneEntry> read_tune_cache(const char* path) {
+  std::vector<TuneEntry> out;
+  FILE* f = fopen(path, "r");
+  if (!f) return out;
+  char line[1024];
+  while (fgets(line, sizeof(line), f)) {
+    const char* q0 = strchr(line, '"');
+    const char* q1 = q0 ? strchr(q0 + 1, '"') : nullptr;
+    if (!q1) continue;
+    unsigned t = 0, bpc = 0;
+    const char* rest = strstr(q1, "\"tile_log2\":");
+    const char* rest2 = strstr(q1, "\"blocks_per_cu\":");
+    if (!rest || !rest2 || sscanf(rest, "\"tile_log2\": %u", &t) != 1 ||
+        sscanf(rest2, "\"blocks_per_cu\": %u", &bpc) != 1)
+      continue;
+    out.push_back(TuneEntry{std::string(q0 + 1, q1), t, bpc});
+  }
+  fclose(f);
+  return out;
+}
+
+bool write_tune_cache(const char* path, const std::vector<TuneEntry>& entries) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  fprintf(f, "{\n");
+  for (size_t i = 0; i < entries.size(); ++i)
+    fprintf(f, "\"%s\": {\"tile_log2\": %u, \"blocks_per_cu\": %u}%s\n", entries[i].key.c_str(),
+            entries[i].tile_log2, entries[i].blocks_per_cu, i + 1 < entries.size() ? "," : "");
+  fprintf(f, "}\n");
+  const bool ok = fclose(f) == 0;
+  return ok && rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+leco_status leco_batch_tune_cached(leco_batch* b, int op, const char* cache_path,
+                                   hipStream_t stream, uint32_t* tile_log2,
+                                   uint32_t* blocks_per_cu, int32_t* from_cache) {
+  if (!b || !valid_op(op)) return LECO_EINVAL;
+  if (from_cache) *from_cache = 0;
+  const char* path = cache_path ? cache_path : getenv("LECO_AUTOTUNE_CACHE");
+  if (!path || !*path) return leco_batch_tune(b, op, stream, tile_log2, blocks_per_cu);
+  const std::string key = tune_key(b, op);
+  std::vector<TuneEntry> entries = read_tune_cache(path);
+  for (const TuneEntry& e : entries) {
+    if (e.key != key) continue;
+    const leco_status st = leco_batch_set_shape(b, e.tile_log2, e.blocks_per_cu);
+    if (st != LECO_OK) break;  // an unusable entry is tuned again below
+    if (tile_log2) *tile_log2 = e.tile_log2;
+    if (blocks_per_cu) *blocks_per_cu = e.blocks_per_cu;
+    if (from_cache) *from_cache = 1;
+    return LECO_OK;
+  }
+  uint32_t t = 0, bpc = 0;
+  leco_status st = leco_batch_tune(b, op, stream, &t, &bpc);
+  if (st != LECO_OK) return st;
+  if (tile_log2) *tile_log2 = t;
+  if (blocks_per_cu) *blocks_per_cu = bpc;
+  std::vector<TuneEntry> kept;
+  for (const TuneEntry& e : entries)
+    if (e.key != key) kept.push_back(e);
+  kept.push_back(TuneEntry{key, t, bpc});
+  if (!write_tune_cache(path, kept)) return bfail(b, LECO_EINVAL, "cannot write the tuner cache file");
+  return LECO_OK;
 }
 
 }  // extern "C"

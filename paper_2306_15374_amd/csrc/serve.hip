@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -24,22 +25,19 @@ struct ServeCol {
   uint64_t blob_bytes;
   uint64_t n;
   uint32_t dtype;
-  uint32_t pad;
+  uint32_t tile_log2;  // values per range work item, as decode_all's tiles
 };
 
 // One workgroup of a step.  Random access: b positions, at index a of the
 // position ring (LECO_REQ_RANDOM_ACCESS) or at device address a
 // (LECO_REQ_RANDOM_ACCESS_DEV), results to out_off.  Range: values [a, b)
-// of the column (at most one workgroup tile), results to out_off.
+// of the column (at most one decode tile of the column), results to out_off.
 struct WorkItem {
   uint32_t kind;
   uint32_t col;
   uint64_t a, b;
   uint64_t out_off;  // bytes into the result arena
 };
-
-constexpr uint32_t kServeTileLog2 = 12;
-constexpr uint64_t kServeTile = uint64_t(1) << kServeTileLog2;
 
 // The position ring lives in pinned host memory; the lanes of a workgroup
 // read 256 consecutive positions (from the ring or from device memory), so
@@ -79,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
     return;
   }
   uint64_t g0, g1;
-  wave_share(it.a, it.b, kServeTileLog2, g0, g1);
+  wave_share(it.a, it.b, c.tile_log2, g0, g1);
   if (g0 >= g1) return;
   bool ok;
   if (h.dtype == 8) {
@@ -140,6 +138,7 @@ class Arena {
   }
   uint64_t used() const { return used_; }
   uint64_t peak() const { return peak_; }
+  void reset_peak() { peak_ = used_; }
   static uint64_t round(uint64_t b) { return (b + 255) & ~uint64_t(255); }
 
  private:
@@ -152,6 +151,7 @@ struct Pending {
   leco_request req;
   uint64_t pos_off;  // byte offset of the positions in the ring (host positions)
   uint64_t count, out_bytes;
+  uint64_t items;    // work items (workgroups) of the request
   Clock::time_point t_submit;
 };
 
@@ -163,6 +163,7 @@ struct Result {
 // A step slot: its stream, completion event and work-item staging.
 struct Slot {
   hipStream_t stream = nullptr;
+  hipEvent_t start = nullptr;  // timing events around the step
   hipEvent_t done = nullptr;
   leco::WorkItem* items_host = nullptr;  // pinned
   leco::WorkItem* items_dev = nullptr;
@@ -198,19 +199,28 @@ struct leco_server {
   leco_server_stats stats{};
   std::atomic<bool> stop{false};
   std::thread worker;
+
+  // Host time of the loop's phases (ns), written by the worker thread
+  // outside the lock and by submitting threads.
+  std::atomic<uint64_t> t_submit{0}, t_admit{0}, t_build{0}, t_launch{0}, t_retire{0}, t_wait{0};
+  // Device intervals of retired steps, in ms after the reference event
+  // (guarded by mu).
+  hipEvent_t ref = nullptr;
+  std::vector<std::pair<double, double>> intervals;
 };
 
 namespace {
+
+uint64_t ns_since(Clock::time_point t0) {
+  return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count());
+}
 
 leco_status sfail(leco_server* s, leco_status st, const char* msg) {
   if (s && s->ctx) s->ctx->last_error = msg;
   return st;
 }
 
-uint64_t step_items(const Pending& p) {
-  return p.req.kind != LECO_REQ_RANGE ? (p.count + leco::kBlock - 1) / leco::kBlock
-                                      : (p.count + leco::kServeTile - 1) / leco::kServeTile;
-}
+uint64_t step_items(const Pending& p) { return p.items; }
 
 // While a step is running, the next one waits until the queued work that
 // fits it is worth a launch: enough result bytes, half the step's items,
@@ -244,6 +254,7 @@ bool batch_ready(const leco_server* s) {
 // belongs to the worker until it is marked busy).  Returns true if a step
 // was launched.
 bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
+  const Clock::time_point t_enter = Clock::now();
   Slot* slot = nullptr;
   for (size_t i = 0; i < s->slots.size(); ++i) {
     Slot& c = s->slots[(s->next_slot + i) % s->slots.size()];
@@ -281,6 +292,8 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
   s->stats.steps += 1;
   slot->busy = true;  // keeps other launches off this slot while unlocked
   lk.unlock();
+  const Clock::time_point t_built0 = Clock::now();
+  s->t_admit += uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(t_built0 - t_enter).count());
   uint32_t k = 0;
   for (size_t r = 0; r < slot->reqs.size(); ++r) {
     const Pending& p = slot->reqs[r];
@@ -297,15 +310,18 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
                                                off + first * col.dtype};
       }
     } else {
-      for (uint64_t g = p.req.begin; g < p.req.end; g += leco::kServeTile) {
-        const uint64_t e = g + leco::kServeTile < p.req.end ? g + leco::kServeTile : p.req.end;
+      const uint64_t tile = uint64_t(1) << col.tile_log2;
+      for (uint64_t g = p.req.begin; g < p.req.end; g += tile) {
+        const uint64_t e = g + tile < p.req.end ? g + tile : p.req.end;
         slot->items_host[k++] = leco::WorkItem{LECO_REQ_RANGE, p.req.col, g, e,
                                                off + (g - p.req.begin) * col.dtype};
       }
     }
   }
-  hipError_t e = hipSuccess;
-  if (k) {
+  const Clock::time_point t_launch0 = Clock::now();
+  s->t_build += uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(t_launch0 - t_built0).count());
+  hipError_t e = hipEventRecord(slot->start, slot->stream);
+  if (k && e == hipSuccess) {
     e = hipMemcpyAsync(slot->items_dev, slot->items_host, sizeof(leco::WorkItem) * k,
                        hipMemcpyHostToDevice, slot->stream);
     if (e == hipSuccess) {
@@ -318,7 +334,9 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
   if (e == hipSuccess) e = hipEventRecord(slot->done, slot->stream);
   // a failed step completes its requests with EDEVICE once its stream drains
   if (e != hipSuccess) (void)hipStreamSynchronize(slot->stream);
+  s->t_launch += ns_since(t_launch0);
   lk.lock();
+  s->stats.items += k;
   slot->status = e == hipSuccess ? LECO_OK : LECO_EDEVICE;
   slot->launched = true;
   return true;
@@ -333,6 +351,10 @@ bool retire_steps(leco_server* s) {
         (slot.status == LECO_OK && hipEventQuery(slot.done) != hipSuccess))
       continue;
     const Clock::time_point now = Clock::now();
+    float t0_ms = 0.f, t1_ms = 0.f;
+    if (slot.status == LECO_OK && hipEventElapsedTime(&t0_ms, s->ref, slot.start) == hipSuccess &&
+        hipEventElapsedTime(&t1_ms, s->ref, slot.done) == hipSuccess)
+      s->intervals.emplace_back(double(t0_ms), double(t1_ms));
     for (size_t i = 0; i < slot.reqs.size(); ++i) {
       const Pending& p = slot.reqs[i];
       if (p.req.kind == LECO_REQ_RANDOM_ACCESS && p.count) s->ring->release(p.pos_off, 8 * p.count);
@@ -362,12 +384,15 @@ void worker_main(leco_server* s) {
   (void)hipSetDevice(s->ctx->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
+    const Clock::time_point t0 = Clock::now();
     retire_steps(s);
+    s->t_retire += ns_since(t0);
     const bool launched = launch_step(s, lk);
     bool busy = false;
     for (const Slot& slot : s->slots) busy = busy || slot.busy;
     if (s->stop && s->queue.empty() && !busy) break;
     if (!launched) {
+      const Clock::time_point tw = Clock::now();
       if (busy) {
         lk.unlock();
         std::this_thread::yield();
@@ -375,6 +400,7 @@ void worker_main(leco_server* s) {
       } else {
         s->cv.wait_for(lk, std::chrono::microseconds(200));
       }
+      s->t_wait += ns_since(tw);
     }
   }
 }
@@ -383,11 +409,13 @@ void free_server(leco_server* s) {
   for (Slot& slot : s->slots) {
     if (slot.stream) (void)hipStreamSynchronize(slot.stream);
     if (slot.done) (void)hipEventDestroy(slot.done);
+    if (slot.start) (void)hipEventDestroy(slot.start);
     // teardown: an error here leaves nothing to undo, so it is not reported
     if (slot.stream) (void)hipStreamDestroy(slot.stream);
     if (slot.items_host) (void)hipHostFree(slot.items_host);
     if (slot.items_dev) (void)hipFree(slot.items_dev);
   }
+  if (s->ref) (void)hipEventDestroy(s->ref);
   if (s->cols_dev) (void)hipFree(s->cols_dev);
   if (s->arena_dev) (void)hipFree(s->arena_dev);
   if (s->ring_host) (void)hipHostFree(s->ring_host);
@@ -435,7 +463,8 @@ leco_status leco_server_start(leco_ctx* ctx, const leco_resident_col* cols, uint
       return LECO_EFORMAT;
     }
     s->cols.push_back(leco::ServeCol{static_cast<const uint8_t*>(cols[i].blob_dev),
-                                     cols[i].blob_bytes, n, uint32_t(dt), 0});
+                                     cols[i].blob_bytes, n, uint32_t(dt),
+                                     leco::pick_tile_log2(leco::Tune{}, cols[i].blob_bytes, n)});
   }
   bool ok = hipMalloc(&s->cols_dev, sizeof(leco::ServeCol) * ncols) == hipSuccess &&
             hipMemcpy(s->cols_dev, s->cols.data(), sizeof(leco::ServeCol) * ncols,
@@ -448,11 +477,15 @@ leco_status leco_server_start(leco_ctx* ctx, const leco_resident_col* cols, uint
   s->slots.resize(cfg->num_streams);
   for (Slot& slot : s->slots) {
     ok = ok && hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreate(&slot.start) == hipSuccess && hipEventCreate(&slot.done) == hipSuccess &&
          hipHostMalloc(&slot.items_host, sizeof(leco::WorkItem) * s->cfg.max_step_items,
                        hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&slot.items_dev, sizeof(leco::WorkItem) * s->cfg.max_step_items) == hipSuccess;
   }
+  // the reference the step events are timed against
+  ok = ok && hipEventCreate(&s->ref) == hipSuccess &&
+       hipEventRecord(s->ref, s->slots[0].stream) == hipSuccess &&
+       hipEventSynchronize(s->ref) == hipSuccess;
   if (!ok) {
     free_server(s);
     ctx->last_error = "server allocation failed";
@@ -488,11 +521,12 @@ leco_status prepare_request(leco_server* s, const leco_request* r, Pending& p) {
     if ((r->k + leco::kBlock - 1) / leco::kBlock > s->cfg.max_step_items)
       return sfail(s, LECO_EINVAL, "more positions than a step holds");
     p.count = r->k;
+    p.items = (p.count + leco::kBlock - 1) / leco::kBlock;
   } else if (r->kind == LECO_REQ_RANGE) {
     if (r->begin > r->end || r->end > col.n) return sfail(s, LECO_ERANGE, "range outside [0, n)");
     p.count = r->end - r->begin;
-    if ((p.count + leco::kServeTile - 1) / leco::kServeTile > s->cfg.max_step_items)
-      return sfail(s, LECO_EINVAL, "range larger than a step");
+    p.items = (p.count + (uint64_t(1) << col.tile_log2) - 1) >> col.tile_log2;
+    if (p.items > s->cfg.max_step_items) return sfail(s, LECO_EINVAL, "range larger than a step");
   } else {
     return sfail(s, LECO_EINVAL, "unknown request kind");
   }
@@ -564,6 +598,7 @@ leco_status leco_server_submit_batch(leco_server* s, const leco_request* reqs, u
     }
     s->cv.notify_all();
   }
+  s->t_submit += ns_since(t_enter);
   if (accepted) *accepted = ready.size();
   return st;
 }
@@ -600,6 +635,52 @@ leco_status leco_server_stats_get(leco_server* s, leco_server_stats* out) {
   out->out_bytes_in_use = s->arena->used();
   out->out_bytes_peak = s->arena->peak();
   out->queued = s->queue.size();
+  out->host_submit_ns = s->t_submit;
+  out->host_admit_ns = s->t_admit;
+  out->host_build_ns = s->t_build;
+  out->host_launch_ns = s->t_launch;
+  out->host_retire_ns = s->t_retire;
+  out->host_wait_ns = s->t_wait;
+  // step durations, their union and their span
+  std::vector<std::pair<double, double>> iv = s->intervals;
+  std::sort(iv.begin(), iv.end());
+  double sum = 0, busy = 0, cur_a = 0, cur_b = 0, lo = 0, hi = 0;
+  bool open = false;
+  for (const auto& x : iv) {
+    sum += x.second - x.first;
+    if (!open) {
+      cur_a = x.first;
+      cur_b = x.second;
+      lo = x.first;
+      hi = x.second;
+      open = true;
+      continue;
+    }
+    hi = x.second > hi ? x.second : hi;
+    if (x.first > cur_b) {
+      busy += cur_b - cur_a;
+      cur_a = x.first;
+      cur_b = x.second;
+    } else if (x.second > cur_b) {
+      cur_b = x.second;
+    }
+  }
+  if (open) busy += cur_b - cur_a;
+  out->gpu_step_ns = uint64_t(sum * 1e6);
+  out->gpu_busy_ns = uint64_t(busy * 1e6);
+  out->gpu_span_ns = uint64_t((hi - lo) * 1e6);
+  return LECO_OK;
+}
+
+leco_status leco_server_stats_reset(leco_server* s) {
+  if (!s) return LECO_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  const uint64_t in_use = s->stats.out_bytes_in_use;
+  s->stats = leco_server_stats{};
+  s->stats.out_bytes_in_use = in_use;
+  s->arena->reset_peak();
+  s->t_submit = s->t_admit = s->t_build = s->t_launch = s->t_retire = s->t_wait = 0;
+  s->intervals.clear();
   return LECO_OK;
 }
 
@@ -679,6 +760,121 @@ leco_status leco_server_replay(leco_server* s, const leco_request* reqs, const d
     *elapsed_s = std::chrono::duration<double>(last - t0).count() - first;
   }
   return LECO_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+leco_status leco_plain_replay(leco_ctx* ctx, const leco_resident_col* cols, uint64_t ncols,
+                              const leco_request* reqs, const double* arrival_s, uint64_t n,
+                              void* out_dev, uint64_t out_bytes, hipStream_t stream,
+                              double* latency_us_out, double* elapsed_s) {
+  if (!ctx) return LECO_EINVAL;
+  if ((ncols && !cols) || (n && (!reqs || !arrival_s)) || !out_dev) {
+    ctx->last_error = "plain replay: null argument";
+    return LECO_EINVAL;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return LECO_EDEVICE;
+  // dtypes of the columns, and the checks the served loop makes at submission
+  std::vector<uint32_t> dt(ncols);
+  for (uint64_t c = 0; c < ncols; ++c) {
+    uint8_t hdr[64];
+    leco_dtype d;
+    uint64_t nn = 0;
+    if (!cols[c].blob_dev || hipMemcpy(hdr, cols[c].blob_dev, 64, hipMemcpyDeviceToHost) != hipSuccess ||
+        leco_blob_info(hdr, &nn, &d, nullptr) != LECO_OK || nn != cols[c].n) {
+      ctx->last_error = "plain replay: column with a bad blob";
+      return LECO_EINVAL;
+    }
+    dt[c] = uint32_t(d);
+  }
+  for (uint64_t i = 0; i < n; ++i) {
+    const leco_request& r = reqs[i];
+    if (r.col >= ncols) {
+      ctx->last_error = "plain replay: no such column";
+      return LECO_EINVAL;
+    }
+    uint64_t count = 0;
+    if (r.kind == LECO_REQ_RANDOM_ACCESS_DEV) {
+      if (r.k && !r.positions) {
+        ctx->last_error = "plain replay: positions are null";
+        return LECO_EINVAL;
+      }
+      count = r.k;
+    } else if (r.kind == LECO_REQ_RANGE) {
+      if (r.begin > r.end || r.end > cols[r.col].n) {
+        ctx->last_error = "plain replay: range outside [0, n)";
+        return LECO_ERANGE;
+      }
+      count = r.end - r.begin;
+    } else {
+      ctx->last_error = "plain replay: requests must be ranges or device-position lookups";
+      return LECO_EINVAL;
+    }
+    if (count * dt[r.col] > out_bytes) {
+      ctx->last_error = "plain replay: output buffer smaller than a request";
+      return LECO_ENOSPC;
+    }
+  }
+  // a ring of completion events, retired in launch order
+  constexpr uint64_t kEvents = 1024;
+  std::vector<hipEvent_t> ev(kEvents, nullptr);
+  for (auto& e : ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+      return LECO_EDEVICE;
+    }
+  const Clock::time_point t0 = Clock::now();
+  auto due_at = [&](uint64_t i) {
+    return t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+  };
+  Clock::time_point last = t0;
+  uint64_t head = 0, tail = 0;  // requests [head, tail) are launched and not yet seen complete
+  leco_status st = LECO_OK;
+  auto retire = [&](bool wait) {
+    while (head < tail) {
+      hipEvent_t e = ev[head % kEvents];
+      const hipError_t q = wait ? hipEventSynchronize(e) : hipEventQuery(e);
+      if (q == hipErrorNotReady) return;
+      if (q != hipSuccess) st = LECO_EDEVICE;
+      last = Clock::now();
+      if (latency_us_out)
+        latency_us_out[head] = std::chrono::duration<double, std::micro>(last - due_at(head)).count();
+      ++head;
+      wait = false;
+    }
+  };
+  for (uint64_t i = 0; i < n && st == LECO_OK; ++i) {
+    while (Clock::now() < due_at(i)) retire(false);
+    while (tail - head >= kEvents) retire(true);  // the ring is full
+    const leco_request& r = reqs[i];
+    const leco_resident_col& c = cols[r.col];
+    const leco_status ls =
+        r.kind == LECO_REQ_RANGE
+            ? leco_decode_range(ctx, c.blob_dev, c.blob_bytes, r.begin, r.end, out_dev, stream)
+            : leco_random_access(ctx, c.blob_dev, c.blob_bytes, r.positions, r.k, out_dev, stream);
+    if (ls != LECO_OK) {
+      st = ls;
+      break;
+    }
+    if (hipEventRecord(ev[tail % kEvents], stream) != hipSuccess) {
+      st = LECO_EDEVICE;
+      break;
+    }
+    ++tail;
+    retire(false);
+  }
+  while (head < tail) {
+    const leco_status before = st;
+    retire(true);
+    if (st != before) break;
+  }
+  (void)hipStreamSynchronize(stream);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (elapsed_s) *elapsed_s = std::chrono::duration<double>(last - t0).count() - (n ? arrival_s[0] : 0.0);
+  return st;
 }
 
 }  // extern "C"

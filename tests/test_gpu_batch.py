@@ -198,3 +198,44 @@ def test_batch_rejects_mismatched_length(torch, codec):
         assert P.leco_sync(codec.ctx) == P.LECO_EFORMAT
     finally:
         P.leco_batch_destroy(batch)
+
+
+def test_tuner_cache_file(torch, codec, tmp_path):
+    """The tuner's choice is kept per device, op and batch shape in a JSON
+    file: the first call tunes and writes it, the second (same shape) reads
+    it back without tuning, another op or shape gets its own member, and
+    results are unchanged."""
+    import json
+    specs = small_specs(ncols=16, seed=10)
+    cols = [W.make_column_device(s) for s in specs]
+    blobs = [codec.encode(c, fixed_len=s["fixed_len"]) for s, c in zip(specs, cols)]
+    batch, outs, sums, bounds = make_batch(torch, codec, specs, cols, blobs)
+    path = str(tmp_path / "tune.json")
+    try:
+        st, tl, bpc, hit = P.leco_batch_tune_cached(batch, 3, path)
+        codec.check("tune_cached", st)
+        assert not hit
+        cache = json.load(open(path))
+        assert len(cache) == 1
+        (key, val), = cache.items()
+        assert val == {"tile_log2": tl, "blocks_per_cu": bpc} and "op3" in key
+        codec.check("set_shape", P.leco_batch_set_shape(batch, 9, 1))
+        st, tl2, bpc2, hit = P.leco_batch_tune_cached(batch, 3, path)
+        codec.check("tune_cached", st)
+        assert hit and (tl2, bpc2) == (tl, bpc)
+        st, _, _, hit = P.leco_batch_tune_cached(batch, 1, path)
+        assert st == P.LECO_OK and not hit and len(json.load(open(path))) == 2
+        for o in outs:
+            o.zero_()
+        codec.check("leco_batch_run", P.leco_batch_run(batch, 3))
+        codec.sync()
+        check_outputs(torch, specs, cols, outs, sums, bounds)
+    finally:
+        P.leco_batch_destroy(batch)
+    # a different batch shape is a different member
+    batch2, outs2, sums2, bounds2 = make_batch(torch, codec, specs[:8], cols[:8], blobs[:8])
+    try:
+        st, _, _, hit = P.leco_batch_tune_cached(batch2, 3, path)
+        assert st == P.LECO_OK and not hit and len(json.load(open(path))) == 3
+    finally:
+        P.leco_batch_destroy(batch2)
