@@ -177,6 +177,26 @@ leco_status leco_encode_async(leco_ctx *ctx, const void *col_dev, uint64_t n,
                               void *blob_dev, uint64_t blob_cap,
                               uint64_t *blob_bytes_dev, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * encode of leco_encode_async, producing the same bytes, that allocates
+ * nothing.  Its scratch (per-partition models, word counts and offsets,
+ * variable starts, running hulls) lives in a fixed array of
+ * LECO_NOALLOC_SCRATCH_BYTES in each GPU's memory, held by the library
+ * until the process ends; every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other threads, other
+ * contexts) race and must be ordered by the caller.  About 56 bytes per
+ * partition are needed (plus 8 (m + 1) for variable starts and 8 n for
+ * minimax partitions longer than 4096 values); a call needing more than the
+ * array returns LECO_ENOSPC before anything is enqueued.  Requires
+ * blob_cap >= leco_max_blob_bytes(...); the blob size goes to
+ * *blob_bytes_dev. */
+#define LECO_NOALLOC_SCRATCH_BYTES (32u << 20)
+leco_status leco_encode_noalloc(leco_ctx *ctx, const void *col_dev, uint64_t n,
+                                leco_dtype dtype, const leco_partitioning *part,
+                                void *blob_dev, uint64_t blob_cap,
+                                uint64_t *blob_bytes_dev, hipStream_t stream);
+
 /* Decoder, full column (section 3.3, range decompression over [0, n)).
  *   out_dev: room for out_cap_elems values of the blob's dtype.  A blob with
  *   n > out_cap_elems raises LECO_ENOSPC on the device flag. */

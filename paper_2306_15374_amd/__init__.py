@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libleco_hip.so")
 
 LECO_OK, LECO_EINVAL, LECO_ENOMEM, LECO_ENOSPC, LECO_EFORMAT, LECO_ERANGE, LECO_EDEVICE = range(7)
 LECO_U32, LECO_U64 = 4, 8
+LECO_NOALLOC_SCRATCH_BYTES = 32 << 20
 STATUS_NAMES = {0: "LECO_OK", 1: "LECO_EINVAL", 2: "LECO_ENOMEM", 3: "LECO_ENOSPC",
                 4: "LECO_EFORMAT", 5: "LECO_ERANGE", 6: "LECO_EDEVICE"}
 
@@ -26,6 +27,7 @@ STATUS_NAMES = {0: "LECO_OK", 1: "LECO_EINVAL", 2: "LECO_ENOMEM", 3: "LECO_ENOSP
 EXPORTS = [
     "leco_create", "leco_destroy", "leco_last_error", "leco_sync", "leco_max_blob_bytes",
     "leco_blob_info", "leco_validate_blob", "leco_encode", "leco_encode_async",
+    "leco_encode_noalloc",
     "leco_decode_all", "leco_decode_range", "leco_random_access", "leco_filter_sum",
     "leco_diag_slope", "leco_diag_copy", "leco_encode_batch", "leco_batch_create",
     "leco_batch_destroy", "leco_batch_run", "leco_batch_run_graph", "leco_batch_tune",
@@ -128,6 +130,7 @@ def _bind(L: C.CDLL) -> C.CDLL:
         "leco_validate_blob": ([vp, vp, u64, vp], i32),
         "leco_encode": ([vp, vp, u64, i32, P(Partitioning), vp, u64, P(u64), vp], i32),
         "leco_encode_async": ([vp, vp, u64, i32, P(Partitioning), vp, u64, vp, vp], i32),
+        "leco_encode_noalloc": ([vp, vp, u64, i32, P(Partitioning), vp, u64, vp, vp], i32),
         "leco_decode_all": ([vp, vp, u64, vp, u64, vp], i32),
         "leco_decode_range": ([vp, vp, u64, u64, u64, vp, vp], i32),
         "leco_random_access": ([vp, vp, u64, vp, u64, vp, vp], i32),
@@ -263,6 +266,12 @@ def leco_encode_async(ctx: int, col, n: int, dtype: int, part: Partitioning, blo
                       blob_cap: int, size_dev, stream=None) -> int:
     return lib().leco_encode_async(ctx, _ptr(col), n, dtype, C.byref(part), _ptr(blob),
                                    blob_cap, _ptr(size_dev), _stream(stream))
+
+
+def leco_encode_noalloc(ctx: int, col, n: int, dtype: int, part: Partitioning, blob,
+                        blob_cap: int, size_dev, stream=None) -> int:
+    return lib().leco_encode_noalloc(ctx, _ptr(col), n, dtype, C.byref(part), _ptr(blob),
+                                     blob_cap, _ptr(size_dev), _stream(stream))
 
 
 def leco_decode_all(ctx: int, blob, blob_bytes: int, out, out_cap: int, stream=None) -> int:

@@ -4,6 +4,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -11,7 +13,32 @@
 
 using leco::kMaxPartLen;
 
+// Device scratch of the encoder variant that allocates nothing
+// (leco_encode_noalloc): a fixed array in every GPU's memory for the whole
+// process.  Its name is only a host-side stand-in; host code uses the
+// per-device address that noalloc_scratch_address looks up.
+constexpr size_t kNoAllocScratchBytes = size_t(LECO_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
 namespace {
+
+// Address of `scratch` on the current device, looked up once per device.
+hipError_t noalloc_scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  addr[device] = ptr;
+  *out = ptr;
+  return hipSuccess;
+}
 
 leco_status fail(leco_ctx* ctx, leco_status st, const char* fmt, ...) {
   if (ctx) {
@@ -112,9 +139,12 @@ struct EncodeCall {
 };
 
 // Checks the arguments, carves the encode scratch and copies variable starts.
+// The scratch is the context's (grown as needed), or when fixed is given the
+// fixed_bytes at fixed (LECO_ENOSPC if the call needs more).
 leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtype dtype,
                            const leco_partitioning* part, void* blob, uint64_t cap,
-                           hipStream_t stream, EncodeCall* call) {
+                           hipStream_t stream, EncodeCall* call, void* fixed = nullptr,
+                           size_t fixed_bytes = 0) {
   if (dtype != LECO_U32 && dtype != LECO_U64) return fail(ctx, LECO_EINVAL, "bad dtype");
   if (n > 0 && !col) return fail(ctx, LECO_EINVAL, "column is null");
   if (!blob) return fail(ctx, LECO_EINVAL, "blob is null");
@@ -133,8 +163,15 @@ leco_status prepare_encode(leco_ctx* ctx, const void* col, uint64_t n, leco_dtyp
   const bool hulls = part->regressor == LECO_REGRESSOR_MINIMAX && call->max_len > leco::kHullTileValues;
   const size_t o_hull = off;   off = align256(off + (hulls ? 8 * n : 0));
   void* scr = nullptr;
-  st = get_scratch(ctx, off, &scr);
-  if (st != LECO_OK) return st;
+  if (fixed) {
+    if (off > fixed_bytes)
+      return fail(ctx, LECO_ENOSPC, "encode needs %zu bytes of scratch, the fixed scratch holds %zu",
+                  off, fixed_bytes);
+    scr = fixed;
+  } else {
+    st = get_scratch(ctx, off, &scr);
+    if (st != LECO_OK) return st;
+  }
   char* b = static_cast<char*>(scr);
   leco::EncColumn& c = call->col;
   c.col = static_cast<const uint8_t*>(col);
@@ -206,7 +243,8 @@ leco_status leco_create(int hip_device, leco_ctx** out) {
     return LECO_ENOMEM;
   }
   ctx->pinned_u64 = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ctx->err_host) + 64);
-  if (hipMemset(ctx->err_dev, 0, 256) != hipSuccess) {
+  if (hipMemset(ctx->err_dev, 0, 256) != hipSuccess ||
+      noalloc_scratch_address(hip_device, &ctx->noalloc_scratch) != hipSuccess) {
     leco_destroy(ctx);
     return LECO_EDEVICE;
   }
@@ -335,9 +373,11 @@ leco_status leco_validate_blob(leco_ctx* ctx, const void* blob_dev, uint64_t blo
 
 static leco_status encode_common(leco_ctx* ctx, const void* col, uint64_t n, leco_dtype dtype,
                                  const leco_partitioning* part, void* blob, uint64_t cap,
-                                 uint64_t* size_dev, hipStream_t stream, EncodeCall* call) {
+                                 uint64_t* size_dev, hipStream_t stream, EncodeCall* call,
+                                 void* fixed = nullptr, size_t fixed_bytes = 0) {
   if (!ctx) return LECO_EINVAL;
-  leco_status st = prepare_encode(ctx, col, n, dtype, part, blob, cap, stream, call);
+  leco_status st = prepare_encode(ctx, col, n, dtype, part, blob, cap, stream, call, fixed,
+                                  fixed_bytes);
   if (st != LECO_OK) return st;
   if (size_dev) call->col.size_out = size_dev;
   HIP_TRY(ctx, leco::launch_encode_columns(ctx, nullptr, 1, call->col, call->col.m, call->max_len,
@@ -376,6 +416,23 @@ leco_status leco_encode_async(leco_ctx* ctx, const void* col_dev, uint64_t n, le
   EncodeCall call;
   return encode_common(ctx, col_dev, n, dtype, part, blob_dev, blob_cap, blob_bytes_dev, stream,
                        &call);
+}
+
+leco_status leco_encode_noalloc(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_dtype dtype,
+                                const leco_partitioning* part, void* blob_dev, uint64_t blob_cap,
+                                uint64_t* blob_bytes_dev, hipStream_t stream) {
+  if (!ctx) return LECO_EINVAL;
+  if (!blob_bytes_dev) return fail(ctx, LECO_EINVAL, "blob_bytes_dev is null");
+  if (!ctx->noalloc_scratch) return fail(ctx, LECO_EDEVICE, "no fixed scratch on this device");
+  uint64_t bound = 0;
+  leco_status st = leco_max_blob_bytes(n, dtype, part, &bound);
+  if (st != LECO_OK) return fail(ctx, st, "bad encode arguments");
+  if (blob_cap < bound)
+    return fail(ctx, LECO_ENOSPC, "encode needs capacity %llu", (unsigned long long)bound);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  EncodeCall call;
+  return encode_common(ctx, col_dev, n, dtype, part, blob_dev, blob_cap, blob_bytes_dev, stream,
+                       &call, ctx->noalloc_scratch, kNoAllocScratchBytes);
 }
 
 leco_status leco_encode_batch(leco_ctx* ctx, const leco_encode_job* jobs, uint64_t ncols,

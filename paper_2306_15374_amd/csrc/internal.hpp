@@ -117,6 +117,7 @@ struct leco_ctx {
   uint64_t* pinned_u64 = nullptr;  // pinned host words for small readbacks
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  void* noalloc_scratch = nullptr;  // this device's fixed encode scratch
   leco::Tune tune;
   std::string last_error;
 };
