@@ -395,10 +395,12 @@ def bench_served(args, codec=None):
                 break
         c = comp[0]
         nbytes = c.count * 8
-        buf = torch.empty(max((nbytes + 15) // 16 * 16, 16), dtype=torch.uint8, device="cuda")
+        head = c.out_dev % 16  # results are aligned to the value width
+        padded = (head + nbytes + 15) // 16 * 16
+        buf = torch.empty(max(padded, 16), dtype=torch.uint8, device="cuda")
         if nbytes:
-            codec.check("copy", P.leco_diag_copy(codec.ctx, c.out_dev, buf, (nbytes + 15) // 16 * 16))
-        got = buf[:nbytes].view(torch.int64)
+            codec.check("copy", P.leco_diag_copy(codec.ctx, c.out_dev - head, buf, padded))
+        got = buf[head: head + nbytes].view(torch.int64)
         col = cols[r["col"]]
         exp = col[torch.from_numpy(r["positions"].astype(np.int64)).cuda()] if r["kind"] == "ra" \
             else col[r["begin"]: r["end"]]
@@ -556,6 +558,7 @@ def bench_variable(args):
             t0 = time.perf_counter()
             starts = codec.partition(d, tau=args.tau)
             t_part.append(time.perf_counter() - t0)
+            log(f"{name}: partitioned in {t_part[-1] * 1e3:.1f} ms, {len(starts) - 1} partitions")
         t_part = float(np.median(t_part))
         m = len(starts) - 1
         part, keep = P.make_partitioning(starts=starts)
@@ -585,6 +588,7 @@ def bench_variable(args):
             t0 = time.perf_counter()
             starts_sp = codec.partition(d, tau=args.tau, start_positions=True)
             t_sp.append(time.perf_counter() - t0)
+            log(f"{name}: with starting partitions in {t_sp[-1] * 1e3:.1f} ms")
         blob_sp = codec.encode(d, starts=starts_sp)
         lens = np.diff(starts.astype(np.int64))
         per[name] = {"partitions": m, "mean_len": round(float(lens.mean()), 1),
@@ -608,15 +612,18 @@ def bench_variable(args):
         torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
-        # the oracle on the first 2^20 values of each column (one split segment)
+        # the oracle on the first 2^16 values of each column: its merge scan
+        # refits every grown partition at each step, so a sample of 2^20
+        # values of the polyline takes minutes
         import oracle
-        k = min(n, 1 << 20)
+        k = min(n, 1 << 16)
         t_p = t_d = 0.0
         for col in host_cols:
             c = col[:k]
             t0 = time.perf_counter()
             st = oracle.partition_greedy(c, tau=args.tau)
             t_p += time.perf_counter() - t0
+            log(f"oracle partitioned {k} values in {time.perf_counter() - t0:.2f} s")
             blob = oracle.encode(c, starts=st)
             t0 = time.perf_counter()
             assert np.array_equal(oracle.decode_all(blob), c)

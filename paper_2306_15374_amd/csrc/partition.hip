@@ -25,8 +25,11 @@
 // until one merges nothing.  The scan's state is the current partition
 // (its first index and size), and it is reset by every refused merge, so
 // the same speculation applies: chunks of the partition list are scanned
-// in parallel as if a partition began at each chunk's start, then walked in
-// order from the true state until both runs keep the same boundary.
+// in parallel as if a partition began at each chunk's start; then, in
+// rounds, every chunk whose entry state changed is walked again from it
+// until it keeps a boundary its recorded run also kept, and each chunk's
+// end state becomes the next one's entry, until no entry changes.  A run of
+// merges spanning c chunks takes about c rounds.
 #include <math.h>
 
 #include <utility>
@@ -667,14 +670,27 @@ __device__ uint64_t range_cost_wave(const uint8_t* col, uint32_t dtype, uint64_t
   if (len <= 64u * kCostRegs)
     return dtype == 8 ? range_cost_wave_regs(reinterpret_cast<const uint64_t*>(src), len)
                       : range_cost_wave_regs(reinterpret_cast<const uint32_t*>(src), len);
+  // longer ranges in blocks of 64 kCostRegs values, each block's loads
+  // issued together (indices clamped, the extra lanes masked)
   uint64_t vmin = ~uint64_t(0), vmax = 0;
   U128 sv{0, 0}, stv{0, 0};
-  for (uint64_t t = lane; t < len; t += 64) {
-    const uint64_t x = load_value(src, dtype, t);
-    vmin = x < vmin ? x : vmin;
-    vmax = x > vmax ? x : vmax;
-    sv = add128(sv, U128{x, 0});
-    stv = add128(stv, mul64x64(t, x));
+  for (uint64_t t0 = 0; t0 < len; t0 += 64u * kCostRegs) {
+    uint64_t x[kCostRegs];
+#pragma unroll
+    for (int k = 0; k < kCostRegs; ++k) {
+      const uint64_t t = t0 + lane + 64u * k;
+      x[k] = load_value(src, dtype, t < len ? t : len - 1);
+    }
+#pragma unroll
+    for (int k = 0; k < kCostRegs; ++k) {
+      const uint64_t t = t0 + lane + 64u * k;
+      if (t < len) {
+        vmin = x[k] < vmin ? x[k] : vmin;
+        vmax = x[k] > vmax ? x[k] : vmax;
+        sv = add128(sv, U128{x[k], 0});
+        stv = add128(stv, mul64x64(t, x[k]));
+      }
+    }
   }
   wave_minmax_u64(vmin, vmax);
   const uint64_t range = vmax - vmin;
@@ -683,10 +699,22 @@ __device__ uint64_t range_cost_wave(const uint8_t* col, uint32_t dtype, uint64_t
     wave_sum_u128x2(sv, stv);
     const double th = ls_slope(len, sv, stv);
     int64_t rmin = INT64_MAX, rmax = INT64_MIN;
-    for (uint64_t t = lane; t < len; t += 64) {
-      const int64_t rr = int64_t(load_value(src, dtype, t) - vmin) - predict(th, uint32_t(t));
-      rmin = rr < rmin ? rr : rmin;
-      rmax = rr > rmax ? rr : rmax;
+    for (uint64_t t0 = 0; t0 < len; t0 += 64u * kCostRegs) {
+      uint64_t x[kCostRegs];
+#pragma unroll
+      for (int k = 0; k < kCostRegs; ++k) {
+        const uint64_t t = t0 + lane + 64u * k;
+        x[k] = load_value(src, dtype, t < len ? t : len - 1);
+      }
+#pragma unroll
+      for (int k = 0; k < kCostRegs; ++k) {
+        const uint64_t t = t0 + lane + 64u * k;
+        if (t < len) {
+          const int64_t rr = int64_t(x[k] - vmin) - predict(th, uint32_t(t));
+          rmin = rr < rmin ? rr : rmin;
+          rmax = rr > rmax ? rr : rmax;
+        }
+      }
     }
     wave_minmax_i64(rmin, rmax);
     choose_model(md, th, rmin, rmax);
@@ -787,13 +815,11 @@ __global__ __launch_bounds__(kEncBlock) void k_costs_long(const uint8_t* __restr
 //   merge when union < cc + cost[k]: the current partition grows (cc =
 //   union); else boundary k is kept, and partition k is the current one
 //   (a = k, cc = cost[k]).
-// The pass keeps a bitmap of kept boundaries (bit 0 always set) and, for a
-// current partition that absorbed others, its size in pcost[a] when it
-// closes.
+// The pass keeps a bitmap of kept boundaries (bit 0 always set); the
+// partitions that absorbed others are sized once the pass is done.
 
 constexpr uint32_t kMergeChunkLog2 = 8;  // boundaries per speculative chunk
 constexpr uint64_t kMergeChunk = uint64_t(1) << kMergeChunkLog2;
-constexpr uint64_t kMergeGroup = 64;     // chunks per first-level fix-up walk
 
 struct MergeState {
   uint64_t a;   // boundary where the current partition begins
@@ -819,8 +845,7 @@ template <bool kFix>
 __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
                            const uint64_t* __restrict__ s, const uint64_t* __restrict__ cost,
                            const uint64_t* __restrict__ pair, uint64_t max_len, uint64_t kb,
-                           uint64_t ke, MergeState& st, unsigned long long* __restrict__ keep,
-                           uint64_t* __restrict__ pcost) {
+                           uint64_t ke, MergeState& st, unsigned long long* __restrict__ keep) {
   const uint32_t lane = threadIdx.x & 63;
   uint64_t k = kb;
   while (k < ke) {
@@ -870,7 +895,6 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
     }
     bool met = false;
     if (lane == 0) {
-      pcost[st.a] = st.cc;
       if (kFix) met = bit_set(keep, k);
       if (!met) set_bits(keep, k, 1);
     }
@@ -885,12 +909,11 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
 
 // Speculative pass: one wavefront per chunk of kMergeChunk boundaries,
 // scanned as if its first boundary were kept (chunk 0 from the true start);
-// each chunk's end state goes to states.
+// each chunk's end state goes to out.
 __global__ __launch_bounds__(kEncBlock) void k_merge_spec(
     const uint8_t* __restrict__ col, uint32_t dtype, const uint64_t* __restrict__ s,
     const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair, uint64_t m,
-    uint64_t max_len, unsigned long long* __restrict__ keep, uint64_t* __restrict__ pcost,
-    MergeState* __restrict__ states) {
+    uint64_t max_len, unsigned long long* __restrict__ keep, MergeState* __restrict__ out) {
   const uint64_t q = uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6);
   const uint64_t k0 = q << kMergeChunkLog2;
   if (k0 >= m) return;
@@ -904,62 +927,64 @@ __global__ __launch_bounds__(kEncBlock) void k_merge_spec(
   } else {
     st = MergeState{k0 - 1, cost[k0 - 1]};
   }
-  merge_walk<false>(col, dtype, s, cost, pair, max_len, kb, ke, st, keep, pcost);
-  if ((threadIdx.x & 63) == 0) states[q] = st;
+  merge_walk<false>(col, dtype, s, cost, pair, max_len, kb, ke, st, keep);
+  if ((threadIdx.x & 63) == 0) out[q] = st;
 }
 
-// Walks chunks [q, q_end) in order from state st (fix mode); returns true
-// at the first meeting (the rest of that chunk, and of the run, is then the
-// recorded one), else false with st the state after the last chunk.
-__device__ bool walk_chunks(const uint8_t* col, uint32_t dtype, const uint64_t* s,
-                            const uint64_t* cost, const uint64_t* pair, uint64_t m,
-                            uint64_t max_len, uint64_t q, uint64_t q_end, MergeState& st,
-                            unsigned long long* keep, uint64_t* pcost) {
-  for (; q < q_end; ++q) {
-    const uint64_t kb = q << kMergeChunkLog2;
-    if (kb >= m) break;
-    const uint64_t ke = m - kb < kMergeChunk ? m : kb + kMergeChunk;
-    if (merge_walk<true>(col, dtype, s, cost, pair, max_len, kb, ke, st, keep, pcost)) return true;
-  }
-  return false;
+// Fix-up rounds.  out[q] is the end state of the run recorded in chunk q's
+// bits, entry[q] the state chunk q is assumed to begin in (the end state of
+// chunk q - 1).  A round re-walks every chunk whose entry changed: the walk
+// rewrites the chunk's bits from its entry until it keeps a boundary the
+// recorded run also kept (from there on that run is right, and so is its
+// end state) or reaches the chunk's end (its end state is the new out[q]).
+// Chunk 0 begins where the column does, so after round r at least chunks
+// 0..r are right; rounds repeat until no entry changes.
+__global__ __launch_bounds__(64) void k_merge_round_init(const MergeState* __restrict__ out,
+                                                        uint64_t nchunks,
+                                                        MergeState* __restrict__ entry,
+                                                        uint8_t* __restrict__ dirty) {
+  const uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nchunks) return;
+  if (q > 0) entry[q] = out[q - 1];
+  dirty[q] = q > 0 ? 1 : 0;
 }
 
-// First-level fix-up: one wavefront per group of kMergeGroup chunks walks
-// chunks 1.. of its group in order from the state the previous chunk ends
-// in; the group's end state (as if its first chunk began as assumed) goes
-// to gstates.
-__global__ __launch_bounds__(64) void k_merge_fix(
+__global__ __launch_bounds__(kEncBlock) void k_merge_round(
     const uint8_t* __restrict__ col, uint32_t dtype, const uint64_t* __restrict__ s,
     const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair, uint64_t m,
-    uint64_t max_len, unsigned long long* __restrict__ keep, uint64_t* __restrict__ pcost,
-    const MergeState* __restrict__ states, uint64_t nchunks, MergeState* __restrict__ gstates) {
-  const uint64_t q0 = uint64_t(blockIdx.x) * kMergeGroup;
-  if (q0 >= nchunks) return;
-  const uint64_t q_end = q0 + kMergeGroup < nchunks ? q0 + kMergeGroup : nchunks;
-  MergeState st = states[q0];
-  for (uint64_t q = q0 + 1; q < q_end; ++q)
-    if (walk_chunks(col, dtype, s, cost, pair, m, max_len, q, q + 1, st, keep, pcost))
-      st = states[q];
-  if (threadIdx.x == 0) gstates[blockIdx.x] = st;
+    uint64_t max_len, unsigned long long* __restrict__ keep, const MergeState* __restrict__ entry,
+    MergeState* __restrict__ out, uint8_t* __restrict__ dirty, uint64_t nchunks) {
+  const uint64_t q = uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6);
+  if (q >= nchunks || !dirty[q]) return;
+  const uint64_t kb = q << kMergeChunkLog2;
+  const uint64_t ke = m - kb < kMergeChunk ? m : kb + kMergeChunk;
+  MergeState st = entry[q];
+  const bool met = merge_walk<true>(col, dtype, s, cost, pair, max_len, kb, ke, st, keep);
+  if ((threadIdx.x & 63) == 0) {
+    if (!met) out[q] = st;
+    dirty[q] = 0;
+  }
 }
 
-// Second-level fix-up: one wavefront walks each group from the true state
-// the previous group ends in, until it meets the recorded run; then records
-// the size of the last partition.
-__global__ __launch_bounds__(64) void k_merge_join(
-    const uint8_t* __restrict__ col, uint32_t dtype, const uint64_t* __restrict__ s,
-    const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair, uint64_t m,
-    uint64_t max_len, unsigned long long* __restrict__ keep, uint64_t* __restrict__ pcost,
-    const MergeState* __restrict__ gstates, uint64_t nchunks) {
-  const uint64_t ngroups = (nchunks + kMergeGroup - 1) / kMergeGroup;
-  MergeState st = gstates[0];
-  for (uint64_t g = 1; g < ngroups; ++g) {
-    const uint64_t q0 = g * kMergeGroup;
-    const uint64_t q_end = q0 + kMergeGroup < nchunks ? q0 + kMergeGroup : nchunks;
-    if (walk_chunks(col, dtype, s, cost, pair, m, max_len, q0, q_end, st, keep, pcost))
-      st = gstates[g];
+// entry[q] = out[q - 1] where that changed, marking chunk q for the next
+// round; *changes counts them.
+__global__ __launch_bounds__(256) void k_merge_propagate(const MergeState* __restrict__ out,
+                                                        uint64_t nchunks,
+                                                        MergeState* __restrict__ entry,
+                                                        uint8_t* __restrict__ dirty,
+                                                        unsigned long long* __restrict__ changes) {
+  uint32_t c = 0;
+  for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x + 1; q < nchunks;
+       q += uint64_t(gridDim.x) * blockDim.x) {
+    const MergeState o = out[q - 1];
+    if (entry[q].a != o.a) {
+      entry[q] = o;
+      dirty[q] = 1;
+      ++c;
+    }
   }
-  if (threadIdx.x == 0) pcost[st.a] = st.cc;
+  for (int off = 32; off > 0; off >>= 1) c += uint32_t(__shfl_xor(int(c), off, 64));
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(changes, static_cast<unsigned long long>(c));
 }
 
 // ---- compaction after a pass --------------------------------------------------------
@@ -988,15 +1013,14 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_count(const unsigned long l
   if (threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
-// Copies the kept starts to their new places with their sizes (the size
-// recorded at close for a partition that absorbed others, its own
-// otherwise), whether it absorbed others, and its old index.
+// Copies the kept starts to their new places with their sizes (a
+// partition that absorbed others is sized afterwards), whether it absorbed
+// others, and its old index.
 __global__ __launch_bounds__(kScanBlock) void k_keep_emit(
     const unsigned long long* __restrict__ keep, uint64_t m, const uint64_t* __restrict__ offsets,
     const uint64_t* __restrict__ starts, const uint64_t* __restrict__ cost,
-    const uint64_t* __restrict__ pcost, uint64_t* __restrict__ starts_out,
-    uint64_t* __restrict__ cost_out, uint8_t* __restrict__ changed_out,
-    uint64_t* __restrict__ old_out) {
+    uint64_t* __restrict__ starts_out, uint64_t* __restrict__ cost_out,
+    uint8_t* __restrict__ changed_out, uint64_t* __restrict__ old_out) {
   const uint64_t w0 = uint64_t(blockIdx.x) * kItemsPerBlock + threadIdx.x * 4;
   uint32_t c = 0;
 #pragma unroll
@@ -1010,7 +1034,7 @@ __global__ __launch_bounds__(kScanBlock) void k_keep_emit(
       if (!kept_bit(keep, k, m)) continue;
       const bool absorbed = k + 1 < m && !kept_bit(keep, k + 1, m);
       starts_out[out] = starts[k];
-      cost_out[out] = absorbed ? pcost[k] : cost[k];
+      cost_out[out] = cost[k];
       changed_out[out] = absorbed ? 1 : 0;
       old_out[out] = k;
       ++out;
@@ -1163,20 +1187,19 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   uint64_t m = 0;
   P_TRY(scan_counts(counts, nb, &m, stream));
   uint64_t *starts = nullptr, *starts2 = nullptr, *cost = nullptr, *cost2 = nullptr,
-           *pair = nullptr, *pair2 = nullptr, *old = nullptr, *keep_counts = nullptr,
-           *pcost = nullptr;
-  uint8_t *changed = nullptr, *dirty = nullptr;
-  unsigned long long* keep = nullptr;
-  leco::MergeState *mstates = nullptr, *gstates = nullptr;
+           *pair = nullptr, *pair2 = nullptr, *old = nullptr, *keep_counts = nullptr;
+  uint8_t *changed = nullptr, *dirty = nullptr, *cdirty = nullptr;
+  unsigned long long *keep = nullptr, *changes = nullptr;
+  leco::MergeState *mout = nullptr, *mentry = nullptr;
   const uint64_t kwords = (m + 63) / 64;
   const uint64_t nbk = (kwords + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
   const uint64_t nchunks0 = (m + leco::kMergeChunk - 1) / leco::kMergeChunk;
-  const uint64_t ngroups0 = (nchunks0 + leco::kMergeGroup - 1) / leco::kMergeGroup;
   if (!buf.alloc(&starts, m + 1) || !buf.alloc(&starts2, m + 1) || !buf.alloc(&cost, m) ||
       !buf.alloc(&cost2, m) || !buf.alloc(&pair, m) || !buf.alloc(&pair2, m) ||
-      !buf.alloc(&old, m) || !buf.alloc(&pcost, m) || !buf.alloc(&changed, m) ||
-      !buf.alloc(&dirty, m) || !buf.alloc(&keep, kwords) || !buf.alloc(&keep_counts, nbk) ||
-      !buf.alloc(&mstates, nchunks0) || !buf.alloc(&gstates, ngroups0))
+      !buf.alloc(&old, m) || !buf.alloc(&changed, m) || !buf.alloc(&dirty, m) ||
+      !buf.alloc(&keep, kwords) || !buf.alloc(&keep_counts, nbk) ||
+      !buf.alloc(&mout, nchunks0) || !buf.alloc(&mentry, nchunks0) ||
+      !buf.alloc(&cdirty, nchunks0) || !buf.alloc(&changes, 1))
     return pfail(ctx, LECO_ENOMEM, "partition: partition arrays");
   hipLaunchKernelGGL(leco::k_bitmap_emit, dim3(uint32_t(nb)), dim3(leco::kScanBlock), 0, stream,
                      reinterpret_cast<const uint64_t*>(bitmap), nwords, counts, starts);
@@ -1221,19 +1244,29 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
     if (m < 2) break;
     const uint64_t words = (m + 63) / 64;
     const uint64_t nchunks = (m + leco::kMergeChunk - 1) / leco::kMergeChunk;
-    const uint64_t ngroups = (nchunks + leco::kMergeGroup - 1) / leco::kMergeGroup;
     P_TRY(hipMemsetAsync(keep, 0, 8 * words, stream));
-    hipLaunchKernelGGL(leco::k_merge_spec,
-                       dim3(uint32_t((nchunks + leco::kEncWaves - 1) / leco::kEncWaves)),
-                       dim3(leco::kEncBlock), 0, stream, col, w, starts, cost, pair, m,
-                       prm->max_len, keep, pcost, mstates);
+    const uint32_t gch = uint32_t((nchunks + leco::kEncWaves - 1) / leco::kEncWaves);
+    hipLaunchKernelGGL(leco::k_merge_spec, dim3(gch), dim3(leco::kEncBlock), 0, stream, col, w,
+                       starts, cost, pair, m, prm->max_len, keep, mout);
     P_TRY(hipGetLastError());
-    hipLaunchKernelGGL(leco::k_merge_fix, dim3(uint32_t(ngroups)), dim3(64), 0, stream, col, w,
-                       starts, cost, pair, m, prm->max_len, keep, pcost, mstates, nchunks, gstates);
+    // fix-up rounds until no chunk's entry state changes
+    hipLaunchKernelGGL(leco::k_merge_round_init, dim3(uint32_t((nchunks + 63) / 64)), dim3(64), 0,
+                       stream, mout, nchunks, mentry, cdirty);
     P_TRY(hipGetLastError());
-    hipLaunchKernelGGL(leco::k_merge_join, dim3(1), dim3(64), 0, stream, col, w, starts, cost,
-                       pair, m, prm->max_len, keep, pcost, gstates, nchunks);
-    P_TRY(hipGetLastError());
+    const uint64_t gp = (nchunks + 255) / 256;
+    for (uint64_t r = 0; r < nchunks; ++r) {  // chunk r is right after round r
+      hipLaunchKernelGGL(leco::k_merge_round, dim3(gch), dim3(leco::kEncBlock), 0, stream, col, w,
+                         starts, cost, pair, m, prm->max_len, keep, mentry, mout, cdirty, nchunks);
+      P_TRY(hipGetLastError());
+      P_TRY(hipMemsetAsync(changes, 0, 8, stream));
+      hipLaunchKernelGGL(leco::k_merge_propagate, dim3(uint32_t(gp < grid_cap ? gp : grid_cap)),
+                         dim3(256), 0, stream, mout, nchunks, mentry, cdirty, changes);
+      P_TRY(hipGetLastError());
+      unsigned long long nchanged = 0;
+      P_TRY(hipMemcpyAsync(&nchanged, changes, 8, hipMemcpyDeviceToHost, stream));
+      P_TRY(hipStreamSynchronize(stream));
+      if (nchanged == 0) break;
+    }
     const uint64_t blocks = (words + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
     hipLaunchKernelGGL(leco::k_keep_count, dim3(uint32_t(blocks)), dim3(leco::kScanBlock), 0,
                        stream, keep, m, keep_counts);
@@ -1242,10 +1275,11 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
     P_TRY(scan_counts(keep_counts, blocks, &m2, stream));
     if (m2 == m) break;  // the pass merged nothing
     hipLaunchKernelGGL(leco::k_keep_emit, dim3(uint32_t(blocks)), dim3(leco::kScanBlock), 0,
-                       stream, keep, m, keep_counts, starts, cost, pcost, starts2, cost2, changed,
-                       old);
+                       stream, keep, m, keep_counts, starts, cost, starts2, cost2, changed, old);
     P_TRY(hipGetLastError());
     P_TRY(hipMemcpyAsync(starts2 + m2, &n, 8, hipMemcpyHostToDevice, stream));
+    // sizes of the partitions that absorbed others
+    P_TRY(costs(starts2, m2, 1, changed, cost2));
     if (m2 >= 2) {
       // pair sizes for the next pass: reused, or sized where a merge happened
       hipLaunchKernelGGL(leco::k_pair_reuse, dim3(uint32_t((m2 - 1 + 255) / 256)), dim3(256), 0,

@@ -60,17 +60,21 @@ def to_request(r):
 
 
 def fetch(torch, codec, comp):
-    """Copies a completion's result (device memory owned by the server) to
-    the host through the library's plain copy kernel."""
+    """Copies a completion's result (device memory owned by the server,
+    aligned to the value width) to the host through the library's plain
+    copy kernel, from the 16-byte boundary below it."""
     nbytes = comp.count * comp.dtype
-    padded = (nbytes + 15) // 16 * 16
+    assert comp.out_dev % comp.dtype == 0
+    head = comp.out_dev % 16
+    padded = (head + nbytes + 15) // 16 * 16
     buf = torch.empty(max(padded, 16), dtype=torch.uint8, device="cuda")
-    if padded:
+    if nbytes:
         lib = P.lib()
-        assert lib.leco_diag_copy(codec.ctx, comp.out_dev, buf.data_ptr(), padded,
+        assert lib.leco_diag_copy(codec.ctx, comp.out_dev - head, buf.data_ptr(), padded,
                                   torch.cuda.current_stream().cuda_stream) == P.LECO_OK
     torch.cuda.synchronize()
-    return buf[:nbytes].cpu().numpy().view(np.uint32 if comp.dtype == 4 else np.uint64).copy()
+    return buf[head: head + nbytes].cpu().numpy().view(
+        np.uint32 if comp.dtype == 4 else np.uint64).copy()
 
 
 def expected(r, hosts):
