@@ -26,10 +26,13 @@
 // (its first index and size), and it is reset by every refused merge, so
 // the same speculation applies: chunks of the partition list are scanned
 // in parallel as if a partition began at each chunk's start; then, in
-// rounds, every chunk whose entry state changed is walked again from it
-// until it keeps a boundary its recorded run also kept, and each chunk's
-// end state becomes the next one's entry, until no entry changes.  A run of
-// merges spanning c chunks takes about c rounds.
+// rounds of alternating parity, every chunk whose left neighbour's end
+// state changed is walked again from it until it keeps a boundary its
+// recorded run also kept.  A run of merges spanning c chunks takes about c
+// rounds.  Within a run, 64 steps are sized at once (one per lane), and a
+// long current partition is represented by the convex hulls of its points,
+// which bound its residuals exactly for any slope, so a step costs the
+// values it adds rather than the whole union.
 #include <math.h>
 
 #include <utility>
@@ -821,10 +824,167 @@ __global__ __launch_bounds__(kEncBlock) void k_costs_long(const uint8_t* __restr
 constexpr uint32_t kMergeChunkLog2 = 8;  // boundaries per speculative chunk
 constexpr uint64_t kMergeChunk = uint64_t(1) << kMergeChunkLog2;
 
+__device__ inline uint64_t shfl_up64(uint64_t x, int d) {
+  return uint64_t(__shfl_up(static_cast<unsigned long long>(x), d, 64));
+}
+
+// Lane k's value of x, k uniform across the wavefront.
+__device__ inline uint64_t readlane64(uint64_t x, uint32_t k) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), int(k)));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), int(k)));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// Value summary of a range of the column: smallest and largest value, and
+// the sums of v and of t * v (t counted from the range's first position)
+// modulo 2^128: the least-squares slope needs no more (N is the same for
+// shifted values, and exact because |N| < 2^121).
+struct RangeSum {
+  uint64_t vmin, vmax;
+  U128 sy, sty;
+};
+
+// The summary of [x, z) from those of [x, y) and [y, z).
+__device__ inline RangeSum join(const RangeSum& a, const RangeSum& b, uint64_t a_len) {
+  RangeSum r;
+  r.vmin = a.vmin < b.vmin ? a.vmin : b.vmin;
+  r.vmax = a.vmax > b.vmax ? a.vmax : b.vmax;
+  r.sy = add128(a.sy, b.sy);
+  r.sty = add128(add128(a.sty, b.sty), mul128x64(b.sy, a_len));
+  return r;
+}
+
 struct MergeState {
   uint64_t a;   // boundary where the current partition begins
   uint64_t cc;  // its size in bytes
+  RangeSum sum; // its values' summary
 };
+
+// Convex hulls of the current partition's points (t, v_t), t counted from
+// its first value: the upper hull (left to right, right turns only) and the
+// lower one.  Over any set of points, v_t - theta1 * t is largest at an
+// upper-hull vertex and smallest at a lower-hull vertex, whatever theta1;
+// so is the exact residual v_t - floor(theta1 * t), the ceiling of that real
+// number.  The encoder's residual takes the binary64 product, whose floor
+// exceeds the exact one by 1 exactly when the product rounds up onto an
+// integer (merge_walk checks for that).  A long run of merges then sizes
+// each union from the hulls and the values it adds, not from all its values.
+constexpr uint32_t kHullMax = 64;              // vertices per hull
+constexpr uint64_t kHullBuildMin = 1024;       // shorter partitions are scanned whole
+constexpr uint64_t kHullBuildMax = 16384;      // values a hull is first built from
+constexpr uint64_t kHullAppendMax = 8192;      // values one step may append
+constexpr uint64_t kHullNewMax = 4096;         // new values a batch sizes by scanning
+enum : uint32_t { kHullNone = 0, kHullValid = 1, kHullDead = 2 };
+
+struct ChainHull {
+  uint32_t nu, nl, state, pad;
+  uint32_t tu[kHullMax], tl[kHullMax];
+  uint64_t xu[kHullMax], xl[kHullMax];
+};
+
+// The hulls' counts and state, identical in every lane of the wavefront.
+struct HullRegs {
+  uint32_t nu, nl, state;
+};
+
+__device__ inline void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Sign of (b - a) x (c - a) for points with ta < tb < tc whose values lie
+// within 2^61 of each other.
+__device__ inline int turn(uint32_t ta, uint64_t xa, uint32_t tb, uint64_t xb, uint32_t tc,
+                           uint64_t xc) {
+  const __int128 l = __int128(int64_t(tb - ta)) * __int128(int64_t(xc - xa));
+  const __int128 r = __int128(int64_t(xb - xa)) * __int128(int64_t(tc - ta));
+  return l > r ? 1 : (l < r ? -1 : 0);
+}
+
+// Appends the points [u0, u1) of the partition beginning at column position
+// sa to both hulls (monotone chain); too many vertices mark them dead.
+// Called by a whole wavefront with uniform arguments; lane 0 writes.
+__device__ inline void hull_append(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t sa,
+                                   uint64_t u0, uint64_t u1, ChainHull& h, HullRegs& hr) {
+  const uint32_t lane = threadIdx.x & 63;
+  for (uint64_t b = u0; b < u1 && hr.state == kHullValid; b += 64) {
+    const uint64_t x = load_value(col, dtype, sa + (b + lane < u1 ? b + lane : u1 - 1));
+    const uint32_t cnt = u1 - b < 64 ? uint32_t(u1 - b) : 64u;
+    for (uint32_t q = 0; q < cnt; ++q) {
+      const uint64_t xq = readlane64(x, q);
+      const uint32_t tq = uint32_t(b + q);
+      while (hr.nu >= 2 &&
+             turn(h.tu[hr.nu - 2], h.xu[hr.nu - 2], h.tu[hr.nu - 1], h.xu[hr.nu - 1], tq, xq) >= 0)
+        --hr.nu;
+      while (hr.nl >= 2 &&
+             turn(h.tl[hr.nl - 2], h.xl[hr.nl - 2], h.tl[hr.nl - 1], h.xl[hr.nl - 1], tq, xq) <= 0)
+        --hr.nl;
+      if (hr.nu == kHullMax || hr.nl == kHullMax) {
+        hr.state = kHullDead;
+        break;
+      }
+      if (lane == 0) {
+        h.tu[hr.nu] = tq;
+        h.xu[hr.nu] = xq;
+        h.tl[hr.nl] = tq;
+        h.xl[hr.nl] = xq;
+      }
+      ++hr.nu;
+      ++hr.nl;
+      wave_lds_order();
+    }
+  }
+}
+
+__device__ inline void hull_store(ChainHull* __restrict__ g, const ChainHull& h, const HullRegs& hr) {
+  const uint32_t lane = threadIdx.x & 63;
+  if (hr.state == kHullValid) {
+    if (lane < hr.nu) {
+      g->tu[lane] = h.tu[lane];
+      g->xu[lane] = h.xu[lane];
+    }
+    if (lane < hr.nl) {
+      g->tl[lane] = h.tl[lane];
+      g->xl[lane] = h.xl[lane];
+    }
+  }
+  if (lane == 0) {
+    g->nu = hr.nu;
+    g->nl = hr.nl;
+    g->state = hr.state;
+  }
+}
+
+__device__ inline HullRegs hull_load(const ChainHull* __restrict__ g, ChainHull& h) {
+  const uint32_t lane = threadIdx.x & 63;
+  HullRegs hr{g->nu, g->nl, g->state};
+  if (hr.state == kHullValid) {
+    if (lane < hr.nu) {
+      h.tu[lane] = g->tu[lane];
+      h.xu[lane] = g->xu[lane];
+    }
+    if (lane < hr.nl) {
+      h.tl[lane] = g->tl[lane];
+      h.xl[lane] = g->xl[lane];
+    }
+  }
+  wave_lds_order();
+  return hr;
+}
+
+// The encoder's residual v - vmin - floor(fl(theta1 * t)) at a hull vertex,
+// plus 1 when the binary64 product rounded up onto an integer (then the
+// exact residual is one more; `up` says so).  `gap` is 1 - frac(theta1 * t)
+// of the exact product, to within 2^-50, when up is false.
+__device__ inline int64_t vertex_residual(double th, uint32_t t, uint64_t x, uint64_t vmin,
+                                          bool& up, double& gap) {
+  const double p = __dmul_rn(th, double(t));
+  const double fp = floor(p);
+  const double e = __fma_rn(th, double(t), -p);  // exact: theta1 * t - p
+  up = fp == p && e < 0.0;
+  gap = ((fp + 1.0) - p) - e;
+  return int64_t(x - vmin) - int64_t(fp) + (up ? 1 : 0);
+}
 
 __device__ inline void set_bits(unsigned long long* bits, uint64_t k, uint64_t mask) {
   const uint64_t w = k >> 6, off = k & 63;
@@ -840,13 +1000,17 @@ __device__ inline void clear_bit(unsigned long long* bits, uint64_t k) {
 // there and the walk sets the kept bits.  kFix = true: the bits are another
 // run's, made from a different state; the walk rewrites them until it keeps
 // a boundary that run also kept (from there on both runs are the same) and
-// returns true at that point.  Called by a whole wavefront.
+// returns true at that point.  h / hr: the current partition's hulls, valid
+// when hr.state is kHullValid and a merge is pending.  Called by a whole
+// wavefront.
 template <bool kFix>
 __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
                            const uint64_t* __restrict__ s, const uint64_t* __restrict__ cost,
-                           const uint64_t* __restrict__ pair, uint64_t max_len, uint64_t kb,
-                           uint64_t ke, MergeState& st, unsigned long long* __restrict__ keep) {
+                           const uint64_t* __restrict__ pair, const RangeSum* __restrict__ psum,
+                           uint64_t max_len, uint64_t kb, uint64_t ke, MergeState& st,
+                           unsigned long long* __restrict__ keep, ChainHull& h, HullRegs& hr) {
   const uint32_t lane = threadIdx.x & 63;
+  constexpr uint64_t kWide = uint64_t(1) << 61;  // value spread beyond which no line is fitted
   uint64_t k = kb;
   while (k < ke) {
     if (st.a + 1 == k) {
@@ -873,6 +1037,7 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
         const uint64_t last = uint64_t(63 - __clzll(static_cast<long long>(vmask)));
         st.a = k + last;
         st.cc = cost[st.a];
+        st.sum = psum[st.a];
         k += last + 1;
         continue;
       }
@@ -880,41 +1045,250 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
       if (kFix && lane == 0) clear_bit(keep, km);
       st.a = km - 1;
       st.cc = pair[km - 1];
+      st.sum = join(psum[km - 1], psum[km], s[km] - s[km - 1]);
+      hr = HullRegs{0, 0, kHullNone};
       k = km + 1;
       continue;
     }
-    // The current partition absorbed others: size its union with partition
-    // k now, with the encoder's fit.
-    const uint64_t lo = s[st.a], hi = s[k + 1], ck = cost[k];
-    const uint64_t u = hi - lo <= max_len ? range_cost_wave(col, dtype, lo, hi) : kNoMerge;
-    if (u != kNoMerge && u < st.cc + ck) {
-      if (kFix && lane == 0) clear_bit(keep, k);
-      st.cc = u;
-      ++k;
+    // The current partition absorbed others.  Lane l sizes its union with
+    // partitions k .. k+l: the union's sums and extremes from the
+    // partitions' summaries (a prefix across lanes), its slope from them,
+    // and its residual range from the current partition's hulls and one
+    // pass over the added values, every value broadcast to all lanes, each
+    // lane predicting with its own slope.  Without hulls the pass covers
+    // every value of the longest union, and the lanes taken are those
+    // whose union is at most about twice the current length, so a run that
+    // stops early wastes little of it.
+    const uint64_t sa = s[st.a];
+    const uint64_t lold = s[k] - sa;
+    if (hr.state == kHullNone && lold >= kHullBuildMin) {
+      if (lold <= kHullBuildMax && st.sum.vmax - st.sum.vmin < kWide) {
+        hr = HullRegs{0, 0, kHullValid};
+        hull_append(col, dtype, sa, 0, lold, h, hr);
+      } else {
+        hr.state = kHullDead;
+      }
+    }
+    const bool via_hull = hr.state == kHullValid;
+    const uint64_t j = k + lane;
+    const uint64_t len0 = s[k + 1] - sa;
+    const uint64_t lcap = len0 + (len0 > 512 ? len0 : 512);
+    const uint64_t e_l = j < ke ? s[j + 1] : 0;
+    const bool act =
+        j < ke && (lane == 0 || (via_hull ? e_l - sa - lold <= kHullNewMax : e_l - sa <= lcap));
+    const uint32_t nact = uint32_t(__popcll(__ballot(act)));  // a prefix of the lanes
+    const uint64_t len_l = act ? e_l - sa : 0;
+    RangeSum u{~uint64_t(0), 0, U128{0, 0}, U128{0, 0}};
+    if (act) {
+      u = psum[j];
+      u.sty = add128(u.sty, mul128x64(u.sy, s[j] - sa));
+    }
+    // inclusive prefix over the lanes (the inactive ones add nothing)
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t mn = shfl_up64(u.vmin, d), mx = shfl_up64(u.vmax, d);
+      const U128 y{shfl_up64(u.sy.lo, d), shfl_up64(u.sy.hi, d)};
+      const U128 ty{shfl_up64(u.sty.lo, d), shfl_up64(u.sty.hi, d)};
+      if (int(lane) >= d) {
+        u.vmin = mn < u.vmin ? mn : u.vmin;
+        u.vmax = mx > u.vmax ? mx : u.vmax;
+        u.sy = add128(u.sy, y);
+        u.sty = add128(u.sty, ty);
+      }
+    }
+    const uint64_t vmin = st.sum.vmin < u.vmin ? st.sum.vmin : u.vmin;
+    const uint64_t vmax = st.sum.vmax > u.vmax ? st.sum.vmax : u.vmax;
+    const uint64_t range = vmax - vmin;
+    const bool fits = act && len_l <= max_len;
+    const bool lin = fits && len_l > 1 && range < kWide;
+    double th = 0.0;
+    if (lin) th = ls_slope(len_l, add128(st.sum.sy, u.sy), add128(st.sum.sty, u.sty));
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+    const uint64_t lmax = readlane64(len_l, nact - 1);
+    const uint8_t* src = col + sa * dtype;
+    auto scan = [&](uint64_t tb) {
+      for (uint64_t t0 = tb; t0 < lmax; t0 += 64) {
+        const uint64_t t = t0 + lane;
+        const uint64_t x = load_value(src, dtype, t < lmax ? t : lmax - 1);
+        const uint32_t cnt = lmax - t0 < 64 ? uint32_t(lmax - t0) : 64u;
+        for (uint32_t q = 0; q < cnt; ++q) {
+          const uint64_t xq = readlane64(x, q);
+          const uint64_t tq = t0 + q;
+          if (lin && tq < len_l) {
+            const int64_t rr = int64_t(xq - vmin) - predict(th, uint32_t(tq));
+            rmin = rr < rmin ? rr : rmin;
+            rmax = rr > rmax ? rr : rmax;
+          }
+        }
+      }
+    };
+    bool scan_all = !via_hull;
+    if (via_hull) {
+      scan(lold);  // the added values
+      bool unsure = false;
+      if (lin) {
+        if (!(__dmul_rn(fabs(th), double(len_l)) < 2147483648.0)) {
+          unsure = true;  // products too large for the rounding test below
+        } else {
+          // Old values.  Exact residuals: the largest, R, is at an upper
+          // vertex and the smallest, Q, at a lower one.  The encoder's
+          // largest is R unless every value reaching R rounds up; its
+          // smallest is Q - 1 if some value reaching Q rounds up, which
+          // needs a product within 2^-22 (half an ulp below 2^31) under an
+          // integer: ruled out when the lower vertices reaching Q, among
+          // them the one minimising v - theta1 * t, have a larger gap.
+          int64_t R = INT64_MIN, Q = INT64_MAX;
+          bool r_exact = false, q_up = false, q_gap = true;
+          for (uint32_t i = 0; i < hr.nu; ++i) {
+            bool up;
+            double gap;
+            const int64_t rr = vertex_residual(th, h.tu[i], h.xu[i], vmin, up, gap);
+            if (rr > R) {
+              R = rr;
+              r_exact = !up;
+            } else if (rr == R) {
+              r_exact = r_exact || !up;
+            }
+          }
+          for (uint32_t i = 0; i < hr.nl; ++i) {
+            bool up;
+            double gap;
+            const int64_t rr = vertex_residual(th, h.tl[i], h.xl[i], vmin, up, gap);
+            const bool wide_gap = gap >= 0x1p-20;
+            if (rr < Q) {
+              Q = rr;
+              q_up = up;
+              q_gap = wide_gap;
+            } else if (rr == Q) {
+              q_up = q_up || up;
+              q_gap = q_gap && wide_gap;
+            }
+          }
+          if (r_exact || rmax >= R) rmax = rmax > R ? rmax : R;
+          else unsure = true;
+          if (q_up) rmin = rmin < Q - 1 ? rmin : Q - 1;
+          else if (q_gap) rmin = rmin < Q ? rmin : Q;
+          else if (rmin > Q - 1) unsure = true;
+        }
+      }
+      scan_all = __ballot(unsure) != 0;
+      if (scan_all) {
+        rmin = INT64_MAX;
+        rmax = INT64_MIN;
+      }
+    }
+    if (scan_all) scan(0);
+    uint32_t bits = bitlen64(range);
+    if (lin) {
+      const uint32_t b_ls = bitlen64(uint64_t(rmax) - uint64_t(rmin));
+      if (b_ls < bits) bits = b_ls;
+    }
+    const uint64_t size = fits ? kRecordBytes + 8 + 8 * ((len_l * bits + 63) >> 6) : kNoMerge;
+    uint64_t prev = shfl_up64(size, 1);
+    if (lane == 0) prev = st.cc;
+    const bool merge = act && size != kNoMerge && size < prev + (act ? cost[j] : 0);
+    const uint64_t refuse = __ballot(act && !merge);
+    const uint32_t f = refuse ? uint32_t(__ffsll(static_cast<long long>(refuse)) - 1) : nact;
+    if (kFix && lane == 0 && f > 0) {  // steps k .. k+f-1 merged
+      for (uint32_t i = 0; i < f; ++i) clear_bit(keep, k + i);
+    }
+    if (f == nact) {  // the chain goes on past the batch
+      st.cc = readlane64(size, f - 1);
+      st.sum.vmin = readlane64(vmin, f - 1);
+      st.sum.vmax = readlane64(vmax, f - 1);
+      st.sum.sy = add128(st.sum.sy, U128{readlane64(u.sy.lo, f - 1), readlane64(u.sy.hi, f - 1)});
+      st.sum.sty = add128(st.sum.sty, U128{readlane64(u.sty.lo, f - 1), readlane64(u.sty.hi, f - 1)});
+      if (hr.state == kHullValid) {
+        const uint64_t lnew = s[k + f] - sa;
+        if (lnew - lold > kHullAppendMax || st.sum.vmax - st.sum.vmin >= kWide)
+          hr.state = kHullDead;
+        else
+          hull_append(col, dtype, sa, lold, lnew, h, hr);
+      }
+      k += f;
       continue;
     }
+    // step k+f refuses: boundary k+f is kept and partition k+f is current
+    const uint64_t kk = k + f;
     bool met = false;
     if (lane == 0) {
-      if (kFix) met = bit_set(keep, k);
-      if (!met) set_bits(keep, k, 1);
+      if (kFix) met = bit_set(keep, kk);
+      if (!met) set_bits(keep, kk, 1);
     }
     met = __ballot(met) != 0;
-    st.a = k;
-    st.cc = ck;
-    ++k;
+    st.a = kk;
+    st.cc = cost[kk];
+    st.sum = psum[kk];
+    hr = HullRegs{0, 0, kHullNone};
+    k = kk + 1;
     if (met) return true;
   }
   return false;
 }
 
+
+// psum[j] = the summary of partition j, j < m: one lane per partition of at
+// most 64 values, the wavefront together for the longer ones of its 64.
+__global__ __launch_bounds__(kEncBlock) void k_part_sums(const uint8_t* __restrict__ col,
+                                                        uint32_t dtype,
+                                                        const uint64_t* __restrict__ s,
+                                                        uint64_t m, RangeSum* __restrict__ psum) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t waves = uint64_t(gridDim.x) * kEncWaves;
+  for (uint64_t j0 = (uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6)) * 64; j0 < m;
+       j0 += waves * 64) {
+    const uint64_t j = j0 + lane;
+    uint64_t a = 0, e = 0;
+    if (j < m) {
+      a = s[j];
+      e = s[j + 1];
+    }
+    const bool shortp = j < m && e - a <= 64;
+    if (shortp) {
+      RangeSum r{~uint64_t(0), 0, U128{0, 0}, U128{0, 0}};
+      for (uint64_t t = 0; t < e - a; ++t) {
+        const uint64_t x = load_value(col, dtype, a + t);
+        r.vmin = x < r.vmin ? x : r.vmin;
+        r.vmax = x > r.vmax ? x : r.vmax;
+        r.sy = add128(r.sy, U128{x, 0});
+        r.sty = add128(r.sty, mul64x64(t, x));
+      }
+      psum[j] = r;
+    }
+    uint64_t todo = __ballot(j < m && !shortp);
+    while (todo) {
+      const uint32_t l = uint32_t(__ffsll(static_cast<long long>(todo)) - 1);
+      todo &= todo - 1;
+      const uint64_t la = readlane64(a, l), le = readlane64(e, l);
+      RangeSum r{~uint64_t(0), 0, U128{0, 0}, U128{0, 0}};
+      for (uint64_t t = lane; t < le - la; t += 64) {
+        const uint64_t x = load_value(col, dtype, la + t);
+        r.vmin = x < r.vmin ? x : r.vmin;
+        r.vmax = x > r.vmax ? x : r.vmax;
+        r.sy = add128(r.sy, U128{x, 0});
+        r.sty = add128(r.sty, mul64x64(t, x));
+      }
+      wave_minmax_u64(r.vmin, r.vmax);
+      wave_sum_u128x2(r.sy, r.sty);
+      if (lane == 0) psum[j0 + l] = r;
+    }
+  }
+}
+
+
 // Speculative pass: one wavefront per chunk of kMergeChunk boundaries,
 // scanned as if its first boundary were kept (chunk 0 from the true start);
-// each chunk's end state goes to out.
+// each chunk's end state and hulls go to out and hulls, and seen[q] records
+// the entry state the chunk was walked from.
 __global__ __launch_bounds__(kEncBlock) void k_merge_spec(
     const uint8_t* __restrict__ col, uint32_t dtype, const uint64_t* __restrict__ s,
-    const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair, uint64_t m,
-    uint64_t max_len, unsigned long long* __restrict__ keep, MergeState* __restrict__ out) {
-  const uint64_t q = uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6);
+    const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair,
+    const RangeSum* __restrict__ psum, uint64_t m, uint64_t max_len,
+    unsigned long long* __restrict__ keep, MergeState* __restrict__ out,
+    ChainHull* __restrict__ hulls, uint64_t* __restrict__ seen) {
+  __shared__ ChainHull lds[kEncWaves];
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint64_t q = uint64_t(blockIdx.x) * kEncWaves + wv;
   const uint64_t k0 = q << kMergeChunkLog2;
   if (k0 >= m) return;
   const uint64_t ke = m - k0 < kMergeChunk ? m : k0 + kMergeChunk;
@@ -922,69 +1296,53 @@ __global__ __launch_bounds__(kEncBlock) void k_merge_spec(
   uint64_t kb = k0;
   if (q == 0) {
     if ((threadIdx.x & 63) == 0) set_bits(keep, 0, 1);
-    st = MergeState{0, cost[0]};
+    st = MergeState{0, cost[0], psum[0]};
     kb = 1;
   } else {
-    st = MergeState{k0 - 1, cost[k0 - 1]};
+    st = MergeState{k0 - 1, cost[k0 - 1], psum[k0 - 1]};
+    if ((threadIdx.x & 63) == 0) seen[q] = k0 - 1;
   }
-  merge_walk<false>(col, dtype, s, cost, pair, max_len, kb, ke, st, keep);
+  HullRegs hr{0, 0, kHullNone};
+  merge_walk<false>(col, dtype, s, cost, pair, psum, max_len, kb, ke, st, keep, lds[wv], hr);
   if ((threadIdx.x & 63) == 0) out[q] = st;
+  hull_store(hulls + q, lds[wv], hr);
 }
 
-// Fix-up rounds.  out[q] is the end state of the run recorded in chunk q's
-// bits, entry[q] the state chunk q is assumed to begin in (the end state of
-// chunk q - 1).  A round re-walks every chunk whose entry changed: the walk
-// rewrites the chunk's bits from its entry until it keeps a boundary the
-// recorded run also kept (from there on that run is right, and so is its
-// end state) or reaches the chunk's end (its end state is the new out[q]).
-// Chunk 0 begins where the column does, so after round r at least chunks
-// 0..r are right; rounds repeat until no entry changes.
-__global__ __launch_bounds__(64) void k_merge_round_init(const MergeState* __restrict__ out,
-                                                        uint64_t nchunks,
-                                                        MergeState* __restrict__ entry,
-                                                        uint8_t* __restrict__ dirty) {
-  const uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= nchunks) return;
-  if (q > 0) entry[q] = out[q - 1];
-  dirty[q] = q > 0 ? 1 : 0;
-}
-
+// Fix-up rounds.  out[q] is the end state (hulls[q] its hulls) of the run
+// recorded in chunk q's bits, and seen[q] the state that run began in.  A
+// round walks the chunks of one parity whose left neighbour's end state
+// differs from seen: from that state, rewriting the chunk's bits until it
+// keeps a boundary the recorded run also kept (from there on that run is
+// right, and so is its end state) or reaches the chunk's end (its end state
+// is the new out[q]).  The neighbours, of the other parity, do not run in
+// the same round.  Chunk 0 begins where the column does, so after round r
+// (parities 1, 0, 1, ...) at least chunks 0..r are right; rounds repeat
+// until two in a row walk nothing.
 __global__ __launch_bounds__(kEncBlock) void k_merge_round(
     const uint8_t* __restrict__ col, uint32_t dtype, const uint64_t* __restrict__ s,
-    const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair, uint64_t m,
-    uint64_t max_len, unsigned long long* __restrict__ keep, const MergeState* __restrict__ entry,
-    MergeState* __restrict__ out, uint8_t* __restrict__ dirty, uint64_t nchunks) {
-  const uint64_t q = uint64_t(blockIdx.x) * kEncWaves + (threadIdx.x >> 6);
-  if (q >= nchunks || !dirty[q]) return;
+    const uint64_t* __restrict__ cost, const uint64_t* __restrict__ pair,
+    const RangeSum* __restrict__ psum, uint64_t m, uint64_t max_len,
+    unsigned long long* __restrict__ keep, MergeState* __restrict__ out,
+    ChainHull* __restrict__ hulls, uint64_t* __restrict__ seen, uint64_t nchunks,
+    uint32_t parity, unsigned long long* __restrict__ walks) {
+  __shared__ ChainHull lds[kEncWaves];
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint64_t q = 2 * (uint64_t(blockIdx.x) * kEncWaves + wv) + parity;
+  if (q == 0 || q >= nchunks) return;
+  MergeState st = out[q - 1];
+  if (st.a == seen[q]) return;
   const uint64_t kb = q << kMergeChunkLog2;
   const uint64_t ke = m - kb < kMergeChunk ? m : kb + kMergeChunk;
-  MergeState st = entry[q];
-  const bool met = merge_walk<true>(col, dtype, s, cost, pair, max_len, kb, ke, st, keep);
+  HullRegs hr{0, 0, kHullNone};
+  if (st.a + 1 < kb) hr = hull_load(hulls + (q - 1), lds[wv]);
+  const bool met =
+      merge_walk<true>(col, dtype, s, cost, pair, psum, max_len, kb, ke, st, keep, lds[wv], hr);
   if ((threadIdx.x & 63) == 0) {
+    seen[q] = out[q - 1].a;
     if (!met) out[q] = st;
-    dirty[q] = 0;
+    atomicAdd(walks, 1ull);
   }
-}
-
-// entry[q] = out[q - 1] where that changed, marking chunk q for the next
-// round; *changes counts them.
-__global__ __launch_bounds__(256) void k_merge_propagate(const MergeState* __restrict__ out,
-                                                        uint64_t nchunks,
-                                                        MergeState* __restrict__ entry,
-                                                        uint8_t* __restrict__ dirty,
-                                                        unsigned long long* __restrict__ changes) {
-  uint32_t c = 0;
-  for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x + 1; q < nchunks;
-       q += uint64_t(gridDim.x) * blockDim.x) {
-    const MergeState o = out[q - 1];
-    if (entry[q].a != o.a) {
-      entry[q] = o;
-      dirty[q] = 1;
-      ++c;
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) c += uint32_t(__shfl_xor(int(c), off, 64));
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(changes, static_cast<unsigned long long>(c));
+  if (!met) hull_store(hulls + q, lds[wv], hr);
 }
 
 // ---- compaction after a pass --------------------------------------------------------
@@ -1188,9 +1546,13 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
   P_TRY(scan_counts(counts, nb, &m, stream));
   uint64_t *starts = nullptr, *starts2 = nullptr, *cost = nullptr, *cost2 = nullptr,
            *pair = nullptr, *pair2 = nullptr, *old = nullptr, *keep_counts = nullptr;
-  uint8_t *changed = nullptr, *dirty = nullptr, *cdirty = nullptr;
-  unsigned long long *keep = nullptr, *changes = nullptr;
-  leco::MergeState *mout = nullptr, *mentry = nullptr;
+  uint8_t *changed = nullptr, *dirty = nullptr;
+  unsigned long long *keep = nullptr, *walks = nullptr;
+  leco::MergeState* mout = nullptr;
+  leco::ChainHull* hulls = nullptr;
+  leco::RangeSum* psum = nullptr;
+  uint64_t* seen = nullptr;
+  constexpr int kRoundGroup = 8;  // fix-up rounds launched between checks
   const uint64_t kwords = (m + 63) / 64;
   const uint64_t nbk = (kwords + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
   const uint64_t nchunks0 = (m + leco::kMergeChunk - 1) / leco::kMergeChunk;
@@ -1198,8 +1560,8 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
       !buf.alloc(&cost2, m) || !buf.alloc(&pair, m) || !buf.alloc(&pair2, m) ||
       !buf.alloc(&old, m) || !buf.alloc(&changed, m) || !buf.alloc(&dirty, m) ||
       !buf.alloc(&keep, kwords) || !buf.alloc(&keep_counts, nbk) ||
-      !buf.alloc(&mout, nchunks0) || !buf.alloc(&mentry, nchunks0) ||
-      !buf.alloc(&cdirty, nchunks0) || !buf.alloc(&changes, 1))
+      !buf.alloc(&mout, nchunks0) || !buf.alloc(&hulls, nchunks0) || !buf.alloc(&psum, m) ||
+      !buf.alloc(&seen, nchunks0) || !buf.alloc(&walks, kRoundGroup))
     return pfail(ctx, LECO_ENOMEM, "partition: partition arrays");
   hipLaunchKernelGGL(leco::k_bitmap_emit, dim3(uint32_t(nb)), dim3(leco::kScanBlock), 0, stream,
                      reinterpret_cast<const uint64_t*>(bitmap), nwords, counts, starts);
@@ -1245,27 +1607,30 @@ leco_status leco_partition(leco_ctx* ctx, const void* col_dev, uint64_t n, leco_
     const uint64_t words = (m + 63) / 64;
     const uint64_t nchunks = (m + leco::kMergeChunk - 1) / leco::kMergeChunk;
     P_TRY(hipMemsetAsync(keep, 0, 8 * words, stream));
+    const uint64_t gsum = (m + 64 * leco::kEncWaves - 1) / (64 * leco::kEncWaves);
+    hipLaunchKernelGGL(leco::k_part_sums, dim3(uint32_t(gsum < grid_cap ? gsum : grid_cap)),
+                       dim3(leco::kEncBlock), 0, stream, col, w, starts, m, psum);
+    P_TRY(hipGetLastError());
     const uint32_t gch = uint32_t((nchunks + leco::kEncWaves - 1) / leco::kEncWaves);
     hipLaunchKernelGGL(leco::k_merge_spec, dim3(gch), dim3(leco::kEncBlock), 0, stream, col, w,
-                       starts, cost, pair, m, prm->max_len, keep, mout);
+                       starts, cost, pair, psum, m, prm->max_len, keep, mout, hulls, seen);
     P_TRY(hipGetLastError());
-    // fix-up rounds until no chunk's entry state changes
-    hipLaunchKernelGGL(leco::k_merge_round_init, dim3(uint32_t((nchunks + 63) / 64)), dim3(64), 0,
-                       stream, mout, nchunks, mentry, cdirty);
-    P_TRY(hipGetLastError());
-    const uint64_t gp = (nchunks + 255) / 256;
-    for (uint64_t r = 0; r < nchunks; ++r) {  // chunk r is right after round r
-      hipLaunchKernelGGL(leco::k_merge_round, dim3(gch), dim3(leco::kEncBlock), 0, stream, col, w,
-                         starts, cost, pair, m, prm->max_len, keep, mentry, mout, cdirty, nchunks);
-      P_TRY(hipGetLastError());
-      P_TRY(hipMemsetAsync(changes, 0, 8, stream));
-      hipLaunchKernelGGL(leco::k_merge_propagate, dim3(uint32_t(gp < grid_cap ? gp : grid_cap)),
-                         dim3(256), 0, stream, mout, nchunks, mentry, cdirty, changes);
-      P_TRY(hipGetLastError());
-      unsigned long long nchanged = 0;
-      P_TRY(hipMemcpyAsync(&nchanged, changes, 8, hipMemcpyDeviceToHost, stream));
+    // fix-up rounds, parities 1, 0, 1, ..., until two in a row walk nothing;
+    // chunk r is right after round r, so nchunks rounds always suffice
+    const uint64_t half = (nchunks + 1) / 2;
+    const uint32_t ghalf = uint32_t((half + leco::kEncWaves - 1) / leco::kEncWaves);
+    for (uint64_t r0 = 0; nchunks > 1 && r0 < nchunks + 2 * kRoundGroup; r0 += kRoundGroup) {
+      P_TRY(hipMemsetAsync(walks, 0, 8 * kRoundGroup, stream));
+      for (int i = 0; i < kRoundGroup; ++i) {
+        hipLaunchKernelGGL(leco::k_merge_round, dim3(ghalf), dim3(leco::kEncBlock), 0, stream, col,
+                           w, starts, cost, pair, psum, m, prm->max_len, keep, mout, hulls, seen,
+                           nchunks, uint32_t((r0 + i + 1) & 1), walks + i);
+        P_TRY(hipGetLastError());
+      }
+      unsigned long long nwalk[kRoundGroup];
+      P_TRY(hipMemcpyAsync(nwalk, walks, 8 * kRoundGroup, hipMemcpyDeviceToHost, stream));
       P_TRY(hipStreamSynchronize(stream));
-      if (nchanged == 0) break;
+      if (nwalk[kRoundGroup - 2] == 0 && nwalk[kRoundGroup - 1] == 0) break;
     }
     const uint64_t blocks = (words + leco::kItemsPerBlock - 1) / leco::kItemsPerBlock;
     hipLaunchKernelGGL(leco::k_keep_count, dim3(uint32_t(blocks)), dim3(leco::kScanBlock), 0,
