@@ -870,16 +870,24 @@ struct MergeState {
 // integer (merge_walk checks for that).  A long run of merges then sizes
 // each union from the hulls and the values it adds, not from all its values.
 constexpr uint32_t kHullMax = 64;              // vertices per hull
-constexpr uint64_t kHullBuildMin = 1024;       // shorter partitions are scanned whole
+constexpr uint64_t kHullBuildMin = 256;        // shorter partitions are scanned whole
 constexpr uint64_t kHullBuildMax = 16384;      // values a hull is first built from
 constexpr uint64_t kHullAppendMax = 8192;      // values one step may append
 constexpr uint64_t kHullNewMax = 4096;         // new values a batch sizes by scanning
 enum : uint32_t { kHullNone = 0, kHullValid = 1, kHullDead = 2 };
 
-struct ChainHull {
+struct ChainHull {  // hull 0: upper, hull 1: lower
   uint32_t nu, nl, state, pad;
-  uint32_t tu[kHullMax], tl[kHullMax];
-  uint64_t xu[kHullMax], xl[kHullMax];
+  uint32_t t[2][kHullMax];
+  uint64_t x[2][kHullMax];
+};
+
+// A wavefront's LDS: the hulls and a window of values with a 16-value halo
+// on either side.
+constexpr uint32_t kHalo = 16;
+struct HullLds {
+  ChainHull h;
+  uint64_t stage[64 + 2 * kHalo];
 };
 
 // The hulls' counts and state, identical in every lane of the wavefront.
@@ -893,59 +901,130 @@ __device__ inline void wave_lds_order() {
 }
 
 // Sign of (b - a) x (c - a) for points with ta < tb < tc whose values lie
-// within 2^61 of each other.
+// within 2^61 of each other (kNarrow: within 2^43, so that with t < 2^20
+// each product fits in 64 bits).
+template <bool kNarrow = false>
 __device__ inline int turn(uint32_t ta, uint64_t xa, uint32_t tb, uint64_t xb, uint32_t tc,
                            uint64_t xc) {
+  if (kNarrow) {
+    const int64_t l = int64_t(tb - ta) * int64_t(xc - xa);
+    const int64_t r = int64_t(xb - xa) * int64_t(tc - ta);
+    return l > r ? 1 : (l < r ? -1 : 0);
+  }
   const __int128 l = __int128(int64_t(tb - ta)) * __int128(int64_t(xc - xa));
   const __int128 r = __int128(int64_t(xb - xa)) * __int128(int64_t(tc - ta));
   return l > r ? 1 : (l < r ? -1 : 0);
 }
 
 // Appends the points [u0, u1) of the partition beginning at column position
-// sa to both hulls (monotone chain); too many vertices mark them dead.
-// Called by a whole wavefront with uniform arguments; lane 0 writes.
-__device__ inline void hull_append(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t sa,
-                                   uint64_t u0, uint64_t u1, ChainHull& h, HullRegs& hr) {
+// sa to both hulls; too many vertices mark them dead.  Each lane first tests
+// its point against chords through points of [0, u1) at distances 1..16 on
+// either side: a point on or below such a chord is no upper-hull vertex of
+// any set holding both ends, one on or above it no lower-hull vertex.  The
+// survivors then go through the monotone chain in order, lane 0 keeping the
+// upper hull and lane 1 the lower one side by side, each with its two last
+// vertices in registers.  Called by a whole wavefront, uniform arguments.
+template <bool kNarrow>
+__device__ inline void hull_append_t(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t sa,
+                                     uint64_t u0, uint64_t u1, HullLds& w, HullRegs& hr) {
   const uint32_t lane = threadIdx.x & 63;
-  for (uint64_t b = u0; b < u1 && hr.state == kHullValid; b += 64) {
-    const uint64_t x = load_value(col, dtype, sa + (b + lane < u1 ? b + lane : u1 - 1));
-    const uint32_t cnt = u1 - b < 64 ? uint32_t(u1 - b) : 64u;
-    for (uint32_t q = 0; q < cnt; ++q) {
+  const uint8_t* src = col + sa * dtype;
+  ChainHull& h = w.h;
+  const uint32_t side = lane & 1;  // lanes 0 and 1: the hull they keep
+  uint32_t n = side ? hr.nl : hr.nu;
+  uint32_t t1 = 0, t2 = 0;  // last and second-last vertex
+  uint64_t x1 = 0, x2 = 0;
+  if (lane < 2) {
+    if (n >= 1) { t1 = h.t[side][n - 1]; x1 = h.x[side][n - 1]; }
+    if (n >= 2) { t2 = h.t[side][n - 2]; x2 = h.x[side][n - 2]; }
+  }
+  bool over = false;
+  for (uint64_t b = u0; b < u1; b += 64) {
+    // positions b - kHalo .. b + 63 + kHalo that lie in [0, u1), staged once
+    for (uint32_t i = lane; i < 64 + 2 * kHalo; i += 64) {
+      if (b + i >= kHalo && b + i - kHalo < u1) w.stage[i] = load_value(src, dtype, b + i - kHalo);
+    }
+    wave_lds_order();
+    const uint64_t t = b + lane;
+    const bool in = t < u1;
+    const uint64_t x = w.stage[kHalo + lane];  // used only where in
+    bool cu = in, cl = in;
+#pragma unroll
+    for (uint32_t ia = 0; ia < 5; ++ia) {
+      const uint32_t a = 1u << ia;
+      if (!in || t < a) break;
+      const uint64_t xa = w.stage[kHalo + lane - a];
+#pragma unroll
+      for (uint32_t ic = 0; ic < 5; ++ic) {
+        const uint32_t c = 1u << ic;
+        if (t + c >= u1) break;
+        const int tr = turn<kNarrow>(0, xa, a, x, a + c, w.stage[kHalo + lane + c]);
+        if (tr >= 0) cu = false;
+        if (tr <= 0) cl = false;
+      }
+    }
+    wave_lds_order();  // every read of the window precedes the next block's
+    const uint64_t mu = __ballot(cu), ml = __ballot(cl);
+    uint64_t todo = mu | ml;
+    while (todo) {
+      const uint32_t q = uint32_t(__ffsll(static_cast<long long>(todo)) - 1);
+      todo &= todo - 1;
       const uint64_t xq = readlane64(x, q);
       const uint32_t tq = uint32_t(b + q);
-      while (hr.nu >= 2 &&
-             turn(h.tu[hr.nu - 2], h.xu[hr.nu - 2], h.tu[hr.nu - 1], h.xu[hr.nu - 1], tq, xq) >= 0)
-        --hr.nu;
-      while (hr.nl >= 2 &&
-             turn(h.tl[hr.nl - 2], h.xl[hr.nl - 2], h.tl[hr.nl - 1], h.xl[hr.nl - 1], tq, xq) <= 0)
-        --hr.nl;
-      if (hr.nu == kHullMax || hr.nl == kHullMax) {
-        hr.state = kHullDead;
-        break;
+      const bool mine = lane < 2 && (((side ? ml : mu) >> q) & 1);
+      if (mine && !over) {
+        while (n >= 2) {
+          const int tr = turn<kNarrow>(t2, x2, t1, x1, tq, xq);
+          if (side ? tr > 0 : tr < 0) break;  // a strict turn keeps the last vertex
+          --n;
+          t1 = t2;
+          x1 = x2;
+          if (n >= 2) {
+            t2 = h.t[side][n - 2];
+            x2 = h.x[side][n - 2];
+          }
+        }
+        if (n == kHullMax) {
+          over = true;
+        } else {
+          h.t[side][n] = tq;
+          h.x[side][n] = xq;
+          ++n;
+          t2 = t1;
+          x2 = x1;
+          t1 = tq;
+          x1 = xq;
+        }
       }
-      if (lane == 0) {
-        h.tu[hr.nu] = tq;
-        h.xu[hr.nu] = xq;
-        h.tl[hr.nl] = tq;
-        h.xl[hr.nl] = xq;
-      }
-      ++hr.nu;
-      ++hr.nl;
-      wave_lds_order();
     }
+    if (__ballot(over)) break;
   }
+  const uint32_t nu = uint32_t(__builtin_amdgcn_readlane(int(n), 0));
+  const uint32_t nl = uint32_t(__builtin_amdgcn_readlane(int(n), 1));
+  hr = __ballot(over) ? HullRegs{0, 0, kHullDead} : HullRegs{nu, nl, kHullValid};
+  wave_lds_order();  // the vertices are read by every lane next
+}
+
+// Values spread below 2^43 take the 64-bit turn test.
+__device__ inline void hull_append(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t sa,
+                                   uint64_t u0, uint64_t u1, uint64_t spread, HullLds& w,
+                                   HullRegs& hr) {
+  if (spread < (uint64_t(1) << 43))
+    hull_append_t<true>(col, dtype, sa, u0, u1, w, hr);
+  else
+    hull_append_t<false>(col, dtype, sa, u0, u1, w, hr);
 }
 
 __device__ inline void hull_store(ChainHull* __restrict__ g, const ChainHull& h, const HullRegs& hr) {
   const uint32_t lane = threadIdx.x & 63;
   if (hr.state == kHullValid) {
     if (lane < hr.nu) {
-      g->tu[lane] = h.tu[lane];
-      g->xu[lane] = h.xu[lane];
+      g->t[0][lane] = h.t[0][lane];
+      g->x[0][lane] = h.x[0][lane];
     }
     if (lane < hr.nl) {
-      g->tl[lane] = h.tl[lane];
-      g->xl[lane] = h.xl[lane];
+      g->t[1][lane] = h.t[1][lane];
+      g->x[1][lane] = h.x[1][lane];
     }
   }
   if (lane == 0) {
@@ -960,12 +1039,12 @@ __device__ inline HullRegs hull_load(const ChainHull* __restrict__ g, ChainHull&
   HullRegs hr{g->nu, g->nl, g->state};
   if (hr.state == kHullValid) {
     if (lane < hr.nu) {
-      h.tu[lane] = g->tu[lane];
-      h.xu[lane] = g->xu[lane];
+      h.t[0][lane] = g->t[0][lane];
+      h.x[0][lane] = g->x[0][lane];
     }
     if (lane < hr.nl) {
-      h.tl[lane] = g->tl[lane];
-      h.xl[lane] = g->xl[lane];
+      h.t[1][lane] = g->t[1][lane];
+      h.x[1][lane] = g->x[1][lane];
     }
   }
   wave_lds_order();
@@ -1008,7 +1087,8 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
                            const uint64_t* __restrict__ s, const uint64_t* __restrict__ cost,
                            const uint64_t* __restrict__ pair, const RangeSum* __restrict__ psum,
                            uint64_t max_len, uint64_t kb, uint64_t ke, MergeState& st,
-                           unsigned long long* __restrict__ keep, ChainHull& h, HullRegs& hr) {
+                           unsigned long long* __restrict__ keep, HullLds& w, HullRegs& hr) {
+  const ChainHull& h = w.h;
   const uint32_t lane = threadIdx.x & 63;
   constexpr uint64_t kWide = uint64_t(1) << 61;  // value spread beyond which no line is fitted
   uint64_t k = kb;
@@ -1064,7 +1144,7 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
     if (hr.state == kHullNone && lold >= kHullBuildMin) {
       if (lold <= kHullBuildMax && st.sum.vmax - st.sum.vmin < kWide) {
         hr = HullRegs{0, 0, kHullValid};
-        hull_append(col, dtype, sa, 0, lold, h, hr);
+        hull_append(col, dtype, sa, 0, lold, st.sum.vmax - st.sum.vmin, w, hr);
       } else {
         hr.state = kHullDead;
       }
@@ -1127,22 +1207,26 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
       scan(lold);  // the added values
       bool unsure = false;
       if (lin) {
-        if (!(__dmul_rn(fabs(th), double(len_l)) < 2147483648.0)) {
+        const double pmax = __dmul_rn(fabs(th), double(len_l));  // bounds every |product|
+        if (!(pmax < 2147483648.0)) {
           unsure = true;  // products too large for the rounding test below
         } else {
           // Old values.  Exact residuals: the largest, R, is at an upper
           // vertex and the smallest, Q, at a lower one.  The encoder's
           // largest is R unless every value reaching R rounds up; its
           // smallest is Q - 1 if some value reaching Q rounds up, which
-          // needs a product within 2^-22 (half an ulp below 2^31) under an
-          // integer: ruled out when the lower vertices reaching Q, among
-          // them the one minimising v - theta1 * t, have a larger gap.
+          // needs a product within half an ulp of pmax under an integer:
+          // ruled out when the lower vertices reaching Q, among them the
+          // one minimising v - theta1 * t, have a larger gap (margin: two
+          // ulps of pmax, at least 2^-48 against the gap's own rounding).
+          const double margin = pmax >= 0x1p-3 ? fmax(ldexp(1.0, ilogb(pmax) - 51), 0x1p-48)
+                                               : 0x1p-48;
           int64_t R = INT64_MIN, Q = INT64_MAX;
           bool r_exact = false, q_up = false, q_gap = true;
           for (uint32_t i = 0; i < hr.nu; ++i) {
             bool up;
             double gap;
-            const int64_t rr = vertex_residual(th, h.tu[i], h.xu[i], vmin, up, gap);
+            const int64_t rr = vertex_residual(th, h.t[0][i], h.x[0][i], vmin, up, gap);
             if (rr > R) {
               R = rr;
               r_exact = !up;
@@ -1153,8 +1237,8 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
           for (uint32_t i = 0; i < hr.nl; ++i) {
             bool up;
             double gap;
-            const int64_t rr = vertex_residual(th, h.tl[i], h.xl[i], vmin, up, gap);
-            const bool wide_gap = gap >= 0x1p-20;
+            const int64_t rr = vertex_residual(th, h.t[1][i], h.x[1][i], vmin, up, gap);
+            const bool wide_gap = gap >= margin;
             if (rr < Q) {
               Q = rr;
               q_up = up;
@@ -1203,7 +1287,7 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
         if (lnew - lold > kHullAppendMax || st.sum.vmax - st.sum.vmin >= kWide)
           hr.state = kHullDead;
         else
-          hull_append(col, dtype, sa, lold, lnew, h, hr);
+          hull_append(col, dtype, sa, lold, lnew, st.sum.vmax - st.sum.vmin, w, hr);
       }
       k += f;
       continue;
@@ -1286,7 +1370,7 @@ __global__ __launch_bounds__(kEncBlock) void k_merge_spec(
     const RangeSum* __restrict__ psum, uint64_t m, uint64_t max_len,
     unsigned long long* __restrict__ keep, MergeState* __restrict__ out,
     ChainHull* __restrict__ hulls, uint64_t* __restrict__ seen) {
-  __shared__ ChainHull lds[kEncWaves];
+  __shared__ HullLds lds[kEncWaves];
   const uint32_t wv = threadIdx.x >> 6;
   const uint64_t q = uint64_t(blockIdx.x) * kEncWaves + wv;
   const uint64_t k0 = q << kMergeChunkLog2;
@@ -1305,7 +1389,7 @@ __global__ __launch_bounds__(kEncBlock) void k_merge_spec(
   HullRegs hr{0, 0, kHullNone};
   merge_walk<false>(col, dtype, s, cost, pair, psum, max_len, kb, ke, st, keep, lds[wv], hr);
   if ((threadIdx.x & 63) == 0) out[q] = st;
-  hull_store(hulls + q, lds[wv], hr);
+  hull_store(hulls + q, lds[wv].h, hr);
 }
 
 // Fix-up rounds.  out[q] is the end state (hulls[q] its hulls) of the run
@@ -1325,7 +1409,7 @@ __global__ __launch_bounds__(kEncBlock) void k_merge_round(
     unsigned long long* __restrict__ keep, MergeState* __restrict__ out,
     ChainHull* __restrict__ hulls, uint64_t* __restrict__ seen, uint64_t nchunks,
     uint32_t parity, unsigned long long* __restrict__ walks) {
-  __shared__ ChainHull lds[kEncWaves];
+  __shared__ HullLds lds[kEncWaves];
   const uint32_t wv = threadIdx.x >> 6;
   const uint64_t q = 2 * (uint64_t(blockIdx.x) * kEncWaves + wv) + parity;
   if (q == 0 || q >= nchunks) return;
@@ -1334,7 +1418,7 @@ __global__ __launch_bounds__(kEncBlock) void k_merge_round(
   const uint64_t kb = q << kMergeChunkLog2;
   const uint64_t ke = m - kb < kMergeChunk ? m : kb + kMergeChunk;
   HullRegs hr{0, 0, kHullNone};
-  if (st.a + 1 < kb) hr = hull_load(hulls + (q - 1), lds[wv]);
+  if (st.a + 1 < kb) hr = hull_load(hulls + (q - 1), lds[wv].h);
   const bool met =
       merge_walk<true>(col, dtype, s, cost, pair, psum, max_len, kb, ke, st, keep, lds[wv], hr);
   if ((threadIdx.x & 63) == 0) {
@@ -1342,7 +1426,7 @@ __global__ __launch_bounds__(kEncBlock) void k_merge_round(
     if (!met) out[q] = st;
     atomicAdd(walks, 1ull);
   }
-  if (!met) hull_store(hulls + q, lds[wv], hr);
+  if (!met) hull_store(hulls + q, lds[wv].h, hr);
 }
 
 // ---- compaction after a pass --------------------------------------------------------
