@@ -202,6 +202,21 @@ def time_events(torch, stream, fn, reps: int) -> float:
     return float(np.median(ts))
 
 
+def time_stream(torch, stream, fn, reps: int) -> float:
+    """Mean seconds of fn() over reps launches back to back on `stream`,
+    between two HIP events (the launches queue while earlier ones run, as
+    in a loop of calls; the kernel profiler's durations compare to this)."""
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / 1e3 / reps
+
+
 def bench_batched(args, codec=None):
     """4,096 columns (lognormal lengths 1e3..1e7, ~2.0e9 values, half uint32)
     encoded in one launch sequence and decoded in one persistent launch,
@@ -569,7 +584,7 @@ def bench_variable(args):
             codec.ctx, d, n, P.LECO_U32, part, buf, cap, size))
         enc()
         codec.sync()
-        t_enc = time_events(torch, stream, enc, args.steps)
+        t_enc = time_stream(torch, stream, enc, args.steps)
         codec.sync()
         nbytes = int(size.cpu().numpy().view(np.uint64)[0])
         blob = buf[:nbytes]
@@ -579,7 +594,8 @@ def bench_variable(args):
         dec()
         codec.sync()
         assert torch.equal(out, d), f"{name}: variable-partition round trip"
-        t_dec = time_events(torch, stream, dec, args.steps)
+        t_dec = time_stream(torch, stream, dec, args.steps)
+        t_dec_iso = time_events(torch, stream, dec, args.steps)
         codec.sync()
         fixed = {L: codec.encode(d, fixed_len=L).numel() for L in (1024, 4096)}
         # the split also beginning partitions at the starting positions
@@ -598,7 +614,8 @@ def bench_variable(args):
                      "ratio_fixed_4096": round(fixed[4096] / (4 * n), 5),
                      "partition_ms": round(t_part * 1e3, 2),
                      "partition_values_per_s": round(n / t_part, 1),
-                     "encode_ms": round(t_enc * 1e3, 3), "decode_all_ms": round(t_dec * 1e3, 3),
+                     "encode_ms": round(t_enc * 1e3, 3), "decode_all_ms": round(t_dec * 1e3, 4),
+                     "decode_all_ms_isolated": round(t_dec_iso * 1e3, 4),
                      "decode_hbm_frac": round((nbytes + 4 * n) / t_dec / HBM_PEAK, 4),
                      "start_positions": {"partitions": len(starts_sp) - 1,
                                          "ratio": round(blob_sp.numel() / (4 * n), 5),
