@@ -1046,6 +1046,272 @@ __global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(5))) 
                 b, gw32, limit, k_begin, k_end, lds[wave]);
 }
 
+// ---- one pass: fit, word offset by look-back, record and pack ----------------------
+//
+// For least-squares columns whose partitions hold at most kEncRegLen
+// values: one workgroup per partition reads the values once into registers
+// (wavefront w holds values 1024 w .. 1024 w + 1023, 16 per lane, so its
+// rounds of 64 residuals are consecutive), fits the model as fit_block
+// does, and takes the partition's word offset from the word counts of the
+// partitions before it in its column (decoupled look-back: each partition
+// publishes its count as soon as it is fitted, and its inclusive prefix as
+// soon as it knows it).  Partitions take their index from a ticket in the
+// order their workgroups start, so every partition a workgroup waits on is
+// already running and publishes without waiting on later ones: the waits
+// end.  It then writes its record (and start) and packs its residuals from
+// the registers; the last partition of a column writes the header.
+
+// A look-back state: flag in the top two bits, a word count below them.
+// Each state is one 64-bit word read and written with relaxed atomics at
+// device scope: the word is the whole message, so nothing needs ordering
+// around it (acquire / release at device scope would write back or
+// invalidate the L2 of an XCD at every access).
+constexpr uint64_t kLbCount = uint64_t(1) << 62;      // the partition's own count
+constexpr uint64_t kLbInclusive = uint64_t(2) << 62;  // counts of its column up to it
+constexpr uint64_t kLbValue = kLbCount - 1;
+
+__device__ inline void lb_publish(uint64_t* st, uint64_t P, uint64_t v) {
+  __hip_atomic_store(st + P, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Words of partitions [first, P) of a column, by one wavefront: lane l reads
+// the state of partition hi - 1 - l, 64 predecessors per round, down to the
+// nearest one with an inclusive prefix; rounds wait (sleeping between
+// reads) while a partition closer than that has published nothing yet.
+__device__ inline uint64_t lb_exclusive(const uint64_t* st, uint64_t first, uint64_t P) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t acc = 0, hi = P;
+  while (hi > first) {
+    const uint64_t span = hi - first < 64 ? hi - first : 64;
+    const bool in = lane < span;
+    const uint64_t j = hi - 1 - lane;
+    uint64_t s = 0;
+    int stop;
+    while (true) {
+      s = in ? __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+      const uint64_t inc = __ballot(in && (s >> 62) == 2);
+      stop = inc ? __ffsll(static_cast<long long>(inc)) - 1 : int(span) - 1;
+      const uint64_t need = stop >= 63 ? ~0ull : (2ull << stop) - 1;  // lanes 0..stop
+      if (__ballot(in && (s >> 62) == 0) & need) {
+        __builtin_amdgcn_s_sleep(8);
+        continue;
+      }
+      break;
+    }
+    uint64_t x = in && int(lane) <= stop ? (s & kLbValue) : 0;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) x += shfl_xor64(x, m);
+    acc += x;
+    const bool found = __ballot(in && int(lane) == stop && (s >> 62) == 2) != 0;
+    if (found) break;
+    hi -= span;
+  }
+  return acc;
+}
+
+// The model of a partition held in registers as described above.  When
+// the residuals v - vmin - floor(theta1 t) fit int32 (`small`), r32 keeps
+// them for the packing.
+__device__ __attribute__((always_inline)) inline Model fit_regs(FitShared& sh, const uint64_t (&v)[kEncRegs],
+                                                               uint32_t t0, uint64_t len,
+                                                               bool force_constant,
+                                                               int32_t (&r32)[kEncRegs],
+                                                               bool& small_out) {
+  small_out = false;
+  // clamped loads hold the partition's last value: min and max unchanged
+  uint64_t vmin = v[0], vmax = v[0];
+#pragma unroll
+  for (int k = 1; k < kEncRegs; ++k) {
+    vmin = v[k] < vmin ? v[k] : vmin;
+    vmax = v[k] > vmax ? v[k] : vmax;
+  }
+  block_minmax_u64(sh, vmin, vmax);
+  const uint64_t range = vmax - vmin;
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
+  if (len > 1 && !force_constant && range < (uint64_t(1) << 61)) {
+    double th;
+    bool small = false;
+    if (range < kNarrowRange) {
+      uint64_t sy = 0, sty = 0;  // < 2^42 and < 2^54
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = t0 + 64 * k;
+        const uint64_t y = t < len ? uint32_t(v[k]) - uint32_t(vmin) : 0;
+        sy += y;
+        sty += uint64_t(t) * y;
+      }
+      block_sum_u64x2(sh, sy, sty);
+      th = block_slope(sh, len, U128{sy, 0}, U128{sty, 0});
+      small = __dmul_rn(fabs(th), double(len)) < 1073741824.0;
+    } else {
+      U128 sv{0, 0}, stv{0, 0};
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = t0 + 64 * k;
+        const uint64_t x = t < len ? v[k] : 0;
+        sv = add128(sv, U128{x, 0});
+        stv = add128(stv, mul64x64(t, x));
+      }
+      block_sum_u128x2(sh, sv, stv);
+      th = block_slope(sh, len, sv, stv);
+    }
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+    if (small) {
+      int32_t mn = INT32_MAX, mx = INT32_MIN;
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = t0 + 64 * k;
+        r32[k] = int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t);
+        if (t < len) {
+          mn = r32[k] < mn ? r32[k] : mn;
+          mx = r32[k] > mx ? r32[k] : mx;
+        }
+      }
+      rmin = mn;
+      rmax = mx;
+    } else {
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = t0 + 64 * k;
+        const int64_t rr = int64_t(v[k] - vmin) - predict(th, t);
+        if (t < len) {
+          rmin = rr < rmin ? rr : rmin;
+          rmax = rr > rmax ? rr : rmax;
+        }
+      }
+    }
+    block_minmax_i64(sh, rmin, rmax);
+    choose_model(md, th, rmin, rmax);
+    small_out = small;
+  }
+  return md;
+}
+
+struct FusedShared {
+  FitShared fit;
+  uint64_t P, woff;
+  // each wavefront's 16 rounds of residuals, packed: 2 b words per round
+  uint32_t words[kEncWaves][2 * 64 * kEncRegs];
+};
+
+// One workgroup per partition (its index from a ticket): values loaded
+// once, model fitted, word count published; the residuals packed into LDS
+// (which needs no offset) while the partitions before it publish theirs;
+// then the look-back, the record, and the packed words copied out.
+__device__ __attribute__((always_inline)) inline void encode_fused_part(
+    FusedShared& sh, const EncColumn& c, uint64_t P, const EncScratch& scr, int* err) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint64_t start, len;
+  const uint64_t j = P - c.part_base;
+  part_bounds(c, j, start, len);
+  const uint32_t t0 = wave * 64 * kEncRegs + lane;  // value t0 + 64 k is v[k]
+  uint64_t v[kEncRegs];
+  if (c.dtype == 8) {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(c.col) + start;
+#pragma unroll
+    for (int k = 0; k < kEncRegs; ++k) v[k] = load_clamped(src, t0 + 64 * k, len);
+  } else {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(c.col) + start;
+#pragma unroll
+    for (int k = 0; k < kEncRegs; ++k) v[k] = load_clamped(src, t0 + 64 * k, len);
+  }
+  int32_t r32[kEncRegs];
+  bool small;
+  const Model md = fit_regs(sh.fit, v, t0, len, c.force_constant != 0, r32, small);
+  const uint64_t nw = (len * md.bits + 63) >> 6;
+  uint64_t* st = scr.woff;
+  if (threadIdx.x == 0) lb_publish(st, P, (j == 0 ? kLbInclusive : kLbCount) | nw);
+  // pack this wavefront's rounds 16 w .. 16 w + 15 into its LDS words
+  const uint32_t b = md.bits;
+  const uint64_t rounds = (len + 63) / 64;
+  const uint64_t r0 = uint64_t(wave) * kEncRegs;
+  const uint32_t nr = r0 >= rounds ? 0 : uint32_t(rounds - r0 < kEncRegs ? rounds - r0 : kEncRegs);
+  const uint32_t nwb = 2 * b * nr;
+  uint32_t* w32 = sh.words[wave];
+  if (nwb) {
+    for (uint32_t q = lane; q < nwb; q += 64) w32[q] = 0;
+    wave_fence();
+    // the encoder's residual: (v - vmin) - floor(theta1 t) - rmin for the
+    // line (from the fit's registers when they hold it), v - vmin for the
+    // constant model
+    const bool fits32 = prediction_fits_i32(md.theta1, len);
+    const bool reuse = md.linear && small;
+#pragma unroll
+    for (int k = 0; k < kEncRegs; ++k) {
+      const uint32_t t = t0 + 64 * k;
+      uint64_t u;
+      if (reuse) {
+        u = uint64_t(uint32_t(r32[k] - int32_t(md.rmin)));
+      } else {
+        const uint64_t p = !md.linear ? 0
+                           : fits32   ? uint64_t(int64_t(predict32(md.theta1, t)))
+                                      : uint64_t(predict(md.theta1, t));
+        u = (v[k] - md.base) - p;
+      }
+      if (t >= len) u = 0;
+      if (uint32_t(k) < nr) or_bits(w32, (64 * k + lane) * b, b, u);
+    }
+    wave_fence();
+  }
+  if (j != 0 && wave == 0) {
+    const uint64_t before = lb_exclusive(st, c.part_base, P);
+    if (lane == 0) {
+      lb_publish(st, P, kLbInclusive | (before + nw));
+      sh.woff = before;
+    }
+  }
+  __syncthreads();
+  const uint64_t woff = j == 0 ? 0 : sh.woff;
+  if (threadIdx.x == 0) {
+    const uint64_t rec = kHeaderBytes + kRecordBytes * j;
+    if (rec + kRecordBytes <= c.cap) {
+      uint64_t* r = reinterpret_cast<uint64_t*>(c.blob + rec);
+      r[0] = md.base;
+      r[1] = uint64_t(__double_as_longlong(md.theta1));
+      r[2] = woff;
+      r[3] = uint64_t(md.bits);
+    }
+    if (c.fixed_len == 0) {
+      const uint64_t so = kHeaderBytes + kRecordBytes * c.m + 8 * j;
+      if (so + 8 <= c.cap) *reinterpret_cast<uint64_t*>(c.blob + so) = start;
+    }
+    if (j + 1 == c.m) finish_column(c, woff + nw, err);
+  }
+  if (nwb) {
+    const auto gdst = global_ptr(reinterpret_cast<uint32_t*>(c.blob + c.words_off) + 2 * woff);
+    const uint64_t cap_w32 = c.cap > c.words_off ? (c.cap - c.words_off) / 4 : 0;
+    const uint64_t avail = cap_w32 > 2 * woff ? cap_w32 - 2 * woff : 0;
+    const uint64_t limit = 2 * nw < avail ? 2 * nw : avail;
+    const uint64_t first = 2 * b * r0;
+    const uint64_t count = first >= limit ? 0 : (limit - first < nwb ? limit - first : nwb);
+    for (uint32_t q = lane; q < count; q += 64) gdst[first + q] = w32[q];
+  }
+}
+
+// The look-back states (scr.woff) and the ticket (scr.bsum[0]) start at 0.
+__global__ void k_fused_clear(EncScratch scr, uint64_t nparts) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nparts; i += stride)
+    scr.woff[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) scr.bsum[0] = 0;
+}
+
+__global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_encode_fused(
+    const EncColumn* __restrict__ cols, uint64_t ncols, EncColumn single, uint64_t nparts,
+    EncScratch scr, int* err) {
+  __shared__ FusedShared sh;
+  if (threadIdx.x == 0)
+    sh.P = atomicAdd(reinterpret_cast<unsigned long long*>(scr.bsum), 1ull);
+  __syncthreads();
+  const uint64_t Pw = sh.P;  // the same in every lane: made scalar
+  const uint64_t P = (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(Pw >> 32))))) << 32) |
+                     uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(Pw))));
+  if (P >= nparts) return;
+  const EncColumn c = column_of(cols, ncols, single, P);
+  encode_fused_part(sh, c, P, scr, err);
+}
+
 // Writes the complete blob of every empty column (no partitions, so no
 // other kernel sees it).
 __global__ void k_encode_prepare(const EncColumn* __restrict__ cols, uint64_t ncols,
@@ -1131,6 +1397,17 @@ hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint6
   hipLaunchKernelGGL(k_encode_prepare, dim3(uint32_t(cg < 4096 ? cg : 4096)), dim3(256), 0,
                      stream, cols_dev, ncols, single, ctx->err_dev);
   if (nparts == 0) return hipGetLastError();
+  const bool wave_fit = max_len <= kWaveEncMax ||
+                        (max_len <= 2 * kWaveEncMax && ctx->tune.encode_wave32);
+  if (regs == kRegLS && ctx->tune.encode_fused && max_len <= kEncRegLen &&
+      !(wave_fit && ctx->tune.encode_wave)) {
+    const uint64_t gc = (nparts + 255) / 256;
+    hipLaunchKernelGGL(k_fused_clear, dim3(uint32_t(gc < 1024 ? gc : 1024)), dim3(256), 0, stream,
+                       scr, nparts);
+    hipLaunchKernelGGL(k_encode_fused, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream,
+                       cols_dev, ncols, single, nparts, scr, ctx->err_dev);
+    return hipGetLastError();
+  }
   const hipError_t e = launch_fit_columns(ctx, cols_dev, ncols, single, nparts, max_len, regs,
                                           scr, stream);
   if (e != hipSuccess) return e;

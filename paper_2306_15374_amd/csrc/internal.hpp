@@ -18,11 +18,12 @@ struct Tune {
   uint32_t ra_lookups_per_lane = 1;  // 1, 2, 4 or 8 positions per lane
   uint32_t encode_wave = 1;          // 1 = one wavefront per partition when all are short
   uint32_t encode_wave32 = 1;        // 1 = the same up to 2048 values (32 per lane)
+  uint32_t encode_fused = 0;         // 1 = one pass over the column (partitions of 2049..4096)
 };
 
 // Reads LECO_TILE_LOG2, LECO_DECODE_BLOCKS_PER_CU, LECO_XCD_REMAP,
-// LECO_RA_LPT, LECO_ENCODE_WAVE and LECO_ENCODE_WAVE32 overrides from the
-// environment.
+// LECO_RA_LPT, LECO_ENCODE_WAVE, LECO_ENCODE_WAVE32 and LECO_ENCODE_FUSED
+// overrides from the environment.
 void tune_from_env(Tune& t);
 
 // One column for the encoder: input, partitioning, output blob.  A table of
