@@ -972,6 +972,8 @@ def main():
         "decode_all_ms": round(t_dec * 1e3, 4),
         "compression_ratio": round(ratio, 5),
         "encode_GBps": round(out_bytes / t_enc / 1e9, 2),
+        # the column read once and the blob written, against 8 TB/s
+        "encode_hbm_frac": round((out_bytes + blob_bytes) / t_enc / HBM_PEAK, 4),
         "roofline": {"bound": "hbm", "achieved": round(alg_bytes / t_dec / 1e9, 1),
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": round(alg_bytes / t_dec / HBM_PEAK, 4),
