@@ -454,7 +454,10 @@ typedef struct {
   uint64_t ticket;
   int32_t status;          /* LECO_OK, or the error that ended the request     */
   int32_t dtype;           /* 4 or 8                                           */
-  const void *out_dev;     /* count values, valid until leco_server_release    */
+  /* count values, valid until leco_server_release; aligned to the value
+   * width (a range's values are placed with value g at g * width modulo
+   * 256 bytes, so that the decoder's stores line up with cache lines) */
+  const void *out_dev;
   uint64_t count;
   double latency_us;       /* submit to observed completion of its step        */
 } leco_completion;
@@ -486,8 +489,9 @@ leco_status leco_server_start(leco_ctx *ctx, const leco_resident_col *cols_host,
  * against n and copied into the position ring here (LECO_ERANGE; LECO_ENOMEM
  * when the ring is momentarily full: retry once earlier requests complete);
  * a request larger than the whole budget is refused (LECO_ENOSPC), one
- * larger than a step (max_step_items workgroups of 256 lookups, or of one
- * decode tile of range values: 2^8 to 2^14 values, the most whose residual
+ * larger than a step (max_step_items workgroups: 256 lookups each, or for a
+ * range one each per tile of the column's decode grid that it touches,
+ * tiles of 2^8 to 2^14 values from position 0, the most whose residual
  * words fit a workgroup's staging memory at the column's bits per value) is
  * LECO_EINVAL.  A request's latency runs from the start of this call. */
 leco_status leco_server_submit(leco_server *s, const leco_request *req,

@@ -31,7 +31,8 @@ struct ServeCol {
 // One workgroup of a step.  Random access: b positions, at index a of the
 // position ring (LECO_REQ_RANDOM_ACCESS) or at device address a
 // (LECO_REQ_RANDOM_ACCESS_DEV), results to out_off.  Range: values [a, b)
-// of the column (at most one decode tile of the column), results to out_off.
+// of the column within one tile of its grid (tiles of 2^tile_log2 values
+// from position 0, as decode_all's), results to out_off.
 struct WorkItem {
   uint32_t kind;
   uint32_t col;
@@ -76,8 +77,14 @@ __global__ __launch_bounds__(kBlock) void k_serve_step(const ServeCol* __restric
       reinterpret_cast<uint32_t*>(out)[i] = uint32_t(v);
     return;
   }
-  uint64_t g0, g1;
-  wave_share(it.a, it.b, c.tile_log2, g0, g1);
+  // the item lies in one tile of the column's grid; wavefront w takes
+  // quarter w of that tile, clipped to the item, so a share starts on the
+  // grid (as in decode_all) except where the request itself begins
+  const uint64_t q = uint64_t(1) << (c.tile_log2 - 2);
+  const uint64_t base = (it.a >> c.tile_log2) << c.tile_log2;
+  uint64_t g0 = base + wave_id() * q, g1 = g0 + q;
+  g0 = g0 > it.a ? g0 : it.a;
+  g1 = g1 < it.b ? g1 : it.b;
   if (g0 >= g1) return;
   bool ok;
   if (h.dtype == 8) {
@@ -152,6 +159,11 @@ struct Pending {
   uint64_t pos_off;  // byte offset of the positions in the ring (host positions)
   uint64_t count, out_bytes;
   uint64_t items;    // work items (workgroups) of the request
+  // bytes between the result's allocation and its first value: a range's
+  // values are placed so that value g sits at g * dtype modulo 256, which
+  // lines up the stores of work items on the column's tile grid with
+  // cache lines
+  uint64_t pad;
   Clock::time_point t_submit;
 };
 
@@ -279,12 +291,13 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
     if (ra && npos + p.count > s->cfg.max_step_positions) break;
     if (s->inflight >= s->cfg.max_inflight) break;
     uint64_t off = 0;
-    if (!s->arena->alloc(p.out_bytes ? p.out_bytes : 1, &off)) break;  // wait for memory
+    const uint64_t bytes = p.out_bytes + p.pad ? p.out_bytes + p.pad : 1;
+    if (!s->arena->alloc(bytes, &off)) break;  // wait for memory
     nitems += items;
     if (ra) npos += p.count;
-    s->results[p.ticket] = Result{off, p.out_bytes ? p.out_bytes : 1, false};
+    s->results[p.ticket] = Result{off, bytes, false};
     ++s->inflight;
-    slot->offs.push_back(off);
+    slot->offs.push_back(off + p.pad);
     slot->reqs.push_back(p);
     s->queue.pop_front();
   }
@@ -310,11 +323,14 @@ bool launch_step(leco_server* s, std::unique_lock<std::mutex>& lk) {
                                                off + first * col.dtype};
       }
     } else {
+      // one item per tile of the column's grid that the range touches
       const uint64_t tile = uint64_t(1) << col.tile_log2;
-      for (uint64_t g = p.req.begin; g < p.req.end; g += tile) {
-        const uint64_t e = g + tile < p.req.end ? g + tile : p.req.end;
+      for (uint64_t g = p.req.begin; g < p.req.end;) {
+        const uint64_t next = (g | (tile - 1)) + 1;
+        const uint64_t e = next < p.req.end ? next : p.req.end;
         slot->items_host[k++] = leco::WorkItem{LECO_REQ_RANGE, p.req.col, g, e,
                                                off + (g - p.req.begin) * col.dtype};
+        g = e;
       }
     }
   }
@@ -525,13 +541,15 @@ leco_status prepare_request(leco_server* s, const leco_request* r, Pending& p) {
   } else if (r->kind == LECO_REQ_RANGE) {
     if (r->begin > r->end || r->end > col.n) return sfail(s, LECO_ERANGE, "range outside [0, n)");
     p.count = r->end - r->begin;
-    p.items = (p.count + (uint64_t(1) << col.tile_log2) - 1) >> col.tile_log2;
+    // tiles of the column's grid that [begin, end) touches
+    p.items = p.count ? ((r->end - 1) >> col.tile_log2) - (r->begin >> col.tile_log2) + 1 : 0;
     if (p.items > s->cfg.max_step_items) return sfail(s, LECO_EINVAL, "range larger than a step");
   } else {
     return sfail(s, LECO_EINVAL, "unknown request kind");
   }
   p.out_bytes = p.count * col.dtype;
-  if (Arena::round(p.out_bytes) > s->cfg.out_budget_bytes)
+  p.pad = r->kind == LECO_REQ_RANGE ? (r->begin * col.dtype) & 255 : 0;
+  if (Arena::round(p.out_bytes + p.pad) > s->cfg.out_budget_bytes)
     return sfail(s, LECO_ENOSPC, "request larger than the output budget");
   if (ring && p.count) {
     // Reserve ring space under the lock, then check and copy the positions
