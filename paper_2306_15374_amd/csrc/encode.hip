@@ -1109,6 +1109,27 @@ __device__ inline uint64_t lb_exclusive(const uint64_t* st, uint64_t first, uint
   return acc;
 }
 
+// Every thread receives the workgroup's min and max of int32 values.
+__device__ inline void block_minmax_i32(FitShared& sh, int32_t& mn, int32_t& mx) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    mn = min(mn, __shfl_xor(mn, m, 64));
+    mx = max(mx, __shfl_xor(mx, m, 64));
+  }
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh.red[wave][0] = uint64_t(uint32_t(mn));
+    sh.red[wave][1] = uint64_t(uint32_t(mx));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kEncWaves; ++w) {
+    mn = min(mn, int32_t(uint32_t(sh.red[w][0])));
+    mx = max(mx, int32_t(uint32_t(sh.red[w][1])));
+  }
+  __syncthreads();
+}
+
 // The model of a partition held in registers as described above.  When
 // the residuals v - vmin - floor(theta1 t) fit int32 (`small`), r32 keeps
 // them for the packing.
@@ -1118,6 +1139,7 @@ __device__ __attribute__((always_inline)) inline Model fit_regs(FitShared& sh, c
                                                                int32_t (&r32)[kEncRegs],
                                                                bool& small_out) {
   small_out = false;
+  const bool full = len == kEncRegLen;  // no position needs masking
   // clamped loads hold the partition's last value: min and max unchanged
   uint64_t vmin = v[0], vmax = v[0];
 #pragma unroll
@@ -1136,7 +1158,7 @@ __device__ __attribute__((always_inline)) inline Model fit_regs(FitShared& sh, c
 #pragma unroll
       for (int k = 0; k < kEncRegs; ++k) {
         const uint32_t t = t0 + 64 * k;
-        const uint64_t y = t < len ? uint32_t(v[k]) - uint32_t(vmin) : 0;
+        const uint64_t y = full || t < len ? uint32_t(v[k]) - uint32_t(vmin) : 0;
         sy += y;
         sty += uint64_t(t) * y;
       }
@@ -1148,7 +1170,7 @@ __device__ __attribute__((always_inline)) inline Model fit_regs(FitShared& sh, c
 #pragma unroll
       for (int k = 0; k < kEncRegs; ++k) {
         const uint32_t t = t0 + 64 * k;
-        const uint64_t x = t < len ? v[k] : 0;
+        const uint64_t x = full || t < len ? v[k] : 0;
         sv = add128(sv, U128{x, 0});
         stv = add128(stv, mul64x64(t, x));
       }
@@ -1162,13 +1184,15 @@ __device__ __attribute__((always_inline)) inline Model fit_regs(FitShared& sh, c
       for (int k = 0; k < kEncRegs; ++k) {
         const uint32_t t = t0 + 64 * k;
         r32[k] = int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t);
-        if (t < len) {
-          mn = r32[k] < mn ? r32[k] : mn;
-          mx = r32[k] > mx ? r32[k] : mx;
+        if (full || t < len) {
+          mn = min(mn, r32[k]);
+          mx = max(mx, r32[k]);
         }
       }
-      rmin = mn;
-      rmax = mx;
+      block_minmax_i32(sh, mn, mx);
+      small_out = true;
+      choose_model(md, th, mn, mx);
+      return md;
     } else {
 #pragma unroll
       for (int k = 0; k < kEncRegs; ++k) {
@@ -1207,14 +1231,25 @@ __device__ __attribute__((always_inline)) inline void encode_fused_part(
   part_bounds(c, j, start, len);
   const uint32_t t0 = wave * 64 * kEncRegs + lane;  // value t0 + 64 k is v[k]
   uint64_t v[kEncRegs];
+  const bool full = len == kEncRegLen;  // no load clamped, no position masked
   if (c.dtype == 8) {
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(c.col) + start;
+    const auto src = global_ptr(reinterpret_cast<const uint64_t*>(c.col) + start);
+    if (full) {
 #pragma unroll
-    for (int k = 0; k < kEncRegs; ++k) v[k] = load_clamped(src, t0 + 64 * k, len);
+      for (int k = 0; k < kEncRegs; ++k) v[k] = src[t0 + 64 * k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) v[k] = load_clamped(src, t0 + 64 * k, len);
+    }
   } else {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(c.col) + start;
+    const auto src = global_ptr(reinterpret_cast<const uint32_t*>(c.col) + start);
+    if (full) {
 #pragma unroll
-    for (int k = 0; k < kEncRegs; ++k) v[k] = load_clamped(src, t0 + 64 * k, len);
+      for (int k = 0; k < kEncRegs; ++k) v[k] = src[t0 + 64 * k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) v[k] = load_clamped(src, t0 + 64 * k, len);
+    }
   }
   int32_t r32[kEncRegs];
   bool small;
@@ -1237,20 +1272,33 @@ __device__ __attribute__((always_inline)) inline void encode_fused_part(
     // constant model
     const bool fits32 = prediction_fits_i32(md.theta1, len);
     const bool reuse = md.linear && small;
+    if (reuse && full) {
+      // every round whole, widths below 32: each residual ORs into two words
+      // (the second gets zero bits when it fits in one)
+      const int32_t rmin = int32_t(md.rmin);
 #pragma unroll
-    for (int k = 0; k < kEncRegs; ++k) {
-      const uint32_t t = t0 + 64 * k;
-      uint64_t u;
-      if (reuse) {
-        u = uint64_t(uint32_t(r32[k] - int32_t(md.rmin)));
-      } else {
-        const uint64_t p = !md.linear ? 0
-                           : fits32   ? uint64_t(int64_t(predict32(md.theta1, t)))
-                                      : uint64_t(predict(md.theta1, t));
-        u = (v[k] - md.base) - p;
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t q = (64 * k + lane) * b;
+        const uint64_t x = uint64_t(uint32_t(r32[k] - rmin)) << (q & 31);
+        atomicOr(&w32[q >> 5], uint32_t(x));
+        atomicOr(&w32[(q >> 5) + 1], uint32_t(x >> 32));
       }
-      if (t >= len) u = 0;
-      if (uint32_t(k) < nr) or_bits(w32, (64 * k + lane) * b, b, u);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kEncRegs; ++k) {
+        const uint32_t t = t0 + 64 * k;
+        uint64_t u;
+        if (reuse) {
+          u = uint64_t(uint32_t(r32[k] - int32_t(md.rmin)));
+        } else {
+          const uint64_t p = !md.linear ? 0
+                             : fits32   ? uint64_t(int64_t(predict32(md.theta1, t)))
+                                        : uint64_t(predict(md.theta1, t));
+          u = (v[k] - md.base) - p;
+        }
+        if (t >= len) u = 0;
+        if (uint32_t(k) < nr) or_bits(w32, (64 * k + lane) * b, b, u);
+      }
     }
     wave_fence();
   }
