@@ -901,12 +901,18 @@ __device__ inline void wave_lds_order() {
 }
 
 // Sign of (b - a) x (c - a) for points with ta < tb < tc whose values lie
-// within 2^61 of each other (kNarrow: within 2^43, so that with t < 2^20
-// each product fits in 64 bits).
-template <bool kNarrow = false>
+// within 2^61 of each other.  kW = 64: within 2^43, so that with t < 2^20
+// each product fits in 64 bits; kW = 32: within 2^31, so that each factor
+// fits in 32 bits as well (one 32 x 32 -> 64 multiply).
+template <int kW = 128>
 __device__ inline int turn(uint32_t ta, uint64_t xa, uint32_t tb, uint64_t xb, uint32_t tc,
                            uint64_t xc) {
-  if (kNarrow) {
+  if (kW == 32) {
+    const int64_t l = int64_t(int32_t(tb - ta)) * int64_t(int32_t(uint32_t(xc - xa)));
+    const int64_t r = int64_t(int32_t(uint32_t(xb - xa))) * int64_t(int32_t(tc - ta));
+    return l > r ? 1 : (l < r ? -1 : 0);
+  }
+  if (kW == 64) {
     const int64_t l = int64_t(tb - ta) * int64_t(xc - xa);
     const int64_t r = int64_t(xb - xa) * int64_t(tc - ta);
     return l > r ? 1 : (l < r ? -1 : 0);
@@ -924,7 +930,7 @@ __device__ inline int turn(uint32_t ta, uint64_t xa, uint32_t tb, uint64_t xb, u
 // survivors then go through the monotone chain in order, lane 0 keeping the
 // upper hull and lane 1 the lower one side by side, each with its two last
 // vertices in registers.  Called by a whole wavefront, uniform arguments.
-template <bool kNarrow>
+template <int kW>
 __device__ inline void hull_append_t(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t sa,
                                      uint64_t u0, uint64_t u1, HullLds& w, HullRegs& hr) {
   const uint32_t lane = threadIdx.x & 63;
@@ -958,7 +964,7 @@ __device__ inline void hull_append_t(const uint8_t* __restrict__ col, uint32_t d
       for (uint32_t ic = 0; ic < 5; ++ic) {
         const uint32_t c = 1u << ic;
         if (t + c >= u1) break;
-        const int tr = turn<kNarrow>(0, xa, a, x, a + c, w.stage[kHalo + lane + c]);
+        const int tr = turn<kW>(0, xa, a, x, a + c, w.stage[kHalo + lane + c]);
         if (tr >= 0) cu = false;
         if (tr <= 0) cl = false;
       }
@@ -974,7 +980,7 @@ __device__ inline void hull_append_t(const uint8_t* __restrict__ col, uint32_t d
       const bool mine = lane < 2 && (((side ? ml : mu) >> q) & 1);
       if (mine && !over) {
         while (n >= 2) {
-          const int tr = turn<kNarrow>(t2, x2, t1, x1, tq, xq);
+          const int tr = turn<kW>(t2, x2, t1, x1, tq, xq);
           if (side ? tr > 0 : tr < 0) break;  // a strict turn keeps the last vertex
           --n;
           t1 = t2;
@@ -1005,14 +1011,16 @@ __device__ inline void hull_append_t(const uint8_t* __restrict__ col, uint32_t d
   wave_lds_order();  // the vertices are read by every lane next
 }
 
-// Values spread below 2^43 take the 64-bit turn test.
+// Values spread below 2^31 take the 32-bit turn test, below 2^43 the 64-bit one.
 __device__ inline void hull_append(const uint8_t* __restrict__ col, uint32_t dtype, uint64_t sa,
                                    uint64_t u0, uint64_t u1, uint64_t spread, HullLds& w,
                                    HullRegs& hr) {
-  if (spread < (uint64_t(1) << 43))
-    hull_append_t<true>(col, dtype, sa, u0, u1, w, hr);
+  if (spread < (uint64_t(1) << 31))
+    hull_append_t<32>(col, dtype, sa, u0, u1, w, hr);
+  else if (spread < (uint64_t(1) << 43))
+    hull_append_t<64>(col, dtype, sa, u0, u1, w, hr);
   else
-    hull_append_t<false>(col, dtype, sa, u0, u1, w, hr);
+    hull_append_t<128>(col, dtype, sa, u0, u1, w, hr);
 }
 
 __device__ inline void hull_store(ChainHull* __restrict__ g, const ChainHull& h, const HullRegs& hr) {
@@ -1186,20 +1194,42 @@ __device__ bool merge_walk(const uint8_t* __restrict__ col, uint32_t dtype,
     int64_t rmin = INT64_MAX, rmax = INT64_MIN;
     const uint64_t lmax = readlane64(len_l, nact - 1);
     const uint8_t* src = col + sa * dtype;
+    // 32 bits suffice when, on every lane fitting a line, the union's values
+    // lie within 2^31 of its minimum and every |prediction| is below 2^31
+    const bool narrow =
+        __ballot(lin && !(range < (uint64_t(1) << 31) &&
+                          __dmul_rn(fabs(th), double(len_l)) < 2147483648.0)) == 0;
+    // the values of [tb, lmax) staged 64 at a time in LDS, each read by
+    // every lane at once, every lane predicting with its own slope
     auto scan = [&](uint64_t tb) {
       for (uint64_t t0 = tb; t0 < lmax; t0 += 64) {
         const uint64_t t = t0 + lane;
-        const uint64_t x = load_value(src, dtype, t < lmax ? t : lmax - 1);
+        w.stage[lane] = load_value(src, dtype, t < lmax ? t : lmax - 1);
+        wave_lds_order();
         const uint32_t cnt = lmax - t0 < 64 ? uint32_t(lmax - t0) : 64u;
-        for (uint32_t q = 0; q < cnt; ++q) {
-          const uint64_t xq = readlane64(x, q);
-          const uint64_t tq = t0 + q;
-          if (lin && tq < len_l) {
-            const int64_t rr = int64_t(xq - vmin) - predict(th, uint32_t(tq));
-            rmin = rr < rmin ? rr : rmin;
-            rmax = rr > rmax ? rr : rmax;
+        if (narrow) {
+          const uint32_t vmin32 = uint32_t(vmin);
+          int32_t mn = INT32_MAX, mx = INT32_MIN;
+          for (uint32_t q = 0; q < cnt; ++q) {
+            const uint32_t tq = uint32_t(t0) + q;
+            const bool in = lin && tq < len_l;
+            const int32_t rr = int32_t(uint32_t(w.stage[q]) - vmin32) - predict32(th, in ? tq : 0);
+            mn = in ? min(mn, rr) : mn;
+            mx = in ? max(mx, rr) : mx;
+          }
+          rmin = mn < rmin ? mn : rmin;
+          rmax = mx > rmax ? mx : rmax;
+        } else {
+          for (uint32_t q = 0; q < cnt; ++q) {
+            const uint64_t tq = t0 + q;
+            if (lin && tq < len_l) {
+              const int64_t rr = int64_t(w.stage[q] - vmin) - predict(th, uint32_t(tq));
+              rmin = rr < rmin ? rr : rmin;
+              rmax = rr > rmax ? rr : rmax;
+            }
           }
         }
+        wave_lds_order();  // every read of the block precedes the next one's staging
       }
     };
     bool scan_all = !via_hull;
