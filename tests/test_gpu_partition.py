@@ -107,6 +107,27 @@ def test_merge_chains_across_chunks_and_groups(torch, codec, ref):
     check(torch, codec, ref, runs, "short runs tau 0", tau=0.0)
 
 
+def test_merge_chains_wide_values(torch, codec, ref):
+    """Long runs of merges (tau = 0 splits into partitions of two values,
+    the scan merges them back into partitions of thousands) on 64-bit
+    values whose spread needs the 64-bit turn tests of the partition's hulls
+    (2^38), the 128-bit ones (2^58), and steep lines whose largest
+    prediction reaches 2^33, where the hull range test hands every batch to
+    a scan of all the values."""
+    rng = np.random.default_rng(90)
+    n = 60_000
+    base = W.piecewise_linear(n, 93, segments=20).astype(np.uint64)
+    check(torch, codec, ref, base * np.uint64(1 << 20) + rng.integers(0, 1 << 20, n, dtype=np.uint64),
+          "polyline x 2^20 (spread 2^38)", tau=0.0)
+    check(torch, codec, ref, base * np.uint64(1 << 40) + rng.integers(0, 1 << 40, n, dtype=np.uint64),
+          "polyline x 2^40 (spread 2^58)", tau=0.0)
+    steep = np.arange(n, dtype=np.uint64) * np.uint64(1 << 22) + rng.integers(0, 1 << 12, n,
+                                                                            dtype=np.uint64)
+    check(torch, codec, ref, steep, "steep line (predictions beyond 2^31)", tau=0.0)
+    check(torch, codec, ref, steep, "steep line, one pass, cap 3000", tau=0.0, max_passes=1,
+          max_len=3000)
+
+
 def test_cap_counts_from_the_partition_start(torch, codec, ref):
     """One line cut by the cost at 1000, then 2^20 + 5000 values of another
     line: the cap cuts at 1000 + 2^20, inside the second split segment."""
