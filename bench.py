@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=24 * 4096 * 1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["sorted_keys", "batched", "served", "variable",
-                                           "encode_options", "higher_order"],
+                                           "encode_options", "higher_order", "encode_latency"],
                     default="sorted_keys")
     ap.add_argument("--var-n", type=int, default=100_000_000)
     ap.add_argument("--tau", type=float, default=0.03,
@@ -744,6 +744,69 @@ def bench_encode_options(args):
     codec.close()
 
 
+def bench_encode_latency(args):
+    """Encode time of one sorted-key uint64 column from 1e4 to 1e8 values at
+    partitions of 1024 and 4096, launches back to back on one stream: the
+    default context (a one-pass encoder for launches of at most two
+    workgroups per CU, else two passes) against one with the one-pass
+    encoders off.  Both contexts' blobs are compared byte for byte."""
+    import torch
+    import paper_2306_15374_amd as P
+    from paper_2306_15374_amd import workloads as W
+
+    keys = ("LECO_ENCODE_FUSED", "LECO_ENCODE_FUSED_WAVE")
+    old = {k: os.environ.get(k) for k in keys}
+    auto = P.Codec(0)
+    os.environ.update({k: "0" for k in keys})
+    try:
+        two = P.Codec(0)  # the overrides are read when a context is created
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    stream = torch.cuda.current_stream()
+    rows = []
+    for L in (1024, 4096):
+        for n in (10**4, 10**5, 10**6, 2 * 10**6, 3 * 10**6, 10**7, 10**8):
+            d = W.lognormal_keys_device(n, 5, np.uint64)
+            part, keep = P.make_partitioning(fixed_len=L)
+            cap = P.leco_max_blob_bytes(n, P.LECO_U64, part)
+            size = torch.zeros(1, dtype=torch.uint64, device="cuda")
+            row, blobs = {"L": L, "n": n}, []
+            for name, c in (("default", auto), ("two_pass", two)):
+                buf = torch.empty(cap, dtype=torch.uint8, device="cuda")
+                f = lambda: c.check("leco_encode_async", P.leco_encode_async(
+                    c.ctx, d, n, P.LECO_U64, part, buf, cap, size))
+                f()
+                c.sync()
+                blobs.append(buf[: int(size.item())].clone())
+                reps = max(5, min(200, int(2e9 / n)))
+                row[f"{name}_us"] = round(time_stream(torch, stream, f, reps) * 1e6, 2)
+            assert torch.equal(blobs[0], blobs[1]), f"encode_latency: blobs differ at L {L} n {n}"
+            log(f"encode latency: {row}")
+            rows.append(row)
+            del d, blobs, keep
+    torch.cuda.empty_cache()
+    head = next(r for r in rows if r["L"] == 1024 and r["n"] == 10**6)
+    res = {
+        "metric": "decoded GB/s + lookups/s vs HBM roofline (batched/served vs plain); p99 latency",
+        "value": head["default_us"], "unit": "us per encode (1e6 uint64 values, partitions of 1024)",
+        "n_gpus": 1, "steps": None, "warmup": 1, "ms_per_step": round(head["default_us"] / 1e3, 5),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic (seeded lognormal-gap sorted keys)",
+        "config": {"workload": "encode latency: one uint64 column of 1e4..1e8 values, partitions "
+                               "of 1024 and 4096, default context against two passes"},
+        "sizes": rows,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+    auto.close()
+    two.close()
+
+
 def bench_higher_order(args):
     """The polynomial regressor on the evaluation's higher-order data: a
     two-sine signal with Gaussian noise (1e8 uint32 values, partitions of
@@ -848,6 +911,8 @@ def main():
         return bench_encode_options(args)
     if args.workload == "higher_order":
         return bench_higher_order(args)
+    if args.workload == "encode_latency":
+        return bench_encode_latency(args)
     import torch
     import paper_2306_15374_amd as P
     from paper_2306_15374_amd import workloads as W

@@ -172,13 +172,13 @@ __device__ inline uint64_t load_clamped(const T* src, uint32_t t, uint64_t len) 
   return uint64_t(global_ptr(src)[t < len ? t : uint32_t(len - 1)]);
 }
 
-// The model of a partition of len <= 64 kR values, by one wavefront.
-template <int kR, class T>
-__device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, uint64_t len, bool force_constant) {
+// The model of a partition of len <= 64 kR values held by one wavefront,
+// value lane + 64 k in v[k] (positions past len holding its last value).
+template <int kR>
+__device__ __attribute__((always_inline)) inline Model fit_wave_regs(const uint64_t (&v)[kR],
+                                                                    uint64_t len,
+                                                                    bool force_constant) {
   const uint32_t lane = threadIdx.x & 63;
-  uint64_t v[kR];
-#pragma unroll
-  for (int k = 0; k < kR; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
   // clamped lanes hold the last value, which leaves min and max unchanged
   uint64_t vmin = v[0], vmax = v[0];
 #pragma unroll
@@ -232,6 +232,16 @@ __device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, ui
     choose_model(md, th, rmin, rmax);
   }
   return md;
+}
+
+// The same, loading the partition (len <= 64 kR values) first.
+template <int kR, class T>
+__device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, uint64_t len, bool force_constant) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint64_t v[kR];
+#pragma unroll
+  for (int k = 0; k < kR; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
+  return fit_wave_regs<kR>(v, len, force_constant);
 }
 
 template <int kR>
@@ -1337,12 +1347,19 @@ __device__ __attribute__((always_inline)) inline void encode_fused_part(
   }
 }
 
-// The look-back states (scr.woff) and the ticket (scr.bsum[0]) start at 0.
-__global__ void k_fused_clear(EncScratch scr, uint64_t nparts) {
+// Before a one-pass encode: the look-back states (scr.woff) and the ticket
+// (scr.bsum[0]) start at 0, and every empty column's blob is written whole
+// (as k_encode_prepare does; one launch instead of two).
+__global__ void k_fused_prepare(const EncColumn* __restrict__ cols, uint64_t ncols,
+                                EncColumn single, EncScratch scr, uint64_t nparts, int* err) {
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nparts; i += stride)
-    scr.woff[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) scr.bsum[0] = 0;
+  const uint64_t first = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (uint64_t i = first; i < nparts; i += stride) scr.woff[i] = 0;
+  if (first == 0) scr.bsum[0] = 0;
+  for (uint64_t i = first; i < ncols; i += stride) {
+    const EncColumn& c = cols ? cols[i] : single;
+    if (c.m == 0) finish_column(c, 0, err);
+  }
 }
 
 __global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_encode_fused(
@@ -1358,6 +1375,100 @@ __global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(4))) 
   if (P >= nparts) return;
   const EncColumn c = column_of(cols, ncols, single, P);
   encode_fused_part(sh, c, P, scr, err);
+}
+
+// The one-pass encoder for partitions of at most 64 kR values: one
+// wavefront per partition, no workgroup barrier after the ticket.  Values in
+// registers, model by wavefront shuffles, word count published, residuals
+// packed in the wavefront's LDS slice, look-back, record and words written.
+template <int kR>
+__global__ __launch_bounds__(kEncBlock) void k_encode_fused_wave(
+    const EncColumn* __restrict__ cols, uint64_t ncols, EncColumn single, uint64_t nparts,
+    EncScratch scr, int* err) {
+  __shared__ uint32_t words[kEncWaves][2 * 64 * kR];
+  __shared__ uint64_t ticket;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // one ticket per workgroup, whose waves take partitions 4 ticket ..
+  // 4 ticket + 3 (a ticket per wavefront, 2e6 device-scope atomics on one
+  // word for 2e9 values, doubled the time of such a launch)
+  if (threadIdx.x == 0)
+    ticket = atomicAdd(reinterpret_cast<unsigned long long*>(scr.bsum), 1ull);
+  __syncthreads();
+  const uint64_t tk = ticket;
+  const uint64_t P = kEncWaves * ((uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(tk >> 32))))) << 32) |
+                                  uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(tk))))) +
+                     wave;
+  if (P >= nparts) return;
+  const EncColumn c = column_of(cols, ncols, single, P);
+  uint64_t start, len;
+  const uint64_t j = P - c.part_base;
+  part_bounds(c, j, start, len);
+  if (len > 64 * kR) {  // the host sends such launches to the two passes
+    if (lane == 0) raise(err, kErrDevice);
+    return;
+  }
+  uint64_t v[kR];
+  if (c.dtype == 8) {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(c.col) + start;
+#pragma unroll
+    for (int k = 0; k < kR; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
+  } else {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(c.col) + start;
+#pragma unroll
+    for (int k = 0; k < kR; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
+  }
+  const Model md = fit_wave_regs<kR>(v, len, c.force_constant != 0);
+  const uint64_t nw = (len * md.bits + 63) >> 6;
+  uint64_t* st = scr.woff;
+  if (lane == 0) lb_publish(st, P, (j == 0 ? kLbInclusive : kLbCount) | nw);
+  const uint32_t b = md.bits;
+  const uint32_t nr = uint32_t((len + 63) / 64);
+  const uint32_t nwb = 2 * b * nr;
+  uint32_t* w32 = words[wave];
+  if (nwb) {
+    for (uint32_t q = lane; q < nwb; q += 64) w32[q] = 0;
+    wave_fence();
+    const bool fits32 = prediction_fits_i32(md.theta1, len);
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      const uint32_t t = lane + 64 * k;
+      const uint64_t p = !md.linear ? 0
+                         : fits32   ? uint64_t(int64_t(predict32(md.theta1, t)))
+                                    : uint64_t(predict(md.theta1, t));
+      const uint64_t u = t < len ? (v[k] - md.base) - p : 0;
+      if (uint32_t(k) < nr) or_bits(w32, t * b, b, u);
+    }
+    wave_fence();
+  }
+  uint64_t woff = 0;
+  if (j != 0) {
+    woff = lb_exclusive(st, c.part_base, P);
+    if (lane == 0) lb_publish(st, P, kLbInclusive | (woff + nw));
+  }
+  if (lane == 0) {
+    const uint64_t rec = kHeaderBytes + kRecordBytes * j;
+    if (rec + kRecordBytes <= c.cap) {
+      uint64_t* r = reinterpret_cast<uint64_t*>(c.blob + rec);
+      r[0] = md.base;
+      r[1] = uint64_t(__double_as_longlong(md.theta1));
+      r[2] = woff;
+      r[3] = uint64_t(md.bits);
+    }
+    if (c.fixed_len == 0) {
+      const uint64_t so = kHeaderBytes + kRecordBytes * c.m + 8 * j;
+      if (so + 8 <= c.cap) *reinterpret_cast<uint64_t*>(c.blob + so) = start;
+    }
+    if (j + 1 == c.m) finish_column(c, woff + nw, err);
+  }
+  if (nwb) {
+    const auto gdst = global_ptr(reinterpret_cast<uint32_t*>(c.blob + c.words_off) + 2 * woff);
+    const uint64_t cap_w32 = c.cap > c.words_off ? (c.cap - c.words_off) / 4 : 0;
+    const uint64_t avail = cap_w32 > 2 * woff ? cap_w32 - 2 * woff : 0;
+    const uint64_t limit = 2 * nw < avail ? 2 * nw : avail;
+    const uint64_t count = limit < nwb ? limit : nwb;
+    for (uint32_t q = lane; q < count; q += 64) gdst[q] = w32[q];
+  }
 }
 
 // Writes the complete blob of every empty column (no partitions, so no
@@ -1441,26 +1552,38 @@ hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t
 hipError_t launch_encode_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t ncols,
                                  const EncColumn& single, uint64_t nparts, uint64_t max_len,
                                  uint32_t regs, const EncScratch& scr, hipStream_t stream) {
+  const bool wave_fit = max_len <= kWaveEncMax ||
+                        (max_len <= 2 * kWaveEncMax && ctx->tune.encode_wave32);
+  const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
+  const auto fused = [&](uint32_t mode, uint64_t workgroups) {
+    return mode == 1 || (mode == 2 && workgroups <= uint64_t(kFusedAutoPerCu) * ctx->num_cus);
+  };
+  const bool one_pass_wave = nparts != 0 && regs == kRegLS && ctx->tune.encode_wave &&
+                             max_len <= kWaveEncMax && fused(ctx->tune.encode_fused_wave, pw);
+  const bool one_pass = nparts != 0 && regs == kRegLS && !one_pass_wave &&
+                        max_len <= kEncRegLen && !(wave_fit && ctx->tune.encode_wave) &&
+                        fused(ctx->tune.encode_fused, nparts);
+  if (one_pass_wave || one_pass) {
+    const uint64_t items = nparts > ncols ? nparts : ncols;
+    const uint64_t g = (items + 255) / 256;
+    hipLaunchKernelGGL(k_fused_prepare, dim3(uint32_t(g < 4096 ? g : 4096)), dim3(256), 0, stream,
+                       cols_dev, ncols, single, scr, nparts, ctx->err_dev);
+    if (one_pass_wave)
+      hipLaunchKernelGGL(k_encode_fused_wave<kWaveRegs>, dim3(uint32_t(pw)), dim3(kEncBlock), 0,
+                         stream, cols_dev, ncols, single, nparts, scr, ctx->err_dev);
+    else
+      hipLaunchKernelGGL(k_encode_fused, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream,
+                         cols_dev, ncols, single, nparts, scr, ctx->err_dev);
+    return hipGetLastError();
+  }
   const uint64_t cg = (ncols + 255) / 256;
   hipLaunchKernelGGL(k_encode_prepare, dim3(uint32_t(cg < 4096 ? cg : 4096)), dim3(256), 0,
                      stream, cols_dev, ncols, single, ctx->err_dev);
   if (nparts == 0) return hipGetLastError();
-  const bool wave_fit = max_len <= kWaveEncMax ||
-                        (max_len <= 2 * kWaveEncMax && ctx->tune.encode_wave32);
-  if (regs == kRegLS && ctx->tune.encode_fused && max_len <= kEncRegLen &&
-      !(wave_fit && ctx->tune.encode_wave)) {
-    const uint64_t gc = (nparts + 255) / 256;
-    hipLaunchKernelGGL(k_fused_clear, dim3(uint32_t(gc < 1024 ? gc : 1024)), dim3(256), 0, stream,
-                       scr, nparts);
-    hipLaunchKernelGGL(k_encode_fused, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream,
-                       cols_dev, ncols, single, nparts, scr, ctx->err_dev);
-    return hipGetLastError();
-  }
   const hipError_t e = launch_fit_columns(ctx, cols_dev, ncols, single, nparts, max_len, regs,
                                           scr, stream);
   if (e != hipSuccess) return e;
   const bool wave = max_len <= kWaveEncMax && ctx->tune.encode_wave;  // pack only
-  const uint64_t pw = (nparts + kEncWaves - 1) / kEncWaves;
   const uint64_t ng = (nparts + kScanItems - 1) / kScanItems;
   hipLaunchKernelGGL(k_scan_sums, dim3(uint32_t(ng)), dim3(kEncBlock), 0, stream, scr, nparts);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kEncBlock), 0, stream, scr, ng);

@@ -18,12 +18,22 @@ struct Tune {
   uint32_t ra_lookups_per_lane = 1;  // 1, 2, 4 or 8 positions per lane
   uint32_t encode_wave = 1;          // 1 = one wavefront per partition when all are short
   uint32_t encode_wave32 = 1;        // 1 = the same up to 2048 values (32 per lane)
-  uint32_t encode_fused = 0;         // 1 = one pass over the column (partitions of 2049..4096)
+  // One pass over the column with a decoupled look-back: a workgroup per
+  // partition (partitions of 2049..4096) or a wavefront per partition (at
+  // most 1024).  0 = never, 1 = always where it applies, 2 = for launches of
+  // at most kFusedAutoPerCu workgroups per CU.
+  uint32_t encode_fused = 2;
+  uint32_t encode_fused_wave = 2;
 };
 
+// Past about two workgroups per CU (2e6 8-byte values at partitions of 1024
+// or 4096) the two-pass encoder is faster; below, its six launches cost more
+// than the one-pass kernel's look-back.
+constexpr uint32_t kFusedAutoPerCu = 2;
+
 // Reads LECO_TILE_LOG2, LECO_DECODE_BLOCKS_PER_CU, LECO_XCD_REMAP,
-// LECO_RA_LPT, LECO_ENCODE_WAVE, LECO_ENCODE_WAVE32 and LECO_ENCODE_FUSED
-// overrides from the environment.
+// LECO_RA_LPT, LECO_ENCODE_WAVE, LECO_ENCODE_WAVE32, LECO_ENCODE_FUSED and
+// LECO_ENCODE_FUSED_WAVE overrides from the environment.
 void tune_from_env(Tune& t);
 
 // One column for the encoder: input, partitioning, output blob.  A table of

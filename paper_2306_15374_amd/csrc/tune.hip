@@ -21,7 +21,8 @@ void tune_from_env(Tune& t) {
   env_u32("LECO_XCD_REMAP", 0, 1, &t.xcd_remap);
   env_u32("LECO_ENCODE_WAVE", 0, 1, &t.encode_wave);
   env_u32("LECO_ENCODE_WAVE32", 0, 1, &t.encode_wave32);
-  env_u32("LECO_ENCODE_FUSED", 0, 1, &t.encode_fused);
+  env_u32("LECO_ENCODE_FUSED", 0, 2, &t.encode_fused);
+  env_u32("LECO_ENCODE_FUSED_WAVE", 0, 2, &t.encode_fused_wave);
   uint32_t lpt = t.ra_lookups_per_lane;
   if (env_u32("LECO_RA_LPT", 1, 8, &lpt) && (lpt == 1 || lpt == 2 || lpt == 4 || lpt == 8))
     t.ra_lookups_per_lane = lpt;
