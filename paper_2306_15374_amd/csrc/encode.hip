@@ -379,6 +379,16 @@ __global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(5))) 
 
 // ---- fit with the minimax regressor: one workgroup per partition ------------------
 
+// A hull tile's LDS word for an offset below kHullF64Range: its binary64 bits.
+__device__ inline uint64_t f64_word(uint64_t offset) {
+  return uint64_t(__double_as_longlong(double(offset)));
+}
+// The value a hull tile's word stands for: the word itself, or (f64) the
+// offset its binary64 bits hold (an integer below 2^40: exact).
+__device__ inline uint64_t tile_word_value(uint64_t word, bool f64) {
+  return f64 ? uint64_t(__longlong_as_double(static_cast<long long>(word))) : word;
+}
+
 // The least-squares model of fit_block, then (minimax) the minimax line
 // of section 3.1's fixed-width objective, stored instead when its residual
 // width is strictly smaller.  run_up / run_lo: the partition's running hulls
@@ -393,6 +403,8 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
   const auto gsrc = global_ptr(src);
   const uint32_t tid = threadIdx.x;
   const uint32_t ntiles = uint32_t((len + kHullTile - 1) / kHullTile);
+  // one tile of a narrow range: the hull tests in binary64
+  const bool f64 = ntiles == 1 && md.range < kHullF64Range;
   for (uint32_t k = 0; k < ntiles; ++k) {
     const uint32_t t0 = k * kHullTile;
     const uint32_t cnt = uint32_t(len - t0 < kHullTile ? len - t0 : kHullTile);
@@ -406,11 +418,14 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
 #pragma unroll
       for (uint32_t j = 0; j < kHullChunk; ++j) {
         const uint32_t x = tid + j * kEncBlock;
-        if (x < cnt) hs.v[x] = tv[j];
+        if (x < cnt) hs.v[x] = f64 ? f64_word(tv[j] - md.vmin) : tv[j];
       }
     }
     __syncthreads();
-    tile_hulls<kEncBlock>(hs, cnt, tid);
+    if (f64)
+      tile_hulls<kEncBlock, true>(hs, cnt, tid);
+    else
+      tile_hulls<kEncBlock, false>(hs, cnt, tid);
     if (ntiles == 1) break;
     uint32_t keep[2], from[2], c[2];
     for (uint32_t side = 0; side < 2; ++side) c[side] = hs.cnt[side][0];
@@ -449,15 +464,13 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
     __syncthreads();
   }
   EdgeSlope th;
-  if (ntiles == 1) {
-    const auto U = [&](uint32_t i) {
-      const uint32_t t = hs.h[0][i];
-      return HullPoint{t, hs.v[t]};
-    };
-    const auto L = [&](uint32_t i) {
-      const uint32_t t = hs.h[1][i];
-      return HullPoint{t, hs.v[t]};
-    };
+  if (f64) {
+    const auto U = [&](uint32_t i) { return hull_pt<true>(hs.h[0][i], hs.v[hs.h[0][i]]); };
+    const auto L = [&](uint32_t i) { return hull_pt<true>(hs.h[1][i], hs.v[hs.h[1][i]]); };
+    th = minimax_bend<kEncBlock>(hs, U, hs.cnt[0][0], L, hs.cnt[1][0], tid);
+  } else if (ntiles == 1) {
+    const auto U = [&](uint32_t i) { return hull_pt<false>(hs.h[0][i], hs.v[hs.h[0][i]]); };
+    const auto L = [&](uint32_t i) { return hull_pt<false>(hs.h[1][i], hs.v[hs.h[1][i]]); };
     th = minimax_bend<kEncBlock>(hs, U, hs.cnt[0][0], L, hs.cnt[1][0], tid);
   } else {
     const auto U = [&](uint32_t i) {
@@ -479,7 +492,8 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax(FitShared& fs
     for (uint32_t j = 0; j < kHullChunk; ++j) {
       const uint32_t t = t0 + tid + j * kEncBlock;
       if (t < len) {
-        const uint64_t x = ntiles == 1 ? hs.v[t] : uint64_t(gsrc[t]);
+        const uint64_t x = ntiles == 1 ? (f64 ? md.vmin + tile_word_value(hs.v[t], true) : hs.v[t])
+                                       : uint64_t(gsrc[t]);
         const int64_t rr = int64_t(x - md.vmin) - predict(theta, t);
         rmin = rr < rmin ? rr : rmin;
         rmax = rr > rmax ? rr : rmax;
@@ -547,20 +561,25 @@ __device__ __attribute__((always_inline)) inline Model fit_minimax_wave(HullShar
   uint64_t v[kWaveRegs];
 #pragma unroll
   for (int k = 0; k < kWaveRegs; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
+  const bool f64 = md.range < kHullF64Range;  // the hull tests in binary64
 #pragma unroll
   for (int k = 0; k < kWaveRegs; ++k)
-    if (lane + 64 * k < len) hs.v[lane + 64 * k] = v[k];
+    if (lane + 64 * k < len) hs.v[lane + 64 * k] = f64 ? f64_word(v[k] - md.vmin) : v[k];
   group_sync<64>();
-  tile_hulls<64>(hs, uint32_t(len), lane);
-  const auto U = [&](uint32_t i) {
-    const uint32_t t = hs.h[0][i];
-    return HullPoint{t, hs.v[t]};
-  };
-  const auto L = [&](uint32_t i) {
-    const uint32_t t = hs.h[1][i];
-    return HullPoint{t, hs.v[t]};
-  };
-  const EdgeSlope th = minimax_bend<64>(hs, U, hs.cnt[0][0], L, hs.cnt[1][0], lane);
+  if (f64)
+    tile_hulls<64, true>(hs, uint32_t(len), lane);
+  else
+    tile_hulls<64, false>(hs, uint32_t(len), lane);
+  EdgeSlope th;
+  if (f64) {
+    const auto U = [&](uint32_t i) { return hull_pt<true>(hs.h[0][i], hs.v[hs.h[0][i]]); };
+    const auto L = [&](uint32_t i) { return hull_pt<true>(hs.h[1][i], hs.v[hs.h[1][i]]); };
+    th = minimax_bend<64>(hs, U, hs.cnt[0][0], L, hs.cnt[1][0], lane);
+  } else {
+    const auto U = [&](uint32_t i) { return hull_pt<false>(hs.h[0][i], hs.v[hs.h[0][i]]); };
+    const auto L = [&](uint32_t i) { return hull_pt<false>(hs.h[1][i], hs.v[hs.h[1][i]]); };
+    th = minimax_bend<64>(hs, U, hs.cnt[0][0], L, hs.cnt[1][0], lane);
+  }
   double theta = static_cast<double>(th.dy) / static_cast<double>(th.dt);
   if (theta == 0.0) theta = 0.0;  // +0.0, never -0.0
   int64_t rmin = INT64_MAX, rmax = INT64_MIN;

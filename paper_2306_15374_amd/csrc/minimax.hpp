@@ -20,7 +20,12 @@
 //     sign needs one binary search over the other hull; a workgroup
 //     minimum picks the smallest passing edge.
 // Cross products are exact: positions differ by less than 2^20 and values by
-// less than 2^61, so differences fit int64 and products int128.
+// less than 2^61, so differences fit int64 and products int128.  A hull tile
+// whose values span less than 2^40 holds them as binary64 offsets from the
+// partition minimum instead: positions below 2^12 and offsets below 2^40
+// give differences below 2^41 and products below 2^53, so the same tests
+// are exact in binary64, at a few instructions instead of two 128-bit
+// products.
 #pragma once
 
 #include "fit.hpp"
@@ -35,12 +40,37 @@ struct HullPoint {
   uint64_t v;   // value
 };
 
+// A point of a tile held in binary64: position and offset from the minimum.
+struct HullPointF {
+  double t, y;
+};
+
+// Offsets below this bound take the binary64 tests (tiles of at most 4096
+// points).
+constexpr uint64_t kHullF64Range = uint64_t(1) << 40;
+
 // Whether q leaves the upper (lower) hull of p, q, r with p.t < q.t < r.t:
 // r lies on or above (on or below) the line through p and q.
 __device__ inline bool hull_drops(bool upper, HullPoint p, HullPoint q, HullPoint r) {
   const __int128 a = __int128(int64_t(q.t - p.t)) * int64_t(r.v - p.v);
   const __int128 b = __int128(int64_t(q.v - p.v)) * int64_t(r.t - p.t);
   return upper ? a >= b : a <= b;
+}
+
+__device__ inline bool hull_drops(bool upper, HullPointF p, HullPointF q, HullPointF r) {
+  const double a = __dmul_rn(q.t - p.t, r.y - p.y);
+  const double b = __dmul_rn(q.y - p.y, r.t - p.t);
+  return upper ? a >= b : a <= b;
+}
+
+// Tile point x with its LDS word: the value itself, or (kF) the bits of its
+// binary64 offset.
+template <bool kF>
+__device__ __attribute__((always_inline)) inline auto hull_pt(uint32_t x, uint64_t word) {
+  if constexpr (kF)
+    return HullPointF{double(x), __longlong_as_double(static_cast<long long>(word))};
+  else
+    return HullPoint{x, word};
 }
 
 struct EdgeSlope {
@@ -60,6 +90,27 @@ __device__ inline bool slope_lt(EdgeSlope a, EdgeSlope b) {
   return __int128(a.dy) * b.dt < __int128(b.dy) * a.dt;
 }
 
+// The same on binary64 points (offsets below 2^40, positions below 2^12:
+// dy and dt exact, products below 2^52).
+struct EdgeSlopeF {
+  double dy, dt;
+};
+
+__device__ inline EdgeSlopeF edge_slope(HullPointF a, HullPointF b) {
+  return EdgeSlopeF{b.y - a.y, b.t - a.t};
+}
+
+__device__ inline bool slope_le(EdgeSlopeF a, EdgeSlopeF b) {
+  return __dmul_rn(a.dy, b.dt) <= __dmul_rn(b.dy, a.dt);
+}
+
+__device__ inline EdgeSlope edge_int(EdgeSlope s) { return s; }
+__device__ inline EdgeSlope edge_int(EdgeSlopeF s) {
+  return EdgeSlope{static_cast<int64_t>(s.dy), static_cast<uint32_t>(s.dt)};
+}
+__device__ inline uint32_t hull_pos(HullPoint p) { return p.t; }
+__device__ inline uint32_t hull_pos(HullPointF p) { return static_cast<uint32_t>(p.t); }
+
 // Bridge of hull A (p vertices) and hull B (q vertices), A entirely left of
 // B: the union's hull is A[0, keep) followed by B[from, q).  A(i) and B(j)
 // return vertices.  Walks inwards from the facing ends until neither end
@@ -68,18 +119,19 @@ template <class PA, class PB>
 __device__ __attribute__((always_inline)) inline void hull_bridge(bool upper, const PA& A, uint32_t p, const PB& B, uint32_t q,
                                    uint32_t& keep, uint32_t& from) {
   uint32_t i = p - 1, j = 0;
-  HullPoint a = A(i), b = B(j);
+  auto a = A(i);
+  auto b = B(j);
   for (;;) {
     bool moved = false;
     while (i > 0) {
-      const HullPoint a0 = A(i - 1);
+      const auto a0 = A(i - 1);
       if (!hull_drops(upper, a0, a, b)) break;
       a = a0;
       --i;
       moved = true;
     }
     while (j + 1 < q) {
-      const HullPoint b1 = B(j + 1);
+      const auto b1 = B(j + 1);
       if (!hull_drops(upper, a, b, b1)) break;
       b = b1;
       ++j;
@@ -120,10 +172,10 @@ __device__ __attribute__((always_inline)) inline void group_sync() {
   }
 }
 
-// Upper and lower hulls of the tile's points 0 .. cnt-1 (values in sh.v),
-// left in sh.h[side][0 .. sh.cnt[side][0]).  Called by every thread tid of
-// the group.
-template <int kT>
+// Upper and lower hulls of the tile's points 0 .. cnt-1 (sh.v: values, or
+// with kF the bits of binary64 offsets below kHullF64Range), left in
+// sh.h[side][0 .. sh.cnt[side][0]).  Called by every thread tid of the group.
+template <int kT, bool kF>
 __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>& sh, uint32_t cnt,
                                                                  uint32_t tid) {
   const uint32_t c0 = tid * kHullChunk;
@@ -136,16 +188,16 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
   for (uint32_t side = 0; side < 2; ++side) {
     uint16_t* H = sh.h[side] + c0;
     uint32_t k = 0;
-    HullPoint below{0, 0}, top{0, 0};  // H[k-2] and H[k-1] when k >= 2
+    auto below = hull_pt<kF>(0, 0), top = below;  // H[k-2] and H[k-1] when k >= 2
 #pragma unroll
     for (uint32_t j = 0; j < kHullChunk; ++j) {
       const uint32_t t = c0 + j;
       if (t < c1) {
-        const HullPoint r{t, pv[j]};
+        const auto r = hull_pt<kF>(t, pv[j]);
         while (k >= 2 && hull_drops(side == 0, below, top, r)) {
           --k;
           top = below;
-          if (k >= 2) below = HullPoint{H[k - 2], sh.v[H[k - 2]]};
+          if (k >= 2) below = hull_pt<kF>(H[k - 2], sh.v[H[k - 2]]);
         }
         H[k++] = uint16_t(t);
         below = top;
@@ -167,8 +219,8 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
       } else if (q > 0) {
         const uint16_t* HA = sh.h[side] + kHullChunk * g;
         const uint16_t* HB = sh.h[side] + kHullChunk * (g + half);
-        const auto A = [&](uint32_t i) { return HullPoint{HA[i], sh.v[HA[i]]}; };
-        const auto B = [&](uint32_t j) { return HullPoint{HB[j], sh.v[HB[j]]}; };
+        const auto A = [&](uint32_t i) { return hull_pt<kF>(HA[i], sh.v[HA[i]]); };
+        const auto B = [&](uint32_t j) { return hull_pt<kF>(HB[j], sh.v[HB[j]]); };
         hull_bridge(side == 0, A, p, B, q, keep, from);
       }
       sh.keep[side][g] = uint16_t(keep);
@@ -206,7 +258,9 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
 }
 
 // The smallest hull edge slope at which the strip width stops decreasing,
-// over hulls U (nu vertices) and L (nl vertices) given by accessors.  Every
+// over hulls U (nu vertices) and L (nl vertices) given by accessors (of
+// HullPoint or HullPointF vertices: the binary searches compare slopes of
+// the accessors' type, the answer is kept as an exact EdgeSlope).  Every
 // thread receives the answer.  Called by every thread tid of the group.
 template <int kT, class PU, class PL>
 __device__ __attribute__((always_inline)) inline EdgeSlope minimax_bend(HullSharedT<kT>& sh,
@@ -223,29 +277,31 @@ __device__ __attribute__((always_inline)) inline EdgeSlope minimax_bend(HullShar
     if (e < nu - 1) {
       // upper edge e: just above its slope the strip touches U[e] from above
       upper_edge = true;
-      const HullPoint a = U(e);
-      th = edge_slope(a, U(e + 1));
-      t_up = a.t;
+      const auto a = U(e);
+      const auto s = edge_slope(a, U(e + 1));
+      t_up = hull_pos(a);
       // and L[c] from below, c = number of lower edges with slope <= th
       uint32_t lo = 0, hi = nl - 1;
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (slope_le(edge_slope(L(mid), L(mid + 1)), th)) lo = mid + 1; else hi = mid;
+        if (slope_le(edge_slope(L(mid), L(mid + 1)), s)) lo = mid + 1; else hi = mid;
       }
-      t_lo = L(lo).t;
+      t_lo = hull_pos(L(lo));
+      th = edge_int(s);
     } else {
       upper_edge = false;
       const uint32_t j = e - (nu - 1);
-      const HullPoint b = L(j + 1);
-      th = edge_slope(L(j), b);
-      t_lo = b.t;
+      const auto b = L(j + 1);
+      const auto s = edge_slope(L(j), b);
+      t_lo = hull_pos(b);
       // U[k], k = first upper edge with slope <= th (upper slopes decrease)
       uint32_t lo = 0, hi = nu - 1;
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (slope_le(edge_slope(U(mid), U(mid + 1)), th)) hi = mid; else lo = mid + 1;
+        if (slope_le(edge_slope(U(mid), U(mid + 1)), s)) hi = mid; else lo = mid + 1;
       }
-      t_up = U(lo).t;
+      t_up = hull_pos(U(lo));
+      th = edge_int(s);
     }
     if (t_lo >= t_up) {
       const bool better = !found || slope_lt(th, best) || (!slope_lt(best, th) && upper_edge && !from_upper);

@@ -68,7 +68,30 @@ def spiky(n, seed):
     return v
 
 
+def steep_line(n, L, span, seed):
+    """A noisy line whose partitions of L values each span about `span`
+    (offsets from 2^61, noise below 2^20)."""
+    rng = np.random.default_rng(seed)
+    slope = np.uint64(span // (L - 1))
+    t = np.arange(n, dtype=np.uint64)
+    return np.uint64(1 << 61) + t * slope + rng.integers(0, 1 << 20, n).astype(np.uint64)
+
+
+def periodic_bowl(n, L, shift):
+    """(t mod L)^2 << shift above 2^62: every point of a partition is a
+    lower-hull vertex, the range (L-1)^2 << shift."""
+    t = np.arange(n, dtype=np.uint64) % np.uint64(L)
+    return np.uint64(1 << 62) + ((t * t) << np.uint64(shift))
+
+
 FIXED = [
+    # hull tests in binary64 below a range of 2^40, in 128-bit integers above
+    ("line_below_2_40_L1024", lambda: steep_line(100_000, 1024, (1 << 40) - (1 << 21), 40), 1024),
+    ("line_above_2_40_L1024", lambda: steep_line(100_000, 1024, (1 << 40) + (1 << 21), 41), 1024),
+    ("line_below_2_40_L4096", lambda: steep_line(100_000, 4096, (1 << 40) - (1 << 21), 42), 4096),
+    ("bowl_below_2_40_L4096", lambda: periodic_bowl(40_000, 4096, 16), 4096),
+    ("bowl_2_41_L4096", lambda: periodic_bowl(40_000, 4096, 17), 4096),
+    ("bowl_L1024", lambda: periodic_bowl(40_000, 1024, 20), 1024),
     ("linear_noise", lambda: W.linear_noise(200_000, 1), 1024),
     ("lognormal_keys_u64", lambda: W.lognormal_keys(300_000, 2), 4096),
     ("lognormal_keys_u32", lambda: W.lognormal_keys(300_000, 3).astype(np.uint32), 4096),
