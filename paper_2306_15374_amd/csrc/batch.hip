@@ -36,6 +36,9 @@ struct BatchSink {
   // runs of short partitions in full rounds when only storing: the fused
   // filter's accumulators would push the kernel past its register budget
   static constexpr bool kFlat = kStore && !kFilter;
+  // polynomial predictions by forward differences (decode_range_poly) only
+  // when storing alone, for the same reason
+  static constexpr bool kGramWalk = kStore && !kFilter;
   OutT* out;
   FilterSink f;
   __device__ bool visit_segment(const Part& p, uint32_t t0, uint32_t t1) {

@@ -483,6 +483,7 @@ template <typename OutT, bool kFlatRuns = true>
 struct StoreSink {
   static constexpr bool kWholeTile = true;
   static constexpr bool kFlat = kFlatRuns;
+  static constexpr bool kGramWalk = true;
   OutT* out;
   uint64_t origin;
   __device__ bool visit_segment(const Part&, uint32_t, uint32_t) { return true; }
@@ -592,20 +593,35 @@ __device__ bool decode_range_poly(const uint8_t* __restrict__ blob, const Header
         qoff = int64_t(64 * p.word_off) - int64_t(32 * a0);
         wave_sync();
       }
-      for (uint32_t t = c0 + lane; t < c1; t += kWave) {
-        uint64_t u = 0;
-        if (b != 0) {
-          // three words cover any field of up to 64 bits; the words past
-          // the staged ones only meet masked bits
-          const uint32_t q = uint32_t(qoff + int64_t(b) * t);
-          const uint32_t* w = stage + (q >> 5);
-          const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-          u = ((uint64_t(__builtin_amdgcn_alignbit(w2, w1, q & 31)) << 32) |
-               __builtin_amdgcn_alignbit(w1, w0, q & 31)) & mask;
+      // three words cover any field of up to 64 bits; the words past the
+      // staged ones only meet masked bits
+      const auto field = [&](uint32_t t) -> uint64_t {
+        if (b == 0) return 0;
+        const uint32_t q = uint32_t(qoff + int64_t(b) * t);
+        const uint32_t* w = stage + (q >> 5);
+        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+        return ((uint64_t(__builtin_amdgcn_alignbit(w2, w1, q & 31)) << 32) |
+                __builtin_amdgcn_alignbit(w1, w0, q & 31)) & mask;
+      };
+      if (kind && Sink::kGramWalk) {
+        // sinks that only store: the lane's Gram polynomials by forward
+        // differences (its positions are kWave apart); the filtering sinks
+        // evaluate them per value, which keeps those kernels within their
+        // register budgets on every blob
+        GramWalk gw;
+        gw.start(c0 + lane, uint32_t(p.len), kWave);
+        for (uint32_t t = c0 + lane; t < c1; t += kWave) {
+          const uint64_t u = field(t);
+          sink.put(p.start + t, p.base + uint64_t(gw.predict(p.theta1, c2, c3)) + u);
+          gw.next();
         }
-        const int64_t pred = kind ? poly_predict(p.theta1, c2, c3, t, uint32_t(p.len))
-                                  : predict(p.theta1, t);
-        sink.put(p.start + t, p.base + uint64_t(pred) + u);
+      } else if (kind) {
+        for (uint32_t t = c0 + lane; t < c1; t += kWave)
+          sink.put(p.start + t,
+                   p.base + uint64_t(poly_predict(p.theta1, c2, c3, t, uint32_t(p.len))) + field(t));
+      } else {
+        for (uint32_t t = c0 + lane; t < c1; t += kWave)
+          sink.put(p.start + t, p.base + uint64_t(predict(p.theta1, t)) + field(t));
       }
       if (b != 0) wave_sync();
       c0 = c1;
@@ -642,6 +658,7 @@ __device__ inline bool lookup_value_poly(const uint8_t* __restrict__ blob, const
 struct FilterSink {
   static constexpr bool kWholeTile = false;  // may skip segments by their model bounds
   static constexpr bool kFlat = false;
+  static constexpr bool kGramWalk = false;
   uint64_t lo, hi;
   uint64_t sum_lo, sum_hi, count;
   int prune;

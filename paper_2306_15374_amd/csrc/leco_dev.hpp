@@ -239,6 +239,13 @@ __device__ inline bool prediction_fits_i32(double theta1, uint64_t len) {
 // The g_k are evaluated in binary64 in Horner form: for t, n <= 4096 every
 // intermediate is an integer below 2^42, so each operation is exact and the
 // values equal the integer polynomials.
+__device__ inline int64_t poly_combine(double c1, double c2, double c3, double g1, double g2,
+                                       double g3) {
+  double s = __dadd_rn(__dmul_rn(c1, g1), __dmul_rn(c2, g2));
+  s = __dadd_rn(s, __dmul_rn(c3, g3));
+  return static_cast<int64_t>(floor(s));
+}
+
 __device__ inline int64_t poly_predict(double c1, double c2, double c3, uint32_t t, uint32_t n) {
   const double x = double(t), N = double(n), a = N - 1.0;
   const double g1 = __dadd_rn(__dmul_rn(2.0, x), -a);
@@ -248,10 +255,48 @@ __device__ inline int64_t poly_predict(double c1, double c2, double c3, uint32_t
   const double e3 = __dmul_rn(e2, N - 3.0);
   const double h3 = __dadd_rn(__dmul_rn(20.0, x), __dmul_rn(-30.0, a));
   const double g3 = __dadd_rn(__dmul_rn(__dadd_rn(__dmul_rn(h3, x), k3), x), -e3);
-  double s = __dadd_rn(__dmul_rn(c1, g1), __dmul_rn(c2, g2));
-  s = __dadd_rn(s, __dmul_rn(c3, g3));
-  return static_cast<int64_t>(floor(s));
+  return poly_combine(c1, c2, c3, g1, g2, g3);
 }
+
+// The same predictions at positions t, t + h, t + 2h, ... (a lane's
+// positions, h its stride): the Gram polynomials advanced by forward
+// differences.  With a = n - 1, their first differences are 2h,
+// 12ht + 6h^2 - 6ah and 60ht^2 + (60h^2 - 60ah)t + 20h^3 - 30ah^2 + k3 h,
+// the second 12h^2 and 120h^2 t + 120h^3 - 60ah^2, the third 120h^3.  For
+// n <= 4096, h <= 256 and positions below n + 3h every value, difference
+// and product here is an integer below 2^53, so each step is exact and
+// gives the g1, g2, g3 that poly_predict evaluates.
+struct GramWalk {
+  double g1, g2, g3, d1, d2, dd2, d3, dd3, ddd3;
+
+  __device__ void start(uint32_t t, uint32_t n, uint32_t h) {
+    const double x = double(t), N = double(n), a = N - 1.0, H = double(h);
+    const double e2 = a * (N - 2.0);
+    const double k3 = (12.0 * N - 30.0) * N + 22.0;
+    const double e3 = e2 * (N - 3.0);
+    g1 = 2.0 * x - a;
+    g2 = (6.0 * x - 6.0 * a) * x + e2;
+    g3 = ((20.0 * x - 30.0 * a) * x + k3) * x - e3;
+    const double H2 = H * H, H3 = H2 * H;
+    d1 = 2.0 * H;
+    d2 = 12.0 * H * x + (6.0 * H2 - 6.0 * a * H);
+    dd2 = 12.0 * H2;
+    d3 = (60.0 * H * x + (60.0 * H2 - 60.0 * a * H)) * x + (20.0 * H3 - 30.0 * a * H2 + k3 * H);
+    dd3 = 120.0 * H2 * x + (120.0 * H3 - 60.0 * a * H2);
+    ddd3 = 120.0 * H3;
+  }
+  __device__ int64_t predict(double c1, double c2, double c3) const {
+    return poly_combine(c1, c2, c3, g1, g2, g3);
+  }
+  __device__ void next() {
+    g1 += d1;
+    g2 += d2;
+    d2 += dd2;
+    g3 += d3;
+    d3 += dd3;
+    dd3 += ddd3;
+  }
+};
 
 // ---- residual extraction from 32-bit words ---------------------------------
 
