@@ -233,3 +233,20 @@ def test_two_pass_small_launches(torch, two_pass_codec, ref):
         s.append(min(n, s[-1] + int(rng.choice([1, 5, 64, 1000, 3000, 4096, 9000]))))
     check(torch, c, ref, W.piecewise_linear(n, 46, segments=20), "polyline u32 variable",
           starts=np.array(s, dtype=np.uint64))
+
+
+def test_default_switches_at_two_workgroups_per_cu(torch, ref):
+    """A default context takes the one-pass encoder up to two workgroups per
+    CU and the two passes above: columns on both sides of the switch, for
+    the wavefront kernel (partitions of 1024, four per workgroup) and the
+    workgroup kernel (partitions of 4096), give the oracle's bytes."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    c = P.Codec(0)
+    try:
+        for L, per_wg in ((1024, 4), (4096, 1)):
+            limit = 2 * cus * per_wg  # partitions at the switch
+            for m in (limit, limit + 1):
+                col = W.lognormal_keys(m * L - 7, 50 + m % 7)  # ragged last partition
+                check(torch, c, ref, col, f"default L{L} m={m}", fixed_len=L)
+    finally:
+        c.close()
