@@ -715,19 +715,23 @@ __device__ __attribute__((always_inline)) inline void poly_stage(
     if (c[k] == 0.0) c[k] = 0.0;  // +0.0, never -0.0
   }
   // the residuals of both degrees in one pass (the degree-2 prediction is
-  // the degree-3 one with c3 = 0: the two share their Gram values)
+  // the degree-3 one with c3 = 0: the two share their Gram values, which
+  // the thread steps by forward differences over its positions kT apart)
   int64_t mn2 = INT64_MAX, mx2 = INT64_MIN, mn3 = INT64_MAX, mx3 = INT64_MIN;
+  GramWalk gw;
+  gw.start(tid, n, kT);
 #pragma unroll
   for (int k = 0; k < kR; ++k) {
     const uint32_t t = tid + k * kT;
     if (t < n) {
-      const int64_t r2 = int64_t(y[k]) - poly_predict(c[0], c[1], 0.0, t, n);
-      const int64_t r3 = int64_t(y[k]) - poly_predict(c[0], c[1], c[2], t, n);
+      const int64_t r2 = int64_t(y[k]) - poly_combine(c[0], c[1], 0.0, gw.g1, gw.g2, gw.g3);
+      const int64_t r3 = int64_t(y[k]) - gw.predict(c[0], c[1], c[2]);
       mn2 = r2 < mn2 ? r2 : mn2;
       mx2 = r2 > mx2 ? r2 : mx2;
       mn3 = r3 < mn3 ? r3 : mn3;
       mx3 = r3 > mx3 ? r3 : mx3;
     }
+    gw.next();
   }
   minmax(mn2, mx2);
   minmax(mn3, mx3);
