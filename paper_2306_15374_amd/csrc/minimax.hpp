@@ -206,8 +206,19 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
     }
     sh.cnt[side][tid] = uint16_t(k);
   }
-  group_sync<kT>();
+  // A round of G <= 64 threads reads and writes only its group's hulls,
+  // which lie in one wavefront: a wavefront barrier orders it.  Wider
+  // rounds take the workgroup barrier, and the first of them one more
+  // before it starts (the wavefronts' narrow rounds ran unsynchronised).
+  const auto round_sync = [](uint32_t G) {
+    if (kT > 64 && G > 64)
+      __syncthreads();
+    else
+      group_sync<64>();
+  };
+  round_sync(2);
   for (uint32_t G = 2; G <= uint32_t(kT); G <<= 1) {
+    if (kT > 64 && G == 128) __syncthreads();
     const uint32_t half = G >> 1, r = tid & (G - 1), g = tid - r;
     if (r < 2) {
       const uint32_t side = r;
@@ -226,7 +237,7 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
       sh.keep[side][g] = uint16_t(keep);
       sh.from[side][g] = uint16_t(from);
     }
-    group_sync<kT>();
+    round_sync(G);
     // the right hull's kept vertices, staged so that moving them left never
     // overwrites one not yet read: at most 16 * half / G = 8 per thread
     constexpr uint32_t kStage = kHullChunk / 2;
@@ -242,7 +253,7 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
         stage[side][s] = x < moved[side] ? HB[x] : 0;
       }
     }
-    group_sync<kT>();
+    round_sync(G);
     for (uint32_t side = 0; side < 2; ++side) {
       const uint32_t keep = sh.keep[side][g];
       uint16_t* HA = sh.h[side] + kHullChunk * g + keep;
@@ -253,7 +264,7 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
       }
       if (r == side) sh.cnt[side][g] = uint16_t(keep + moved[side]);
     }
-    group_sync<kT>();
+    round_sync(G);
   }
 }
 
