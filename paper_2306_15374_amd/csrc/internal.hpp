@@ -27,7 +27,7 @@ struct Tune {
 };
 
 // Past about two workgroups per CU (2e6 8-byte values at partitions of 1024
-// or 4096) the two-pass encoder is faster; below, its six launches cost more
+// or 4096) the two-pass encoder is faster; below, its seven launches cost more
 // than the one-pass kernel's look-back.
 constexpr uint32_t kFusedAutoPerCu = 2;
 
