@@ -104,6 +104,18 @@ __device__ inline bool slope_le(EdgeSlopeF a, EdgeSlopeF b) {
   return __dmul_rn(a.dy, b.dt) <= __dmul_rn(b.dy, a.dt);
 }
 
+__device__ inline bool slope_lt(EdgeSlopeF a, EdgeSlopeF b) {
+  return __dmul_rn(a.dy, b.dt) < __dmul_rn(b.dy, a.dt);
+}
+
+__device__ inline EdgeSlope shfl_xor_slope(EdgeSlope s, uint32_t m) {
+  return EdgeSlope{static_cast<int64_t>(__shfl_xor(static_cast<long long>(s.dy), int(m), 64)),
+                   static_cast<uint32_t>(__shfl_xor(static_cast<int>(s.dt), int(m), 64))};
+}
+__device__ inline EdgeSlopeF shfl_xor_slope(EdgeSlopeF s, uint32_t m) {
+  return EdgeSlopeF{__shfl_xor(s.dy, int(m), 64), __shfl_xor(s.dt, int(m), 64)};
+}
+
 __device__ inline EdgeSlope edge_int(EdgeSlope s) { return s; }
 __device__ inline EdgeSlope edge_int(EdgeSlopeF s) {
   return EdgeSlope{static_cast<int64_t>(s.dy), static_cast<uint32_t>(s.dt)};
@@ -142,6 +154,65 @@ __device__ __attribute__((always_inline)) inline void hull_bridge(bool upper, co
   keep = i + 1;
   from = j;
 }
+
+// The same bridge found by hg lanes of one wavefront at once (an aligned
+// block of lanes; this lane is l of them), without a dependent walk.  For
+// the upper hulls: the tangent from B's vertex j to A touches the vertex k
+// of smallest slope(A[k], B[j]), and the common tangent is the one of
+// largest slope over j; the walk passes collinear vertices, so it ends on
+// the leftmost such k and the rightmost such j, which the ties below
+// reproduce.  The lower hulls mirror it (largest slope to A, smallest over
+// j).  Lane l takes j = l, l + hg, ...; every lane of the block receives
+// the bridge.
+template <class PA, class PB>
+__device__ __attribute__((always_inline)) inline void hull_bridge_lanes(
+    bool upper, const PA& A, uint32_t p, const PB& B, uint32_t q, uint32_t l, uint32_t hg,
+    uint32_t& keep, uint32_t& from) {
+  using S = decltype(edge_slope(A(0), B(0)));
+  // x before y in the order of preference: upper, smaller tangent slope to
+  // A and larger over B; lower, the reverse
+  const auto ahead = [&](S x, S y) { return upper ? slope_lt(x, y) : slope_lt(y, x); };
+  bool have = false;
+  S best = edge_slope(A(0), B(0));
+  uint32_t bi = 0, bj = 0;
+  for (uint32_t j = l; j < q; j += hg) {
+    const auto b = B(j);
+    S s = edge_slope(A(0), b);
+    uint32_t i = 0;
+    for (uint32_t k = 1; k < p; ++k) {
+      const S sk = edge_slope(A(k), b);
+      if (ahead(sk, s)) {  // strictly: the leftmost k on ties
+        s = sk;
+        i = k;
+      }
+    }
+    if (!have || !ahead(s, best)) {  // j grows: the rightmost j on ties
+      best = s;
+      bi = i;
+      bj = j;
+      have = true;
+    }
+  }
+  for (uint32_t m = 1; m < hg; m <<= 1) {
+    const bool oh = __shfl_xor(int(have), int(m), 64) != 0;
+    const S os = shfl_xor_slope(best, m);
+    const uint32_t oi = uint32_t(__shfl_xor(int(bi), int(m), 64));
+    const uint32_t oj = uint32_t(__shfl_xor(int(bj), int(m), 64));
+    const bool tie = !ahead(os, best) && !ahead(best, os);
+    if (oh && (!have || ahead(best, os) || (tie && oj > bj))) {
+      best = os;
+      bi = oi;
+      bj = oj;
+      have = true;
+    }
+  }
+  keep = bi + 1;
+  from = bj;
+}
+
+// Rounds from this many threads find their bridges with all of them
+// (hull_bridge_lanes), narrower ones with one thread per side (hull_bridge).
+constexpr uint32_t kLaneBridgeMin = 16;
 
 template <int kT>
 struct HullSharedT {
@@ -220,7 +291,26 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
   for (uint32_t G = 2; G <= uint32_t(kT); G <<= 1) {
     if (kT > 64 && G == 128) __syncthreads();
     const uint32_t half = G >> 1, r = tid & (G - 1), g = tid - r;
-    if (r < 2) {
+    if (G >= kLaneBridgeMin && G <= 64) {
+      // every thread of the group: half of them per side, in one wavefront
+      const uint32_t side = r / half, l = r - side * half;
+      const uint32_t p = sh.cnt[side][g], q = sh.cnt[side][g + half];
+      uint32_t keep = p, from = q;  // an empty right hull adds nothing
+      if (q > 0 && p == 0) {
+        keep = 0;
+        from = 0;
+      } else if (q > 0) {
+        const uint16_t* HA = sh.h[side] + kHullChunk * g;
+        const uint16_t* HB = sh.h[side] + kHullChunk * (g + half);
+        const auto A = [&](uint32_t i) { return hull_pt<kF>(HA[i], sh.v[HA[i]]); };
+        const auto B = [&](uint32_t j) { return hull_pt<kF>(HB[j], sh.v[HB[j]]); };
+        hull_bridge_lanes(side == 0, A, p, B, q, l, half, keep, from);
+      }
+      if (l == 0) {
+        sh.keep[side][g] = uint16_t(keep);
+        sh.from[side][g] = uint16_t(from);
+      }
+    } else if (r < 2) {
       const uint32_t side = r;
       const uint32_t p = sh.cnt[side][g], q = sh.cnt[side][g + half];
       uint32_t keep = p, from = q;  // an empty right hull adds nothing

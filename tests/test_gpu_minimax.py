@@ -92,6 +92,11 @@ FIXED = [
     ("bowl_below_2_40_L4096", lambda: periodic_bowl(40_000, 4096, 16), 4096),
     ("bowl_2_41_L4096", lambda: periodic_bowl(40_000, 4096, 17), 4096),
     ("bowl_L1024", lambda: periodic_bowl(40_000, 1024, 20), 1024),
+    # every point collinear (hulls of two vertices after the ties), and
+    # collinear runs meeting at corners
+    ("exact_line", lambda: np.uint64(7) + np.arange(60_000, dtype=np.uint64) * np.uint64(3), 1024),
+    ("exact_sawtooth", lambda: (np.arange(60_000, dtype=np.uint64) % np.uint64(37)) * np.uint64(5), 1000),
+    ("exact_sawtooth_4096", lambda: (np.arange(60_000, dtype=np.uint64) % np.uint64(301)) * np.uint64(9), 4096),
     ("linear_noise", lambda: W.linear_noise(200_000, 1), 1024),
     ("lognormal_keys_u64", lambda: W.lognormal_keys(300_000, 2), 4096),
     ("lognormal_keys_u32", lambda: W.lognormal_keys(300_000, 3).astype(np.uint32), 4096),
