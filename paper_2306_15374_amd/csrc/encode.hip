@@ -163,6 +163,58 @@ __device__ inline void store_model(const EncScratch& s, uint64_t P, const Model&
   s.nwords[P] = (len * md.bits + 63) >> 6;
 }
 
+// ---- fit: one thread per partition ------------------------------------------------
+
+// Partitions of at most this many values are fitted by one thread each when
+// a launch holds no longer ones (a wavefront per partition left 63 of its
+// 64 lanes idle at one value per partition: 1.4 ms for the 2e6 sampled
+// partitions of a size search's first length).
+constexpr uint64_t kLaneFitMax = 32;
+
+// The model fit_wave_regs computes, by one thread: the same exact sums (the
+// slope is one function of them, whatever their order), the same residual
+// range and the same choice.
+__device__ inline Model fit_lane(const uint8_t* src, uint32_t dtype, uint64_t len,
+                                 bool force_constant) {
+  uint64_t vmin = ~uint64_t(0), vmax = 0;
+  U128 sv{0, 0}, stv{0, 0};
+  for (uint64_t t = 0; t < len; ++t) {
+    const uint64_t x = load_value(src, dtype, t);
+    vmin = x < vmin ? x : vmin;
+    vmax = x > vmax ? x : vmax;
+    sv = add128(sv, U128{x, 0});
+    stv = add128(stv, mul64x64(t, x));
+  }
+  const uint64_t range = vmax - vmin;
+  Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
+  if (len > 1 && !force_constant && range < (uint64_t(1) << 61)) {
+    const double th = ls_slope(len, sv, stv);
+    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
+    for (uint64_t t = 0; t < len; ++t) {
+      const int64_t rr = int64_t(load_value(src, dtype, t) - vmin) - predict(th, uint32_t(t));
+      rmin = rr < rmin ? rr : rmin;
+      rmax = rr > rmax ? rr : rmax;
+    }
+    choose_model(md, th, rmin, rmax);
+  }
+  return md;
+}
+
+// Least-squares partitions of at most kLaneFitMax values, one thread each
+// (grid-stride over the launch's partitions).
+__global__ __launch_bounds__(256) void k_fit_lane(const EncColumn* __restrict__ cols,
+                                                  uint64_t ncols, EncColumn single,
+                                                  uint64_t nparts, EncScratch scr) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t P = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; P < nparts; P += stride) {
+    const EncColumn c = column_of(cols, ncols, single, P);
+    uint64_t start, len;
+    part_bounds(c, P - c.part_base, start, len);
+    const Model md = fit_lane(c.col + start * c.dtype, c.dtype, len, c.force_constant != 0);
+    store_model(scr, P, md, len);
+  }
+}
+
 // ---- fit: one wavefront per partition ---------------------------------------------
 
 // Loads of value t of a partition of len values: the index is clamped so
@@ -1552,6 +1604,12 @@ hipError_t launch_fit_columns(leco_ctx* ctx, const EncColumn* cols_dev, uint64_t
     hipLaunchKernelGGL(k_fit_poly, dim3(uint32_t(nparts)), dim3(kEncBlock), 0, stream, cols_dev,
                        ncols, single, nparts, scr);
   if (!(regs & (kRegLS | kRegMinimax))) return hipGetLastError();
+  if (regs == kRegLS && max_len <= kLaneFitMax && ctx->tune.encode_wave) {
+    const uint64_t g = (nparts + 255) / 256, cap = uint64_t(ctx->num_cus) * 16;
+    hipLaunchKernelGGL(k_fit_lane, dim3(uint32_t(g < cap ? g : cap)), dim3(256), 0, stream,
+                       cols_dev, ncols, single, nparts, scr);
+    return hipGetLastError();
+  }
   // k_fit_wave fits every column it is given: not with polynomial columns
   const bool poly = regs & kRegPoly;
   if ((regs & kRegMinimax) && wave16 && !poly)

@@ -362,3 +362,22 @@ def test_encode_async_matches_sync(torch, codec, ref):
     codec.sync()
     s = int(host(size)[0])
     assert np.array_equal(host(buf[:s]), ref.encode(col, fixed_len=4096))
+
+
+def test_short_partitions_one_thread_each(torch, codec, ref):
+    """Launches whose partitions hold at most 32 values (more than 2,048 of
+    them, so the two-pass encoder runs) are fitted one thread per
+    partition: both widths, lengths 1..32 with ragged last partitions, the
+    constant model forced, ranges at and beyond 2^61."""
+    rng = np.random.default_rng(91)
+    keys = W.lognormal_keys(120_001, 92)
+    for L in (1, 2, 3, 17, 32):
+        check_column(torch, codec, ref, keys, f"keys u64 L={L}", fixed_len=L, ra=200)
+    check_column(torch, codec, ref, W.linear_noise(100_003, 93, np.uint32), "noise u32 L=31",
+                 fixed_len=31, ra=200)
+    check_column(torch, codec, ref, keys, "forced constant L=8", fixed_len=8, force_constant=True,
+                 ra=200)
+    wide = rng.integers(0, 2**64 - 1, 80_000, dtype=np.uint64, endpoint=True)
+    check_column(torch, codec, ref, wide, "64-bit noise L=32", fixed_len=32, ra=200)
+    edge = np.where(rng.random(80_000) < 0.5, np.uint64(0), np.uint64(2**61)).astype(np.uint64)
+    check_column(torch, codec, ref, edge, "range exactly 2^61 L=16", fixed_len=16, ra=200)
