@@ -163,7 +163,11 @@ __device__ __attribute__((always_inline)) inline void hull_bridge(bool upper, co
 // the leftmost such k and the rightmost such j, which the ties below
 // reproduce.  The lower hulls mirror it (largest slope to A, smallest over
 // j).  Lane l takes j = l, l + hg, ...; every lane of the block receives
-// the bridge.
+// the bridge.  Since b = B[j] lies right of every vertex of A, the slope
+// from A[k] to b falls strictly while b is strictly below the line through
+// A[k] and A[k+1] (upper hulls; above, for the lower), and that holds for
+// a prefix of k because A is convex: a binary search for the end of the
+// prefix finds the leftmost tangent vertex in log2(p) steps.
 template <class PA, class PB>
 __device__ __attribute__((always_inline)) inline void hull_bridge_lanes(
     bool upper, const PA& A, uint32_t p, const PB& B, uint32_t q, uint32_t l, uint32_t hg,
@@ -177,15 +181,15 @@ __device__ __attribute__((always_inline)) inline void hull_bridge_lanes(
   uint32_t bi = 0, bj = 0;
   for (uint32_t j = l; j < q; j += hg) {
     const auto b = B(j);
-    S s = edge_slope(A(0), b);
-    uint32_t i = 0;
-    for (uint32_t k = 1; k < p; ++k) {
-      const S sk = edge_slope(A(k), b);
-      if (ahead(sk, s)) {  // strictly: the leftmost k on ties
-        s = sk;
-        i = k;
-      }
+    uint32_t i = 0, hi = p - 1;
+    while (i < hi) {
+      const uint32_t mid = (i + hi) >> 1;
+      if (ahead(edge_slope(A(mid + 1), b), edge_slope(A(mid), b)))
+        i = mid + 1;
+      else
+        hi = mid;
     }
+    const S s = edge_slope(A(i), b);
     if (!have || !ahead(s, best)) {  // j grows: the rightmost j on ties
       best = s;
       bi = i;
@@ -210,9 +214,11 @@ __device__ __attribute__((always_inline)) inline void hull_bridge_lanes(
   from = bj;
 }
 
-// Rounds from this many threads find their bridges with all of them
-// (hull_bridge_lanes), narrower ones with one thread per side (hull_bridge).
+// Rounds of kLaneBridgeMin to kLaneBridgeMax threads find their bridges
+// with all of them, at most a wavefront per side (hull_bridge_lanes); the
+// others with one thread per side (hull_bridge).
 constexpr uint32_t kLaneBridgeMin = 16;
+constexpr uint32_t kLaneBridgeMax = 64;
 
 template <int kT>
 struct HullSharedT {
@@ -291,20 +297,22 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
   for (uint32_t G = 2; G <= uint32_t(kT); G <<= 1) {
     if (kT > 64 && G == 128) __syncthreads();
     const uint32_t half = G >> 1, r = tid & (G - 1), g = tid - r;
-    if (G >= kLaneBridgeMin && G <= 64) {
-      // every thread of the group: half of them per side, in one wavefront
+    if (G >= kLaneBridgeMin && G <= kLaneBridgeMax) {
+      // half of the group per side, of which the first wavefront (or all
+      // of them, in a narrower round) searches
       const uint32_t side = r / half, l = r - side * half;
+      const uint32_t hg = half < 64 ? half : 64;
       const uint32_t p = sh.cnt[side][g], q = sh.cnt[side][g + half];
       uint32_t keep = p, from = q;  // an empty right hull adds nothing
       if (q > 0 && p == 0) {
         keep = 0;
         from = 0;
-      } else if (q > 0) {
+      } else if (q > 0 && l < hg) {
         const uint16_t* HA = sh.h[side] + kHullChunk * g;
         const uint16_t* HB = sh.h[side] + kHullChunk * (g + half);
         const auto A = [&](uint32_t i) { return hull_pt<kF>(HA[i], sh.v[HA[i]]); };
         const auto B = [&](uint32_t j) { return hull_pt<kF>(HB[j], sh.v[HB[j]]); };
-        hull_bridge_lanes(side == 0, A, p, B, q, l, half, keep, from);
+        hull_bridge_lanes(side == 0, A, p, B, q, l, hg, keep, from);
       }
       if (l == 0) {
         sh.keep[side][g] = uint16_t(keep);

@@ -104,6 +104,10 @@ FIXED = [
     ("constant_runs", lambda: W.constant_runs(120_000, 33), 777),
     ("convex", lambda: convex(50_000), 4096),
     ("concave", lambda: convex(30_000, -1), 2048),
+    # every point a lower-hull vertex: the merge rounds' tangent searches
+    # run over hulls of hundreds of vertices
+    ("convex_1024", lambda: convex(60_000), 1024),
+    ("rounded_root", lambda: np.floor(np.sqrt(np.arange(60_000.0)) * 1e6).astype(np.uint64), 1024),
     ("decreasing", lambda: (np.uint64(1 << 40) - W.lognormal_keys(100_000, 5)), 512),
     ("spiky", lambda: spiky(100_000, 6), 1024),
     ("uniform_wide", lambda: np.random.default_rng(7).integers(0, 1 << 60, 40_000, dtype=np.uint64), 300),
