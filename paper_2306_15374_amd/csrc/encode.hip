@@ -217,6 +217,43 @@ __global__ __launch_bounds__(256) void k_fit_lane(const EncColumn* __restrict__ 
 
 // ---- fit: one wavefront per partition ---------------------------------------------
 
+// Range of the least-squares residuals of kN register-held values, value k
+// at position t0 + k * kStride (positions from len on ignored).  When small
+// (values below vmin + 2^30, every |floor(theta1 t)| below 2^30, the same
+// in every lane) each residual fits int32 and the range is taken in 32-bit
+// operations; otherwise in 64-bit ones with the full prediction.
+template <int kN, uint32_t kStride, class W>
+__device__ __attribute__((always_inline)) inline void residual_range_regs(
+    const W (&v)[kN], uint32_t t0, uint64_t len, uint64_t vmin, double th, bool small,
+    int64_t& rmin, int64_t& rmax) {
+  if (__builtin_amdgcn_readfirstlane(int(small))) {
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
+#pragma unroll
+    for (int k = 0; k < kN; ++k) {
+      const uint32_t t = t0 + k * kStride;
+      const int32_t rr = int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t);
+      if (t < len) {
+        mn = rr < mn ? rr : mn;
+        mx = rr > mx ? rr : mx;
+      }
+    }
+    rmin = mn;
+    rmax = mx;
+  } else {
+    rmin = INT64_MAX;
+    rmax = INT64_MIN;
+#pragma unroll
+    for (int k = 0; k < kN; ++k) {
+      const uint32_t t = t0 + k * kStride;
+      const int64_t rr = int64_t(uint64_t(v[k]) - vmin) - predict(th, t);
+      if (t < len) {
+        rmin = rr < rmin ? rr : rmin;
+        rmax = rr > rmax ? rr : rmax;
+      }
+    }
+  }
+}
+
 // Loads of value t of a partition of len values: the index is clamped so
 // every lane loads (no branch between loads), and callers mask t >= len.
 template <class T>
@@ -225,19 +262,21 @@ __device__ inline uint64_t load_clamped(const T* src, uint32_t t, uint64_t len) 
 }
 
 // The model of a partition of len <= 64 kR values held by one wavefront,
-// value lane + 64 k in v[k] (positions past len holding its last value).
-template <int kR>
-__device__ __attribute__((always_inline)) inline Model fit_wave_regs(const uint64_t (&v)[kR],
+// value lane + 64 k in v[k] (positions past len holding its last value;
+// W: the column's value type, or uint64_t for either).
+template <int kR, class W>
+__device__ __attribute__((always_inline)) inline Model fit_wave_regs(const W (&v)[kR],
                                                                     uint64_t len,
                                                                     bool force_constant) {
   const uint32_t lane = threadIdx.x & 63;
   // clamped lanes hold the last value, which leaves min and max unchanged
-  uint64_t vmin = v[0], vmax = v[0];
+  W lo = v[0], hi = v[0];
 #pragma unroll
   for (int k = 1; k < kR; ++k) {
-    vmin = v[k] < vmin ? v[k] : vmin;
-    vmax = v[k] > vmax ? v[k] : vmax;
+    lo = v[k] < lo ? v[k] : lo;
+    hi = v[k] > hi ? v[k] : hi;
   }
+  uint64_t vmin = lo, vmax = hi;
   wave_minmax_u64(vmin, vmax);
   const uint64_t range = vmax - vmin;
   Model md{vmin, vmin, 0.0, bitlen64(range), false, 0, range};
@@ -260,7 +299,7 @@ __device__ __attribute__((always_inline)) inline Model fit_wave_regs(const uint6
 #pragma unroll
       for (int k = 0; k < kR; ++k) {
         const uint32_t t = lane + 64 * k;
-        const uint64_t x = t < len ? v[k] : 0;
+        const uint64_t x = t < len ? uint64_t(v[k]) : 0;
         sv = add128(sv, U128{x, 0});
         stv = add128(stv, mul64x64(t, x));
       }
@@ -269,17 +308,8 @@ __device__ __attribute__((always_inline)) inline Model fit_wave_regs(const uint6
     }
     // |floor(theta1 t)| < 2^30 for every t < len: predictions fit int32
     const bool small = narrow && __dmul_rn(fabs(th), double(len)) < 1073741824.0;
-    int64_t rmin = INT64_MAX, rmax = INT64_MIN;
-#pragma unroll
-    for (int k = 0; k < kR; ++k) {
-      const uint32_t t = lane + 64 * k;
-      const int64_t rr = small ? int64_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t))
-                               : int64_t(v[k] - vmin) - predict(th, t);
-      if (t < len) {
-        rmin = rr < rmin ? rr : rmin;
-        rmax = rr > rmax ? rr : rmax;
-      }
-    }
+    int64_t rmin, rmax;
+    residual_range_regs<kR, 64>(v, lane, len, vmin, th, small, rmin, rmax);
     wave_minmax_i64(rmin, rmax);
     choose_model(md, th, rmin, rmax);
   }
@@ -290,9 +320,9 @@ __device__ __attribute__((always_inline)) inline Model fit_wave_regs(const uint6
 template <int kR, class T>
 __device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, uint64_t len, bool force_constant) {
   const uint32_t lane = threadIdx.x & 63;
-  uint64_t v[kR];
+  T v[kR];
 #pragma unroll
-  for (int k = 0; k < kR; ++k) v[k] = load_clamped(src, lane + 64 * k, len);
+  for (int k = 0; k < kR; ++k) v[k] = T(load_clamped(src, lane + 64 * k, len));
   return fit_wave_regs<kR>(v, len, force_constant);
 }
 
@@ -384,17 +414,7 @@ __device__ __attribute__((always_inline)) inline Model fit_block(FitShared& sh, 
     }
     int64_t rmin = INT64_MAX, rmax = INT64_MIN;
     if (in_regs) {
-#pragma unroll
-      for (int k = 0; k < kEncRegs; ++k) {
-        const uint32_t t = tid + k * kEncBlock;
-        const int64_t rr = small
-                               ? int64_t(int32_t(uint32_t(v[k]) - uint32_t(vmin)) - predict32(th, t))
-                               : int64_t(v[k] - vmin) - predict(th, t);
-        if (t < len) {
-          rmin = rr < rmin ? rr : rmin;
-          rmax = rr > rmax ? rr : rmax;
-        }
-      }
+      residual_range_regs<kEncRegs, kEncBlock>(v, tid, len, vmin, th, small, rmin, rmax);
     } else {
       for (uint64_t t = tid; t < len; t += kEncBlock) {
         const int64_t rr = int64_t(uint64_t(gsrc[t]) - vmin) - predict(th, uint32_t(t));
