@@ -381,3 +381,32 @@ def test_short_partitions_one_thread_each(torch, codec, ref):
     check_column(torch, codec, ref, wide, "64-bit noise L=32", fixed_len=32, ra=200)
     edge = np.where(rng.random(80_000) < 0.5, np.uint64(0), np.uint64(2**61)).astype(np.uint64)
     check_column(torch, codec, ref, edge, "range exactly 2^61 L=16", fixed_len=16, ra=200)
+
+
+def test_narrow_residual_boundaries(torch, codec, ref):
+    """The register-held fits take residuals in 32 bits when the partition's
+    range is below 2^30 and every |floor(theta1 t)| stays below 2^30: lines
+    of slope 2^20 +- 1 per value over partitions of 1024 (|theta1| len on
+    either side of 2^30, range just below it), rising and falling, ranges of
+    exactly 2^30 - 1 and 2^30, both widths, the u64 ones offset by 2^40, at
+    L 1024 (one wavefront per partition), 2000 (32 per lane) and 4096 (one
+    workgroup)."""
+    rng = np.random.default_rng(95)
+    n = 40 * 4096 + 777
+    for L in (1024, 2000, 4096):
+        t = np.arange(n, dtype=np.uint64) % np.uint64(L)
+        noise = rng.integers(0, 16, n).astype(np.uint64)
+        cols = {}
+        for slope in ((1 << 30) // L - 1, (1 << 30) // L + 1):
+            s = np.uint64(slope)
+            cols[f"rising slope {slope}"] = s * t + noise
+            cols[f"falling slope {slope}"] = s * (np.uint64(L - 1) - t) + noise
+        for r in ((1 << 30) - 1, 1 << 30):
+            spike = (rng.random(n) < 0.01) | (t == np.uint64(L // 2))
+            cols[f"range {r}"] = np.where(spike, np.uint64(r), noise).astype(np.uint64)
+        for name, v in cols.items():
+            if int(v.max()) < 2**32:
+                check_column(torch, codec, ref, v.astype(np.uint32), f"u32 {name} L={L}",
+                             fixed_len=L, ra=200)
+            check_column(torch, codec, ref, v + np.uint64(1 << 40), f"u64 {name} L={L}",
+                         fixed_len=L, ra=200)
