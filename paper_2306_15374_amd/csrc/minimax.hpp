@@ -348,7 +348,8 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
 #pragma unroll
       for (uint32_t s = 0; s < kStage; ++s) {
         const uint32_t x = r + s * G;
-        stage[side][s] = x < moved[side] ? HB[x] : 0;
+        if (x >= moved[side]) break;  // most rounds move a few vertices
+        stage[side][s] = HB[x];
       }
     }
     round_sync(G);
@@ -358,7 +359,8 @@ __device__ __attribute__((always_inline)) inline void tile_hulls(HullSharedT<kT>
 #pragma unroll
       for (uint32_t s = 0; s < kStage; ++s) {
         const uint32_t x = r + s * G;
-        if (x < moved[side]) HA[x] = stage[side][s];
+        if (x >= moved[side]) break;
+        HA[x] = stage[side][s];
       }
       if (r == side) sh.cnt[side][g] = uint16_t(keep + moved[side]);
     }
