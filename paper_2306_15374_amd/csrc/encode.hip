@@ -430,11 +430,12 @@ __device__ __attribute__((always_inline)) inline Model fit_block(FitShared& sh, 
   return md;
 }
 
-// Five waves per SIMD (at most 96 VGPRs): the 16 values each thread holds
-// leave 114 otherwise, and the extra wave of loads in flight outweighs the
-// few spilled registers of the 128-bit-sum path (C2 encode 0.76 -> 0.71 ms
-// with k_pack below).
-__global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_fit_block(
+// Six waves per SIMD (at most 80 VGPRs; 114 unconstrained): the extra
+// waves of loads in flight outweigh the registers the 128-bit-sum path
+// spills.  Encode of 2e8 u64 values at L 4096: sorted keys 0.73-0.74 ->
+// 0.70 ms (0.76 at four waves), a noisy line 0.66 -> 0.64 ms; partitions
+// spanning 2^30 or more, which take that path, 1.07 -> 1.22 ms.
+__global__ __launch_bounds__(kEncBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_fit_block(
     const EncColumn* __restrict__ cols, uint64_t ncols, EncColumn single, uint64_t nparts,
     EncScratch scr) {
   __shared__ FitShared sh;
