@@ -217,6 +217,36 @@ __global__ __launch_bounds__(256) void k_fit_lane(const EncColumn* __restrict__ 
 
 // ---- fit: one wavefront per partition ---------------------------------------------
 
+// Exact sums of y = v - vmin (below 2^61) and of t y over kN register-held
+// values (value k at position t0 + k * kStride, positions from len on
+// ignored), each y split at bit 32: s = {sum y_lo, sum y_hi} and
+// st = {sum t y_lo, sum t y_hi}.  With at most 4096 values (t < 2^12) every
+// component stays below 2^56, so the wavefront and workgroup sums of U128
+// pairs add them component-wise (no carry leaves a low half), and
+// join_split makes the 128-bit sums.  The slope of the offsets is the
+// slope of the values.
+template <int kN, uint32_t kStride, class W>
+__device__ __attribute__((always_inline)) inline void split_sums_regs(
+    const W (&v)[kN], uint32_t t0, uint64_t len, uint64_t vmin, U128& s, U128& st) {
+  uint64_t sl = 0, sh = 0, stl = 0, sth = 0;
+#pragma unroll
+  for (int k = 0; k < kN; ++k) {
+    const uint32_t t = t0 + k * kStride;
+    const uint64_t y = t < len ? uint64_t(v[k]) - vmin : 0;
+    const uint64_t yl = y & 0xffffffffu, yh = y >> 32;
+    sl += yl;
+    sh += yh;
+    stl += uint64_t(t) * yl;
+    sth += uint64_t(t) * yh;
+  }
+  s = U128{sl, sh};
+  st = U128{stl, sth};
+}
+
+__device__ inline U128 join_split(U128 p) {
+  return add128(U128{p.lo, 0}, U128{p.hi << 32, p.hi >> 32});
+}
+
 // Range of the least-squares residuals of kN register-held values, value k
 // at position t0 + k * kStride (positions from len on ignored).  When small
 // (values below vmin + 2^30, every |floor(theta1 t)| below 2^30, the same
@@ -295,16 +325,10 @@ __device__ __attribute__((always_inline)) inline Model fit_wave_regs(const W (&v
       wave_sum_u64x2(sy, sty);
       th = ls_slope(len, U128{sy, 0}, U128{sty, 0});
     } else {
-      U128 sv{0, 0}, stv{0, 0};
-#pragma unroll
-      for (int k = 0; k < kR; ++k) {
-        const uint32_t t = lane + 64 * k;
-        const uint64_t x = t < len ? uint64_t(v[k]) : 0;
-        sv = add128(sv, U128{x, 0});
-        stv = add128(stv, mul64x64(t, x));
-      }
-      wave_sum_u128x2(sv, stv);
-      th = ls_slope(len, sv, stv);
+      U128 s, st;
+      split_sums_regs<kR, 64>(v, lane, len, vmin, s, st);
+      wave_sum_u128x2(s, st);
+      th = ls_slope(len, join_split(s), join_split(st));
     }
     // |floor(theta1 t)| < 2^30 for every t < len: predictions fit int32
     const bool small = narrow && __dmul_rn(fabs(th), double(len)) < 1073741824.0;
