@@ -350,8 +350,8 @@ __device__ __attribute__((always_inline)) inline Model fit_wave(const T* src, ui
   return fit_wave_regs<kR>(v, len, force_constant);
 }
 
-// At 16 values per lane, held to five waves per SIMD (96 VGPRs instead of
-// 104, a few spilled): 2% faster on u64 columns.
+// At 16 values per lane, held to five waves per SIMD (90 VGPRs instead of
+// 104): 2% faster on u64 columns.
 template <int kR>
 __global__ __launch_bounds__(kEncBlock, kR == 16 ? 5 : 1) void k_fit_wave(const EncColumn* __restrict__ cols,
                                                        uint64_t ncols, EncColumn single,
