@@ -228,19 +228,19 @@ __global__ __launch_bounds__(256) void k_fit_lane(const EncColumn* __restrict__ 
 template <int kN, uint32_t kStride, class W>
 __device__ __attribute__((always_inline)) inline void split_sums_regs(
     const W (&v)[kN], uint32_t t0, uint64_t len, uint64_t vmin, U128& s, U128& st) {
-  uint64_t sl = 0, sh = 0, stl = 0, sth = 0;
+  uint64_t slo = 0, shi = 0, stlo = 0, sthi = 0;
 #pragma unroll
   for (int k = 0; k < kN; ++k) {
     const uint32_t t = t0 + k * kStride;
     const uint64_t y = t < len ? uint64_t(v[k]) - vmin : 0;
     const uint64_t yl = y & 0xffffffffu, yh = y >> 32;
-    sl += yl;
-    sh += yh;
-    stl += uint64_t(t) * yl;
-    sth += uint64_t(t) * yh;
+    slo += yl;
+    shi += yh;
+    stlo += uint64_t(t) * yl;
+    sthi += uint64_t(t) * yh;
   }
-  s = U128{sl, sh};
-  st = U128{stl, sth};
+  s = U128{slo, shi};
+  st = U128{stlo, sthi};
 }
 
 __device__ inline U128 join_split(U128 p) {
