@@ -410,3 +410,20 @@ def test_narrow_residual_boundaries(torch, codec, ref):
                              fixed_len=L, ra=200)
             check_column(torch, codec, ref, v + np.uint64(1 << 40), f"u64 {name} L={L}",
                          fixed_len=L, ra=200)
+
+
+def test_wide_range_sums_at_their_bounds(torch, codec, ref):
+    """Partitions spanning just under 2^61 (the largest range a line is
+    fitted to), with a trend so that the fit matters, at the longest
+    partitions each wavefront fit holds (1024 and 2048 values) and at 4096:
+    the wide-range sums at their largest magnitudes."""
+    rng = np.random.default_rng(97)
+    n = 24 * 4096 + 333
+    top = (1 << 61) - 1
+    for L in (1024, 2048, 4096):
+        t = (np.arange(n) % L).astype(np.float64) / (L - 1)
+        trend = (t * (top - (1 << 58))).astype(np.uint64)
+        col = trend + rng.integers(0, 1 << 58, n, dtype=np.uint64)
+        col[np.arange(n) % L == 0] = 0  # every partition spans close to 2^61
+        assert int(col.max()) <= top
+        check_column(torch, codec, ref, col, f"near 2^61 L={L}", fixed_len=L, ra=200)
